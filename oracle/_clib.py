@@ -1,0 +1,37 @@
+"""Loader for the oracle's plain-C direct sums (oracle/o1.c); test infrastructure only.
+
+The shared object is built with gcc next to the source on first use (or by the repository's
+build step) and rebuilt when the source is newer.
+"""
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "o1.c")
+_LIB = os.path.join(_HERE, "libo1.so")
+_lib = None
+
+
+def build(force=False):
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build())
+        i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+        f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+        _lib.o1_entries.argtypes = [ctypes.c_int64, i64p, i64p, i64p, i64p, f64p, f64p, f64p, f64p]
+        _lib.o1_entries.restype = ctypes.c_int
+        _lib.o1_apply.argtypes = [ctypes.c_int64, i64p, i64p, f64p, f64p, f64p, f64p, ctypes.c_int64, i64p, f64p]
+        _lib.o1_apply.restype = ctypes.c_int
+    return _lib

@@ -1,0 +1,228 @@
+"""O2: Algorithm 1 (BC-FMM for the VtV calculation) step by step in FP64 (test infrastructure only).
+
+Each phase follows the paper's Algorithm 1 and the translation operators of Section 3:
+
+  near field    u_w = sum_{w' in N*(w)} <1_w, N_w' f>        for leaves w (N* with marked
+                sources expanded to their leaves; entries as in oracle.direct)
+  moments       m_w^b = <(. - x_w)^b, f>_{L2(w)}, |b| <= q      for leaves (2x2x2 point rule)
+  upward pass   m_w = sum_{w' in K(w)} M(w, w') m_w'            l = L-1..0, w in M_l
+  interaction   lambda_w = sum_{w' in I(w)} T(w, w') m_w'       every cell of every level
+  downward pass lambda_w' += L(w', w) lambda_w                  l = 0..L-1, w in M_l, w' in K(w)
+  evaluation    u_w += U(w) lambda_w                            for leaves (2x2x2 point rule)
+
+The far field of a leaf pair is therefore the order-q Taylor polynomial of G about the centres
+of the ancestors that meet in an interaction list, integrated with the same point rule as
+the near field; as q grows the result tends to O1 (oracle.direct).
+
+Expansion order q is fixed across levels (the paper's q_l schedule is not used here).
+`apply` runs every phase over every cell. `apply_sampled` runs the moment and upward phases
+over every cell and then the interaction, downward and evaluation phases only along the
+ancestor chains of the given target leaves, which yields the same numbers for those leaves.
+"""
+
+import numpy as np
+
+from . import direct
+from .taylor import l2l_matrix, m2l_matrix, m2m_matrix, monomials, n_coeffs
+
+_CHILD_POS = [(dx, dy, dz) for dz in (0, 1) for dy in (0, 1) for dx in (0, 1)]
+
+
+class FMM:
+    def __init__(self, mesh, q):
+        self.mesh = mesh
+        self.q = q
+        self.K = n_coeffs(q)
+        self.leaves = mesh.leaf_array()
+        self._cache = {}
+        self._rows = self._leaf_rows()
+
+    # -- helpers -----------------------------------------------------------------------------
+    def _leaf_rows(self):
+        """Per level: (positions of the level's leaves within the level, their leaf indices)."""
+        mesh = self.mesh
+        rows = []
+        for lev in range(mesh.L + 1):
+            pos, idx = [], []
+            for p, c in enumerate(mesh.levels[lev]):
+                key = (lev, *c)
+                if key in mesh.leaf_index:
+                    pos.append(p)
+                    idx.append(mesh.leaf_index[key])
+            rows.append((np.array(pos, dtype=np.int64), np.array(idx, dtype=np.int64)))
+        return rows
+
+    def _point_moments(self, lev, cells, chunk=8192):
+        """sum_g w_g (x_g - x_w)^b over the 2x2x2 points of level-lev cells: (n, K)."""
+        a = self.mesh.side(lev)
+        lo_all = np.asarray(cells, dtype=np.float64).reshape(-1, 3) * a
+        out = np.empty((len(lo_all), self.K))
+        for s in range(0, len(lo_all), chunk):
+            lo = lo_all[s : s + chunk]
+            pts, w = direct.gauss_points(lo, np.full(len(lo), a))
+            centre = lo + 0.5 * a
+            mono = monomials(pts - centre[:, None, :], self.q)  # (n, 8, K)
+            out[s : s + chunk] = mono.sum(axis=1) * w[:, None]
+        return out
+
+    def _child_offset(self, lev, pos):
+        """x_child - x_parent for a parent at level lev and child position pos in {0,1}^3."""
+        a = self.mesh.side(lev)
+        return np.array([(p - 0.5) * a / 2.0 for p in pos])
+
+    def _m2m(self, lev, pos):
+        key = ("m2m", lev, pos)
+        if key not in self._cache:
+            self._cache[key] = m2m_matrix(self._child_offset(lev, pos), self.q)
+        return self._cache[key]
+
+    def _l2l(self, lev, pos):
+        key = ("l2l", lev, pos)
+        if key not in self._cache:
+            self._cache[key] = l2l_matrix(self._child_offset(lev, pos), self.q)
+        return self._cache[key]
+
+    def _m2l(self, lev, offsets):
+        """T(w, w') for integer offsets (target minus source) between level-lev cells."""
+        need = [o for o in set(offsets) if ("m2l", lev, o) not in self._cache]
+        if need:
+            a = self.mesh.side(lev)
+            Ts = m2l_matrix(np.array(need, dtype=np.float64) * a, self.q)
+            for o, T in zip(need, Ts):
+                self._cache[("m2l", lev, o)] = T
+        return [self._cache[("m2l", lev, o)] for o in offsets]
+
+    # -- Algorithm 1 phases --------------------------------------------------------------------
+    def near_field(self, f, targets):
+        """u_w = sum over N*(w) of the Galerkin entries times f (near-field calculation)."""
+        mesh = self.mesh
+        ti, si = [], []
+        for n, t in enumerate(targets):
+            lev, i, j, k = mesh.leaves[t]
+            for s in mesh.near_leaf_sources(lev, (i, j, k)):
+                ti.append(n)
+                si.append(mesh.leaf_index[s])
+        ti = np.array(ti, dtype=np.int64)
+        si = np.array(si, dtype=np.int64)
+        vals = direct.entries(self.leaves, mesh.L, np.asarray(targets, dtype=np.int64)[ti], si)
+        return np.bincount(ti, weights=vals * f[si], minlength=len(targets))
+
+    def moments(self, f):
+        """Moment calculation: m_w = sum_g w_g f_w (x_g - x_w)^b for every leaf, by level."""
+        mesh = self.mesh
+        m = [np.zeros((len(mesh.levels[lev]), self.K)) for lev in range(mesh.L + 1)]
+        for lev, (pos, idx) in enumerate(self._rows):
+            if len(pos):
+                cells = [mesh.levels[lev][p] for p in pos]
+                m[lev][pos] = self._point_moments(lev, cells) * f[idx][:, None]
+        return m
+
+    def _children_rows(self, lev):
+        """For marked cells of level lev: their positions and, per child position, the child rows."""
+        mesh = self.mesh
+        par = [p for p, c in enumerate(mesh.levels[lev]) if mesh.is_refined(lev, c)]
+        kids = {pos: [] for pos in _CHILD_POS}
+        for p in par:
+            c = mesh.levels[lev][p]
+            for pos in _CHILD_POS:
+                ch = (2 * c[0] + pos[0], 2 * c[1] + pos[1], 2 * c[2] + pos[2])
+                kids[pos].append(mesh.index[lev + 1][ch])
+        return np.array(par, dtype=np.int64), {k: np.array(v, dtype=np.int64) for k, v in kids.items()}
+
+    def upward(self, m):
+        """Upward pass: m_w = sum_{w' in K(w)} M(w, w') m_w' for l = L-1..0 and w in M_l."""
+        for lev in range(self.mesh.L - 1, -1, -1):
+            par, kids = self._children_rows(lev)
+            if len(par) == 0:
+                continue
+            acc = np.zeros((len(par), self.K))
+            for pos in _CHILD_POS:
+                acc += m[lev + 1][kids[pos]] @ self._m2m(lev, pos).T
+            m[lev][par] = acc
+        return m
+
+    def interaction(self, m):
+        """Interaction phase: lambda_w = sum_{w' in I(w)} T(w, w') m_w' for every cell."""
+        mesh = self.mesh
+        lam = [np.zeros((len(mesh.levels[lev]), self.K)) for lev in range(mesh.L + 1)]
+        for lev in range(mesh.L + 1):
+            groups = {}
+            idx = mesh.index[lev]
+            for p, c in enumerate(mesh.levels[lev]):
+                for s in mesh.interaction_list(lev, c):
+                    o = (c[0] - s[0], c[1] - s[1], c[2] - s[2])
+                    groups.setdefault(o, ([], []))
+                    groups[o][0].append(p)
+                    groups[o][1].append(idx[s])
+            offsets = list(groups)
+            for o, T in zip(offsets, self._m2l(lev, offsets)):
+                tp = np.array(groups[o][0], dtype=np.int64)
+                sp = np.array(groups[o][1], dtype=np.int64)
+                lam[lev][tp] += m[lev][sp] @ T.T  # a target has at most one source per offset
+        return lam
+
+    def downward(self, lam):
+        """Downward pass: lambda_w' += L(w', w) lambda_w for l = 0..L-1, w in M_l, w' in K(w)."""
+        for lev in range(self.mesh.L):
+            par, kids = self._children_rows(lev)
+            if len(par) == 0:
+                continue
+            for pos in _CHILD_POS:
+                lam[lev + 1][kids[pos]] += lam[lev][par] @ self._l2l(lev, pos).T
+        return lam
+
+    def evaluation(self, lam, u):
+        """Evaluation phase: u_w += sum_g w_g sum_a lambda_w^a (x_g - x_w)^a for every leaf."""
+        mesh = self.mesh
+        for lev, (pos, idx) in enumerate(self._rows):
+            if len(pos):
+                cells = [mesh.levels[lev][p] for p in pos]
+                u[idx] += np.sum(self._point_moments(lev, cells) * lam[lev][pos], axis=1)
+        return u
+
+    def apply(self, f):
+        """The BC-FMM potential at every leaf: all phases of Algorithm 1 over all cells."""
+        f = np.asarray(f, dtype=np.float64)
+        u = self.near_field(f, np.arange(len(self.leaves)))
+        m = self.upward(self.moments(f))
+        lam = self.downward(self.interaction(m))
+        return self.evaluation(lam, u)
+
+    # -- sampled targets ---------------------------------------------------------------------
+    def _local_chain(self, lev, c, m, memo):
+        """lambda of cell (lev, c): its own interaction-list sum plus L2L of its parent's lambda."""
+        key = (lev, c)
+        if key in memo:
+            return memo[key]
+        mesh = self.mesh
+        srcs = mesh.interaction_list(lev, c)
+        lam = np.zeros(self.K)
+        if srcs:
+            offs = [(c[0] - s[0], c[1] - s[1], c[2] - s[2]) for s in srcs]
+            idx = mesh.index[lev]
+            for T, s in zip(self._m2l(lev, offs), srcs):
+                lam += T @ m[lev][idx[s]]
+        if lev > 0:
+            par = (c[0] >> 1, c[1] >> 1, c[2] >> 1)
+            pos = (c[0] & 1, c[1] & 1, c[2] & 1)
+            lam = lam + self._l2l(lev - 1, pos) @ self._local_chain(lev - 1, par, m, memo)
+        memo[key] = lam
+        return lam
+
+    def apply_sampled(self, f, targets):
+        """The BC-FMM potential at the given target leaves only."""
+        f = np.asarray(f, dtype=np.float64)
+        targets = np.asarray(targets, dtype=np.int64)
+        u = self.near_field(f, targets)
+        m = self.upward(self.moments(f))
+        memo = {}
+        for n, t in enumerate(targets):
+            lev, i, j, k = self.mesh.leaves[t]
+            lam = self._local_chain(lev, (i, j, k), m, memo)
+            u[n] += float(self._point_moments(lev, [(i, j, k)])[0] @ lam)
+        return u
+
+
+def apply(mesh, f, q, targets=None):
+    fm = FMM(mesh, q)
+    return fm.apply(f) if targets is None else fm.apply_sampled(f, targets)

@@ -1,0 +1,97 @@
+/*
+ * Direct O(N^2) Galerkin sums for the VtV volume potential -- TEST INFRASTRUCTURE ONLY.
+ * Part of the CPU oracle (see oracle/__init__.py); never linked into the product library.
+ *
+ * u_t = sum_s A_ts f_s with (Sec. 1.2, Galerkin projection with degree 0, indicator basis):
+ *   A_ts = C_class * a_small^5 / (4 pi)          if the closed cubes t and s intersect,
+ *   A_ts = sum_{g in t} sum_{g' in s} w_g w_g' / (4 pi |x_g - y_g'|)   otherwise,
+ * with the 2x2x2 Gauss-Legendre rule on each cube (w_g = a^3 / 8).
+ * The seven class constants are passed in (computed by oracle/touching.py).
+ *
+ * Leaves are described by integer lower corners and sides at level-L resolution (for the
+ * touching test, exact) and by floating lower corners and sides (for the point rule).
+ * Plain loops; OpenMP over targets only (each target's sum is one thread's fixed-order loop).
+ */
+#include <math.h>
+#include <stdint.h>
+
+static double node(int g) { return g == 0 ? 0.5 - 0.5 / sqrt(3.0) : 0.5 + 0.5 / sqrt(3.0); }
+
+/* Touching class: -1 not touching; 0 self, 1 face, 2 edge, 3 vertex (equal sides);
+ * 4 face, 5 edge, 6 vertex (sides in ratio 2); -2 if the pair breaks 2:1 balance. */
+int o1_touch_class(const int64_t *lo_t, int64_t s_t, const int64_t *lo_s, int64_t s_s)
+{
+    int contact = 0;
+    for (int i = 0; i < 3; ++i) {
+        int64_t lo = lo_t[i] > lo_s[i] ? lo_t[i] : lo_s[i];
+        int64_t ht = lo_t[i] + s_t, hs = lo_s[i] + s_s;
+        int64_t hi = ht < hs ? ht : hs;
+        if (lo > hi) return -1;
+        if (lo == hi) ++contact;
+    }
+    if (s_t == s_s) return contact; /* 0 = self (same cell) */
+    int64_t big = s_t > s_s ? s_t : s_s, small = s_t > s_s ? s_s : s_t;
+    if (big != 2 * small || contact == 0) return -2;
+    return 3 + contact;
+}
+
+double o1_point_rule(const double *lo_t, double a_t, const double *lo_s, double a_s)
+{
+    double sum = 0.0;
+    for (int gz = 0; gz < 2; ++gz)
+        for (int gy = 0; gy < 2; ++gy)
+            for (int gx = 0; gx < 2; ++gx)
+                for (int hz = 0; hz < 2; ++hz)
+                    for (int hy = 0; hy < 2; ++hy)
+                        for (int hx = 0; hx < 2; ++hx) {
+                            double dx = (lo_t[0] + a_t * node(gx)) - (lo_s[0] + a_s * node(hx));
+                            double dy = (lo_t[1] + a_t * node(gy)) - (lo_s[1] + a_s * node(hy));
+                            double dz = (lo_t[2] + a_t * node(gz)) - (lo_s[2] + a_s * node(hz));
+                            sum += 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+                        }
+    double wt = a_t * a_t * a_t / 8.0, ws = a_s * a_s * a_s / 8.0;
+    return wt * ws * sum / (4.0 * M_PI);
+}
+
+static double entry(int64_t t, int64_t s, const int64_t *lo_int, const int64_t *size,
+                    const double *lo, const double *a, const double *consts, int *bad)
+{
+    int c = o1_touch_class(lo_int + 3 * t, size[t], lo_int + 3 * s, size[s]);
+    if (c == -2) { *bad = 1; return 0.0; }
+    if (c >= 0) {
+        double as = a[t] < a[s] ? a[t] : a[s];
+        return consts[c] * as * as * as * as * as / (4.0 * M_PI);
+    }
+    return o1_point_rule(lo + 3 * t, a[t], lo + 3 * s, a[s]);
+}
+
+/* out[p] = A_{ti[p], si[p]} for n pairs. Returns 0, or 1 if a touching pair breaks 2:1 balance. */
+int o1_entries(int64_t n, const int64_t *ti, const int64_t *si, const int64_t *lo_int,
+               const int64_t *size, const double *lo, const double *a, const double *consts, double *out)
+{
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int64_t p = 0; p < n; ++p) {
+        int b = 0;
+        out[p] = entry(ti[p], si[p], lo_int, size, lo, a, consts, &b);
+        bad |= b;
+    }
+    return bad;
+}
+
+/* u[k] = sum over all n leaves s of A_{targets[k], s} f[s]. Returns 0, or 1 on a 2:1 violation. */
+int o1_apply(int64_t n, const int64_t *lo_int, const int64_t *size, const double *lo, const double *a,
+             const double *consts, const double *f, int64_t n_targets, const int64_t *targets, double *u)
+{
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(| : bad)
+    for (int64_t k = 0; k < n_targets; ++k) {
+        int b = 0;
+        double acc = 0.0;
+        for (int64_t s = 0; s < n; ++s)
+            acc += entry(targets[k], s, lo_int, size, lo, a, consts, &b) * f[s];
+        u[k] = acc;
+        bad |= b;
+    }
+    return bad;
+}
