@@ -1,0 +1,158 @@
+/*
+ * bcv.h -- C ABI of the boundary-concentrated FMM for Galerkin volume potentials on MI355X (gfx950).
+ *
+ * The library evaluates the volume-to-volume (VtV) potential of Mohyaddin & Tausch,
+ * "A fast method for evaluating volume potentials in the Galerkin boundary element method":
+ * given a density f that is constant on each leaf of a boundary-concentrated (BC) mesh of
+ * Omega = [0,1]^3, it returns the Galerkin coefficients
+ *
+ *     u_w = < 1_w , N f >_{L2(Omega)},   N f(x) = int_Omega G(x,y) f(y) dy,   G = 1/(4 pi |x-y|)
+ *
+ * for every leaf w (Sec. 1: volume potential and its L2 projection with degree-0 elements;
+ * Sec. 3: Algorithm 1). The mesh is a cube octree refined towards the boundary (Sec. 2 with
+ * cube cells); the far field uses Cartesian Taylor expansions of order q (Sec. 3, translation
+ * operators); the near field uses exact integrals for touching cell pairs and the 2x2x2 Gauss
+ * rule on both cells otherwise.
+ *
+ * Conventions shared by every entry point:
+ *   - Every call returns a bcv_status. No C++ exception crosses this interface. On failure the
+ *     thread-local message returned by bcv_last_error() describes the cause.
+ *   - The library owns trees and plans (opaque handles, created here, freed by *_destroy).
+ *     The caller owns every pointer it passes.
+ *   - Device pointers are HIP device addresses on the plan's device; host pointers are ordinary
+ *     process memory. Each argument says which it is.
+ *   - Leaf order: leaves are numbered by the Morton key of their lower corner at level-L
+ *     resolution (bit b of i, j, k at bits 3b, 3b+1, 3b+2). bcv_tree_leaves() exposes
+ *     (level, i, j, k) per leaf in this order; densities and potentials use it.
+ *   - A plan may be used from any host thread. Calls that run on one plan and overlap in time
+ *     (two streams, or two threads) race on the plan's workspace: serialise them.
+ */
+#ifndef BCV_H
+#define BCV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bcv_tree_s *bcv_tree;
+typedef struct bcv_plan_s *bcv_plan;
+
+typedef enum {
+    BCV_OK = 0,
+    BCV_EINVAL = 1,  /* an argument is out of range or a required pointer is NULL */
+    BCV_ENOMEM = 2,  /* host or device allocation failed */
+    BCV_EDEVICE = 3, /* a HIP call failed; bcv_last_error() carries the HIP message */
+    BCV_ENOTSUP = 4, /* valid request that this build does not implement */
+    BCV_ESTATE = 5   /* a handle is not a live object of the expected kind */
+} bcv_status;
+
+/* Mesh description (Sec. 2, Boundary Concentrated Mesh, with cube cells on [0,1]^3).
+ * Level 0 is the unit cube; level-l cells are cubes of side 2^-l. For l < L a cell is marked
+ * (refined) iff it has a face on the boundary; every level-L cell is a leaf. */
+typedef struct {
+    int L;       /* finest level, 2 <= L <= 9 (boundary leaves have side h = 2^-L) */
+    int marking; /* must be 0: the face-on-boundary marking rule */
+} bcv_mesh_desc;
+
+enum { BCV_NEAR_QUADRATURE = 0, BCV_NEAR_ASSEMBLED = 1 };
+enum { BCV_FP64 = 0 };
+
+/* Plan options. */
+typedef struct {
+    double eta0;   /* separation parameter of the neighbour test (eq. def:neighbors); must be 0.5 */
+    int q;         /* expansion order, |alpha| + |beta| <= q (Sec. 3); supported: 4, 6 */
+    int precision; /* BCV_FP64 */
+    int direct;    /* 1: every leaf pair is treated as near (no far field; small meshes only) */
+    int nearfield; /* BCV_NEAR_QUADRATURE: the apply evaluates every near-pair entry on the fly;
+                      BCV_NEAR_ASSEMBLED: the plan stores every near-pair entry (FP64) once and
+                      the apply multiplies by them */
+} bcv_plan_opts;
+
+/* Sizes of a plan (all counts, no pointers). */
+typedef struct {
+    int64_t n_leaves;     /* unknowns */
+    int64_t n_cells;      /* all cells of all levels */
+    int64_t n_near;       /* ordered near (target leaf, source leaf) pairs */
+    int64_t n_touch;      /* of which the closed cubes touch (exact singular entries) */
+    int64_t n_m2l;        /* ordered interaction-list pairs (cells), all levels */
+    int64_t n_m2l_lanes;  /* lane-pairs the interaction kernel executes (>= n_m2l; padding) */
+    int64_t n_offsets;    /* distinct integer interaction offsets (derivative tables) */
+    int64_t device_bytes; /* device memory held by the plan */
+    int32_t K;            /* expansion coefficients per cell, (q+1)(q+2)(q+3)/6 */
+    int32_t L;
+} bcv_plan_info;
+
+/* Build the BC octree of Sec. 2 on the host. desc and out must be non-NULL.
+ * Errors: BCV_EINVAL (L outside 2..9, marking != 0), BCV_ENOMEM. */
+bcv_status bcv_build_bc_tree(const bcv_mesh_desc *desc, bcv_tree *out);
+
+/* Number of leaves (host integer). */
+bcv_status bcv_tree_num_leaves(bcv_tree tree, int64_t *n);
+
+/* Copy (level, i, j, k) of every leaf, in leaf order, into level_ijk (host, n_leaves x 4 int32). */
+bcv_status bcv_tree_leaves(bcv_tree tree, int32_t *level_ijk);
+
+void bcv_tree_destroy(bcv_tree tree);
+
+/* Build the interaction plan of Sec. 3 for `tree` on HIP device `device`: neighbour lists
+ * (eq. def:neighbors), interaction lists, extended neighbour lists N* with marked sources
+ * expanded to their leaves (Lemma 1, eq. spaceDecomp:OmOm), touching classes, derivative
+ * tables, and all device workspace. Allocates device memory; the apply never does.
+ * The plan copies what it needs: the tree may be destroyed afterwards.
+ * Errors: BCV_EINVAL (NULL pointers, eta0 != 0.5, q not supported, precision not FP64),
+ * BCV_ENOTSUP, BCV_ENOMEM, BCV_EDEVICE, BCV_ESTATE (bad tree handle). */
+bcv_status bcv_plan_interactions(bcv_tree tree, const bcv_plan_opts *opts, int device, bcv_plan *out);
+
+bcv_status bcv_plan_get_info(bcv_plan plan, bcv_plan_info *info);
+
+void bcv_plan_destroy(bcv_plan plan);
+
+/* VtV apply, Algorithm 1: u = near field + far field for density f.
+ *   f_dev: device, n_leaves doubles in leaf order (the density value on each leaf);
+ *   u_dev: device, n_leaves doubles in leaf order, OVERWRITTEN with u_w = <1_w, N f>.
+ *   hip_stream: a hipStream_t on the plan's device (NULL = the null stream).
+ * Stream-ordered and asynchronous: returns after enqueueing; allocates nothing.
+ * f_dev and u_dev must not overlap. Errors: BCV_EINVAL (NULL pointers), BCV_ESTATE, BCV_EDEVICE. */
+bcv_status bcv_vtv_apply(bcv_plan plan, const double *f_dev, double *u_dev, void *hip_stream);
+
+/* The same apply restricted to parts of Algorithm 1, for testing and timing:
+ * parts = BCV_PART_NEAR (near field only), BCV_PART_FAR (moments through evaluation only),
+ * or both. u_dev is overwritten with the sum of the selected parts. */
+enum { BCV_PART_NEAR = 1, BCV_PART_FAR = 2 };
+bcv_status bcv_vtv_apply_parts(bcv_plan plan, const double *f_dev, double *u_dev, void *hip_stream, int parts);
+
+/* Per-phase device timing of applies, with HIP events recorded on each apply's stream between
+ * the phases of Algorithm 1: moments (P2M), upward pass (M2M), interaction phase (M2L), downward
+ * pass (L2L), and near field fused with the evaluation phase (NEAR).
+ * bcv_plan_enable_timing creates 6 * max_applies events (host call, may allocate) and resets
+ * the record; each following apply records its phase boundaries until max_applies applies have
+ * been recorded (later applies are not timed). max_applies = 0 disables timing and frees the
+ * events. bcv_plan_phase_times waits for the recorded events and returns, per phase, the total
+ * milliseconds over the recorded applies (ms: host, BCV_N_PHASES doubles) and the number of
+ * recorded applies (n_applies: host). Errors: BCV_EINVAL, BCV_ESTATE, BCV_EDEVICE. */
+enum { BCV_PHASE_P2M = 0, BCV_PHASE_M2M = 1, BCV_PHASE_M2L = 2, BCV_PHASE_L2L = 3, BCV_PHASE_NEAR = 4, BCV_N_PHASES = 5 };
+bcv_status bcv_plan_enable_timing(bcv_plan plan, int max_applies);
+bcv_status bcv_plan_phase_times(bcv_plan plan, double *ms, int64_t *n_applies);
+
+/* Volume-to-boundary (Algorithm 2) and boundary-to-volume (Algorithm 3) applies on the same
+ * tree. Not implemented in this build: both return BCV_ENOTSUP. */
+bcv_status bcv_vtb_apply(bcv_plan plan, const double *f_dev, double *u_face_dev, void *hip_stream);
+bcv_status bcv_btv_apply(bcv_plan plan, const double *q_face_dev, const double *g_face_dev, double *u_dev,
+                         void *hip_stream);
+
+/* The seven exact touching-pair integrals int_A int_B 1/|x-y| the library uses for the singular
+ * near-field entries (smaller side 1; order: self, face, edge, vertex, then face, edge, vertex
+ * with the larger side 2). Computed on `device` once per process from the self-similarity of
+ * the cube (splitting both cubes into halves) with regular pairs integrated by a 6-D Gauss rule.
+ * out: host, 7 doubles. Errors: BCV_EINVAL, BCV_EDEVICE. */
+bcv_status bcv_touching_integrals(int device, double *out);
+
+/* Thread-local description of the last failure on this thread (valid until the next call). */
+const char *bcv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BCV_H */

@@ -1,0 +1,201 @@
+"""ctypes binding of libbcvol (include/bcv.h): argument marshalling only.
+
+Every computation runs in the library's HIP kernels; PyTorch supplies device memory and
+streams. The binding raises if the library has not been built.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbcvol.so")
+_lib = None
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOTSUP, ESTATE = range(6)
+NEAR_QUADRATURE, NEAR_ASSEMBLED = 0, 1
+PART_NEAR, PART_FAR = 1, 2
+TOUCH_CLASSES = ("self", "face", "edge", "vertex", "face2", "edge2", "vertex2")
+
+
+class BCVError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("bcv status %d: %s" % (status, message))
+        self.status = status
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int), ("marking", ctypes.c_int)]
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("eta0", ctypes.c_double), ("q", ctypes.c_int), ("precision", ctypes.c_int),
+                ("direct", ctypes.c_int), ("nearfield", ctypes.c_int)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("n_leaves", "n_cells", "n_near", "n_touch", "n_m2l", "n_m2l_lanes",
+                                              "n_offsets", "device_bytes")] + [("K", ctypes.c_int32),
+                                                                               ("L", ctypes.c_int32)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError("libbcvol.so is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(_LIB_PATH)
+        vp, i64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)
+        L.bcv_build_bc_tree.argtypes = [ctypes.POINTER(MeshDesc), ctypes.POINTER(vp)]
+        L.bcv_tree_num_leaves.argtypes = [vp, i64p]
+        L.bcv_tree_leaves.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+        L.bcv_tree_destroy.argtypes = [vp]
+        L.bcv_tree_destroy.restype = None
+        L.bcv_plan_interactions.argtypes = [vp, ctypes.POINTER(PlanOpts), ctypes.c_int, ctypes.POINTER(vp)]
+        L.bcv_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+        L.bcv_plan_destroy.argtypes = [vp]
+        L.bcv_plan_destroy.restype = None
+        L.bcv_vtv_apply.argtypes = [vp, vp, vp, vp]
+        L.bcv_vtv_apply_parts.argtypes = [vp, vp, vp, vp, ctypes.c_int]
+        L.bcv_vtb_apply.argtypes = [vp, vp, vp, vp]
+        L.bcv_btv_apply.argtypes = [vp, vp, vp, vp, vp]
+        L.bcv_plan_enable_timing.argtypes = [vp, ctypes.c_int]
+        L.bcv_plan_phase_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i64p]
+        L.bcv_touching_integrals.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+        L.bcv_last_error.restype = ctypes.c_char_p
+        for name in ("bcv_build_bc_tree", "bcv_tree_num_leaves", "bcv_tree_leaves", "bcv_plan_interactions",
+                     "bcv_plan_get_info", "bcv_vtv_apply", "bcv_vtv_apply_parts", "bcv_vtb_apply", "bcv_btv_apply",
+                     "bcv_touching_integrals", "bcv_plan_enable_timing", "bcv_plan_phase_times"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != OK:
+        raise BCVError(status, lib().bcv_last_error().decode())
+
+
+class Tree:
+    def __init__(self, handle):
+        self._h = handle
+
+    @property
+    def handle(self):
+        return self._h
+
+    def num_leaves(self):
+        n = ctypes.c_int64()
+        _check(lib().bcv_tree_num_leaves(self._h, ctypes.byref(n)))
+        return n.value
+
+    def leaves(self):
+        """(level, i, j, k) per leaf in leaf order, int32 (n, 4)."""
+        out = np.empty((self.num_leaves(), 4), dtype=np.int32)
+        _check(lib().bcv_tree_leaves(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return out
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.bcv_tree_destroy(self._h)
+            self._h = None
+
+
+def build_bc_tree(L, marking=0):
+    desc = MeshDesc(L, marking)
+    h = ctypes.c_void_p()
+    _check(lib().bcv_build_bc_tree(ctypes.byref(desc), ctypes.byref(h)))
+    return Tree(h)
+
+
+class Plan:
+    def __init__(self, handle, device):
+        self._h = handle
+        self.device = device
+        info = PlanInfo()
+        _check(lib().bcv_plan_get_info(self._h, ctypes.byref(info)))
+        self.info = {n: getattr(info, n) for n, _ in PlanInfo._fields_}
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def n_leaves(self):
+        return self.info["n_leaves"]
+
+    def destroy(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.bcv_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.destroy()
+
+
+def plan_interactions(tree, q=6, eta0=0.5, direct=False, nearfield=NEAR_QUADRATURE, device=0):
+    opts = PlanOpts(eta0, q, 0, 1 if direct else 0, nearfield)
+    h = ctypes.c_void_p()
+    _check(lib().bcv_plan_interactions(tree.handle, ctypes.byref(opts), device, ctypes.byref(h)))
+    return Plan(h, device)
+
+
+def _dev_ptr(t, n, device, name):
+    import torch
+
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("%s must be a contiguous float64 CUDA tensor" % name)
+    if t.numel() != n or t.device.index != device:
+        raise ValueError("%s must hold %d values on cuda:%d" % (name, n, device))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream, device):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def vtv_apply(plan, f, u, stream=None):
+    """u <- VtV potential of density f (device tensors in leaf order); stream-ordered."""
+    n = plan.n_leaves
+    _check(lib().bcv_vtv_apply(plan.handle, _dev_ptr(f, n, plan.device, "f"), _dev_ptr(u, n, plan.device, "u"),
+                               _stream(stream, plan.device)))
+
+
+def vtv_apply_parts(plan, f, u, parts, stream=None):
+    n = plan.n_leaves
+    _check(lib().bcv_vtv_apply_parts(plan.handle, _dev_ptr(f, n, plan.device, "f"),
+                                     _dev_ptr(u, n, plan.device, "u"), _stream(stream, plan.device), parts))
+
+
+def vtb_apply(plan, f, u_face, stream=None):
+    _check(lib().bcv_vtb_apply(plan.handle, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u_face.data_ptr()),
+                               _stream(stream, plan.device)))
+
+
+def btv_apply(plan, q_face, g_face, u, stream=None):
+    _check(lib().bcv_btv_apply(plan.handle, ctypes.c_void_p(q_face.data_ptr()), ctypes.c_void_p(g_face.data_ptr()),
+                               ctypes.c_void_p(u.data_ptr()), _stream(stream, plan.device)))
+
+
+PHASES = ("p2m", "m2m", "m2l", "l2l", "near")
+
+
+def plan_enable_timing(plan, max_applies):
+    _check(lib().bcv_plan_enable_timing(plan.handle, max_applies))
+
+
+def plan_phase_times(plan):
+    """(total ms per phase as a dict, number of recorded applies)."""
+    ms = (ctypes.c_double * len(PHASES))()
+    n = ctypes.c_int64()
+    _check(lib().bcv_plan_phase_times(plan.handle, ms, ctypes.byref(n)))
+    return dict(zip(PHASES, list(ms))), n.value
+
+
+def touching_integrals(device=0):
+    out = np.empty(7)
+    _check(lib().bcv_touching_integrals(device, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out

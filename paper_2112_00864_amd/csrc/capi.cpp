@@ -1,0 +1,221 @@
+// extern "C" entry points of bcv.h: argument checks, handle checks, and translation of C++
+// exceptions into bcv_status plus a thread-local message.
+#include <new>
+#include <string>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace bcv {
+bcv_tree_s *build_tree(int L);
+bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int device);
+void destroy_plan(bcv_plan_s *p);
+void touching_integrals(int device, double out[kTouchClasses]);
+void set_timing(bcv_plan_s *p, int max_applies);
+void phase_times(const bcv_plan_s *p, double *ms, int64_t *n);
+}  // namespace bcv
+
+namespace {
+
+thread_local std::string g_error;
+
+template <class F>
+bcv_status guard(F &&f)
+{
+    try {
+        f();
+        g_error.clear();
+        return BCV_OK;
+    } catch (const bcv::Error &e) {
+        g_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_error = "host allocation failed";
+        return BCV_ENOMEM;
+    } catch (const std::exception &e) {
+        g_error = std::string("internal error: ") + e.what();
+        return BCV_ESTATE;
+    } catch (...) {
+        g_error = "internal error";
+        return BCV_ESTATE;
+    }
+}
+
+void check_tree(bcv_tree t)
+{
+    BCV_REQUIRE(t != nullptr, BCV_EINVAL, "tree handle is NULL");
+    BCV_REQUIRE(t->magic == bcv_tree_s::kMagic, BCV_ESTATE, "not a live bcv_tree");
+}
+
+void check_plan(bcv_plan p)
+{
+    BCV_REQUIRE(p != nullptr, BCV_EINVAL, "plan handle is NULL");
+    BCV_REQUIRE(p->magic == bcv_plan_s::kMagic, BCV_ESTATE, "not a live bcv_plan");
+}
+
+// Runs f with the plan's device current and restores the caller's device afterwards.
+template <class F>
+void on_device(int device, F &&f)
+{
+    int old = 0;
+    BCV_HIP(hipGetDevice(&old));
+    BCV_HIP(hipSetDevice(device));
+    try {
+        f();
+    } catch (...) {
+        (void)hipSetDevice(old);
+        throw;
+    }
+    BCV_HIP(hipSetDevice(old));
+}
+
+}  // namespace
+
+extern "C" {
+
+bcv_status bcv_build_bc_tree(const bcv_mesh_desc *desc, bcv_tree *out)
+{
+    return guard([&] {
+        BCV_REQUIRE(desc != nullptr && out != nullptr, BCV_EINVAL, "NULL argument");
+        *out = nullptr;
+        BCV_REQUIRE(desc->L >= 2 && desc->L <= 9, BCV_EINVAL, "L must be in 2..9");
+        BCV_REQUIRE(desc->marking == 0, BCV_EINVAL, "only the face-on-boundary marking rule (0) is supported");
+        *out = bcv::build_tree(desc->L);
+    });
+}
+
+bcv_status bcv_tree_num_leaves(bcv_tree tree, int64_t *n)
+{
+    return guard([&] {
+        check_tree(tree);
+        BCV_REQUIRE(n != nullptr, BCV_EINVAL, "NULL argument");
+        *n = tree->n_leaves();
+    });
+}
+
+bcv_status bcv_tree_leaves(bcv_tree tree, int32_t *level_ijk)
+{
+    return guard([&] {
+        check_tree(tree);
+        BCV_REQUIRE(level_ijk != nullptr, BCV_EINVAL, "NULL argument");
+        for (int64_t l = 0; l < tree->n_leaves(); ++l) {
+            const int32_t c = tree->leaf_cell[l];
+            level_ijk[4 * l] = tree->level[c];
+            for (int ax = 0; ax < 3; ++ax) level_ijk[4 * l + 1 + ax] = tree->ijk[3 * c + ax];
+        }
+    });
+}
+
+void bcv_tree_destroy(bcv_tree tree)
+{
+    if (tree && tree->magic == bcv_tree_s::kMagic) {
+        tree->magic = 0;
+        delete tree;
+    }
+}
+
+bcv_status bcv_plan_interactions(bcv_tree tree, const bcv_plan_opts *opts, int device, bcv_plan *out)
+{
+    return guard([&] {
+        check_tree(tree);
+        BCV_REQUIRE(opts != nullptr && out != nullptr, BCV_EINVAL, "NULL argument");
+        *out = nullptr;
+        BCV_REQUIRE(opts->eta0 == 0.5, BCV_EINVAL, "eta0 must be 0.5");
+        BCV_REQUIRE(opts->q == 4 || opts->q == 6, BCV_EINVAL, "q must be 4 or 6");
+        BCV_REQUIRE(opts->precision == BCV_FP64, BCV_EINVAL, "precision must be BCV_FP64");
+        BCV_REQUIRE(opts->direct == 0 || opts->direct == 1, BCV_EINVAL, "direct must be 0 or 1");
+        BCV_REQUIRE(opts->nearfield == BCV_NEAR_QUADRATURE || opts->nearfield == BCV_NEAR_ASSEMBLED, BCV_EINVAL,
+                    "unknown nearfield mode");
+        int n_dev = 0;
+        BCV_HIP(hipGetDeviceCount(&n_dev));
+        BCV_REQUIRE(device >= 0 && device < n_dev, BCV_EINVAL, "no such HIP device");
+        on_device(device, [&] { *out = bcv::build_plan(*tree, *opts, device); });
+    });
+}
+
+bcv_status bcv_plan_get_info(bcv_plan plan, bcv_plan_info *info)
+{
+    return guard([&] {
+        check_plan(plan);
+        BCV_REQUIRE(info != nullptr, BCV_EINVAL, "NULL argument");
+        info->n_leaves = plan->n_leaves;
+        info->n_cells = plan->n_cells;
+        info->n_near = plan->n_near;
+        info->n_touch = plan->n_touch;
+        info->n_m2l = plan->n_m2l;
+        info->n_m2l_lanes = plan->n_m2l_lanes;
+        info->n_offsets = plan->n_offsets;
+        info->device_bytes = plan->device_bytes;
+        info->K = plan->K;
+        info->L = plan->L;
+    });
+}
+
+void bcv_plan_destroy(bcv_plan plan)
+{
+    if (plan && plan->magic == bcv_plan_s::kMagic) bcv::destroy_plan(plan);
+}
+
+bcv_status bcv_vtv_apply_parts(bcv_plan plan, const double *f_dev, double *u_dev, void *hip_stream, int parts)
+{
+    return guard([&] {
+        check_plan(plan);
+        BCV_REQUIRE(f_dev != nullptr && u_dev != nullptr, BCV_EINVAL, "NULL density or potential pointer");
+        BCV_REQUIRE(parts >= 1 && parts <= 3, BCV_EINVAL, "parts must be a non-empty subset of NEAR|FAR");
+        on_device(plan->device, [&] { bcv::launch_apply(*plan, f_dev, u_dev, parts, (hipStream_t)hip_stream); });
+    });
+}
+
+bcv_status bcv_vtv_apply(bcv_plan plan, const double *f_dev, double *u_dev, void *hip_stream)
+{
+    return bcv_vtv_apply_parts(plan, f_dev, u_dev, hip_stream, BCV_PART_NEAR | BCV_PART_FAR);
+}
+
+bcv_status bcv_plan_enable_timing(bcv_plan plan, int max_applies)
+{
+    return guard([&] {
+        check_plan(plan);
+        BCV_REQUIRE(max_applies >= 0 && max_applies <= 1000000, BCV_EINVAL, "max_applies out of range");
+        on_device(plan->device, [&] { bcv::set_timing(plan, max_applies); });
+    });
+}
+
+bcv_status bcv_plan_phase_times(bcv_plan plan, double *ms, int64_t *n_applies)
+{
+    return guard([&] {
+        check_plan(plan);
+        BCV_REQUIRE(ms != nullptr && n_applies != nullptr, BCV_EINVAL, "NULL argument");
+        on_device(plan->device, [&] { bcv::phase_times(plan, ms, n_applies); });
+    });
+}
+
+bcv_status bcv_vtb_apply(bcv_plan plan, const double *, double *, void *)
+{
+    return guard([&] {
+        check_plan(plan);
+        bcv::fail(BCV_ENOTSUP, "volume-to-boundary apply is not implemented in this build");
+    });
+}
+
+bcv_status bcv_btv_apply(bcv_plan plan, const double *, const double *, double *, void *)
+{
+    return guard([&] {
+        check_plan(plan);
+        bcv::fail(BCV_ENOTSUP, "boundary-to-volume apply is not implemented in this build");
+    });
+}
+
+bcv_status bcv_touching_integrals(int device, double *out)
+{
+    return guard([&] {
+        BCV_REQUIRE(out != nullptr, BCV_EINVAL, "NULL argument");
+        int n_dev = 0;
+        BCV_HIP(hipGetDeviceCount(&n_dev));
+        BCV_REQUIRE(device >= 0 && device < n_dev, BCV_EINVAL, "no such HIP device");
+        on_device(device, [&] { bcv::touching_integrals(device, out); });
+    });
+}
+
+const char *bcv_last_error(void) { return g_error.c_str(); }
+
+}  // extern "C"

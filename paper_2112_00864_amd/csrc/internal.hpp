@@ -1,0 +1,77 @@
+// Internal object layouts behind the opaque bcv_tree / bcv_plan handles.
+#pragma once
+#include <cstdint>
+#include <vector>
+
+#include "common.hpp"
+
+struct bcv_tree_s {
+    static constexpr uint32_t kMagic = 0x42435654u;  // "BCVT"
+    uint32_t magic = kMagic;
+    int L = 0;
+    // Cells of all levels, numbered level by level and in Morton order within a level. The
+    // children of a marked cell are 8 consecutive cells of the next level (x fastest).
+    std::vector<int32_t> lvl_start;  // L + 2 entries
+    std::vector<int32_t> ijk;        // 3 per cell
+    std::vector<int8_t> level;
+    std::vector<uint8_t> refined;    // marked (has children)
+    std::vector<int32_t> parent;     // -1 for the root
+    std::vector<int32_t> first_child;
+    std::vector<int32_t> leaf_of_cell;  // leaf number or -1 (marked cell)
+    std::vector<int32_t> leaf_cell;     // cell of each leaf, leaf order
+
+    int64_t n_cells() const { return (int64_t)level.size(); }
+    int64_t n_leaves() const { return (int64_t)leaf_cell.size(); }
+};
+
+namespace bcv {
+
+// Device-side description of one 64-lane interaction (M2L) task: 64 targets of one level that
+// share their child position, and a list of slots, each an interaction offset shared by the
+// lanes together with one source cell per lane (or the zero row).
+struct M2LTask {
+    int32_t slot_begin;  // first slot
+    int32_t n_slots;
+    int32_t level;  // level of the 64 targets (cell side 2^-level); targets at 64 * task index
+    int32_t pad;
+};
+
+// Touching-pair classes in the order of bcv_touching_integrals().
+constexpr int kTouchClasses = 7;
+
+}  // namespace bcv
+
+struct bcv_plan_s {
+    static constexpr uint32_t kMagic = 0x42435650u;  // "BCVP"
+    uint32_t magic = kMagic;
+    int device = 0;
+    int L = 0, q = 0, K = 0;
+    int direct = 0, nearfield = 0;
+    int64_t n_leaves = 0, n_cells = 0, n_near = 0, n_touch = 0, n_m2l = 0, n_m2l_lanes = 0, n_offsets = 0;
+    int64_t device_bytes = 0;
+    double touch_value[bcv::kTouchClasses];  // touching integrals / (4 pi), smaller side 1
+
+    // Phase timing: 6 events per recorded apply (phase boundaries), see bcv_plan_enable_timing.
+    std::vector<hipEvent_t> events;
+    int timing_cap = 0;
+    mutable int timing_used = 0;
+
+    // Host copies needed to launch level-by-level passes.
+    std::vector<int32_t> parent_begin;  // per level l: range of marked cells of level l in d_parents
+    int64_t n_tasks = 0;
+
+    // Device buffers (owned).
+    double *d_leaf_geom = nullptr;  // 4 per leaf: lower corner x, y, z and side
+    int32_t *d_leaf_cell = nullptr;
+    int64_t *d_row = nullptr;       // near CSR row pointers (n_leaves + 1)
+    uint32_t *d_col = nullptr;      // source leaf | (touch class + 1) << 28
+    double *d_val = nullptr;        // assembled near entries (nearfield == ASSEMBLED)
+    double *d_M = nullptr;          // moments, (n_cells + 1) x K; the last row stays zero
+    double *d_Lam = nullptr;        // local coefficients, n_cells x K
+    double *d_G = nullptr;          // derivative tables, n_offsets x K
+    int32_t *d_parents = nullptr;   // (marked cell, first child) pairs, grouped by level
+    bcv::M2LTask *d_tasks = nullptr;
+    int32_t *d_task_targets = nullptr;  // 64 per task, -1 = idle lane
+    int32_t *d_slot_off = nullptr;      // offset id per slot
+    int32_t *d_slot_src = nullptr;      // 64 source cells per slot (n_cells = zero row)
+};

@@ -1,0 +1,431 @@
+// Device kernels of the VtV apply (Algorithm 1 of the paper) for gfx950, FP64.
+//
+// Expansion coefficients are stored scaled so that every translation is level independent.
+// For a cell w of side a and centre x_w, with the moments m^b and local coefficients lambda^a
+// of Sec. 3 (translation operators):
+//     M^b      = (-1)^|b| m^b / (b! a^|b|)          (moments)
+//     Lambda^a = lambda^a  a! a^|a|                 (local coefficients)
+// Then, with tau = (x_child - x_parent)/a_parent in {-1/4, +1/4}^3 and o = (x_w - x_w')/a:
+//     P2M  M^b       = f a^3 kappa_b,  kappa_b = (1/8) sum_g xi_g^b / b!  (2x2x2 Gauss nodes xi_g)
+//     M2M  M_P^b     = sum_c sum_{g<=b} (-tau_c)^(b-g)/(b-g)! 2^-|g| M_c^g
+//     M2L  Lambda^a += a^-1 sum_{|b|<=q-|a|} D^{a+b}g(o) M^b,  g = 1/(4 pi |.|)
+//     L2L  Lambda_c^a += 2^-|a| sum_{b>=a} tau_c^(b-a)/(b-a)! Lambda_P^b
+//     L2P  u_w      += a^3 sum_a kappa_a Lambda^a
+// The near field adds, per leaf w, sum over N*(w) of A_{w s} f_s, with A_{w s} the exact
+// touching integral C_class a_small^5/(4 pi) or the 2x2x2 x 2x2x2 point rule.
+#include <utility>
+
+#include "kernels.hpp"
+#include "multiindex.hpp"
+
+namespace bcv {
+namespace {
+
+constexpr int kWave = 64;
+constexpr double kNode0 = 0.21132486540518711775;  // 1/2 - 1/(2 sqrt 3): 2-point Gauss on [0,1]
+constexpr double kNode1 = 0.78867513459481288225;  // 1/2 + 1/(2 sqrt 3)
+constexpr double kInv4Pi = 0.079577471545947667884;
+
+template <int Q>
+struct Tables {
+    static constexpr MultiIndex<Q> mi{};
+};
+
+// mu(e)/e! with mu(e) = (1/2)(xi^e + (-xi)^e), xi = 1/(2 sqrt 3), xi^2 = 1/12: the per-axis factor
+// of kappa.
+__host__ __device__ constexpr double kappa_axis(int e)
+{
+    if (e & 1) return 0.0;
+    double v = 1.0;
+    for (int t = 2; t <= e; t += 2) v /= 12.0;
+    for (int t = 2; t <= e; ++t) v /= (double)t;
+    return v;
+}
+
+// (s/4)^k / k! with s = +-1.
+__device__ __forceinline__ double quarter_pow_over_fact(int k, double s)
+{
+    double v = 1.0;
+    for (int t = 1; t <= k; ++t) v *= s * 0.25 / (double)t;
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+struct TouchValues {
+    double v[kTouchClasses];  // C_class / (4 pi), smaller side 1
+};
+
+// sum_{g in t} sum_{g' in s} w_g w_g' G(x_g, y_g') with the 2x2x2 rule on both cubes.
+__device__ __forceinline__ double point_rule(const double4 gt, const double4 gs)
+{
+    double d2[3][4];
+    const double lt[3] = {gt.x, gt.y, gt.z}, ls[3] = {gs.x, gs.y, gs.z};
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const double x0 = lt[ax] + gt.w * kNode0, x1 = lt[ax] + gt.w * kNode1;
+        const double y0 = ls[ax] + gs.w * kNode0, y1 = ls[ax] + gs.w * kNode1;
+        const double d[4] = {x0 - y0, x0 - y1, x1 - y0, x1 - y1};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) d2[ax][m] = d[m] * d[m];
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const double xy = d2[0][a] + d2[1][b];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) s += rsqrt(xy + d2[2][c]);
+        }
+    const double wt = gt.w * gt.w * gt.w * 0.125, ws = gs.w * gs.w * gs.w * 0.125;
+    return s * wt * ws * kInv4Pi;
+}
+
+__device__ __forceinline__ double near_entry(uint32_t code, const double4 gt, const double4 *__restrict__ geom,
+                                             const TouchValues &tv)
+{
+    const int32_t s = (int32_t)(code & 0x0FFFFFFFu);
+    const uint32_t cls = code >> 28;
+    const double4 gs = geom[s];
+    if (cls) {
+        const double a = fmin(gt.w, gs.w);
+        return tv.v[cls - 1] * (a * a) * (a * a) * a;
+    }
+    return point_rule(gt, gs);
+}
+
+// ---- P2M: M^b = f a^3 kappa_b on every leaf ------------------------------------------------------
+template <int Q>
+__global__ void p2m_kernel(int64_t n_leaves, const int32_t *__restrict__ leaf_cell, const double4 *__restrict__ geom,
+                           const double *__restrict__ f, double *__restrict__ M)
+{
+    constexpr auto &mi = Tables<Q>::mi;
+    constexpr int K = MultiIndex<Q>::K;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t leaf = idx / K;
+    const int b = (int)(idx - leaf * K);
+    if (leaf >= n_leaves) return;
+    const double a = geom[leaf].w;
+    const double kap = kappa_axis(mi.e[b][0]) * kappa_axis(mi.e[b][1]) * kappa_axis(mi.e[b][2]);
+    M[(int64_t)leaf_cell[leaf] * K + b] = f[leaf] * (a * a * a) * kap;
+}
+
+// ---- M2M: one thread per (marked cell of one level, coefficient) ---------------------------------
+template <int Q>
+__global__ void m2m_kernel(int n_par, const int32_t *__restrict__ parents, double *__restrict__ M)
+{
+    constexpr auto &mi = Tables<Q>::mi;
+    constexpr int K = MultiIndex<Q>::K;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int pi = (int)(idx / K);
+    const int b = (int)(idx - (int64_t)pi * K);
+    if (pi >= n_par) return;
+    const int32_t cell = parents[2 * pi], child0 = parents[2 * pi + 1];
+    const int b0 = mi.e[b][0], b1 = mi.e[b][1], b2 = mi.e[b][2];
+    double acc = 0.0;
+    for (int c = 0; c < 8; ++c) {
+        // -tau = +1/4 for a child in the lower half of an axis, -1/4 in the upper half
+        const double s0 = (c & 1) ? -1.0 : 1.0, s1 = (c & 2) ? -1.0 : 1.0, s2 = (c & 4) ? -1.0 : 1.0;
+        const double *__restrict__ Mc = M + (int64_t)(child0 + c) * K;
+        for (int g0 = 0; g0 <= b0; ++g0) {
+            const double f0 = quarter_pow_over_fact(b0 - g0, s0);
+            for (int g1 = 0; g1 <= b1; ++g1) {
+                const double f01 = f0 * quarter_pow_over_fact(b1 - g1, s1);
+                for (int g2 = 0; g2 <= b2; ++g2) {
+                    const double w = f01 * quarter_pow_over_fact(b2 - g2, s2) * ldexp(1.0, -(g0 + g1 + g2));
+                    acc = fma(w, Mc[mi_index(g0, g1, g2)], acc);
+                }
+            }
+        }
+    }
+    M[(int64_t)cell * K + b] = acc;
+}
+
+// ---- M2L: 64 targets per wave, one uniform interaction offset per slot --------------------------
+// acc[a] += D^{a+b} g(o) * M_s^b for all |a| + |b| <= Q, straight-line code from the index tables.
+template <int Q, int B, int... A>
+__device__ __forceinline__ void m2l_column(double *acc, const double *__restrict__ G, double mb,
+                                           std::integer_sequence<int, A...>)
+{
+    constexpr auto &mi = Tables<Q>::mi;
+    ((acc[A] = fma(G[mi.sum(A, B)], mb, acc[A])), ...);
+}
+
+template <int Q, int... B>
+__device__ __forceinline__ void m2l_all(double *acc, const double *__restrict__ G, const double *__restrict__ Ms,
+                                        std::integer_sequence<int, B...>)
+{
+    constexpr auto &mi = Tables<Q>::mi;
+    (m2l_column<Q, B>(acc, G, Ms[B], std::make_integer_sequence<int, ncoef(Q - mi.deg[B])>{}), ...);
+}
+
+template <int Q>
+__global__ __launch_bounds__(kWave) void m2l_kernel(const M2LTask *__restrict__ tasks,
+                                                   const int32_t *__restrict__ targets,
+                                                   const int32_t *__restrict__ slot_off,
+                                                   const int32_t *__restrict__ slot_src,
+                                                   const double *__restrict__ G, const double *__restrict__ M,
+                                                   double *__restrict__ Lam)
+{
+    constexpr int K = MultiIndex<Q>::K;
+    const M2LTask task = tasks[blockIdx.x];
+    const int lane = threadIdx.x;
+    double acc[K];
+#pragma unroll
+    for (int a = 0; a < K; ++a) acc[a] = 0.0;
+    for (int j = 0; j < task.n_slots; ++j) {
+        const int64_t slot = (int64_t)task.slot_begin + j;
+        const double *__restrict__ Gs = G + (int64_t)slot_off[slot] * K;
+        const double *__restrict__ Ms = M + (int64_t)slot_src[slot * kWave + lane] * K;
+        m2l_all<Q>(acc, Gs, Ms, std::make_integer_sequence<int, K>{});
+    }
+    const int32_t t = targets[(int64_t)blockIdx.x * kWave + lane];
+    if (t < 0) return;
+    const double inv_a = ldexp(1.0, task.level);
+#pragma unroll
+    for (int a = 0; a < K; ++a) Lam[(int64_t)t * K + a] = acc[a] * inv_a;
+}
+
+// ---- L2L: one thread per (child of a marked cell of one level, coefficient) ---------------------
+template <int Q>
+__global__ void l2l_kernel(int n_par, const int32_t *__restrict__ parents, double *__restrict__ Lam)
+{
+    constexpr auto &mi = Tables<Q>::mi;
+    constexpr int K = MultiIndex<Q>::K;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t pc = idx / K;
+    const int a = (int)(idx - pc * K);
+    const int pi = (int)(pc >> 3), c = (int)(pc & 7);
+    if (pi >= n_par) return;
+    const int32_t cell = parents[2 * pi], child = parents[2 * pi + 1] + c;
+    const double *__restrict__ LP = Lam + (int64_t)cell * K;
+    // tau = -1/4 for a child in the lower half of an axis, +1/4 in the upper half
+    const double s0 = (c & 1) ? 1.0 : -1.0, s1 = (c & 2) ? 1.0 : -1.0, s2 = (c & 4) ? 1.0 : -1.0;
+    const int a0 = mi.e[a][0], a1 = mi.e[a][1], a2 = mi.e[a][2];
+    const int rest = Q - mi.deg[a];
+    double acc = 0.0;
+    for (int d0 = 0; d0 <= rest; ++d0) {
+        const double f0 = quarter_pow_over_fact(d0, s0);
+        for (int d1 = 0; d1 <= rest - d0; ++d1) {
+            const double f01 = f0 * quarter_pow_over_fact(d1, s1);
+            for (int d2 = 0; d2 <= rest - d0 - d1; ++d2)
+                acc = fma(f01 * quarter_pow_over_fact(d2, s2), LP[mi_index(a0 + d0, a1 + d1, a2 + d2)], acc);
+        }
+    }
+    Lam[(int64_t)child * K + a] += acc * ldexp(1.0, -mi.deg[a]);
+}
+
+// ---- near field + evaluation: one wave per target leaf -------------------------------------------
+template <int Q, bool kAssembled>
+__global__ __launch_bounds__(256) void near_eval_kernel(int64_t n_leaves, const int64_t *__restrict__ row,
+                                                        const uint32_t *__restrict__ col,
+                                                        const double *__restrict__ val,
+                                                        const double4 *__restrict__ geom,
+                                                        const double *__restrict__ f,
+                                                        const double *__restrict__ Lam,
+                                                        const int32_t *__restrict__ leaf_cell, TouchValues tv,
+                                                        int parts, double *__restrict__ u)
+{
+    constexpr auto &mi = Tables<Q>::mi;
+    constexpr int K = MultiIndex<Q>::K;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t t = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (t >= n_leaves) return;  // uniform per wave
+    const double4 gt = geom[t];
+    double acc = 0.0;
+    if (parts & BCV_PART_NEAR) {
+        const int64_t e1 = row[t + 1];
+        for (int64_t e = row[t] + lane; e < e1; e += kWave) {
+            const uint32_t code = col[e];
+            const double v = kAssembled ? val[e] : near_entry(code, gt, geom, tv);
+            acc = fma(v, f[code & 0x0FFFFFFFu], acc);
+        }
+    }
+    if ((parts & BCV_PART_FAR) && Lam != nullptr) {
+        const double *__restrict__ lam = Lam + (int64_t)leaf_cell[t] * K;
+        double s = 0.0;
+        for (int a = lane; a < K; a += kWave)
+            s = fma(kappa_axis(mi.e[a][0]) * kappa_axis(mi.e[a][1]) * kappa_axis(mi.e[a][2]), lam[a], s);
+        acc = fma(s, gt.w * gt.w * gt.w, acc);
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) u[t] = acc;
+}
+
+// ---- plan-time assembly of the near-pair entries --------------------------------------------------
+__global__ __launch_bounds__(256) void near_assemble_kernel(int64_t n_leaves, const int64_t *__restrict__ row,
+                                                            const uint32_t *__restrict__ col,
+                                                            const double4 *__restrict__ geom, TouchValues tv,
+                                                            double *__restrict__ val)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t t = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (t >= n_leaves) return;
+    const double4 gt = geom[t];
+    for (int64_t e = row[t] + lane; e < row[t + 1]; e += kWave) val[e] = near_entry(col[e], gt, geom, tv);
+}
+
+// ---- regular cube pairs (touching-integral self-similarity system) -------------------------------
+constexpr int kMaxGauss = 16;
+struct GaussRule {
+    double x[kMaxGauss], w[kMaxGauss];
+};
+
+__global__ __launch_bounds__(256) void regular_cube_pairs_kernel(const int *__restrict__ deltas, int n_gauss,
+                                                                 GaussRule rule, double *__restrict__ out)
+{
+    __shared__ double part[256];
+    const int d0 = deltas[3 * blockIdx.x], d1 = deltas[3 * blockIdx.x + 1], d2 = deltas[3 * blockIdx.x + 2];
+    const int n2 = n_gauss * n_gauss;
+    const int64_t total = (int64_t)n2 * n2 * n2;
+    double s = 0.0;
+    for (int64_t idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int p0 = (int)(idx % n2), p1 = (int)((idx / n2) % n2), p2 = (int)(idx / ((int64_t)n2 * n2));
+        // axis pair (g, h): x = node g of the first cube, y = d + node h of the second
+        const double x0 = rule.x[p0 / n_gauss] - (d0 + rule.x[p0 % n_gauss]);
+        const double x1 = rule.x[p1 / n_gauss] - (d1 + rule.x[p1 % n_gauss]);
+        const double x2 = rule.x[p2 / n_gauss] - (d2 + rule.x[p2 % n_gauss]);
+        const double w = rule.w[p0 / n_gauss] * rule.w[p0 % n_gauss] * rule.w[p1 / n_gauss] * rule.w[p1 % n_gauss] *
+                         rule.w[p2 / n_gauss] * rule.w[p2 % n_gauss];
+        s = fma(w, rsqrt(x0 * x0 + x1 * x1 + x2 * x2), s);
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = part[0];
+}
+
+TouchValues touch_values(const bcv_plan_s &p)
+{
+    TouchValues tv;
+    for (int c = 0; c < kTouchClasses; ++c) tv.v[c] = p.touch_value[c];
+    return tv;
+}
+
+void check_launch()
+{
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) fail(BCV_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+}
+
+// Records phase boundary `k` (0..5) of the current apply if timing is on.
+struct PhaseMarks {
+    const bcv_plan_s &p;
+    hipStream_t st;
+    int slot;
+    PhaseMarks(const bcv_plan_s &plan, hipStream_t s) : p(plan), st(s), slot(-1)
+    {
+        if (p.timing_used < p.timing_cap) slot = p.timing_used++;
+    }
+    void mark(int k) const
+    {
+        if (slot >= 0) BCV_HIP(hipEventRecord(p.events[6 * slot + k], st));
+    }
+};
+
+template <int Q>
+void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStream_t st)
+{
+    constexpr int K = MultiIndex<Q>::K;
+    const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
+    const bool far = (parts & BCV_PART_FAR) && !p.direct;
+    const PhaseMarks marks(p, st);
+    marks.mark(0);
+    if (far) {
+        const int64_t nthr = p.n_leaves * K;
+        p2m_kernel<Q><<<(unsigned)((nthr + 255) / 256), 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, f, p.d_M);
+        check_launch();
+        marks.mark(1);
+        for (int lev = p.L - 1; lev >= 2; --lev) {  // upward pass; moments below level 2 are never used
+            const int n_par = p.parent_begin[lev + 1] - p.parent_begin[lev];
+            if (n_par == 0) continue;
+            const int64_t n = (int64_t)n_par * K;
+            m2m_kernel<Q><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n_par, p.d_parents + 2 * p.parent_begin[lev],
+                                                                        p.d_M);
+            check_launch();
+        }
+        marks.mark(2);
+        if (p.n_tasks > 0) {
+            m2l_kernel<Q><<<(unsigned)p.n_tasks, kWave, 0, st>>>(p.d_tasks, p.d_task_targets, p.d_slot_off,
+                                                                 p.d_slot_src, p.d_G, p.d_M, p.d_Lam);
+            check_launch();
+        }
+        marks.mark(3);
+        for (int lev = 2; lev < p.L; ++lev) {  // downward pass
+            const int n_par = p.parent_begin[lev + 1] - p.parent_begin[lev];
+            if (n_par == 0) continue;
+            const int64_t n = (int64_t)n_par * 8 * K;
+            l2l_kernel<Q><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n_par, p.d_parents + 2 * p.parent_begin[lev],
+                                                                        p.d_Lam);
+            check_launch();
+        }
+    } else {
+        marks.mark(1);
+        marks.mark(2);
+        marks.mark(3);
+    }
+    marks.mark(4);
+    const unsigned blocks = (unsigned)((p.n_leaves + 3) / 4);
+    const double *lam = far ? p.d_Lam : nullptr;
+    const int near_parts = (parts & BCV_PART_NEAR) | (far ? BCV_PART_FAR : 0);
+    if (p.d_val)
+        near_eval_kernel<Q, true><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_row, p.d_col, p.d_val, geom, f, lam,
+                                                          p.d_leaf_cell, touch_values(p), near_parts, u);
+    else
+        near_eval_kernel<Q, false><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_row, p.d_col, nullptr, geom, f, lam,
+                                                           p.d_leaf_cell, touch_values(p), near_parts, u);
+    check_launch();
+    marks.mark(5);
+}
+
+}  // namespace
+
+void launch_apply(const bcv_plan_s &p, const double *f, double *u, int parts, hipStream_t st)
+{
+    switch (p.q) {
+    case 4: apply_q<4>(p, f, u, parts, st); break;
+    case 6: apply_q<6>(p, f, u, parts, st); break;
+    default: fail(BCV_ENOTSUP, "expansion order not compiled");
+    }
+}
+
+void launch_near_assemble(const bcv_plan_s &p, hipStream_t st)
+{
+    const unsigned blocks = (unsigned)((p.n_leaves + 3) / 4);
+    near_assemble_kernel<<<blocks, 256, 0, st>>>(p.n_leaves, p.d_row, p.d_col,
+                                                 reinterpret_cast<const double4 *>(p.d_leaf_geom), touch_values(p),
+                                                 p.d_val);
+    check_launch();
+}
+
+void gauss_legendre01(int n, double *x, double *w);
+
+void regular_cube_pairs(const int *deltas, int n, int n_gauss, double *out)
+{
+    BCV_REQUIRE(n_gauss >= 1 && n_gauss <= kMaxGauss, BCV_EINVAL, "bad Gauss order");
+    GaussRule rule{};
+    gauss_legendre01(n_gauss, rule.x, rule.w);
+    int *d_deltas = nullptr;
+    double *d_out = nullptr;
+    BCV_HIP(hipMalloc(&d_deltas, sizeof(int) * 3 * n));
+    BCV_HIP(hipMalloc(&d_out, sizeof(double) * n));
+    BCV_HIP(hipMemcpy(d_deltas, deltas, sizeof(int) * 3 * n, hipMemcpyHostToDevice));
+    regular_cube_pairs_kernel<<<n, 256>>>(d_deltas, n_gauss, rule, d_out);
+    const hipError_t e = hipGetLastError();
+    hipError_t e2 = hipMemcpy(out, d_out, sizeof(double) * n, hipMemcpyDeviceToHost);
+    (void)hipFree(d_deltas);
+    (void)hipFree(d_out);
+    BCV_HIP(e);
+    BCV_HIP(e2);
+}
+
+}  // namespace bcv

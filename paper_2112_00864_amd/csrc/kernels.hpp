@@ -1,0 +1,19 @@
+// Launchers of the device kernels (kernels.hip, singular.hip).
+#pragma once
+#include "internal.hpp"
+
+namespace bcv {
+
+// Algorithm 1 on `stream`: moments, upward pass, interaction phase, downward pass, and the
+// near field fused with the evaluation phase. parts: BCV_PART_NEAR | BCV_PART_FAR.
+void launch_apply(const bcv_plan_s &p, const double *f, double *u, int parts, hipStream_t stream);
+
+// Stores every near-pair Galerkin entry of the plan in p.d_val (plan time).
+void launch_near_assemble(const bcv_plan_s &p, hipStream_t stream);
+
+// int_{[0,1]^3} int_{delta+[0,1]^3} 1/|x-y| dy dx for n non-touching integer offsets (host arrays:
+// deltas 3 per offset, out n), by an n_gauss-point Gauss-Legendre rule in each of the six variables,
+// on the current device.
+void regular_cube_pairs(const int *deltas, int n, int n_gauss, double *out);
+
+}  // namespace bcv

@@ -1,0 +1,452 @@
+// Interaction plan of the BC-FMM (Sec. 3 of the paper), built on the host and uploaded once.
+//
+//  * Neighbours N(w) (eq. def:neighbors): same-level cubes at integer offset o with
+//    eta = sqrt(3)/|o| > eta0 = 1/2, i.e. |o|^2 < 12 (rho = a sqrt(3)/2 from eq. def:diam).
+//  * Interaction lists I(w): children of the parent's neighbours that are not neighbours of w.
+//  * Near field of a leaf w: N*(w) = N_M(w) plus N_L(pi_l(w)) for every ancestor level l
+//    (Sec. 3, before Lemma 1); a marked cell of N_M(w) stands for all of its leaves. The
+//    decomposition eq. spaceDecomp:OmOm then covers every ordered leaf pair exactly once.
+//  * Near pairs whose closed cubes touch get one of seven singular classes; all others use the
+//    2x2x2 point rule on both cells.
+//  * M2L work is packed into 64-lane tasks: 64 targets of one level sharing their position in
+//    the parent, so that each interaction offset of the union of their lists is valid for every
+//    lane that has a source there; the lanes of a slot share the offset (one derivative table)
+//    and each lane reads its own source moments.
+#include <omp.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+#include "multiindex.hpp"
+
+namespace bcv {
+
+void derivative_table(int q, const int o[3], double *out);
+void touching_integrals(int device, double out[kTouchClasses]);
+
+namespace {
+
+struct Grid {  // dense (i, j, k) -> cell index of one level
+    int n = 0;
+    std::vector<int32_t> idx;
+    int32_t at(int i, int j, int k) const
+    {
+        if (i < 0 || j < 0 || k < 0 || i >= n || j >= n || k >= n) return -1;
+        return idx[((size_t)k * n + j) * n + i];
+    }
+};
+
+std::vector<Grid> make_grids(const bcv_tree_s &t)
+{
+    std::vector<Grid> g(t.L + 1);
+    for (int lev = 0; lev <= t.L; ++lev) {
+        g[lev].n = 1 << lev;
+        g[lev].idx.assign((size_t)g[lev].n * g[lev].n * g[lev].n, -1);
+        for (int32_t c = t.lvl_start[lev]; c < t.lvl_start[lev + 1]; ++c)
+            g[lev].idx[((size_t)t.ijk[3 * c + 2] * g[lev].n + t.ijk[3 * c + 1]) * g[lev].n + t.ijk[3 * c]] = c;
+    }
+    return g;
+}
+
+bool is_neighbour_offset(int a, int b, int c) { return a * a + b * b + c * c < 12; }
+
+const std::vector<std::array<int, 3>> &stencil()
+{
+    static const std::vector<std::array<int, 3>> s = [] {
+        std::vector<std::array<int, 3>> v;
+        for (int c = -3; c <= 3; ++c)
+            for (int b = -3; b <= 3; ++b)
+                for (int a = -3; a <= 3; ++a)
+                    if (is_neighbour_offset(a, b, c)) v.push_back({a, b, c});
+        return v;
+    }();
+    return s;
+}
+
+constexpr uint32_t kBadTouch = 15u;
+
+// Touch code of two cubes given at level-L resolution: 0 if the closed cubes are disjoint, else
+// 1 + class (0 self, 1 face, 2 edge, 3 vertex with equal sides; 4 face, 5 edge, 6 vertex with
+// sides 1:2). The mesh is 2:1 balanced, so any other touching pair (kBadTouch) is an internal error.
+uint32_t touch_code(const int64_t lo_a[3], int64_t sa, const int64_t lo_b[3], int64_t sb)
+{
+    int contacts = 0;
+    for (int ax = 0; ax < 3; ++ax) {
+        const int64_t lo = std::max(lo_a[ax], lo_b[ax]);
+        const int64_t hi = std::min(lo_a[ax] + sa, lo_b[ax] + sb);
+        if (lo > hi) return 0;
+        if (lo == hi) ++contacts;
+    }
+    if (sa == sb) return 1u + (uint32_t)contacts;
+    if (std::max(sa, sb) != 2 * std::min(sa, sb) || contacts == 0) return kBadTouch;
+    return 4u + (uint32_t)contacts;
+}
+
+struct LeafGeo {
+    std::vector<int64_t> lo;  // 3 per leaf, level-L resolution
+    std::vector<int64_t> size;
+};
+
+LeafGeo leaf_geometry(const bcv_tree_s &t)
+{
+    LeafGeo g;
+    const int64_t n = t.n_leaves();
+    g.lo.resize(3 * n);
+    g.size.resize(n);
+    for (int64_t l = 0; l < n; ++l) {
+        const int32_t c = t.leaf_cell[l];
+        const int s = t.L - t.level[c];
+        for (int ax = 0; ax < 3; ++ax) g.lo[3 * l + ax] = (int64_t)t.ijk[3 * c + ax] << s;
+        g.size[l] = (int64_t)1 << s;
+    }
+    return g;
+}
+
+// Leaves y with (w, y) in w x N*(w) for the leaf cell w (marked sources expanded to leaves).
+void near_sources(const bcv_tree_s &t, const std::vector<Grid> &g, int32_t cell, std::vector<int32_t> &out,
+                  std::vector<int32_t> &stack)
+{
+    out.clear();
+    const int lev = t.level[cell];
+    const int i = t.ijk[3 * cell], j = t.ijk[3 * cell + 1], k = t.ijk[3 * cell + 2];
+    for (const auto &o : stencil()) {  // N(w) = N_L(w) + N_M(w)
+        const int32_t s = g[lev].at(i + o[0], j + o[1], k + o[2]);
+        if (s < 0) continue;
+        if (!t.refined[s]) {
+            out.push_back(t.leaf_of_cell[s]);
+            continue;
+        }
+        stack.assign(1, s);  // all leaves below a marked neighbour
+        while (!stack.empty()) {
+            const int32_t c = stack.back();
+            stack.pop_back();
+            if (!t.refined[c]) {
+                out.push_back(t.leaf_of_cell[c]);
+            } else {
+                for (int ch = 7; ch >= 0; --ch) stack.push_back(t.first_child[c] + ch);
+            }
+        }
+    }
+    for (int lp = lev - 1; lp >= 0; --lp) {  // N_L of every proper ancestor
+        const int sh = lev - lp;
+        const int ai = i >> sh, aj = j >> sh, ak = k >> sh;
+        for (const auto &o : stencil()) {
+            const int32_t s = g[lp].at(ai + o[0], aj + o[1], ak + o[2]);
+            if (s >= 0 && !t.refined[s]) out.push_back(t.leaf_of_cell[s]);
+        }
+    }
+}
+
+struct NearCSR {
+    std::vector<int64_t> row;
+    std::vector<uint32_t> col;
+    int64_t n_touch = 0;
+};
+
+NearCSR build_near(const bcv_tree_s &t, const std::vector<Grid> &g, const LeafGeo &geo, bool direct)
+{
+    const int64_t nl = t.n_leaves();
+    NearCSR r;
+    r.row.assign(nl + 1, 0);
+    auto gen = [&](int64_t n, std::vector<int32_t> &src, std::vector<int32_t> &stack) {
+        if (direct) {
+            src.resize(nl);
+            for (int64_t s = 0; s < nl; ++s) src[s] = (int32_t)s;
+        } else {
+            near_sources(t, g, t.leaf_cell[n], src, stack);
+        }
+    };
+#pragma omp parallel
+    {
+        std::vector<int32_t> src, stack;
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t n = 0; n < nl; ++n) {
+            gen(n, src, stack);
+            r.row[n + 1] = (int64_t)src.size();
+        }
+    }
+    for (int64_t n = 0; n < nl; ++n) r.row[n + 1] += r.row[n];
+    r.col.resize(r.row[nl]);
+    int64_t touch = 0, bad = 0;
+#pragma omp parallel reduction(+ : touch, bad)
+    {
+        std::vector<int32_t> src, stack;
+        std::vector<uint32_t> codes;
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t n = 0; n < nl; ++n) {
+            gen(n, src, stack);
+            codes.resize(src.size());
+            for (size_t e = 0; e < src.size(); ++e) {
+                const int32_t s = src[e];
+                const uint32_t tc = touch_code(&geo.lo[3 * n], geo.size[n], &geo.lo[3 * s], geo.size[s]);
+                bad += tc == kBadTouch;
+                touch += tc != 0;
+                codes[e] = (uint32_t)s | (tc << 28);
+            }
+            // touching pairs first (they are cheap), then by source leaf
+            std::sort(codes.begin(), codes.end(), [](uint32_t a, uint32_t b) {
+                const bool ta = (a >> 28) != 0, tb = (b >> 28) != 0;
+                if (ta != tb) return ta;
+                return (a & 0x0FFFFFFFu) < (b & 0x0FFFFFFFu);
+            });
+            std::copy(codes.begin(), codes.end(), r.col.begin() + r.row[n]);
+        }
+    }
+    if (bad) fail(BCV_ESTATE, "internal: touching leaves violate 2:1 balance");
+    r.n_touch = touch;
+    return r;
+}
+
+struct M2LPlan {
+    std::vector<M2LTask> tasks;
+    std::vector<int32_t> targets;   // 64 per task
+    std::vector<int32_t> slot_key;  // offset key per slot, later replaced by the offset id
+    std::vector<int32_t> slot_src;  // 64 per slot
+    int64_t n_pairs = 0;
+};
+
+int offset_key(int a, int b, int c) { return ((a + 7) * 15 + (b + 7)) * 15 + (c + 7); }
+
+M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g)
+{
+    M2LPlan m;
+    const int32_t zero_row = (int32_t)t.n_cells();
+    struct Chunk {
+        int lev;
+        std::vector<int32_t> cells;
+    };
+    std::vector<Chunk> chunks;
+    for (int lev = 2; lev <= t.L; ++lev) {
+        std::vector<int32_t> by_pos[8];
+        for (int32_t c = t.lvl_start[lev]; c < t.lvl_start[lev + 1]; ++c) {
+            const int pos = (t.ijk[3 * c] & 1) | ((t.ijk[3 * c + 1] & 1) << 1) | ((t.ijk[3 * c + 2] & 1) << 2);
+            by_pos[pos].push_back(c);
+        }
+        for (int pos = 0; pos < 8; ++pos)
+            for (size_t b = 0; b < by_pos[pos].size(); b += 64) {
+                Chunk ch{lev, {}};
+                ch.cells.assign(by_pos[pos].begin() + b, by_pos[pos].begin() + std::min(b + 64, by_pos[pos].size()));
+                chunks.push_back(std::move(ch));
+            }
+    }
+    struct Out {
+        std::vector<int32_t> keys, src;
+        int64_t pairs = 0;
+    };
+    std::vector<Out> outs(chunks.size());
+#pragma omp parallel for schedule(dynamic, 4)
+    for (size_t q = 0; q < chunks.size(); ++q) {
+        const Chunk &ch = chunks[q];
+        const int lev = ch.lev;
+        std::vector<char> used(15 * 15 * 15, 0);
+        for (int32_t c : ch.cells) {  // union of the interaction offsets of the chunk
+            const int i = t.ijk[3 * c], j = t.ijk[3 * c + 1], k = t.ijk[3 * c + 2];
+            for (const auto &o : stencil()) {
+                const int32_t pn = g[lev - 1].at((i >> 1) + o[0], (j >> 1) + o[1], (k >> 1) + o[2]);
+                if (pn < 0 || !t.refined[pn]) continue;
+                for (int d = 0; d < 8; ++d) {
+                    const int32_t s = t.first_child[pn] + d;
+                    const int a = i - t.ijk[3 * s], b = j - t.ijk[3 * s + 1], cc = k - t.ijk[3 * s + 2];
+                    if (!is_neighbour_offset(a, b, cc)) used[offset_key(a, b, cc)] = 1;
+                }
+            }
+        }
+        Out &o = outs[q];
+        for (int key = 0; key < 15 * 15 * 15; ++key) {
+            if (!used[key]) continue;
+            const int a = key / 225 - 7, b = (key / 15) % 15 - 7, cc = key % 15 - 7;
+            o.keys.push_back(key);
+            for (int lane = 0; lane < 64; ++lane) {
+                int32_t s = -1;
+                if (lane < (int)ch.cells.size()) {
+                    const int32_t c = ch.cells[lane];
+                    s = g[lev].at(t.ijk[3 * c] - a, t.ijk[3 * c + 1] - b, t.ijk[3 * c + 2] - cc);
+                }
+                o.pairs += s >= 0;
+                o.src.push_back(s >= 0 ? s : zero_row);
+            }
+        }
+    }
+    for (size_t q = 0; q < chunks.size(); ++q) {
+        M2LTask task;
+        task.slot_begin = (int32_t)m.slot_key.size();
+        task.n_slots = (int32_t)outs[q].keys.size();
+        task.level = chunks[q].lev;
+        task.pad = 0;
+        m.tasks.push_back(task);
+        for (int lane = 0; lane < 64; ++lane)
+            m.targets.push_back(lane < (int)chunks[q].cells.size() ? chunks[q].cells[lane] : -1);
+        m.slot_key.insert(m.slot_key.end(), outs[q].keys.begin(), outs[q].keys.end());
+        m.slot_src.insert(m.slot_src.end(), outs[q].src.begin(), outs[q].src.end());
+        m.n_pairs += outs[q].pairs;
+    }
+    return m;
+}
+
+template <class T>
+T *upload(bcv_plan_s *p, const std::vector<T> &v)
+{
+    if (v.empty()) return nullptr;
+    T *d = nullptr;
+    const size_t bytes = v.size() * sizeof(T);
+    if (hipMalloc(&d, bytes) != hipSuccess) fail(BCV_ENOMEM, "hipMalloc failed for a plan buffer");
+    p->device_bytes += (int64_t)bytes;
+    BCV_HIP(hipMemcpy(d, v.data(), bytes, hipMemcpyHostToDevice));
+    return d;
+}
+
+template <class T>
+T *alloc_zero(bcv_plan_s *p, size_t count)
+{
+    T *d = nullptr;
+    const size_t bytes = count * sizeof(T);
+    if (hipMalloc(&d, bytes) != hipSuccess) fail(BCV_ENOMEM, "hipMalloc failed for plan workspace");
+    p->device_bytes += (int64_t)bytes;
+    BCV_HIP(hipMemset(d, 0, bytes));
+    return d;
+}
+
+}  // namespace
+
+void destroy_plan(bcv_plan_s *p);
+
+bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int device)
+{
+    BCV_HIP(hipSetDevice(device));
+    std::unique_ptr<bcv_plan_s, void (*)(bcv_plan_s *)> p(new bcv_plan_s, destroy_plan);
+    p->device = device;
+    p->L = t.L;
+    p->q = opts.q;
+    p->K = ncoef(opts.q);
+    p->direct = opts.direct;
+    p->nearfield = opts.nearfield;
+    p->n_leaves = t.n_leaves();
+    p->n_cells = t.n_cells();
+    BCV_REQUIRE(p->n_leaves < (1 << 28), BCV_ENOTSUP, "more than 2^28 leaves");
+    if (opts.direct) BCV_REQUIRE(p->n_leaves <= 20000, BCV_EINVAL, "direct mode is limited to 20000 leaves");
+
+    double touch[kTouchClasses];
+    touching_integrals(device, touch);
+    for (int c = 0; c < kTouchClasses; ++c) p->touch_value[c] = touch[c] / (4.0 * M_PI);
+
+    const std::vector<Grid> grids = make_grids(t);
+    const LeafGeo geo = leaf_geometry(t);
+
+    // Leaf geometry (lower corner and side, exact dyadic values) and leaf -> cell map.
+    std::vector<double> lg(4 * p->n_leaves);
+    for (int64_t l = 0; l < p->n_leaves; ++l) {
+        const int32_t c = t.leaf_cell[l];
+        const double a = std::ldexp(1.0, -t.level[c]);
+        for (int ax = 0; ax < 3; ++ax) lg[4 * l + ax] = t.ijk[3 * c + ax] * a;
+        lg[4 * l + 3] = a;
+    }
+    p->d_leaf_geom = upload(p.get(), lg);
+    p->d_leaf_cell = upload(p.get(), t.leaf_cell);
+
+    {
+        NearCSR near = build_near(t, grids, geo, opts.direct != 0);
+        p->n_near = (int64_t)near.col.size();
+        p->n_touch = near.n_touch;
+        p->d_row = upload(p.get(), near.row);
+        p->d_col = upload(p.get(), near.col);
+    }
+
+    if (!opts.direct) {
+        // Per-level lists of marked cells for the upward and downward passes.
+        std::vector<int32_t> parents;
+        p->parent_begin.assign(t.L + 2, 0);
+        for (int lev = 0; lev <= t.L; ++lev) {
+            p->parent_begin[lev] = (int32_t)parents.size() / 2;
+            for (int32_t c = t.lvl_start[lev]; c < t.lvl_start[lev + 1]; ++c)
+                if (t.refined[c]) {
+                    parents.push_back(c);
+                    parents.push_back(t.first_child[c]);
+                }
+        }
+        p->parent_begin[t.L + 1] = (int32_t)parents.size() / 2;
+        p->d_parents = upload(p.get(), parents);
+
+        M2LPlan m2l = build_m2l(t, grids);
+        std::vector<int32_t> id_of_key(15 * 15 * 15, -1);
+        for (int32_t key : m2l.slot_key) id_of_key[key] = 0;
+        std::vector<double> G;
+        int32_t n_off = 0;
+        for (int key = 0; key < 15 * 15 * 15; ++key) {
+            if (id_of_key[key] < 0) continue;
+            id_of_key[key] = n_off++;
+            const int o[3] = {key / 225 - 7, (key / 15) % 15 - 7, key % 15 - 7};
+            const size_t at = G.size();
+            G.resize(at + p->K);
+            derivative_table(p->q, o, &G[at]);
+        }
+        for (int32_t &s : m2l.slot_key) s = id_of_key[s];
+        p->n_offsets = n_off;
+        p->n_m2l = m2l.n_pairs;
+        p->n_m2l_lanes = (int64_t)m2l.slot_key.size() * 64;
+        p->n_tasks = (int64_t)m2l.tasks.size();
+        p->d_G = upload(p.get(), G);
+        p->d_tasks = upload(p.get(), m2l.tasks);
+        p->d_task_targets = upload(p.get(), m2l.targets);
+        p->d_slot_off = upload(p.get(), m2l.slot_key);
+        p->d_slot_src = upload(p.get(), m2l.slot_src);
+        p->d_M = alloc_zero<double>(p.get(), (size_t)(p->n_cells + 1) * p->K);
+        p->d_Lam = alloc_zero<double>(p.get(), (size_t)p->n_cells * p->K);
+    }
+
+    if (opts.nearfield == BCV_NEAR_ASSEMBLED) {
+        p->d_val = alloc_zero<double>(p.get(), (size_t)p->n_near);
+        launch_near_assemble(*p, nullptr);
+        BCV_HIP(hipDeviceSynchronize());
+    }
+    BCV_HIP(hipDeviceSynchronize());
+    return p.release();
+}
+
+void destroy_plan(bcv_plan_s *p)
+{
+    if (!p) return;
+    (void)hipSetDevice(p->device);
+    for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
+    void *bufs[] = {p->d_leaf_geom, p->d_leaf_cell, p->d_row, p->d_col, p->d_val, p->d_M, p->d_Lam, p->d_G,
+                    p->d_parents, p->d_tasks, p->d_task_targets, p->d_slot_off, p->d_slot_src};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    p->magic = 0;
+    delete p;
+}
+
+void set_timing(bcv_plan_s *p, int max_applies)
+{
+    for (hipEvent_t e : p->events) BCV_HIP(hipEventDestroy(e));
+    p->events.clear();
+    p->timing_cap = 0;
+    p->timing_used = 0;
+    for (int64_t n = 0; n < 6 * (int64_t)max_applies; ++n) {
+        hipEvent_t e;
+        BCV_HIP(hipEventCreate(&e));
+        p->events.push_back(e);
+    }
+    p->timing_cap = max_applies;
+}
+
+void phase_times(const bcv_plan_s *p, double *ms, int64_t *n)
+{
+    for (int k = 0; k < BCV_N_PHASES; ++k) ms[k] = 0.0;
+    for (int s = 0; s < p->timing_used; ++s) {
+        BCV_HIP(hipEventSynchronize(p->events[6 * s + 5]));
+        for (int k = 0; k < BCV_N_PHASES; ++k) {
+            float t = 0.0f;
+            BCV_HIP(hipEventElapsedTime(&t, p->events[6 * s + k], p->events[6 * s + k + 1]));
+            ms[k] += t;
+        }
+    }
+    *n = p->timing_used;
+}
+
+}  // namespace bcv

@@ -1,0 +1,64 @@
+// BC octree of the unit cube (Sec. 2, Boundary Concentrated Mesh, with cube cells).
+//
+// Level 0 is [0,1]^3. A level-l cell (i, j, k) is the cube [i, i+1] x [j, j+1] x [k, k+1] times 2^-l.
+// For l < L the marked cells M_l are those with a face on the boundary (B_l); the leaves of level l
+// are L_l = C_l minus M_l; C_{l+1} consists of the children of M_l; every level-L cell is a leaf.
+#include <algorithm>
+#include <numeric>
+
+#include "internal.hpp"
+
+namespace bcv {
+
+static bool on_boundary(int lev, int32_t i, int32_t j, int32_t k)
+{
+    const int32_t top = (1 << lev) - 1;
+    return i == 0 || j == 0 || k == 0 || i == top || j == top || k == top;
+}
+
+bcv_tree_s *build_tree(int L)
+{
+    auto *t = new bcv_tree_s;
+    t->L = L;
+    auto push = [&](int32_t i, int32_t j, int32_t k, int lev, int32_t par) {
+        t->ijk.push_back(i);
+        t->ijk.push_back(j);
+        t->ijk.push_back(k);
+        t->level.push_back((int8_t)lev);
+        t->refined.push_back(0);
+        t->parent.push_back(par);
+        t->first_child.push_back(-1);
+        t->leaf_of_cell.push_back(-1);
+    };
+    push(0, 0, 0, 0, -1);
+    t->lvl_start.push_back(0);
+    for (int lev = 0; lev <= L; ++lev) {
+        const int32_t b = t->lvl_start[lev], e = (int32_t)t->level.size();
+        t->lvl_start.push_back(e);  // start of level lev + 1 (children appended below)
+        if (lev == L) break;
+        for (int32_t c = b; c < e; ++c) {
+            const int32_t i = t->ijk[3 * c], j = t->ijk[3 * c + 1], k = t->ijk[3 * c + 2];
+            if (!on_boundary(lev, i, j, k)) continue;
+            t->refined[c] = 1;
+            t->first_child[c] = (int32_t)t->level.size();
+            for (int ch = 0; ch < 8; ++ch)
+                push(2 * i + (ch & 1), 2 * j + ((ch >> 1) & 1), 2 * k + ((ch >> 2) & 1), lev + 1, c);
+        }
+    }
+    // lvl_start now has L + 2 entries: level l occupies [lvl_start[l], lvl_start[l + 1]).
+    std::vector<int32_t> leaves;
+    for (int32_t c = 0; c < (int32_t)t->level.size(); ++c)
+        if (!t->refined[c]) leaves.push_back(c);
+    std::vector<uint64_t> key(t->level.size());
+    for (int32_t c : leaves) {
+        const int s = L - t->level[c];
+        key[c] = morton3((uint32_t)t->ijk[3 * c] << s, (uint32_t)t->ijk[3 * c + 1] << s,
+                         (uint32_t)t->ijk[3 * c + 2] << s, L);
+    }
+    std::sort(leaves.begin(), leaves.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+    t->leaf_cell = leaves;
+    for (size_t n = 0; n < leaves.size(); ++n) t->leaf_of_cell[leaves[n]] = (int32_t)n;
+    return t;
+}
+
+}  // namespace bcv

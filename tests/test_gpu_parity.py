@@ -1,0 +1,130 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, on cuda:0.
+
+Bar (FP64 path): relative L2(Omega) error <= 1e-10 against the oracle computing the same operator
+(O1 for direct mode, O2 for the FMM); expected ~1e-14 (rounding order only).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2112_00864_amd as bcv
+import synth
+from gpu_util import gpu_apply, rel_l2
+from oracle import direct, fmm, touching
+from oracle.mesh import BCMesh
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def announce(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+_MESH = {}
+
+
+def mesh(L):
+    if L not in _MESH:
+        m = BCMesh(L)
+        _MESH[L] = (m, m.leaf_array())
+    return _MESH[L]
+
+
+def test_touching_integrals_match_oracle():
+    announce("bcv_touching_integrals device 0")
+    lib = bcv.touching_integrals(0)
+    ora = touching.constants(40)
+    assert np.max(np.abs(lib - ora) / ora) < 1e-13
+
+
+@pytest.mark.parametrize("L", [2, 3, 4])
+def test_direct_mode_matches_O1(L):
+    m, lv = mesh(L)
+    f = synth.leaf_density(lv, seed=0)
+    announce("direct plan L=%d n=%d" % (L, len(lv)))
+    t = bcv.build_bc_tree(L)
+    plan = bcv.plan_interactions(t, q=4, direct=True)
+    assert plan.info["n_near"] == len(lv) ** 2
+    u = gpu_apply(plan, f)
+    ref = direct.apply(lv, L, f)
+    e = rel_l2(lv, u, ref)
+    announce("direct L=%d rel-L2 %.3e" % (L, e))
+    assert e <= TOL
+    assert np.max(np.abs(u - ref) / np.abs(ref)) < 1e-12
+
+
+@pytest.mark.parametrize("L,q", [(2, 4), (3, 4), (3, 6), (4, 6)])
+def test_fmm_matches_O2(L, q):
+    m, lv = mesh(L)
+    f = synth.leaf_density(lv, seed=1)
+    announce("fmm plan L=%d q=%d n=%d" % (L, q, len(lv)))
+    plan = bcv.plan_interactions(bcv.build_bc_tree(L), q=q)
+    F = fmm.FMM(m, q)
+    near_ref = F.near_field(f, np.arange(len(lv)))
+    full_ref = F.apply(f)
+    u_near = gpu_apply(plan, f, bcv.PART_NEAR)
+    u_far = gpu_apply(plan, f, bcv.PART_FAR)
+    u = gpu_apply(plan, f)
+    e_near = rel_l2(lv, u_near, near_ref)
+    e_far = rel_l2(lv, u_far, full_ref - near_ref)
+    e = rel_l2(lv, u, full_ref)
+    announce("fmm L=%d q=%d rel-L2 near %.3e far %.3e total %.3e" % (L, q, e_near, e_far, e))
+    assert e_near <= TOL and e_far <= TOL and e <= TOL
+    info = plan.info
+    ti, _ = m.near_pairs()
+    assert info["n_near"] == len(ti)
+    assert info["n_m2l"] == len(m.interaction_pairs())
+
+
+def test_assembled_near_field_equals_quadrature():
+    m, lv = mesh(4)
+    f = synth.leaf_density(lv, seed=2)
+    t = bcv.build_bc_tree(4)
+    announce("assembled vs quadrature L=4")
+    a = gpu_apply(bcv.plan_interactions(t, q=6, nearfield=bcv.NEAR_ASSEMBLED), f)
+    b = gpu_apply(bcv.plan_interactions(t, q=6, nearfield=bcv.NEAR_QUADRATURE), f)
+    assert np.max(np.abs(a - b) / np.abs(b)) < 1e-14
+
+
+def test_degenerate_densities():
+    m, lv = mesh(3)
+    plan = bcv.plan_interactions(bcv.build_bc_tree(3), q=6)
+    announce("zero density L=3")
+    assert np.all(gpu_apply(plan, np.zeros(len(lv))) == 0.0)
+    # a single nonzero leaf: the column of the operator, checked against O2 column
+    f = np.zeros(len(lv))
+    f[123] = 1.0
+    announce("unit density on leaf 123, L=3")
+    u = gpu_apply(plan, f)
+    ref = fmm.FMM(m, 6).apply(f)
+    assert np.max(np.abs(u - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_full_size_sampled():
+    """h = 1/128 (219,080 leaves), q = 6: every sampled leaf against O2 evaluated one by one."""
+    L, q = 7, 6
+    m, lv = mesh(L)
+    f = synth.leaf_density(lv, seed=0)
+    announce("full-size plan L=7 q=6 n=%d" % len(lv))
+    plan = bcv.plan_interactions(bcv.build_bc_tree(L), q=q)
+    u = gpu_apply(plan, f)
+    assert np.all(np.isfinite(u))
+    rng = np.random.default_rng(7)
+    sample = np.concatenate([[0, len(lv) - 1], rng.choice(len(lv), 10, replace=False)])
+    announce("oracle O2 on %d sampled leaves" % len(sample))
+    ref = fmm.FMM(m, q).apply_sampled(f, sample)
+    err = np.abs(u[sample] - ref) / np.abs(ref)
+    announce("full-size max rel err %.3e" % err.max())
+    assert err.max() <= TOL
