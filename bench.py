@@ -83,7 +83,20 @@ def main():
     ap.add_argument("--nearfield", choices=["quadrature", "assembled"], default="quadrature")
     ap.add_argument("--cpu-targets", type=int, default=12)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+
+        n = args.calibrate_copy * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_dispatch": n * 8}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the box has one MI355X and this build runs no multi-GPU path",
               file=sys.stderr)
@@ -143,13 +156,15 @@ def main():
                      "unit": "TFLOP/s"}
     m2l_roof = {"bound": "alu", "achieved": m2l_fl / (m2l_ms * 1e-3) / 1e12, "peak": PEAK_FP64 / 1e12,
                 "unit": "TFLOP/s"}
-    if m2l_ms >= near_ms:
-        dom, roof = "m2l_kernel", m2l_roof
-    else:
-        dom, roof = "near_eval_kernel", near_roof
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = dom
+    from paper_2112_00864_amd import profiling
+
+    m2l_name = "m2l_kernel<%d>" % args.q
+    near_name = "near_eval_kernel<%d, %s>" % (args.q, "true" if args.nearfield == "assembled" else "false")
+    for roof_, name in ((m2l_roof, m2l_name), (near_roof, near_name)):
+        roof_["frac"] = roof_["achieved"] / roof_["peak"]
+        roof_["traffic"] = profiling.traffic_for(name)  # HBM bytes per launch (PMC), None if stale
+        roof_["kernel"] = name
+    roof = m2l_roof if m2l_ms >= near_ms else near_roof
 
     cpu = None
     if not args.no_cpu:

@@ -42,12 +42,22 @@ __host__ __device__ constexpr double kappa_axis(int e)
     return v;
 }
 
+// (1/4)^k / k! for k = 0..kMaxOrder (translation coefficients; the sign (-1)^k is applied by the caller).
+constexpr int kMaxOrder = 8;
+struct QuarterTable {
+    double v[kMaxOrder + 1];
+    constexpr QuarterTable() : v{}
+    {
+        v[0] = 1.0;
+        for (int k = 1; k <= kMaxOrder; ++k) v[k] = v[k - 1] * 0.25 / k;
+    }
+};
+__constant__ constexpr QuarterTable kQuarter{};
+
 // (s/4)^k / k! with s = +-1.
 __device__ __forceinline__ double quarter_pow_over_fact(int k, double s)
 {
-    double v = 1.0;
-    for (int t = 1; t <= k; ++t) v *= s * 0.25 / (double)t;
-    return v;
+    return ((k & 1) && s < 0.0) ? -kQuarter.v[k] : kQuarter.v[k];
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -60,6 +70,15 @@ __device__ __forceinline__ double wave_sum(double v)
 struct TouchValues {
     double v[kTouchClasses];  // C_class / (4 pi), smaller side 1
 };
+
+// 1/sqrt(x) for finite x > 0: the hardware estimate (relative error about 5e-8) refined by one
+// Newton step y <- y + y (1 - x y^2) / 2 (relative error below 5e-15, measured on gfx950).
+__device__ __forceinline__ double rsqrt_pos(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-(x * y), y, 1.0);
+    return fma(0.5 * y, e, y);
+}
 
 // sum_{g in t} sum_{g' in s} w_g w_g' G(x_g, y_g') with the 2x2x2 rule on both cubes.
 __device__ __forceinline__ double point_rule(const double4 gt, const double4 gs)
@@ -81,7 +100,7 @@ __device__ __forceinline__ double point_rule(const double4 gt, const double4 gs)
         for (int b = 0; b < 4; ++b) {
             const double xy = d2[0][a] + d2[1][b];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) s += rsqrt(xy + d2[2][c]);
+            for (int c = 0; c < 4; ++c) s += rsqrt_pos(xy + d2[2][c]);
         }
     const double wt = gt.w * gt.w * gt.w * 0.125, ws = gs.w * gs.w * gs.w * 0.125;
     return s * wt * ws * kInv4Pi;
@@ -116,35 +135,136 @@ __global__ void p2m_kernel(int64_t n_leaves, const int32_t *__restrict__ leaf_ce
     M[(int64_t)leaf_cell[leaf] * K + b] = f[leaf] * (a * a * a) * kap;
 }
 
-// ---- M2M: one thread per (marked cell of one level, coefficient) ---------------------------------
-template <int Q>
-__global__ void m2m_kernel(int n_par, const int32_t *__restrict__ parents, double *__restrict__ M)
+// ---- M2M and L2L: one wave per marked cell, separable per-axis shifts through LDS -----------------
+// Both translations are tensor products of 1-D shifts, and stay inside |b| <= Q axis by axis:
+//   M2M  M_P^b  = sum_c prod_i [ sum_{g_i <= b_i} (-tau_i)^(b_i-g_i)/(b_i-g_i)! 2^-g_i ] M_c^g
+//   L2L  Lam_c^a = 2^-|a| prod_i [ sum_{b_i >= a_i} tau_i^(b_i-a_i)/(b_i-a_i)! ] Lam_P^b
+// so the 8 children are combined pairwise along x, then y, then z (M2M), and the parent is
+// expanded along z, then y, then x (L2L): 14 one-dimensional passes per parent instead of 8 full
+// three-dimensional sums.
+constexpr int kTreeWaves = 4;  // parents per 256-thread block
+
+template <int Q, int AX>
+__device__ __forceinline__ int step_index(int a0, int a1, int a2, int v)  // index with component AX replaced by v
+{
+    return AX == 0 ? mi_index(v, a1, a2) : (AX == 1 ? mi_index(a0, v, a2) : mi_index(a0, a1, v));
+}
+
+// out[b] = sum over the two children cs = 0, 1 along axis AX of sum_{g <= b_AX} (-tau)^(b-g)/(b-g)! 2^-g in_cs[.., g, ..]
+template <int Q, int AX>
+__device__ __forceinline__ void m2m_pass(const double *in0, const double *in1, double *out, int lane)
 {
     constexpr auto &mi = Tables<Q>::mi;
     constexpr int K = MultiIndex<Q>::K;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int pi = (int)(idx / K);
-    const int b = (int)(idx - (int64_t)pi * K);
-    if (pi >= n_par) return;
-    const int32_t cell = parents[2 * pi], child0 = parents[2 * pi + 1];
-    const int b0 = mi.e[b][0], b1 = mi.e[b][1], b2 = mi.e[b][2];
-    double acc = 0.0;
-    for (int c = 0; c < 8; ++c) {
-        // -tau = +1/4 for a child in the lower half of an axis, -1/4 in the upper half
-        const double s0 = (c & 1) ? -1.0 : 1.0, s1 = (c & 2) ? -1.0 : 1.0, s2 = (c & 4) ? -1.0 : 1.0;
-        const double *__restrict__ Mc = M + (int64_t)(child0 + c) * K;
-        for (int g0 = 0; g0 <= b0; ++g0) {
-            const double f0 = quarter_pow_over_fact(b0 - g0, s0);
-            for (int g1 = 0; g1 <= b1; ++g1) {
-                const double f01 = f0 * quarter_pow_over_fact(b1 - g1, s1);
-                for (int g2 = 0; g2 <= b2; ++g2) {
-                    const double w = f01 * quarter_pow_over_fact(b2 - g2, s2) * ldexp(1.0, -(g0 + g1 + g2));
-                    acc = fma(w, Mc[mi_index(g0, g1, g2)], acc);
-                }
+    for (int b = lane; b < K; b += kWave) {
+        const int e[3] = {mi.e[b][0], mi.e[b][1], mi.e[b][2]};
+        double acc = 0.0;
+        for (int g = 0; g <= e[AX]; ++g) {
+            const int idx = step_index<Q, AX>(e[0], e[1], e[2], g);
+            const double w = kQuarter.v[e[AX] - g] * ldexp(1.0, -g);
+            // lower child (cs = 0): -tau = +1/4; upper child: -tau = -1/4
+            const double sgn = ((e[AX] - g) & 1) ? -1.0 : 1.0;
+            acc = fma(w, in0[idx] + sgn * in1[idx], acc);
+        }
+        out[b] = acc;
+    }
+}
+
+template <int Q>
+__global__ __launch_bounds__(kWave *kTreeWaves) void m2m_kernel(int n_par, const int32_t *__restrict__ parents,
+                                                                 double *__restrict__ M)
+{
+    constexpr int K = MultiIndex<Q>::K;
+    __shared__ double buf[kTreeWaves][14][K];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int pi = blockIdx.x * kTreeWaves + wave;
+    const bool active = pi < n_par;
+    double(*B)[K] = buf[wave];
+    int32_t cell = 0;
+    if (active) {
+        cell = parents[2 * pi];
+        const double *__restrict__ src = M + (int64_t)parents[2 * pi + 1] * K;  // 8 consecutive children
+        for (int n = lane; n < 8 * K; n += kWave) B[n / K][n % K] = src[n];
+    }
+    __syncthreads();
+    if (active)  // x: children (0,y,z) + (1,y,z) -> 4 vectors, slots 8..11 indexed by y + 2z
+        for (int yz = 0; yz < 4; ++yz) m2m_pass<Q, 0>(B[2 * yz], B[2 * yz + 1], B[8 + yz], lane);
+    __syncthreads();
+    if (active)  // y: slots 8 + (0,z), 8 + (1,z) -> slots 12 + z
+        for (int z = 0; z < 2; ++z) m2m_pass<Q, 1>(B[8 + 2 * z], B[8 + 2 * z + 1], B[12 + z], lane);
+    __syncthreads();
+    if (active) {  // z: slots 12, 13 -> parent moments
+        double out[2];
+        constexpr auto &mi = Tables<Q>::mi;
+        int n = 0;
+        for (int b = lane; b < K; b += kWave, ++n) {
+            const int e[3] = {mi.e[b][0], mi.e[b][1], mi.e[b][2]};
+            double acc = 0.0;
+            for (int g = 0; g <= e[2]; ++g) {
+                const int idx = mi_index(e[0], e[1], g);
+                const double sgn = ((e[2] - g) & 1) ? -1.0 : 1.0;
+                acc = fma(kQuarter.v[e[2] - g] * ldexp(1.0, -g), B[12][idx] + sgn * B[13][idx], acc);
             }
+            out[n] = acc;
+        }
+        n = 0;
+        for (int b = lane; b < K; b += kWave, ++n) M[(int64_t)cell * K + b] = out[n];
+    }
+}
+
+// out_cs[a] = sum_{b >= a_AX} tau_cs^(b-a)/(b-a)! in[.., b, ..] for the two children cs (tau = -1/4, +1/4)
+template <int Q, int AX>
+__device__ __forceinline__ void l2l_pass(const double *in, double *out0, double *out1, int lane)
+{
+    constexpr auto &mi = Tables<Q>::mi;
+    constexpr int K = MultiIndex<Q>::K;
+    for (int a = lane; a < K; a += kWave) {
+        const int e[3] = {mi.e[a][0], mi.e[a][1], mi.e[a][2]};
+        const int top = Q - mi.deg[a] + e[AX];
+        double lo = 0.0, hi = 0.0;
+        for (int b = e[AX]; b <= top; ++b) {
+            const double v = in[step_index<Q, AX>(e[0], e[1], e[2], b)] * kQuarter.v[b - e[AX]];
+            hi += v;
+            lo += ((b - e[AX]) & 1) ? -v : v;
+        }
+        out0[a] = lo;
+        out1[a] = hi;
+    }
+}
+
+template <int Q>
+__global__ __launch_bounds__(kWave *kTreeWaves) void l2l_kernel(int n_par, const int32_t *__restrict__ parents,
+                                                                 double *__restrict__ Lam)
+{
+    constexpr auto &mi = Tables<Q>::mi;
+    constexpr int K = MultiIndex<Q>::K;
+    __shared__ double buf[kTreeWaves][15][K];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int pi = blockIdx.x * kTreeWaves + wave;
+    const bool active = pi < n_par;
+    double(*B)[K] = buf[wave];
+    int32_t child0 = 0;
+    if (active) {
+        child0 = parents[2 * pi + 1];
+        const double *__restrict__ src = Lam + (int64_t)parents[2 * pi] * K;
+        for (int n = lane; n < K; n += kWave) B[0][n] = src[n];
+    }
+    __syncthreads();
+    if (active) l2l_pass<Q, 2>(B[0], B[1], B[2], lane);  // z: slots 1 + z
+    __syncthreads();
+    if (active)  // y: slot 1 + z -> slots 3 + y + 2z
+        for (int z = 0; z < 2; ++z) l2l_pass<Q, 1>(B[1 + z], B[3 + 2 * z], B[3 + 2 * z + 1], lane);
+    __syncthreads();
+    if (active)  // x: slot 3 + y + 2z -> slots 7 + x + 2y + 4z = 7 + child
+        for (int yz = 0; yz < 4; ++yz) l2l_pass<Q, 0>(B[3 + yz], B[7 + 2 * yz], B[7 + 2 * yz + 1], lane);
+    __syncthreads();
+    if (active) {
+        double *__restrict__ dst = Lam + (int64_t)child0 * K;  // 8 consecutive children
+        for (int n = lane; n < 8 * K; n += kWave) {
+            const int c = n / K, a = n % K;
+            dst[n] += B[7 + c][a] * ldexp(1.0, -mi.deg[a]);
         }
     }
-    M[(int64_t)cell * K + b] = acc;
 }
 
 // ---- M2L: 64 targets per wave, one uniform interaction offset per slot --------------------------
@@ -165,8 +285,17 @@ __device__ __forceinline__ void m2l_all(double *acc, const double *__restrict__ 
     (m2l_column<Q, B>(acc, G, Ms[B], std::make_integer_sequence<int, ncoef(Q - mi.deg[B])>{}), ...);
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin; map them so that each XCD (with its own L2)
+// runs a contiguous range of tasks, which are in spatial order. Launch 8 * ceil(n/8) groups.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_task(int n_tasks)
+{
+    const int per = (n_tasks + kXcds - 1) / kXcds;
+    return (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+}
+
 template <int Q>
-__global__ __launch_bounds__(kWave) void m2l_kernel(const M2LTask *__restrict__ tasks,
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2, 2))) void m2l_kernel(int n_tasks, const M2LTask *__restrict__ tasks,
                                                    const int32_t *__restrict__ targets,
                                                    const int32_t *__restrict__ slot_off,
                                                    const int32_t *__restrict__ slot_src,
@@ -174,51 +303,35 @@ __global__ __launch_bounds__(kWave) void m2l_kernel(const M2LTask *__restrict__ 
                                                    double *__restrict__ Lam)
 {
     constexpr int K = MultiIndex<Q>::K;
-    const M2LTask task = tasks[blockIdx.x];
+    const int ti = xcd_task(n_tasks);
+    if (ti >= n_tasks) return;
+    const M2LTask task = tasks[ti];
     const int lane = threadIdx.x;
     double acc[K];
 #pragma unroll
     for (int a = 0; a < K; ++a) acc[a] = 0.0;
+    // the next slot's offset and source are fetched one slot ahead
+    int32_t off_next = 0, src_next = 0;
+    if (task.n_slots > 0) {
+        off_next = slot_off[task.slot_begin];
+        src_next = slot_src[(int64_t)task.slot_begin * kWave + lane];
+    }
     for (int j = 0; j < task.n_slots; ++j) {
-        const int64_t slot = (int64_t)task.slot_begin + j;
-        const double *__restrict__ Gs = G + (int64_t)slot_off[slot] * K;
-        const double *__restrict__ Ms = M + (int64_t)slot_src[slot * kWave + lane] * K;
+        const int32_t off = off_next, src = src_next;
+        if (j + 1 < task.n_slots) {
+            const int64_t nxt = (int64_t)task.slot_begin + j + 1;
+            off_next = slot_off[nxt];
+            src_next = slot_src[nxt * kWave + lane];
+        }
+        const double *__restrict__ Gs = G + (int64_t)off * K;
+        const double *__restrict__ Ms = M + (int64_t)src * K;
         m2l_all<Q>(acc, Gs, Ms, std::make_integer_sequence<int, K>{});
     }
-    const int32_t t = targets[(int64_t)blockIdx.x * kWave + lane];
+    const int32_t t = targets[(int64_t)ti * kWave + lane];
     if (t < 0) return;
     const double inv_a = ldexp(1.0, task.level);
 #pragma unroll
     for (int a = 0; a < K; ++a) Lam[(int64_t)t * K + a] = acc[a] * inv_a;
-}
-
-// ---- L2L: one thread per (child of a marked cell of one level, coefficient) ---------------------
-template <int Q>
-__global__ void l2l_kernel(int n_par, const int32_t *__restrict__ parents, double *__restrict__ Lam)
-{
-    constexpr auto &mi = Tables<Q>::mi;
-    constexpr int K = MultiIndex<Q>::K;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t pc = idx / K;
-    const int a = (int)(idx - pc * K);
-    const int pi = (int)(pc >> 3), c = (int)(pc & 7);
-    if (pi >= n_par) return;
-    const int32_t cell = parents[2 * pi], child = parents[2 * pi + 1] + c;
-    const double *__restrict__ LP = Lam + (int64_t)cell * K;
-    // tau = -1/4 for a child in the lower half of an axis, +1/4 in the upper half
-    const double s0 = (c & 1) ? 1.0 : -1.0, s1 = (c & 2) ? 1.0 : -1.0, s2 = (c & 4) ? 1.0 : -1.0;
-    const int a0 = mi.e[a][0], a1 = mi.e[a][1], a2 = mi.e[a][2];
-    const int rest = Q - mi.deg[a];
-    double acc = 0.0;
-    for (int d0 = 0; d0 <= rest; ++d0) {
-        const double f0 = quarter_pow_over_fact(d0, s0);
-        for (int d1 = 0; d1 <= rest - d0; ++d1) {
-            const double f01 = f0 * quarter_pow_over_fact(d1, s1);
-            for (int d2 = 0; d2 <= rest - d0 - d1; ++d2)
-                acc = fma(f01 * quarter_pow_over_fact(d2, s2), LP[mi_index(a0 + d0, a1 + d1, a2 + d2)], acc);
-        }
-    }
-    Lam[(int64_t)child * K + a] += acc * ldexp(1.0, -mi.deg[a]);
 }
 
 // ---- near field + evaluation: one wave per target leaf -------------------------------------------
@@ -348,24 +461,23 @@ void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStre
         for (int lev = p.L - 1; lev >= 2; --lev) {  // upward pass; moments below level 2 are never used
             const int n_par = p.parent_begin[lev + 1] - p.parent_begin[lev];
             if (n_par == 0) continue;
-            const int64_t n = (int64_t)n_par * K;
-            m2m_kernel<Q><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n_par, p.d_parents + 2 * p.parent_begin[lev],
-                                                                        p.d_M);
+            m2m_kernel<Q><<<(unsigned)((n_par + kTreeWaves - 1) / kTreeWaves), kWave * kTreeWaves, 0, st>>>(
+                n_par, p.d_parents + 2 * p.parent_begin[lev], p.d_M);
             check_launch();
         }
         marks.mark(2);
         if (p.n_tasks > 0) {
-            m2l_kernel<Q><<<(unsigned)p.n_tasks, kWave, 0, st>>>(p.d_tasks, p.d_task_targets, p.d_slot_off,
-                                                                 p.d_slot_src, p.d_G, p.d_M, p.d_Lam);
+            const unsigned groups = (unsigned)(kXcds * ((p.n_tasks + kXcds - 1) / kXcds));
+            m2l_kernel<Q><<<groups, kWave, 0, st>>>((int)p.n_tasks, p.d_tasks, p.d_task_targets, p.d_slot_off,
+                                                    p.d_slot_src, p.d_G, p.d_M, p.d_Lam);
             check_launch();
         }
         marks.mark(3);
         for (int lev = 2; lev < p.L; ++lev) {  // downward pass
             const int n_par = p.parent_begin[lev + 1] - p.parent_begin[lev];
             if (n_par == 0) continue;
-            const int64_t n = (int64_t)n_par * 8 * K;
-            l2l_kernel<Q><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n_par, p.d_parents + 2 * p.parent_begin[lev],
-                                                                        p.d_Lam);
+            l2l_kernel<Q><<<(unsigned)((n_par + kTreeWaves - 1) / kTreeWaves), kWave * kTreeWaves, 0, st>>>(
+                n_par, p.d_parents + 2 * p.parent_begin[lev], p.d_Lam);
             check_launch();
         }
     } else {

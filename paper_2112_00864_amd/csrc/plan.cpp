@@ -213,6 +213,36 @@ struct M2LPlan {
 
 int offset_key(int a, int b, int c) { return ((a + 7) * 15 + (b + 7)) * 15 + (c + 7); }
 
+// Sorted interaction-offset keys of cell c at level lev (its I list, eq. after spaceDecomp:Om).
+void interaction_keys(const bcv_tree_s &t, const std::vector<Grid> &g, int lev, int32_t c, std::vector<int32_t> &keys)
+{
+    keys.clear();
+    const int i = t.ijk[3 * c], j = t.ijk[3 * c + 1], k = t.ijk[3 * c + 2];
+    for (const auto &o : stencil()) {
+        const int32_t pn = g[lev - 1].at((i >> 1) + o[0], (j >> 1) + o[1], (k >> 1) + o[2]);
+        if (pn < 0 || !t.refined[pn]) continue;  // only marked parent-neighbours have children
+        for (int d = 0; d < 8; ++d) {
+            const int32_t s = t.first_child[pn] + d;
+            const int a = i - t.ijk[3 * s], b = j - t.ijk[3 * s + 1], cc = k - t.ijk[3 * s + 2];
+            if (!is_neighbour_offset(a, b, cc)) keys.push_back(offset_key(a, b, cc));
+        }
+    }
+    std::sort(keys.begin(), keys.end());
+}
+
+uint64_t hash_keys(const std::vector<int32_t> &keys)
+{
+    uint64_t h = 1469598103934665603ull;
+    for (int32_t k : keys) h = (h ^ (uint64_t)(uint32_t)k) * 1099511628211ull;
+    return h ^ keys.size();
+}
+
+// Packs the interaction phase into 64-lane tasks. Targets of one level are grouped by the
+// signature of their interaction list (cells in the interior of a face share it, cells along an
+// edge share it with the other cells at the same distance from the edge): each signature class
+// fills whole 64-lane tasks, and the remainders are packed together in Morton order. A task's
+// slots are the union of its targets' offsets; a lane gets a source only for offsets in its own
+// list, otherwise the zero row.
 M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g)
 {
     M2LPlan m;
@@ -222,54 +252,88 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g)
         std::vector<int32_t> cells;
     };
     std::vector<Chunk> chunks;
-    for (int lev = 2; lev <= t.L; ++lev) {
-        std::vector<int32_t> by_pos[8];
-        for (int32_t c = t.lvl_start[lev]; c < t.lvl_start[lev + 1]; ++c) {
-            const int pos = (t.ijk[3 * c] & 1) | ((t.ijk[3 * c + 1] & 1) << 1) | ((t.ijk[3 * c + 2] & 1) << 2);
-            by_pos[pos].push_back(c);
-        }
-        for (int pos = 0; pos < 8; ++pos)
-            for (size_t b = 0; b < by_pos[pos].size(); b += 64) {
-                Chunk ch{lev, {}};
-                ch.cells.assign(by_pos[pos].begin() + b, by_pos[pos].begin() + std::min(b + 64, by_pos[pos].size()));
-                chunks.push_back(std::move(ch));
+    for (int lev = t.L; lev >= 2; --lev) {
+        const int32_t b = t.lvl_start[lev], n = t.lvl_start[lev + 1] - b;
+        std::vector<uint64_t> sig(n);
+#pragma omp parallel
+        {
+            std::vector<int32_t> keys;
+#pragma omp for schedule(dynamic, 256)
+            for (int32_t q = 0; q < n; ++q) {
+                interaction_keys(t, g, lev, b + q, keys);
+                sig[q] = hash_keys(keys);
             }
+        }
+        // classes in order of their first (Morton-smallest) member
+        std::vector<int32_t> order(n);
+        for (int32_t q = 0; q < n; ++q) order[q] = q;
+        std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return sig[x] < sig[y]; });
+        std::vector<Chunk> level_chunks;
+        std::vector<std::vector<int32_t>> remainders;
+        for (int32_t s0 = 0; s0 < n;) {
+            int32_t s1 = s0;
+            while (s1 < n && sig[order[s1]] == sig[order[s0]]) ++s1;
+            int32_t q = s0;
+            for (; q + 64 <= s1; q += 64) {
+                Chunk ch{lev, {}};
+                for (int32_t r = q; r < q + 64; ++r) ch.cells.push_back(b + order[r]);
+                level_chunks.push_back(std::move(ch));
+            }
+            if (q < s1) {
+                std::vector<int32_t> rem;
+                for (int32_t r = q; r < s1; ++r) rem.push_back(b + order[r]);
+                remainders.push_back(std::move(rem));
+            }
+            s0 = s1;
+        }
+        std::sort(remainders.begin(), remainders.end(),
+                  [](const std::vector<int32_t> &x, const std::vector<int32_t> &y) { return x[0] < y[0]; });
+        Chunk cur{lev, {}};
+        for (const auto &rem : remainders) {
+            if (cur.cells.size() + rem.size() > 64) {
+                level_chunks.push_back(std::move(cur));
+                cur = Chunk{lev, {}};
+            }
+            cur.cells.insert(cur.cells.end(), rem.begin(), rem.end());
+        }
+        if (!cur.cells.empty()) level_chunks.push_back(std::move(cur));
+        // spatial order of tasks within the level (Morton order of the first target)
+        std::sort(level_chunks.begin(), level_chunks.end(),
+                  [](const Chunk &x, const Chunk &y) { return x.cells[0] < y.cells[0]; });
+        for (auto &ch : level_chunks) chunks.push_back(std::move(ch));
     }
     struct Out {
         std::vector<int32_t> keys, src;
         int64_t pairs = 0;
     };
     std::vector<Out> outs(chunks.size());
-#pragma omp parallel for schedule(dynamic, 4)
-    for (size_t q = 0; q < chunks.size(); ++q) {
-        const Chunk &ch = chunks[q];
-        const int lev = ch.lev;
-        std::vector<char> used(15 * 15 * 15, 0);
-        for (int32_t c : ch.cells) {  // union of the interaction offsets of the chunk
-            const int i = t.ijk[3 * c], j = t.ijk[3 * c + 1], k = t.ijk[3 * c + 2];
-            for (const auto &o : stencil()) {
-                const int32_t pn = g[lev - 1].at((i >> 1) + o[0], (j >> 1) + o[1], (k >> 1) + o[2]);
-                if (pn < 0 || !t.refined[pn]) continue;
-                for (int d = 0; d < 8; ++d) {
-                    const int32_t s = t.first_child[pn] + d;
-                    const int a = i - t.ijk[3 * s], b = j - t.ijk[3 * s + 1], cc = k - t.ijk[3 * s + 2];
-                    if (!is_neighbour_offset(a, b, cc)) used[offset_key(a, b, cc)] = 1;
-                }
+#pragma omp parallel
+    {
+        std::vector<std::vector<int32_t>> lane_keys(64);
+        std::vector<char> used(15 * 15 * 15);
+#pragma omp for schedule(dynamic, 4)
+        for (size_t q = 0; q < chunks.size(); ++q) {
+            const Chunk &ch = chunks[q];
+            std::fill(used.begin(), used.end(), 0);
+            for (size_t lane = 0; lane < ch.cells.size(); ++lane) {
+                interaction_keys(t, g, ch.lev, ch.cells[lane], lane_keys[lane]);
+                for (int32_t key : lane_keys[lane]) used[key] = 1;
             }
-        }
-        Out &o = outs[q];
-        for (int key = 0; key < 15 * 15 * 15; ++key) {
-            if (!used[key]) continue;
-            const int a = key / 225 - 7, b = (key / 15) % 15 - 7, cc = key % 15 - 7;
-            o.keys.push_back(key);
-            for (int lane = 0; lane < 64; ++lane) {
-                int32_t s = -1;
-                if (lane < (int)ch.cells.size()) {
-                    const int32_t c = ch.cells[lane];
-                    s = g[lev].at(t.ijk[3 * c] - a, t.ijk[3 * c + 1] - b, t.ijk[3 * c + 2] - cc);
+            Out &o = outs[q];
+            for (int key = 0; key < 15 * 15 * 15; ++key) {
+                if (!used[key]) continue;
+                const int a = key / 225 - 7, b = (key / 15) % 15 - 7, cc = key % 15 - 7;
+                o.keys.push_back(key);
+                for (int lane = 0; lane < 64; ++lane) {
+                    int32_t s = -1;
+                    if (lane < (int)ch.cells.size() &&
+                        std::binary_search(lane_keys[lane].begin(), lane_keys[lane].end(), key)) {
+                        const int32_t c = ch.cells[lane];
+                        s = g[ch.lev].at(t.ijk[3 * c] - a, t.ijk[3 * c + 1] - b, t.ijk[3 * c + 2] - cc);
+                    }
+                    o.pairs += s >= 0;
+                    o.src.push_back(s >= 0 ? s : zero_row);
                 }
-                o.pairs += s >= 0;
-                o.src.push_back(s >= 0 ? s : zero_row);
             }
         }
     }
@@ -286,6 +350,7 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g)
         m.slot_src.insert(m.slot_src.end(), outs[q].src.begin(), outs[q].src.end());
         m.n_pairs += outs[q].pairs;
     }
+    BCV_REQUIRE(m.slot_key.size() < (size_t)INT32_MAX, BCV_ENOTSUP, "interaction plan too large");
     return m;
 }
 
