@@ -81,6 +81,8 @@ def main():
     ap.add_argument("--L", type=int, default=7)
     ap.add_argument("--q", type=int, default=6)
     ap.add_argument("--nearfield", choices=["quadrature", "assembled"], default="quadrature")
+    ap.add_argument("--streams", type=int, choices=[1, 2], default=2,
+                    help="2: near field concurrent with the far field on a second stream")
     ap.add_argument("--cpu-targets", type=int, default=12)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -113,7 +115,7 @@ def main():
     tree = bcv.build_bc_tree(args.L)
     leaves = tree.leaves()
     nf = bcv.NEAR_ASSEMBLED if args.nearfield == "assembled" else bcv.NEAR_QUADRATURE
-    plan = bcv.plan_interactions(tree, q=args.q, nearfield=nf, device=dev)
+    plan = bcv.plan_interactions(tree, q=args.q, nearfield=nf, device=dev, streams=args.streams)
     plan_s = time.perf_counter() - t0
     info = plan.info
     n = info["n_leaves"]
@@ -185,8 +187,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "VtV apply, plain FP64 BC-FMM, unit cube BC octree h=1/%d (L=%d), %d leaves, q=%d, "
-                        "Gaussian-mixture density seed 0, near field %s"
-                        % (2 ** args.L, args.L, n, args.q, args.nearfield),
+                        "Gaussian-mixture density seed 0, near field %s, %d stream(s)"
+                        % (2 ** args.L, args.L, n, args.q, args.nearfield, args.streams),
             "n_leaves": n,
             "q": args.q,
             "n_near_pairs": info["n_near"],

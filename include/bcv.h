@@ -68,6 +68,10 @@ typedef struct {
     int nearfield; /* BCV_NEAR_QUADRATURE: the apply evaluates every near-pair entry on the fly;
                       BCV_NEAR_ASSEMBLED: the plan stores every near-pair entry (FP64) once and
                       the apply multiplies by them */
+    int streams;   /* 1: every phase runs on the caller's stream, in Algorithm 1's order;
+                      2: the near field runs on a plan-owned second stream (default priority),
+                      concurrently with moments, passes and interactions, joined back to the
+                      caller's stream before the evaluation phase */
 } bcv_plan_opts;
 
 /* Sizes of a plan (all counts, no pointers). */
@@ -123,16 +127,25 @@ bcv_status bcv_vtv_apply(bcv_plan plan, const double *f_dev, double *u_dev, void
 enum { BCV_PART_NEAR = 1, BCV_PART_FAR = 2 };
 bcv_status bcv_vtv_apply_parts(bcv_plan plan, const double *f_dev, double *u_dev, void *hip_stream, int parts);
 
-/* Per-phase device timing of applies, with HIP events recorded on each apply's stream between
- * the phases of Algorithm 1: moments (P2M), upward pass (M2M), interaction phase (M2L), downward
- * pass (L2L), and near field fused with the evaluation phase (NEAR).
- * bcv_plan_enable_timing creates 6 * max_applies events (host call, may allocate) and resets
+/* Per-phase device timing of applies, with HIP events recorded around each phase of Algorithm 1
+ * on the stream it runs on: moments (P2M), upward pass (M2M), interaction phase (M2L), downward
+ * pass (L2L), near field (NEAR; with streams = 1 it also contains the evaluation phase) and
+ * evaluation (EVAL; streams = 2 only).
+ * bcv_plan_enable_timing creates 2 * BCV_N_PHASES * max_applies events (host call, may allocate) and resets
  * the record; each following apply records its phase boundaries until max_applies applies have
  * been recorded (later applies are not timed). max_applies = 0 disables timing and frees the
  * events. bcv_plan_phase_times waits for the recorded events and returns, per phase, the total
  * milliseconds over the recorded applies (ms: host, BCV_N_PHASES doubles) and the number of
  * recorded applies (n_applies: host). Errors: BCV_EINVAL, BCV_ESTATE, BCV_EDEVICE. */
-enum { BCV_PHASE_P2M = 0, BCV_PHASE_M2M = 1, BCV_PHASE_M2L = 2, BCV_PHASE_L2L = 3, BCV_PHASE_NEAR = 4, BCV_N_PHASES = 5 };
+enum {
+    BCV_PHASE_P2M = 0,
+    BCV_PHASE_M2M = 1,
+    BCV_PHASE_M2L = 2,
+    BCV_PHASE_L2L = 3,
+    BCV_PHASE_NEAR = 4,
+    BCV_PHASE_EVAL = 5,
+    BCV_N_PHASES = 6
+};
 bcv_status bcv_plan_enable_timing(bcv_plan plan, int max_applies);
 bcv_status bcv_plan_phase_times(bcv_plan plan, double *ms, int64_t *n_applies);
 

@@ -30,7 +30,7 @@ class MeshDesc(ctypes.Structure):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("eta0", ctypes.c_double), ("q", ctypes.c_int), ("precision", ctypes.c_int),
-                ("direct", ctypes.c_int), ("nearfield", ctypes.c_int)]
+                ("direct", ctypes.c_int), ("nearfield", ctypes.c_int), ("streams", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -133,8 +133,8 @@ class Plan:
         self.destroy()
 
 
-def plan_interactions(tree, q=6, eta0=0.5, direct=False, nearfield=NEAR_QUADRATURE, device=0):
-    opts = PlanOpts(eta0, q, 0, 1 if direct else 0, nearfield)
+def plan_interactions(tree, q=6, eta0=0.5, direct=False, nearfield=NEAR_QUADRATURE, device=0, streams=2):
+    opts = PlanOpts(eta0, q, 0, 1 if direct else 0, nearfield, streams)
     h = ctypes.c_void_p()
     _check(lib().bcv_plan_interactions(tree.handle, ctypes.byref(opts), device, ctypes.byref(h)))
     return Plan(h, device)
@@ -180,7 +180,7 @@ def btv_apply(plan, q_face, g_face, u, stream=None):
                                ctypes.c_void_p(u.data_ptr()), _stream(stream, plan.device)))
 
 
-PHASES = ("p2m", "m2m", "m2l", "l2l", "near")
+PHASES = ("p2m", "m2m", "m2l", "l2l", "near", "eval")
 
 
 def plan_enable_timing(plan, max_applies):

@@ -126,6 +126,7 @@ bcv_status bcv_plan_interactions(bcv_tree tree, const bcv_plan_opts *opts, int d
         BCV_REQUIRE(opts->direct == 0 || opts->direct == 1, BCV_EINVAL, "direct must be 0 or 1");
         BCV_REQUIRE(opts->nearfield == BCV_NEAR_QUADRATURE || opts->nearfield == BCV_NEAR_ASSEMBLED, BCV_EINVAL,
                     "unknown nearfield mode");
+        BCV_REQUIRE(opts->streams == 1 || opts->streams == 2, BCV_EINVAL, "streams must be 1 or 2");
         int n_dev = 0;
         BCV_HIP(hipGetDeviceCount(&n_dev));
         BCV_REQUIRE(device >= 0 && device < n_dev, BCV_EINVAL, "no such HIP device");

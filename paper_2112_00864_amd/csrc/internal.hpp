@@ -51,7 +51,12 @@ struct bcv_plan_s {
     int64_t device_bytes = 0;
     double touch_value[bcv::kTouchClasses];  // touching integrals / (4 pi), smaller side 1
 
-    // Phase timing: 6 events per recorded apply (phase boundaries), see bcv_plan_enable_timing.
+    // Second stream for the near field (streams == 2) and its fork/join events.
+    int streams = 1;
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+
+    // Phase timing: a start and a stop event per phase per recorded apply, see bcv_plan_enable_timing.
     std::vector<hipEvent_t> events;
     int timing_cap = 0;
     mutable int timing_used = 0;
@@ -64,6 +69,7 @@ struct bcv_plan_s {
     double *d_leaf_geom = nullptr;  // 4 per leaf: lower corner x, y, z and side
     int32_t *d_leaf_cell = nullptr;
     int64_t *d_row = nullptr;       // near CSR row pointers (n_leaves + 1)
+    int64_t *d_split = nullptr;     // per row: first point-rule entry (touching entries come first)
     uint32_t *d_col = nullptr;      // source leaf | (touch class + 1) << 28
     double *d_val = nullptr;        // assembled near entries (nearfield == ASSEMBLED)
     double *d_M = nullptr;          // moments, (n_cells + 1) x K; the last row stays zero

@@ -26,14 +26,8 @@ constexpr double kNode0 = 0.21132486540518711775;  // 1/2 - 1/(2 sqrt 3): 2-poin
 constexpr double kNode1 = 0.78867513459481288225;  // 1/2 + 1/(2 sqrt 3)
 constexpr double kInv4Pi = 0.079577471545947667884;
 
-template <int Q>
-struct Tables {
-    static constexpr MultiIndex<Q> mi{};
-};
-
-// mu(e)/e! with mu(e) = (1/2)(xi^e + (-xi)^e), xi = 1/(2 sqrt 3), xi^2 = 1/12: the per-axis factor
-// of kappa.
-__host__ __device__ constexpr double kappa_axis(int e)
+// mu(e)/e! per axis, mu(e) = (1/2)(xi^e + (-xi)^e), xi = 1/(2 sqrt 3) so xi^2 = 1/12.
+constexpr double kappa_axis_ce(int e)
 {
     if (e & 1) return 0.0;
     double v = 1.0;
@@ -41,6 +35,25 @@ __host__ __device__ constexpr double kappa_axis(int e)
     for (int t = 2; t <= e; ++t) v /= (double)t;
     return v;
 }
+
+template <int Q>
+struct KappaTable {  // kappa_a = prod_i mu(a_i)/a_i! for every multi-index of order <= Q
+    double v[MultiIndex<Q>::K];
+    constexpr KappaTable() : v{}
+    {
+        constexpr MultiIndex<Q> mi{};
+        for (int a = 0; a < MultiIndex<Q>::K; ++a)
+            v[a] = kappa_axis_ce(mi.e[a][0]) * kappa_axis_ce(mi.e[a][1]) * kappa_axis_ce(mi.e[a][2]);
+    }
+};
+
+template <int Q>
+struct Tables {
+    static constexpr MultiIndex<Q> mi{};
+};
+
+template <int Q>
+__constant__ constexpr KappaTable<Q> kKappa{};
 
 // (1/4)^k / k! for k = 0..kMaxOrder (translation coefficients; the sign (-1)^k is applied by the caller).
 constexpr int kMaxOrder = 8;
@@ -124,15 +137,13 @@ template <int Q>
 __global__ void p2m_kernel(int64_t n_leaves, const int32_t *__restrict__ leaf_cell, const double4 *__restrict__ geom,
                            const double *__restrict__ f, double *__restrict__ M)
 {
-    constexpr auto &mi = Tables<Q>::mi;
     constexpr int K = MultiIndex<Q>::K;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t leaf = idx / K;
     const int b = (int)(idx - leaf * K);
     if (leaf >= n_leaves) return;
     const double a = geom[leaf].w;
-    const double kap = kappa_axis(mi.e[b][0]) * kappa_axis(mi.e[b][1]) * kappa_axis(mi.e[b][2]);
-    M[(int64_t)leaf_cell[leaf] * K + b] = f[leaf] * (a * a * a) * kap;
+    M[(int64_t)leaf_cell[leaf] * K + b] = f[leaf] * (a * a * a) * kKappa<Q>.v[b];
 }
 
 // ---- M2M and L2L: one wave per marked cell, separable per-axis shifts through LDS -----------------
@@ -269,9 +280,8 @@ __global__ __launch_bounds__(kWave *kTreeWaves) void l2l_kernel(int n_par, const
 
 // ---- M2L: 64 targets per wave, one uniform interaction offset per slot --------------------------
 // acc[a] += D^{a+b} g(o) * M_s^b for all |a| + |b| <= Q, straight-line code from the index tables.
-template <int Q, int B, int... A>
-__device__ __forceinline__ void m2l_column(double *acc, const double *__restrict__ G, double mb,
-                                           std::integer_sequence<int, A...>)
+template <int Q, int B, class GP, int... A>
+__device__ __forceinline__ void m2l_column(double *acc, GP G, double mb, std::integer_sequence<int, A...>)
 {
     constexpr auto &mi = Tables<Q>::mi;
     ((acc[A] = fma(G[mi.sum(A, B)], mb, acc[A])), ...);
@@ -335,8 +345,12 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2, 2))) v
 }
 
 // ---- near field + evaluation: one wave per target leaf -------------------------------------------
+// Row t of the near CSR holds the touching pairs in [row[t], split[t]) and the point-rule pairs in
+// [split[t], row[t+1]). Touching pairs cost one FMA; the point-rule loop fetches the next pair's
+// source while it evaluates the current one.
 template <int Q, bool kAssembled>
 __global__ __launch_bounds__(256) void near_eval_kernel(int64_t n_leaves, const int64_t *__restrict__ row,
+                                                        const int64_t *__restrict__ split,
                                                         const uint32_t *__restrict__ col,
                                                         const double *__restrict__ val,
                                                         const double4 *__restrict__ geom,
@@ -345,7 +359,6 @@ __global__ __launch_bounds__(256) void near_eval_kernel(int64_t n_leaves, const 
                                                         const int32_t *__restrict__ leaf_cell, TouchValues tv,
                                                         int parts, double *__restrict__ u)
 {
-    constexpr auto &mi = Tables<Q>::mi;
     constexpr int K = MultiIndex<Q>::K;
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t t = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
@@ -353,22 +366,74 @@ __global__ __launch_bounds__(256) void near_eval_kernel(int64_t n_leaves, const 
     const double4 gt = geom[t];
     double acc = 0.0;
     if (parts & BCV_PART_NEAR) {
-        const int64_t e1 = row[t + 1];
-        for (int64_t e = row[t] + lane; e < e1; e += kWave) {
-            const uint32_t code = col[e];
-            const double v = kAssembled ? val[e] : near_entry(code, gt, geom, tv);
-            acc = fma(v, f[code & 0x0FFFFFFFu], acc);
+        const int64_t e0 = row[t], e1 = row[t + 1];
+        if (kAssembled) {
+            int64_t e = e0 + lane;
+            for (; e + kWave < e1; e += 2 * kWave) {  // two pairs per lane per step
+                const uint32_t c0 = col[e], c1 = col[e + kWave];
+                const double v0 = val[e], v1 = val[e + kWave];
+                acc = fma(v0, f[c0 & 0x0FFFFFFFu], acc);
+                acc = fma(v1, f[c1 & 0x0FFFFFFFu], acc);
+            }
+            if (e < e1) acc = fma(val[e], f[col[e] & 0x0FFFFFFFu], acc);
+        } else {
+            const int64_t es = split[t];
+            const double a_t = gt.w;
+            for (int64_t e = e0 + lane; e < es; e += kWave) {  // touching pairs
+                const uint32_t code = col[e];
+                const int32_t s = (int32_t)(code & 0x0FFFFFFFu);
+                const double a = fmin(a_t, geom[s].w);
+                acc = fma(tv.v[(code >> 28) - 1] * (a * a) * (a * a) * a, f[s], acc);
+            }
+            int64_t e = es + lane;
+            double4 gs_next = make_double4(0.0, 0.0, 0.0, 1.0);
+            double f_next = 0.0;
+            if (e < e1) {
+                const int32_t s = (int32_t)(col[e] & 0x0FFFFFFFu);
+                gs_next = geom[s];
+                f_next = f[s];
+            }
+            for (; e < e1; e += kWave) {
+                const double4 gs = gs_next;
+                const double fs = f_next;
+                if (e + kWave < e1) {
+                    const int32_t s = (int32_t)(col[e + kWave] & 0x0FFFFFFFu);
+                    gs_next = geom[s];
+                    f_next = f[s];
+                }
+                acc = fma(point_rule(gt, gs), fs, acc);
+            }
         }
     }
     if ((parts & BCV_PART_FAR) && Lam != nullptr) {
         const double *__restrict__ lam = Lam + (int64_t)leaf_cell[t] * K;
         double s = 0.0;
-        for (int a = lane; a < K; a += kWave)
-            s = fma(kappa_axis(mi.e[a][0]) * kappa_axis(mi.e[a][1]) * kappa_axis(mi.e[a][2]), lam[a], s);
+        for (int a = lane; a < K; a += kWave) s = fma(kKappa<Q>.v[a], lam[a], s);
         acc = fma(s, gt.w * gt.w * gt.w, acc);
     }
     acc = wave_sum(acc);
     if (lane == 0) u[t] = acc;
+}
+
+// ---- evaluation phase alone (near field computed concurrently): u += a^3 sum_a kappa_a Lambda^a --
+template <int Q>
+__global__ __launch_bounds__(256) void eval_add_kernel(int64_t n_leaves, const double4 *__restrict__ geom,
+                                                       const double *__restrict__ Lam,
+                                                       const int32_t *__restrict__ leaf_cell,
+                                                       double *__restrict__ u)
+{
+    constexpr int K = MultiIndex<Q>::K;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t t = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (t >= n_leaves) return;
+    const double *__restrict__ lam = Lam + (int64_t)leaf_cell[t] * K;
+    double s = 0.0;
+    for (int a = lane; a < K; a += kWave) s = fma(kKappa<Q>.v[a], lam[a], s);
+    s = wave_sum(s);
+    if (lane == 0) {
+        const double a = geom[t].w;
+        u[t] = fma(s, a * a * a, u[t]);
+    }
 }
 
 // ---- plan-time assembly of the near-pair entries --------------------------------------------------
@@ -430,20 +495,49 @@ void check_launch()
     if (e != hipSuccess) fail(BCV_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
 }
 
-// Records phase boundary `k` (0..5) of the current apply if timing is on.
+// Start and stop events of each phase of the current apply, if timing is on. A phase that does not
+// run gets both events recorded back to back on the caller's stream (zero time).
 struct PhaseMarks {
     const bcv_plan_s &p;
-    hipStream_t st;
     int slot;
-    PhaseMarks(const bcv_plan_s &plan, hipStream_t s) : p(plan), st(s), slot(-1)
+    bool done[BCV_N_PHASES] = {};
+    explicit PhaseMarks(const bcv_plan_s &plan) : p(plan), slot(-1)
     {
         if (p.timing_used < p.timing_cap) slot = p.timing_used++;
     }
-    void mark(int k) const
+    hipEvent_t ev(int k, int which) const { return p.events[2 * (BCV_N_PHASES * slot + k) + which]; }
+    void start(int k, hipStream_t st) const
     {
-        if (slot >= 0) BCV_HIP(hipEventRecord(p.events[6 * slot + k], st));
+        if (slot >= 0) BCV_HIP(hipEventRecord(ev(k, 0), st));
+    }
+    void stop(int k, hipStream_t st)
+    {
+        if (slot >= 0) BCV_HIP(hipEventRecord(ev(k, 1), st));
+        done[k] = true;
+    }
+    void finish(hipStream_t st)
+    {
+        for (int k = 0; k < BCV_N_PHASES; ++k)
+            if (!done[k]) {
+                start(k, st);
+                stop(k, st);
+            }
     }
 };
+
+template <int Q>
+void launch_near(const bcv_plan_s &p, const double *f, const double *lam, int parts, double *u, hipStream_t st)
+{
+    const unsigned blocks = (unsigned)((p.n_leaves + 3) / 4);
+    const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
+    if (p.d_val)
+        near_eval_kernel<Q, true><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_row, p.d_split, p.d_col, p.d_val, geom,
+                                                          f, lam, p.d_leaf_cell, touch_values(p), parts, u);
+    else
+        near_eval_kernel<Q, false><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_row, p.d_split, p.d_col, nullptr,
+                                                           geom, f, lam, p.d_leaf_cell, touch_values(p), parts, u);
+    check_launch();
+}
 
 template <int Q>
 void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStream_t st)
@@ -451,13 +545,24 @@ void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStre
     constexpr int K = MultiIndex<Q>::K;
     const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
     const bool far = (parts & BCV_PART_FAR) && !p.direct;
-    const PhaseMarks marks(p, st);
-    marks.mark(0);
+    const bool near = (parts & BCV_PART_NEAR) != 0;
+    const bool fork = far && near && p.streams == 2;
+    PhaseMarks marks(p);
+    if (fork) {  // near field on the side stream, concurrently with the far field
+        BCV_HIP(hipEventRecord(p.ev_fork, st));
+        BCV_HIP(hipStreamWaitEvent(p.side, p.ev_fork, 0));
+        marks.start(BCV_PHASE_NEAR, p.side);
+        launch_near<Q>(p, f, nullptr, BCV_PART_NEAR, u, p.side);
+        marks.stop(BCV_PHASE_NEAR, p.side);
+        BCV_HIP(hipEventRecord(p.ev_join, p.side));
+    }
     if (far) {
+        marks.start(BCV_PHASE_P2M, st);
         const int64_t nthr = p.n_leaves * K;
         p2m_kernel<Q><<<(unsigned)((nthr + 255) / 256), 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, f, p.d_M);
         check_launch();
-        marks.mark(1);
+        marks.stop(BCV_PHASE_P2M, st);
+        marks.start(BCV_PHASE_M2M, st);
         for (int lev = p.L - 1; lev >= 2; --lev) {  // upward pass; moments below level 2 are never used
             const int n_par = p.parent_begin[lev + 1] - p.parent_begin[lev];
             if (n_par == 0) continue;
@@ -465,14 +570,16 @@ void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStre
                 n_par, p.d_parents + 2 * p.parent_begin[lev], p.d_M);
             check_launch();
         }
-        marks.mark(2);
+        marks.stop(BCV_PHASE_M2M, st);
+        marks.start(BCV_PHASE_M2L, st);
         if (p.n_tasks > 0) {
             const unsigned groups = (unsigned)(kXcds * ((p.n_tasks + kXcds - 1) / kXcds));
             m2l_kernel<Q><<<groups, kWave, 0, st>>>((int)p.n_tasks, p.d_tasks, p.d_task_targets, p.d_slot_off,
                                                     p.d_slot_src, p.d_G, p.d_M, p.d_Lam);
             check_launch();
         }
-        marks.mark(3);
+        marks.stop(BCV_PHASE_M2L, st);
+        marks.start(BCV_PHASE_L2L, st);
         for (int lev = 2; lev < p.L; ++lev) {  // downward pass
             const int n_par = p.parent_begin[lev + 1] - p.parent_begin[lev];
             if (n_par == 0) continue;
@@ -480,23 +587,22 @@ void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStre
                 n_par, p.d_parents + 2 * p.parent_begin[lev], p.d_Lam);
             check_launch();
         }
-    } else {
-        marks.mark(1);
-        marks.mark(2);
-        marks.mark(3);
+        marks.stop(BCV_PHASE_L2L, st);
     }
-    marks.mark(4);
-    const unsigned blocks = (unsigned)((p.n_leaves + 3) / 4);
-    const double *lam = far ? p.d_Lam : nullptr;
-    const int near_parts = (parts & BCV_PART_NEAR) | (far ? BCV_PART_FAR : 0);
-    if (p.d_val)
-        near_eval_kernel<Q, true><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_row, p.d_col, p.d_val, geom, f, lam,
-                                                          p.d_leaf_cell, touch_values(p), near_parts, u);
-    else
-        near_eval_kernel<Q, false><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_row, p.d_col, nullptr, geom, f, lam,
-                                                           p.d_leaf_cell, touch_values(p), near_parts, u);
-    check_launch();
-    marks.mark(5);
+    if (fork) {
+        BCV_HIP(hipStreamWaitEvent(st, p.ev_join, 0));
+        marks.start(BCV_PHASE_EVAL, st);
+        eval_add_kernel<Q><<<(unsigned)((p.n_leaves + 3) / 4), 256, 0, st>>>(p.n_leaves, geom, p.d_Lam,
+                                                                             p.d_leaf_cell, u);
+        check_launch();
+        marks.stop(BCV_PHASE_EVAL, st);
+    } else {
+        // near field and evaluation fused (either part may be absent)
+        marks.start(BCV_PHASE_NEAR, st);
+        launch_near<Q>(p, f, far ? p.d_Lam : nullptr, (near ? BCV_PART_NEAR : 0) | (far ? BCV_PART_FAR : 0), u, st);
+        marks.stop(BCV_PHASE_NEAR, st);
+    }
+    marks.finish(st);
 }
 
 }  // namespace

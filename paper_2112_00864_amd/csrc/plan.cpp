@@ -145,6 +145,7 @@ void near_sources(const bcv_tree_s &t, const std::vector<Grid> &g, int32_t cell,
 
 struct NearCSR {
     std::vector<int64_t> row;
+    std::vector<int64_t> split;  // first non-touching entry of each row
     std::vector<uint32_t> col;
     int64_t n_touch = 0;
 };
@@ -173,6 +174,7 @@ NearCSR build_near(const bcv_tree_s &t, const std::vector<Grid> &g, const LeafGe
     }
     for (int64_t n = 0; n < nl; ++n) r.row[n + 1] += r.row[n];
     r.col.resize(r.row[nl]);
+    r.split.assign(nl, 0);
     int64_t touch = 0, bad = 0;
 #pragma omp parallel reduction(+ : touch, bad)
     {
@@ -196,6 +198,9 @@ NearCSR build_near(const bcv_tree_s &t, const std::vector<Grid> &g, const LeafGe
                 return (a & 0x0FFFFFFFu) < (b & 0x0FFFFFFFu);
             });
             std::copy(codes.begin(), codes.end(), r.col.begin() + r.row[n]);
+            int64_t n_t = 0;
+            while (n_t < (int64_t)codes.size() && (codes[n_t] >> 28) != 0) ++n_t;
+            r.split[n] = r.row[n] + n_t;
         }
     }
     if (bad) fail(BCV_ESTATE, "internal: touching leaves violate 2:1 balance");
@@ -391,6 +396,12 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
     p->K = ncoef(opts.q);
     p->direct = opts.direct;
     p->nearfield = opts.nearfield;
+    p->streams = opts.streams;
+    if (p->streams == 2) {
+        BCV_HIP(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
+        BCV_HIP(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+        BCV_HIP(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
+    }
     p->n_leaves = t.n_leaves();
     p->n_cells = t.n_cells();
     BCV_REQUIRE(p->n_leaves < (1 << 28), BCV_ENOTSUP, "more than 2^28 leaves");
@@ -419,6 +430,7 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         p->n_near = (int64_t)near.col.size();
         p->n_touch = near.n_touch;
         p->d_row = upload(p.get(), near.row);
+        p->d_split = upload(p.get(), near.split);
         p->d_col = upload(p.get(), near.col);
     }
 
@@ -478,7 +490,10 @@ void destroy_plan(bcv_plan_s *p)
     if (!p) return;
     (void)hipSetDevice(p->device);
     for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
-    void *bufs[] = {p->d_leaf_geom, p->d_leaf_cell, p->d_row, p->d_col, p->d_val, p->d_M, p->d_Lam, p->d_G,
+    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+    if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+    if (p->side) (void)hipStreamDestroy(p->side);
+    void *bufs[] = {p->d_leaf_geom, p->d_leaf_cell, p->d_row, p->d_split, p->d_col, p->d_val, p->d_M, p->d_Lam, p->d_G,
                     p->d_parents, p->d_tasks, p->d_task_targets, p->d_slot_off, p->d_slot_src};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -492,7 +507,7 @@ void set_timing(bcv_plan_s *p, int max_applies)
     p->events.clear();
     p->timing_cap = 0;
     p->timing_used = 0;
-    for (int64_t n = 0; n < 6 * (int64_t)max_applies; ++n) {
+    for (int64_t n = 0; n < 2 * BCV_N_PHASES * (int64_t)max_applies; ++n) {
         hipEvent_t e;
         BCV_HIP(hipEventCreate(&e));
         p->events.push_back(e);
@@ -503,14 +518,14 @@ void set_timing(bcv_plan_s *p, int max_applies)
 void phase_times(const bcv_plan_s *p, double *ms, int64_t *n)
 {
     for (int k = 0; k < BCV_N_PHASES; ++k) ms[k] = 0.0;
-    for (int s = 0; s < p->timing_used; ++s) {
-        BCV_HIP(hipEventSynchronize(p->events[6 * s + 5]));
+    for (int s = 0; s < p->timing_used; ++s)
         for (int k = 0; k < BCV_N_PHASES; ++k) {
+            const hipEvent_t a = p->events[2 * (BCV_N_PHASES * s + k)], b = p->events[2 * (BCV_N_PHASES * s + k) + 1];
+            BCV_HIP(hipEventSynchronize(b));
             float t = 0.0f;
-            BCV_HIP(hipEventElapsedTime(&t, p->events[6 * s + k], p->events[6 * s + k + 1]));
+            BCV_HIP(hipEventElapsedTime(&t, a, b));
             ms[k] += t;
         }
-    }
     *n = p->timing_used;
 }
 

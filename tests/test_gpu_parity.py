@@ -98,6 +98,18 @@ def test_assembled_near_field_equals_quadrature():
     assert np.max(np.abs(a - b) / np.abs(b)) < 1e-14
 
 
+@pytest.mark.parametrize("nearfield", [bcv.NEAR_QUADRATURE, bcv.NEAR_ASSEMBLED])
+def test_one_and_two_streams_agree(nearfield):
+    """The near field on a second stream (joined before evaluation) gives the same potential."""
+    m, lv = mesh(4)
+    f = synth.leaf_density(lv, seed=4)
+    t = bcv.build_bc_tree(4)
+    announce("streams 1 vs 2, L=4, nearfield mode %d" % nearfield)
+    a = gpu_apply(bcv.plan_interactions(t, q=6, nearfield=nearfield, streams=1), f)
+    b = gpu_apply(bcv.plan_interactions(t, q=6, nearfield=nearfield, streams=2), f)
+    assert np.max(np.abs(a - b) / np.abs(a)) < 1e-14
+
+
 def test_degenerate_densities():
     m, lv = mesh(3)
     plan = bcv.plan_interactions(bcv.build_bc_tree(3), q=6)
