@@ -1,14 +1,19 @@
 """Benchmark of the VtV apply (BC-FMM volume potential) on one MI355X.
 
 Workload: unit-cube BC octree with boundary leaves of side h = 1/128 (L = 7, 219,080 leaves),
-expansion order q = 6, FP64 throughout, piecewise-constant Gaussian-mixture density (seed 0).
-A step is one full VtV apply (Algorithm 1: moments, upward pass, interaction phase, downward
-pass, near field and evaluation) with the density already resident in HBM. Plan construction
-(lists, tables, workspace) happens once before timing and is reported separately.
+expansion order q = 6, piecewise-constant Gaussian-mixture density (seed 0). A step is one full
+VtV apply (Algorithm 1: moments, upward pass, interaction phase, downward pass, near field and
+evaluation) with the density already resident in HBM. Plan construction (lists, tables, workspace)
+happens once before timing and is reported separately.
+
+By default the same mesh is timed twice: with the plain FP64 path and with the mixed path (FP32
+interaction phase and non-touching near field, FP64 singular pairs, tree passes and accumulation).
+The headline value is the mixed rate if the mixed result is within rel-L2 1e-6 of the FP64 result
+(L2 norm of cell averages over Omega), else the FP64 rate.
 
 Prints one JSON line with the metric, the per-phase device times from HIP events recorded on the
-apply's stream, the roofline of the dominant kernel, and the CPU oracle's throughput on a bounded
-sample of the same workload.
+apply's stream, the roofline of the dominant kernel, the FP64 rate and the ratio, and the CPU
+oracle's throughput on a bounded sample of the same workload.
 """
 
 import argparse
@@ -24,6 +29,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "VtV cell-potentials/s at rel-L2≤1e-6, mixed+surrogate vs plain FP64, 1 GPU"
 PEAK_FP64 = 78.6e12  # MI355X FP64 vector (= FP64 matrix) peak, FLOP/s
+PEAK_FP32 = 157.3e12  # MI355X FP32 vector peak, FLOP/s
+REL_L2_GATE = 1e-6  # the mixed path counts only if its rel-L2 against the FP64 path is within this
 PEAK_HBM = 8.0e12  # bytes/s
 
 
@@ -46,6 +53,7 @@ def near_flops(info, q):
 
 
 def cpu_baseline(L, q, f, u_gpu, n_targets, leaves):
+    # u_gpu: the FP64 GPU result, compared with the oracle at the sampled leaves
     """The CPU oracle (O2, Algorithm 1 step by step in FP64) on a sample of target leaves."""
     from oracle import fmm
     from oracle.mesh import BCMesh
@@ -73,6 +81,64 @@ def cpu_baseline(L, q, f, u_gpu, n_targets, leaves):
     }
 
 
+def measure(bcv, torch, tree, f, args, dev, nf, prec):
+    """Plan, warm up, then time `args.steps` applies with per-phase HIP events."""
+    t0 = time.perf_counter()
+    plan = bcv.plan_interactions(tree, q=args.q, nearfield=nf, device=dev, streams=args.streams,
+                                 precision=bcv.MIXED_F32 if prec == "mixed" else bcv.FP64)
+    plan_s = time.perf_counter() - t0
+    info = plan.info
+    u = torch.empty_like(f)
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(args.warmup):
+        bcv.vtv_apply(plan, f, u, stream)
+    torch.cuda.synchronize()
+    bcv.plan_enable_timing(plan, args.steps)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        bcv.vtv_apply(plan, f, u, stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    phases, n_rec = bcv.plan_phase_times(plan)
+    bcv.plan_enable_timing(plan, 0)
+    phase_avg = {k: v / max(n_rec, 1) for k, v in phases.items()}
+    roof, roof_other = roofline(info, phase_avg, args, prec)
+    out = {"plan_s": plan_s, "info": info, "ms": 1e3 * elapsed / args.steps, "phases": phase_avg,
+           "u": u.cpu().numpy(), "roof": roof, "roof_other": roof_other}
+    del plan
+    return out
+
+
+def roofline(info, phase_avg, args, prec):
+    """Roofline of the interaction and near-field kernels (per launch, averaged over the timed applies)."""
+    from paper_2112_00864_amd import profiling
+
+    mixed = prec == "mixed"
+    peak = (PEAK_FP32 if mixed else PEAK_FP64) / 1e12
+    m2l_ms = phase_avg["m2l"]
+    near_ms = phase_avg["near"]
+    n = info["n_leaves"]
+    m2l_roof = {"bound": "alu", "achieved": info["n_m2l"] * m2l_flops_per_pair(args.q) / (m2l_ms * 1e-3) / 1e12,
+                "peak": peak, "unit": "TFLOP/s"}
+    if args.nearfield == "assembled":
+        near_bytes = info["n_near"] * (8 + 4 + 8) + n * (8 * 2 + 8 + 8 + 32)
+        near_roof = {"bound": "hbm", "achieved": near_bytes / (near_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
+                     "unit": "GB/s"}
+    else:
+        near_roof = {"bound": "alu", "achieved": near_flops(info, args.q) / (near_ms * 1e-3) / 1e12,
+                     "peak": peak, "unit": "TFLOP/s"}
+    m2l_name = "m2l_kernel<%d, %s>" % (args.q, "float" if mixed else "double")
+    near_name = "near_eval_kernel<%d, %s, %s>" % (args.q, "true" if args.nearfield == "assembled" else "false",
+                                                  "true" if mixed and args.nearfield != "assembled" else "false")
+    for roof_, name in ((m2l_roof, m2l_name), (near_roof, near_name)):
+        roof_["frac"] = roof_["achieved"] / roof_["peak"]
+        roof_["traffic"] = profiling.traffic_for(name)  # HBM bytes per launch (PMC), None if stale
+        roof_["kernel"] = name
+    dominant = m2l_roof if m2l_ms >= near_ms else near_roof
+    return dominant, {"m2l_kernel": m2l_roof, "near_eval_kernel": near_roof}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +147,8 @@ def main():
     ap.add_argument("--L", type=int, default=7)
     ap.add_argument("--q", type=int, default=6)
     ap.add_argument("--nearfield", choices=["quadrature", "assembled"], default="quadrature")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both",
+                    help="both: time the FP64 and the mixed path on the same mesh and report the ratio")
     ap.add_argument("--streams", type=int, choices=[1, 2], default=2,
                     help="2: near field concurrent with the far field on a second stream")
     ap.add_argument("--cpu-targets", type=int, default=12)
@@ -114,95 +182,79 @@ def main():
     t0 = time.perf_counter()
     tree = bcv.build_bc_tree(args.L)
     leaves = tree.leaves()
-    nf = bcv.NEAR_ASSEMBLED if args.nearfield == "assembled" else bcv.NEAR_QUADRATURE
-    plan = bcv.plan_interactions(tree, q=args.q, nearfield=nf, device=dev, streams=args.streams)
-    plan_s = time.perf_counter() - t0
-    info = plan.info
-    n = info["n_leaves"]
-    print("plan: %d leaves, %d near pairs, %d M2L pairs, %.1f s" % (n, info["n_near"], info["n_m2l"], plan_s),
-          file=sys.stderr, flush=True)
-
+    tree_s = time.perf_counter() - t0
     f = torch.tensor(synth.leaf_density(leaves, seed=0), device="cuda:%d" % dev)
-    u = torch.empty_like(f)
-    stream = torch.cuda.current_stream(dev)
-    for _ in range(args.warmup):
-        bcv.vtv_apply(plan, f, u, stream)
-    torch.cuda.synchronize()
+    n = len(leaves)
+    nf = bcv.NEAR_ASSEMBLED if args.nearfield == "assembled" else bcv.NEAR_QUADRATURE
+    precisions = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
 
-    bcv.plan_enable_timing(plan, args.steps)
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        bcv.vtv_apply(plan, f, u, stream)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    phases, n_rec = bcv.plan_phase_times(plan)
-    bcv.plan_enable_timing(plan, 0)
-    ms_step = 1e3 * elapsed / args.steps
-    phase_avg = {k: v / max(n_rec, 1) for k, v in phases.items()}
-    u_host = u.cpu().numpy()
-    print("step %.3f ms; phases (ms): %s" % (ms_step, json.dumps({k: round(v, 4) for k, v in phase_avg.items()})),
-          file=sys.stderr, flush=True)
+    runs = {}
+    for prec in precisions:
+        runs[prec] = measure(bcv, torch, tree, f, args, dev, nf, prec)
+        r = runs[prec]
+        print("%s: plan %.1f s, step %.3f ms; phases (ms): %s"
+              % (prec, r["plan_s"], r["ms"], json.dumps({k: round(v, 4) for k, v in r["phases"].items()})),
+              file=sys.stderr, flush=True)
 
-    # Roofline of the dominant kernel (per launch, averaged over the timed applies).
-    m2l_ms = phase_avg["m2l"]
-    near_ms = phase_avg["near"]
-    m2l_fl = info["n_m2l"] * m2l_flops_per_pair(args.q)
-    if args.nearfield == "assembled":
-        near_bytes = info["n_near"] * (8 + 4 + 8) + n * (8 * 2 + 8 + 8 + 32)
-        near_roof = {"bound": "hbm", "achieved": near_bytes / (near_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
-                     "unit": "GB/s"}
-    else:
-        near_fl = near_flops(info, args.q)
-        near_roof = {"bound": "alu", "achieved": near_fl / (near_ms * 1e-3) / 1e12, "peak": PEAK_FP64 / 1e12,
-                     "unit": "TFLOP/s"}
-    m2l_roof = {"bound": "alu", "achieved": m2l_fl / (m2l_ms * 1e-3) / 1e12, "peak": PEAK_FP64 / 1e12,
-                "unit": "TFLOP/s"}
-    from paper_2112_00864_amd import profiling
-
-    m2l_name = "m2l_kernel<%d>" % args.q
-    near_name = "near_eval_kernel<%d, %s>" % (args.q, "true" if args.nearfield == "assembled" else "false")
-    for roof_, name in ((m2l_roof, m2l_name), (near_roof, near_name)):
-        roof_["frac"] = roof_["achieved"] / roof_["peak"]
-        roof_["traffic"] = profiling.traffic_for(name)  # HBM bytes per launch (PMC), None if stale
-        roof_["kernel"] = name
-    roof = m2l_roof if m2l_ms >= near_ms else near_roof
+    info = runs[precisions[0]]["info"]
+    rel_l2 = None
+    if "fp64" in runs and "mixed" in runs:
+        a, b = runs["mixed"]["u"], runs["fp64"]["u"]
+        # relative L2(Omega) error of the cell averages (cell volume weights)
+        w = 0.125 ** leaves[:, 0].astype(np.float64)
+        avg_a, avg_b = a / w, b / w
+        rel_l2 = float(np.sqrt(np.sum(w * (avg_a - avg_b) ** 2) / np.sum(w * avg_b ** 2)))
+    # Headline: the mixed path when it meets the error gate against the FP64 path, else FP64.
+    head = "mixed" if ("mixed" in runs and rel_l2 is not None and rel_l2 <= REL_L2_GATE) else precisions[-1]
+    if args.precision == "both" and head != "mixed":
+        print("mixed path missed the rel-L2 gate (%s): reporting FP64" % rel_l2, file=sys.stderr, flush=True)
+    h = runs[head]
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(args.L, args.q, f.cpu().numpy(), u_host, args.cpu_targets, leaves)
+        u_ref = runs["fp64"]["u"] if "fp64" in runs else h["u"]
+        cpu = cpu_baseline(args.L, args.q, f.cpu().numpy(), u_ref, args.cpu_targets, leaves)
 
     line = {
         "metric": METRIC,
-        "value": n / (ms_step * 1e-3),
+        "value": n / (h["ms"] * 1e-3),
         "unit": "cell-potentials/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": h["ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if head == "mixed" else "f64",
         "data": "synthetic",
         "config": {
-            "workload": "VtV apply, plain FP64 BC-FMM, unit cube BC octree h=1/%d (L=%d), %d leaves, q=%d, "
-                        "Gaussian-mixture density seed 0, near field %s, %d stream(s)"
-                        % (2 ** args.L, args.L, n, args.q, args.nearfield, args.streams),
+            "workload": "VtV apply, BC-FMM, unit cube BC octree h=1/%d (L=%d), %d leaves, q=%d, Gaussian-mixture "
+                        "density seed 0, near field %s, %d stream(s), %s"
+                        % (2 ** args.L, args.L, n, args.q, args.nearfield, args.streams,
+                           "mixed FP32 M2L and far near field, FP64 singular pairs and accumulation"
+                           if head == "mixed" else "plain FP64"),
             "n_leaves": n,
             "q": args.q,
             "n_near_pairs": info["n_near"],
             "n_touching_pairs": info["n_touch"],
             "n_m2l_pairs": info["n_m2l"],
             "m2l_lane_efficiency": info["n_m2l"] / max(info["n_m2l_lanes"], 1),
-            "plan_seconds": plan_s,
-            "plan_device_bytes": info["device_bytes"],
+            "tree_seconds": tree_s,
+            "plan_seconds": h["plan_s"],
+            "plan_device_bytes": h["info"]["device_bytes"],
         },
-        "phase_ms": phase_avg,
-        "roofline": roof,
-        "roofline_other": {"m2l_kernel": m2l_roof, "near_eval_kernel": near_roof},
+        "phase_ms": h["phases"],
+        "roofline": h["roof"],
+        "roofline_other": h["roof_other"],
         "cpu_baseline": cpu,
     }
+    if "fp64" in runs:
+        line["fp64"] = {"value": n / (runs["fp64"]["ms"] * 1e-3), "ms_per_step": runs["fp64"]["ms"],
+                        "phase_ms": runs["fp64"]["phases"], "roofline": runs["fp64"]["roof"]}
+    if rel_l2 is not None:
+        line["mixed_vs_fp64"] = {"rel_l2": rel_l2, "gate": REL_L2_GATE,
+                                 "speedup": runs["fp64"]["ms"] / runs["mixed"]["ms"]}
     print(json.dumps(line), flush=True)
 
 

@@ -57,13 +57,19 @@ typedef struct {
 } bcv_mesh_desc;
 
 enum { BCV_NEAR_QUADRATURE = 0, BCV_NEAR_ASSEMBLED = 1 };
-enum { BCV_FP64 = 0 };
+/* Arithmetic of the apply.
+ * BCV_FP64: every phase in FP64.
+ * BCV_MIXED_F32: the interaction phase (M2L) reads FP32 copies of the moments and derivative tables
+ *   and accumulates in FP32; the non-touching near-field pairs evaluate their 64 kernel values in
+ *   FP32 (per-axis differences formed in FP64); the touching (singular) pairs, the moments, the
+ *   upward and downward passes, the evaluation and the final accumulation of u stay in FP64. */
+enum { BCV_FP64 = 0, BCV_MIXED_F32 = 1 };
 
 /* Plan options. */
 typedef struct {
     double eta0;   /* separation parameter of the neighbour test (eq. def:neighbors); must be 0.5 */
     int q;         /* expansion order, |alpha| + |beta| <= q (Sec. 3); supported: 4, 6 */
-    int precision; /* BCV_FP64 */
+    int precision; /* BCV_FP64 or BCV_MIXED_F32 */
     int direct;    /* 1: every leaf pair is treated as near (no far field; small meshes only) */
     int nearfield; /* BCV_NEAR_QUADRATURE: the apply evaluates every near-pair entry on the fly;
                       BCV_NEAR_ASSEMBLED: the plan stores every near-pair entry (FP64) once and
@@ -105,7 +111,7 @@ void bcv_tree_destroy(bcv_tree tree);
  * expanded to their leaves (Lemma 1, eq. spaceDecomp:OmOm), touching classes, derivative
  * tables, and all device workspace. Allocates device memory; the apply never does.
  * The plan copies what it needs: the tree may be destroyed afterwards.
- * Errors: BCV_EINVAL (NULL pointers, eta0 != 0.5, q not supported, precision not FP64),
+ * Errors: BCV_EINVAL (NULL pointers, eta0 != 0.5, q not supported, unknown precision),
  * BCV_ENOTSUP, BCV_ENOMEM, BCV_EDEVICE, BCV_ESTATE (bad tree handle). */
 bcv_status bcv_plan_interactions(bcv_tree tree, const bcv_plan_opts *opts, int device, bcv_plan *out);
 

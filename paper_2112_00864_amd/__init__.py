@@ -2,6 +2,8 @@
 
 from .bcv import (  # noqa: F401
     BCVError,
+    FP64,
+    MIXED_F32,
     NEAR_ASSEMBLED,
     NEAR_QUADRATURE,
     PART_FAR,

@@ -14,6 +14,7 @@ _lib = None
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTSUP, ESTATE = range(6)
 NEAR_QUADRATURE, NEAR_ASSEMBLED = 0, 1
+FP64, MIXED_F32 = 0, 1
 PART_NEAR, PART_FAR = 1, 2
 TOUCH_CLASSES = ("self", "face", "edge", "vertex", "face2", "edge2", "vertex2")
 
@@ -133,8 +134,9 @@ class Plan:
         self.destroy()
 
 
-def plan_interactions(tree, q=6, eta0=0.5, direct=False, nearfield=NEAR_QUADRATURE, device=0, streams=2):
-    opts = PlanOpts(eta0, q, 0, 1 if direct else 0, nearfield, streams)
+def plan_interactions(tree, q=6, eta0=0.5, direct=False, nearfield=NEAR_QUADRATURE, device=0, streams=2,
+                      precision=FP64):
+    opts = PlanOpts(eta0, q, precision, 1 if direct else 0, nearfield, streams)
     h = ctypes.c_void_p()
     _check(lib().bcv_plan_interactions(tree.handle, ctypes.byref(opts), device, ctypes.byref(h)))
     return Plan(h, device)

@@ -46,7 +46,7 @@ struct bcv_plan_s {
     uint32_t magic = kMagic;
     int device = 0;
     int L = 0, q = 0, K = 0;
-    int direct = 0, nearfield = 0;
+    int direct = 0, nearfield = 0, precision = 0;
     int64_t n_leaves = 0, n_cells = 0, n_near = 0, n_touch = 0, n_m2l = 0, n_m2l_lanes = 0, n_offsets = 0;
     int64_t device_bytes = 0;
     double touch_value[bcv::kTouchClasses];  // touching integrals / (4 pi), smaller side 1
@@ -75,6 +75,8 @@ struct bcv_plan_s {
     double *d_M = nullptr;          // moments, (n_cells + 1) x K; the last row stays zero
     double *d_Lam = nullptr;        // local coefficients, n_cells x K
     double *d_G = nullptr;          // derivative tables, n_offsets x K
+    float *d_M32 = nullptr;         // BCV_MIXED_F32: FP32 copy of the moments, (n_cells + 1) x K
+    float *d_G32 = nullptr;         // BCV_MIXED_F32: FP32 derivative tables
     int32_t *d_parents = nullptr;   // (marked cell, first child) pairs, grouped by level
     bcv::M2LTask *d_tasks = nullptr;
     int32_t *d_task_targets = nullptr;  // 64 per task, -1 = idle lane

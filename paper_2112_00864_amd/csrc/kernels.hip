@@ -13,6 +13,7 @@
 //     L2P  u_w      += a^3 sum_a kappa_a Lambda^a
 // The near field adds, per leaf w, sum over N*(w) of A_{w s} f_s, with A_{w s} the exact
 // touching integral C_class a_small^5/(4 pi) or the 2x2x2 x 2x2x2 point rule.
+#include <algorithm>
 #include <utility>
 
 #include "kernels.hpp"
@@ -117,6 +118,34 @@ __device__ __forceinline__ double point_rule(const double4 gt, const double4 gs)
         }
     const double wt = gt.w * gt.w * gt.w * 0.125, ws = gs.w * gs.w * gs.w * 0.125;
     return s * wt * ws * kInv4Pi;
+}
+
+// The same point rule with the 64 kernel evaluations in FP32: per-axis differences are formed in
+// FP64 (exact inputs, so their rounding is relative to the gap, not to the coordinates), then
+// squared and summed in FP32 with the hardware reciprocal square root (about 1 ulp).
+__device__ __forceinline__ double point_rule_f32(const double4 gt, const double4 gs)
+{
+    float d2[3][4];
+    const double lt[3] = {gt.x, gt.y, gt.z}, ls[3] = {gs.x, gs.y, gs.z};
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const double x0 = lt[ax] + gt.w * kNode0, x1 = lt[ax] + gt.w * kNode1;
+        const double y0 = ls[ax] + gs.w * kNode0, y1 = ls[ax] + gs.w * kNode1;
+        const float d[4] = {(float)(x0 - y0), (float)(x0 - y1), (float)(x1 - y0), (float)(x1 - y1)};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) d2[ax][m] = d[m] * d[m];
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const float xy = d2[0][a] + d2[1][b];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) s += __builtin_amdgcn_rsqf(xy + d2[2][c]);
+        }
+    const double wt = gt.w * gt.w * gt.w * 0.125, ws = gs.w * gs.w * gs.w * 0.125;
+    return (double)s * wt * ws * kInv4Pi;
 }
 
 __device__ __forceinline__ double near_entry(uint32_t code, const double4 gt, const double4 *__restrict__ geom,
@@ -280,15 +309,15 @@ __global__ __launch_bounds__(kWave *kTreeWaves) void l2l_kernel(int n_par, const
 
 // ---- M2L: 64 targets per wave, one uniform interaction offset per slot --------------------------
 // acc[a] += D^{a+b} g(o) * M_s^b for all |a| + |b| <= Q, straight-line code from the index tables.
-template <int Q, int B, class GP, int... A>
-__device__ __forceinline__ void m2l_column(double *acc, GP G, double mb, std::integer_sequence<int, A...>)
+template <int Q, int B, class T, class GP, int... A>
+__device__ __forceinline__ void m2l_column(T *acc, GP G, T mb, std::integer_sequence<int, A...>)
 {
     constexpr auto &mi = Tables<Q>::mi;
     ((acc[A] = fma(G[mi.sum(A, B)], mb, acc[A])), ...);
 }
 
-template <int Q, int... B>
-__device__ __forceinline__ void m2l_all(double *acc, const double *__restrict__ G, const double *__restrict__ Ms,
+template <int Q, class T, int... B>
+__device__ __forceinline__ void m2l_all(T *acc, const T *__restrict__ G, const T *__restrict__ Ms,
                                         std::integer_sequence<int, B...>)
 {
     constexpr auto &mi = Tables<Q>::mi;
@@ -304,12 +333,14 @@ __device__ __forceinline__ int xcd_task(int n_tasks)
     return (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
 }
 
-template <int Q>
+// T = double (BCV_FP64) or float (BCV_MIXED_F32: FP32 moments, tables and accumulation; the
+// local coefficients are written in FP64).
+template <int Q, class T>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2, 2))) void m2l_kernel(int n_tasks, const M2LTask *__restrict__ tasks,
                                                    const int32_t *__restrict__ targets,
                                                    const int32_t *__restrict__ slot_off,
                                                    const int32_t *__restrict__ slot_src,
-                                                   const double *__restrict__ G, const double *__restrict__ M,
+                                                   const T *__restrict__ G, const T *__restrict__ M,
                                                    double *__restrict__ Lam)
 {
     constexpr int K = MultiIndex<Q>::K;
@@ -317,9 +348,9 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2, 2))) v
     if (ti >= n_tasks) return;
     const M2LTask task = tasks[ti];
     const int lane = threadIdx.x;
-    double acc[K];
+    T acc[K];
 #pragma unroll
-    for (int a = 0; a < K; ++a) acc[a] = 0.0;
+    for (int a = 0; a < K; ++a) acc[a] = T(0);
     // the next slot's offset and source are fetched one slot ahead
     int32_t off_next = 0, src_next = 0;
     if (task.n_slots > 0) {
@@ -333,22 +364,29 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2, 2))) v
             off_next = slot_off[nxt];
             src_next = slot_src[nxt * kWave + lane];
         }
-        const double *__restrict__ Gs = G + (int64_t)off * K;
-        const double *__restrict__ Ms = M + (int64_t)src * K;
-        m2l_all<Q>(acc, Gs, Ms, std::make_integer_sequence<int, K>{});
+        const T *__restrict__ Gs = G + (int64_t)off * K;
+        const T *__restrict__ Ms = M + (int64_t)src * K;
+        m2l_all<Q, T>(acc, Gs, Ms, std::make_integer_sequence<int, K>{});
     }
     const int32_t t = targets[(int64_t)ti * kWave + lane];
     if (t < 0) return;
     const double inv_a = ldexp(1.0, task.level);
 #pragma unroll
-    for (int a = 0; a < K; ++a) Lam[(int64_t)t * K + a] = acc[a] * inv_a;
+    for (int a = 0; a < K; ++a) Lam[(int64_t)t * K + a] = (double)acc[a] * inv_a;
+}
+
+// FP32 copy of the moments for the mixed-precision interaction phase.
+__global__ void to_f32_kernel(int64_t n, const double *__restrict__ in, float *__restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (float)in[i];
 }
 
 // ---- near field + evaluation: one wave per target leaf -------------------------------------------
 // Row t of the near CSR holds the touching pairs in [row[t], split[t]) and the point-rule pairs in
 // [split[t], row[t+1]). Touching pairs cost one FMA; the point-rule loop fetches the next pair's
 // source while it evaluates the current one.
-template <int Q, bool kAssembled>
+template <int Q, bool kAssembled, bool kMixed>
 __global__ __launch_bounds__(256) void near_eval_kernel(int64_t n_leaves, const int64_t *__restrict__ row,
                                                         const int64_t *__restrict__ split,
                                                         const uint32_t *__restrict__ col,
@@ -401,7 +439,7 @@ __global__ __launch_bounds__(256) void near_eval_kernel(int64_t n_leaves, const 
                     gs_next = geom[s];
                     f_next = f[s];
                 }
-                acc = fma(point_rule(gt, gs), fs, acc);
+                acc = fma(kMixed ? point_rule_f32(gt, gs) : point_rule(gt, gs), fs, acc);
             }
         }
     }
@@ -531,11 +569,17 @@ void launch_near(const bcv_plan_s &p, const double *f, const double *lam, int pa
     const unsigned blocks = (unsigned)((p.n_leaves + 3) / 4);
     const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
     if (p.d_val)
-        near_eval_kernel<Q, true><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_row, p.d_split, p.d_col, p.d_val, geom,
-                                                          f, lam, p.d_leaf_cell, touch_values(p), parts, u);
+        near_eval_kernel<Q, true, false><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_row, p.d_split, p.d_col, p.d_val,
+                                                                 geom, f, lam, p.d_leaf_cell, touch_values(p),
+                                                                 parts, u);
+    else if (p.precision == BCV_MIXED_F32)
+        near_eval_kernel<Q, false, true><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_row, p.d_split, p.d_col, nullptr,
+                                                                 geom, f, lam, p.d_leaf_cell, touch_values(p),
+                                                                 parts, u);
     else
-        near_eval_kernel<Q, false><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_row, p.d_split, p.d_col, nullptr,
-                                                           geom, f, lam, p.d_leaf_cell, touch_values(p), parts, u);
+        near_eval_kernel<Q, false, false><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_row, p.d_split, p.d_col, nullptr,
+                                                                  geom, f, lam, p.d_leaf_cell, touch_values(p),
+                                                                  parts, u);
     check_launch();
 }
 
@@ -574,8 +618,17 @@ void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStre
         marks.start(BCV_PHASE_M2L, st);
         if (p.n_tasks > 0) {
             const unsigned groups = (unsigned)(kXcds * ((p.n_tasks + kXcds - 1) / kXcds));
-            m2l_kernel<Q><<<groups, kWave, 0, st>>>((int)p.n_tasks, p.d_tasks, p.d_task_targets, p.d_slot_off,
-                                                    p.d_slot_src, p.d_G, p.d_M, p.d_Lam);
+            if (p.precision == BCV_MIXED_F32) {
+                const int64_t n = (p.n_cells + 1) * K;
+                to_f32_kernel<<<(unsigned)std::min<int64_t>((n + 255) / 256, 65536), 256, 0, st>>>(n, p.d_M, p.d_M32);
+                check_launch();
+                m2l_kernel<Q, float><<<groups, kWave, 0, st>>>((int)p.n_tasks, p.d_tasks, p.d_task_targets,
+                                                               p.d_slot_off, p.d_slot_src, p.d_G32, p.d_M32,
+                                                               p.d_Lam);
+            } else {
+                m2l_kernel<Q, double><<<groups, kWave, 0, st>>>((int)p.n_tasks, p.d_tasks, p.d_task_targets,
+                                                                p.d_slot_off, p.d_slot_src, p.d_G, p.d_M, p.d_Lam);
+            }
             check_launch();
         }
         marks.stop(BCV_PHASE_M2L, st);

@@ -396,6 +396,7 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
     p->K = ncoef(opts.q);
     p->direct = opts.direct;
     p->nearfield = opts.nearfield;
+    p->precision = opts.precision;
     p->streams = opts.streams;
     if (p->streams == 2) {
         BCV_HIP(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
@@ -468,12 +469,17 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         p->n_m2l_lanes = (int64_t)m2l.slot_key.size() * 64;
         p->n_tasks = (int64_t)m2l.tasks.size();
         p->d_G = upload(p.get(), G);
+        if (p->precision == BCV_MIXED_F32) {
+            std::vector<float> G32(G.begin(), G.end());
+            p->d_G32 = upload(p.get(), G32);
+        }
         p->d_tasks = upload(p.get(), m2l.tasks);
         p->d_task_targets = upload(p.get(), m2l.targets);
         p->d_slot_off = upload(p.get(), m2l.slot_key);
         p->d_slot_src = upload(p.get(), m2l.slot_src);
         p->d_M = alloc_zero<double>(p.get(), (size_t)(p->n_cells + 1) * p->K);
         p->d_Lam = alloc_zero<double>(p.get(), (size_t)p->n_cells * p->K);
+        if (p->precision == BCV_MIXED_F32) p->d_M32 = alloc_zero<float>(p.get(), (size_t)(p->n_cells + 1) * p->K);
     }
 
     if (opts.nearfield == BCV_NEAR_ASSEMBLED) {
@@ -494,6 +500,7 @@ void destroy_plan(bcv_plan_s *p)
     if (p->ev_join) (void)hipEventDestroy(p->ev_join);
     if (p->side) (void)hipStreamDestroy(p->side);
     void *bufs[] = {p->d_leaf_geom, p->d_leaf_cell, p->d_row, p->d_split, p->d_col, p->d_val, p->d_M, p->d_Lam, p->d_G,
+                    p->d_M32, p->d_G32,
                     p->d_parents, p->d_tasks, p->d_task_targets, p->d_slot_off, p->d_slot_src};
     for (void *b : bufs)
         if (b) (void)hipFree(b);

@@ -110,6 +110,40 @@ def test_one_and_two_streams_agree(nearfield):
     assert np.max(np.abs(a - b) / np.abs(a)) < 1e-14
 
 
+MIXED_TOL = 1e-6  # gate for the mixed-precision apply (relative L2 of cell averages)
+
+
+@pytest.mark.parametrize("L,q", [(3, 4), (4, 6)])
+def test_mixed_precision_against_O2(L, q):
+    """FP32 M2L and FP32 far near field, FP64 singular pairs and accumulation: rel-L2 <= 1e-6 vs O2."""
+    m, lv = mesh(L)
+    f = synth.leaf_density(lv, seed=1)
+    announce("mixed plan L=%d q=%d" % (L, q))
+    plan = bcv.plan_interactions(bcv.build_bc_tree(L), q=q, precision=bcv.MIXED_F32)
+    F = fmm.FMM(m, q)
+    near_ref = F.near_field(f, np.arange(len(lv)))
+    ref = F.apply(f)
+    e_near = rel_l2(lv, gpu_apply(plan, f, bcv.PART_NEAR), near_ref)
+    e_far = rel_l2(lv, gpu_apply(plan, f, bcv.PART_FAR), ref - near_ref)
+    e = rel_l2(lv, gpu_apply(plan, f), ref)
+    announce("mixed L=%d q=%d rel-L2 near %.3e far %.3e (of far part) total %.3e" % (L, q, e_near, e_far, e))
+    assert e <= MIXED_TOL
+
+
+def test_mixed_precision_full_size():
+    """h = 1/128, q = 6: mixed apply against the FP64 apply on the GPU, all leaves."""
+    L = 7
+    m, lv = mesh(L)
+    f = synth.leaf_density(lv, seed=0)
+    t = bcv.build_bc_tree(L)
+    announce("full-size mixed vs FP64, L=7 q=6")
+    u64 = gpu_apply(bcv.plan_interactions(t, q=6), f)
+    u32 = gpu_apply(bcv.plan_interactions(t, q=6, precision=bcv.MIXED_F32), f)
+    e = rel_l2(lv, u32, u64)
+    announce("full-size mixed rel-L2 vs FP64 %.3e, max rel %.3e" % (e, np.max(np.abs(u32 - u64) / np.abs(u64))))
+    assert e <= MIXED_TOL
+
+
 def test_degenerate_densities():
     m, lv = mesh(3)
     plan = bcv.plan_interactions(bcv.build_bc_tree(3), q=6)
