@@ -33,7 +33,31 @@ struct M2LTask {
     int32_t slot_begin;  // first slot
     int32_t n_slots;
     int32_t level;  // level of the 64 targets (cell side 2^-level); targets at 64 * task index
-    int32_t pad;
+    int32_t out;    // -1: write the local coefficients; else the piece's partial block (see M2LSplit)
+};
+
+// A 64-target task whose slot list was cut into `count` pieces (tasks with out = first ...
+// first + count - 1, all holding the same targets): their partial local coefficients are summed
+// in piece order. `task` is the first piece.
+struct M2LSplit {
+    int32_t task, first, count, pad;
+};
+
+// Tasks are dealt to the 8 XCDs in contiguous ranges of about equal work.
+constexpr int kXcds = 8;
+
+// One wave's share of the near field: entries [begin, end) of the near row of `target`. Rows
+// longer than a unit (the coarse leaves, whose extended neighbour lists reach thousands of fine
+// leaves) are cut into several units, so that no wave holds the GPU much longer than the others.
+struct NearUnit {
+    int64_t begin, end;
+    int32_t target;
+    int32_t out;  // -1: the unit is the whole row and writes u[target]; else its partial-sum index
+};
+
+// A target whose row is cut into units: their partial sums are [first, first + count), in row order.
+struct NearSplit {
+    int32_t target, first, count, pad;
 };
 
 // Touching-pair classes in the order of bcv_touching_integrals().
@@ -64,14 +88,19 @@ struct bcv_plan_s {
     // Host copies needed to launch level-by-level passes.
     std::vector<int32_t> parent_begin;  // per level l: range of marked cells of level l in d_parents
     int64_t n_tasks = 0;
+    int64_t n_units = 0, n_splits = 0;
+    int64_t n_m2l_splits = 0, m2l_groups = 0;  // split tasks; workgroups of the interaction kernel
+    int32_t xcd_begin[bcv::kXcds + 1] = {};     // task range of each XCD
 
     // Device buffers (owned).
     double *d_leaf_geom = nullptr;  // 4 per leaf: lower corner x, y, z and side
     int32_t *d_leaf_cell = nullptr;
-    int64_t *d_row = nullptr;       // near CSR row pointers (n_leaves + 1)
-    int64_t *d_split = nullptr;     // per row: first point-rule entry (touching entries come first)
+    int64_t *d_split = nullptr;     // per near row: first point-rule entry (touching entries come first)
     uint32_t *d_col = nullptr;      // source leaf | (touch class + 1) << 28
     double *d_val = nullptr;        // assembled near entries (nearfield == ASSEMBLED)
+    bcv::NearUnit *d_units = nullptr;   // near-field work units, longest first
+    bcv::NearSplit *d_splits = nullptr; // targets whose row spans several units
+    double *d_partial = nullptr;        // one partial near sum per unit of a split row
     double *d_M = nullptr;          // moments, (n_cells + 1) x K; the last row stays zero
     double *d_Lam = nullptr;        // local coefficients, n_cells x K
     double *d_G = nullptr;          // derivative tables, n_offsets x K
@@ -82,4 +111,6 @@ struct bcv_plan_s {
     int32_t *d_task_targets = nullptr;  // 64 per task, -1 = idle lane
     int32_t *d_slot_off = nullptr;      // offset id per slot
     int32_t *d_slot_src = nullptr;      // 64 source cells per slot (n_cells = zero row)
+    bcv::M2LSplit *d_m2l_splits = nullptr;
+    double *d_m2l_partial = nullptr;    // 64 x K per piece of a split task
 };

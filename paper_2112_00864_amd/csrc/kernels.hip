@@ -68,11 +68,6 @@ struct QuarterTable {
 };
 __constant__ constexpr QuarterTable kQuarter{};
 
-// (s/4)^k / k! with s = +-1.
-__device__ __forceinline__ double quarter_pow_over_fact(int k, double s)
-{
-    return ((k & 1) && s < 0.0) ? -kQuarter.v[k] : kQuarter.v[k];
-}
 
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -324,28 +319,30 @@ __device__ __forceinline__ void m2l_all(T *acc, const T *__restrict__ G, const T
     (m2l_column<Q, B>(acc, G, Ms[B], std::make_integer_sequence<int, ncoef(Q - mi.deg[B])>{}), ...);
 }
 
-// Workgroups are dealt to the 8 XCDs round-robin; map them so that each XCD (with its own L2)
-// runs a contiguous range of tasks, which are in spatial order. Launch 8 * ceil(n/8) groups.
-constexpr int kXcds = 8;
-__device__ __forceinline__ int xcd_task(int n_tasks)
+// Workgroups are dealt to the 8 XCDs round-robin (workgroup b runs on XCD b mod 8). XCD x runs
+// the tasks [begin[x], begin[x + 1]), a spatially contiguous range, so that neighbouring targets
+// share its L2; the ranges carry about equal work. Launch 8 * (longest range) workgroups.
+struct XcdRanges {
+    int32_t begin[kXcds + 1];
+};
+__device__ __forceinline__ int xcd_task(const XcdRanges &r)
 {
-    const int per = (n_tasks + kXcds - 1) / kXcds;
-    return (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+    const int x = (int)(blockIdx.x % kXcds);
+    const int t = r.begin[x] + (int)(blockIdx.x / kXcds);
+    return t < r.begin[x + 1] ? t : -1;
 }
 
 // T = double (BCV_FP64) or float (BCV_MIXED_F32: FP32 moments, tables and accumulation; the
 // local coefficients are written in FP64).
 template <int Q, class T>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2, 2))) void m2l_kernel(int n_tasks, const M2LTask *__restrict__ tasks,
-                                                   const int32_t *__restrict__ targets,
-                                                   const int32_t *__restrict__ slot_off,
-                                                   const int32_t *__restrict__ slot_src,
-                                                   const T *__restrict__ G, const T *__restrict__ M,
-                                                   double *__restrict__ Lam)
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2, 2))) void m2l_kernel(
+    XcdRanges ranges, const M2LTask *__restrict__ tasks, const int32_t *__restrict__ targets,
+    const int32_t *__restrict__ slot_off, const int32_t *__restrict__ slot_src, const T *__restrict__ G,
+    const T *__restrict__ M, double *__restrict__ partial, double *__restrict__ Lam)
 {
     constexpr int K = MultiIndex<Q>::K;
-    const int ti = xcd_task(n_tasks);
-    if (ti >= n_tasks) return;
+    const int ti = xcd_task(ranges);
+    if (ti < 0) return;
     const M2LTask task = tasks[ti];
     const int lane = threadIdx.x;
     T acc[K];
@@ -371,8 +368,34 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2, 2))) v
     const int32_t t = targets[(int64_t)ti * kWave + lane];
     if (t < 0) return;
     const double inv_a = ldexp(1.0, task.level);
+    if (task.out < 0) {
 #pragma unroll
-    for (int a = 0; a < K; ++a) Lam[(int64_t)t * K + a] = (double)acc[a] * inv_a;
+        for (int a = 0; a < K; ++a) Lam[(int64_t)t * K + a] = (double)acc[a] * inv_a;
+    } else {  // [piece][a][lane]: coalesced
+        double *__restrict__ dst = partial + (int64_t)task.out * K * kWave + lane;
+#pragma unroll
+        for (int a = 0; a < K; ++a) dst[a * kWave] = (double)acc[a] * inv_a;
+    }
+}
+
+// Split tasks: Lambda_t = sum of the pieces' partial local coefficients, in piece order. Block
+// (split, g) handles coefficients 4g .. 4g + 3 of the split's 64 targets, one thread per (a, lane).
+template <int Q>
+__global__ __launch_bounds__(256) void m2l_combine_kernel(const M2LSplit *__restrict__ splits,
+                                                          const int32_t *__restrict__ targets,
+                                                          const double *__restrict__ partial,
+                                                          double *__restrict__ Lam)
+{
+    constexpr int K = MultiIndex<Q>::K;
+    const M2LSplit sp = splits[blockIdx.x];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int a = 4 * (int)blockIdx.y + (int)(threadIdx.x / kWave);
+    const int32_t t = targets[(int64_t)sp.task * kWave + lane];
+    if (t < 0 || a >= K) return;
+    const double *__restrict__ src = partial + ((int64_t)sp.first * K + a) * kWave + lane;
+    double s = 0.0;
+    for (int k = 0; k < sp.count; ++k) s += src[(int64_t)k * K * kWave];
+    Lam[(int64_t)t * K + a] = s;
 }
 
 // FP32 copy of the moments for the mixed-precision interaction phase.
@@ -382,12 +405,23 @@ __global__ void to_f32_kernel(int64_t n, const double *__restrict__ in, float *_
         out[i] = (float)in[i];
 }
 
-// ---- near field + evaluation: one wave per target leaf -------------------------------------------
+// ---- near field + evaluation: one wave per work unit --------------------------------------------
 // Row t of the near CSR holds the touching pairs in [row[t], split[t]) and the point-rule pairs in
-// [split[t], row[t+1]). Touching pairs cost one FMA; the point-rule loop fetches the next pair's
-// source while it evaluates the current one.
+// [split[t], row[t+1]); a unit covers a range of one row. Touching pairs cost one FMA; the
+// point-rule loop fetches the next pair's source while it evaluates the current one. A unit that
+// is its target's whole row writes u (adding the evaluation phase when Lam is given); the units
+// of a longer row write partial sums that near_combine_kernel adds up.
+template <int Q>
+__device__ __forceinline__ double eval_far(const double *__restrict__ lam, double a, int lane)
+{
+    constexpr int K = MultiIndex<Q>::K;
+    double s = 0.0;
+    for (int k = lane; k < K; k += kWave) s = fma(kKappa<Q>.v[k], lam[k], s);
+    return s * (a * a * a);
+}
+
 template <int Q, bool kAssembled, bool kMixed>
-__global__ __launch_bounds__(256) void near_eval_kernel(int64_t n_leaves, const int64_t *__restrict__ row,
+__global__ __launch_bounds__(256) void near_eval_kernel(int64_t n_units, const NearUnit *__restrict__ units,
                                                         const int64_t *__restrict__ split,
                                                         const uint32_t *__restrict__ col,
                                                         const double *__restrict__ val,
@@ -395,16 +429,19 @@ __global__ __launch_bounds__(256) void near_eval_kernel(int64_t n_leaves, const 
                                                         const double *__restrict__ f,
                                                         const double *__restrict__ Lam,
                                                         const int32_t *__restrict__ leaf_cell, TouchValues tv,
-                                                        int parts, double *__restrict__ u)
+                                                        int parts, double *__restrict__ partial,
+                                                        double *__restrict__ u)
 {
     constexpr int K = MultiIndex<Q>::K;
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t t = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
-    if (t >= n_leaves) return;  // uniform per wave
+    const int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (w >= n_units) return;  // uniform per wave
+    const NearUnit un = units[w];
+    const int32_t t = un.target;
     const double4 gt = geom[t];
     double acc = 0.0;
     if (parts & BCV_PART_NEAR) {
-        const int64_t e0 = row[t], e1 = row[t + 1];
+        const int64_t e0 = un.begin, e1 = un.end;
         if (kAssembled) {
             int64_t e = e0 + lane;
             for (; e + kWave < e1; e += 2 * kWave) {  // two pairs per lane per step
@@ -415,7 +452,7 @@ __global__ __launch_bounds__(256) void near_eval_kernel(int64_t n_leaves, const 
             }
             if (e < e1) acc = fma(val[e], f[col[e] & 0x0FFFFFFFu], acc);
         } else {
-            const int64_t es = split[t];
+            const int64_t es = min(max(split[t], e0), e1);
             const double a_t = gt.w;
             for (int64_t e = e0 + lane; e < es; e += kWave) {  // touching pairs
                 const uint32_t code = col[e];
@@ -443,14 +480,38 @@ __global__ __launch_bounds__(256) void near_eval_kernel(int64_t n_leaves, const 
             }
         }
     }
-    if ((parts & BCV_PART_FAR) && Lam != nullptr) {
-        const double *__restrict__ lam = Lam + (int64_t)leaf_cell[t] * K;
-        double s = 0.0;
-        for (int a = lane; a < K; a += kWave) s = fma(kKappa<Q>.v[a], lam[a], s);
-        acc = fma(s, gt.w * gt.w * gt.w, acc);
-    }
+    if (un.out < 0 && (parts & BCV_PART_FAR) && Lam != nullptr)
+        acc += eval_far<Q>(Lam + (int64_t)leaf_cell[t] * K, gt.w, lane);
     acc = wave_sum(acc);
-    if (lane == 0) u[t] = acc;
+    if (lane == 0) {
+        if (un.out < 0)
+            u[t] = acc;
+        else
+            partial[un.out] = acc;
+    }
+}
+
+// Rows cut into several units: u = sum of the partial sums in row order (+ evaluation phase).
+template <int Q>
+__global__ __launch_bounds__(256) void near_combine_kernel(int64_t n_splits, const NearSplit *__restrict__ splits,
+                                                           const double *__restrict__ partial,
+                                                           const double4 *__restrict__ geom,
+                                                           const double *__restrict__ Lam,
+                                                           const int32_t *__restrict__ leaf_cell,
+                                                           double *__restrict__ u)
+{
+    constexpr int K = MultiIndex<Q>::K;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (w >= n_splits) return;  // uniform per wave
+    const NearSplit sp = splits[w];
+    double far = 0.0;
+    if (Lam != nullptr) far = wave_sum(eval_far<Q>(Lam + (int64_t)leaf_cell[sp.target] * K, geom[sp.target].w, lane));
+    if (lane == 0) {
+        double acc = 0.0;
+        for (int k = 0; k < sp.count; ++k) acc += partial[sp.first + k];
+        u[sp.target] = acc + far;
+    }
 }
 
 // ---- evaluation phase alone (near field computed concurrently): u += a^3 sum_a kappa_a Lambda^a --
@@ -475,16 +536,17 @@ __global__ __launch_bounds__(256) void eval_add_kernel(int64_t n_leaves, const d
 }
 
 // ---- plan-time assembly of the near-pair entries --------------------------------------------------
-__global__ __launch_bounds__(256) void near_assemble_kernel(int64_t n_leaves, const int64_t *__restrict__ row,
+__global__ __launch_bounds__(256) void near_assemble_kernel(int64_t n_units, const NearUnit *__restrict__ units,
                                                             const uint32_t *__restrict__ col,
                                                             const double4 *__restrict__ geom, TouchValues tv,
                                                             double *__restrict__ val)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t t = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
-    if (t >= n_leaves) return;
-    const double4 gt = geom[t];
-    for (int64_t e = row[t] + lane; e < row[t + 1]; e += kWave) val[e] = near_entry(col[e], gt, geom, tv);
+    const int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (w >= n_units) return;
+    const NearUnit un = units[w];
+    const double4 gt = geom[un.target];
+    for (int64_t e = un.begin + lane; e < un.end; e += kWave) val[e] = near_entry(col[e], gt, geom, tv);
 }
 
 // ---- regular cube pairs (touching-integral self-similarity system) -------------------------------
@@ -566,23 +628,27 @@ struct PhaseMarks {
 template <int Q>
 void launch_near(const bcv_plan_s &p, const double *f, const double *lam, int parts, double *u, hipStream_t st)
 {
-    const unsigned blocks = (unsigned)((p.n_leaves + 3) / 4);
+    const unsigned blocks = (unsigned)((p.n_units + 3) / 4);
     const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
     if (p.d_val)
-        near_eval_kernel<Q, true, false><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_row, p.d_split, p.d_col, p.d_val,
+        near_eval_kernel<Q, true, false><<<blocks, 256, 0, st>>>(p.n_units, p.d_units, p.d_split, p.d_col, p.d_val,
                                                                  geom, f, lam, p.d_leaf_cell, touch_values(p),
-                                                                 parts, u);
+                                                                 parts, p.d_partial, u);
     else if (p.precision == BCV_MIXED_F32)
-        near_eval_kernel<Q, false, true><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_row, p.d_split, p.d_col, nullptr,
+        near_eval_kernel<Q, false, true><<<blocks, 256, 0, st>>>(p.n_units, p.d_units, p.d_split, p.d_col, nullptr,
                                                                  geom, f, lam, p.d_leaf_cell, touch_values(p),
-                                                                 parts, u);
+                                                                 parts, p.d_partial, u);
     else
-        near_eval_kernel<Q, false, false><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_row, p.d_split, p.d_col, nullptr,
+        near_eval_kernel<Q, false, false><<<blocks, 256, 0, st>>>(p.n_units, p.d_units, p.d_split, p.d_col, nullptr,
                                                                   geom, f, lam, p.d_leaf_cell, touch_values(p),
-                                                                  parts, u);
+                                                                  parts, p.d_partial, u);
     check_launch();
+    if (p.n_splits > 0) {
+        near_combine_kernel<Q><<<(unsigned)((p.n_splits + 3) / 4), 256, 0, st>>>(
+            p.n_splits, p.d_splits, p.d_partial, geom, (parts & BCV_PART_FAR) ? lam : nullptr, p.d_leaf_cell, u);
+        check_launch();
+    }
 }
-
 template <int Q>
 void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStream_t st)
 {
@@ -617,19 +683,27 @@ void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStre
         marks.stop(BCV_PHASE_M2M, st);
         marks.start(BCV_PHASE_M2L, st);
         if (p.n_tasks > 0) {
-            const unsigned groups = (unsigned)(kXcds * ((p.n_tasks + kXcds - 1) / kXcds));
+            const unsigned groups = (unsigned)p.m2l_groups;
+            XcdRanges ranges;
+            for (int x = 0; x <= kXcds; ++x) ranges.begin[x] = p.xcd_begin[x];
             if (p.precision == BCV_MIXED_F32) {
                 const int64_t n = (p.n_cells + 1) * K;
                 to_f32_kernel<<<(unsigned)std::min<int64_t>((n + 255) / 256, 65536), 256, 0, st>>>(n, p.d_M, p.d_M32);
                 check_launch();
-                m2l_kernel<Q, float><<<groups, kWave, 0, st>>>((int)p.n_tasks, p.d_tasks, p.d_task_targets,
-                                                               p.d_slot_off, p.d_slot_src, p.d_G32, p.d_M32,
+                m2l_kernel<Q, float><<<groups, kWave, 0, st>>>(ranges, p.d_tasks, p.d_task_targets, p.d_slot_off,
+                                                               p.d_slot_src, p.d_G32, p.d_M32, p.d_m2l_partial,
                                                                p.d_Lam);
             } else {
-                m2l_kernel<Q, double><<<groups, kWave, 0, st>>>((int)p.n_tasks, p.d_tasks, p.d_task_targets,
-                                                                p.d_slot_off, p.d_slot_src, p.d_G, p.d_M, p.d_Lam);
+                m2l_kernel<Q, double><<<groups, kWave, 0, st>>>(ranges, p.d_tasks, p.d_task_targets, p.d_slot_off,
+                                                                p.d_slot_src, p.d_G, p.d_M, p.d_m2l_partial,
+                                                                p.d_Lam);
             }
             check_launch();
+            if (p.n_m2l_splits > 0) {
+                m2l_combine_kernel<Q><<<dim3((unsigned)p.n_m2l_splits, (K + 3) / 4), 256, 0, st>>>(
+                    p.d_m2l_splits, p.d_task_targets, p.d_m2l_partial, p.d_Lam);
+                check_launch();
+            }
         }
         marks.stop(BCV_PHASE_M2L, st);
         marks.start(BCV_PHASE_L2L, st);
@@ -671,8 +745,8 @@ void launch_apply(const bcv_plan_s &p, const double *f, double *u, int parts, hi
 
 void launch_near_assemble(const bcv_plan_s &p, hipStream_t st)
 {
-    const unsigned blocks = (unsigned)((p.n_leaves + 3) / 4);
-    near_assemble_kernel<<<blocks, 256, 0, st>>>(p.n_leaves, p.d_row, p.d_col,
+    const unsigned blocks = (unsigned)((p.n_units + 3) / 4);
+    near_assemble_kernel<<<blocks, 256, 0, st>>>(p.n_units, p.d_units, p.d_col,
                                                  reinterpret_cast<const double4 *>(p.d_leaf_geom), touch_values(p),
                                                  p.d_val);
     check_launch();

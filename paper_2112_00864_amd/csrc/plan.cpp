@@ -208,13 +208,63 @@ NearCSR build_near(const bcv_tree_s &t, const std::vector<Grid> &g, const LeafGe
     return r;
 }
 
+// Near-field work units of at most kNearUnitPairs entries (a few hundred point-rule pairs per
+// wave). A row is cut into equal pieces; units are ordered longest first so that the long units
+// start early.
+constexpr int64_t kNearUnitPairs = 512;
+
+struct NearUnits {
+    std::vector<NearUnit> units;
+    std::vector<NearSplit> splits;
+    int64_t n_partial = 0;
+};
+
+NearUnits build_near_units(const NearCSR &near, int64_t n_leaves)
+{
+    NearUnits r;
+    for (int64_t t = 0; t < n_leaves; ++t) {
+        const int64_t b = near.row[t], len = near.row[t + 1] - b;
+        const int64_t pieces = std::max<int64_t>(1, (len + kNearUnitPairs - 1) / kNearUnitPairs);
+        if (pieces == 1) {
+            r.units.push_back(NearUnit{b, b + len, (int32_t)t, -1});
+            continue;
+        }
+        BCV_REQUIRE(r.n_partial + pieces < INT32_MAX, BCV_ENOTSUP, "near field too large");
+        r.splits.push_back(NearSplit{(int32_t)t, (int32_t)r.n_partial, (int32_t)pieces, 0});
+        for (int64_t k = 0; k < pieces; ++k)
+            r.units.push_back(NearUnit{b + len * k / pieces, b + len * (k + 1) / pieces, (int32_t)t,
+                                       (int32_t)(r.n_partial + k)});
+        r.n_partial += pieces;
+    }
+    std::stable_sort(r.units.begin(), r.units.end(),
+                     [](const NearUnit &x, const NearUnit &y) { return x.end - x.begin > y.end - y.begin; });
+    // every entry of every row is covered by exactly one unit
+    std::vector<int64_t> covered(n_leaves, 0);
+    for (const NearUnit &u : r.units) {
+        BCV_REQUIRE(u.target >= 0 && u.target < n_leaves && u.begin >= near.row[u.target] &&
+                        u.end <= near.row[u.target + 1] && u.begin <= u.end && u.out < r.n_partial,
+                    BCV_ESTATE, "internal: near unit out of range");
+        covered[u.target] += u.end - u.begin;
+    }
+    for (int64_t t = 0; t < n_leaves; ++t)
+        BCV_REQUIRE(covered[t] == near.row[t + 1] - near.row[t], BCV_ESTATE, "internal: near units do not tile a row");
+    return r;
+}
+
 struct M2LPlan {
     std::vector<M2LTask> tasks;
     std::vector<int32_t> targets;   // 64 per task
     std::vector<int32_t> slot_key;  // offset key per slot, later replaced by the offset id
     std::vector<int32_t> slot_src;  // 64 per slot
+    std::vector<M2LSplit> splits;
+    int32_t n_pieces = 0;           // partial blocks of split tasks
+    int32_t xcd_begin[kXcds + 1] = {};
     int64_t n_pairs = 0;
 };
+
+// Longest slot list of one interaction task: longer lists (the remainder tasks, whose lanes
+// belong to many signature classes) are cut into pieces so that no wave outlasts the others.
+constexpr int32_t kMaxTaskSlots = 256;
 
 int offset_key(int a, int b, int c) { return ((a + 7) * 15 + (b + 7)) * 15 + (c + 7); }
 
@@ -342,20 +392,65 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g)
             }
         }
     }
-    for (size_t q = 0; q < chunks.size(); ++q) {
+    // Pieces of at most kMaxTaskSlots slots, in task order.
+    struct Piece {
         M2LTask task;
-        task.slot_begin = (int32_t)m.slot_key.size();
-        task.n_slots = (int32_t)outs[q].keys.size();
-        task.level = chunks[q].lev;
-        task.pad = 0;
-        m.tasks.push_back(task);
-        for (int lane = 0; lane < 64; ++lane)
-            m.targets.push_back(lane < (int)chunks[q].cells.size() ? chunks[q].cells[lane] : -1);
+        int32_t chunk;
+    };
+    std::vector<Piece> pieces;
+    std::vector<M2LSplit> split_of_chunk(chunks.size(), M2LSplit{-1, 0, 0, 0});
+    for (size_t q = 0; q < chunks.size(); ++q) {
+        const int32_t base = (int32_t)m.slot_key.size();
+        const int32_t n = (int32_t)outs[q].keys.size();
+        const int32_t np = std::max<int32_t>(1, (n + kMaxTaskSlots - 1) / kMaxTaskSlots);
+        if (np > 1) split_of_chunk[q] = M2LSplit{-1, m.n_pieces, np, 0};
+        for (int32_t k = 0; k < np; ++k) {
+            const int32_t b = base + (int32_t)((int64_t)n * k / np), e = base + (int32_t)((int64_t)n * (k + 1) / np);
+            pieces.push_back(Piece{M2LTask{b, e - b, chunks[q].lev, np > 1 ? m.n_pieces + k : -1}, (int32_t)q});
+        }
+        if (np > 1) m.n_pieces += np;
         m.slot_key.insert(m.slot_key.end(), outs[q].keys.begin(), outs[q].keys.end());
         m.slot_src.insert(m.slot_src.end(), outs[q].src.begin(), outs[q].src.end());
         m.n_pairs += outs[q].pairs;
     }
     BCV_REQUIRE(m.slot_key.size() < (size_t)INT32_MAX, BCV_ENOTSUP, "interaction plan too large");
+    // XCD ranges: contiguous runs of pieces (spatially ordered, so an XCD's L2 sees neighbouring
+    // sources) with about equal slot totals; inside a range the longest pieces go first.
+    int64_t total = 0;
+    for (const Piece &pc : pieces) total += pc.task.n_slots;
+    std::vector<size_t> cut(kXcds + 1, pieces.size());
+    cut[0] = 0;
+    {
+        int64_t acc = 0;
+        int x = 1;
+        for (size_t i = 0; i < pieces.size() && x < kXcds; ++i) {
+            acc += pieces[i].task.n_slots;
+            while (x < kXcds && acc * kXcds >= total * x) cut[x++] = i + 1;
+        }
+    }
+    for (int x = 0; x < kXcds; ++x)
+        std::stable_sort(pieces.begin() + cut[x], pieces.begin() + cut[x + 1],
+                         [](const Piece &a, const Piece &b) { return a.task.n_slots > b.task.n_slots; });
+    for (int x = 0; x <= kXcds; ++x) m.xcd_begin[x] = (int32_t)cut[x];
+    for (const Piece &pc : pieces) {
+        const int32_t ti = (int32_t)m.tasks.size();
+        m.tasks.push_back(pc.task);
+        const Chunk &ch = chunks[pc.chunk];
+        for (int lane = 0; lane < 64; ++lane) m.targets.push_back(lane < (int)ch.cells.size() ? ch.cells[lane] : -1);
+        M2LSplit &sp = split_of_chunk[pc.chunk];
+        if (pc.task.out == sp.first && sp.count > 1) sp.task = ti;  // the first piece carries the targets
+    }
+    for (const M2LSplit &sp : split_of_chunk)
+        if (sp.count > 1) m.splits.push_back(sp);
+    for (const M2LTask &tk : m.tasks)
+        BCV_REQUIRE(tk.slot_begin >= 0 && tk.n_slots >= 0 && (size_t)tk.slot_begin + tk.n_slots <= m.slot_key.size() &&
+                        tk.out < m.n_pieces,
+                    BCV_ESTATE, "internal: interaction task out of range");
+    for (const M2LSplit &sp : m.splits)
+        BCV_REQUIRE(sp.task >= 0 && sp.task < (int32_t)m.tasks.size() && sp.first >= 0 &&
+                        sp.first + sp.count <= m.n_pieces,
+                    BCV_ESTATE, "internal: split interaction task out of range");
+    BCV_REQUIRE(m.xcd_begin[kXcds] == (int32_t)m.tasks.size(), BCV_ESTATE, "internal: XCD ranges");
     return m;
 }
 
@@ -430,9 +525,14 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         NearCSR near = build_near(t, grids, geo, opts.direct != 0);
         p->n_near = (int64_t)near.col.size();
         p->n_touch = near.n_touch;
-        p->d_row = upload(p.get(), near.row);
         p->d_split = upload(p.get(), near.split);
         p->d_col = upload(p.get(), near.col);
+        const NearUnits nu = build_near_units(near, p->n_leaves);
+        p->n_units = (int64_t)nu.units.size();
+        p->n_splits = (int64_t)nu.splits.size();
+        p->d_units = upload(p.get(), nu.units);
+        p->d_splits = upload(p.get(), nu.splits);
+        if (nu.n_partial > 0) p->d_partial = alloc_zero<double>(p.get(), (size_t)nu.n_partial);
     }
 
     if (!opts.direct) {
@@ -477,6 +577,14 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         p->d_task_targets = upload(p.get(), m2l.targets);
         p->d_slot_off = upload(p.get(), m2l.slot_key);
         p->d_slot_src = upload(p.get(), m2l.slot_src);
+        p->n_m2l_splits = (int64_t)m2l.splits.size();
+        p->d_m2l_splits = upload(p.get(), m2l.splits);
+        if (m2l.n_pieces > 0)
+            p->d_m2l_partial = alloc_zero<double>(p.get(), (size_t)m2l.n_pieces * 64 * p->K);
+        int32_t longest = 0;
+        for (int x = 0; x <= kXcds; ++x) p->xcd_begin[x] = m2l.xcd_begin[x];
+        for (int x = 0; x < kXcds; ++x) longest = std::max(longest, m2l.xcd_begin[x + 1] - m2l.xcd_begin[x]);
+        p->m2l_groups = (int64_t)kXcds * longest;
         p->d_M = alloc_zero<double>(p.get(), (size_t)(p->n_cells + 1) * p->K);
         p->d_Lam = alloc_zero<double>(p.get(), (size_t)p->n_cells * p->K);
         if (p->precision == BCV_MIXED_F32) p->d_M32 = alloc_zero<float>(p.get(), (size_t)(p->n_cells + 1) * p->K);
@@ -499,9 +607,11 @@ void destroy_plan(bcv_plan_s *p)
     if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
     if (p->ev_join) (void)hipEventDestroy(p->ev_join);
     if (p->side) (void)hipStreamDestroy(p->side);
-    void *bufs[] = {p->d_leaf_geom, p->d_leaf_cell, p->d_row, p->d_split, p->d_col, p->d_val, p->d_M, p->d_Lam, p->d_G,
+    void *bufs[] = {p->d_leaf_geom, p->d_leaf_cell, p->d_split, p->d_col, p->d_val, p->d_units,
+                    p->d_splits, p->d_partial, p->d_M, p->d_Lam, p->d_G,
                     p->d_M32, p->d_G32,
-                    p->d_parents, p->d_tasks, p->d_task_targets, p->d_slot_off, p->d_slot_src};
+                    p->d_parents, p->d_tasks, p->d_task_targets, p->d_slot_off, p->d_slot_src,
+                    p->d_m2l_splits, p->d_m2l_partial};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     p->magic = 0;
