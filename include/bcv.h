@@ -68,7 +68,7 @@ enum { BCV_FP64 = 0, BCV_MIXED_F32 = 1 };
 /* Plan options. */
 typedef struct {
     double eta0;   /* separation parameter of the neighbour test (eq. def:neighbors); must be 0.5 */
-    int q;         /* expansion order, |alpha| + |beta| <= q (Sec. 3); supported: 4, 6 */
+    int q;         /* expansion order, |alpha| + |beta| <= q (Sec. 3); supported: 4, 6, 8 */
     int precision; /* BCV_FP64 or BCV_MIXED_F32 */
     int direct;    /* 1: every leaf pair is treated as near (no far field; small meshes only) */
     int nearfield; /* BCV_NEAR_QUADRATURE: the apply evaluates every near-pair entry on the fly;

@@ -121,7 +121,7 @@ bcv_status bcv_plan_interactions(bcv_tree tree, const bcv_plan_opts *opts, int d
         BCV_REQUIRE(opts != nullptr && out != nullptr, BCV_EINVAL, "NULL argument");
         *out = nullptr;
         BCV_REQUIRE(opts->eta0 == 0.5, BCV_EINVAL, "eta0 must be 0.5");
-        BCV_REQUIRE(opts->q == 4 || opts->q == 6, BCV_EINVAL, "q must be 4 or 6");
+        BCV_REQUIRE(opts->q == 4 || opts->q == 6 || opts->q == 8, BCV_EINVAL, "q must be 4, 6 or 8");
         BCV_REQUIRE(opts->precision == BCV_FP64 || opts->precision == BCV_MIXED_F32, BCV_EINVAL,
                     "precision must be BCV_FP64 or BCV_MIXED_F32");
         BCV_REQUIRE(opts->direct == 0 || opts->direct == 1, BCV_EINVAL, "direct must be 0 or 1");

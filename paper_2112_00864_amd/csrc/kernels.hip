@@ -177,7 +177,12 @@ __global__ void p2m_kernel(int64_t n_leaves, const int32_t *__restrict__ leaf_ce
 // so the 8 children are combined pairwise along x, then y, then z (M2M), and the parent is
 // expanded along z, then y, then x (L2L): 14 one-dimensional passes per parent instead of 8 full
 // three-dimensional sums.
-constexpr int kTreeWaves = 4;  // parents per 256-thread block
+// Parents per block (one wave each); fewer at q = 8 to keep the LDS buffers of a block small.
+template <int Q>
+constexpr int tree_waves()
+{
+    return Q <= 6 ? 4 : 2;
+}
 
 template <int Q, int AX>
 __device__ __forceinline__ int step_index(int a0, int a1, int a2, int v)  // index with component AX replaced by v
@@ -206,13 +211,13 @@ __device__ __forceinline__ void m2m_pass(const double *in0, const double *in1, d
 }
 
 template <int Q>
-__global__ __launch_bounds__(kWave *kTreeWaves) void m2m_kernel(int n_par, const int32_t *__restrict__ parents,
-                                                                 double *__restrict__ M)
+__global__ __launch_bounds__(kWave *tree_waves<Q>()) void m2m_kernel(int n_par, const int32_t *__restrict__ parents,
+                                                                      double *__restrict__ M)
 {
     constexpr int K = MultiIndex<Q>::K;
-    __shared__ double buf[kTreeWaves][14][K];
+    __shared__ double buf[tree_waves<Q>()][14][K];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int pi = blockIdx.x * kTreeWaves + wave;
+    const int pi = blockIdx.x * tree_waves<Q>() + wave;
     const bool active = pi < n_par;
     double(*B)[K] = buf[wave];
     int32_t cell = 0;
@@ -229,7 +234,7 @@ __global__ __launch_bounds__(kWave *kTreeWaves) void m2m_kernel(int n_par, const
         for (int z = 0; z < 2; ++z) m2m_pass<Q, 1>(B[8 + 2 * z], B[8 + 2 * z + 1], B[12 + z], lane);
     __syncthreads();
     if (active) {  // z: slots 12, 13 -> parent moments
-        double out[2];
+        double out[(K + kWave - 1) / kWave];
         constexpr auto &mi = Tables<Q>::mi;
         int n = 0;
         for (int b = lane; b < K; b += kWave, ++n) {
@@ -268,14 +273,14 @@ __device__ __forceinline__ void l2l_pass(const double *in, double *out0, double 
 }
 
 template <int Q>
-__global__ __launch_bounds__(kWave *kTreeWaves) void l2l_kernel(int n_par, const int32_t *__restrict__ parents,
-                                                                 double *__restrict__ Lam)
+__global__ __launch_bounds__(kWave *tree_waves<Q>()) void l2l_kernel(int n_par, const int32_t *__restrict__ parents,
+                                                                      double *__restrict__ Lam)
 {
     constexpr auto &mi = Tables<Q>::mi;
     constexpr int K = MultiIndex<Q>::K;
-    __shared__ double buf[kTreeWaves][15][K];
+    __shared__ double buf[tree_waves<Q>()][15][K];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int pi = blockIdx.x * kTreeWaves + wave;
+    const int pi = blockIdx.x * tree_waves<Q>() + wave;
     const bool active = pi < n_par;
     double(*B)[K] = buf[wave];
     int32_t child0 = 0;
@@ -304,19 +309,28 @@ __global__ __launch_bounds__(kWave *kTreeWaves) void l2l_kernel(int n_par, const
 
 // ---- M2L: 64 targets per wave, one uniform interaction offset per slot --------------------------
 // acc[a] += D^{a+b} g(o) * M_s^b for all |a| + |b| <= Q, straight-line code from the index tables.
-template <int Q, int B, class T, class GP, int... A>
+// A wave may hold only the coefficients a in [A0, A1) (acc[a - A0]); column b then touches
+// a in [A0, min(A1, ncoef(Q - |b|))), and a column with none of them is not loaded at all.
+template <int Q, int A0, int B, class T, class GP, int... A>
 __device__ __forceinline__ void m2l_column(T *acc, GP G, T mb, std::integer_sequence<int, A...>)
 {
     constexpr auto &mi = Tables<Q>::mi;
-    ((acc[A] = fma(G[mi.sum(A, B)], mb, acc[A])), ...);
+    ((acc[A] = fma(G[mi.sum(A0 + A, B)], mb, acc[A])), ...);
 }
 
-template <int Q, class T, int... B>
+template <int Q, class T, int A0, int A1, int B>
+__device__ __forceinline__ void m2l_beta(T *acc, const T *__restrict__ G, const T *__restrict__ Ms)
+{
+    constexpr int n = ncoef(Q - Tables<Q>::mi.deg[B]);
+    constexpr int hi = n < A1 ? n : A1;
+    if constexpr (hi > A0) m2l_column<Q, A0, B>(acc, G, Ms[B], std::make_integer_sequence<int, hi - A0>{});
+}
+
+template <int Q, class T, int A0, int A1, int... B>
 __device__ __forceinline__ void m2l_all(T *acc, const T *__restrict__ G, const T *__restrict__ Ms,
                                         std::integer_sequence<int, B...>)
 {
-    constexpr auto &mi = Tables<Q>::mi;
-    (m2l_column<Q, B>(acc, G, Ms[B], std::make_integer_sequence<int, ncoef(Q - mi.deg[B])>{}), ...);
+    (m2l_beta<Q, T, A0, A1, B>(acc, G, Ms), ...);
 }
 
 // Workgroups are dealt to the 8 XCDs round-robin (workgroup b runs on XCD b mod 8). XCD x runs
@@ -333,21 +347,23 @@ __device__ __forceinline__ int xcd_task(const XcdRanges &r)
 }
 
 // T = double (BCV_FP64) or float (BCV_MIXED_F32: FP32 moments, tables and accumulation; the
-// local coefficients are written in FP64).
-template <int Q, class T>
+// local coefficients are written in FP64). The wave accumulates Lambda^a for a in [A0, A1): all
+// of them when the accumulators fit the register budget of two waves per SIMD, else the range is
+// split over launches (q = 8 in FP64).
+template <int Q, class T, int A0, int A1>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2, 2))) void m2l_kernel(
     XcdRanges ranges, const M2LTask *__restrict__ tasks, const int32_t *__restrict__ targets,
     const int32_t *__restrict__ slot_off, const int32_t *__restrict__ slot_src, const T *__restrict__ G,
     const T *__restrict__ M, double *__restrict__ partial, double *__restrict__ Lam)
 {
-    constexpr int K = MultiIndex<Q>::K;
+    constexpr int K = MultiIndex<Q>::K, NA = A1 - A0;
     const int ti = xcd_task(ranges);
     if (ti < 0) return;
     const M2LTask task = tasks[ti];
     const int lane = threadIdx.x;
-    T acc[K];
+    T acc[NA];
 #pragma unroll
-    for (int a = 0; a < K; ++a) acc[a] = T(0);
+    for (int a = 0; a < NA; ++a) acc[a] = T(0);
     // the next slot's offset and source are fetched one slot ahead
     int32_t off_next = 0, src_next = 0;
     if (task.n_slots > 0) {
@@ -363,18 +379,18 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2, 2))) v
         }
         const T *__restrict__ Gs = G + (int64_t)off * K;
         const T *__restrict__ Ms = M + (int64_t)src * K;
-        m2l_all<Q, T>(acc, Gs, Ms, std::make_integer_sequence<int, K>{});
+        m2l_all<Q, T, A0, A1>(acc, Gs, Ms, std::make_integer_sequence<int, K>{});
     }
     const int32_t t = targets[(int64_t)ti * kWave + lane];
     if (t < 0) return;
     const double inv_a = ldexp(1.0, task.level);
     if (task.out < 0) {
 #pragma unroll
-        for (int a = 0; a < K; ++a) Lam[(int64_t)t * K + a] = (double)acc[a] * inv_a;
+        for (int a = 0; a < NA; ++a) Lam[(int64_t)t * K + A0 + a] = (double)acc[a] * inv_a;
     } else {  // [piece][a][lane]: coalesced
-        double *__restrict__ dst = partial + (int64_t)task.out * K * kWave + lane;
+        double *__restrict__ dst = partial + ((int64_t)task.out * K + A0) * kWave + lane;
 #pragma unroll
-        for (int a = 0; a < K; ++a) dst[a * kWave] = (double)acc[a] * inv_a;
+        for (int a = 0; a < NA; ++a) dst[a * kWave] = (double)acc[a] * inv_a;
     }
 }
 
@@ -649,6 +665,31 @@ void launch_near(const bcv_plan_s &p, const double *f, const double *lam, int pa
         check_launch();
     }
 }
+// Interaction kernel over all tasks. Up to q = 6 one wave holds all K accumulators; at q = 8
+// (K = 165) the coefficient range is split in two launches, |a| <= 5 and 6 <= |a| <= 8, to stay
+// within the register budget of two waves per SIMD.
+template <int Q, class T>
+void launch_m2l(const bcv_plan_s &p, const T *G, const T *M, hipStream_t st)
+{
+    constexpr int K = MultiIndex<Q>::K;
+    const unsigned groups = (unsigned)p.m2l_groups;
+    XcdRanges ranges;
+    for (int x = 0; x <= kXcds; ++x) ranges.begin[x] = p.xcd_begin[x];
+    if constexpr (K <= 84) {
+        m2l_kernel<Q, T, 0, K><<<groups, kWave, 0, st>>>(ranges, p.d_tasks, p.d_task_targets, p.d_slot_off,
+                                                         p.d_slot_src, G, M, p.d_m2l_partial, p.d_Lam);
+        check_launch();
+    } else {
+        constexpr int S = ncoef(Q - 3);  // |a| <= Q - 3, then the rest
+        m2l_kernel<Q, T, 0, S><<<groups, kWave, 0, st>>>(ranges, p.d_tasks, p.d_task_targets, p.d_slot_off,
+                                                         p.d_slot_src, G, M, p.d_m2l_partial, p.d_Lam);
+        check_launch();
+        m2l_kernel<Q, T, S, K><<<groups, kWave, 0, st>>>(ranges, p.d_tasks, p.d_task_targets, p.d_slot_off,
+                                                         p.d_slot_src, G, M, p.d_m2l_partial, p.d_Lam);
+        check_launch();
+    }
+}
+
 template <int Q>
 void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStream_t st)
 {
@@ -676,29 +717,21 @@ void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStre
         for (int lev = p.L - 1; lev >= 2; --lev) {  // upward pass; moments below level 2 are never used
             const int n_par = p.parent_begin[lev + 1] - p.parent_begin[lev];
             if (n_par == 0) continue;
-            m2m_kernel<Q><<<(unsigned)((n_par + kTreeWaves - 1) / kTreeWaves), kWave * kTreeWaves, 0, st>>>(
+            m2m_kernel<Q><<<(unsigned)((n_par + tree_waves<Q>() - 1) / tree_waves<Q>()), kWave * tree_waves<Q>(), 0, st>>>(
                 n_par, p.d_parents + 2 * p.parent_begin[lev], p.d_M);
             check_launch();
         }
         marks.stop(BCV_PHASE_M2M, st);
         marks.start(BCV_PHASE_M2L, st);
         if (p.n_tasks > 0) {
-            const unsigned groups = (unsigned)p.m2l_groups;
-            XcdRanges ranges;
-            for (int x = 0; x <= kXcds; ++x) ranges.begin[x] = p.xcd_begin[x];
             if (p.precision == BCV_MIXED_F32) {
                 const int64_t n = (p.n_cells + 1) * K;
                 to_f32_kernel<<<(unsigned)std::min<int64_t>((n + 255) / 256, 65536), 256, 0, st>>>(n, p.d_M, p.d_M32);
                 check_launch();
-                m2l_kernel<Q, float><<<groups, kWave, 0, st>>>(ranges, p.d_tasks, p.d_task_targets, p.d_slot_off,
-                                                               p.d_slot_src, p.d_G32, p.d_M32, p.d_m2l_partial,
-                                                               p.d_Lam);
+                launch_m2l<Q, float>(p, p.d_G32, p.d_M32, st);
             } else {
-                m2l_kernel<Q, double><<<groups, kWave, 0, st>>>(ranges, p.d_tasks, p.d_task_targets, p.d_slot_off,
-                                                                p.d_slot_src, p.d_G, p.d_M, p.d_m2l_partial,
-                                                                p.d_Lam);
+                launch_m2l<Q, double>(p, p.d_G, p.d_M, st);
             }
-            check_launch();
             if (p.n_m2l_splits > 0) {
                 m2l_combine_kernel<Q><<<dim3((unsigned)p.n_m2l_splits, (K + 3) / 4), 256, 0, st>>>(
                     p.d_m2l_splits, p.d_task_targets, p.d_m2l_partial, p.d_Lam);
@@ -710,7 +743,7 @@ void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStre
         for (int lev = 2; lev < p.L; ++lev) {  // downward pass
             const int n_par = p.parent_begin[lev + 1] - p.parent_begin[lev];
             if (n_par == 0) continue;
-            l2l_kernel<Q><<<(unsigned)((n_par + kTreeWaves - 1) / kTreeWaves), kWave * kTreeWaves, 0, st>>>(
+            l2l_kernel<Q><<<(unsigned)((n_par + tree_waves<Q>() - 1) / tree_waves<Q>()), kWave * tree_waves<Q>(), 0, st>>>(
                 n_par, p.d_parents + 2 * p.parent_begin[lev], p.d_Lam);
             check_launch();
         }
@@ -739,6 +772,7 @@ void launch_apply(const bcv_plan_s &p, const double *f, double *u, int parts, hi
     switch (p.q) {
     case 4: apply_q<4>(p, f, u, parts, st); break;
     case 6: apply_q<6>(p, f, u, parts, st); break;
+    case 8: apply_q<8>(p, f, u, parts, st); break;
     default: fail(BCV_ENOTSUP, "expansion order not compiled");
     }
 }

@@ -65,7 +65,7 @@ def test_direct_mode_matches_O1(L):
     assert np.max(np.abs(u - ref) / np.abs(ref)) < 1e-12
 
 
-@pytest.mark.parametrize("L,q", [(2, 4), (3, 4), (3, 6), (4, 6)])
+@pytest.mark.parametrize("L,q", [(2, 4), (3, 4), (3, 6), (4, 6), (3, 8), (4, 8)])
 def test_fmm_matches_O2(L, q):
     m, lv = mesh(L)
     f = synth.leaf_density(lv, seed=1)
@@ -113,7 +113,7 @@ def test_one_and_two_streams_agree(nearfield):
 MIXED_TOL = 1e-6  # gate for the mixed-precision apply (relative L2 of cell averages)
 
 
-@pytest.mark.parametrize("L,q", [(3, 4), (4, 6)])
+@pytest.mark.parametrize("L,q", [(3, 4), (4, 6), (4, 8)])
 def test_mixed_precision_against_O2(L, q):
     """FP32 M2L and FP32 far near field, FP64 singular pairs and accumulation: rel-L2 <= 1e-6 vs O2."""
     m, lv = mesh(L)
