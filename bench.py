@@ -128,7 +128,9 @@ def roofline(info, phase_avg, args, prec):
     else:
         near_roof = {"bound": "alu", "achieved": near_flops(info, args.q) / (near_ms * 1e-3) / 1e12,
                      "peak": peak, "unit": "TFLOP/s"}
-    m2l_name = "m2l_kernel<%d, %s>" % (args.q, "float" if mixed else "double")
+    K = (args.q + 1) * (args.q + 2) * (args.q + 3) // 6
+    K_first = K if K <= 84 else (args.q - 2) * (args.q - 1) * args.q // 6  # q = 8: two launches
+    m2l_name = "m2l_kernel<%d, %s, 0, %d>" % (args.q, "float" if mixed else "double", K_first)
     near_name = "near_eval_kernel<%d, %s, %s>" % (args.q, "true" if args.nearfield == "assembled" else "false",
                                                   "true" if mixed and args.nearfield != "assembled" else "false")
     for roof_, name in ((m2l_roof, m2l_name), (near_roof, near_name)):
