@@ -38,6 +38,7 @@ extern "C" {
 
 typedef struct bcv_tree_s *bcv_tree;
 typedef struct bcv_plan_s *bcv_plan;
+typedef struct bcv_mlp_s *bcv_mlp;
 
 typedef enum {
     BCV_OK = 0,
@@ -78,6 +79,13 @@ typedef struct {
                       2: the near field runs on a plan-owned second stream (default priority),
                       concurrently with moments, passes and interactions, joined back to the
                       caller's stream before the evaluation phase */
+    bcv_mlp surrogate;     /* NULL: the touching-pair integrals come from bcv_touching_integrals.
+                              Else the six face/edge/vertex classes take the trained surrogate's
+                              value where its error estimate is <= surrogate_tol (relative), and
+                              the high-order box-pair quadrature otherwise; the self class keeps
+                              the exact value. The plan copies the values: the network may be
+                              destroyed afterwards. */
+    double surrogate_tol;  /* e.g. 1e-7; 0 forces the fallback for every class */
 } bcv_plan_opts;
 
 /* Sizes of a plan (all counts, no pointers). */
@@ -92,6 +100,8 @@ typedef struct {
     int64_t device_bytes; /* device memory held by the plan */
     int32_t K;            /* expansion coefficients per cell, (q+1)(q+2)(q+3)/6 */
     int32_t L;
+    int32_t surrogate_classes; /* touching classes whose value came from the surrogate (0..6) */
+    int32_t pad;
 } bcv_plan_info;
 
 /* Build the BC octree of Sec. 2 on the host. desc and out must be non-NULL.
@@ -167,6 +177,83 @@ bcv_status bcv_btv_apply(bcv_plan plan, const double *q_face_dev, const double *
  * the cube (splitting both cubes into halves) with regular pairs integrated by a 6-D Gauss rule.
  * out: host, 7 doubles. Errors: BCV_EINVAL, BCV_EDEVICE. */
 bcv_status bcv_touching_integrals(int device, double *out);
+
+/* ---- Touching-pair surrogate -------------------------------------------------------------
+ * A small network (features -> width -> width -> 2, SiLU, FP32, trained on the GPU by the library's
+ * own forward, backward and Adam kernels) that corrects a low-order quadrature of the Galerkin
+ * integral of 1/|x-y| over two touching cubes to the accuracy of the high-order quadrature, which
+ * stays the fallback and the judge (Sec. 3: singular near-field entries by singularity-removing
+ * transforms and tensor Gauss rules).
+ *
+ * Canonical touching pair: A = [0,1]^3 is the smaller cube; B is a cube of side rho in [1, 2]
+ * touching A's +x face (FACE), the +x,+y edge (EDGE) or the +x,+y,+z vertex (VERTEX). B's lower
+ * corner is (1, off[0], off[1]) for FACE, (1, 1, off[0]) for EDGE and (1, 1, 1) for VERTEX, with
+ * every used off[k] in (-rho, 1). Any touching pair of axis-aligned cubes with side ratio in [1, 2]
+ * maps onto this form by a rigid motion and a scaling by the smaller side a; its Galerkin entry is
+ * J * a^5 / (4 pi) with J the canonical integral. */
+enum { BCV_CONTACT_FACE = 1, BCV_CONTACT_EDGE = 2, BCV_CONTACT_VERTEX = 3 };
+typedef struct {
+    int32_t contact; /* BCV_CONTACT_* */
+    int32_t pad;
+    double rho;      /* side of B / side of A, in [1, 2] */
+    double off[2];   /* free coordinates of B's lower corner; unused entries are ignored */
+} bcv_touch_pair;
+
+typedef struct {
+    int64_t n_train, n_valid; /* training pairs and held-out pairs (random canonical pairs) */
+    int32_t epochs, batch;    /* passes over the training pairs; minibatch size */
+    double lr;                /* peak Adam step (cosine decay to 0) */
+    uint64_t seed;            /* pairs, shuffling */
+    int32_t n_gauss_lo;       /* Gauss order of the corrected quadrature (e.g. 4) */
+    int32_t n_gauss_hi;       /* Gauss order of the reference quadrature (e.g. 16, at most 16) */
+    double tol;               /* acceptance tolerance used for the held-out report */
+} bcv_mlp_train_opts;
+
+typedef struct {
+    double residual_scale;             /* RMS of (J_hi - J_lo) / J_lo over the training pairs */
+    double kappa;                      /* factor of the error estimate, calibrated on the held-out
+                                          pairs: 1.5 x max (true error / raw estimate) */
+    double valid_max_rel_err_lo;       /* held-out: max |J_lo - J_hi| / |J_hi| (without the network) */
+    double valid_max_rel_err;          /* held-out: max relative error of the corrected value */
+    double valid_rms_rel_err;
+    double valid_max_rel_err_accepted; /* held-out: max relative error among accepted pairs */
+    int64_t valid_accepted;            /* held-out pairs whose error estimate is <= tol */
+} bcv_mlp_train_report;
+
+/* J for n pairs of axis-aligned boxes by the high-order quadrature: geom holds 12 doubles per pair
+ * (A lower corner, A upper corner, B lower corner, B upper corner), n_gauss points (1..16) per
+ * direction on every cell of the graded decomposition; out[n]. Host arrays; runs on `device`. A pair
+ * whose decomposition exceeds the kernel's lists gets NaN. Errors: BCV_EINVAL, BCV_ENOMEM, BCV_EDEVICE. */
+bcv_status bcv_box_pair_integrals(int device, int64_t n, const double *geom, int n_gauss, double *out);
+/* The same for canonical touching pairs (host arrays). Errors: BCV_EINVAL (not a touching pair). */
+bcv_status bcv_touch_pair_quadrature(int device, int64_t n, const bcv_touch_pair *pairs, int n_gauss, double *out);
+
+/* A network of the given width (2..1024) with seeded uniform(+-1/sqrt(fan-in)) weights on `device`. */
+bcv_status bcv_mlp_create(int width, uint64_t seed, int device, bcv_mlp *out);
+void bcv_mlp_destroy(bcv_mlp mlp);
+/* Parameters as one FP32 vector, in this order: W1 [6 x width] (row-major, input-major), b1 [width],
+ * W2 [width x width], b2 [width], W3 [width x 2], b3 [2]. Host arrays of bcv_mlp_num_params floats. */
+bcv_status bcv_mlp_num_params(bcv_mlp mlp, int64_t *n);
+bcv_status bcv_mlp_get_params(bcv_mlp mlp, float *params);
+bcv_status bcv_mlp_set_params(bcv_mlp mlp, const float *params);
+/* Y [n x 2] = network(X [n x 6]) with the GPU kernels (host arrays). */
+bcv_status bcv_mlp_forward(bcv_mlp mlp, int64_t n, const float *X, float *Y);
+/* Training loss of the batch (X [n x 6], targets r [n]) and its gradient with respect to every
+ * parameter (host arrays; grad has bcv_mlp_num_params floats), with the GPU kernels:
+ *   loss = mean (y0 - r)^2 + 0.1 mean (y1 - log(|y0 - r| + 1e-5))^2, the second term with y0 fixed. */
+bcv_status bcv_mlp_loss_grad(bcv_mlp mlp, int64_t n, const float *X, const float *r, double *loss, float *grad);
+/* Generates the pairs, computes J at both Gauss orders on the GPU, and trains with Adam. */
+bcv_status bcv_mlp_train(bcv_mlp mlp, const bcv_mlp_train_opts *opts, bcv_mlp_train_report *report);
+/* value[i] = the corrected J of pair i where its error estimate est_err[i] <= tol (relative; the raw
+ * estimate of the network's second output times the calibrated factor kappa), else the
+ * high-order quadrature (fallback[i] = 1); n_fallback counts the fallbacks. Host arrays.
+ * Errors: BCV_ESTATE (untrained network), BCV_EINVAL. */
+bcv_status bcv_surrogate_eval(bcv_mlp mlp, int64_t n, const bcv_touch_pair *pairs, double tol, double *value,
+                              double *est_err, int32_t *fallback, int64_t *n_fallback);
+/* Flat file: header (magic, version, inputs, width, both Gauss orders, residual scale, kappa) then the
+ * FP32 parameters. */
+bcv_status bcv_mlp_save(bcv_mlp mlp, const char *path);
+bcv_status bcv_mlp_load(const char *path, int device, bcv_mlp *out);
 
 /* Thread-local description of the last failure on this thread (valid until the next call). */
 const char *bcv_last_error(void);

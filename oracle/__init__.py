@@ -13,6 +13,8 @@ Contents (each function cites the passage of the paper it follows):
   direct.py    O1: u = A f by direct O(N^2) evaluation of the Galerkin entries.
   fmm.py       O2: Algorithm 1 step by step (near field, moments, upward pass, interaction
                phase, downward pass, evaluation) in FP64.
+  mlp.py       the touching-pair surrogate's network in FP64: forward pass, training loss and its
+               gradient by the chain rule (reference for the GPU kernels' gradients).
 
 Readings of the paper used here (all for the cube-octree form of the method):
   * marking rule: M_l = B_l (cells with a face on the boundary), l < L;

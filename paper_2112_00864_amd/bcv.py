@@ -31,13 +31,34 @@ class MeshDesc(ctypes.Structure):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("eta0", ctypes.c_double), ("q", ctypes.c_int), ("precision", ctypes.c_int),
-                ("direct", ctypes.c_int), ("nearfield", ctypes.c_int), ("streams", ctypes.c_int)]
+                ("direct", ctypes.c_int), ("nearfield", ctypes.c_int), ("streams", ctypes.c_int),
+                ("surrogate", ctypes.c_void_p), ("surrogate_tol", ctypes.c_double)]
 
 
 class PlanInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("n_leaves", "n_cells", "n_near", "n_touch", "n_m2l", "n_m2l_lanes",
-                                              "n_offsets", "device_bytes")] + [("K", ctypes.c_int32),
-                                                                               ("L", ctypes.c_int32)]
+                                              "n_offsets", "device_bytes")] + [
+        ("K", ctypes.c_int32), ("L", ctypes.c_int32), ("surrogate_classes", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+CONTACT_FACE, CONTACT_EDGE, CONTACT_VERTEX = 1, 2, 3
+
+
+class TouchPair(ctypes.Structure):
+    _fields_ = [("contact", ctypes.c_int32), ("pad", ctypes.c_int32), ("rho", ctypes.c_double),
+                ("off", ctypes.c_double * 2)]
+
+
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("n_train", ctypes.c_int64), ("n_valid", ctypes.c_int64), ("epochs", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("lr", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("n_gauss_lo", ctypes.c_int32), ("n_gauss_hi", ctypes.c_int32), ("tol", ctypes.c_double)]
+
+
+class TrainReport(ctypes.Structure):
+    _fields_ = [("residual_scale", ctypes.c_double), ("kappa", ctypes.c_double), ("valid_max_rel_err_lo", ctypes.c_double),
+                ("valid_max_rel_err", ctypes.c_double), ("valid_rms_rel_err", ctypes.c_double),
+                ("valid_max_rel_err_accepted", ctypes.c_double), ("valid_accepted", ctypes.c_int64)]
 
 
 def lib():
@@ -63,10 +84,30 @@ def lib():
         L.bcv_plan_enable_timing.argtypes = [vp, ctypes.c_int]
         L.bcv_plan_phase_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i64p]
         L.bcv_touching_integrals.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+        dp, fp, i32p = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int32)
+        L.bcv_box_pair_integrals.argtypes = [ctypes.c_int, ctypes.c_int64, dp, ctypes.c_int, dp]
+        L.bcv_touch_pair_quadrature.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.POINTER(TouchPair), ctypes.c_int,
+                                                dp]
+        L.bcv_mlp_create.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(vp)]
+        L.bcv_mlp_destroy.argtypes = [vp]
+        L.bcv_mlp_destroy.restype = None
+        L.bcv_mlp_num_params.argtypes = [vp, i64p]
+        L.bcv_mlp_get_params.argtypes = [vp, fp]
+        L.bcv_mlp_set_params.argtypes = [vp, fp]
+        L.bcv_mlp_forward.argtypes = [vp, ctypes.c_int64, fp, fp]
+        L.bcv_mlp_loss_grad.argtypes = [vp, ctypes.c_int64, fp, fp, dp, fp]
+        L.bcv_mlp_train.argtypes = [vp, ctypes.POINTER(TrainOpts), ctypes.POINTER(TrainReport)]
+        L.bcv_surrogate_eval.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(TouchPair), ctypes.c_double, dp, dp,
+                                         i32p, i64p]
+        L.bcv_mlp_save.argtypes = [vp, ctypes.c_char_p]
+        L.bcv_mlp_load.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(vp)]
         L.bcv_last_error.restype = ctypes.c_char_p
         for name in ("bcv_build_bc_tree", "bcv_tree_num_leaves", "bcv_tree_leaves", "bcv_plan_interactions",
                      "bcv_plan_get_info", "bcv_vtv_apply", "bcv_vtv_apply_parts", "bcv_vtb_apply", "bcv_btv_apply",
-                     "bcv_touching_integrals", "bcv_plan_enable_timing", "bcv_plan_phase_times"):
+                     "bcv_touching_integrals", "bcv_plan_enable_timing", "bcv_plan_phase_times",
+                     "bcv_box_pair_integrals", "bcv_touch_pair_quadrature", "bcv_mlp_create", "bcv_mlp_num_params",
+                     "bcv_mlp_get_params", "bcv_mlp_set_params", "bcv_mlp_forward", "bcv_mlp_loss_grad",
+                     "bcv_mlp_train", "bcv_surrogate_eval", "bcv_mlp_save", "bcv_mlp_load"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -135,8 +176,9 @@ class Plan:
 
 
 def plan_interactions(tree, q=6, eta0=0.5, direct=False, nearfield=NEAR_QUADRATURE, device=0, streams=2,
-                      precision=FP64):
-    opts = PlanOpts(eta0, q, precision, 1 if direct else 0, nearfield, streams)
+                      precision=FP64, surrogate=None, surrogate_tol=1e-7):
+    opts = PlanOpts(eta0, q, precision, 1 if direct else 0, nearfield, streams,
+                    surrogate.handle if surrogate is not None else None, surrogate_tol)
     h = ctypes.c_void_p()
     _check(lib().bcv_plan_interactions(tree.handle, ctypes.byref(opts), device, ctypes.byref(h)))
     return Plan(h, device)
@@ -201,3 +243,117 @@ def touching_integrals(device=0):
     out = np.empty(7)
     _check(lib().bcv_touching_integrals(device, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return out
+
+
+# ---- touching-pair surrogate ---------------------------------------------------------------------
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _fp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def box_pair_integrals(geom, n_gauss=16, device=0):
+    """int_A int_B 1/|x-y| for boxes given as rows (A lo, A hi, B lo, B hi) of 12 doubles."""
+    geom = np.ascontiguousarray(geom, dtype=np.float64).reshape(-1, 12)
+    out = np.empty(len(geom))
+    _check(lib().bcv_box_pair_integrals(device, len(geom), _dp(geom), n_gauss, _dp(out)))
+    return out
+
+
+def touch_pairs(contact, rho, off0=0.0, off1=0.0):
+    """Array of canonical touching pairs from broadcast arrays of parameters."""
+    contact, rho, off0, off1 = np.broadcast_arrays(np.asarray(contact), np.asarray(rho, dtype=np.float64),
+                                                   np.asarray(off0, dtype=np.float64),
+                                                   np.asarray(off1, dtype=np.float64))
+    arr = (TouchPair * contact.size)()
+    for i, (c, r, a, b) in enumerate(zip(contact.ravel(), rho.ravel(), off0.ravel(), off1.ravel())):
+        arr[i].contact, arr[i].rho = int(c), float(r)
+        arr[i].off[0], arr[i].off[1] = float(a), float(b)
+    return arr
+
+
+def touch_pair_quadrature(pairs, n_gauss=16, device=0):
+    out = np.empty(len(pairs))
+    _check(lib().bcv_touch_pair_quadrature(device, len(pairs), pairs, n_gauss, _dp(out)))
+    return out
+
+
+class MLP:
+    def __init__(self, handle, device):
+        self._h = handle
+        self.device = device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def num_params(self):
+        n = ctypes.c_int64()
+        _check(lib().bcv_mlp_num_params(self._h, ctypes.byref(n)))
+        return n.value
+
+    def get_params(self):
+        p = np.empty(self.num_params(), dtype=np.float32)
+        _check(lib().bcv_mlp_get_params(self._h, _fp(p)))
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == self.num_params()
+        _check(lib().bcv_mlp_set_params(self._h, _fp(p)))
+
+    def forward(self, X):
+        X = np.ascontiguousarray(X, dtype=np.float32).reshape(-1, 6)
+        Y = np.empty((len(X), 2), dtype=np.float32)
+        _check(lib().bcv_mlp_forward(self._h, len(X), _fp(X), _fp(Y)))
+        return Y
+
+    def loss_grad(self, X, r):
+        X = np.ascontiguousarray(X, dtype=np.float32).reshape(-1, 6)
+        r = np.ascontiguousarray(r, dtype=np.float32)
+        g = np.empty(self.num_params(), dtype=np.float32)
+        loss = ctypes.c_double()
+        _check(lib().bcv_mlp_loss_grad(self._h, len(X), _fp(X), _fp(r), ctypes.byref(loss), _fp(g)))
+        return loss.value, g
+
+    def train(self, n_train=100000, n_valid=4000, epochs=40, batch=1024, lr=2e-3, seed=42, n_gauss_lo=4,
+              n_gauss_hi=16, tol=1e-7):
+        opts = TrainOpts(n_train, n_valid, epochs, batch, lr, seed, n_gauss_lo, n_gauss_hi, tol)
+        rep = TrainReport()
+        _check(lib().bcv_mlp_train(self._h, ctypes.byref(opts), ctypes.byref(rep)))
+        return {n: getattr(rep, n) for n, _ in TrainReport._fields_}
+
+    def eval(self, pairs, tol=1e-7):
+        n = len(pairs)
+        value, est = np.empty(n), np.empty(n)
+        fb = np.empty(n, dtype=np.int32)
+        nf = ctypes.c_int64()
+        _check(lib().bcv_surrogate_eval(self._h, n, pairs, tol, _dp(value), _dp(est),
+                                        fb.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(nf)))
+        return value, est, fb.astype(bool)
+
+    def save(self, path):
+        _check(lib().bcv_mlp_save(self._h, os.fsencode(path)))
+
+    def destroy(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.bcv_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.destroy()
+
+
+def mlp_create(width=128, seed=0, device=0):
+    h = ctypes.c_void_p()
+    _check(lib().bcv_mlp_create(width, seed, device, ctypes.byref(h)))
+    return MLP(h, device)
+
+
+def mlp_load(path, device=0):
+    h = ctypes.c_void_p()
+    _check(lib().bcv_mlp_load(os.fsencode(path), device, ctypes.byref(h)))
+    return MLP(h, device)

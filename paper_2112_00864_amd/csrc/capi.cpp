@@ -5,6 +5,7 @@
 
 #include "internal.hpp"
 #include "kernels.hpp"
+#include "quadrature.hpp"
 
 namespace bcv {
 bcv_tree_s *build_tree(int L);
@@ -45,6 +46,19 @@ void check_tree(bcv_tree t)
 {
     BCV_REQUIRE(t != nullptr, BCV_EINVAL, "tree handle is NULL");
     BCV_REQUIRE(t->magic == bcv_tree_s::kMagic, BCV_ESTATE, "not a live bcv_tree");
+}
+
+void check_mlp(bcv_mlp m)
+{
+    BCV_REQUIRE(m != nullptr, BCV_EINVAL, "network handle is NULL");
+    BCV_REQUIRE(m->magic == bcv_mlp_s::kMagic, BCV_ESTATE, "not a live bcv_mlp");
+}
+
+void check_device(int device)
+{
+    int n_dev = 0;
+    BCV_HIP(hipGetDeviceCount(&n_dev));
+    BCV_REQUIRE(device >= 0 && device < n_dev, BCV_EINVAL, "no such HIP device");
 }
 
 void check_plan(bcv_plan p)
@@ -128,6 +142,11 @@ bcv_status bcv_plan_interactions(bcv_tree tree, const bcv_plan_opts *opts, int d
         BCV_REQUIRE(opts->nearfield == BCV_NEAR_QUADRATURE || opts->nearfield == BCV_NEAR_ASSEMBLED, BCV_EINVAL,
                     "unknown nearfield mode");
         BCV_REQUIRE(opts->streams == 1 || opts->streams == 2, BCV_EINVAL, "streams must be 1 or 2");
+        if (opts->surrogate) {
+            check_mlp(opts->surrogate);
+            BCV_REQUIRE(opts->surrogate_tol >= 0.0, BCV_EINVAL, "negative surrogate tolerance");
+            BCV_REQUIRE(opts->surrogate->device == device, BCV_EINVAL, "the surrogate lives on another device");
+        }
         int n_dev = 0;
         BCV_HIP(hipGetDeviceCount(&n_dev));
         BCV_REQUIRE(device >= 0 && device < n_dev, BCV_EINVAL, "no such HIP device");
@@ -150,6 +169,8 @@ bcv_status bcv_plan_get_info(bcv_plan plan, bcv_plan_info *info)
         info->device_bytes = plan->device_bytes;
         info->K = plan->K;
         info->L = plan->L;
+        info->surrogate_classes = plan->surrogate_classes;
+        info->pad = 0;
     });
 }
 
@@ -215,6 +236,123 @@ bcv_status bcv_touching_integrals(int device, double *out)
         BCV_HIP(hipGetDeviceCount(&n_dev));
         BCV_REQUIRE(device >= 0 && device < n_dev, BCV_EINVAL, "no such HIP device");
         on_device(device, [&] { bcv::touching_integrals(device, out); });
+    });
+}
+
+bcv_status bcv_box_pair_integrals(int device, int64_t n, const double *geom, int n_gauss, double *out)
+{
+    return guard([&] {
+        BCV_REQUIRE(n >= 0 && (n == 0 || (geom != nullptr && out != nullptr)), BCV_EINVAL, "bad arguments");
+        check_device(device);
+        on_device(device, [&] { bcv::box_pair_integrals(device, n, geom, n_gauss, out); });
+    });
+}
+
+bcv_status bcv_touch_pair_quadrature(int device, int64_t n, const bcv_touch_pair *pairs, int n_gauss, double *out)
+{
+    return guard([&] {
+        BCV_REQUIRE(n >= 0 && (n == 0 || (pairs != nullptr && out != nullptr)), BCV_EINVAL, "bad arguments");
+        BCV_REQUIRE(n_gauss >= 1 && n_gauss <= 16, BCV_EINVAL, "Gauss order must be 1..16");
+        check_device(device);
+        on_device(device, [&] { bcv::touch_pair_quadrature(device, n, pairs, n_gauss, out); });
+    });
+}
+
+bcv_status bcv_mlp_create(int width, uint64_t seed, int device, bcv_mlp *out)
+{
+    return guard([&] {
+        BCV_REQUIRE(out != nullptr, BCV_EINVAL, "NULL argument");
+        *out = nullptr;
+        check_device(device);
+        on_device(device, [&] { *out = bcv::mlp_create(width, seed, device); });
+    });
+}
+
+void bcv_mlp_destroy(bcv_mlp mlp)
+{
+    if (mlp && mlp->magic == bcv_mlp_s::kMagic) bcv::mlp_destroy(mlp);
+}
+
+bcv_status bcv_mlp_num_params(bcv_mlp mlp, int64_t *n)
+{
+    return guard([&] {
+        check_mlp(mlp);
+        BCV_REQUIRE(n != nullptr, BCV_EINVAL, "NULL argument");
+        *n = bcv::mlp_n_params(*mlp);
+    });
+}
+
+bcv_status bcv_mlp_get_params(bcv_mlp mlp, float *params)
+{
+    return guard([&] {
+        check_mlp(mlp);
+        BCV_REQUIRE(params != nullptr, BCV_EINVAL, "NULL argument");
+        on_device(mlp->device, [&] { bcv::mlp_get_params(*mlp, params); });
+    });
+}
+
+bcv_status bcv_mlp_set_params(bcv_mlp mlp, const float *params)
+{
+    return guard([&] {
+        check_mlp(mlp);
+        BCV_REQUIRE(params != nullptr, BCV_EINVAL, "NULL argument");
+        on_device(mlp->device, [&] { bcv::mlp_set_params(*mlp, params); });
+    });
+}
+
+bcv_status bcv_mlp_forward(bcv_mlp mlp, int64_t n, const float *X, float *Y)
+{
+    return guard([&] {
+        check_mlp(mlp);
+        BCV_REQUIRE(n >= 0 && (n == 0 || (X != nullptr && Y != nullptr)), BCV_EINVAL, "bad arguments");
+        on_device(mlp->device, [&] { bcv::mlp_forward_host(*mlp, n, X, Y); });
+    });
+}
+
+bcv_status bcv_mlp_loss_grad(bcv_mlp mlp, int64_t n, const float *X, const float *r, double *loss, float *grad)
+{
+    return guard([&] {
+        check_mlp(mlp);
+        BCV_REQUIRE(n >= 1 && X && r && loss && grad, BCV_EINVAL, "bad arguments");
+        on_device(mlp->device, [&] { *loss = bcv::mlp_loss_grad_host(*mlp, n, X, r, grad); });
+    });
+}
+
+bcv_status bcv_mlp_train(bcv_mlp mlp, const bcv_mlp_train_opts *opts, bcv_mlp_train_report *report)
+{
+    return guard([&] {
+        check_mlp(mlp);
+        BCV_REQUIRE(opts != nullptr, BCV_EINVAL, "NULL argument");
+        on_device(mlp->device, [&] { bcv::mlp_train(*mlp, *opts, report); });
+    });
+}
+
+bcv_status bcv_surrogate_eval(bcv_mlp mlp, int64_t n, const bcv_touch_pair *pairs, double tol, double *value,
+                              double *est_err, int32_t *fallback, int64_t *n_fallback)
+{
+    return guard([&] {
+        check_mlp(mlp);
+        BCV_REQUIRE(n >= 0 && (n == 0 || (pairs && value && est_err && fallback)), BCV_EINVAL, "bad arguments");
+        on_device(mlp->device, [&] { bcv::surrogate_eval(*mlp, n, pairs, tol, value, est_err, fallback, n_fallback); });
+    });
+}
+
+bcv_status bcv_mlp_save(bcv_mlp mlp, const char *path)
+{
+    return guard([&] {
+        check_mlp(mlp);
+        BCV_REQUIRE(path != nullptr, BCV_EINVAL, "NULL argument");
+        on_device(mlp->device, [&] { bcv::mlp_save(*mlp, path); });
+    });
+}
+
+bcv_status bcv_mlp_load(const char *path, int device, bcv_mlp *out)
+{
+    return guard([&] {
+        BCV_REQUIRE(path != nullptr && out != nullptr, BCV_EINVAL, "NULL argument");
+        *out = nullptr;
+        check_device(device);
+        on_device(device, [&] { *out = bcv::mlp_load(path, device); });
     });
 }
 

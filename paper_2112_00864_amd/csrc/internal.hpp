@@ -65,6 +65,36 @@ constexpr int kTouchClasses = 7;
 
 }  // namespace bcv
 
+// Surrogate network (surrogate.cpp): FP32 parameters, gradient and Adam moments on `device`.
+struct bcv_mlp_s {
+    static constexpr uint32_t kMagic = 0x42435650u ^ 0x00FF00FFu;
+    uint32_t magic = kMagic;
+    int device = 0;
+    int d_in = 0, width = 0;
+    int trained = 0;
+    int n_gauss_lo = 0, n_gauss_hi = 0;
+    double scale = 0.0;  // RMS of the relative residual (J_hi - J_lo) / J_lo over the training pairs
+    double kappa = 1.0;  // calibrated factor of the error estimate
+    float *d_params = nullptr, *d_grad = nullptr, *d_m = nullptr, *d_v = nullptr;
+};
+
+namespace bcv {
+constexpr int kMlpIn = 6, kMlpOut = 2;
+int64_t mlp_n_params(const bcv_mlp_s &net);
+bcv_mlp_s *mlp_create(int width, uint64_t seed, int device);
+void mlp_destroy(bcv_mlp_s *net);
+void mlp_get_params(const bcv_mlp_s &net, float *host);
+void mlp_set_params(bcv_mlp_s &net, const float *host);
+void mlp_forward_host(const bcv_mlp_s &net, int64_t n, const float *X, float *Y);
+double mlp_loss_grad_host(const bcv_mlp_s &net, int64_t n, const float *X, const float *r, float *grad);
+void mlp_train(bcv_mlp_s &net, const bcv_mlp_train_opts &o, bcv_mlp_train_report *rep);
+void surrogate_eval(const bcv_mlp_s &net, int64_t n, const bcv_touch_pair *pairs, double tol, double *value,
+                    double *est_err, int32_t *fallback, int64_t *n_fallback);
+void touch_pair_quadrature(int device, int64_t n, const bcv_touch_pair *pairs, int n_gauss, double *out);
+void mlp_save(const bcv_mlp_s &net, const char *path);
+bcv_mlp_s *mlp_load(const char *path, int device);
+}  // namespace bcv
+
 struct bcv_plan_s {
     static constexpr uint32_t kMagic = 0x42435650u;  // "BCVP"
     uint32_t magic = kMagic;
@@ -74,6 +104,7 @@ struct bcv_plan_s {
     int64_t n_leaves = 0, n_cells = 0, n_near = 0, n_touch = 0, n_m2l = 0, n_m2l_lanes = 0, n_offsets = 0;
     int64_t device_bytes = 0;
     double touch_value[bcv::kTouchClasses];  // touching integrals / (4 pi), smaller side 1
+    int surrogate_classes = 0;               // classes whose value came from the surrogate
 
     // Second stream for the near field (streams == 2) and its fork/join events.
     int streams = 1;

@@ -1,0 +1,187 @@
+// Kernels of the surrogate network: a multilayer perceptron with SiLU activations in FP32,
+// forward (inference and training), backward and the Adam step. Matrices are row-major;
+// a layer computes Z = X W + b with X [B x K], W [K x N], then H = silu(Z).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "common.hpp"
+#include "mlp.hpp"
+
+namespace bcv {
+namespace {
+
+constexpr int kTile = 64, kTileK = 16, kThreads = 256;
+
+__device__ __forceinline__ float sigmoid(float z) { return 1.0f / (1.0f + __expf(-z)); }
+
+// C[M x N] = op(A) op(B) (+ bias, + C if accumulate). op(A)[m][k] = TA ? A[k * lda + m] :
+// A[m * lda + k]; op(B)[k][n] = TB ? B[n * ldb + k] : B[k * ldb + n]. If H is given it also
+// receives silu(C). One 256-thread block per 64 x 64 tile, 4 x 4 outputs per thread, K in steps
+// of 16 through LDS. Every thread sums in the same order: results do not depend on the launch.
+template <bool TA, bool TB>
+__global__ __launch_bounds__(kThreads) void gemm_kernel(int M, int N, int K, const float *__restrict__ A, int lda,
+                                                        const float *__restrict__ B, int ldb,
+                                                        const float *__restrict__ bias, int accumulate,
+                                                        float *__restrict__ C, int ldc, float *__restrict__ H)
+{
+    __shared__ float As[kTileK][kTile + 1];
+    __shared__ float Bs[kTileK][kTile + 1];
+    const int m0 = blockIdx.y * kTile, n0 = blockIdx.x * kTile;
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    float acc[4][4] = {};
+    for (int k0 = 0; k0 < K; k0 += kTileK) {
+        for (int e = threadIdx.x; e < kTileK * kTile; e += kThreads) {
+            const int kk = e / kTile, mm = e % kTile;
+            const int m = m0 + mm, k = k0 + kk;
+            As[kk][mm] = (m < M && k < K) ? (TA ? A[(int64_t)k * lda + m] : A[(int64_t)m * lda + k]) : 0.0f;
+            const int n = n0 + mm;
+            Bs[kk][mm] = (n < N && k < K) ? (TB ? B[(int64_t)n * ldb + k] : B[(int64_t)k * ldb + n]) : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kTileK; ++kk) {
+            float a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int m = m0 + ty + 16 * i, n = n0 + tx + 16 * j;
+            if (m >= M || n >= N) continue;
+            float z = acc[i][j];
+            if (bias) z += bias[n];
+            float *c = C + (int64_t)m * ldc + n;
+            if (accumulate) z += *c;
+            *c = z;
+            if (H) H[(int64_t)m * ldc + n] = z * sigmoid(z);
+        }
+}
+
+// dZ = dH * silu'(Z), silu'(z) = s (1 + z (1 - s)), s = sigmoid(z).
+__global__ void silu_backward_kernel(int64_t n, const float *__restrict__ Z, const float *__restrict__ dH,
+                                     float *__restrict__ dZ)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float z = Z[i], s = sigmoid(z);
+        dZ[i] = dH[i] * s * (1.0f + z * (1.0f - s));
+    }
+}
+
+// Column sums: db[n] = sum_m dZ[m][n] (fixed order over m).
+__global__ void column_sum_kernel(int M, int N, const float *__restrict__ dZ, float *__restrict__ db)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float s = 0.0f;
+    for (int m = 0; m < M; ++m) s += dZ[(int64_t)m * N + n];
+    db[n] = s;
+}
+
+// Loss of a batch of B rows Y = (value, log-error) against targets r (mean over the batch):
+//   L = mean (y0 - r)^2 + w_err * mean (y1 - log(|y0 - r| + eps))^2,
+// the second term with y0 held fixed (the error head learns the size of the value head's miss).
+// dY receives dL/dY; loss_terms[i] the two squared terms of row i.
+__global__ void loss_kernel(int B, const float *__restrict__ Y, const float *__restrict__ r, float w_err, float eps,
+                            float *__restrict__ dY, float *__restrict__ loss_terms)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B) return;
+    const float d = Y[2 * i] - r[i];
+    const float e = Y[2 * i + 1] - logf(fabsf(d) + eps);
+    dY[2 * i] = 2.0f * d / B;
+    dY[2 * i + 1] = 2.0f * w_err * e / B;
+    loss_terms[2 * i] = d * d;
+    loss_terms[2 * i + 1] = e * e;
+}
+
+// Adam (Kingma & Ba 2015) with bias correction folded into the step size.
+__global__ void adam_kernel(int64_t n, float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                            float *__restrict__ v, float lr_t, float b1, float b2, float eps)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr_t * mi / (sqrtf(vi) + eps);
+    }
+}
+
+// Gather rows: out[i][:] = in[idx[i]][:] (minibatches), width d.
+__global__ void gather_rows_kernel(int B, int d, const int32_t *__restrict__ idx, const float *__restrict__ in,
+                                   float *__restrict__ out)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)B * d) return;
+    const int i = (int)(e / d), c = (int)(e % d);
+    out[e] = in[(int64_t)idx[i] * d + c];
+}
+
+unsigned grid_for(int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 256, 4096); }
+
+}  // namespace
+
+void gemm(bool ta, bool tb, int M, int N, int K, const float *A, int lda, const float *B, int ldb, const float *bias,
+          bool accumulate, float *C, int ldc, float *H, hipStream_t st)
+{
+    if (M <= 0 || N <= 0) return;
+    const dim3 grid((N + kTile - 1) / kTile, (M + kTile - 1) / kTile);
+    if (!ta && !tb)
+        gemm_kernel<false, false><<<grid, kThreads, 0, st>>>(M, N, K, A, lda, B, ldb, bias, accumulate, C, ldc, H);
+    else if (!ta && tb)
+        gemm_kernel<false, true><<<grid, kThreads, 0, st>>>(M, N, K, A, lda, B, ldb, bias, accumulate, C, ldc, H);
+    else if (ta && !tb)
+        gemm_kernel<true, false><<<grid, kThreads, 0, st>>>(M, N, K, A, lda, B, ldb, bias, accumulate, C, ldc, H);
+    else
+        gemm_kernel<true, true><<<grid, kThreads, 0, st>>>(M, N, K, A, lda, B, ldb, bias, accumulate, C, ldc, H);
+    BCV_HIP(hipGetLastError());
+}
+
+void silu_backward(int64_t n, const float *Z, const float *dH, float *dZ, hipStream_t st)
+{
+    if (n == 0) return;
+    silu_backward_kernel<<<grid_for(n), 256, 0, st>>>(n, Z, dH, dZ);
+    BCV_HIP(hipGetLastError());
+}
+
+void column_sum(int M, int N, const float *dZ, float *db, hipStream_t st)
+{
+    column_sum_kernel<<<(N + 127) / 128, 128, 0, st>>>(M, N, dZ, db);
+    BCV_HIP(hipGetLastError());
+}
+
+void loss_grad(int B, const float *Y, const float *r, float w_err, float eps, float *dY, float *terms, hipStream_t st)
+{
+    loss_kernel<<<(B + 255) / 256, 256, 0, st>>>(B, Y, r, w_err, eps, dY, terms);
+    BCV_HIP(hipGetLastError());
+}
+
+void adam_step(int64_t n, float *p, const float *g, float *m, float *v, float lr_t, float b1, float b2, float eps,
+               hipStream_t st)
+{
+    adam_kernel<<<grid_for(n), 256, 0, st>>>(n, p, g, m, v, lr_t, b1, b2, eps);
+    BCV_HIP(hipGetLastError());
+}
+
+void gather_rows(int B, int d, const int32_t *idx, const float *in, float *out, hipStream_t st)
+{
+    const int64_t n = (int64_t)B * d;
+    if (n == 0) return;
+    gather_rows_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(B, d, idx, in, out);
+    BCV_HIP(hipGetLastError());
+}
+
+}  // namespace bcv

@@ -1,0 +1,31 @@
+// Launchers of the surrogate network's kernels (mlp.hip). Device pointers, stream-ordered, FP32.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace bcv {
+
+// C[M x N] = op(A) op(B) (+ bias[N]) (+ C if accumulate); if H != nullptr also H = silu(C).
+// op(A) is A [M x K] (row stride lda), or A^T with A stored [K x M] when ta; likewise op(B).
+void gemm(bool ta, bool tb, int M, int N, int K, const float *A, int lda, const float *B, int ldb, const float *bias,
+          bool accumulate, float *C, int ldc, float *H, hipStream_t st);
+
+// dZ = dH * silu'(Z), elementwise over n values.
+void silu_backward(int64_t n, const float *Z, const float *dH, float *dZ, hipStream_t st);
+
+// db[n] = sum over the M rows of dZ [M x N].
+void column_sum(int M, int N, const float *dZ, float *db, hipStream_t st);
+
+// Loss of B rows Y = (value, log-error) against targets r (see mlp.hip): dY = dL/dY, terms = the
+// two squared terms per row.
+void loss_grad(int B, const float *Y, const float *r, float w_err, float eps, float *dY, float *terms, hipStream_t st);
+
+// One Adam step over n parameters; lr_t includes the bias correction.
+void adam_step(int64_t n, float *p, const float *g, float *m, float *v, float lr_t, float b1, float b2, float eps,
+               hipStream_t st);
+
+// out[i] = in[idx[i]] for B rows of width d.
+void gather_rows(int B, int d, const int32_t *idx, const float *in, float *out, hipStream_t st);
+
+}  // namespace bcv

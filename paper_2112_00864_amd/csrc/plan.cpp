@@ -505,6 +505,18 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
 
     double touch[kTouchClasses];
     touching_integrals(device, touch);
+    if (opts.surrogate) {
+        // the six contact classes as canonical pairs (smaller cube [0,1]^3, the other of side 1 or 2)
+        const bcv_touch_pair cls[6] = {{BCV_CONTACT_FACE, 0, 1.0, {0.0, 0.0}},   {BCV_CONTACT_EDGE, 0, 1.0, {0.0, 0.0}},
+                                       {BCV_CONTACT_VERTEX, 0, 1.0, {0.0, 0.0}}, {BCV_CONTACT_FACE, 0, 2.0, {0.0, 0.0}},
+                                       {BCV_CONTACT_EDGE, 0, 2.0, {0.0, 0.0}},   {BCV_CONTACT_VERTEX, 0, 2.0, {0.0, 0.0}}};
+        double value[6], est[6];
+        int32_t fb[6];
+        int64_t n_fb = 0;
+        surrogate_eval(*opts.surrogate, 6, cls, opts.surrogate_tol, value, est, fb, &n_fb);
+        for (int c = 0; c < 6; ++c) touch[1 + c] = value[c];
+        p->surrogate_classes = (int)(6 - n_fb);
+    }
     for (int c = 0; c < kTouchClasses; ++c) p->touch_value[c] = touch[c] / (4.0 * M_PI);
 
     const std::vector<Grid> grids = make_grids(t);
