@@ -39,6 +39,7 @@ extern "C" {
 typedef struct bcv_tree_s *bcv_tree;
 typedef struct bcv_plan_s *bcv_plan;
 typedef struct bcv_mlp_s *bcv_mlp;
+typedef struct bcv_graph_s *bcv_graph;
 
 typedef enum {
     BCV_OK = 0,
@@ -86,6 +87,11 @@ typedef struct {
                               the exact value. The plan copies the values: the network may be
                               destroyed afterwards. */
     double surrogate_tol;  /* e.g. 1e-7; 0 forces the fallback for every class */
+    int near_unit;         /* work-unit size of the near field: rows longer than this many entries are
+                              cut into pieces of about equal length (0 = 512; else 64..65536) */
+    int m2l_max_slots;     /* longest slot list of one interaction task; longer lists are cut into
+                              pieces whose partial sums are added in a fixed order (0 = 256;
+                              else 16..65536) */
 } bcv_plan_opts;
 
 /* Sizes of a plan (all counts, no pointers). */
@@ -107,6 +113,17 @@ typedef struct {
 /* Build the BC octree of Sec. 2 on the host. desc and out must be non-NULL.
  * Errors: BCV_EINVAL (L outside 2..9, marking != 0), BCV_ENOMEM. */
 bcv_status bcv_build_bc_tree(const bcv_mesh_desc *desc, bcv_tree *out);
+
+/* A forest of n_meshes BC meshes for a batched apply: one tree, one plan and one apply (and one
+ * captured graph) evaluate all meshes at once. descs[m] describes mesh m (same rules as
+ * bcv_build_bc_tree, 1 <= n_meshes <= 4096). Mesh m occupies [4m, 4m + 1) x [0, 1)^2 in units of a
+ * level-0 cube, so leaves (level, i, j, k) of mesh m have i in [4m 2^level, (4m + 1) 2^level);
+ * meshes never interact. Leaf order: the Morton order of the whole forest (bcv_tree_leaf_mesh
+ * tells the mesh of each leaf). Errors: BCV_EINVAL, BCV_ENOMEM. */
+bcv_status bcv_build_bc_forest(int n_meshes, const bcv_mesh_desc *descs, bcv_tree *out);
+
+/* Mesh of every leaf (host, n_leaves int32). */
+bcv_status bcv_tree_leaf_mesh(bcv_tree tree, int32_t *mesh_of_leaf);
 
 /* Number of leaves (host integer). */
 bcv_status bcv_tree_num_leaves(bcv_tree tree, int64_t *n);
@@ -164,6 +181,25 @@ enum {
 };
 bcv_status bcv_plan_enable_timing(bcv_plan plan, int max_applies);
 bcv_status bcv_plan_phase_times(bcv_plan plan, double *ms, int64_t *n_applies);
+
+/* The full apply (bcv_vtv_apply with both parts) captured once into an instantiated HIP graph:
+ * every kernel of every phase, and the second stream's fork and join, become one graph launch.
+ * Each launch reads f_dev and overwrites u_dev at the addresses given here (device, n_leaves
+ * doubles each, owned by the caller, kept alive while the graph is used). The graph uses the
+ * plan's workspace: launches must not overlap with each other or with applies of the same plan,
+ * and the plan must outlive the graph. Phase timing must be off while capturing.
+ * Errors: BCV_EINVAL, BCV_ESTATE (timing enabled, bad handle), BCV_EDEVICE. */
+bcv_status bcv_vtv_graph_create(bcv_plan plan, const double *f_dev, double *u_dev, bcv_graph *out);
+bcv_status bcv_graph_launch(bcv_graph graph, void *hip_stream);
+void bcv_graph_destroy(bcv_graph graph);
+
+/* Autotuner of the plan's work decomposition: for the tree and base options, builds plans with
+ * candidate near_unit (256, 512, 1024, 2048) and then m2l_max_slots (128, 256, 512, 1024) values,
+ * times n_applies applies of each (HIP events, after two warm-up applies, density 1) on `device`,
+ * and returns the options of the fastest plan in *best and its milliseconds per apply in *best_ms
+ * (host). Allocates and frees plans and buffers. Errors: as bcv_plan_interactions. */
+bcv_status bcv_autotune(bcv_tree tree, const bcv_plan_opts *base, int device, int n_applies, bcv_plan_opts *best,
+                        double *best_ms);
 
 /* Volume-to-boundary (Algorithm 2) and boundary-to-volume (Algorithm 3) applies on the same
  * tree. Not implemented in this build: both return BCV_ENOTSUP. */

@@ -32,7 +32,8 @@ class MeshDesc(ctypes.Structure):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("eta0", ctypes.c_double), ("q", ctypes.c_int), ("precision", ctypes.c_int),
                 ("direct", ctypes.c_int), ("nearfield", ctypes.c_int), ("streams", ctypes.c_int),
-                ("surrogate", ctypes.c_void_p), ("surrogate_tol", ctypes.c_double)]
+                ("surrogate", ctypes.c_void_p), ("surrogate_tol", ctypes.c_double), ("near_unit", ctypes.c_int),
+                ("m2l_max_slots", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -101,13 +102,22 @@ def lib():
                                          i32p, i64p]
         L.bcv_mlp_save.argtypes = [vp, ctypes.c_char_p]
         L.bcv_mlp_load.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(vp)]
+        L.bcv_build_bc_forest.argtypes = [ctypes.c_int, ctypes.POINTER(MeshDesc), ctypes.POINTER(vp)]
+        L.bcv_tree_leaf_mesh.argtypes = [vp, i32p]
+        L.bcv_vtv_graph_create.argtypes = [vp, vp, vp, ctypes.POINTER(vp)]
+        L.bcv_graph_launch.argtypes = [vp, vp]
+        L.bcv_graph_destroy.argtypes = [vp]
+        L.bcv_graph_destroy.restype = None
+        L.bcv_autotune.argtypes = [vp, ctypes.POINTER(PlanOpts), ctypes.c_int, ctypes.c_int, ctypes.POINTER(PlanOpts),
+                                   dp]
         L.bcv_last_error.restype = ctypes.c_char_p
         for name in ("bcv_build_bc_tree", "bcv_tree_num_leaves", "bcv_tree_leaves", "bcv_plan_interactions",
                      "bcv_plan_get_info", "bcv_vtv_apply", "bcv_vtv_apply_parts", "bcv_vtb_apply", "bcv_btv_apply",
                      "bcv_touching_integrals", "bcv_plan_enable_timing", "bcv_plan_phase_times",
                      "bcv_box_pair_integrals", "bcv_touch_pair_quadrature", "bcv_mlp_create", "bcv_mlp_num_params",
                      "bcv_mlp_get_params", "bcv_mlp_set_params", "bcv_mlp_forward", "bcv_mlp_loss_grad",
-                     "bcv_mlp_train", "bcv_surrogate_eval", "bcv_mlp_save", "bcv_mlp_load"):
+                     "bcv_mlp_train", "bcv_surrogate_eval", "bcv_mlp_save", "bcv_mlp_load", "bcv_build_bc_forest",
+                     "bcv_tree_leaf_mesh", "bcv_vtv_graph_create", "bcv_graph_launch", "bcv_autotune"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -131,6 +141,12 @@ class Tree:
         _check(lib().bcv_tree_num_leaves(self._h, ctypes.byref(n)))
         return n.value
 
+    def leaf_mesh(self):
+        """Mesh index of every leaf, int32 (n,)."""
+        out = np.empty(self.num_leaves(), dtype=np.int32)
+        _check(lib().bcv_tree_leaf_mesh(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return out
+
     def leaves(self):
         """(level, i, j, k) per leaf in leaf order, int32 (n, 4)."""
         out = np.empty((self.num_leaves(), 4), dtype=np.int32)
@@ -141,6 +157,14 @@ class Tree:
         if getattr(self, "_h", None) and _lib is not None:
             _lib.bcv_tree_destroy(self._h)
             self._h = None
+
+
+def build_bc_forest(Ls, marking=0):
+    """One tree holding len(Ls) meshes; mesh m occupies [4m, 4m+1) x [0,1)^2 (see bcv.h)."""
+    descs = (MeshDesc * len(Ls))(*[MeshDesc(int(L), marking) for L in Ls])
+    h = ctypes.c_void_p()
+    _check(lib().bcv_build_bc_forest(len(Ls), descs, ctypes.byref(h)))
+    return Tree(h)
 
 
 def build_bc_tree(L, marking=0):
@@ -175,10 +199,15 @@ class Plan:
         self.destroy()
 
 
+def _opts(q=6, eta0=0.5, direct=False, nearfield=NEAR_QUADRATURE, streams=2, precision=FP64, surrogate=None,
+          surrogate_tol=1e-7, near_unit=0, m2l_max_slots=0):
+    return PlanOpts(eta0, q, precision, 1 if direct else 0, nearfield, streams,
+                    surrogate.handle if surrogate is not None else None, surrogate_tol, near_unit, m2l_max_slots)
+
+
 def plan_interactions(tree, q=6, eta0=0.5, direct=False, nearfield=NEAR_QUADRATURE, device=0, streams=2,
-                      precision=FP64, surrogate=None, surrogate_tol=1e-7):
-    opts = PlanOpts(eta0, q, precision, 1 if direct else 0, nearfield, streams,
-                    surrogate.handle if surrogate is not None else None, surrogate_tol)
+                      precision=FP64, surrogate=None, surrogate_tol=1e-7, near_unit=0, m2l_max_slots=0):
+    opts = _opts(q, eta0, direct, nearfield, streams, precision, surrogate, surrogate_tol, near_unit, m2l_max_slots)
     h = ctypes.c_void_p()
     _check(lib().bcv_plan_interactions(tree.handle, ctypes.byref(opts), device, ctypes.byref(h)))
     return Plan(h, device)
@@ -357,3 +386,40 @@ def mlp_load(path, device=0):
     h = ctypes.c_void_p()
     _check(lib().bcv_mlp_load(os.fsencode(path), device, ctypes.byref(h)))
     return MLP(h, device)
+
+
+# ---- captured applies and the autotuner ------------------------------------------------------------
+
+class Graph:
+    """bcv_vtv_apply captured into one HIP graph; keeps f and u (torch tensors) alive."""
+
+    def __init__(self, handle, plan, f, u):
+        self._h, self._plan, self.f, self.u = handle, plan, f, u
+
+    def launch(self, stream=None):
+        _check(lib().bcv_graph_launch(self._h, _stream(stream, self._plan.device)))
+
+    def destroy(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.bcv_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.destroy()
+
+
+def vtv_graph_create(plan, f, u):
+    n = plan.n_leaves
+    h = ctypes.c_void_p()
+    _check(lib().bcv_vtv_graph_create(plan.handle, _dev_ptr(f, n, plan.device, "f"), _dev_ptr(u, n, plan.device, "u"),
+                                      ctypes.byref(h)))
+    return Graph(h, plan, f, u)
+
+
+def autotune(tree, device=0, n_applies=5, **opts):
+    """Best (near_unit, m2l_max_slots) for the tree and options, and its ms per apply."""
+    base = _opts(**opts)
+    best = PlanOpts()
+    ms = ctypes.c_double()
+    _check(lib().bcv_autotune(tree.handle, ctypes.byref(base), device, n_applies, ctypes.byref(best), ctypes.byref(ms)))
+    return {"near_unit": best.near_unit, "m2l_max_slots": best.m2l_max_slots}, ms.value

@@ -2,6 +2,7 @@
 // exceptions into bcv_status plus a thread-local message.
 #include <new>
 #include <string>
+#include <vector>
 
 #include "internal.hpp"
 #include "kernels.hpp"
@@ -9,6 +10,7 @@
 
 namespace bcv {
 bcv_tree_s *build_tree(int L);
+bcv_tree_s *build_forest(int n, const int *Ls);
 bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int device);
 void destroy_plan(bcv_plan_s *p);
 void touching_integrals(int device, double out[kTouchClasses]);
@@ -61,6 +63,30 @@ void check_device(int device)
     BCV_REQUIRE(device >= 0 && device < n_dev, BCV_EINVAL, "no such HIP device");
 }
 
+void check_plan_opts(const bcv_plan_opts &o, int device)
+{
+    BCV_REQUIRE(o.eta0 == 0.5, BCV_EINVAL, "eta0 must be 0.5");
+    BCV_REQUIRE(o.q == 4 || o.q == 6 || o.q == 8, BCV_EINVAL, "q must be 4, 6 or 8");
+    BCV_REQUIRE(o.precision == BCV_FP64 || o.precision == BCV_MIXED_F32, BCV_EINVAL,
+                "precision must be BCV_FP64 or BCV_MIXED_F32");
+    BCV_REQUIRE(o.direct == 0 || o.direct == 1, BCV_EINVAL, "direct must be 0 or 1");
+    BCV_REQUIRE(o.nearfield == BCV_NEAR_QUADRATURE || o.nearfield == BCV_NEAR_ASSEMBLED, BCV_EINVAL,
+                "unknown nearfield mode");
+    BCV_REQUIRE(o.streams == 1 || o.streams == 2, BCV_EINVAL, "streams must be 1 or 2");
+    BCV_REQUIRE(o.near_unit == 0 || (o.near_unit >= 64 && o.near_unit <= 65536), BCV_EINVAL,
+                "near_unit must be 0 or 64..65536");
+    BCV_REQUIRE(o.m2l_max_slots == 0 || (o.m2l_max_slots >= 16 && o.m2l_max_slots <= 65536),
+                BCV_EINVAL, "m2l_max_slots must be 0 or 16..65536");
+    if (o.surrogate) {
+        check_mlp(o.surrogate);
+        BCV_REQUIRE(o.surrogate_tol >= 0.0, BCV_EINVAL, "negative surrogate tolerance");
+        BCV_REQUIRE(o.surrogate->device == device, BCV_EINVAL, "the surrogate lives on another device");
+    }
+    int n_dev = 0;
+    BCV_HIP(hipGetDeviceCount(&n_dev));
+    BCV_REQUIRE(device >= 0 && device < n_dev, BCV_EINVAL, "no such HIP device");
+}
+
 void check_plan(bcv_plan p)
 {
     BCV_REQUIRE(p != nullptr, BCV_EINVAL, "plan handle is NULL");
@@ -86,6 +112,34 @@ void on_device(int device, F &&f)
 }  // namespace
 
 extern "C" {
+
+bcv_status bcv_build_bc_forest(int n_meshes, const bcv_mesh_desc *descs, bcv_tree *out)
+{
+    return guard([&] {
+        BCV_REQUIRE(descs != nullptr && out != nullptr, BCV_EINVAL, "NULL argument");
+        *out = nullptr;
+        BCV_REQUIRE(n_meshes >= 1 && n_meshes <= 4096, BCV_EINVAL, "n_meshes must be in 1..4096");
+        std::vector<int> Ls(n_meshes);
+        for (int m = 0; m < n_meshes; ++m) {
+            BCV_REQUIRE(descs[m].L >= 2 && descs[m].L <= 9, BCV_EINVAL, "L must be in 2..9");
+            BCV_REQUIRE(descs[m].marking == 0, BCV_EINVAL, "only the face-on-boundary marking rule (0) is supported");
+            Ls[m] = descs[m].L;
+        }
+        *out = bcv::build_forest(n_meshes, Ls.data());
+    });
+}
+
+bcv_status bcv_tree_leaf_mesh(bcv_tree tree, int32_t *mesh_of_leaf)
+{
+    return guard([&] {
+        check_tree(tree);
+        BCV_REQUIRE(mesh_of_leaf != nullptr, BCV_EINVAL, "NULL argument");
+        for (int64_t l = 0; l < tree->n_leaves(); ++l) {
+            const int32_t c = tree->leaf_cell[l];
+            mesh_of_leaf[l] = (tree->ijk[3 * c] >> tree->level[c]) / 4;
+        }
+    });
+}
 
 bcv_status bcv_build_bc_tree(const bcv_mesh_desc *desc, bcv_tree *out)
 {
@@ -134,22 +188,7 @@ bcv_status bcv_plan_interactions(bcv_tree tree, const bcv_plan_opts *opts, int d
         check_tree(tree);
         BCV_REQUIRE(opts != nullptr && out != nullptr, BCV_EINVAL, "NULL argument");
         *out = nullptr;
-        BCV_REQUIRE(opts->eta0 == 0.5, BCV_EINVAL, "eta0 must be 0.5");
-        BCV_REQUIRE(opts->q == 4 || opts->q == 6 || opts->q == 8, BCV_EINVAL, "q must be 4, 6 or 8");
-        BCV_REQUIRE(opts->precision == BCV_FP64 || opts->precision == BCV_MIXED_F32, BCV_EINVAL,
-                    "precision must be BCV_FP64 or BCV_MIXED_F32");
-        BCV_REQUIRE(opts->direct == 0 || opts->direct == 1, BCV_EINVAL, "direct must be 0 or 1");
-        BCV_REQUIRE(opts->nearfield == BCV_NEAR_QUADRATURE || opts->nearfield == BCV_NEAR_ASSEMBLED, BCV_EINVAL,
-                    "unknown nearfield mode");
-        BCV_REQUIRE(opts->streams == 1 || opts->streams == 2, BCV_EINVAL, "streams must be 1 or 2");
-        if (opts->surrogate) {
-            check_mlp(opts->surrogate);
-            BCV_REQUIRE(opts->surrogate_tol >= 0.0, BCV_EINVAL, "negative surrogate tolerance");
-            BCV_REQUIRE(opts->surrogate->device == device, BCV_EINVAL, "the surrogate lives on another device");
-        }
-        int n_dev = 0;
-        BCV_HIP(hipGetDeviceCount(&n_dev));
-        BCV_REQUIRE(device >= 0 && device < n_dev, BCV_EINVAL, "no such HIP device");
+        check_plan_opts(*opts, device);
         on_device(device, [&] { *out = bcv::build_plan(*tree, *opts, device); });
     });
 }
@@ -353,6 +392,41 @@ bcv_status bcv_mlp_load(const char *path, int device, bcv_mlp *out)
         *out = nullptr;
         check_device(device);
         on_device(device, [&] { *out = bcv::mlp_load(path, device); });
+    });
+}
+
+bcv_status bcv_vtv_graph_create(bcv_plan plan, const double *f_dev, double *u_dev, bcv_graph *out)
+{
+    return guard([&] {
+        check_plan(plan);
+        BCV_REQUIRE(f_dev != nullptr && u_dev != nullptr && out != nullptr, BCV_EINVAL, "NULL argument");
+        *out = nullptr;
+        on_device(plan->device, [&] { *out = bcv::graph_create(*plan, f_dev, u_dev); });
+    });
+}
+
+bcv_status bcv_graph_launch(bcv_graph graph, void *hip_stream)
+{
+    return guard([&] {
+        BCV_REQUIRE(graph != nullptr, BCV_EINVAL, "graph handle is NULL");
+        BCV_REQUIRE(graph->magic == bcv_graph_s::kMagic, BCV_ESTATE, "not a live bcv_graph");
+        on_device(graph->device, [&] { bcv::graph_launch(*graph, static_cast<hipStream_t>(hip_stream)); });
+    });
+}
+
+void bcv_graph_destroy(bcv_graph graph)
+{
+    if (graph && graph->magic == bcv_graph_s::kMagic) bcv::graph_destroy(graph);
+}
+
+bcv_status bcv_autotune(bcv_tree tree, const bcv_plan_opts *base, int device, int n_applies, bcv_plan_opts *best,
+                        double *best_ms)
+{
+    return guard([&] {
+        check_tree(tree);
+        BCV_REQUIRE(base != nullptr && best != nullptr && best_ms != nullptr, BCV_EINVAL, "NULL argument");
+        check_plan_opts(*base, device);
+        on_device(device, [&] { *best_ms = bcv::autotune(*tree, *base, device, n_applies, *best); });
     });
 }
 

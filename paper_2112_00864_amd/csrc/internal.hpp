@@ -20,6 +20,11 @@ struct bcv_tree_s {
     std::vector<int32_t> leaf_of_cell;  // leaf number or -1 (marked cell)
     std::vector<int32_t> leaf_cell;     // cell of each leaf, leaf order
 
+    // Forest of meshes (a single mesh is the forest of one): mesh m occupies [4m, 4m + 1) x [0, 1)^2
+    // and has finest level mesh_L[m].
+    int n_meshes = 1;
+    std::vector<int> mesh_L;
+
     int64_t n_cells() const { return (int64_t)level.size(); }
     int64_t n_leaves() const { return (int64_t)leaf_cell.size(); }
 };
@@ -145,3 +150,20 @@ struct bcv_plan_s {
     bcv::M2LSplit *d_m2l_splits = nullptr;
     double *d_m2l_partial = nullptr;    // 64 x K per piece of a split task
 };
+
+// A captured apply (graph.cpp).
+struct bcv_graph_s {
+    static constexpr uint32_t kMagic = 0x42434752u;  // "BCGR"
+    uint32_t magic = kMagic;
+    int device = 0;
+    const bcv_plan_s *plan = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace bcv {
+bcv_graph_s *graph_create(const bcv_plan_s &p, const double *f, double *u);
+void graph_launch(const bcv_graph_s &g, hipStream_t st);
+void graph_destroy(bcv_graph_s *g);
+double autotune(const bcv_tree_s &t, const bcv_plan_opts &base, int device, int n_applies, bcv_plan_opts &best);
+}  // namespace bcv

@@ -32,13 +32,13 @@ void touching_integrals(int device, double out[kTouchClasses]);
 
 namespace {
 
-struct Grid {  // dense (i, j, k) -> cell index of one level
-    int n = 0;
+struct Grid {  // dense (i, j, k) -> cell index of one level, over the bounding box of its cells
+    int nx = 0, ny = 0, nz = 0;
     std::vector<int32_t> idx;
     int32_t at(int i, int j, int k) const
     {
-        if (i < 0 || j < 0 || k < 0 || i >= n || j >= n || k >= n) return -1;
-        return idx[((size_t)k * n + j) * n + i];
+        if (i < 0 || j < 0 || k < 0 || i >= nx || j >= ny || k >= nz) return -1;
+        return idx[((size_t)k * ny + j) * nx + i];
     }
 };
 
@@ -46,10 +46,15 @@ std::vector<Grid> make_grids(const bcv_tree_s &t)
 {
     std::vector<Grid> g(t.L + 1);
     for (int lev = 0; lev <= t.L; ++lev) {
-        g[lev].n = 1 << lev;
-        g[lev].idx.assign((size_t)g[lev].n * g[lev].n * g[lev].n, -1);
+        Grid &G = g[lev];
+        for (int32_t c = t.lvl_start[lev]; c < t.lvl_start[lev + 1]; ++c) {
+            G.nx = std::max(G.nx, t.ijk[3 * c] + 1);
+            G.ny = std::max(G.ny, t.ijk[3 * c + 1] + 1);
+            G.nz = std::max(G.nz, t.ijk[3 * c + 2] + 1);
+        }
+        G.idx.assign((size_t)G.nx * G.ny * G.nz, -1);
         for (int32_t c = t.lvl_start[lev]; c < t.lvl_start[lev + 1]; ++c)
-            g[lev].idx[((size_t)t.ijk[3 * c + 2] * g[lev].n + t.ijk[3 * c + 1]) * g[lev].n + t.ijk[3 * c]] = c;
+            G.idx[((size_t)t.ijk[3 * c + 2] * G.ny + t.ijk[3 * c + 1]) * G.nx + t.ijk[3 * c]] = c;
     }
     return g;
 }
@@ -208,10 +213,10 @@ NearCSR build_near(const bcv_tree_s &t, const std::vector<Grid> &g, const LeafGe
     return r;
 }
 
-// Near-field work units of at most kNearUnitPairs entries (a few hundred point-rule pairs per
-// wave). A row is cut into equal pieces; units are ordered longest first so that the long units
+// Near-field work units of at most `unit` entries (a few hundred point-rule pairs per wave by
+// default). A row is cut into equal pieces; units are ordered longest first so that the long units
 // start early.
-constexpr int64_t kNearUnitPairs = 512;
+constexpr int kDefaultNearUnit = 512;
 
 struct NearUnits {
     std::vector<NearUnit> units;
@@ -219,12 +224,12 @@ struct NearUnits {
     int64_t n_partial = 0;
 };
 
-NearUnits build_near_units(const NearCSR &near, int64_t n_leaves)
+NearUnits build_near_units(const NearCSR &near, int64_t n_leaves, int64_t unit)
 {
     NearUnits r;
     for (int64_t t = 0; t < n_leaves; ++t) {
         const int64_t b = near.row[t], len = near.row[t + 1] - b;
-        const int64_t pieces = std::max<int64_t>(1, (len + kNearUnitPairs - 1) / kNearUnitPairs);
+        const int64_t pieces = std::max<int64_t>(1, (len + unit - 1) / unit);
         if (pieces == 1) {
             r.units.push_back(NearUnit{b, b + len, (int32_t)t, -1});
             continue;
@@ -262,9 +267,9 @@ struct M2LPlan {
     int64_t n_pairs = 0;
 };
 
-// Longest slot list of one interaction task: longer lists (the remainder tasks, whose lanes
-// belong to many signature classes) are cut into pieces so that no wave outlasts the others.
-constexpr int32_t kMaxTaskSlots = 256;
+// Default longest slot list of one interaction task: longer lists (the remainder tasks, whose
+// lanes belong to many signature classes) are cut into pieces so that no wave outlasts the others.
+constexpr int kDefaultMaxSlots = 256;
 
 int offset_key(int a, int b, int c) { return ((a + 7) * 15 + (b + 7)) * 15 + (c + 7); }
 
@@ -298,7 +303,7 @@ uint64_t hash_keys(const std::vector<int32_t> &keys)
 // fills whole 64-lane tasks, and the remainders are packed together in Morton order. A task's
 // slots are the union of its targets' offsets; a lane gets a source only for offsets in its own
 // list, otherwise the zero row.
-M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g)
+M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, int32_t max_slots)
 {
     M2LPlan m;
     const int32_t zero_row = (int32_t)t.n_cells();
@@ -392,7 +397,7 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g)
             }
         }
     }
-    // Pieces of at most kMaxTaskSlots slots, in task order.
+    // Pieces of at most max_slots slots, in task order.
     struct Piece {
         M2LTask task;
         int32_t chunk;
@@ -402,7 +407,7 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g)
     for (size_t q = 0; q < chunks.size(); ++q) {
         const int32_t base = (int32_t)m.slot_key.size();
         const int32_t n = (int32_t)outs[q].keys.size();
-        const int32_t np = std::max<int32_t>(1, (n + kMaxTaskSlots - 1) / kMaxTaskSlots);
+        const int32_t np = std::max<int32_t>(1, (n + max_slots - 1) / max_slots);
         if (np > 1) split_of_chunk[q] = M2LSplit{-1, m.n_pieces, np, 0};
         for (int32_t k = 0; k < np; ++k) {
             const int32_t b = base + (int32_t)((int64_t)n * k / np), e = base + (int32_t)((int64_t)n * (k + 1) / np);
@@ -539,7 +544,7 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         p->n_touch = near.n_touch;
         p->d_split = upload(p.get(), near.split);
         p->d_col = upload(p.get(), near.col);
-        const NearUnits nu = build_near_units(near, p->n_leaves);
+        const NearUnits nu = build_near_units(near, p->n_leaves, opts.near_unit > 0 ? opts.near_unit : kDefaultNearUnit);
         p->n_units = (int64_t)nu.units.size();
         p->n_splits = (int64_t)nu.splits.size();
         p->d_units = upload(p.get(), nu.units);
@@ -562,7 +567,7 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         p->parent_begin[t.L + 1] = (int32_t)parents.size() / 2;
         p->d_parents = upload(p.get(), parents);
 
-        M2LPlan m2l = build_m2l(t, grids);
+        M2LPlan m2l = build_m2l(t, grids, opts.m2l_max_slots > 0 ? opts.m2l_max_slots : kDefaultMaxSlots);
         std::vector<int32_t> id_of_key(15 * 15 * 15, -1);
         for (int32_t key : m2l.slot_key) id_of_key[key] = 0;
         std::vector<double> G;

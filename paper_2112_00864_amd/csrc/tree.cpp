@@ -16,10 +16,17 @@ static bool on_boundary(int lev, int32_t i, int32_t j, int32_t k)
     return i == 0 || j == 0 || k == 0 || i == top || j == top || k == top;
 }
 
-bcv_tree_s *build_tree(int L)
+// A forest of n unit-cube BC meshes with finest levels L[m]: mesh m occupies [4m, 4m + 1) x [0, 1)^2
+// (in units of a level-0 cell), so cells of different meshes are never neighbours at any level
+// (their integer offsets are at least 4 * 2^l - 2^l > sqrt(12) apart at level l) and the planner
+// treats the forest as one mesh. With n = 1 this is the single mesh of the unit cube.
+bcv_tree_s *build_forest(int n, const int *Ls)
 {
     auto *t = new bcv_tree_s;
-    t->L = L;
+    t->L = 0;
+    for (int m = 0; m < n; ++m) t->L = std::max(t->L, Ls[m]);
+    t->n_meshes = n;
+    t->mesh_L.assign(Ls, Ls + n);
     auto push = [&](int32_t i, int32_t j, int32_t k, int lev, int32_t par) {
         t->ijk.push_back(i);
         t->ijk.push_back(j);
@@ -30,15 +37,16 @@ bcv_tree_s *build_tree(int L)
         t->first_child.push_back(-1);
         t->leaf_of_cell.push_back(-1);
     };
-    push(0, 0, 0, 0, -1);
+    for (int m = 0; m < n; ++m) push(4 * m, 0, 0, 0, -1);
     t->lvl_start.push_back(0);
-    for (int lev = 0; lev <= L; ++lev) {
+    for (int lev = 0; lev <= t->L; ++lev) {
         const int32_t b = t->lvl_start[lev], e = (int32_t)t->level.size();
         t->lvl_start.push_back(e);  // start of level lev + 1 (children appended below)
-        if (lev == L) break;
+        if (lev == t->L) break;
         for (int32_t c = b; c < e; ++c) {
             const int32_t i = t->ijk[3 * c], j = t->ijk[3 * c + 1], k = t->ijk[3 * c + 2];
-            if (!on_boundary(lev, i, j, k)) continue;
+            const int m = (i >> lev) / 4;
+            if (lev >= Ls[m] || !on_boundary(lev, i - ((4 * m) << lev), j, k)) continue;
             t->refined[c] = 1;
             t->first_child[c] = (int32_t)t->level.size();
             for (int ch = 0; ch < 8; ++ch)
@@ -49,16 +57,20 @@ bcv_tree_s *build_tree(int L)
     std::vector<int32_t> leaves;
     for (int32_t c = 0; c < (int32_t)t->level.size(); ++c)
         if (!t->refined[c]) leaves.push_back(c);
+    int bits = t->L;  // enough bits for every coordinate at level-L resolution
+    while ((int64_t(4 * (n - 1) + 1) << t->L) > (int64_t(1) << bits)) ++bits;
     std::vector<uint64_t> key(t->level.size());
     for (int32_t c : leaves) {
-        const int s = L - t->level[c];
-        key[c] = morton3((uint32_t)t->ijk[3 * c] << s, (uint32_t)t->ijk[3 * c + 1] << s,
-                         (uint32_t)t->ijk[3 * c + 2] << s, L);
+        const int sh = t->L - t->level[c];
+        key[c] = morton3((uint32_t)t->ijk[3 * c] << sh, (uint32_t)t->ijk[3 * c + 1] << sh,
+                         (uint32_t)t->ijk[3 * c + 2] << sh, bits);
     }
     std::sort(leaves.begin(), leaves.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
     t->leaf_cell = leaves;
-    for (size_t n = 0; n < leaves.size(); ++n) t->leaf_of_cell[leaves[n]] = (int32_t)n;
+    for (size_t q = 0; q < leaves.size(); ++q) t->leaf_of_cell[leaves[q]] = (int32_t)q;
     return t;
 }
+
+bcv_tree_s *build_tree(int L) { return build_forest(1, &L); }
 
 }  // namespace bcv

@@ -60,3 +60,25 @@ def test_null_handles():
     assert b"NULL" in lib.bcv_last_error()
     lib.bcv_plan_destroy(None)  # no-op
     lib.bcv_tree_destroy(None)
+
+
+def test_forest_leaves_are_the_meshes_leaves():
+    """Each mesh of a forest has exactly the leaves of its own BC mesh, in the same order."""
+    from oracle.mesh import BCMesh
+
+    Ls = [3, 4, 2, 3]
+    t = bcv.build_bc_forest(Ls)
+    lv = t.leaves().astype(np.int64)
+    mesh = t.leaf_mesh()
+    assert np.array_equal(np.bincount(mesh), [len(BCMesh(L).leaf_array()) for L in Ls])
+    for m, L in enumerate(Ls):
+        loc = lv[mesh == m].copy()
+        loc[:, 1] -= (4 * m) << loc[:, 0]
+        assert np.array_equal(loc, BCMesh(L).leaf_array())
+
+
+def test_forest_argument_errors():
+    for Ls in ([], [1], [10], [3, 0]):
+        with pytest.raises(bcv.BCVError) as e:
+            bcv.build_bc_forest(Ls)
+        assert e.value.status == bcv.bcv.EINVAL

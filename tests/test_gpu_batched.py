@@ -1,0 +1,102 @@
+"""Batched applies: many BC meshes in one forest plan, its apply captured in one HIP graph, and the
+autotuner of the work decomposition."""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+
+import synth  # noqa: E402
+from gpu_util import gpu_apply, rel_l2  # noqa: E402
+
+import paper_2112_00864_amd as bcv  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+LS = [2, 3, 4, 3, 2, 4, 4, 3]
+
+
+def announce(*a):
+    print("[gpu]", *a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def forest_density(tree, Ls):
+    """Density of every leaf: mesh m gets the Gaussian mixture of seed m on its own unit cube."""
+    lv = tree.leaves().astype(np.int64)
+    mesh = tree.leaf_mesh()
+    f = np.empty(len(lv))
+    for m in range(len(Ls)):
+        sel = mesh == m
+        loc = lv[sel].copy()
+        loc[:, 1] -= (4 * m) << loc[:, 0]
+        f[sel] = synth.leaf_density(loc, seed=m)
+    return lv, mesh, f
+
+
+@pytest.mark.parametrize("precision", [bcv.FP64, bcv.MIXED_F32])
+def test_forest_equals_separate_meshes(precision):
+    announce("forest of %d meshes, precision %d" % (len(LS), precision))
+    forest = bcv.build_bc_forest(LS)
+    lv, mesh, f = forest_density(forest, LS)
+    u = gpu_apply(bcv.plan_interactions(forest, q=6, precision=precision), f)
+    worst = 0.0
+    for m, L in enumerate(LS):
+        sel = mesh == m
+        um = gpu_apply(bcv.plan_interactions(bcv.build_bc_tree(L), q=6, precision=precision), f[sel])
+        worst = max(worst, rel_l2(lv[sel], u[sel], um))
+    announce("max per-mesh rel-L2 forest vs separate: %.2e" % worst)
+    assert worst <= (1e-13 if precision == bcv.FP64 else 1e-6)
+
+
+def test_graph_replays_match_eager():
+    """Replays with other work and synchronisations between them; every replay equals the eager apply."""
+    import torch
+
+    forest = bcv.build_bc_forest(LS)
+    lv, mesh, f = forest_density(forest, LS)
+    plan = bcv.plan_interactions(forest, q=6, precision=bcv.MIXED_F32)
+    fd = torch.tensor(f, device="cuda:0")
+    ud = torch.full_like(fd, float("nan"))
+    ref = torch.empty_like(fd)
+    bcv.vtv_apply(plan, fd, ref)
+    torch.cuda.synchronize()
+    graph = bcv.vtv_graph_create(plan, fd, ud)
+    other = bcv.plan_interactions(bcv.build_bc_tree(3), q=4)
+    fo = torch.ones(other.n_leaves, dtype=torch.float64, device="cuda:0")
+    uo = torch.empty_like(fo)
+    for rep in range(4):
+        ud.fill_(float("nan"))
+        graph.launch()
+        torch.cuda.synchronize()
+        diff = float(torch.max(torch.abs(ud - ref)).item())
+        announce("replay %d: max |graph - eager| %.3e" % (rep, diff))
+        assert diff == 0.0
+        bcv.vtv_apply(other, fo, uo)  # eager work of another plan between replays
+        fd.mul_(1.0)
+        torch.cuda.synchronize()
+    # a new density in the same buffer is picked up by the next replay
+    fd.mul_(2.0)
+    graph.launch()
+    torch.cuda.synchronize()
+    assert float(torch.max(torch.abs(ud - 2.0 * ref)).item()) <= 1e-12 * float(torch.max(torch.abs(ref)).item())
+
+
+def test_autotune_returns_a_valid_faster_or_equal_plan():
+    forest = bcv.build_bc_forest(LS)
+    lv, mesh, f = forest_density(forest, LS)
+    best, ms = bcv.autotune(forest, n_applies=3, q=6, precision=bcv.MIXED_F32)
+    announce("autotune: %s, %.3f ms per apply" % (best, ms))
+    assert best["near_unit"] in (0, 256, 512, 1024, 2048) and best["m2l_max_slots"] in (0, 128, 256, 512, 1024)
+    u0 = gpu_apply(bcv.plan_interactions(forest, q=6, precision=bcv.MIXED_F32), f)
+    u1 = gpu_apply(bcv.plan_interactions(forest, q=6, precision=bcv.MIXED_F32, **best), f)
+    assert rel_l2(lv, u1, u0) <= 1e-6
