@@ -7,7 +7,9 @@ evaluation) with the density already resident in HBM. Plan construction (lists, 
 happens once before timing and is reported separately.
 
 By default the same mesh is timed twice: with the plain FP64 path and with the mixed path (FP32
-interaction phase and non-touching near field, FP64 singular pairs, tree passes and accumulation).
+interaction phase and non-touching near field, FP64 singular pairs, tree passes and accumulation),
+whose touching-pair class values come from the trained surrogate where it certifies 1e-7 (the
+network is trained on the GPU before timing).
 The headline value is the mixed rate if the mixed result is within rel-L2 1e-6 of the FP64 result
 (L2 norm of cell averages over Omega), else the FP64 rate.
 
@@ -31,6 +33,7 @@ METRIC = "VtV cell-potentials/s at rel-L2≤1e-6, mixed+surrogate vs plain FP64,
 PEAK_FP64 = 78.6e12  # MI355X FP64 vector (= FP64 matrix) peak, FLOP/s
 PEAK_FP32 = 157.3e12  # MI355X FP32 vector peak, FLOP/s
 REL_L2_GATE = 1e-6  # the mixed path counts only if its rel-L2 against the FP64 path is within this
+SURROGATE_TOL = 1e-7  # touching-pair surrogate: accepted where its calibrated error estimate is below this
 PEAK_HBM = 8.0e12  # bytes/s
 
 
@@ -81,11 +84,12 @@ def cpu_baseline(L, q, f, u_gpu, n_targets, leaves):
     }
 
 
-def measure(bcv, torch, tree, f, args, dev, nf, prec):
+def measure(bcv, torch, tree, f, args, dev, nf, prec, surrogate=None):
     """Plan, warm up, then time `args.steps` applies with per-phase HIP events."""
     t0 = time.perf_counter()
     plan = bcv.plan_interactions(tree, q=args.q, nearfield=nf, device=dev, streams=args.streams,
-                                 precision=bcv.MIXED_F32 if prec == "mixed" else bcv.FP64)
+                                 precision=bcv.MIXED_F32 if prec == "mixed" else bcv.FP64,
+                                 surrogate=surrogate, surrogate_tol=SURROGATE_TOL)
     plan_s = time.perf_counter() - t0
     info = plan.info
     u = torch.empty_like(f)
@@ -104,7 +108,7 @@ def measure(bcv, torch, tree, f, args, dev, nf, prec):
     bcv.plan_enable_timing(plan, 0)
     phase_avg = {k: v / max(n_rec, 1) for k, v in phases.items()}
     roof, roof_other = roofline(info, phase_avg, args, prec)
-    out = {"plan_s": plan_s, "info": info, "ms": 1e3 * elapsed / args.steps, "phases": phase_avg,
+    out = {"plan_s": plan_s, "info": plan.info, "ms": 1e3 * elapsed / args.steps, "phases": phase_avg,
            "u": u.cpu().numpy(), "roof": roof, "roof_other": roof_other}
     del plan
     return out
@@ -234,8 +238,9 @@ def main():
                     help="both: time the FP64 and the mixed path on the same mesh and report the ratio")
     ap.add_argument("--streams", type=int, choices=[1, 2], default=2,
                     help="2: near field concurrent with the far field on a second stream")
-    ap.add_argument("--cpu-targets", type=int, default=12)
+    ap.add_argument("--cpu-targets", type=int, default=4000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true", help="mixed path without the touching-pair surrogate")
     ap.add_argument("--batched", action="store_true",
                     help="the batched workload: 64 meshes in one forest plan and one graph launch")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -277,9 +282,19 @@ def main():
     nf = bcv.NEAR_ASSEMBLED if args.nearfield == "assembled" else bcv.NEAR_QUADRATURE
     precisions = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
 
+    surrogate, sur_report = None, None
+    if "mixed" in precisions and not args.no_surrogate:
+        # touching-pair surrogate for the mixed path, trained on the GPU (not timed)
+        t0 = time.perf_counter()
+        surrogate = bcv.mlp_create(width=128, seed=1, device=dev)
+        sur_report = surrogate.train(n_train=100000, n_valid=20000, epochs=20, batch=2048, lr=2e-3, seed=42,
+                                     n_gauss_lo=5, n_gauss_hi=16, tol=SURROGATE_TOL)
+        sur_report["train_seconds"] = time.perf_counter() - t0
+        print("surrogate trained: %s" % json.dumps(sur_report), file=sys.stderr, flush=True)
+
     runs = {}
     for prec in precisions:
-        runs[prec] = measure(bcv, torch, tree, f, args, dev, nf, prec)
+        runs[prec] = measure(bcv, torch, tree, f, args, dev, nf, prec, surrogate if prec == "mixed" else None)
         r = runs[prec]
         print("%s: plan %.1f s, step %.3f ms; phases (ms): %s"
               % (prec, r["plan_s"], r["ms"], json.dumps({k: round(v, 4) for k, v in r["phases"].items()})),
@@ -321,7 +336,8 @@ def main():
             "workload": "VtV apply, BC-FMM, unit cube BC octree h=1/%d (L=%d), %d leaves, q=%d, Gaussian-mixture "
                         "density seed 0, near field %s, %d stream(s), %s"
                         % (2 ** args.L, args.L, n, args.q, args.nearfield, args.streams,
-                           "mixed FP32 M2L and far near field, FP64 singular pairs and accumulation"
+                           ("mixed FP32 M2L and far near field, FP64 singular pairs and accumulation"
+                            + (", touching classes from the surrogate" if surrogate is not None else ""))
                            if head == "mixed" else "plain FP64"),
             "n_leaves": n,
             "q": args.q,
@@ -344,6 +360,9 @@ def main():
     if rel_l2 is not None:
         line["mixed_vs_fp64"] = {"rel_l2": rel_l2, "gate": REL_L2_GATE,
                                  "speedup": runs["fp64"]["ms"] / runs["mixed"]["ms"]}
+    if surrogate is not None:
+        line["surrogate"] = {"classes_from_network": runs["mixed"]["info"]["surrogate_classes"], "of": 6,
+                             "tol": SURROGATE_TOL, "training": sur_report}
     print(json.dumps(line), flush=True)
 
 
