@@ -77,9 +77,10 @@ typedef struct {
                       BCV_NEAR_ASSEMBLED: the plan stores every near-pair entry (FP64) once and
                       the apply multiplies by them */
     int streams;   /* 1: every phase runs on the caller's stream, in Algorithm 1's order;
-                      2: the near field runs on a plan-owned second stream (default priority),
-                      concurrently with moments, passes and interactions, joined back to the
-                      caller's stream before the evaluation phase */
+                      2: after the upward pass, the near field is forked to a plan-owned second
+                      stream (default priority), runs concurrently with the interaction phase
+                      and the downward pass, and is joined back to the caller's stream before
+                      the evaluation phase */
     bcv_mlp surrogate;     /* NULL: the touching-pair integrals come from bcv_touching_integrals.
                               Else the six face/edge/vertex classes take the trained surrogate's
                               value where its error estimate is <= surrogate_tol (relative), and

@@ -699,14 +699,6 @@ void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStre
     const bool near = (parts & BCV_PART_NEAR) != 0;
     const bool fork = far && near && p.streams == 2;
     PhaseMarks marks(p);
-    if (fork) {  // near field on the side stream, concurrently with the far field
-        BCV_HIP(hipEventRecord(p.ev_fork, st));
-        BCV_HIP(hipStreamWaitEvent(p.side, p.ev_fork, 0));
-        marks.start(BCV_PHASE_NEAR, p.side);
-        launch_near<Q>(p, f, nullptr, BCV_PART_NEAR, u, p.side);
-        marks.stop(BCV_PHASE_NEAR, p.side);
-        BCV_HIP(hipEventRecord(p.ev_join, p.side));
-    }
     if (far) {
         marks.start(BCV_PHASE_P2M, st);
         const int64_t nthr = p.n_leaves * K;
@@ -722,6 +714,17 @@ void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStre
             check_launch();
         }
         marks.stop(BCV_PHASE_M2M, st);
+        if (fork) {
+            // Near field on the side stream, concurrently with the interaction phase. It is forked
+            // after the upward pass: the short, level-by-level moment kernels are on the critical
+            // path and would otherwise share the CUs with it.
+            BCV_HIP(hipEventRecord(p.ev_fork, st));
+            BCV_HIP(hipStreamWaitEvent(p.side, p.ev_fork, 0));
+            marks.start(BCV_PHASE_NEAR, p.side);
+            launch_near<Q>(p, f, nullptr, BCV_PART_NEAR, u, p.side);
+            marks.stop(BCV_PHASE_NEAR, p.side);
+            BCV_HIP(hipEventRecord(p.ev_join, p.side));
+        }
         marks.start(BCV_PHASE_M2L, st);
         if (p.n_tasks > 0) {
             if (p.precision == BCV_MIXED_F32) {
