@@ -44,6 +44,26 @@ def m2l_flops_per_pair(q):
     return 2 * comb(q + 6, 6)
 
 
+def ncoef(d):
+    return (d + 1) * (d + 2) * (d + 3) // 6
+
+
+def m2l_kernel_names(q, mixed):
+    """The interaction-phase launches of one apply (see launch_m2l in kernels.hip)."""
+    K = ncoef(q)
+    if not mixed:
+        if K <= 84:
+            return ["m2l_kernel<%d, double, 0, %d>" % (q, K)]
+        S = ncoef(q - 3)
+        return ["m2l_kernel<%d, double, 0, %d>" % (q, S), "m2l_kernel<%d, double, %d, %d>" % (q, S, K)]
+    if q <= 6:
+        S = ncoef(q // 2 - 1)
+        blocks = [(0, K, 0, S), (0, ncoef(q - q // 2), S, K)]
+    else:
+        blocks = [(0, 84, 0, 10), (84, K, 0, 4), (0, 56, 10, 35), (0, 20, 35, 84), (0, 4, 84, K)]
+    return ["m2l_shift_kernel<%d, %d, %d, %d, %d>" % ((q,) + b) for b in blocks]
+
+
 def near_flops(info, q):
     """Algorithmic flops of the on-the-fly near field: 64 kernel evaluations per point-rule pair.
 
@@ -84,38 +104,56 @@ def cpu_baseline(L, q, f, u_gpu, n_targets, leaves):
     }
 
 
-def measure(bcv, torch, tree, f, args, dev, nf, prec, surrogate=None):
-    """Plan, warm up, then time `args.steps` applies with per-phase HIP events."""
-    t0 = time.perf_counter()
-    plan = bcv.plan_interactions(tree, q=args.q, nearfield=nf, device=dev, streams=args.streams,
-                                 precision=bcv.MIXED_F32 if prec == "mixed" else bcv.FP64,
-                                 surrogate=surrogate, surrogate_tol=SURROGATE_TOL)
-    plan_s = time.perf_counter() - t0
-    info = plan.info
-    u = torch.empty_like(f)
+def timed_applies(bcv, torch, plan, f, u, warmup, steps, dev):
+    """Warm up, then time `steps` applies (wall clock around them) with per-phase HIP events."""
     stream = torch.cuda.current_stream(dev)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         bcv.vtv_apply(plan, f, u, stream)
     torch.cuda.synchronize()
-    bcv.plan_enable_timing(plan, args.steps)
+    bcv.plan_enable_timing(plan, steps)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         bcv.vtv_apply(plan, f, u, stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     phases, n_rec = bcv.plan_phase_times(plan)
     bcv.plan_enable_timing(plan, 0)
-    phase_avg = {k: v / max(n_rec, 1) for k, v in phases.items()}
-    roof, roof_other = roofline(info, phase_avg, args, prec)
-    out = {"plan_s": plan_s, "info": plan.info, "ms": 1e3 * elapsed / args.steps, "phases": phase_avg,
-           "u": u.cpu().numpy(), "roof": roof, "roof_other": roof_other}
+    return 1e3 * elapsed / steps, {k: v / max(n_rec, 1) for k, v in phases.items()}
+
+
+def measure(bcv, torch, tree, f, args, dev, nf, prec, surrogate=None):
+    """Plan, warm up, then time `args.steps` applies with per-phase HIP events. The roofline comes
+    from a second timed pass in which the near field runs after the far field on one stream, so
+    that every phase's kernels have the GPU to themselves (with two streams the near-field and
+    interaction kernels share the compute units and their durations say nothing about either)."""
+    def make_plan(streams):
+        return bcv.plan_interactions(tree, q=args.q, nearfield=nf, device=dev, streams=streams,
+                                     precision=bcv.MIXED_F32 if prec == "mixed" else bcv.FP64,
+                                     surrogate=surrogate, surrogate_tol=SURROGATE_TOL)
+
+    t0 = time.perf_counter()
+    plan = make_plan(args.streams)
+    plan_s = time.perf_counter() - t0
+    info = plan.info
+    u = torch.empty_like(f)
+    ms, phase_avg = timed_applies(bcv, torch, plan, f, u, args.warmup, args.steps, dev)
+    u_host = u.cpu().numpy()
     del plan
-    return out
+    if args.streams == 1:
+        iso = phase_avg
+    else:
+        plan = make_plan(1)
+        _, iso = timed_applies(bcv, torch, plan, f, u, args.warmup, args.steps, dev)
+        del plan
+    roof, roof_other = roofline(info, iso, args, prec)
+    return {"plan_s": plan_s, "info": info, "ms": ms, "phases": phase_avg, "phases_serial": iso, "u": u_host,
+            "roof": roof, "roof_other": roof_other}
 
 
 def roofline(info, phase_avg, args, prec):
-    """Roofline of the interaction and near-field kernels (per launch, averaged over the timed applies)."""
+    """Roofline of the interaction phase and the near-field kernel, per apply, from the phase times
+    of the serialized pass (HIP events on the stream the phase runs on, averaged over the applies)."""
     from paper_2112_00864_amd import profiling
 
     mixed = prec == "mixed"
@@ -132,15 +170,20 @@ def roofline(info, phase_avg, args, prec):
     else:
         near_roof = {"bound": "alu", "achieved": near_flops(info, args.q) / (near_ms * 1e-3) / 1e12,
                      "peak": peak, "unit": "TFLOP/s"}
-    K = (args.q + 1) * (args.q + 2) * (args.q + 3) // 6
-    K_first = K if K <= 84 else (args.q - 2) * (args.q - 1) * args.q // 6  # q = 8: two launches
-    m2l_name = "m2l_kernel<%d, %s, 0, %d>" % (args.q, "float" if mixed else "double", K_first)
     near_name = "near_eval_kernel<%d, %s, %s>" % (args.q, "true" if args.nearfield == "assembled" else "false",
                                                   "true" if mixed and args.nearfield != "assembled" else "false")
-    for roof_, name in ((m2l_roof, m2l_name), (near_roof, near_name)):
+    # the interaction phase: FP32 copy of the moments (mixed), the interaction launches and the sum
+    # of the split tasks' pieces
+    m2l_names = ((["to_f32_kernel"] if mixed else []) + m2l_kernel_names(args.q, mixed)
+                 + ["m2l_combine_kernel<%d>" % args.q])
+    for roof_, names in ((m2l_roof, m2l_names), (near_roof, [near_name])):
         roof_["frac"] = roof_["achieved"] / roof_["peak"]
-        roof_["traffic"] = profiling.traffic_for(name)  # HBM bytes per launch (PMC), None if stale
-        roof_["kernel"] = name
+        # HBM bytes per apply (PMC, summed over the launches), None if stale
+        traffic = [profiling.traffic_for(n) for n in names]
+        roof_["traffic"] = None if None in traffic else sum(traffic)
+        roof_["kernel"] = " + ".join(names)
+        roof_["measured"] = ("HIP events per phase over %d applies, near field after the far field on one stream"
+                             % args.steps)
     dominant = m2l_roof if m2l_ms >= near_ms else near_roof
     return dominant, {"m2l_kernel": m2l_roof, "near_eval_kernel": near_roof}
 
@@ -345,11 +388,13 @@ def main():
             "n_touching_pairs": info["n_touch"],
             "n_m2l_pairs": info["n_m2l"],
             "m2l_lane_efficiency": info["n_m2l"] / max(info["n_m2l_lanes"], 1),
+            "m2l_gather_fraction": info["n_m2l_gather_lanes"] / max(info["n_m2l_lanes"], 1),
             "tree_seconds": tree_s,
             "plan_seconds": h["plan_s"],
             "plan_device_bytes": h["info"]["device_bytes"],
         },
         "phase_ms": h["phases"],
+        "phase_ms_serial": h["phases_serial"],
         "roofline": h["roof"],
         "roofline_other": h["roof_other"],
         "cpu_baseline": cpu,

@@ -32,13 +32,15 @@ struct bcv_tree_s {
 namespace bcv {
 
 // Device-side description of one 64-lane interaction (M2L) task: 64 targets of one level that
-// share their child position, and a list of slots, each an interaction offset shared by the
-// lanes together with one source cell per lane (or the zero row).
+// share their child position, laid out along rows, and a list of slots, each an interaction offset
+// shared by the lanes together with one source row per lane and whether the offset is in that
+// lane's own list.
 struct M2LTask {
     int32_t slot_begin;  // first slot
     int32_t n_slots;
     int32_t level;  // level of the 64 targets (cell side 2^-level); targets at 64 * task index
     int32_t out;    // -1: write the local coefficients; else the piece's partial block (see M2LSplit)
+    uint64_t heads; // lanes that read their own source at a shifting slot (lane 0 and row starts)
 };
 
 // A 64-target task whose slot list was cut into `count` pieces (tasks with out = first ...
@@ -106,7 +108,8 @@ struct bcv_plan_s {
     int device = 0;
     int L = 0, q = 0, K = 0;
     int direct = 0, nearfield = 0, precision = 0;
-    int64_t n_leaves = 0, n_cells = 0, n_near = 0, n_touch = 0, n_m2l = 0, n_m2l_lanes = 0, n_offsets = 0;
+    int64_t n_leaves = 0, n_cells = 0, n_near = 0, n_touch = 0, n_m2l = 0, n_m2l_lanes = 0, n_offsets = 0,
+            n_m2l_gather_lanes = 0;
     int64_t device_bytes = 0;
     double touch_value[bcv::kTouchClasses];  // touching integrals / (4 pi), smaller side 1
     int surrogate_classes = 0;               // classes whose value came from the surrogate
@@ -145,8 +148,8 @@ struct bcv_plan_s {
     int32_t *d_parents = nullptr;   // (marked cell, first child) pairs, grouped by level
     bcv::M2LTask *d_tasks = nullptr;
     int32_t *d_task_targets = nullptr;  // 64 per task, -1 = idle lane
-    int32_t *d_slot_off = nullptr;      // offset id per slot
-    int32_t *d_slot_src = nullptr;      // 64 source cells per slot (n_cells = zero row)
+    int32_t *d_slot_off = nullptr;      // offset id per slot | (a run of slots starts here) << 31
+    uint32_t *d_slot_src = nullptr;     // 64 per slot: source row (n_cells: none) | (in the lane's list) << 31
     bcv::M2LSplit *d_m2l_splits = nullptr;
     double *d_m2l_partial = nullptr;    // 64 x K per piece of a split task
 };

@@ -333,6 +333,29 @@ __device__ __forceinline__ void m2l_all(T *acc, const T *__restrict__ G, const T
     (m2l_beta<Q, T, A0, A1, B>(acc, G, Ms), ...);
 }
 
+// Block (a in [A0, A1)) x (b in [B0, B0 + NB)) of the same sums with the lane's source moments in
+// registers: m[b - B0] holds M_s^b.
+template <int Q, int A0, int A1, int B, class T>
+__device__ __forceinline__ void m2l_beta_reg(T *acc, const T *__restrict__ G, T mb)
+{
+    constexpr int n = ncoef(Q - Tables<Q>::mi.deg[B]);
+    constexpr int hi = n < A1 ? n : A1;
+    if constexpr (hi > A0) m2l_column<Q, A0, B>(acc, G, mb, std::make_integer_sequence<int, hi - A0>{});
+}
+
+template <int Q, int A0, int A1, int B0, class T, int... Bs>
+__device__ __forceinline__ void m2l_block_reg(T *acc, const T *__restrict__ G, const T *m,
+                                             std::integer_sequence<int, Bs...>)
+{
+    (m2l_beta_reg<Q, A0, A1, B0 + Bs>(acc, G, m[Bs]), ...);
+}
+
+// Lane l takes lane l - 1's value; lane 0 keeps its own (DPP wave shift right by one lane).
+__device__ __forceinline__ float shift_up(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+
 // Workgroups are dealt to the 8 XCDs round-robin (workgroup b runs on XCD b mod 8). XCD x runs
 // the tasks [begin[x], begin[x + 1]), a spatially contiguous range, so that neighbouring targets
 // share its L2; the ranges carry about equal work. Launch 8 * (longest range) workgroups.
@@ -346,15 +369,15 @@ __device__ __forceinline__ int xcd_task(const XcdRanges &r)
     return t < r.begin[x + 1] ? t : -1;
 }
 
-// T = double (BCV_FP64) or float (BCV_MIXED_F32: FP32 moments, tables and accumulation; the
-// local coefficients are written in FP64). The wave accumulates Lambda^a for a in [A0, A1): all
-// of them when the accumulators fit the register budget of two waves per SIMD, else the range is
-// split over launches (q = 8 in FP64).
+// FP64 interaction kernel: every slot gathers the 64 lanes' source rows (the zero row where the
+// offset is outside a lane's list; slot words: source row | (offset in the lane's list) << 31).
+// The wave accumulates Lambda^a for a in [A0, A1): all of them when the accumulators fit the
+// register budget of two waves per SIMD, else the range is split over launches (q = 8).
 template <int Q, class T, int A0, int A1>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2, 2))) void m2l_kernel(
     XcdRanges ranges, const M2LTask *__restrict__ tasks, const int32_t *__restrict__ targets,
-    const int32_t *__restrict__ slot_off, const int32_t *__restrict__ slot_src, const T *__restrict__ G,
-    const T *__restrict__ M, double *__restrict__ partial, double *__restrict__ Lam)
+    const int32_t *__restrict__ slot_off, const uint32_t *__restrict__ slot_src, const T *__restrict__ G,
+    const T *__restrict__ M, int32_t zero_row, double *__restrict__ partial, double *__restrict__ Lam)
 {
     constexpr int K = MultiIndex<Q>::K, NA = A1 - A0;
     const int ti = xcd_task(ranges);
@@ -364,20 +387,21 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2, 2))) v
     T acc[NA];
 #pragma unroll
     for (int a = 0; a < NA; ++a) acc[a] = T(0);
-    // the next slot's offset and source are fetched one slot ahead
-    int32_t off_next = 0, src_next = 0;
+    auto row_of = [zero_row](uint32_t word) { return (word >> 31) ? (int32_t)(word & 0x7FFFFFFFu) : zero_row; };
+    // the next slot's words are fetched one slot ahead
+    int32_t off_next = 0, src_next = zero_row;
     if (task.n_slots > 0) {
         off_next = slot_off[task.slot_begin];
-        src_next = slot_src[(int64_t)task.slot_begin * kWave + lane];
+        src_next = row_of(slot_src[(int64_t)task.slot_begin * kWave + lane]);
     }
     for (int j = 0; j < task.n_slots; ++j) {
-        const int32_t off = off_next, src = src_next;
+        const int32_t ow = off_next, src = src_next;
         if (j + 1 < task.n_slots) {
             const int64_t nxt = (int64_t)task.slot_begin + j + 1;
             off_next = slot_off[nxt];
-            src_next = slot_src[nxt * kWave + lane];
+            src_next = row_of(slot_src[nxt * kWave + lane]);
         }
-        const T *__restrict__ Gs = G + (int64_t)off * K;
+        const T *__restrict__ Gs = G + (int64_t)(ow & 0x7FFFFFFF) * K;
         const T *__restrict__ Ms = M + (int64_t)src * K;
         m2l_all<Q, T, A0, A1>(acc, Gs, Ms, std::make_integer_sequence<int, K>{});
     }
@@ -391,6 +415,93 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2, 2))) v
         double *__restrict__ dst = partial + ((int64_t)task.out * K + A0) * kWave + lane;
 #pragma unroll
         for (int a = 0; a < NA; ++a) dst[a * kWave] = (double)acc[a] * inv_a;
+    }
+}
+
+// FP32 interaction kernel with lane shifts. The plan lays a task's targets along rows (lane l + 1
+// two cells after lane l, except at the task's head lanes) and orders its slots so that
+// consecutive offsets step by two cells along the same axis: at a slot without the gather bit
+// every lane's new source is the previous slot's source of the lane below, so the source moments
+// stay in registers, move up one lane by a DPP shift, and only the head lanes read a row, instead
+// of 64 lanes gathering 64 rows. Every slot names the real source of every lane (the zero row
+// where there is no cell) and, in bit 31, whether the offset is in the lane's list; only those
+// lanes accumulate. One launch covers the block a in [A0, A1), b in [B0, B1) of the sums
+// (|a| + |b| <= Q): the launches of a full interaction phase tile the triangle in blocks that fit
+// 128 registers, four waves per SIMD (the latency of the row reads at the start of each slot is
+// covered by the other waves). The block with B0 = 0 writes Lambda^a, the others add to it and are
+// launched after it.
+template <int Q, int A0, int A1, int B0, int B1>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4, 4))) void m2l_shift_kernel(
+    XcdRanges ranges, const M2LTask *__restrict__ tasks, const int32_t *__restrict__ targets,
+    const int32_t *__restrict__ slot_off, const uint32_t *__restrict__ slot_src, const float *__restrict__ G,
+    const float *__restrict__ M, double *__restrict__ partial, double *__restrict__ Lam)
+{
+    constexpr int K = MultiIndex<Q>::K, NA = A1 - A0, NB = B1 - B0;
+    const int ti = xcd_task(ranges);
+    if (ti < 0) return;
+    const M2LTask task = tasks[ti];
+    const int lane = threadIdx.x;
+    const bool head = ((task.heads >> lane) & 1ull) != 0ull;
+    const int n = task.n_slots;
+    const int64_t s0 = task.slot_begin;
+    float acc[NA], m[NB];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) acc[a] = 0.0f;
+    if (n > 0) {
+        int32_t ow = slot_off[s0], ow1 = 0;
+        uint32_t w = slot_src[s0 * kWave + lane], w1 = 0;
+        if (n > 1) {
+            ow1 = slot_off[s0 + 1];
+            w1 = slot_src[(s0 + 1) * kWave + lane];
+        }
+        for (int j = 0; j < n; ++j) {
+            int32_t ow2 = 0;  // the slot words are read two slots ahead
+            uint32_t w2 = 0;
+            if (j + 2 < n) {
+                ow2 = slot_off[s0 + j + 2];
+                w2 = slot_src[(s0 + j + 2) * kWave + lane];
+            }
+            const float *__restrict__ Ms = M + (int64_t)(w & 0x7FFFFFFFu) * K + B0;
+            if (ow < 0 || j == 0) {  // gather the sources of all lanes
+#pragma unroll
+                for (int b = 0; b < NB; ++b) m[b] = Ms[b];
+            } else {  // shift by one lane; the head lanes then read their new source
+#pragma unroll
+                for (int b = 0; b < NB; ++b) m[b] = shift_up(m[b]);
+                if (head) {
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) m[b] = Ms[b];
+                }
+            }
+            if (w >> 31)
+                m2l_block_reg<Q, A0, A1, B0>(acc, G + (int64_t)(ow & 0x7FFFFFFF) * K, m,
+                                             std::make_integer_sequence<int, NB>{});
+            ow = ow1, w = w1, ow1 = ow2, w1 = w2;
+        }
+    }
+    // keep the FP64 conversions below the loop (folded into the loop's exit they would hold all NA
+    // results in FP64 at once, twice the registers)
+#pragma unroll
+    for (int a = 0; a < NA; ++a) asm volatile("" : "+v"(acc[a]));
+    const int32_t t = targets[(int64_t)ti * kWave + lane];
+    if (t < 0) return;
+    const double inv_a = ldexp(1.0, task.level);
+    double *__restrict__ dst;
+    int64_t stride;
+    if (task.out < 0) {
+        dst = Lam + (int64_t)t * K + A0;
+        stride = 1;
+    } else {  // [piece][a][lane]: coalesced
+        dst = partial + ((int64_t)task.out * K + A0) * kWave + lane;
+        stride = kWave;
+    }
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+        const double v = (double)acc[a] * inv_a;
+        if constexpr (B0 == 0)
+            dst[a * stride] = v;
+        else
+            dst[a * stride] += v;
     }
 }
 
@@ -665,28 +776,60 @@ void launch_near(const bcv_plan_s &p, const double *f, const double *lam, int pa
         check_launch();
     }
 }
-// Interaction kernel over all tasks. Up to q = 6 one wave holds all K accumulators; at q = 8
-// (K = 165) the coefficient range is split in two launches, |a| <= 5 and 6 <= |a| <= 8, to stay
-// within the register budget of two waves per SIMD.
-template <int Q, class T>
-void launch_m2l(const bcv_plan_s &p, const T *G, const T *M, hipStream_t st)
+template <int Q, int A0, int A1, int B0, int B1>
+void launch_m2l_block(const bcv_plan_s &p, const XcdRanges &ranges, const float *G, const float *M, hipStream_t st)
+{
+    m2l_shift_kernel<Q, A0, A1, B0, B1><<<(unsigned)p.m2l_groups, kWave, 0, st>>>(
+        ranges, p.d_tasks, p.d_task_targets, p.d_slot_off, p.d_slot_src, G, M, p.d_m2l_partial, p.d_Lam);
+    check_launch();
+}
+
+// Interaction phase over all tasks. FP64: one gathering launch holds all K accumulators up to
+// q = 6; at q = 8 (K = 165) the coefficient range is split in two launches, |a| <= 5 and
+// 6 <= |a| <= 8, to stay within the register budget of two waves per SIMD. FP32: lane-shifting
+// launches over blocks of the (a, b) triangle, split by degree (n(d) = number of multi-indices of
+// degree <= d) so that every block fits four waves per SIMD; the blocks that write come first.
+template <int Q>
+void launch_m2l(const bcv_plan_s &p, const double *G, const double *M, hipStream_t st)
 {
     constexpr int K = MultiIndex<Q>::K;
-    const unsigned groups = (unsigned)p.m2l_groups;
     XcdRanges ranges;
     for (int x = 0; x <= kXcds; ++x) ranges.begin[x] = p.xcd_begin[x];
+    const unsigned groups = (unsigned)p.m2l_groups;
+    const int32_t zero_row = (int32_t)p.n_cells;
     if constexpr (K <= 84) {
-        m2l_kernel<Q, T, 0, K><<<groups, kWave, 0, st>>>(ranges, p.d_tasks, p.d_task_targets, p.d_slot_off,
-                                                         p.d_slot_src, G, M, p.d_m2l_partial, p.d_Lam);
+        m2l_kernel<Q, double, 0, K><<<groups, kWave, 0, st>>>(ranges, p.d_tasks, p.d_task_targets, p.d_slot_off,
+                                                              p.d_slot_src, G, M, zero_row, p.d_m2l_partial, p.d_Lam);
         check_launch();
     } else {
-        constexpr int S = ncoef(Q - 3);  // |a| <= Q - 3, then the rest
-        m2l_kernel<Q, T, 0, S><<<groups, kWave, 0, st>>>(ranges, p.d_tasks, p.d_task_targets, p.d_slot_off,
-                                                         p.d_slot_src, G, M, p.d_m2l_partial, p.d_Lam);
+        constexpr int S = ncoef(Q - 3);
+        m2l_kernel<Q, double, 0, S><<<groups, kWave, 0, st>>>(ranges, p.d_tasks, p.d_task_targets, p.d_slot_off,
+                                                              p.d_slot_src, G, M, zero_row, p.d_m2l_partial, p.d_Lam);
         check_launch();
-        m2l_kernel<Q, T, S, K><<<groups, kWave, 0, st>>>(ranges, p.d_tasks, p.d_task_targets, p.d_slot_off,
-                                                         p.d_slot_src, G, M, p.d_m2l_partial, p.d_Lam);
+        m2l_kernel<Q, double, S, K><<<groups, kWave, 0, st>>>(ranges, p.d_tasks, p.d_task_targets, p.d_slot_off,
+                                                              p.d_slot_src, G, M, zero_row, p.d_m2l_partial, p.d_Lam);
         check_launch();
+    }
+}
+
+template <int Q>
+void launch_m2l(const bcv_plan_s &p, const float *G, const float *M, hipStream_t st)
+{
+    constexpr int K = MultiIndex<Q>::K;
+    XcdRanges ranges;
+    for (int x = 0; x <= kXcds; ++x) ranges.begin[x] = p.xcd_begin[x];
+    if constexpr (Q <= 6) {
+        // columns |b| < Q / 2 with every a; columns |b| >= Q / 2 reach only |a| <= Q - Q / 2
+        constexpr int S = ncoef(Q / 2 - 1);
+        launch_m2l_block<Q, 0, K, 0, S>(p, ranges, G, M, st);
+        launch_m2l_block<Q, 0, ncoef(Q - Q / 2), S, K>(p, ranges, G, M, st);
+    } else {
+        static_assert(Q == 8, "orders 4, 6, 8");
+        launch_m2l_block<Q, 0, 84, 0, 10>(p, ranges, G, M, st);   // |a| <= 6, |b| <= 2
+        launch_m2l_block<Q, 84, K, 0, 4>(p, ranges, G, M, st);    // |a| >= 7, |b| <= 1
+        launch_m2l_block<Q, 0, 56, 10, 35>(p, ranges, G, M, st);  // |a| <= 5, 3 <= |b| <= 4
+        launch_m2l_block<Q, 0, 20, 35, 84>(p, ranges, G, M, st);  // |a| <= 3, 5 <= |b| <= 6
+        launch_m2l_block<Q, 0, 4, 84, K>(p, ranges, G, M, st);    // |a| <= 1, 7 <= |b| <= 8
     }
 }
 
@@ -731,9 +874,9 @@ void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStre
                 const int64_t n = (p.n_cells + 1) * K;
                 to_f32_kernel<<<(unsigned)std::min<int64_t>((n + 255) / 256, 65536), 256, 0, st>>>(n, p.d_M, p.d_M32);
                 check_launch();
-                launch_m2l<Q, float>(p, p.d_G32, p.d_M32, st);
+                launch_m2l<Q>(p, p.d_G32, p.d_M32, st);
             } else {
-                launch_m2l<Q, double>(p, p.d_G, p.d_M, st);
+                launch_m2l<Q>(p, p.d_G, p.d_M, st);
             }
             if (p.n_m2l_splits > 0) {
                 m2l_combine_kernel<Q><<<dim3((unsigned)p.n_m2l_splits, (K + 3) / 4), 256, 0, st>>>(

@@ -13,6 +13,7 @@ namespace bcv {
 namespace {
 
 constexpr int kTile = 64, kTileK = 16, kThreads = 256;
+constexpr int kSplitRows = 256;  // rows of the reduction dimension per split (weight and bias gradients)
 
 __device__ __forceinline__ float sigmoid(float z) { return 1.0f / (1.0f + __expf(-z)); }
 
@@ -20,24 +21,30 @@ __device__ __forceinline__ float sigmoid(float z) { return 1.0f / (1.0f + __expf
 // A[m * lda + k]; op(B)[k][n] = TB ? B[n * ldb + k] : B[k * ldb + n]. If H is given it also
 // receives silu(C). One 256-thread block per 64 x 64 tile, 4 x 4 outputs per thread, K in steps
 // of 16 through LDS. Every thread sums in the same order: results do not depend on the launch.
+// Split K: block z covers k in [z k_chunk, (z + 1) k_chunk) and writes its partial product to
+// C + z c_stride (no bias, accumulate or H then; the partial products are summed by
+// sum_splits_kernel in z order).
 template <bool TA, bool TB>
 __global__ __launch_bounds__(kThreads) void gemm_kernel(int M, int N, int K, const float *__restrict__ A, int lda,
                                                         const float *__restrict__ B, int ldb,
                                                         const float *__restrict__ bias, int accumulate,
-                                                        float *__restrict__ C, int ldc, float *__restrict__ H)
+                                                        float *__restrict__ C, int ldc, float *__restrict__ H,
+                                                        int k_chunk, int64_t c_stride)
 {
     __shared__ float As[kTileK][kTile + 1];
     __shared__ float Bs[kTileK][kTile + 1];
     const int m0 = blockIdx.y * kTile, n0 = blockIdx.x * kTile;
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const int k_begin = (int)blockIdx.z * k_chunk, k_end = min(K, k_begin + k_chunk);
+    C += (int64_t)blockIdx.z * c_stride;
     float acc[4][4] = {};
-    for (int k0 = 0; k0 < K; k0 += kTileK) {
+    for (int k0 = k_begin; k0 < k_end; k0 += kTileK) {
         for (int e = threadIdx.x; e < kTileK * kTile; e += kThreads) {
             const int kk = e / kTile, mm = e % kTile;
             const int m = m0 + mm, k = k0 + kk;
-            As[kk][mm] = (m < M && k < K) ? (TA ? A[(int64_t)k * lda + m] : A[(int64_t)m * lda + k]) : 0.0f;
+            As[kk][mm] = (m < M && k < k_end) ? (TA ? A[(int64_t)k * lda + m] : A[(int64_t)m * lda + k]) : 0.0f;
             const int n = n0 + mm;
-            Bs[kk][mm] = (n < N && k < K) ? (TB ? B[(int64_t)n * ldb + k] : B[(int64_t)k * ldb + n]) : 0.0f;
+            Bs[kk][mm] = (n < N && k < k_end) ? (TB ? B[(int64_t)n * ldb + k] : B[(int64_t)k * ldb + n]) : 0.0f;
         }
         __syncthreads();
 #pragma unroll
@@ -69,6 +76,17 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(int M, int N, int K, con
         }
 }
 
+// out[i] = sum over z < splits of part[z * n + i], in z order (+ out[i] if accumulate).
+__global__ void sum_splits_kernel(int64_t n, int splits, const float *__restrict__ part, int accumulate,
+                                  float *__restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        float s = accumulate ? out[i] : 0.0f;
+        for (int z = 0; z < splits; ++z) s += part[(int64_t)z * n + i];
+        out[i] = s;
+    }
+}
+
 // dZ = dH * silu'(Z), silu'(z) = s (1 + z (1 - s)), s = sigmoid(z).
 __global__ void silu_backward_kernel(int64_t n, const float *__restrict__ Z, const float *__restrict__ dH,
                                      float *__restrict__ dZ)
@@ -79,14 +97,16 @@ __global__ void silu_backward_kernel(int64_t n, const float *__restrict__ Z, con
     }
 }
 
-// Column sums: db[n] = sum_m dZ[m][n] (fixed order over m).
-__global__ void column_sum_kernel(int M, int N, const float *__restrict__ dZ, float *__restrict__ db)
+// Partial column sums: part[z][n] = sum of dZ[m][n] over rows m in [z rows, (z + 1) rows), in
+// order; block (x, z) covers columns 128 x .. 128 x + 127 of row chunk z.
+__global__ void column_sum_kernel(int M, int N, int rows, const float *__restrict__ dZ, float *__restrict__ part)
 {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
+    const int m0 = (int)blockIdx.y * rows, m1 = min(M, m0 + rows);
     float s = 0.0f;
-    for (int m = 0; m < M; ++m) s += dZ[(int64_t)m * N + n];
-    db[n] = s;
+    for (int m = m0; m < m1; ++m) s += dZ[(int64_t)m * N + n];
+    part[(int64_t)blockIdx.y * N + n] = s;
 }
 
 // Loss of a batch of B rows Y = (value, log-error) against targets r (mean over the batch):
@@ -139,14 +159,31 @@ void gemm(bool ta, bool tb, int M, int N, int K, const float *A, int lda, const 
 {
     if (M <= 0 || N <= 0) return;
     const dim3 grid((N + kTile - 1) / kTile, (M + kTile - 1) / kTile);
+    const int kc = std::max(K, 1);
     if (!ta && !tb)
-        gemm_kernel<false, false><<<grid, kThreads, 0, st>>>(M, N, K, A, lda, B, ldb, bias, accumulate, C, ldc, H);
+        gemm_kernel<false, false><<<grid, kThreads, 0, st>>>(M, N, K, A, lda, B, ldb, bias, accumulate, C, ldc, H, kc, 0);
     else if (!ta && tb)
-        gemm_kernel<false, true><<<grid, kThreads, 0, st>>>(M, N, K, A, lda, B, ldb, bias, accumulate, C, ldc, H);
+        gemm_kernel<false, true><<<grid, kThreads, 0, st>>>(M, N, K, A, lda, B, ldb, bias, accumulate, C, ldc, H, kc, 0);
     else if (ta && !tb)
-        gemm_kernel<true, false><<<grid, kThreads, 0, st>>>(M, N, K, A, lda, B, ldb, bias, accumulate, C, ldc, H);
+        gemm_kernel<true, false><<<grid, kThreads, 0, st>>>(M, N, K, A, lda, B, ldb, bias, accumulate, C, ldc, H, kc, 0);
     else
-        gemm_kernel<true, true><<<grid, kThreads, 0, st>>>(M, N, K, A, lda, B, ldb, bias, accumulate, C, ldc, H);
+        gemm_kernel<true, true><<<grid, kThreads, 0, st>>>(M, N, K, A, lda, B, ldb, bias, accumulate, C, ldc, H, kc, 0);
+    BCV_HIP(hipGetLastError());
+}
+
+int64_t split_workspace(int M, int N, int K) { return (int64_t)((K + kSplitRows - 1) / kSplitRows) * M * N; }
+
+void gemm_tn_split(int M, int N, int K, const float *A, int lda, const float *B, int ldb, float *C, float *ws,
+                   hipStream_t st)
+{
+    if (M <= 0 || N <= 0) return;
+    const int splits = std::max(1, (K + kSplitRows - 1) / kSplitRows);
+    const dim3 grid((N + kTile - 1) / kTile, (M + kTile - 1) / kTile, splits);
+    gemm_kernel<true, false><<<grid, kThreads, 0, st>>>(M, N, K, A, lda, B, ldb, nullptr, 0, ws, N, nullptr,
+                                                         kSplitRows, (int64_t)M * N);
+    BCV_HIP(hipGetLastError());
+    const int64_t n = (int64_t)M * N;
+    sum_splits_kernel<<<grid_for(n), 256, 0, st>>>(n, splits, ws, 0, C);
     BCV_HIP(hipGetLastError());
 }
 
@@ -157,9 +194,13 @@ void silu_backward(int64_t n, const float *Z, const float *dH, float *dZ, hipStr
     BCV_HIP(hipGetLastError());
 }
 
-void column_sum(int M, int N, const float *dZ, float *db, hipStream_t st)
+void column_sum(int M, int N, const float *dZ, float *db, float *ws, hipStream_t st)
 {
-    column_sum_kernel<<<(N + 127) / 128, 128, 0, st>>>(M, N, dZ, db);
+    if (N <= 0) return;
+    const int splits = std::max(1, (M + kSplitRows - 1) / kSplitRows);
+    column_sum_kernel<<<dim3((N + 127) / 128, splits), 128, 0, st>>>(M, N, kSplitRows, dZ, ws);
+    BCV_HIP(hipGetLastError());
+    sum_splits_kernel<<<grid_for(N), 256, 0, st>>>(N, splits, ws, 0, db);
     BCV_HIP(hipGetLastError());
 }
 

@@ -11,11 +11,19 @@ namespace bcv {
 void gemm(bool ta, bool tb, int M, int N, int K, const float *A, int lda, const float *B, int ldb, const float *bias,
           bool accumulate, float *C, int ldc, float *H, hipStream_t st);
 
+// C[M x N] = A^T B with A stored [K x M] and B [K x N] (weight gradients: K is the batch), split
+// over K in fixed chunks whose partial products go to ws (split_workspace(M, N, K) floats) and are
+// summed in chunk order.
+int64_t split_workspace(int M, int N, int K);
+void gemm_tn_split(int M, int N, int K, const float *A, int lda, const float *B, int ldb, float *C, float *ws,
+                   hipStream_t st);
+
 // dZ = dH * silu'(Z), elementwise over n values.
 void silu_backward(int64_t n, const float *Z, const float *dH, float *dZ, hipStream_t st);
 
-// db[n] = sum over the M rows of dZ [M x N].
-void column_sum(int M, int N, const float *dZ, float *db, hipStream_t st);
+// db[n] = sum over the M rows of dZ [M x N], in fixed row chunks (partial sums in ws,
+// split_workspace(1, N, M) floats) summed in chunk order.
+void column_sum(int M, int N, const float *dZ, float *db, float *ws, hipStream_t st);
 
 // Loss of B rows Y = (value, log-error) against targets r (see mlp.hip): dY = dL/dY, terms = the
 // two squared terms per row.

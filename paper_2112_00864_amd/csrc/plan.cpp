@@ -259,12 +259,13 @@ NearUnits build_near_units(const NearCSR &near, int64_t n_leaves, int64_t unit)
 struct M2LPlan {
     std::vector<M2LTask> tasks;
     std::vector<int32_t> targets;   // 64 per task
-    std::vector<int32_t> slot_key;  // offset key per slot, later replaced by the offset id
-    std::vector<int32_t> slot_src;  // 64 per slot
+    std::vector<int32_t> slot_key;  // offset key per slot | gather bit 31, later the offset id | bit 31
+    std::vector<uint32_t> slot_src; // 64 per slot: source row | (offset in the lane's own list) << 31
     std::vector<M2LSplit> splits;
     int32_t n_pieces = 0;           // partial blocks of split tasks
     int32_t xcd_begin[kXcds + 1] = {};
     int64_t n_pairs = 0;
+    int64_t n_read_lanes = 0;       // lanes that read their source row in a lane-shifting kernel
 };
 
 // Default longest slot list of one interaction task: longer lists (the remainder tasks, whose
@@ -300,15 +301,24 @@ uint64_t hash_keys(const std::vector<int32_t> &keys)
 // Packs the interaction phase into 64-lane tasks. Targets of one level are grouped by the
 // signature of their interaction list (cells in the interior of a face share it, cells along an
 // edge share it with the other cells at the same distance from the edge): each signature class
-// fills whole 64-lane tasks, and the remainders are packed together in Morton order. A task's
-// slots are the union of its targets' offsets; a lane gets a source only for offsets in its own
-// list, otherwise the zero row.
+// fills whole 64-lane tasks, and the remainders are packed together in Morton order. Members of a
+// class share their child position, so along a row of the mesh they are two cells apart; a class
+// is laid out row by row along its longest axis (lane l + 1 two cells after lane l except where a
+// row ends, the task's "heads"). A task's slots are the union of its targets' offsets o = t - s,
+// sorted so that consecutive slots step o by two cells along that axis. Then the source of a
+// non-head lane at a slot is the previous slot's source of the lane before it, and the
+// interaction kernel can shift registers across lanes instead of gathering again; the plan checks
+// this for every slot and lane, and marks the slots where it fails (and the first one) as
+// gathering. Every slot records the source row of every lane (the zero row where there is no
+// cell) and, in bit 31, whether the offset is in that lane's own list.
 M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, int32_t max_slots)
 {
     M2LPlan m;
     const int32_t zero_row = (int32_t)t.n_cells();
+    BCV_REQUIRE(zero_row < (1 << 30), BCV_ENOTSUP, "more than 2^30 cells");
     struct Chunk {
         int lev;
+        int axis;  // rows of the task run along this axis
         std::vector<int32_t> cells;
     };
     std::vector<Chunk> chunks;
@@ -329,32 +339,58 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, int32_t max_s
         for (int32_t q = 0; q < n; ++q) order[q] = q;
         std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return sig[x] < sig[y]; });
         std::vector<Chunk> level_chunks;
-        std::vector<std::vector<int32_t>> remainders;
+        std::vector<Chunk> remainders;
         for (int32_t s0 = 0; s0 < n;) {
             int32_t s1 = s0;
             while (s1 < n && sig[order[s1]] == sig[order[s0]]) ++s1;
+            // the class in rows along the axis with the most member pairs two cells apart (x first on
+            // ties); a class may span several separate patches of the level
+            int axis = 0;
+            {
+                int64_t pairs[3] = {0, 0, 0};
+                for (int32_t r = s0; r < s1; ++r) {
+                    const int32_t *c = &t.ijk[3 * (b + order[r])];
+                    for (int ax = 0; ax < 3; ++ax) {
+                        const int32_t nb = g[lev].at(c[0] + 2 * (ax == 0), c[1] + 2 * (ax == 1), c[2] + 2 * (ax == 2));
+                        pairs[ax] += nb >= 0 && sig[nb - b] == sig[order[s0]];
+                    }
+                }
+                for (int ax = 1; ax < 3; ++ax)
+                    if (pairs[ax] > pairs[axis]) axis = ax;
+                const int u = axis == 0 ? 2 : (axis == 1 ? 2 : 1), v = axis == 0 ? 1 : 0;
+                std::sort(order.begin() + s0, order.begin() + s1, [&](int32_t x, int32_t y) {
+                    const int32_t *a = &t.ijk[3 * (b + x)], *c = &t.ijk[3 * (b + y)];
+                    if (a[u] != c[u]) return a[u] < c[u];
+                    if (a[v] != c[v]) return a[v] < c[v];
+                    return a[axis] < c[axis];
+                });
+            }
             int32_t q = s0;
             for (; q + 64 <= s1; q += 64) {
-                Chunk ch{lev, {}};
+                Chunk ch{lev, axis, {}};
                 for (int32_t r = q; r < q + 64; ++r) ch.cells.push_back(b + order[r]);
                 level_chunks.push_back(std::move(ch));
             }
             if (q < s1) {
-                std::vector<int32_t> rem;
-                for (int32_t r = q; r < s1; ++r) rem.push_back(b + order[r]);
+                Chunk rem{lev, axis, {}};
+                for (int32_t r = q; r < s1; ++r) rem.cells.push_back(b + order[r]);
                 remainders.push_back(std::move(rem));
             }
             s0 = s1;
         }
-        std::sort(remainders.begin(), remainders.end(),
-                  [](const std::vector<int32_t> &x, const std::vector<int32_t> &y) { return x[0] < y[0]; });
-        Chunk cur{lev, {}};
-        for (const auto &rem : remainders) {
-            if (cur.cells.size() + rem.size() > 64) {
+        // the remainders (most are whole classes: the rows of cells along the edges of the
+        // domain) share tasks with remainders of the same row axis, in Morton order
+        std::sort(remainders.begin(), remainders.end(), [](const Chunk &x, const Chunk &y) {
+            return x.axis != y.axis ? x.axis < y.axis : x.cells[0] < y.cells[0];
+        });
+        Chunk cur{lev, 0, {}};
+        for (auto &rem : remainders) {
+            if (!cur.cells.empty() && (cur.axis != rem.axis || cur.cells.size() + rem.cells.size() > 64)) {
                 level_chunks.push_back(std::move(cur));
-                cur = Chunk{lev, {}};
+                cur = Chunk{lev, rem.axis, {}};
             }
-            cur.cells.insert(cur.cells.end(), rem.begin(), rem.end());
+            cur.axis = rem.axis;
+            cur.cells.insert(cur.cells.end(), rem.cells.begin(), rem.cells.end());
         }
         if (!cur.cells.empty()) level_chunks.push_back(std::move(cur));
         // spatial order of tasks within the level (Morton order of the first target)
@@ -363,7 +399,9 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, int32_t max_s
         for (auto &ch : level_chunks) chunks.push_back(std::move(ch));
     }
     struct Out {
-        std::vector<int32_t> keys, src;
+        std::vector<int32_t> keys;  // offset key per slot | (the slot gathers) << 31
+        std::vector<uint32_t> src;  // 64 per slot
+        uint64_t heads = 0;
         int64_t pairs = 0;
     };
     std::vector<Out> outs(chunks.size());
@@ -371,32 +409,60 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, int32_t max_s
     {
         std::vector<std::vector<int32_t>> lane_keys(64);
         std::vector<char> used(15 * 15 * 15);
+        std::vector<std::array<int, 5>> order;  // across 1, across 2, along parity, along, key
 #pragma omp for schedule(dynamic, 4)
         for (size_t q = 0; q < chunks.size(); ++q) {
             const Chunk &ch = chunks[q];
+            const int ax = ch.axis, u = ax == 0 ? 1 : 0, v = ax == 2 ? 1 : 2;
+            const int nl = (int)ch.cells.size();
             std::fill(used.begin(), used.end(), 0);
-            for (size_t lane = 0; lane < ch.cells.size(); ++lane) {
+            for (int lane = 0; lane < nl; ++lane) {
                 interaction_keys(t, g, ch.lev, ch.cells[lane], lane_keys[lane]);
                 for (int32_t key : lane_keys[lane]) used[key] = 1;
             }
             Out &o = outs[q];
+            for (int lane = 0; lane < nl; ++lane) {  // heads: the previous lane is not two cells back
+                bool head = lane == 0;
+                if (!head) {
+                    const int32_t a = ch.cells[lane - 1], c = ch.cells[lane];
+                    for (int k = 0; k < 3; ++k)
+                        head = head || t.ijk[3 * c + k] - t.ijk[3 * a + k] != (k == ax ? 2 : 0);
+                }
+                if (head) o.heads |= 1ull << lane;
+            }
+            order.clear();
             for (int key = 0; key < 15 * 15 * 15; ++key) {
                 if (!used[key]) continue;
-                const int a = key / 225 - 7, b = (key / 15) % 15 - 7, cc = key % 15 - 7;
-                o.keys.push_back(key);
+                const int d[3] = {key / 225 - 7, (key / 15) % 15 - 7, key % 15 - 7};
+                order.push_back({d[u], d[v], d[ax] & 1, d[ax], key});
+            }
+            std::sort(order.begin(), order.end());
+            for (size_t k = 0; k < order.size(); ++k) {
+                const int key = order[k][4];
+                const int d[3] = {key / 225 - 7, (key / 15) % 15 - 7, key % 15 - 7};
+                const size_t at = o.src.size();
                 for (int lane = 0; lane < 64; ++lane) {
                     int32_t s = -1;
-                    if (lane < (int)ch.cells.size() &&
-                        std::binary_search(lane_keys[lane].begin(), lane_keys[lane].end(), key)) {
+                    bool valid = false;
+                    if (lane < nl) {
                         const int32_t c = ch.cells[lane];
-                        s = g[ch.lev].at(t.ijk[3 * c] - a, t.ijk[3 * c + 1] - b, t.ijk[3 * c + 2] - cc);
+                        s = g[ch.lev].at(t.ijk[3 * c] - d[0], t.ijk[3 * c + 1] - d[1], t.ijk[3 * c + 2] - d[2]);
+                        valid = std::binary_search(lane_keys[lane].begin(), lane_keys[lane].end(), key);
+                        if (valid && s < 0) o.pairs = INT64_MIN;  // a listed source must exist
                     }
-                    o.pairs += s >= 0;
-                    o.src.push_back(s >= 0 ? s : zero_row);
+                    o.pairs += valid;
+                    o.src.push_back((uint32_t)(s >= 0 ? s : zero_row) | (valid ? 1u << 31 : 0u));
                 }
+                // the slot can shift if every non-head lane finds its source one lane down
+                bool shift = k > 0;
+                for (int lane = 1; shift && lane < nl; ++lane)
+                    if (!((o.heads >> lane) & 1))
+                        shift = (o.src[at + lane] & 0x7FFFFFFFu) == (o.src[at - 64 + lane - 1] & 0x7FFFFFFFu);
+                o.keys.push_back(shift ? key : (int32_t)((uint32_t)key | (1u << 31)));
             }
         }
     }
+    for (const Out &o : outs) BCV_REQUIRE(o.pairs >= 0, BCV_ESTATE, "internal: interaction source missing");
     // Pieces of at most max_slots slots, in task order.
     struct Piece {
         M2LTask task;
@@ -411,7 +477,10 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, int32_t max_s
         if (np > 1) split_of_chunk[q] = M2LSplit{-1, m.n_pieces, np, 0};
         for (int32_t k = 0; k < np; ++k) {
             const int32_t b = base + (int32_t)((int64_t)n * k / np), e = base + (int32_t)((int64_t)n * (k + 1) / np);
-            pieces.push_back(Piece{M2LTask{b, e - b, chunks[q].lev, np > 1 ? m.n_pieces + k : -1}, (int32_t)q});
+            pieces.push_back(
+                Piece{M2LTask{b, e - b, chunks[q].lev, np > 1 ? m.n_pieces + k : -1, outs[q].heads}, (int32_t)q});
+            for (int32_t j = b; j < e; ++j)  // a piece's first slot always gathers
+                m.n_read_lanes += (j == b || outs[q].keys[j - base] < 0) ? 64 : __builtin_popcountll(outs[q].heads);
         }
         if (np > 1) m.n_pieces += np;
         m.slot_key.insert(m.slot_key.end(), outs[q].keys.begin(), outs[q].keys.end());
@@ -569,7 +638,7 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
 
         M2LPlan m2l = build_m2l(t, grids, opts.m2l_max_slots > 0 ? opts.m2l_max_slots : kDefaultMaxSlots);
         std::vector<int32_t> id_of_key(15 * 15 * 15, -1);
-        for (int32_t key : m2l.slot_key) id_of_key[key] = 0;
+        for (int32_t key : m2l.slot_key) id_of_key[key & 0x7FFFFFFF] = 0;
         std::vector<double> G;
         int32_t n_off = 0;
         for (int key = 0; key < 15 * 15 * 15; ++key) {
@@ -580,10 +649,11 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
             G.resize(at + p->K);
             derivative_table(p->q, o, &G[at]);
         }
-        for (int32_t &s : m2l.slot_key) s = id_of_key[s];
+        for (int32_t &s : m2l.slot_key) s = id_of_key[s & 0x7FFFFFFF] | (s & (int32_t)0x80000000);
         p->n_offsets = n_off;
         p->n_m2l = m2l.n_pairs;
         p->n_m2l_lanes = (int64_t)m2l.slot_key.size() * 64;
+        p->n_m2l_gather_lanes = m2l.n_read_lanes;
         p->n_tasks = (int64_t)m2l.tasks.size();
         p->d_G = upload(p.get(), G);
         if (p->precision == BCV_MIXED_F32) {

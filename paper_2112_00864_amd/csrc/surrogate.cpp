@@ -67,11 +67,13 @@ struct DevBuf {
 // Activations and gradients of one batch.
 struct Work {
     int B, width;
-    DevBuf<float> Z1, H1, Z2, H2, Y, dY, dH, dZ, terms;
-    Work(int B_, int width_)
+    DevBuf<float> Z1, H1, Z2, H2, Y, dY, dH, dZ, terms, split;
+    Work(int B_, int width_, int d_in)
         : B(B_), width(width_), Z1((size_t)B_ * width_), H1((size_t)B_ * width_), Z2((size_t)B_ * width_),
           H2((size_t)B_ * width_), Y((size_t)B_ * kMlpOut), dY((size_t)B_ * kMlpOut), dH((size_t)B_ * width_),
-          dZ((size_t)B_ * width_), terms((size_t)B_ * kMlpOut)
+          dZ((size_t)B_ * width_), terms((size_t)B_ * kMlpOut),
+          split((size_t)std::max<int64_t>(split_workspace(std::max(width_, d_in), width_, B_),
+                                          split_workspace(1, std::max(width_, kMlpOut), B_)))
     {
     }
 };
@@ -93,18 +95,18 @@ void backward(const bcv_mlp_s &net, const float *X, int B, Work &w, float *G, hi
     const float *P = net.d_params;
     const int W = net.width;
     // layer 3: Y = H2 W3 + b3
-    gemm(true, false, W, kMlpOut, B, w.H2.p, W, w.dY.p, kMlpOut, nullptr, false, G + l.w3, kMlpOut, nullptr, st);
-    column_sum(B, kMlpOut, w.dY.p, G + l.b3, st);
+    gemm_tn_split(W, kMlpOut, B, w.H2.p, W, w.dY.p, kMlpOut, G + l.w3, w.split.p, st);
+    column_sum(B, kMlpOut, w.dY.p, G + l.b3, w.split.p, st);
     gemm(false, true, B, W, kMlpOut, w.dY.p, kMlpOut, P + l.w3, kMlpOut, nullptr, false, w.dH.p, W, nullptr, st);
     silu_backward((int64_t)B * W, w.Z2.p, w.dH.p, w.dZ.p, st);
     // layer 2: Z2 = H1 W2 + b2
-    gemm(true, false, W, W, B, w.H1.p, W, w.dZ.p, W, nullptr, false, G + l.w2, W, nullptr, st);
-    column_sum(B, W, w.dZ.p, G + l.b2, st);
+    gemm_tn_split(W, W, B, w.H1.p, W, w.dZ.p, W, G + l.w2, w.split.p, st);
+    column_sum(B, W, w.dZ.p, G + l.b2, w.split.p, st);
     gemm(false, true, B, W, W, w.dZ.p, W, P + l.w2, W, nullptr, false, w.dH.p, W, nullptr, st);
     silu_backward((int64_t)B * W, w.Z1.p, w.dH.p, w.dZ.p, st);
     // layer 1: Z1 = X W1 + b1
-    gemm(true, false, net.d_in, W, B, X, net.d_in, w.dZ.p, W, nullptr, false, G + l.w1, W, nullptr, st);
-    column_sum(B, W, w.dZ.p, G + l.b1, st);
+    gemm_tn_split(net.d_in, W, B, X, net.d_in, w.dZ.p, W, G + l.w1, w.split.p, st);
+    column_sum(B, W, w.dZ.p, G + l.b1, w.split.p, st);
 }
 
 // Canonical geometry: A = [0,1]^3, B of side rho touching A's +x face / +x+y edge / +x+y+z vertex.
@@ -241,7 +243,7 @@ void mlp_forward_host(const bcv_mlp_s &net, int64_t n, const float *X, float *Y)
     if (n == 0) return;
     BCV_REQUIRE(n <= INT32_MAX, BCV_EINVAL, "batch too large");
     DevBuf<float> dX((size_t)n * net.d_in);
-    Work w((int)n, net.width);
+    Work w((int)n, net.width, net.d_in);
     BCV_HIP(hipMemcpy(dX.p, X, (size_t)n * net.d_in * sizeof(float), hipMemcpyHostToDevice));
     forward(net, dX.p, (int)n, w, nullptr);
     BCV_HIP(hipMemcpy(Y, w.Y.p, (size_t)n * kMlpOut * sizeof(float), hipMemcpyDeviceToHost));
@@ -252,7 +254,7 @@ double mlp_loss_grad_host(const bcv_mlp_s &net, int64_t n, const float *X, const
     BCV_REQUIRE(n > 0 && n <= INT32_MAX, BCV_EINVAL, "batch size must be 1..2^31-1");
     const int B = (int)n;
     DevBuf<float> dX((size_t)B * net.d_in), dr(B);
-    Work w(B, net.width);
+    Work w(B, net.width, net.d_in);
     BCV_HIP(hipMemcpy(dX.p, X, (size_t)B * net.d_in * sizeof(float), hipMemcpyHostToDevice));
     BCV_HIP(hipMemcpy(dr.p, r, (size_t)B * sizeof(float), hipMemcpyHostToDevice));
     forward(net, dX.p, B, w, nullptr);
@@ -301,7 +303,7 @@ void mlp_train(bcv_mlp_s &net, const bcv_mlp_train_opts &o, bcv_mlp_train_report
     BCV_HIP(hipMemcpy(dX.p, X.data(), X.size() * sizeof(float), hipMemcpyHostToDevice));
     BCV_HIP(hipMemcpy(dR.p, R.data(), R.size() * sizeof(float), hipMemcpyHostToDevice));
     const int B = (int)std::min<int64_t>(o.batch, N);
-    Work w(B, net.width);
+    Work w(B, net.width, net.d_in);
     DevBuf<float> bX((size_t)B * net.d_in), bR(B);
     DevBuf<int32_t> bIdx(B);
     const int64_t n_par = mlp_n_params(net);
