@@ -52,16 +52,17 @@ def m2l_kernel_names(q, mixed):
     """The interaction-phase launches of one apply (see launch_m2l in kernels.hip)."""
     K = ncoef(q)
     if not mixed:
-        if K <= 84:
-            return ["m2l_kernel<%d, double, 0, %d>" % (q, K)]
-        S = ncoef(q - 3)
-        return ["m2l_kernel<%d, double, 0, %d>" % (q, S), "m2l_kernel<%d, double, %d, %d>" % (q, S, K)]
-    if q <= 6:
+        if q == 8:
+            S = ncoef(q - 3)
+            return ["m2l_kernel<%d, double, 0, %d>" % (q, S), "m2l_kernel<%d, double, %d, %d>" % (q, S, K)]
+        blocks = [(0, K, 0, 4), (0, 10, 4, K)] if q == 4 else [(0, 35, 0, 10), (35, K, 0, 4), (0, 20, 10, 35),
+                                                              (0, 4, 35, K)]
+    elif q <= 6:
         S = ncoef(q // 2 - 1)
         blocks = [(0, K, 0, S), (0, ncoef(q - q // 2), S, K)]
     else:
         blocks = [(0, 84, 0, 10), (84, K, 0, 4), (0, 56, 10, 35), (0, 20, 35, 84), (0, 4, 84, K)]
-    return ["m2l_shift_kernel<%d, %d, %d, %d, %d>" % ((q,) + b) for b in blocks]
+    return ["m2l_shift_kernel<%d, %s, %d, %d, %d, %d>" % ((q, "float" if mixed else "double") + b) for b in blocks]
 
 
 def near_flops(info, q):
@@ -388,7 +389,7 @@ def main():
             "n_touching_pairs": info["n_touch"],
             "n_m2l_pairs": info["n_m2l"],
             "m2l_lane_efficiency": info["n_m2l"] / max(info["n_m2l_lanes"], 1),
-            "m2l_gather_fraction": info["n_m2l_gather_lanes"] / max(info["n_m2l_lanes"], 1),
+            "m2l_read_fraction": info["n_m2l_read_lanes"] / max(info["n_m2l_lanes"], 1),
             "tree_seconds": tree_s,
             "plan_seconds": h["plan_s"],
             "plan_device_bytes": h["info"]["device_bytes"],

@@ -104,8 +104,9 @@ typedef struct {
     int64_t n_m2l;        /* ordered interaction-list pairs (cells), all levels */
     int64_t n_m2l_lanes;  /* lane-pairs the interaction kernel executes (>= n_m2l; padding) */
     int64_t n_offsets;    /* distinct integer interaction offsets (derivative tables) */
-    int64_t n_m2l_gather_lanes; /* of n_m2l_lanes, those whose source moments the mixed-precision
-                                 * kernels read from memory; the rest arrive by a lane shift */
+    int64_t n_m2l_read_lanes; /* of n_m2l_lanes, those whose source moments the lane-shifting
+                               * interaction kernels (FP32; FP64 up to q = 6) read from memory;
+                               * the rest arrive by a lane shift */
     int64_t device_bytes; /* device memory held by the plan */
     int32_t K;            /* expansion coefficients per cell, (q+1)(q+2)(q+3)/6 */
     int32_t L;

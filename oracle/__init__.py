@@ -15,6 +15,9 @@ Contents (each function cites the passage of the paper it follows):
                phase, downward pass, evaluation) in FP64.
   mlp.py       the touching-pair surrogate's network in FP64: forward pass, training loss and its
                gradient by the chain rule (reference for the GPU kernels' gradients).
+  boundary.py  BtV (Algorithm 3): single- and double-layer entries of (leaf, boundary face) pairs
+               (exact by convolution where they touch, point rule elsewhere), O1 by direct
+               summation and O2 step by step.
 
 Readings of the paper used here (all for the cube-octree form of the method):
   * marking rule: M_l = B_l (cells with a face on the boundary), l < L;

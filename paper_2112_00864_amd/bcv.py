@@ -38,7 +38,7 @@ class PlanOpts(ctypes.Structure):
 
 class PlanInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("n_leaves", "n_cells", "n_near", "n_touch", "n_m2l", "n_m2l_lanes",
-                                              "n_offsets", "n_m2l_gather_lanes", "device_bytes")] + [
+                                              "n_offsets", "n_m2l_read_lanes", "device_bytes")] + [
         ("K", ctypes.c_int32), ("L", ctypes.c_int32), ("surrogate_classes", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 

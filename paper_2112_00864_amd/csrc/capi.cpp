@@ -205,7 +205,7 @@ bcv_status bcv_plan_get_info(bcv_plan plan, bcv_plan_info *info)
         info->n_m2l = plan->n_m2l;
         info->n_m2l_lanes = plan->n_m2l_lanes;
         info->n_offsets = plan->n_offsets;
-        info->n_m2l_gather_lanes = plan->n_m2l_gather_lanes;
+        info->n_m2l_read_lanes = plan->n_m2l_read_lanes;
         info->device_bytes = plan->device_bytes;
         info->K = plan->K;
         info->L = plan->L;

@@ -109,7 +109,7 @@ struct bcv_plan_s {
     int L = 0, q = 0, K = 0;
     int direct = 0, nearfield = 0, precision = 0;
     int64_t n_leaves = 0, n_cells = 0, n_near = 0, n_touch = 0, n_m2l = 0, n_m2l_lanes = 0, n_offsets = 0,
-            n_m2l_gather_lanes = 0;
+            n_m2l_read_lanes = 0;
     int64_t device_bytes = 0;
     double touch_value[bcv::kTouchClasses];  // touching integrals / (4 pi), smaller side 1
     int surrogate_classes = 0;               // classes whose value came from the surrogate

@@ -350,10 +350,15 @@ __device__ __forceinline__ void m2l_block_reg(T *acc, const T *__restrict__ G, c
     (m2l_beta_reg<Q, A0, A1, B0 + Bs>(acc, G, m[Bs]), ...);
 }
 
-// Lane l takes lane l - 1's value; lane 0 keeps its own (DPP wave shift right by one lane).
-__device__ __forceinline__ float shift_up(float v)
+// Lane l takes lane l - 1's value; lane 0 keeps its own (DPP wave shift right by one lane; a double
+// moves as its two 32-bit halves).
+__device__ __forceinline__ int shift_up_b32(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ float shift_up(float v) { return __int_as_float(shift_up_b32(__float_as_int(v))); }
+__device__ __forceinline__ double shift_up(double v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x138, 0xf, 0xf, false));
+    const int64_t b = __double_as_longlong(v);
+    const int lo = shift_up_b32((int)(uint32_t)b), hi = shift_up_b32((int)(b >> 32));
+    return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
 }
 
 // Workgroups are dealt to the 8 XCDs round-robin (workgroup b runs on XCD b mod 8). XCD x runs
@@ -369,10 +374,10 @@ __device__ __forceinline__ int xcd_task(const XcdRanges &r)
     return t < r.begin[x + 1] ? t : -1;
 }
 
-// FP64 interaction kernel: every slot gathers the 64 lanes' source rows (the zero row where the
-// offset is outside a lane's list; slot words: source row | (offset in the lane's list) << 31).
-// The wave accumulates Lambda^a for a in [A0, A1): all of them when the accumulators fit the
-// register budget of two waves per SIMD, else the range is split over launches (q = 8).
+// Gathering interaction kernel (FP64 at q = 8): every slot gathers the 64 lanes' source rows (the
+// zero row where the offset is outside a lane's list; slot words: source row | (offset in the
+// lane's list) << 31). The wave accumulates Lambda^a for a in [A0, A1), a range that fits the
+// register budget of two waves per SIMD.
 template <int Q, class T, int A0, int A1>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2, 2))) void m2l_kernel(
     XcdRanges ranges, const M2LTask *__restrict__ tasks, const int32_t *__restrict__ targets,
@@ -418,7 +423,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2, 2))) v
     }
 }
 
-// FP32 interaction kernel with lane shifts. The plan lays a task's targets along rows (lane l + 1
+// Interaction kernel with lane shifts (FP32, and FP64 up to q = 6). The plan lays a task's targets along rows (lane l + 1
 // two cells after lane l, except at the task's head lanes) and orders its slots so that
 // consecutive offsets step by two cells along the same axis: at a slot without the gather bit
 // every lane's new source is the previous slot's source of the lane below, so the source moments
@@ -430,11 +435,11 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2, 2))) v
 // 128 registers, four waves per SIMD (the latency of the row reads at the start of each slot is
 // covered by the other waves). The block with B0 = 0 writes Lambda^a, the others add to it and are
 // launched after it.
-template <int Q, int A0, int A1, int B0, int B1>
+template <int Q, class T, int A0, int A1, int B0, int B1>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4, 4))) void m2l_shift_kernel(
     XcdRanges ranges, const M2LTask *__restrict__ tasks, const int32_t *__restrict__ targets,
-    const int32_t *__restrict__ slot_off, const uint32_t *__restrict__ slot_src, const float *__restrict__ G,
-    const float *__restrict__ M, double *__restrict__ partial, double *__restrict__ Lam)
+    const int32_t *__restrict__ slot_off, const uint32_t *__restrict__ slot_src, const T *__restrict__ G,
+    const T *__restrict__ M, double *__restrict__ partial, double *__restrict__ Lam)
 {
     constexpr int K = MultiIndex<Q>::K, NA = A1 - A0, NB = B1 - B0;
     const int ti = xcd_task(ranges);
@@ -444,9 +449,9 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4, 4))) v
     const bool head = ((task.heads >> lane) & 1ull) != 0ull;
     const int n = task.n_slots;
     const int64_t s0 = task.slot_begin;
-    float acc[NA], m[NB];
+    T acc[NA], m[NB];
 #pragma unroll
-    for (int a = 0; a < NA; ++a) acc[a] = 0.0f;
+    for (int a = 0; a < NA; ++a) acc[a] = T(0);
     if (n > 0) {
         int32_t ow = slot_off[s0], ow1 = 0;
         uint32_t w = slot_src[s0 * kWave + lane], w1 = 0;
@@ -461,7 +466,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4, 4))) v
                 ow2 = slot_off[s0 + j + 2];
                 w2 = slot_src[(s0 + j + 2) * kWave + lane];
             }
-            const float *__restrict__ Ms = M + (int64_t)(w & 0x7FFFFFFFu) * K + B0;
+            const T *__restrict__ Ms = M + (int64_t)(w & 0x7FFFFFFFu) * K + B0;
             if (ow < 0 || j == 0) {  // gather the sources of all lanes
 #pragma unroll
                 for (int b = 0; b < NB; ++b) m[b] = Ms[b];
@@ -776,32 +781,36 @@ void launch_near(const bcv_plan_s &p, const double *f, const double *lam, int pa
         check_launch();
     }
 }
-template <int Q, int A0, int A1, int B0, int B1>
-void launch_m2l_block(const bcv_plan_s &p, const XcdRanges &ranges, const float *G, const float *M, hipStream_t st)
+template <int Q, int A0, int A1, int B0, int B1, class T>
+void launch_m2l_block(const bcv_plan_s &p, const XcdRanges &ranges, const T *G, const T *M, hipStream_t st)
 {
-    m2l_shift_kernel<Q, A0, A1, B0, B1><<<(unsigned)p.m2l_groups, kWave, 0, st>>>(
+    m2l_shift_kernel<Q, T, A0, A1, B0, B1><<<(unsigned)p.m2l_groups, kWave, 0, st>>>(
         ranges, p.d_tasks, p.d_task_targets, p.d_slot_off, p.d_slot_src, G, M, p.d_m2l_partial, p.d_Lam);
     check_launch();
 }
 
-// Interaction phase over all tasks. FP64: one gathering launch holds all K accumulators up to
-// q = 6; at q = 8 (K = 165) the coefficient range is split in two launches, |a| <= 5 and
-// 6 <= |a| <= 8, to stay within the register budget of two waves per SIMD. FP32: lane-shifting
-// launches over blocks of the (a, b) triangle, split by degree (n(d) = number of multi-indices of
-// degree <= d) so that every block fits four waves per SIMD; the blocks that write come first.
+// Interaction phase over all tasks: lane-shifting launches over blocks of the (a, b) triangle, split
+// by degree (n(d) = number of multi-indices of degree <= d) so that every block fits four waves per
+// SIMD; the blocks that write come first. FP64 at q = 8 (K = 165) gathers instead, in two launches
+// over the coefficient range (|a| <= 5, then 6 <= |a| <= 8) at two waves per SIMD.
 template <int Q>
 void launch_m2l(const bcv_plan_s &p, const double *G, const double *M, hipStream_t st)
 {
     constexpr int K = MultiIndex<Q>::K;
     XcdRanges ranges;
     for (int x = 0; x <= kXcds; ++x) ranges.begin[x] = p.xcd_begin[x];
-    const unsigned groups = (unsigned)p.m2l_groups;
-    const int32_t zero_row = (int32_t)p.n_cells;
-    if constexpr (K <= 84) {
-        m2l_kernel<Q, double, 0, K><<<groups, kWave, 0, st>>>(ranges, p.d_tasks, p.d_task_targets, p.d_slot_off,
-                                                              p.d_slot_src, G, M, zero_row, p.d_m2l_partial, p.d_Lam);
-        check_launch();
+    if constexpr (Q == 4) {
+        launch_m2l_block<Q, 0, K, 0, 4>(p, ranges, G, M, st);    // all a, |b| <= 1
+        launch_m2l_block<Q, 0, 10, 4, K>(p, ranges, G, M, st);   // |a| <= 2, |b| >= 2
+    } else if constexpr (Q == 6) {
+        launch_m2l_block<Q, 0, 35, 0, 10>(p, ranges, G, M, st);  // |a| <= 4, |b| <= 2
+        launch_m2l_block<Q, 35, K, 0, 4>(p, ranges, G, M, st);   // |a| >= 5, |b| <= 1
+        launch_m2l_block<Q, 0, 20, 10, 35>(p, ranges, G, M, st); // |a| <= 3, 3 <= |b| <= 4
+        launch_m2l_block<Q, 0, 4, 35, K>(p, ranges, G, M, st);   // |a| <= 1, |b| >= 5
     } else {
+        static_assert(Q == 8, "orders 4, 6, 8");
+        const unsigned groups = (unsigned)p.m2l_groups;
+        const int32_t zero_row = (int32_t)p.n_cells;
         constexpr int S = ncoef(Q - 3);
         m2l_kernel<Q, double, 0, S><<<groups, kWave, 0, st>>>(ranges, p.d_tasks, p.d_task_targets, p.d_slot_off,
                                                               p.d_slot_src, G, M, zero_row, p.d_m2l_partial, p.d_Lam);

@@ -1,8 +1,10 @@
 """Seeded synthetic inputs for volume-potential runs on boundary-concentrated cube meshes.
 
-This module generates densities only. It holds no part of the volume-potential method:
-no Green's function, no quadrature of cell pairs, no expansions. Both the CPU oracle and
-the GPU library receive the densities it produces, keyed by each leaf's (level, i, j, k).
+This module generates input data only: volume densities on leaves, and boundary data on the
+boundary faces. It holds no part of the potential method: no quadrature of cell or face
+pairs, no expansions, no translation operators. Both the CPU oracle and the GPU library
+receive the data it produces, keyed by each leaf's (level, i, j, k) and each face's
+(level, i, j, k, axis, side).
 
 Density recipe (piecewise constant on leaves):
   f(x) = sum_k exp(-|x - c_k|^2 / (2 sigma_k^2)), k = 1..4,
@@ -20,6 +22,9 @@ __all__ = [
     "leaf_density",
     "ball_indicator",
     "constant_one",
+    "harmonic_params",
+    "harmonic",
+    "face_data",
 ]
 
 
@@ -87,3 +92,59 @@ def leaf_density(level_ijk, seed=0, n=2):
     """Seeded Gaussian-mixture density projected to piecewise constants on the given leaves."""
     centres, widths = gaussian_mixture_params(seed)
     return cell_average(level_ijk, lambda x: gaussian_mixture(x, centres, widths), n=n)
+
+
+# -- boundary data: traces of a harmonic function -------------------------------------------------
+#
+# u(x) = sum_k c_k / |x - p_k|, k = 1..4, with c_k ~ U[0.5, 1.5] and p_k = (1/2, 1/2, 1/2) + R_k d_k,
+# d_k uniform on the unit sphere (normalised standard normal), R_k ~ U[1.0, 1.6] (outside the unit
+# cube), drawn from numpy.random.default_rng(seed) in the order c, then d, then R. u is harmonic
+# in the cube. A boundary face (level, i, j, k, axis, side) is the face of that cube normal to
+# `axis` at its low (side 0) or high (side 1) end, outward normal (2 side - 1) e_axis; its data are
+# the face averages (n x n Gauss-Legendre) of the Dirichlet trace g = u and of the Neumann trace
+# q = du/dn.
+
+
+def harmonic_params(seed, n_terms=4):
+    rng = np.random.default_rng(seed)
+    charges = rng.uniform(0.5, 1.5, size=n_terms)
+    d = rng.standard_normal(size=(n_terms, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    radii = rng.uniform(1.0, 1.6, size=n_terms)
+    return charges, 0.5 + radii[:, None] * d
+
+
+def harmonic(x, charges, poles, grad=False):
+    """u(x) (and its gradient if grad) at points x of shape (..., 3)."""
+    x = np.asarray(x, dtype=np.float64)
+    u = np.zeros(x.shape[:-1])
+    g = np.zeros(x.shape)
+    for c, p in zip(charges, poles):
+        d = x - p
+        r = np.sqrt(np.sum(d * d, axis=-1))
+        u += c / r
+        g -= c * d / r[..., None] ** 3
+    return (u, g) if grad else u
+
+
+def face_data(faces, seed=0, n=4):
+    """Face averages (q, g) of du/dn and u on faces given as an int array (N, 6) of
+    (level, i, j, k, axis, side)."""
+    charges, poles = harmonic_params(seed)
+    f = np.asarray(faces, dtype=np.int64).reshape(-1, 6)
+    t, w = _gauss_legendre_unit(n)
+    s_, t_ = np.meshgrid(t, t, indexing="ij")
+    ww = np.outer(w, w).ravel()
+    a = np.ldexp(1.0, -f[:, 0])
+    lo = f[:, 1:4] * a[:, None]
+    ax, side = f[:, 4], f[:, 5]
+    pts = np.repeat(lo[:, None, :], n * n, axis=1)
+    rows = np.arange(len(f))
+    o1, o2 = (ax + 1) % 3, (ax + 2) % 3
+    pts[rows, :, ax] += (side * a)[:, None]
+    pts[rows, :, o1] += a[:, None] * s_.ravel()[None, :]
+    pts[rows, :, o2] += a[:, None] * t_.ravel()[None, :]
+    u, grad = harmonic(pts, charges, poles, grad=True)
+    sign = 2.0 * side - 1.0
+    dudn = sign[:, None] * grad[rows[:, None], np.arange(n * n)[None, :], ax[:, None]]
+    return dudn @ ww, u @ ww

@@ -1,0 +1,149 @@
+"""Pins of the BtV oracle (boundary-to-volume potentials, Algorithm 3)."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import boundary as B
+from oracle import touching
+from oracle.mesh import BCMesh
+
+
+def box_faces(lo, hi):
+    """The six faces of the box [lo, hi] with outward normals: (flo, fhi, axis, sign)."""
+    out = []
+    for ax in range(3):
+        for side in (0, 1):
+            flo, fhi = np.array(lo, float), np.array(hi, float)
+            flo[ax] = fhi[ax] = hi[ax] if side else lo[ax]
+            out.append((flo, fhi, ax, 2.0 * side - 1.0))
+    return out
+
+
+@pytest.mark.parametrize("wlo,whi,inside", [
+    ((0.25, 0.25, 0.25), (0.5, 0.5, 0.5), True),   # interior cell
+    ((0.0, 0.0, 0.0), (0.25, 0.25, 0.25), True),   # corner cell: touches three faces
+    ((0.5, 0.0, 0.25), (0.75, 0.25, 0.5), True),   # touches one face
+    ((1.0, 0.25, 0.25), (1.25, 0.5, 0.5), False),  # outside, touching a face
+    ((-0.5, 1.0, 1.0), (0.0, 1.5, 1.5), False),    # outside, touching a corner only
+])
+def test_double_layer_gauss_law(wlo, whi, inside):
+    """Gauss: the double layer of density 1 on a closed surface is -1 inside and 0 outside, so the
+    exact double-layer entries of a cell against the six faces of the unit cube sum to -|w| or 0
+    (the touching ones go through the Duffy branch)."""
+    tot = sum(B.cell_face_integral(wlo, whi, flo, fhi, ax, sg, "double") for flo, fhi, ax, sg in box_faces(
+        (0, 0, 0), (1, 1, 1)))
+    vol = np.prod(np.subtract(whi, wlo))
+    assert abs(tot - (-vol if inside else 0.0)) <= 1e-13 * vol
+
+
+def _slab_limit(wlo, whi, flo, fhi, ax, side):
+    """V by an independent route: the volume integral of oracle.touching over a slab of thickness t
+    on the face, divided by t, Richardson-extrapolated over t = 1e-2, 5e-3, 2.5e-3."""
+    vals = []
+    for t in (1e-2, 5e-3, 2.5e-3):
+        blo, bhi = np.array(flo, float), np.array(fhi, float)
+        if side == 1:
+            blo[ax] -= t
+        else:
+            bhi[ax] += t
+        vals.append(touching.box_pair_integral(wlo, whi, blo, bhi, n=30) / t / (4 * np.pi))
+    r1, r2 = 2 * vals[1] - vals[0], 2 * vals[2] - vals[1]
+    return (4 * r2 - r1) / 3
+
+
+@pytest.mark.parametrize("case,tol", [
+    (((0, 0, 0), (1, 1, 1), (0, 0, 0), (1, 1, 0), 2, 0), 2e-6),  # the cell's own face
+    (((0, 0, 0), (1, 1, 1), (1, 0, 0), (2, 1, 0), 2, 0), 2e-7),  # coplanar, sharing an edge
+    (((0, 0, 0), (1, 1, 1), (1, 1, 0), (2, 2, 0), 2, 0), 2e-8),  # coplanar, sharing a vertex
+    (((0, 0, 1), (1, 1, 2), (0, 0, 0), (1, 1, 0), 2, 0), 2e-8),  # one cell apart
+    (((0, 0, 0), (2, 2, 2), (2, 0, 0), (2, 1, 1), 0, 1), 2e-6),  # a small face on a big cell
+])
+def test_single_layer_against_slab_limit(case, tol):
+    wlo, whi, flo, fhi, ax, side = case
+    v = B.cell_face_integral(wlo, whi, flo, fhi, ax, 2.0 * side - 1.0, "single")
+    assert abs(v - _slab_limit(wlo, whi, flo, fhi, ax, side)) <= tol * abs(v)
+
+
+def test_point_rule_tends_to_exact_with_distance():
+    """The 2x2x2 x 2x2 point rule approaches the exact entries as the pair separates."""
+    errs = []
+    for d in (2.0, 4.0, 8.0):
+        wlo, whi = np.array([0.0, 0.0, d]), np.array([1.0, 1.0, d + 1.0])
+        flo, fhi = B.face_box(np.zeros(3), 1.0, 2, 1)
+        V = B.cell_face_integral(wlo, whi, flo, fhi, 2, 1.0, "single")
+        K = B.cell_face_integral(wlo, whi, flo, fhi, 2, 1.0, "double")
+        Vp, Kp = B.point_rule(wlo, 1.0, np.zeros(3), 1.0, 2, 1)
+        errs.append(max(abs(Vp - V) / V, abs(Kp - K) / abs(K)))
+    assert errs[0] > errs[1] > errs[2] and errs[0] < 2e-2 and errs[2] < 2e-4
+
+
+def test_homogeneity():
+    """V scales as length^4 and K as length^3 (both kernels are homogeneous)."""
+    args = ((0, 0, 0), (1, 1, 1), (1, 0, 0), (2, 1, 0), 2, -1.0)
+    big = ((0, 0, 0), (2, 2, 2), (2, 0, 0), (4, 2, 0), 2, -1.0)
+    for kind, p in (("single", 4), ("double", 3)):
+        a = B.cell_face_integral(*args, kind)
+        b = B.cell_face_integral(*big, kind)
+        assert abs(b - 2 ** p * a) <= 1e-12 * abs(b)
+
+
+@pytest.fixture(scope="module")
+def mesh2():
+    m = BCMesh(2)
+    faces = B.boundary_faces(m)
+    lv = m.leaf_array()
+    fk = np.column_stack([lv[faces[:, 0]], faces[:, 1:]])
+    qf, gf = synth.face_data(fk, seed=0)
+    return m, faces, qf, gf, B.apply_direct(m, qf, gf)
+
+
+def test_boundary_faces_cover_gamma():
+    for L in (2, 3):
+        m = BCMesh(L)
+        faces = B.boundary_faces(m)
+        assert len(faces) == 6 * 4 ** L
+        assert np.all(m.leaf_array()[faces[:, 0], 0] == L)
+
+
+def test_exact_cover():
+    """Every (leaf, face) pair is near (the face's cell has an ancestor at the leaf's level among
+    the leaf's neighbours) or far at exactly one level (ancestors in each other's interaction
+    lists, the source a boundary cell)."""
+    m = BCMesh(3)
+    F = B.BtVFMM(m, 2)
+    lv = F.leaves
+    for t in range(0, len(lv), 23):
+        lev, i, j, k = lv[t]
+        near = set(F.near_faces(t))
+        for f, (leaf, ax, side) in enumerate(F.faces):
+            _, fi, fj, fk = lv[leaf]
+            hits = 0
+            for l in range(1, lev + 1):
+                tc = (i >> (lev - l), j >> (lev - l), k >> (lev - l))
+                sc = (fi >> (m.L - l), fj >> (m.L - l), fk >> (m.L - l))
+                if sc in m.interaction_list(l, tc):
+                    assert m.on_boundary(l, sc)
+                    hits += 1
+            assert hits + (f in near) == 1
+
+
+def test_o2_converges_to_o1(mesh2):
+    """O2 - O1 decreases geometrically in q (stated: about 4e-5, 8e-6, 4e-7 for q = 4, 6, 8 at L = 2)."""
+    m, faces, qf, gf, u1 = mesh2
+    errs = [np.linalg.norm(B.BtVFMM(m, q).apply(qf, gf) - u1) / np.linalg.norm(u1) for q in (4, 6, 8)]
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[0] < 1e-4 and errs[2] < 1e-6
+
+
+def test_representation_formula(mesh2):
+    """Green's representation formula: for harmonic u, V[du/dn] - K[u] = u in the cube. With face
+    averages as data and cell averages as output, the BtV result matches the cell averages of u to
+    discretisation accuracy (stated: 1.8e-3 relative at L = 2, 6.9e-4 at L = 3)."""
+    m, faces, qf, gf, u1 = mesh2
+    lv = m.leaf_array()
+    charges, poles = synth.harmonic_params(0)
+    avg = synth.cell_average(lv, lambda x: synth.harmonic(x, charges, poles), n=4)
+    vol = np.ldexp(1.0, -3 * lv[:, 0].astype(np.int32))
+    err = np.linalg.norm(u1 / vol - avg) / np.linalg.norm(avg)
+    assert err < 5e-3
