@@ -55,14 +55,17 @@ def m2l_kernel_names(q, mixed):
         if q == 8:
             S = ncoef(q - 3)
             return ["m2l_kernel<%d, double, 0, %d>" % (q, S), "m2l_kernel<%d, double, %d, %d>" % (q, S, K)]
-        blocks = [(0, K, 0, 4), (0, 10, 4, K)] if q == 4 else [(0, 35, 0, 10), (35, K, 0, 4), (0, 20, 10, 35),
-                                                              (0, 4, 35, K)]
+        blocks = [(0, K, 0, 4), (0, 10, 4, K)] if q == 4 else [(0, 35, 0, 10), (35, K, 0, 4), (0, 20, 10, K)]
     elif q <= 6:
         S = ncoef(q // 2 - 1)
         blocks = [(0, K, 0, S), (0, ncoef(q - q // 2), S, K)]
     else:
         blocks = [(0, 84, 0, 10), (84, K, 0, 4), (0, 56, 10, 35), (0, 20, 35, 84), (0, 4, 84, K)]
-    return ["m2l_shift_kernel<%d, %s, %d, %d, %d, %d>" % ((q, "float" if mixed else "double") + b) for b in blocks]
+    def waves(b):  # as launch_m2l_block: two waves per SIMD where the block's registers exceed 110
+        return 2 if (b[1] - b[0] + b[3] - b[2]) * (1 if mixed else 2) > 110 else 4
+
+    return ["m2l_shift_kernel<%d, %s, %d, %d, %d, %d, %d>" % ((q, "float" if mixed else "double") + b + (waves(b),))
+            for b in blocks]
 
 
 def near_flops(info, q):
@@ -189,6 +192,52 @@ def roofline(info, phase_avg, args, prec):
     return dominant, {"m2l_kernel": m2l_roof, "near_eval_kernel": near_roof}
 
 
+def measure_btv(bcv, torch, tree, args, dev):
+    """BtV (Algorithm 3) on the same mesh: FP64 and mixed plans with boundary structures, seeded
+    face data (traces of a harmonic function), `args.steps` timed applies after `args.warmup`."""
+    import synth
+
+    lv = tree.leaves().astype(np.int64)
+    faces = tree.faces().astype(np.int64)
+    fk = np.column_stack([lv[faces[:, 0]], faces[:, 1:]])
+    qf, gf = synth.face_data(fk, seed=0)
+    q = torch.tensor(qf, device="cuda:%d" % dev)
+    g = torch.tensor(gf, device="cuda:%d" % dev)
+    out = {}
+    for prec in ("fp64", "mixed"):
+        t0 = time.perf_counter()
+        plan = bcv.plan_interactions(tree, q=args.q, device=dev, streams=1, boundary=True,
+                                     precision=bcv.MIXED_F32 if prec == "mixed" else bcv.FP64)
+        plan_s = time.perf_counter() - t0
+        u = torch.empty(plan.n_leaves, dtype=torch.float64, device="cuda:%d" % dev)
+        for _ in range(args.warmup):
+            bcv.btv_apply(plan, q, g, u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            bcv.btv_apply(plan, q, g, u)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / args.steps
+        out[prec] = {"ms_per_apply": ms, "value": plan.n_leaves / (ms * 1e-3), "plan_seconds": plan_s,
+                     "u": u.cpu().numpy()}
+        info = plan.info
+        del plan
+    vol = np.ldexp(1.0, -3 * lv[:, 0].astype(np.int32))
+    a, b = out["mixed"]["u"], out["fp64"]["u"]
+    rel = float(np.sqrt(np.sum(vol * ((a - b) / vol) ** 2) / np.sum(vol * (b / vol) ** 2)))
+    charges, poles = synth.harmonic_params(0)
+    avg = synth.cell_average(lv, lambda x: synth.harmonic(x, charges, poles), n=4)
+    rep = float(np.linalg.norm(b / vol - avg) / np.linalg.norm(avg))
+    for prec in out:
+        del out[prec]["u"]
+    return {"metric": "BtV cell-potentials/s (Algorithm 3, u = <1_w, V[q] - K[g]>), 1 GPU",
+            "unit": "cell-potentials/s", "n_faces": info["n_faces"], "n_btv_near_pairs": info["n_btv_near"],
+            "n_btv_touching_pairs": info["n_btv_touch"], "fp64": out["fp64"], "mixed": out["mixed"],
+            "mixed_vs_fp64_rel_l2": rel, "representation_formula_rel_err": rep,
+            "data": "synthetic: face averages of u = sum_k c_k/|x - p_k| (4 poles outside the cube, seed 0) and "
+                    "of du/dn; the representation formula gives u in the cube"}
+
+
 def batched(args):
     """64 unit-cube BC meshes, h drawn from {1/16, 1/32, 1/64} (default_rng(1234)), Gaussian-mixture
     density of seed m on mesh m, mixed precision (FP32 interaction phase): one forest plan with the
@@ -285,6 +334,7 @@ def main():
     ap.add_argument("--cpu-targets", type=int, default=4000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="mixed path without the touching-pair surrogate")
+    ap.add_argument("--no-btv", action="store_true", help="skip the BtV (Algorithm 3) measurement")
     ap.add_argument("--batched", action="store_true",
                     help="the batched workload: 64 meshes in one forest plan and one graph launch")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -409,6 +459,11 @@ def main():
     if surrogate is not None:
         line["surrogate"] = {"classes_from_network": runs["mixed"]["info"]["surrogate_classes"], "of": 6,
                              "tol": SURROGATE_TOL, "training": sur_report}
+    if not args.no_btv:
+        line["btv"] = measure_btv(bcv, torch, tree, args, dev)
+        print("btv: %s" % json.dumps({k: line["btv"][k] for k in ("fp64", "mixed", "mixed_vs_fp64_rel_l2",
+                                                                  "representation_formula_rel_err")}),
+              file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
 
 

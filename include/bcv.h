@@ -93,6 +93,9 @@ typedef struct {
     int m2l_max_slots;     /* longest slot list of one interaction task; longer lists are cut into
                               pieces whose partial sums are added in a fixed order (0 = 256;
                               else 16..65536) */
+    int boundary;          /* 1: also build the BtV structures (boundary faces, their near lists
+                              and touching integrals) so that bcv_btv_apply can run; single-mesh
+                              trees only. 0: VtV only */
 } bcv_plan_opts;
 
 /* Sizes of a plan (all counts, no pointers). */
@@ -107,6 +110,9 @@ typedef struct {
     int64_t n_m2l_read_lanes; /* of n_m2l_lanes, those whose source moments the lane-shifting
                                * interaction kernels (FP32; FP64 up to q = 6) read from memory;
                                * the rest arrive by a lane shift */
+    int64_t n_faces;      /* boundary faces (plans built with opts.boundary; else 0) */
+    int64_t n_btv_near;   /* BtV near (leaf, face) pairs */
+    int64_t n_btv_touch;  /* of which the closed cell and face meet (exact integrals) */
     int64_t device_bytes; /* device memory held by the plan */
     int32_t K;            /* expansion coefficients per cell, (q+1)(q+2)(q+3)/6 */
     int32_t L;
@@ -205,11 +211,46 @@ void bcv_graph_destroy(bcv_graph graph);
 bcv_status bcv_autotune(bcv_tree tree, const bcv_plan_opts *base, int device, int n_applies, bcv_plan_opts *best,
                         double *best_ms);
 
-/* Volume-to-boundary (Algorithm 2) and boundary-to-volume (Algorithm 3) applies on the same
- * tree. Not implemented in this build: both return BCV_ENOTSUP. */
-bcv_status bcv_vtb_apply(bcv_plan plan, const double *f_dev, double *u_face_dev, void *hip_stream);
+/* Boundary faces of a single-mesh tree (BtV data lives on them): the faces of level-L leaves in
+ * the planes x, y, z = 0 or 1 of the unit cube (every cell meeting the boundary has a face on it
+ * and is refined down to level L). Face f is (leaf, axis, side): the leaf's face normal to `axis`
+ * at its low (side 0) or high (side 1) end, outward normal (2 side - 1) e_axis. Order: by leaf,
+ * then axis, then side. leaf_axis_side: host, n_faces x 3 int32.
+ * Errors: BCV_EINVAL (NULL), BCV_ENOTSUP (a forest of several meshes). */
+bcv_status bcv_tree_num_faces(bcv_tree tree, int64_t *n_faces);
+bcv_status bcv_tree_faces(bcv_tree tree, int32_t *leaf_axis_side);
+
+/* Boundary-to-volume apply, Algorithm 3 (BC-FMM for the BtV calculation), degree p = 0:
+ *   u_w = <1_w, V[q] - K[g]>_{L2(w)} for every leaf w,
+ *   V[q](x) = int_Gamma G(x - y) q(y) dS_y,  K[g](x) = int_Gamma dG(x - y)/dn_y g(y) dS_y,
+ * G = 1/(4 pi |x - y|), Gamma the boundary of the unit cube, n its outward normal, q and g
+ * constant on each boundary face (Sec. 1: for harmonic u, q = du/dn and g = u give u in the cube
+ * by Green's representation formula).
+ *   q_face_dev, g_face_dev: device, n_faces doubles each, in bcv_tree_faces order;
+ *   u_dev: device, n_leaves doubles in leaf order, OVERWRITTEN.
+ * Near pairs (the face's cell has an ancestor at the leaf's level among the leaf's neighbours)
+ * use the exact integrals of bcv_boundary_touching_integrals where the closed cell and face meet
+ * and the 2x2x2 x 2x2 point rule otherwise (FP32 kernel evaluations in BCV_MIXED_F32); the rest
+ * goes through boundary moments (2x2 point rule per face), the upward pass, the interaction phase,
+ * the downward pass and the evaluation phase of the plan. The plan must have been built with
+ * opts.boundary = 1. Stream-ordered on hip_stream only (streams = 2 plays no part), asynchronous,
+ * allocates nothing. Overwrites the plan's moment and local-coefficient workspace: do not run it
+ * concurrently with another apply of the same plan.
+ * Errors: BCV_EINVAL (NULL pointers), BCV_ESTATE (plan without boundary structures), BCV_EDEVICE. */
 bcv_status bcv_btv_apply(bcv_plan plan, const double *q_face_dev, const double *g_face_dev, double *u_dev,
                          void *hip_stream);
+
+/* Volume-to-boundary apply (Algorithm 2). Not implemented in this build: returns BCV_ENOTSUP. */
+bcv_status bcv_vtb_apply(bcv_plan plan, const double *f_dev, double *u_face_dev, void *hip_stream);
+
+/* The exact single- and double-layer integrals of touching (cell, boundary face) pairs of side 1:
+ * V[c] = int_cube int_face G dS dx and K[c] = int_cube int_face dG/dn_y dS dx for the unit cube
+ * [0,1]^3 and the face normal to `axis` at the low (side 0) or high (side 1) end of the unit cube
+ * at integer offset o in {-1, 0, 1}^3, class c = (((axis 3 + o0 + 1) 3 + o1 + 1) 3 + o2 + 1) 2 + side
+ * (162 classes; 0 where cell and face do not meet). Computed on the host once per process from the
+ * self-similarity of the pair (halving the cube and the face) with regular pairs integrated by a
+ * 5-D Gauss rule. V, K: host, 162 doubles each. Errors: BCV_EINVAL (NULL). */
+bcv_status bcv_boundary_touching_integrals(double *V, double *K);
 
 /* The seven exact touching-pair integrals int_A int_B 1/|x-y| the library uses for the singular
  * near-field entries (smaller side 1; order: self, face, edge, vertex, then face, edge, vertex

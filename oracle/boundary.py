@@ -268,6 +268,49 @@ def apply_direct(mesh, qf, gf, targets=None, n=24):
     return u
 
 
+def apply_direct_sampled(mesh, qf, gf, targets, n=24):
+    """O1 at the given target leaves only, with the point rule vectorised over all faces (same
+    entries as apply_direct)."""
+    E = Entries(mesh, n)
+    L = mesh.L
+    qf = np.asarray(qf, dtype=np.float64)
+    gf = np.asarray(gf, dtype=np.float64)
+    lv = E.leaves
+    fa = np.ldexp(1.0, -L)
+    fleaf = lv[E.faces[:, 0]]
+    flo = fleaf[:, 1:4] * fa
+    ax, side = E.faces[:, 1], E.faces[:, 2]
+    others = np.stack([(ax + 1) % 3, (ax + 2) % 3], axis=1)
+    # 2x2 face points (nf, 4, 3)
+    fp = np.repeat(flo[:, None, :], 4, axis=1)
+    rows = np.arange(len(flo))
+    fp[rows, :, ax] += (side * fa)[:, None]
+    for m, (i, j) in enumerate([(0, 0), (1, 0), (0, 1), (1, 1)]):
+        fp[rows, m, others[:, 0]] += fa * _XI[i]
+        fp[rows, m, others[:, 1]] += fa * _XI[j]
+    sign = 2.0 * side - 1.0
+    out = np.zeros(len(targets))
+    for m, t in enumerate(targets):
+        lev, i, j, k = lv[t]
+        a = np.ldexp(1.0, -int(lev))
+        xp, wx = cell_points(np.array([i, j, k]) * a, a)
+        d = xp[None, :, None, :] - fp[:, None, :, :]  # (nf, 8, 4, 3)
+        r = np.linalg.norm(d, axis=-1)
+        V = wx * fa * fa / 4.0 * np.sum(1.0 / r, axis=(1, 2)) / (4.0 * np.pi)
+        dn = np.take_along_axis(d, ax[:, None, None, None], axis=-1)[..., 0]
+        K = wx * fa * fa / 4.0 * sign * np.sum(dn / r ** 3, axis=(1, 2)) / (4.0 * np.pi)
+        if lev == L:  # touching pairs (closed cell and face meet): exact
+            lo_t = np.array([i, j, k], dtype=np.int64)
+            fl_int = fleaf[:, 1:4].astype(np.int64)
+            f_lo, f_hi = fl_int.copy(), fl_int + 1
+            f_lo[rows, ax] = f_hi[rows, ax] = fl_int[rows, ax] + side
+            meet = np.all(np.maximum(f_lo, lo_t) <= np.minimum(f_hi, lo_t + 1), axis=1)
+            for f in np.nonzero(meet)[0]:
+                V[f], K[f] = E.exact(t, f)
+        out[m] = V @ qf - K @ gf
+    return out
+
+
 # -- O2: Algorithm 3 --------------------------------------------------------------------------------
 
 class BtVFMM(FMM):
@@ -356,3 +399,95 @@ class BtVFMM(FMM):
         m = self.upward(self.boundary_moments(qf, gf))
         lam = self.downward(self.interaction(m))
         return self.evaluation(lam, u)
+
+
+# -- VtB: Algorithm 2 --------------------------------------------------------------------------------
+#
+# u_f = <1_f, N f_h>_{L2(f)} = sum over leaves l of V_lf f_l for every boundary face f: the
+# potential's face integrals (degree p = 0 on the faces). The entries are the single-layer entries of
+# the BtV calculation (G is symmetric). Algorithm 2: near field of the face's cell w (level L) over
+# N*(w) as in Algorithm 1, moments of every leaf, upward pass, interaction phase for the boundary
+# cells B_l, downward pass into the boundary children, evaluation of the face's cell's local
+# expansion at the face (2x2 point rule).
+
+def vtb_direct(mesh, f, n=24):
+    """O1: u_f = sum over all leaves l of V_lf f_l."""
+    E = Entries(mesh, n)
+    f = np.asarray(f, dtype=np.float64)
+    u = np.zeros(len(E.faces))
+    for fi in range(len(E.faces)):
+        for t in range(len(E.leaves)):
+            u[fi] += E.entry(t, fi)[0] * f[t]
+    return u
+
+
+class VtBFMM(FMM):
+    """Algorithm 2 (BC-FMM for the VtB calculation) step by step in FP64."""
+
+    def __init__(self, mesh, q, n=24):
+        super().__init__(mesh, q)
+        self.E = Entries(mesh, n)
+        self.faces = self.E.faces
+
+    def near_field(self, f):
+        mesh = self.mesh
+        u = np.zeros(len(self.faces))
+        for fi, (leaf, ax, side) in enumerate(self.faces):
+            lev, i, j, k = self.leaves[leaf]
+            for s in mesh.near_leaf_sources(lev, (i, j, k)):
+                t = mesh.leaf_index[s]
+                u[fi] += self.E.entry(t, fi)[0] * f[t]
+        return u
+
+    def interaction(self, m):
+        """lambda_w = sum over I(w) of T(w, w') m_w' for the boundary cells w in B_l."""
+        mesh = self.mesh
+        lam = [np.zeros((len(mesh.levels[lev]), self.K)) for lev in range(mesh.L + 1)]
+        for lev in range(mesh.L + 1):
+            idx = mesh.index[lev]
+            for p, c in enumerate(mesh.levels[lev]):
+                if not mesh.on_boundary(lev, c):
+                    continue
+                srcs = mesh.interaction_list(lev, c)
+                if not srcs:
+                    continue
+                offs = [(c[0] - s[0], c[1] - s[1], c[2] - s[2]) for s in srcs]
+                for T, s in zip(self._m2l(lev, offs), srcs):
+                    lam[lev][p] += T @ m[lev][idx[s]]
+        return lam
+
+    def downward(self, lam):
+        """lambda_w' += L(w', w) lambda_w for w in B_l and its children in B_{l+1}."""
+        mesh = self.mesh
+        for lev in range(mesh.L):
+            for p, c in enumerate(mesh.levels[lev]):
+                if not mesh.on_boundary(lev, c) or not mesh.is_refined(lev, c):
+                    continue
+                for pos in ((dx, dy, dz) for dz in (0, 1) for dy in (0, 1) for dx in (0, 1)):
+                    ch = (2 * c[0] + pos[0], 2 * c[1] + pos[1], 2 * c[2] + pos[2])
+                    if mesh.on_boundary(lev + 1, ch):
+                        lam[lev + 1][mesh.index[lev + 1][ch]] += self._l2l(lev, pos) @ lam[lev][p]
+        return lam
+
+    def evaluation_faces(self, lam, u):
+        """u_f += int_f sum_a lambda_w^a (y - x_w)^a dS (2x2 point rule), w the face's cell."""
+        mesh = self.mesh
+        L = mesh.L
+        a = mesh.side(L)
+        mis = multi_indices(self.q)
+        for fi, (leaf, ax, side) in enumerate(self.faces):
+            _, i, j, k = self.leaves[leaf]
+            lo = np.array([i, j, k]) * a
+            pts, w = face_points(lo, a, ax, side)
+            d = pts - (lo + 0.5 * a)
+            row = mesh.index[L][(int(i), int(j), int(k))]
+            mono = np.array([np.prod(d ** np.array(al), axis=1) for al in mis])  # (K, 4)
+            u[fi] += w * float(np.sum(mono.sum(axis=1) * lam[L][row]))
+        return u
+
+    def apply(self, f):
+        f = np.asarray(f, dtype=np.float64)
+        u = self.near_field(f)
+        m = self.upward(self.moments(f))
+        lam = self.downward(self.interaction(m))
+        return self.evaluation_faces(lam, u)

@@ -33,12 +33,13 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("eta0", ctypes.c_double), ("q", ctypes.c_int), ("precision", ctypes.c_int),
                 ("direct", ctypes.c_int), ("nearfield", ctypes.c_int), ("streams", ctypes.c_int),
                 ("surrogate", ctypes.c_void_p), ("surrogate_tol", ctypes.c_double), ("near_unit", ctypes.c_int),
-                ("m2l_max_slots", ctypes.c_int)]
+                ("m2l_max_slots", ctypes.c_int), ("boundary", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("n_leaves", "n_cells", "n_near", "n_touch", "n_m2l", "n_m2l_lanes",
-                                              "n_offsets", "n_m2l_read_lanes", "device_bytes")] + [
+                                              "n_offsets", "n_m2l_read_lanes", "n_faces", "n_btv_near",
+                                              "n_btv_touch", "device_bytes")] + [
         ("K", ctypes.c_int32), ("L", ctypes.c_int32), ("surrogate_classes", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
@@ -82,6 +83,9 @@ def lib():
         L.bcv_vtv_apply_parts.argtypes = [vp, vp, vp, vp, ctypes.c_int]
         L.bcv_vtb_apply.argtypes = [vp, vp, vp, vp]
         L.bcv_btv_apply.argtypes = [vp, vp, vp, vp, vp]
+        L.bcv_tree_num_faces.argtypes = [vp, i64p]
+        L.bcv_tree_faces.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+        L.bcv_boundary_touching_integrals.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.bcv_plan_enable_timing.argtypes = [vp, ctypes.c_int]
         L.bcv_plan_phase_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i64p]
         L.bcv_touching_integrals.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
@@ -147,6 +151,14 @@ class Tree:
         _check(lib().bcv_tree_leaf_mesh(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
         return out
 
+    def faces(self):
+        """(leaf, axis, side) per boundary face in the library's face order, int32 (n_faces, 3)."""
+        n = ctypes.c_int64()
+        _check(lib().bcv_tree_num_faces(self._h, ctypes.byref(n)))
+        out = np.empty((n.value, 3), dtype=np.int32)
+        _check(lib().bcv_tree_faces(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return out
+
     def leaves(self):
         """(level, i, j, k) per leaf in leaf order, int32 (n, 4)."""
         out = np.empty((self.num_leaves(), 4), dtype=np.int32)
@@ -200,14 +212,17 @@ class Plan:
 
 
 def _opts(q=6, eta0=0.5, direct=False, nearfield=NEAR_QUADRATURE, streams=2, precision=FP64, surrogate=None,
-          surrogate_tol=1e-7, near_unit=0, m2l_max_slots=0):
+          surrogate_tol=1e-7, near_unit=0, m2l_max_slots=0, boundary=False):
     return PlanOpts(eta0, q, precision, 1 if direct else 0, nearfield, streams,
-                    surrogate.handle if surrogate is not None else None, surrogate_tol, near_unit, m2l_max_slots)
+                    surrogate.handle if surrogate is not None else None, surrogate_tol, near_unit, m2l_max_slots,
+                    1 if boundary else 0)
 
 
 def plan_interactions(tree, q=6, eta0=0.5, direct=False, nearfield=NEAR_QUADRATURE, device=0, streams=2,
-                      precision=FP64, surrogate=None, surrogate_tol=1e-7, near_unit=0, m2l_max_slots=0):
-    opts = _opts(q, eta0, direct, nearfield, streams, precision, surrogate, surrogate_tol, near_unit, m2l_max_slots)
+                      precision=FP64, surrogate=None, surrogate_tol=1e-7, near_unit=0, m2l_max_slots=0,
+                      boundary=False):
+    opts = _opts(q, eta0, direct, nearfield, streams, precision, surrogate, surrogate_tol, near_unit, m2l_max_slots,
+                 boundary)
     h = ctypes.c_void_p()
     _check(lib().bcv_plan_interactions(tree.handle, ctypes.byref(opts), device, ctypes.byref(h)))
     return Plan(h, device)
@@ -249,8 +264,20 @@ def vtb_apply(plan, f, u_face, stream=None):
 
 
 def btv_apply(plan, q_face, g_face, u, stream=None):
-    _check(lib().bcv_btv_apply(plan.handle, ctypes.c_void_p(q_face.data_ptr()), ctypes.c_void_p(g_face.data_ptr()),
-                               ctypes.c_void_p(u.data_ptr()), _stream(stream, plan.device)))
+    """u = <1_w, V[q] - K[g]> on every leaf (Algorithm 3); q_face, g_face per boundary face in
+    Tree.faces() order (float64 device tensors), u per leaf (overwritten)."""
+    nf, n = plan.info["n_faces"], plan.n_leaves
+    _check(lib().bcv_btv_apply(plan.handle, _dev_ptr(q_face, nf, plan.device, "q_face"),
+                               _dev_ptr(g_face, nf, plan.device, "g_face"), _dev_ptr(u, n, plan.device, "u"),
+                               _stream(stream, plan.device)))
+
+
+def boundary_touching_integrals():
+    """(V, K): the library's 162-class tables of touching (cell, boundary face) integrals (bcv.h)."""
+    V = np.empty(162)
+    K = np.empty(162)
+    _check(lib().bcv_boundary_touching_integrals(_dp(V), _dp(K)))
+    return V, K
 
 
 PHASES = ("p2m", "m2m", "m2l", "l2l", "near", "eval")

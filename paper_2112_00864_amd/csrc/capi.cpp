@@ -77,6 +77,7 @@ void check_plan_opts(const bcv_plan_opts &o, int device)
                 "near_unit must be 0 or 64..65536");
     BCV_REQUIRE(o.m2l_max_slots == 0 || (o.m2l_max_slots >= 16 && o.m2l_max_slots <= 65536),
                 BCV_EINVAL, "m2l_max_slots must be 0 or 16..65536");
+    BCV_REQUIRE(o.boundary == 0 || o.boundary == 1, BCV_EINVAL, "boundary must be 0 or 1");
     if (o.surrogate) {
         check_mlp(o.surrogate);
         BCV_REQUIRE(o.surrogate_tol >= 0.0, BCV_EINVAL, "negative surrogate tolerance");
@@ -206,6 +207,9 @@ bcv_status bcv_plan_get_info(bcv_plan plan, bcv_plan_info *info)
         info->n_m2l_lanes = plan->n_m2l_lanes;
         info->n_offsets = plan->n_offsets;
         info->n_m2l_read_lanes = plan->n_m2l_read_lanes;
+        info->n_faces = plan->n_faces;
+        info->n_btv_near = plan->n_btv_near;
+        info->n_btv_touch = plan->n_btv_touch;
         info->device_bytes = plan->device_bytes;
         info->K = plan->K;
         info->L = plan->L;
@@ -260,11 +264,42 @@ bcv_status bcv_vtb_apply(bcv_plan plan, const double *, double *, void *)
     });
 }
 
-bcv_status bcv_btv_apply(bcv_plan plan, const double *, const double *, double *, void *)
+bcv_status bcv_btv_apply(bcv_plan plan, const double *q_face_dev, const double *g_face_dev, double *u_dev,
+                         void *hip_stream)
 {
     return guard([&] {
         check_plan(plan);
-        bcv::fail(BCV_ENOTSUP, "boundary-to-volume apply is not implemented in this build");
+        BCV_REQUIRE(q_face_dev != nullptr && g_face_dev != nullptr && u_dev != nullptr, BCV_EINVAL,
+                    "NULL face data or potential pointer");
+        BCV_REQUIRE(plan->boundary, BCV_ESTATE, "the plan was built without boundary structures (opts.boundary)");
+        on_device(plan->device, [&] { bcv::launch_btv(*plan, q_face_dev, g_face_dev, u_dev, (hipStream_t)hip_stream); });
+    });
+}
+
+bcv_status bcv_tree_num_faces(bcv_tree tree, int64_t *n_faces)
+{
+    return guard([&] {
+        check_tree(tree);
+        BCV_REQUIRE(n_faces != nullptr, BCV_EINVAL, "NULL argument");
+        *n_faces = (int64_t)bcv::tree_faces(*tree).size() / 3;
+    });
+}
+
+bcv_status bcv_tree_faces(bcv_tree tree, int32_t *leaf_axis_side)
+{
+    return guard([&] {
+        check_tree(tree);
+        BCV_REQUIRE(leaf_axis_side != nullptr, BCV_EINVAL, "NULL argument");
+        const std::vector<int32_t> f = bcv::tree_faces(*tree);
+        std::copy(f.begin(), f.end(), leaf_axis_side);
+    });
+}
+
+bcv_status bcv_boundary_touching_integrals(double *V, double *K)
+{
+    return guard([&] {
+        BCV_REQUIRE(V != nullptr && K != nullptr, BCV_EINVAL, "NULL argument");
+        bcv::boundary_touching_integrals(V, K);
     });
 }
 

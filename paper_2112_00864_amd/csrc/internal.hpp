@@ -70,6 +70,16 @@ struct NearSplit {
 // Touching-pair classes in the order of bcv_touching_integrals().
 constexpr int kTouchClasses = 7;
 
+// Boundary faces (BtV): a face is (leaf, axis, side), the leaf's face normal to `axis` at its low
+// (side 0) or high (side 1) end. A touching (cell, face) pair of equal size is the cube [0,1]^3 and
+// the face of the cube at integer offset o in {-1, 0, 1}^3 (units of the cell side); its class
+// numbers (axis, o, side) (162 numbers, of which the 108 where the two meet are used).
+constexpr int kFaceClasses = 162;
+inline int face_class(const int o[3], int ax, int side)
+{
+    return (((ax * 3 + o[0] + 1) * 3 + o[1] + 1) * 3 + o[2] + 1) * 2 + side;
+}
+
 }  // namespace bcv
 
 // Surrogate network (surrogate.cpp): FP32 parameters, gradient and Adam moments on `device`.
@@ -98,6 +108,10 @@ void mlp_train(bcv_mlp_s &net, const bcv_mlp_train_opts &o, bcv_mlp_train_report
 void surrogate_eval(const bcv_mlp_s &net, int64_t n, const bcv_touch_pair *pairs, double tol, double *value,
                     double *est_err, int32_t *fallback, int64_t *n_fallback);
 void touch_pair_quadrature(int device, int64_t n, const bcv_touch_pair *pairs, int n_gauss, double *out);
+// Single- and double-layer integrals of the touching (cell, face) classes of side 1 (boundary.cpp).
+void boundary_touching_integrals(double V[kFaceClasses], double K[kFaceClasses]);
+// Boundary faces of a single-mesh tree: (leaf, axis, side) triples in leaf order, then axis, side.
+std::vector<int32_t> tree_faces(const bcv_tree_s &t);
 void mlp_save(const bcv_mlp_s &net, const char *path);
 bcv_mlp_s *mlp_load(const char *path, int device);
 }  // namespace bcv
@@ -148,10 +162,21 @@ struct bcv_plan_s {
     int32_t *d_parents = nullptr;   // (marked cell, first child) pairs, grouped by level
     bcv::M2LTask *d_tasks = nullptr;
     int32_t *d_task_targets = nullptr;  // 64 per task, -1 = idle lane
-    int32_t *d_slot_off = nullptr;      // offset id per slot | (a run of slots starts here) << 31
+    int32_t *d_slot_off = nullptr;      // offset id per slot | (the slot gathers) << 31
     uint32_t *d_slot_src = nullptr;     // 64 per slot: source row (n_cells: none) | (in the lane's list) << 31
     bcv::M2LSplit *d_m2l_splits = nullptr;
     double *d_m2l_partial = nullptr;    // 64 x K per piece of a split task
+
+    // BtV (Algorithm 3), built when the plan options ask for it.
+    int boundary = 0;
+    int64_t n_faces = 0, n_btv_near = 0, n_btv_touch = 0, n_btv_units = 0, n_btv_splits = 0;
+    uint32_t *d_faces = nullptr;        // per boundary face: leaf | (2 axis + side) << 28
+    int32_t *d_leaf_faces = nullptr;    // n_leaves + 1: the faces of leaf t are [d_leaf_faces[t], d_leaf_faces[t + 1])
+    uint32_t *d_btv_col = nullptr;      // near entries: face | (touching class + 1) << 24 (0: point rule)
+    bcv::NearUnit *d_btv_units = nullptr;
+    bcv::NearSplit *d_btv_splits = nullptr;
+    double *d_btv_partial = nullptr;
+    double *d_btv_touch = nullptr;      // 2 x kFaceClasses: V, then K, of touching pairs of side 1
 };
 
 // A captured apply (graph.cpp).

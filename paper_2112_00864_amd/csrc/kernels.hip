@@ -14,6 +14,7 @@
 // The near field adds, per leaf w, sum over N*(w) of A_{w s} f_s, with A_{w s} the exact
 // touching integral C_class a_small^5/(4 pi) or the 2x2x2 x 2x2x2 point rule.
 #include <algorithm>
+#include <type_traits>
 #include <utility>
 
 #include "kernels.hpp"
@@ -55,6 +56,43 @@ struct Tables {
 
 template <int Q>
 __constant__ constexpr KappaTable<Q> kKappa{};
+
+// Boundary moments (BtV, Algorithm 3). The 2x2 Gauss points of a face of a cell, relative to the
+// cell centre in units of its side a, are s = side - 1/2 along the face's normal axis n and
+// +-1/(2 sqrt 3) in the face. With m^b = int_face (y - x_w)^b q - d/dn (y - x_w)^b g (q and g
+// constant on the face) and the scaled moments M^b = (-1)^|b| m^b / (b! a^|b|):
+//     M^b = a^2 q phi^b - a g psi^b,
+//     phi^b = (-1)^|b| s^{b_n}/b_n! kappa(b_1) kappa(b_2),
+//     psi^b = sign (-1)^|b| s^{b_n - 1}/(b_n - 1)! kappa(b_1) kappa(b_2)   (0 if b_n = 0),
+// with b_1, b_2 the in-face components, kappa the per-axis factor of P2M and sign = 2 side - 1 the
+// outward normal. Face type = 2 axis + side.
+template <int Q>
+struct FaceKappaTable {
+    double phi[6][MultiIndex<Q>::K], psi[6][MultiIndex<Q>::K];
+    constexpr FaceKappaTable() : phi{}, psi{}
+    {
+        constexpr MultiIndex<Q> mi{};
+        for (int type = 0; type < 6; ++type) {
+            const int ax = type >> 1, side = type & 1;
+            const double s = side ? 0.5 : -0.5, sign = side ? 1.0 : -1.0;
+            for (int b = 0; b < MultiIndex<Q>::K; ++b) {
+                double in_face = 1.0;
+                for (int d = 0; d < 3; ++d)
+                    if (d != ax) in_face *= kappa_axis_ce(mi.e[b][d]);
+                const int bn = mi.e[b][ax];
+                const double par = (mi.deg[b] & 1) ? -1.0 : 1.0;
+                double p_bn = 1.0, p_bn1 = 1.0;  // s^bn / bn!, s^(bn-1) / (bn-1)!
+                for (int k = 1; k <= bn; ++k) p_bn *= s / k;
+                for (int k = 1; k <= bn - 1; ++k) p_bn1 *= s / k;
+                phi[type][b] = par * p_bn * in_face;
+                psi[type][b] = bn >= 1 ? sign * par * p_bn1 * in_face : 0.0;
+            }
+        }
+    }
+};
+
+template <int Q>
+__constant__ constexpr FaceKappaTable<Q> kFaceKappa{};
 
 // (1/4)^k / k! for k = 0..kMaxOrder (translation coefficients; the sign (-1)^k is applied by the caller).
 constexpr int kMaxOrder = 8;
@@ -433,10 +471,11 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2, 2))) v
 // lanes accumulate. One launch covers the block a in [A0, A1), b in [B0, B1) of the sums
 // (|a| + |b| <= Q): the launches of a full interaction phase tile the triangle in blocks that fit
 // 128 registers, four waves per SIMD (the latency of the row reads at the start of each slot is
-// covered by the other waves). The block with B0 = 0 writes Lambda^a, the others add to it and are
-// launched after it.
-template <int Q, class T, int A0, int A1, int B0, int B1>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4, 4))) void m2l_shift_kernel(
+// covered by the other waves), or two waves for the FP64 block of the high source orders (one
+// block of 40 + 148 registers ran faster than two of four waves each). The block with B0 = 0
+// writes Lambda^a, the others add to it and are launched after it.
+template <int Q, class T, int A0, int A1, int B0, int B1, int kWaves>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kWaves, kWaves))) void m2l_shift_kernel(
     XcdRanges ranges, const M2LTask *__restrict__ tasks, const int32_t *__restrict__ targets,
     const int32_t *__restrict__ slot_off, const uint32_t *__restrict__ slot_src, const T *__restrict__ G,
     const T *__restrict__ M, double *__restrict__ partial, double *__restrict__ Lam)
@@ -667,6 +706,130 @@ __global__ __launch_bounds__(256) void eval_add_kernel(int64_t n_leaves, const d
     }
 }
 
+// ---- BtV (Algorithm 3): boundary moments and the near field of boundary faces --------------------
+
+// Moments of every leaf from its boundary faces (zero for leaves without one): one thread per
+// (leaf, coefficient).
+template <int Q>
+__global__ void btv_p2m_kernel(int64_t n_leaves, const int32_t *__restrict__ leaf_cell,
+                               const double4 *__restrict__ geom, const int32_t *__restrict__ leaf_faces,
+                               const uint32_t *__restrict__ faces, const double *__restrict__ qf,
+                               const double *__restrict__ gf, double *__restrict__ M)
+{
+    constexpr int K = MultiIndex<Q>::K;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t leaf = idx / K;
+    const int b = (int)(idx - leaf * K);
+    if (leaf >= n_leaves) return;
+    const double a = geom[leaf].w;
+    double m = 0.0;
+    for (int32_t f = leaf_faces[leaf]; f < leaf_faces[leaf + 1]; ++f) {
+        const int type = (int)(faces[f] >> 28);
+        m += a * (a * qf[f] * kFaceKappa<Q>.phi[type][b] - gf[f] * kFaceKappa<Q>.psi[type][b]);
+    }
+    M[(int64_t)leaf_cell[leaf] * K + b] = m;
+}
+
+__device__ __forceinline__ double pick3(const double v[3], int d) { return d == 0 ? v[0] : (d == 1 ? v[1] : v[2]); }
+__device__ __forceinline__ double rsq(double x) { return rsqrt_pos(x); }
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// Point rule of a cell (2x2x2 Gauss points) against a boundary face (2x2 Gauss points): the
+// single-layer entry sv = sum w w' G and the double-layer entry dv = sum w w' n.(x - y)/(4 pi r^3).
+// The 32 kernel evaluations run in R (double, or float in the mixed path with the per-axis
+// differences formed in FP64 first, as in the volume point rule).
+template <class R>
+__device__ __forceinline__ void face_rule(const double4 gt, const double4 gf, int ax, int side, double &sv,
+                                          double &dv)
+{
+    const double lt[3] = {gt.x, gt.y, gt.z}, lf[3] = {gf.x, gf.y, gf.z};
+    const int o1 = ax == 0 ? 1 : 0, o2 = ax == 2 ? 1 : 2;
+    const double plane = pick3(lf, ax) + side * gf.w;
+    const R dn[2] = {(R)(pick3(lt, ax) + gt.w * kNode0 - plane), (R)(pick3(lt, ax) + gt.w * kNode1 - plane)};
+    R p1[4], p2[4];
+    {
+        const double x0 = pick3(lt, o1) + gt.w * kNode0, x1 = pick3(lt, o1) + gt.w * kNode1;
+        const double y0 = pick3(lf, o1) + gf.w * kNode0, y1 = pick3(lf, o1) + gf.w * kNode1;
+        const R d[4] = {(R)(x0 - y0), (R)(x0 - y1), (R)(x1 - y0), (R)(x1 - y1)};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) p1[m] = d[m] * d[m];
+    }
+    {
+        const double x0 = pick3(lt, o2) + gt.w * kNode0, x1 = pick3(lt, o2) + gt.w * kNode1;
+        const double y0 = pick3(lf, o2) + gf.w * kNode0, y1 = pick3(lf, o2) + gf.w * kNode1;
+        const R d[4] = {(R)(x0 - y0), (R)(x0 - y1), (R)(x1 - y0), (R)(x1 - y1)};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) p2[m] = d[m] * d[m];
+    }
+    R s = 0, k = 0;
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+        const R dn2 = dn[n] * dn[n];
+        R kn = 0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const R x = dn2 + p1[a];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const R ir = rsq(x + p2[b]);
+                s += ir;
+                kn += ir * ir * ir;
+            }
+        }
+        k += dn[n] * kn;
+    }
+    const double w = (gt.w * gt.w * gt.w * 0.125) * (gf.w * gf.w * 0.25) * kInv4Pi;
+    sv = (double)s * w;
+    dv = (side ? 1.0 : -1.0) * (double)k * w;
+}
+
+// u_w = sum over the near faces of V q - K g (touching pairs from the class table, scaled by a^4
+// and a^3; the others by the point rule), plus the evaluation phase; one wave per work unit.
+template <int Q, bool kMixed>
+__global__ __launch_bounds__(256) void btv_near_kernel(int64_t n_units, const NearUnit *__restrict__ units,
+                                                       const uint32_t *__restrict__ col,
+                                                       const uint32_t *__restrict__ faces,
+                                                       const double4 *__restrict__ geom,
+                                                       const double *__restrict__ qf, const double *__restrict__ gf,
+                                                       const double *__restrict__ touch,
+                                                       const double *__restrict__ Lam,
+                                                       const int32_t *__restrict__ leaf_cell,
+                                                       double *__restrict__ partial, double *__restrict__ u)
+{
+    constexpr int K = MultiIndex<Q>::K;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (w >= n_units) return;  // uniform per wave
+    const NearUnit un = units[w];
+    const int32_t t = un.target;
+    const double4 gt = geom[t];
+    double acc = 0.0;
+    for (int64_t e = un.begin + lane; e < un.end; e += kWave) {
+        const uint32_t code = col[e];
+        const uint32_t f = code & 0x00FFFFFFu, cls = code >> 24;
+        const double q = qf[f], g = gf[f];
+        if (cls) {
+            const double a = gt.w, a3 = a * a * a;
+            acc += touch[cls - 1] * a3 * a * q - touch[kFaceClasses + cls - 1] * a3 * g;
+        } else {
+            const uint32_t fw = faces[f];
+            const int type = (int)(fw >> 28);
+            double sv, dv;
+            face_rule<typename std::conditional<kMixed, float, double>::type>(gt, geom[fw & 0x0FFFFFFFu], type >> 1,
+                                                                              type & 1, sv, dv);
+            acc += sv * q - dv * g;
+        }
+    }
+    if (un.out < 0 && Lam != nullptr) acc += eval_far<Q>(Lam + (int64_t)leaf_cell[t] * K, gt.w, lane);
+    acc = wave_sum(acc);
+    if (lane == 0) {
+        if (un.out < 0)
+            u[t] = acc;
+        else
+            partial[un.out] = acc;
+    }
+}
+
 // ---- plan-time assembly of the near-pair entries --------------------------------------------------
 __global__ __launch_bounds__(256) void near_assemble_kernel(int64_t n_units, const NearUnit *__restrict__ units,
                                                             const uint32_t *__restrict__ col,
@@ -784,7 +947,9 @@ void launch_near(const bcv_plan_s &p, const double *f, const double *lam, int pa
 template <int Q, int A0, int A1, int B0, int B1, class T>
 void launch_m2l_block(const bcv_plan_s &p, const XcdRanges &ranges, const T *G, const T *M, hipStream_t st)
 {
-    m2l_shift_kernel<Q, T, A0, A1, B0, B1><<<(unsigned)p.m2l_groups, kWave, 0, st>>>(
+    // four waves per SIMD (128 registers) where the block fits, else two
+    constexpr int regs = (A1 - A0 + B1 - B0) * (int)(sizeof(T) / 4);
+    m2l_shift_kernel<Q, T, A0, A1, B0, B1, (regs > 110 ? 2 : 4)><<<(unsigned)p.m2l_groups, kWave, 0, st>>>(
         ranges, p.d_tasks, p.d_task_targets, p.d_slot_off, p.d_slot_src, G, M, p.d_m2l_partial, p.d_Lam);
     check_launch();
 }
@@ -805,8 +970,7 @@ void launch_m2l(const bcv_plan_s &p, const double *G, const double *M, hipStream
     } else if constexpr (Q == 6) {
         launch_m2l_block<Q, 0, 35, 0, 10>(p, ranges, G, M, st);  // |a| <= 4, |b| <= 2
         launch_m2l_block<Q, 35, K, 0, 4>(p, ranges, G, M, st);   // |a| >= 5, |b| <= 1
-        launch_m2l_block<Q, 0, 20, 10, 35>(p, ranges, G, M, st); // |a| <= 3, 3 <= |b| <= 4
-        launch_m2l_block<Q, 0, 4, 35, K>(p, ranges, G, M, st);   // |a| <= 1, |b| >= 5
+        launch_m2l_block<Q, 0, 20, 10, K>(p, ranges, G, M, st);  // |a| <= 3, |b| >= 3 (two waves)
     } else {
         static_assert(Q == 8, "orders 4, 6, 8");
         const unsigned groups = (unsigned)p.m2l_groups;
@@ -842,6 +1006,53 @@ void launch_m2l(const bcv_plan_s &p, const float *G, const float *M, hipStream_t
     }
 }
 
+// Upward pass (M2M, l = L-1 .. 2; moments below level 2 are never used), interaction phase (M2L
+// with the FP32 copy of the moments in the mixed path) and downward pass (L2L), shared by the VtV
+// and BtV applies.
+template <int Q>
+void upward_pass(const bcv_plan_s &p, hipStream_t st)
+{
+    for (int lev = p.L - 1; lev >= 2; --lev) {
+        const int n_par = p.parent_begin[lev + 1] - p.parent_begin[lev];
+        if (n_par == 0) continue;
+        m2m_kernel<Q><<<(unsigned)((n_par + tree_waves<Q>() - 1) / tree_waves<Q>()), kWave * tree_waves<Q>(), 0, st>>>(
+            n_par, p.d_parents + 2 * p.parent_begin[lev], p.d_M);
+        check_launch();
+    }
+}
+
+template <int Q>
+void interaction_phase(const bcv_plan_s &p, hipStream_t st)
+{
+    constexpr int K = MultiIndex<Q>::K;
+    if (p.n_tasks == 0) return;
+    if (p.precision == BCV_MIXED_F32) {
+        const int64_t n = (p.n_cells + 1) * K;
+        to_f32_kernel<<<(unsigned)std::min<int64_t>((n + 255) / 256, 65536), 256, 0, st>>>(n, p.d_M, p.d_M32);
+        check_launch();
+        launch_m2l<Q>(p, p.d_G32, p.d_M32, st);
+    } else {
+        launch_m2l<Q>(p, p.d_G, p.d_M, st);
+    }
+    if (p.n_m2l_splits > 0) {
+        m2l_combine_kernel<Q><<<dim3((unsigned)p.n_m2l_splits, (K + 3) / 4), 256, 0, st>>>(
+            p.d_m2l_splits, p.d_task_targets, p.d_m2l_partial, p.d_Lam);
+        check_launch();
+    }
+}
+
+template <int Q>
+void downward_pass(const bcv_plan_s &p, hipStream_t st)
+{
+    for (int lev = 2; lev < p.L; ++lev) {
+        const int n_par = p.parent_begin[lev + 1] - p.parent_begin[lev];
+        if (n_par == 0) continue;
+        l2l_kernel<Q><<<(unsigned)((n_par + tree_waves<Q>() - 1) / tree_waves<Q>()), kWave * tree_waves<Q>(), 0, st>>>(
+            n_par, p.d_parents + 2 * p.parent_begin[lev], p.d_Lam);
+        check_launch();
+    }
+}
+
 template <int Q>
 void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStream_t st)
 {
@@ -858,13 +1069,7 @@ void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStre
         check_launch();
         marks.stop(BCV_PHASE_P2M, st);
         marks.start(BCV_PHASE_M2M, st);
-        for (int lev = p.L - 1; lev >= 2; --lev) {  // upward pass; moments below level 2 are never used
-            const int n_par = p.parent_begin[lev + 1] - p.parent_begin[lev];
-            if (n_par == 0) continue;
-            m2m_kernel<Q><<<(unsigned)((n_par + tree_waves<Q>() - 1) / tree_waves<Q>()), kWave * tree_waves<Q>(), 0, st>>>(
-                n_par, p.d_parents + 2 * p.parent_begin[lev], p.d_M);
-            check_launch();
-        }
+        upward_pass<Q>(p, st);
         marks.stop(BCV_PHASE_M2M, st);
         if (fork) {
             // Near field on the side stream, concurrently with the interaction phase. It is forked
@@ -878,30 +1083,10 @@ void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStre
             BCV_HIP(hipEventRecord(p.ev_join, p.side));
         }
         marks.start(BCV_PHASE_M2L, st);
-        if (p.n_tasks > 0) {
-            if (p.precision == BCV_MIXED_F32) {
-                const int64_t n = (p.n_cells + 1) * K;
-                to_f32_kernel<<<(unsigned)std::min<int64_t>((n + 255) / 256, 65536), 256, 0, st>>>(n, p.d_M, p.d_M32);
-                check_launch();
-                launch_m2l<Q>(p, p.d_G32, p.d_M32, st);
-            } else {
-                launch_m2l<Q>(p, p.d_G, p.d_M, st);
-            }
-            if (p.n_m2l_splits > 0) {
-                m2l_combine_kernel<Q><<<dim3((unsigned)p.n_m2l_splits, (K + 3) / 4), 256, 0, st>>>(
-                    p.d_m2l_splits, p.d_task_targets, p.d_m2l_partial, p.d_Lam);
-                check_launch();
-            }
-        }
+        interaction_phase<Q>(p, st);
         marks.stop(BCV_PHASE_M2L, st);
         marks.start(BCV_PHASE_L2L, st);
-        for (int lev = 2; lev < p.L; ++lev) {  // downward pass
-            const int n_par = p.parent_begin[lev + 1] - p.parent_begin[lev];
-            if (n_par == 0) continue;
-            l2l_kernel<Q><<<(unsigned)((n_par + tree_waves<Q>() - 1) / tree_waves<Q>()), kWave * tree_waves<Q>(), 0, st>>>(
-                n_par, p.d_parents + 2 * p.parent_begin[lev], p.d_Lam);
-            check_launch();
-        }
+        downward_pass<Q>(p, st);
         marks.stop(BCV_PHASE_L2L, st);
     }
     if (fork) {
@@ -920,7 +1105,52 @@ void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStre
     marks.finish(st);
 }
 
+// BtV apply (Algorithm 3), on the caller's stream: boundary moments, upward pass, interaction
+// phase (all interaction-list sources; cells without boundary faces below them carry zero moments),
+// downward pass, then the near field of the boundary faces fused with the evaluation phase.
+template <int Q>
+void btv_q(const bcv_plan_s &p, const double *qf, const double *gf, double *u, hipStream_t st)
+{
+    constexpr int K = MultiIndex<Q>::K;
+    const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
+    const bool far = !p.direct;
+    if (far) {
+        const int64_t nthr = p.n_leaves * K;
+        btv_p2m_kernel<Q><<<(unsigned)((nthr + 255) / 256), 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom,
+                                                                         p.d_leaf_faces, p.d_faces, qf, gf, p.d_M);
+        check_launch();
+        upward_pass<Q>(p, st);
+        interaction_phase<Q>(p, st);
+        downward_pass<Q>(p, st);
+    }
+    const double *lam = far ? p.d_Lam : nullptr;
+    const unsigned blocks = (unsigned)((p.n_btv_units + 3) / 4);
+    if (p.precision == BCV_MIXED_F32)
+        btv_near_kernel<Q, true><<<blocks, 256, 0, st>>>(p.n_btv_units, p.d_btv_units, p.d_btv_col, p.d_faces, geom, qf,
+                                                         gf, p.d_btv_touch, lam, p.d_leaf_cell, p.d_btv_partial, u);
+    else
+        btv_near_kernel<Q, false><<<blocks, 256, 0, st>>>(p.n_btv_units, p.d_btv_units, p.d_btv_col, p.d_faces, geom,
+                                                          qf, gf, p.d_btv_touch, lam, p.d_leaf_cell, p.d_btv_partial,
+                                                          u);
+    check_launch();
+    if (p.n_btv_splits > 0) {
+        near_combine_kernel<Q><<<(unsigned)((p.n_btv_splits + 3) / 4), 256, 0, st>>>(
+            p.n_btv_splits, p.d_btv_splits, p.d_btv_partial, geom, lam, p.d_leaf_cell, u);
+        check_launch();
+    }
+}
+
 }  // namespace
+
+void launch_btv(const bcv_plan_s &p, const double *qf, const double *gf, double *u, hipStream_t st)
+{
+    switch (p.q) {
+    case 4: btv_q<4>(p, qf, gf, u, st); break;
+    case 6: btv_q<6>(p, qf, gf, u, st); break;
+    case 8: btv_q<8>(p, qf, gf, u, st); break;
+    default: fail(BCV_ENOTSUP, "expansion order not compiled");
+    }
+}
 
 void launch_apply(const bcv_plan_s &p, const double *f, double *u, int parts, hipStream_t st)
 {

@@ -7,6 +7,8 @@ namespace bcv {
 // Algorithm 1 on `stream`: moments, upward pass, interaction phase, downward pass, and the
 // near field fused with the evaluation phase. parts: BCV_PART_NEAR | BCV_PART_FAR.
 void launch_apply(const bcv_plan_s &p, const double *f, double *u, int parts, hipStream_t stream);
+// BtV apply (Algorithm 3): u = <1_w, V[q] - K[g]> from face data qf, gf (device, n_faces each).
+void launch_btv(const bcv_plan_s &p, const double *qf, const double *gf, double *u, hipStream_t stream);
 
 // Stores every near-pair Galerkin entry of the plan in p.d_val (plan time).
 void launch_near_assemble(const bcv_plan_s &p, hipStream_t stream);

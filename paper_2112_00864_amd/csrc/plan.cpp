@@ -553,6 +553,121 @@ T *alloc_zero(bcv_plan_s *p, size_t count)
     return d;
 }
 
+// BtV (Algorithm 3) near field. For a leaf w of level l, the pair (w, face) is near when the
+// level-l ancestor of the face's cell is a neighbour of w: then no ancestor pair meets in an
+// interaction list (the parents of neighbours are neighbours), so the far field never covers it.
+// Otherwise the ancestors meet in an interaction list at exactly one level <= l, as in the volume
+// calculation, and there the source is a boundary cell. Every face lies in the subtree of one
+// boundary cell per level; a subtree's leaves are consecutive in leaf (Morton) order, so its faces
+// are one range of the face list.
+struct BtvNear {
+    std::vector<uint32_t> faces;     // leaf | (2 axis + side) << 28
+    std::vector<int32_t> leaf_faces; // n_leaves + 1
+    NearCSR near;                    // col: face | (touching class + 1) << 24
+};
+
+BtvNear build_btv_near(const bcv_tree_s &t, const std::vector<Grid> &g, bool direct)
+{
+    BtvNear r;
+    const std::vector<int32_t> fl = tree_faces(t);
+    const int64_t nf = (int64_t)fl.size() / 3, nl = t.n_leaves();
+    BCV_REQUIRE(nf < (1 << 24), BCV_ENOTSUP, "more than 2^24 boundary faces");
+    r.faces.resize(nf);
+    r.leaf_faces.assign(nl + 1, 0);
+    for (int64_t f = 0; f < nf; ++f) {
+        r.faces[f] = (uint32_t)fl[3 * f] | ((uint32_t)(2 * fl[3 * f + 1] + fl[3 * f + 2]) << 28);
+        ++r.leaf_faces[fl[3 * f] + 1];
+    }
+    for (int64_t q = 0; q < nl; ++q) r.leaf_faces[q + 1] += r.leaf_faces[q];
+    // leaf range [lo, hi) of every cell's subtree, finest level first
+    const int64_t nc = t.n_cells();
+    std::vector<int32_t> lo(nc), hi(nc), count(nc);
+    for (int lev = t.L; lev >= 0; --lev)
+        for (int32_t c = t.lvl_start[lev]; c < t.lvl_start[lev + 1]; ++c) {
+            if (!t.refined[c]) {
+                lo[c] = t.leaf_of_cell[c];
+                hi[c] = lo[c] + 1;
+                count[c] = 1;
+                continue;
+            }
+            lo[c] = INT32_MAX, hi[c] = 0, count[c] = 0;
+            for (int d = 0; d < 8; ++d) {
+                const int32_t ch = t.first_child[c] + d;
+                lo[c] = std::min(lo[c], lo[ch]);
+                hi[c] = std::max(hi[c], hi[ch]);
+                count[c] += count[ch];
+            }
+            BCV_REQUIRE(hi[c] - lo[c] == count[c], BCV_ESTATE, "internal: subtree leaves not consecutive");
+        }
+    const int32_t L = t.L;
+    auto on_boundary = [](int lev, const int32_t *c) {
+        const int32_t top = (1 << lev) - 1;
+        return c[0] == 0 || c[1] == 0 || c[2] == 0 || c[0] == top || c[1] == top || c[2] == top;
+    };
+    // class of (leaf cell c at level L, face f), or -1 if they do not meet
+    auto touch_class = [&](int32_t c, int64_t f) {
+        const int32_t fc = t.leaf_cell[r.faces[f] & 0x0FFFFFFFu];
+        const int type = (int)(r.faces[f] >> 28), ax = type >> 1, side = type & 1;
+        int o[3];
+        for (int d = 0; d < 3; ++d) {
+            o[d] = t.ijk[3 * fc + d] - t.ijk[3 * c + d];
+            if (o[d] < -1 || o[d] > 1) return -1;
+        }
+        for (int d = 0; d < 3; ++d) {
+            const int flo = d == ax ? o[d] + side : o[d], fhi = d == ax ? o[d] + side : o[d] + 1;
+            if (std::max(flo, 0) > std::min(fhi, 1)) return -1;
+        }
+        return face_class(o, ax, side);
+    };
+    auto gen = [&](int64_t q, std::vector<uint32_t> &out) {
+        out.clear();
+        const int32_t c = t.leaf_cell[q];
+        const int lev = t.level[c];
+        auto add = [&](int64_t f0, int64_t f1) {
+            for (int64_t f = f0; f < f1; ++f) {
+                const int cls = lev == L ? touch_class(c, f) : -1;
+                out.push_back((uint32_t)f | ((uint32_t)(cls + 1) << 24));
+            }
+        };
+        if (direct) {
+            add(0, nf);
+            return;
+        }
+        const int32_t *ijk = &t.ijk[3 * c];
+        for (const auto &o : stencil()) {
+            const int32_t nb[3] = {ijk[0] + o[0], ijk[1] + o[1], ijk[2] + o[2]};
+            const int32_t n = g[lev].at(nb[0], nb[1], nb[2]);
+            if (n < 0 || !on_boundary(lev, nb)) continue;
+            add(r.leaf_faces[lo[n]], r.leaf_faces[hi[n]]);
+        }
+    };
+    r.near.row.assign(nl + 1, 0);
+#pragma omp parallel
+    {
+        std::vector<uint32_t> buf;
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t q = 0; q < nl; ++q) {
+            gen(q, buf);
+            r.near.row[q + 1] = (int64_t)buf.size();
+        }
+    }
+    for (int64_t q = 0; q < nl; ++q) r.near.row[q + 1] += r.near.row[q];
+    r.near.col.resize(r.near.row[nl]);
+    int64_t touch = 0;
+#pragma omp parallel reduction(+ : touch)
+    {
+        std::vector<uint32_t> buf;
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t q = 0; q < nl; ++q) {
+            gen(q, buf);
+            std::copy(buf.begin(), buf.end(), r.near.col.begin() + r.near.row[q]);
+            for (uint32_t e : buf) touch += (e >> 24) != 0;
+        }
+    }
+    r.near.n_touch = touch;
+    return r;
+}
+
 }  // namespace
 
 void destroy_plan(bcv_plan_s *p);
@@ -679,6 +794,27 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         if (p->precision == BCV_MIXED_F32) p->d_M32 = alloc_zero<float>(p.get(), (size_t)(p->n_cells + 1) * p->K);
     }
 
+    if (opts.boundary) {
+        BtvNear bn = build_btv_near(t, grids, opts.direct != 0);
+        p->boundary = 1;
+        p->n_faces = (int64_t)bn.faces.size();
+        p->n_btv_near = (int64_t)bn.near.col.size();
+        p->n_btv_touch = bn.near.n_touch;
+        p->d_faces = upload(p.get(), bn.faces);
+        p->d_leaf_faces = upload(p.get(), bn.leaf_faces);
+        p->d_btv_col = upload(p.get(), bn.near.col);
+        const NearUnits nu =
+            build_near_units(bn.near, p->n_leaves, opts.near_unit > 0 ? opts.near_unit : kDefaultNearUnit);
+        p->n_btv_units = (int64_t)nu.units.size();
+        p->n_btv_splits = (int64_t)nu.splits.size();
+        p->d_btv_units = upload(p.get(), nu.units);
+        p->d_btv_splits = upload(p.get(), nu.splits);
+        if (nu.n_partial > 0) p->d_btv_partial = alloc_zero<double>(p.get(), (size_t)nu.n_partial);
+        std::vector<double> tv(2 * kFaceClasses);
+        boundary_touching_integrals(tv.data(), tv.data() + kFaceClasses);
+        p->d_btv_touch = upload(p.get(), tv);
+    }
+
     if (opts.nearfield == BCV_NEAR_ASSEMBLED) {
         p->d_val = alloc_zero<double>(p.get(), (size_t)p->n_near);
         launch_near_assemble(*p, nullptr);
@@ -700,7 +836,8 @@ void destroy_plan(bcv_plan_s *p)
                     p->d_splits, p->d_partial, p->d_M, p->d_Lam, p->d_G,
                     p->d_M32, p->d_G32,
                     p->d_parents, p->d_tasks, p->d_task_targets, p->d_slot_off, p->d_slot_src,
-                    p->d_m2l_splits, p->d_m2l_partial};
+                    p->d_m2l_splits, p->d_m2l_partial, p->d_faces, p->d_leaf_faces, p->d_btv_col,
+                    p->d_btv_units, p->d_btv_splits, p->d_btv_partial, p->d_btv_touch};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     p->magic = 0;

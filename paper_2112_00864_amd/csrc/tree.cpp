@@ -73,4 +73,27 @@ bcv_tree_s *build_forest(int n, const int *Ls)
 
 bcv_tree_s *build_tree(int L) { return build_forest(1, &L); }
 
+// Boundary faces of the unit cube: the faces of level-L leaves in the planes x, y, z = 0 or 1
+// (a cell meeting the boundary has a face on it and is refined down to level L).
+std::vector<int32_t> tree_faces(const bcv_tree_s &t)
+{
+    BCV_REQUIRE(t.n_meshes == 1, BCV_ENOTSUP, "boundary faces: single-mesh trees only");
+    const int32_t top = (1 << t.L) - 1;
+    std::vector<int32_t> out;
+    for (int64_t q = 0; q < t.n_leaves(); ++q) {
+        const int32_t c = t.leaf_cell[q];
+        if (t.level[c] != t.L) continue;
+        for (int ax = 0; ax < 3; ++ax) {
+            const int32_t v = t.ijk[3 * c + ax];
+            for (int side = 0; side < 2; ++side)
+                if (v == (side ? top : 0)) {
+                    out.push_back((int32_t)q);
+                    out.push_back(ax);
+                    out.push_back(side);
+                }
+        }
+    }
+    return out;
+}
+
 }  // namespace bcv

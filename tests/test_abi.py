@@ -32,6 +32,20 @@ def test_tree_matches_oracle_mesh(L):
     assert np.array_equal(t.leaves().astype(np.int64), BCMesh(L).leaf_array())
 
 
+@pytest.mark.parametrize("L", [2, 3, 5])
+def test_tree_faces_match_oracle(L):
+    from oracle import boundary
+
+    t = bcv.build_bc_tree(L)
+    assert np.array_equal(t.faces().astype(np.int64), boundary.boundary_faces(BCMesh(L)))
+
+
+def test_forest_has_no_faces():
+    with pytest.raises(bcv.BCVError) as e:
+        bcv.build_bc_forest([3, 4]).faces()
+    assert e.value.status == bcv.bcv.ENOTSUP
+
+
 def test_tree_argument_errors():
     for L in (1, 10):
         with pytest.raises(bcv.BCVError) as e:

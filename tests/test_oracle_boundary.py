@@ -147,3 +147,75 @@ def test_representation_formula(mesh2):
     vol = np.ldexp(1.0, -3 * lv[:, 0].astype(np.int32))
     err = np.linalg.norm(u1 / vol - avg) / np.linalg.norm(avg)
     assert err < 5e-3
+
+
+def test_library_touching_table_matches_oracle():
+    """The library's touching (cell, face) table (host computation, self-similarity of the pair)
+    against the oracle's convolution integrals, all 108 classes where cell and face meet."""
+    import itertools
+
+    import paper_2112_00864_amd as bcv
+
+    V, K = bcv.boundary_touching_integrals()
+    n = 0
+    for ax in range(3):
+        for o in itertools.product((-1, 0, 1), repeat=3):
+            for side in (0, 1):
+                c = (((ax * 3 + o[0] + 1) * 3 + o[1] + 1) * 3 + o[2] + 1) * 2 + side
+                flo, fhi = B.face_box(np.array(o, float), 1.0, ax, side)
+                if not np.all(np.maximum(flo, 0) <= np.minimum(fhi, 1)):
+                    assert V[c] == 0.0 and K[c] == 0.0
+                    continue
+                n += 1
+                ev = B.cell_face_integral(np.zeros(3), np.ones(3), flo, fhi, ax, 2.0 * side - 1, "single")
+                ek = B.cell_face_integral(np.zeros(3), np.ones(3), flo, fhi, ax, 2.0 * side - 1, "double")
+                assert abs(V[c] - ev) <= 1e-13 * abs(ev)
+                assert abs(K[c] - ek) <= 1e-13 * abs(ek)
+    assert n == 108
+
+
+def test_vtb_is_the_adjoint_of_the_btv_single_layer(mesh2):
+    """VtB (Algorithm 2) and the single-layer part of BtV (Algorithm 3) have the same entries
+    V_lf, so <VtB f, q>_faces = <f, BtV(q, 0)>_leaves: exactly for O1, and for O2 too, whose
+    fixed-q truncated two-centre kernel is symmetric and whose near sets agree."""
+    m, faces, qf, gf, _ = mesh2
+    lv = m.leaf_array()
+    f = synth.leaf_density(lv, seed=0)
+    zero = np.zeros(len(faces))
+    u1 = B.vtb_direct(m, f)
+    b1 = B.apply_direct(m, qf, zero)
+    assert abs(u1 @ qf - f @ b1) <= 1e-14 * abs(u1 @ qf)
+    u2 = B.VtBFMM(m, 4).apply(f)
+    b2 = B.BtVFMM(m, 4).apply(qf, zero)
+    assert abs(u2 @ qf - f @ b2) <= 1e-14 * abs(u2 @ qf)
+    # and O2 -> O1 (stated: 3.8e-6 at q = 4, 6.2e-8 at q = 6)
+    assert np.linalg.norm(u2 - u1) / np.linalg.norm(u1) < 1e-5
+
+
+def test_vtb_constant_density_box_closed_form():
+    """f = 1: the face integrals of the homogeneous-box potential (closed form, tests/closed_forms.py)
+    at point-rule accuracy (stated: 7.8e-5 relative at h = 1/4)."""
+    import closed_forms
+
+    m = BCMesh(2)
+    lv = m.leaf_array()
+    faces = B.boundary_faces(m)
+    u = B.VtBFMM(m, 6).apply(np.ones(len(lv)))
+    a = 0.25
+    ref = np.empty(len(faces))
+    g, w = np.polynomial.legendre.leggauss(8)
+    g, w = 0.5 * (g + 1), 0.5 * w
+    for n, (leaf, ax, side) in enumerate(faces):
+        _, i, j, k = lv[leaf]
+        lo = np.array([i, j, k]) * a
+        o1, o2 = (ax + 1) % 3, (ax + 2) % 3
+        tot = 0.0
+        for s, ws in zip(g, w):
+            for t, wt in zip(g, w):
+                p = lo.copy()
+                p[ax] += side * a
+                p[o1] += a * s
+                p[o2] += a * t
+                tot += ws * wt * closed_forms.box_potential(p)
+        ref[n] = tot * a * a
+    assert np.max(np.abs(u - ref) / np.abs(ref)) < 3e-4
