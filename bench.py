@@ -192,9 +192,10 @@ def roofline(info, phase_avg, args, prec):
     return dominant, {"m2l_kernel": m2l_roof, "near_eval_kernel": near_roof}
 
 
-def measure_btv(bcv, torch, tree, args, dev):
-    """BtV (Algorithm 3) on the same mesh: FP64 and mixed plans with boundary structures, seeded
-    face data (traces of a harmonic function), `args.steps` timed applies after `args.warmup`."""
+def measure_btv(bcv, torch, tree, f, args, dev):
+    """BtV (Algorithm 3) and VtB (Algorithm 2) on the same mesh: FP64 and mixed plans with boundary
+    structures; BtV from seeded face data (traces of a harmonic function), VtB from the leaf density
+    f; `args.steps` timed applies of each after `args.warmup`."""
     import synth
 
     lv = tree.leaves().astype(np.int64)
@@ -220,6 +221,17 @@ def measure_btv(bcv, torch, tree, args, dev):
         ms = 1e3 * (time.perf_counter() - t0) / args.steps
         out[prec] = {"ms_per_apply": ms, "value": plan.n_leaves / (ms * 1e-3), "plan_seconds": plan_s,
                      "u": u.cpu().numpy()}
+        uf = torch.empty(plan.info["n_faces"], dtype=torch.float64, device="cuda:%d" % dev)
+        for _ in range(args.warmup):
+            bcv.vtb_apply(plan, f, uf)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            bcv.vtb_apply(plan, f, uf)
+        torch.cuda.synchronize()
+        ms_vtb = 1e3 * (time.perf_counter() - t0) / args.steps
+        out[prec]["vtb"] = {"ms_per_apply": ms_vtb, "value": plan.info["n_faces"] / (ms_vtb * 1e-3),
+                            "unit": "face-potentials/s", "uf": uf.cpu().numpy()}
         info = plan.info
         del plan
     vol = np.ldexp(1.0, -3 * lv[:, 0].astype(np.int32))
@@ -228,9 +240,12 @@ def measure_btv(bcv, torch, tree, args, dev):
     charges, poles = synth.harmonic_params(0)
     avg = synth.cell_average(lv, lambda x: synth.harmonic(x, charges, poles), n=4)
     rep = float(np.linalg.norm(b / vol - avg) / np.linalg.norm(avg))
+    va, vb = out["mixed"]["vtb"]["uf"], out["fp64"]["vtb"]["uf"]
+    vtb_rel = float(np.linalg.norm(va - vb) / np.linalg.norm(vb))
     for prec in out:
         del out[prec]["u"]
-    return {"metric": "BtV cell-potentials/s (Algorithm 3, u = <1_w, V[q] - K[g]>), 1 GPU",
+        del out[prec]["vtb"]["uf"]
+    return {"vtb_mixed_vs_fp64_rel": vtb_rel, "n_vtb_near_pairs": info["n_vtb_near"],"metric": "BtV cell-potentials/s (Algorithm 3, u = <1_w, V[q] - K[g]>), 1 GPU",
             "unit": "cell-potentials/s", "n_faces": info["n_faces"], "n_btv_near_pairs": info["n_btv_near"],
             "n_btv_touching_pairs": info["n_btv_touch"], "fp64": out["fp64"], "mixed": out["mixed"],
             "mixed_vs_fp64_rel_l2": rel, "representation_formula_rel_err": rep,
@@ -460,9 +475,10 @@ def main():
         line["surrogate"] = {"classes_from_network": runs["mixed"]["info"]["surrogate_classes"], "of": 6,
                              "tol": SURROGATE_TOL, "training": sur_report}
     if not args.no_btv:
-        line["btv"] = measure_btv(bcv, torch, tree, args, dev)
+        line["btv"] = measure_btv(bcv, torch, tree, f, args, dev)
         print("btv: %s" % json.dumps({k: line["btv"][k] for k in ("fp64", "mixed", "mixed_vs_fp64_rel_l2",
-                                                                  "representation_formula_rel_err")}),
+                                                                  "representation_formula_rel_err",
+                                                                  "vtb_mixed_vs_fp64_rel")}),
               file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
 

@@ -113,6 +113,7 @@ typedef struct {
     int64_t n_faces;      /* boundary faces (plans built with opts.boundary; else 0) */
     int64_t n_btv_near;   /* BtV near (leaf, face) pairs */
     int64_t n_btv_touch;  /* of which the closed cell and face meet (exact integrals) */
+    int64_t n_vtb_near;   /* VtB near (face, source leaf) pairs */
     int64_t device_bytes; /* device memory held by the plan */
     int32_t K;            /* expansion coefficients per cell, (q+1)(q+2)(q+3)/6 */
     int32_t L;
@@ -240,7 +241,19 @@ bcv_status bcv_tree_faces(bcv_tree tree, int32_t *leaf_axis_side);
 bcv_status bcv_btv_apply(bcv_plan plan, const double *q_face_dev, const double *g_face_dev, double *u_dev,
                          void *hip_stream);
 
-/* Volume-to-boundary apply (Algorithm 2). Not implemented in this build: returns BCV_ENOTSUP. */
+/* Volume-to-boundary apply, Algorithm 2 (BC-FMM for the VtB calculation), degree p = 0 on the
+ * faces: u_f = <1_f, N f_h>_{L2(f)} = int_f int_Omega G(x - y) f_h(y) dy dS_x for every boundary
+ * face f, with f_h piecewise constant on the leaves.
+ *   f_dev: device, n_leaves doubles in leaf order;
+ *   u_face_dev: device, n_faces doubles in bcv_tree_faces order, OVERWRITTEN.
+ * The near sources of a face are the near sources N*(w) of its level-L cell w (Algorithm 1's near
+ * list); their entries are the single-layer entries of bcv_btv_apply (G is symmetric: the
+ * discrete VtB operator is the transpose of the single-layer part of the discrete BtV operator).
+ * The far field: moments of every leaf, upward pass, interaction phase, downward pass, and the local
+ * expansion of w integrated over the face by the 2x2 point rule. Requires opts.boundary = 1 and at
+ * most 2^24 leaves. Stream-ordered on hip_stream, asynchronous, allocates nothing; overwrites the
+ * plan's moment and local-coefficient workspace (no concurrent applies of one plan).
+ * Errors: BCV_EINVAL (NULL pointers), BCV_ESTATE (plan without boundary structures), BCV_EDEVICE. */
 bcv_status bcv_vtb_apply(bcv_plan plan, const double *f_dev, double *u_face_dev, void *hip_stream);
 
 /* The exact single- and double-layer integrals of touching (cell, boundary face) pairs of side 1:

@@ -491,3 +491,31 @@ class VtBFMM(FMM):
         m = self.upward(self.moments(f))
         lam = self.downward(self.interaction(m))
         return self.evaluation_faces(lam, u)
+
+
+def vtb_direct_sampled(mesh, f, face_idx, n=24):
+    """O1 of VtB at the given faces only, with the point rule vectorised over all leaves."""
+    E = Entries(mesh, n)
+    f = np.asarray(f, dtype=np.float64)
+    lv = E.leaves
+    a = np.ldexp(1.0, -lv[:, 0].astype(np.int32))
+    lo = lv[:, 1:4] * a[:, None]
+    # 2x2x2 cell points (n, 8, 3)
+    ref = np.array([[_XI[i], _XI[j], _XI[k]] for k in (0, 1) for j in (0, 1) for i in (0, 1)])
+    cp = lo[:, None, :] + a[:, None, None] * ref[None, :, :]
+    wc = a ** 3 / 8.0
+    out = np.zeros(len(face_idx))
+    for m_, fi in enumerate(face_idx):
+        leaf, ax, side = E.faces[fi]
+        fl, fi_, fj, fk = lv[leaf]
+        fa = np.ldexp(1.0, -int(fl))
+        fp, wf = face_points(np.array([fi_, fj, fk]) * fa, fa, ax, side)
+        r = np.linalg.norm(cp[:, :, None, :] - fp[None, None, :, :], axis=-1)  # (n, 8, 4)
+        V = wc * wf * np.sum(1.0 / r, axis=(1, 2)) / (4.0 * np.pi)
+        # touching leaves: exact (they are level-L leaves within one cell of the face's cell)
+        near = np.nonzero(np.all(np.abs(lv[:, 1:4] - lv[leaf, 1:4]) <= 1, axis=1) & (lv[:, 0] == fl))[0]
+        for t in near:
+            if E.touches(t, fi):
+                V[t] = E.exact(t, fi)[0]
+        out[m_] = V @ f
+    return out

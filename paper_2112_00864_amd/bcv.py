@@ -39,7 +39,7 @@ class PlanOpts(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("n_leaves", "n_cells", "n_near", "n_touch", "n_m2l", "n_m2l_lanes",
                                               "n_offsets", "n_m2l_read_lanes", "n_faces", "n_btv_near",
-                                              "n_btv_touch", "device_bytes")] + [
+                                              "n_btv_touch", "n_vtb_near", "device_bytes")] + [
         ("K", ctypes.c_int32), ("L", ctypes.c_int32), ("surrogate_classes", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
@@ -259,7 +259,10 @@ def vtv_apply_parts(plan, f, u, parts, stream=None):
 
 
 def vtb_apply(plan, f, u_face, stream=None):
-    _check(lib().bcv_vtb_apply(plan.handle, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u_face.data_ptr()),
+    """u_face = <1_f, N f> on every boundary face (Algorithm 2); f per leaf, u_face per face in
+    Tree.faces() order (float64 device tensors; u_face overwritten)."""
+    _check(lib().bcv_vtb_apply(plan.handle, _dev_ptr(f, plan.n_leaves, plan.device, "f"),
+                               _dev_ptr(u_face, plan.info["n_faces"], plan.device, "u_face"),
                                _stream(stream, plan.device)))
 
 

@@ -210,6 +210,7 @@ bcv_status bcv_plan_get_info(bcv_plan plan, bcv_plan_info *info)
         info->n_faces = plan->n_faces;
         info->n_btv_near = plan->n_btv_near;
         info->n_btv_touch = plan->n_btv_touch;
+        info->n_vtb_near = plan->n_vtb_near;
         info->device_bytes = plan->device_bytes;
         info->K = plan->K;
         info->L = plan->L;
@@ -256,11 +257,13 @@ bcv_status bcv_plan_phase_times(bcv_plan plan, double *ms, int64_t *n_applies)
     });
 }
 
-bcv_status bcv_vtb_apply(bcv_plan plan, const double *, double *, void *)
+bcv_status bcv_vtb_apply(bcv_plan plan, const double *f_dev, double *u_face_dev, void *hip_stream)
 {
     return guard([&] {
         check_plan(plan);
-        bcv::fail(BCV_ENOTSUP, "volume-to-boundary apply is not implemented in this build");
+        BCV_REQUIRE(f_dev != nullptr && u_face_dev != nullptr, BCV_EINVAL, "NULL density or face pointer");
+        BCV_REQUIRE(plan->boundary, BCV_ESTATE, "the plan was built without boundary structures (opts.boundary)");
+        on_device(plan->device, [&] { bcv::launch_vtb(*plan, f_dev, u_face_dev, (hipStream_t)hip_stream); });
     });
 }
 

@@ -177,6 +177,12 @@ struct bcv_plan_s {
     bcv::NearSplit *d_btv_splits = nullptr;
     double *d_btv_partial = nullptr;
     double *d_btv_touch = nullptr;      // 2 x kFaceClasses: V, then K, of touching pairs of side 1
+    // VtB (Algorithm 2): near rows of the boundary faces, sources from the near row of the face's cell
+    int64_t n_vtb_near = 0, n_vtb_units = 0, n_vtb_splits = 0;
+    uint32_t *d_vtb_col = nullptr;      // source leaf | (touching class + 1) << 24 (0: point rule)
+    bcv::NearUnit *d_vtb_units = nullptr;  // targets are faces
+    bcv::NearSplit *d_vtb_splits = nullptr;
+    double *d_vtb_partial = nullptr;
 };
 
 // A captured apply (graph.cpp).

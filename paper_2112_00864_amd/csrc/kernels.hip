@@ -830,6 +830,97 @@ __global__ __launch_bounds__(256) void btv_near_kernel(int64_t n_units, const Ne
     }
 }
 
+// ---- VtB (Algorithm 2): face integrals of the volume potential -------------------------------------
+
+// Evaluation at a face of cell w (side a, face type): int_face sum_a lambda^a (y - x_w)^a dS
+// = a^2 sum_a Lambda^a (-1)^|a| phi_type^a (the face table of the boundary moments without the
+// moments' sign); this lane's share of the sum.
+template <int Q>
+__device__ __forceinline__ double eval_face(const double *__restrict__ lam, double a, int type, int lane)
+{
+    constexpr int K = MultiIndex<Q>::K;
+    double s = 0.0;
+    for (int k = lane; k < K; k += kWave) {
+        const double phi = kFaceKappa<Q>.phi[type][k];
+        s = fma((Tables<Q>::mi.deg[k] & 1) ? -phi : phi, lam[k], s);
+    }
+    return s * (a * a);
+}
+
+// u_f = sum over the near sources s of V_sf f_s (touching pairs from the class table, scaled by
+// a^4; the others by the single-layer part of the face point rule), plus the evaluation at the face;
+// one wave per work unit (targets are faces).
+template <int Q, bool kMixed>
+__global__ __launch_bounds__(256) void vtb_near_kernel(int64_t n_units, const NearUnit *__restrict__ units,
+                                                       const uint32_t *__restrict__ col,
+                                                       const uint32_t *__restrict__ faces,
+                                                       const double4 *__restrict__ geom,
+                                                       const double *__restrict__ f, const double *__restrict__ touch,
+                                                       const double *__restrict__ Lam,
+                                                       const int32_t *__restrict__ leaf_cell,
+                                                       double *__restrict__ partial, double *__restrict__ u)
+{
+    constexpr int K = MultiIndex<Q>::K;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (w >= n_units) return;  // uniform per wave
+    const NearUnit un = units[w];
+    const uint32_t fw = faces[un.target];
+    const int32_t leaf = (int32_t)(fw & 0x0FFFFFFFu);
+    const int type = (int)(fw >> 28);
+    const double4 gf = geom[leaf];
+    double acc = 0.0;
+    for (int64_t e = un.begin + lane; e < un.end; e += kWave) {
+        const uint32_t code = col[e];
+        const int32_t s = (int32_t)(code & 0x00FFFFFFu);
+        const uint32_t cls = code >> 24;
+        if (cls) {
+            const double a = gf.w;
+            acc += touch[cls - 1] * (a * a) * (a * a) * f[s];
+        } else {
+            double sv, dv;
+            face_rule<typename std::conditional<kMixed, float, double>::type>(geom[s], gf, type >> 1, type & 1, sv,
+                                                                              dv);
+            acc += sv * f[s];
+        }
+    }
+    if (un.out < 0 && Lam != nullptr) acc += eval_face<Q>(Lam + (int64_t)leaf_cell[leaf] * K, gf.w, type, lane);
+    acc = wave_sum(acc);
+    if (lane == 0) {
+        if (un.out < 0)
+            u[un.target] = acc;
+        else
+            partial[un.out] = acc;
+    }
+}
+
+// Face rows cut into several units: u_f = sum of the partial sums in row order (+ evaluation).
+template <int Q>
+__global__ __launch_bounds__(256) void vtb_combine_kernel(int64_t n_splits, const NearSplit *__restrict__ splits,
+                                                          const double *__restrict__ partial,
+                                                          const uint32_t *__restrict__ faces,
+                                                          const double4 *__restrict__ geom,
+                                                          const double *__restrict__ Lam,
+                                                          const int32_t *__restrict__ leaf_cell,
+                                                          double *__restrict__ u)
+{
+    constexpr int K = MultiIndex<Q>::K;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (w >= n_splits) return;  // uniform per wave
+    const NearSplit sp = splits[w];
+    const uint32_t fw = faces[sp.target];
+    const int32_t leaf = (int32_t)(fw & 0x0FFFFFFFu);
+    double far = 0.0;
+    if (Lam != nullptr)
+        far = wave_sum(eval_face<Q>(Lam + (int64_t)leaf_cell[leaf] * K, geom[leaf].w, (int)(fw >> 28), lane));
+    if (lane == 0) {
+        double acc = 0.0;
+        for (int k = 0; k < sp.count; ++k) acc += partial[sp.first + k];
+        u[sp.target] = acc + far;
+    }
+}
+
 // ---- plan-time assembly of the near-pair entries --------------------------------------------------
 __global__ __launch_bounds__(256) void near_assemble_kernel(int64_t n_units, const NearUnit *__restrict__ units,
                                                             const uint32_t *__restrict__ col,
@@ -1140,7 +1231,50 @@ void btv_q(const bcv_plan_s &p, const double *qf, const double *gf, double *u, h
     }
 }
 
+// VtB apply (Algorithm 2), on the caller's stream: moments of every leaf, upward pass, interaction
+// phase and downward pass (for every cell; the boundary cells' coefficients are the ones used),
+// then the near field of the faces fused with the evaluation at the faces.
+template <int Q>
+void vtb_q(const bcv_plan_s &p, const double *f, double *uf, hipStream_t st)
+{
+    constexpr int K = MultiIndex<Q>::K;
+    const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
+    const bool far = !p.direct;
+    if (far) {
+        const int64_t nthr = p.n_leaves * K;
+        p2m_kernel<Q><<<(unsigned)((nthr + 255) / 256), 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, f, p.d_M);
+        check_launch();
+        upward_pass<Q>(p, st);
+        interaction_phase<Q>(p, st);
+        downward_pass<Q>(p, st);
+    }
+    const double *lam = far ? p.d_Lam : nullptr;
+    const unsigned blocks = (unsigned)((p.n_vtb_units + 3) / 4);
+    if (p.precision == BCV_MIXED_F32)
+        vtb_near_kernel<Q, true><<<blocks, 256, 0, st>>>(p.n_vtb_units, p.d_vtb_units, p.d_vtb_col, p.d_faces, geom, f,
+                                                         p.d_btv_touch, lam, p.d_leaf_cell, p.d_vtb_partial, uf);
+    else
+        vtb_near_kernel<Q, false><<<blocks, 256, 0, st>>>(p.n_vtb_units, p.d_vtb_units, p.d_vtb_col, p.d_faces, geom, f,
+                                                          p.d_btv_touch, lam, p.d_leaf_cell, p.d_vtb_partial, uf);
+    check_launch();
+    if (p.n_vtb_splits > 0) {
+        vtb_combine_kernel<Q><<<(unsigned)((p.n_vtb_splits + 3) / 4), 256, 0, st>>>(
+            p.n_vtb_splits, p.d_vtb_splits, p.d_vtb_partial, p.d_faces, geom, lam, p.d_leaf_cell, uf);
+        check_launch();
+    }
+}
+
 }  // namespace
+
+void launch_vtb(const bcv_plan_s &p, const double *f, double *uf, hipStream_t st)
+{
+    switch (p.q) {
+    case 4: vtb_q<4>(p, f, uf, st); break;
+    case 6: vtb_q<6>(p, f, uf, st); break;
+    case 8: vtb_q<8>(p, f, uf, st); break;
+    default: fail(BCV_ENOTSUP, "expansion order not compiled");
+    }
+}
 
 void launch_btv(const bcv_plan_s &p, const double *qf, const double *gf, double *u, hipStream_t st)
 {

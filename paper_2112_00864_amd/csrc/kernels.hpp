@@ -9,6 +9,8 @@ namespace bcv {
 void launch_apply(const bcv_plan_s &p, const double *f, double *u, int parts, hipStream_t stream);
 // BtV apply (Algorithm 3): u = <1_w, V[q] - K[g]> from face data qf, gf (device, n_faces each).
 void launch_btv(const bcv_plan_s &p, const double *qf, const double *gf, double *u, hipStream_t stream);
+// VtB apply (Algorithm 2): uf = <1_f, N f> on every boundary face from leaf densities f.
+void launch_vtb(const bcv_plan_s &p, const double *f, double *uf, hipStream_t stream);
 
 // Stores every near-pair Galerkin entry of the plan in p.d_val (plan time).
 void launch_near_assemble(const bcv_plan_s &p, hipStream_t stream);

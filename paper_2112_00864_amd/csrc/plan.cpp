@@ -564,7 +564,55 @@ struct BtvNear {
     std::vector<uint32_t> faces;     // leaf | (2 axis + side) << 28
     std::vector<int32_t> leaf_faces; // n_leaves + 1
     NearCSR near;                    // col: face | (touching class + 1) << 24
+    NearCSR vtb;                     // rows: faces; col: source leaf | (touching class + 1) << 24
 };
+
+// The class of the boundary face (type, of the level-L cell fc) against the volume cell c, or -1
+// if the closed cell and face do not meet.
+int face_touch_class(const bcv_tree_s &t, int32_t c, int32_t fc, int type)
+{
+    if (t.level[c] != t.level[fc]) return -1;  // cells meeting the boundary all have level L
+    const int ax = type >> 1, side = type & 1;
+    int o[3];
+    for (int d = 0; d < 3; ++d) {
+        o[d] = t.ijk[3 * fc + d] - t.ijk[3 * c + d];
+        if (o[d] < -1 || o[d] > 1) return -1;
+    }
+    for (int d = 0; d < 3; ++d) {
+        const int flo = d == ax ? o[d] + side : o[d], fhi = d == ax ? o[d] + side : o[d] + 1;
+        if (std::max(flo, 0) > std::min(fhi, 1)) return -1;
+    }
+    return face_class(o, ax, side);
+}
+
+// VtB (Algorithm 2) near rows: a face's target is its level-L cell w, whose near sources are the
+// leaves of N*(w), the volume near row of w; the entries are the single-layer ones of BtV.
+void build_vtb_near(const bcv_tree_s &t, const NearCSR &vol, BtvNear &r)
+{
+    const int64_t nf = (int64_t)r.faces.size();
+    BCV_REQUIRE(t.n_leaves() < (1 << 24), BCV_ENOTSUP, "VtB: more than 2^24 leaves");
+    r.vtb.row.assign(nf + 1, 0);
+    for (int64_t f = 0; f < nf; ++f) {
+        const int32_t leaf = (int32_t)(r.faces[f] & 0x0FFFFFFFu);
+        r.vtb.row[f + 1] = r.vtb.row[f] + (vol.row[leaf + 1] - vol.row[leaf]);
+    }
+    r.vtb.col.resize(r.vtb.row[nf]);
+    int64_t touch = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : touch)
+    for (int64_t f = 0; f < nf; ++f) {
+        const int32_t leaf = (int32_t)(r.faces[f] & 0x0FFFFFFFu);
+        const int type = (int)(r.faces[f] >> 28);
+        const int32_t fc = t.leaf_cell[leaf];
+        int64_t out = r.vtb.row[f];
+        for (int64_t e = vol.row[leaf]; e < vol.row[leaf + 1]; ++e) {
+            const int32_t s = (int32_t)(vol.col[e] & 0x0FFFFFFFu);
+            const int cls = face_touch_class(t, t.leaf_cell[s], fc, type);
+            touch += cls >= 0;
+            r.vtb.col[out++] = (uint32_t)s | ((uint32_t)(cls + 1) << 24);
+        }
+    }
+    r.vtb.n_touch = touch;
+}
 
 BtvNear build_btv_near(const bcv_tree_s &t, const std::vector<Grid> &g, bool direct)
 {
@@ -599,25 +647,13 @@ BtvNear build_btv_near(const bcv_tree_s &t, const std::vector<Grid> &g, bool dir
             }
             BCV_REQUIRE(hi[c] - lo[c] == count[c], BCV_ESTATE, "internal: subtree leaves not consecutive");
         }
-    const int32_t L = t.L;
     auto on_boundary = [](int lev, const int32_t *c) {
         const int32_t top = (1 << lev) - 1;
         return c[0] == 0 || c[1] == 0 || c[2] == 0 || c[0] == top || c[1] == top || c[2] == top;
     };
-    // class of (leaf cell c at level L, face f), or -1 if they do not meet
+    // class of (leaf cell c, face f), or -1 if they do not meet
     auto touch_class = [&](int32_t c, int64_t f) {
-        const int32_t fc = t.leaf_cell[r.faces[f] & 0x0FFFFFFFu];
-        const int type = (int)(r.faces[f] >> 28), ax = type >> 1, side = type & 1;
-        int o[3];
-        for (int d = 0; d < 3; ++d) {
-            o[d] = t.ijk[3 * fc + d] - t.ijk[3 * c + d];
-            if (o[d] < -1 || o[d] > 1) return -1;
-        }
-        for (int d = 0; d < 3; ++d) {
-            const int flo = d == ax ? o[d] + side : o[d], fhi = d == ax ? o[d] + side : o[d] + 1;
-            if (std::max(flo, 0) > std::min(fhi, 1)) return -1;
-        }
-        return face_class(o, ax, side);
+        return face_touch_class(t, c, t.leaf_cell[r.faces[f] & 0x0FFFFFFFu], (int)(r.faces[f] >> 28));
     };
     auto gen = [&](int64_t q, std::vector<uint32_t> &out) {
         out.clear();
@@ -625,7 +661,7 @@ BtvNear build_btv_near(const bcv_tree_s &t, const std::vector<Grid> &g, bool dir
         const int lev = t.level[c];
         auto add = [&](int64_t f0, int64_t f1) {
             for (int64_t f = f0; f < f1; ++f) {
-                const int cls = lev == L ? touch_class(c, f) : -1;
+                const int cls = touch_class(c, f);
                 out.push_back((uint32_t)f | ((uint32_t)(cls + 1) << 24));
             }
         };
@@ -724,6 +760,7 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
     p->d_leaf_geom = upload(p.get(), lg);
     p->d_leaf_cell = upload(p.get(), t.leaf_cell);
 
+    NearCSR vol_near;  // kept for the VtB rows
     {
         NearCSR near = build_near(t, grids, geo, opts.direct != 0);
         p->n_near = (int64_t)near.col.size();
@@ -736,6 +773,7 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         p->d_units = upload(p.get(), nu.units);
         p->d_splits = upload(p.get(), nu.splits);
         if (nu.n_partial > 0) p->d_partial = alloc_zero<double>(p.get(), (size_t)nu.n_partial);
+        if (opts.boundary) vol_near = std::move(near);
     }
 
     if (!opts.direct) {
@@ -813,6 +851,16 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         std::vector<double> tv(2 * kFaceClasses);
         boundary_touching_integrals(tv.data(), tv.data() + kFaceClasses);
         p->d_btv_touch = upload(p.get(), tv);
+        build_vtb_near(t, vol_near, bn);
+        p->n_vtb_near = (int64_t)bn.vtb.col.size();
+        p->d_vtb_col = upload(p.get(), bn.vtb.col);
+        const NearUnits vu =
+            build_near_units(bn.vtb, p->n_faces, opts.near_unit > 0 ? opts.near_unit : kDefaultNearUnit);
+        p->n_vtb_units = (int64_t)vu.units.size();
+        p->n_vtb_splits = (int64_t)vu.splits.size();
+        p->d_vtb_units = upload(p.get(), vu.units);
+        p->d_vtb_splits = upload(p.get(), vu.splits);
+        if (vu.n_partial > 0) p->d_vtb_partial = alloc_zero<double>(p.get(), (size_t)vu.n_partial);
     }
 
     if (opts.nearfield == BCV_NEAR_ASSEMBLED) {
@@ -837,7 +885,8 @@ void destroy_plan(bcv_plan_s *p)
                     p->d_M32, p->d_G32,
                     p->d_parents, p->d_tasks, p->d_task_targets, p->d_slot_off, p->d_slot_src,
                     p->d_m2l_splits, p->d_m2l_partial, p->d_faces, p->d_leaf_faces, p->d_btv_col,
-                    p->d_btv_units, p->d_btv_splits, p->d_btv_partial, p->d_btv_touch};
+                    p->d_btv_units, p->d_btv_splits, p->d_btv_partial, p->d_btv_touch, p->d_vtb_col,
+                    p->d_vtb_units, p->d_vtb_splits, p->d_vtb_partial};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     p->magic = 0;

@@ -1,4 +1,5 @@
-"""Parity of the BtV apply (Algorithm 3, bcv_btv_apply) with the CPU oracle, on cuda:0.
+"""Parity of the BtV and VtB applies (Algorithms 3 and 2, bcv_btv_apply, bcv_vtb_apply) with the
+CPU oracle, on cuda:0.
 
 Bar: FP64 relative L2(Omega) error <= 1e-10 against the oracle computing the same operator (O1 for
 direct mode, O2 for the FMM); mixed precision <= 1e-6 against the FP64 path.
@@ -134,3 +135,83 @@ def test_representation_formula():
     err = np.linalg.norm(u / vol - avg) / np.linalg.norm(avg)
     announce("BtV representation formula L=5: rel err %.3e" % err)
     assert err < 1e-3
+
+
+def gpu_vtb(plan, f):
+    import torch
+
+    fd = torch.tensor(f, device="cuda:0")
+    u = torch.full((plan.info["n_faces"],), float("nan"), dtype=torch.float64, device="cuda:0")
+    bcv.vtb_apply(plan, fd, u)
+    torch.cuda.synchronize()
+    return u.cpu().numpy()
+
+
+def rel(u, ref):
+    return float(np.linalg.norm(u - ref) / np.linalg.norm(ref))
+
+
+@pytest.mark.parametrize("L", [2, 3])
+def test_vtb_direct_mode_matches_O1(L):
+    m, lv, t, qf, gf = case(L)
+    f = synth.leaf_density(lv, seed=0)
+    announce("VtB direct plan L=%d" % L)
+    plan = bcv.plan_interactions(t, q=4, direct=True, boundary=True)
+    assert plan.info["n_vtb_near"] == len(lv) * len(qf)
+    err = rel(gpu_vtb(plan, f), B.vtb_direct(m, f))
+    announce("VtB direct L=%d rel %.3e" % (L, err))
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("L,q", [(2, 4), (2, 6), (3, 4)])
+def test_vtb_fmm_matches_O2(L, q):
+    m, lv, t, qf, gf = case(L)
+    f = synth.leaf_density(lv, seed=0)
+    announce("VtB FMM plan L=%d q=%d" % (L, q))
+    u = gpu_vtb(bcv.plan_interactions(t, q=q, boundary=True), f)
+    ref = B.VtBFMM(m, q).apply(f)
+    err = rel(u, ref)
+    announce("VtB FMM L=%d q=%d rel %.3e, max rel %.3e" % (L, q, err, np.max(np.abs(u - ref) / np.abs(ref))))
+    assert err <= TOL
+
+
+def test_vtb_is_the_adjoint_of_the_btv_single_layer():
+    """<VtB f, q> = <f, BtV(q, 0)> for the GPU FMM at h = 1/32 (the fixed-q operator is symmetric);
+    mixed precision within 1e-6 of FP64."""
+    import torch
+
+    L = 5
+    t = bcv.build_bc_tree(L)
+    lv = t.leaves().astype(np.int64)
+    f = synth.leaf_density(lv, seed=2)
+    nf = len(t.faces())
+    q = np.random.default_rng(4).standard_normal(nf)
+    announce("VtB/BtV adjoint L=5 q=6")
+    plan = bcv.plan_interactions(t, q=6, boundary=True)
+    uf = gpu_vtb(plan, f)
+    ub = gpu_btv(plan, q, np.zeros(nf))
+    lhs, rhs = uf @ q, f @ ub
+    announce("VtB/BtV adjoint: %.16e vs %.16e (rel %.2e)" % (lhs, rhs, abs(lhs - rhs) / abs(lhs)))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    u32 = gpu_vtb(bcv.plan_interactions(t, q=6, boundary=True, precision=bcv.MIXED_F32), f)
+    err = rel(u32, uf)
+    announce("VtB mixed vs FP64 L=5 rel %.3e" % err)
+    assert err <= 1e-6
+    del torch
+
+
+def test_vtb_full_size_sampled():
+    """h = 1/128: the VtB FMM at two sampled faces against O1 at those faces (truncation error at
+    q = 6, stated about 1e-6)."""
+    L = 7
+    m = BCMesh(L)
+    lv = m.leaf_array()
+    t = bcv.build_bc_tree(L)
+    f = synth.leaf_density(lv, seed=0)
+    announce("VtB full-size plan L=7 q=6")
+    u = gpu_vtb(bcv.plan_interactions(t, q=6, boundary=True), f)
+    fi = np.array([0, len(u) - 1])
+    ref = B.vtb_direct_sampled(m, f, fi)
+    err = np.max(np.abs(u[fi] - ref) / np.abs(ref))
+    announce("VtB full-size FMM vs O1 at 2 faces: max rel %.3e" % err)
+    assert err < 1e-4
