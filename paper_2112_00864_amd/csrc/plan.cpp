@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <array>
+#include <unordered_map>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -319,6 +320,7 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, int32_t max_s
     struct Chunk {
         int lev;
         int axis;  // rows of the task run along this axis
+        int step;  // consecutive lanes of a row are this many cells apart (1 or 2)
         std::vector<int32_t> cells;
     };
     std::vector<Chunk> chunks;
@@ -338,60 +340,102 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, int32_t max_s
         std::vector<int32_t> order(n);
         for (int32_t q = 0; q < n; ++q) order[q] = q;
         std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return sig[x] < sig[y]; });
-        std::vector<Chunk> level_chunks;
-        std::vector<Chunk> remainders;
+        struct Class {
+            int32_t s0, s1;  // range in order
+            int axis;
+        };
+        std::vector<Class> classes;
+        std::unordered_map<uint64_t, int32_t> class_of_sig;
         for (int32_t s0 = 0; s0 < n;) {
             int32_t s1 = s0;
             while (s1 < n && sig[order[s1]] == sig[order[s0]]) ++s1;
             // the class in rows along the axis with the most member pairs two cells apart (x first on
             // ties); a class may span several separate patches of the level
             int axis = 0;
-            {
-                int64_t pairs[3] = {0, 0, 0};
-                for (int32_t r = s0; r < s1; ++r) {
-                    const int32_t *c = &t.ijk[3 * (b + order[r])];
-                    for (int ax = 0; ax < 3; ++ax) {
-                        const int32_t nb = g[lev].at(c[0] + 2 * (ax == 0), c[1] + 2 * (ax == 1), c[2] + 2 * (ax == 2));
-                        pairs[ax] += nb >= 0 && sig[nb - b] == sig[order[s0]];
-                    }
+            int64_t pairs[3] = {0, 0, 0};
+            for (int32_t r = s0; r < s1; ++r) {
+                const int32_t *c = &t.ijk[3 * (b + order[r])];
+                for (int ax = 0; ax < 3; ++ax) {
+                    const int32_t nb = g[lev].at(c[0] + 2 * (ax == 0), c[1] + 2 * (ax == 1), c[2] + 2 * (ax == 2));
+                    pairs[ax] += nb >= 0 && sig[nb - b] == sig[order[s0]];
                 }
-                for (int ax = 1; ax < 3; ++ax)
-                    if (pairs[ax] > pairs[axis]) axis = ax;
-                const int u = axis == 0 ? 2 : (axis == 1 ? 2 : 1), v = axis == 0 ? 1 : 0;
-                std::sort(order.begin() + s0, order.begin() + s1, [&](int32_t x, int32_t y) {
-                    const int32_t *a = &t.ijk[3 * (b + x)], *c = &t.ijk[3 * (b + y)];
-                    if (a[u] != c[u]) return a[u] < c[u];
-                    if (a[v] != c[v]) return a[v] < c[v];
-                    return a[axis] < c[axis];
-                });
             }
-            int32_t q = s0;
-            for (; q + 64 <= s1; q += 64) {
-                Chunk ch{lev, axis, {}};
-                for (int32_t r = q; r < q + 64; ++r) ch.cells.push_back(b + order[r]);
-                level_chunks.push_back(std::move(ch));
-            }
-            if (q < s1) {
-                Chunk rem{lev, axis, {}};
-                for (int32_t r = q; r < s1; ++r) rem.cells.push_back(b + order[r]);
-                remainders.push_back(std::move(rem));
-            }
+            for (int ax = 1; ax < 3; ++ax)
+                if (pairs[ax] > pairs[axis]) axis = ax;
+            class_of_sig[sig[order[s0]]] = (int32_t)classes.size();
+            classes.push_back(Class{s0, s1, axis});
             s0 = s1;
+        }
+        // A class of at least 64 cells whose members' neighbours one cell further along its axis
+        // form one other class of the same size and axis (the cells of the other child position,
+        // e.g. in the interior of a face) is merged with it: rows then step by one cell, so runs of
+        // offsets are twice as long and rows twice as dense, for a slightly larger union of lists.
+        std::vector<int32_t> partner(classes.size(), -1);
+        auto class_of = [&](int32_t cell) -> int32_t {
+            const int32_t *c = &t.ijk[3 * cell];
+            (void)c;
+            return class_of_sig.at(sig[cell - b]);
+        };
+        for (size_t k = 0; k < classes.size(); ++k) {
+            const Class &C = classes[k];
+            if (C.s1 - C.s0 < 64 || partner[k] >= 0) continue;
+            const int ax = C.axis;
+            int32_t cand = -1;
+            bool ok = true;
+            for (int32_t r = C.s0; r < C.s1 && ok; ++r) {
+                const int32_t *c = &t.ijk[3 * (b + order[r])];
+                const int32_t nb = g[lev].at(c[0] + (ax == 0), c[1] + (ax == 1), c[2] + (ax == 2));
+                if (nb < 0) continue;
+                const int32_t pc = class_of(nb);
+                if (cand < 0) cand = pc;
+                ok = pc == cand;
+            }
+            if (!ok || cand < 0 || cand == (int32_t)k || partner[cand] >= 0) continue;
+            const Class &P = classes[cand];
+            if (P.axis != ax || P.s1 - P.s0 != C.s1 - C.s0) continue;
+            partner[k] = cand;
+            partner[cand] = (int32_t)k;
+        }
+        std::vector<Chunk> level_chunks;
+        std::vector<Chunk> remainders;
+        for (size_t k = 0; k < classes.size(); ++k) {
+            if (partner[k] >= 0 && partner[k] < (int32_t)k) continue;  // merged into its partner's rows
+            const Class &C = classes[k];
+            const int axis = C.axis, step = partner[k] >= 0 ? 1 : 2;
+            std::vector<int32_t> cells;
+            for (int32_t r = C.s0; r < C.s1; ++r) cells.push_back(b + order[r]);
+            if (partner[k] >= 0)
+                for (int32_t r = classes[partner[k]].s0; r < classes[partner[k]].s1; ++r) cells.push_back(b + order[r]);
+            const int u = axis == 0 ? 2 : (axis == 1 ? 2 : 1), v = axis == 0 ? 1 : 0;
+            std::sort(cells.begin(), cells.end(), [&](int32_t x, int32_t y) {
+                const int32_t *a = &t.ijk[3 * x], *c = &t.ijk[3 * y];
+                if (a[u] != c[u]) return a[u] < c[u];
+                if (a[v] != c[v]) return a[v] < c[v];
+                return a[axis] < c[axis];
+            });
+            size_t q = 0;
+            for (; q + 64 <= cells.size(); q += 64)
+                level_chunks.push_back(Chunk{lev, axis, step, std::vector<int32_t>(cells.begin() + q, cells.begin() + q + 64)});
+            if (q < cells.size())
+                remainders.push_back(Chunk{lev, axis, step, std::vector<int32_t>(cells.begin() + q, cells.end())});
         }
         // the remainders (most are whole classes: the rows of cells along the edges of the domain,
         // single cells near its corners and on the coarse levels) share tasks with remainders of
         // the same row axis, in Morton order, which keeps similar lists together (a first fit by
         // decreasing size that minimised the added offsets saved under 1% of the slots)
         std::sort(remainders.begin(), remainders.end(), [](const Chunk &x, const Chunk &y) {
+            if (x.step != y.step) return x.step < y.step;
             return x.axis != y.axis ? x.axis < y.axis : x.cells[0] < y.cells[0];
         });
-        Chunk cur{lev, 0, {}};
+        Chunk cur{lev, 0, 2, {}};
         for (auto &rem : remainders) {
-            if (!cur.cells.empty() && (cur.axis != rem.axis || cur.cells.size() + rem.cells.size() > 64)) {
+            if (!cur.cells.empty() &&
+                (cur.axis != rem.axis || cur.step != rem.step || cur.cells.size() + rem.cells.size() > 64)) {
                 level_chunks.push_back(std::move(cur));
-                cur = Chunk{lev, rem.axis, {}};
+                cur = Chunk{lev, rem.axis, rem.step, {}};
             }
             cur.axis = rem.axis;
+            cur.step = rem.step;
             cur.cells.insert(cur.cells.end(), rem.cells.begin(), rem.cells.end());
         }
         if (!cur.cells.empty()) level_chunks.push_back(std::move(cur));
@@ -423,12 +467,12 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, int32_t max_s
                 for (int32_t key : lane_keys[lane]) used[key] = 1;
             }
             Out &o = outs[q];
-            for (int lane = 0; lane < nl; ++lane) {  // heads: the previous lane is not two cells back
+            for (int lane = 0; lane < nl; ++lane) {  // heads: the previous lane is not `step` cells back
                 bool head = lane == 0;
                 if (!head) {
                     const int32_t a = ch.cells[lane - 1], c = ch.cells[lane];
                     for (int k = 0; k < 3; ++k)
-                        head = head || t.ijk[3 * c + k] - t.ijk[3 * a + k] != (k == ax ? 2 : 0);
+                        head = head || t.ijk[3 * c + k] - t.ijk[3 * a + k] != (k == ax ? ch.step : 0);
                 }
                 if (head) o.heads |= 1ull << lane;
             }
@@ -436,7 +480,7 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, int32_t max_s
             for (int key = 0; key < 15 * 15 * 15; ++key) {
                 if (!used[key]) continue;
                 const int d[3] = {key / 225 - 7, (key / 15) % 15 - 7, key % 15 - 7};
-                order.push_back({d[u], d[v], d[ax] & 1, d[ax], key});
+                order.push_back({d[u], d[v], ch.step == 2 ? d[ax] & 1 : 0, d[ax], key});
             }
             std::sort(order.begin(), order.end());
             for (size_t k = 0; k < order.size(); ++k) {
