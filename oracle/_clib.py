@@ -30,8 +30,13 @@ def lib():
         _lib = ctypes.CDLL(build())
         i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
         f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
-        _lib.o1_entries.argtypes = [ctypes.c_int64, i64p, i64p, i64p, i64p, f64p, f64p, f64p, f64p]
+        vp = ctypes.c_void_p  # the Gauss order array and its tables (NULL for the 2x2x2 rule)
+        _lib.o1_entries.argtypes = [ctypes.c_int64, i64p, i64p, i64p, i64p, f64p, f64p, f64p, vp, vp, vp, f64p]
         _lib.o1_entries.restype = ctypes.c_int
-        _lib.o1_apply.argtypes = [ctypes.c_int64, i64p, i64p, f64p, f64p, f64p, f64p, ctypes.c_int64, i64p, f64p]
+        _lib.o1_apply.argtypes = [ctypes.c_int64, i64p, i64p, f64p, f64p, f64p, vp, vp, vp, f64p, ctypes.c_int64,
+                                  i64p, f64p]
         _lib.o1_apply.restype = ctypes.c_int
+        _lib.o1_gauss_rule.argtypes = [f64p, ctypes.c_double, ctypes.c_int, f64p, ctypes.c_double, ctypes.c_int, f64p,
+                                       f64p]
+        _lib.o1_gauss_rule.restype = ctypes.c_double
     return _lib

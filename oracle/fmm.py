@@ -15,6 +15,9 @@ of the ancestors that meet in an interaction list, integrated with the same poin
 the near field; as q grows the result tends to O1 (oracle.direct).
 
 Expansion order q is fixed across levels (the paper's q_l schedule is not used here).
+near_order=1 gives the near field the level-dependent Gauss rule of oracle.direct (n_l = 2 + L - l
+points per axis on a level-l leaf); the moments and the evaluation keep the 2x2x2 rule, so the
+result then tends to oracle.direct.apply_near_order as q grows.
 `apply` runs every phase over every cell. `apply_sampled` runs the moment and upward phases
 over every cell and then the interaction, downward and evaluation phases only along the
 ancestor chains of the given target leaves, which yields the same numbers for those leaves.
@@ -29,11 +32,13 @@ _CHILD_POS = [(dx, dy, dz) for dz in (0, 1) for dy in (0, 1) for dx in (0, 1)]
 
 
 class FMM:
-    def __init__(self, mesh, q):
+    def __init__(self, mesh, q, near_order=0):
         self.mesh = mesh
         self.q = q
+        self.near_order = near_order
         self.K = n_coeffs(q)
         self.leaves = mesh.leaf_array()
+        self.orders = None if near_order == 0 else direct.near_gauss_orders(self.leaves, mesh.L, near_order)
         self._cache = {}
         self._rows = self._leaf_rows()
 
@@ -104,7 +109,7 @@ class FMM:
                 si.append(mesh.leaf_index[s])
         ti = np.array(ti, dtype=np.int64)
         si = np.array(si, dtype=np.int64)
-        vals = direct.entries(self.leaves, mesh.L, np.asarray(targets, dtype=np.int64)[ti], si)
+        vals = direct.entries(self.leaves, mesh.L, np.asarray(targets, dtype=np.int64)[ti], si, self.orders)
         return np.bincount(ti, weights=vals * f[si], minlength=len(targets))
 
     def moments(self, f):
@@ -223,6 +228,6 @@ class FMM:
         return u
 
 
-def apply(mesh, f, q, targets=None):
-    fm = FMM(mesh, q)
+def apply(mesh, f, q, targets=None, near_order=0):
+    fm = FMM(mesh, q, near_order)
     return fm.apply(f) if targets is None else fm.apply_sampled(f, targets)

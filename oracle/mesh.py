@@ -11,8 +11,11 @@ Concentrated FMM), written for axis-aligned cubes of the unit cube [0,1]^3:
     w; at level 0, C_0 minus N(w) (Sec. 2, after eq. spaceDecomp:Om);
   * N_L(w), N_M(w) and the extended neighbour list N*(w) (Sec. 3, before Lemma 1).
 
-Marking reading: M_l = B_l for l < L (cells with a face on the boundary are refined). A
-marked source in N_M(w) stands for all of its leaf descendants, since the density lives
+Marking rules (l < L):
+  marking=0  M_l = B_l: cells with a face on the boundary are refined (the default);
+  marking=1  M_l = {w in C_l : N(w) meets B_l}: cells with a boundary cell among their
+             neighbours are refined (Sec. 2, the definition of M_l).
+A marked source in N_M(w) stands for all of its leaf descendants, since the density lives
 on leaves.
 
 A cell is a tuple (i, j, k) at a level l; it is the cube [i, i+1] x [j, j+1] x [k, k+1]
@@ -64,10 +67,13 @@ def parent(c):
 class BCMesh:
     """The BC refinement of the unit cube down to level L (Sec. 2)."""
 
-    def __init__(self, L):
+    def __init__(self, L, marking=0):
         if not 1 <= L <= 9:
             raise ValueError("L must be in 1..9")
+        if marking not in (0, 1):
+            raise ValueError("marking must be 0 or 1")
         self.L = L
+        self.marking = marking
         self.levels = []  # level -> list of cells (i,j,k), Morton order at that level
         self.index = []  # level -> {cell: position}
         self.refined = []  # level -> set of marked cells M_l (empty at level L)
@@ -76,8 +82,10 @@ class BCMesh:
             cells = sorted(cells, key=lambda c, b=lev: morton_key(*c, b))
             self.levels.append(cells)
             self.index.append({c: n for n, c in enumerate(cells)})
-            if lev < L:
+            if lev < L and marking == 0:
                 marked = [c for c in cells if self.on_boundary(lev, c)]  # M_l = B_l
+            elif lev < L:  # M_l: some neighbour in C_l is a boundary cell
+                marked = [c for c in cells if any(self.on_boundary(lev, nb) for nb in self.neighbours(lev, c))]
             else:
                 marked = []  # every level-L cell is a leaf: L*_L = C_L
             self.refined.append(set(marked))

@@ -8,6 +8,11 @@
  * with the 2x2x2 Gauss-Legendre rule on each cube (w_g = a^3 / 8).
  * The seven class constants are passed in (computed by oracle/touching.py).
  *
+ * Level-dependent near-field order (Sec. 4, the near-field quadrature paragraph: fixed order on the
+ * finest level, raised on coarser levels): when an order array is given, a non-touching pair takes
+ * the n_t^3-point Gauss rule on t and the n_s^3-point rule on s, n = order[leaf], with nodes and
+ * weights on [0, 1] passed in (row n of two 17 x 16 tables, from numpy's Gauss-Legendre routine).
+ *
  * Leaves are described by integer lower corners and sides at level-L resolution (for the
  * touching test, exact) and by floating lower corners and sides (for the point rule).
  * Plain loops; OpenMP over targets only (each target's sum is one thread's fixed-order loop).
@@ -53,8 +58,37 @@ double o1_point_rule(const double *lo_t, double a_t, const double *lo_s, double 
     return wt * ws * sum / (4.0 * M_PI);
 }
 
+/* sum_{g in t} sum_{g' in s} w_g w_g' / (4 pi |x_g - y_g'|), tensor rules of n_t and n_s points per axis. */
+double o1_gauss_rule(const double *lo_t, double a_t, int n_t, const double *lo_s, double a_s, int n_s,
+                     const double *gx, const double *gw)
+{
+    const double *xt = gx + 16 * n_t, *wt = gw + 16 * n_t, *xs = gx + 16 * n_s, *ws = gw + 16 * n_s;
+    double sum = 0.0;
+    for (int i3 = 0; i3 < n_t; ++i3)
+        for (int i2 = 0; i2 < n_t; ++i2)
+            for (int i1 = 0; i1 < n_t; ++i1) {
+                double inner = 0.0;
+                for (int j3 = 0; j3 < n_s; ++j3)
+                    for (int j2 = 0; j2 < n_s; ++j2)
+                        for (int j1 = 0; j1 < n_s; ++j1) {
+                            double dx = (lo_t[0] + a_t * xt[i1]) - (lo_s[0] + a_s * xs[j1]);
+                            double dy = (lo_t[1] + a_t * xt[i2]) - (lo_s[1] + a_s * xs[j2]);
+                            double dz = (lo_t[2] + a_t * xt[i3]) - (lo_s[2] + a_s * xs[j3]);
+                            inner += ws[j1] * ws[j2] * ws[j3] / sqrt(dx * dx + dy * dy + dz * dz);
+                        }
+                sum += wt[i1] * wt[i2] * wt[i3] * inner;
+            }
+    return sum * (a_t * a_t * a_t) * (a_s * a_s * a_s) / (4.0 * M_PI);
+}
+
+/* Gauss orders per leaf (NULL: the 2x2x2 rule everywhere) and the node / weight tables. */
+typedef struct {
+    const int32_t *order;
+    const double *gx, *gw;
+} rule_t;
+
 static double entry(int64_t t, int64_t s, const int64_t *lo_int, const int64_t *size,
-                    const double *lo, const double *a, const double *consts, int *bad)
+                    const double *lo, const double *a, const double *consts, const rule_t *r, int *bad)
 {
     int c = o1_touch_class(lo_int + 3 * t, size[t], lo_int + 3 * s, size[s]);
     if (c == -2) { *bad = 1; return 0.0; }
@@ -62,18 +96,23 @@ static double entry(int64_t t, int64_t s, const int64_t *lo_int, const int64_t *
         double as = a[t] < a[s] ? a[t] : a[s];
         return consts[c] * as * as * as * as * as / (4.0 * M_PI);
     }
+    if (r->order && (r->order[t] != 2 || r->order[s] != 2))
+        return o1_gauss_rule(lo + 3 * t, a[t], r->order[t], lo + 3 * s, a[s], r->order[s], r->gx, r->gw);
     return o1_point_rule(lo + 3 * t, a[t], lo + 3 * s, a[s]);
 }
 
-/* out[p] = A_{ti[p], si[p]} for n pairs. Returns 0, or 1 if a touching pair breaks 2:1 balance. */
+/* out[p] = A_{ti[p], si[p]} for n pairs. Returns 0, or 1 if a touching pair breaks 2:1 balance.
+ * order, gx, gw: see rule_t (order may be NULL). */
 int o1_entries(int64_t n, const int64_t *ti, const int64_t *si, const int64_t *lo_int,
-               const int64_t *size, const double *lo, const double *a, const double *consts, double *out)
+               const int64_t *size, const double *lo, const double *a, const double *consts,
+               const int32_t *order, const double *gx, const double *gw, double *out)
 {
+    const rule_t r = {order, gx, gw};
     int bad = 0;
 #pragma omp parallel for schedule(static) reduction(| : bad)
     for (int64_t p = 0; p < n; ++p) {
         int b = 0;
-        out[p] = entry(ti[p], si[p], lo_int, size, lo, a, consts, &b);
+        out[p] = entry(ti[p], si[p], lo_int, size, lo, a, consts, &r, &b);
         bad |= b;
     }
     return bad;
@@ -81,15 +120,17 @@ int o1_entries(int64_t n, const int64_t *ti, const int64_t *si, const int64_t *l
 
 /* u[k] = sum over all n leaves s of A_{targets[k], s} f[s]. Returns 0, or 1 on a 2:1 violation. */
 int o1_apply(int64_t n, const int64_t *lo_int, const int64_t *size, const double *lo, const double *a,
-             const double *consts, const double *f, int64_t n_targets, const int64_t *targets, double *u)
+             const double *consts, const int32_t *order, const double *gx, const double *gw,
+             const double *f, int64_t n_targets, const int64_t *targets, double *u)
 {
+    const rule_t r = {order, gx, gw};
     int bad = 0;
 #pragma omp parallel for schedule(dynamic, 4) reduction(| : bad)
     for (int64_t k = 0; k < n_targets; ++k) {
         int b = 0;
         double acc = 0.0;
         for (int64_t s = 0; s < n; ++s)
-            acc += entry(targets[k], s, lo_int, size, lo, a, consts, &b) * f[s];
+            acc += entry(targets[k], s, lo_int, size, lo, a, consts, &r, &b) * f[s];
         u[k] = acc;
         bad |= b;
     }

@@ -46,3 +46,18 @@ def test_sampled_equals_full():
     full = F.apply(f)
     tg = np.array([0, 3, 400, 1111, 2527])
     assert np.max(np.abs(F.apply_sampled(f, tg) - full[tg]) / np.abs(full[tg])) < 1e-14
+
+
+def test_level_rule_fmm_converges_to_its_direct_operator():
+    """Neighbour marking (Sec. 2) and the level-dependent near-field rule: O2 tends to the operator
+    with that rule on the near pairs and the 2x2x2 rule elsewhere (oracle.direct.apply_near_order)
+    as q grows (stated at h = 1/32: 1.4e-6 and 8.0e-8 for q = 4 and 6)."""
+    m = BCMesh(5, 1)
+    lv = m.leaf_array()
+    f = synth.leaf_density(lv, seed=0)
+    tg = np.arange(0, len(lv), 191)
+    u1 = direct.apply_near_order(m, f, tg)
+    errs = [np.linalg.norm(fmm.FMM(m, q, near_order=1).apply_sampled(f, tg) - u1) / np.linalg.norm(u1)
+            for q in (4, 6)]
+    assert errs[0] > errs[1]
+    assert errs[0] < 3e-6 and errs[1] < 2e-7

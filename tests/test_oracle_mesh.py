@@ -106,3 +106,87 @@ def test_list_counts_cross_check():
     ti, _ = m.near_pairs()
     assert len(ti) == 359920
     assert len(m.interaction_pairs()) == 734160
+
+
+# -- marking rule 1: M_l = {w in C_l : N(w) meets B_l} (Sec. 2) --------------------------------------
+
+def _neighbour_marking_counts(L):
+    """(#C_l, #M_l, #L*_l) of marking rule 1 in closed form. A level-l cell d cells away from the
+    nearest boundary plane has the boundary cell straight across that plane at offset d, and every
+    boundary cell at least d away along some axis, so it is marked iff d^2 < 12 (d <= 3). Every cell
+    with d <= 3 exists (its parent has d <= 1), so with n = 2^l: #M_l = n^3 - max(n - 8, 0)^3 for
+    l < L, #C_0 = 1 and #C_{l+1} = 8 #M_l."""
+    out, c = [], 1
+    for lev in range(L + 1):
+        n = 1 << lev
+        m = n ** 3 - max(n - 8, 0) ** 3 if lev < L else 0
+        out.append((c, m, c - m))
+        c = 8 * m
+    return out
+
+
+@pytest.mark.parametrize("L", [2, 3, 4, 5, 6])
+def test_neighbour_marking_counts(L):
+    assert BCMesh(L, 1).level_counts() == _neighbour_marking_counts(L)
+
+
+def test_neighbour_marking_rule_and_tiling():
+    L = 5
+    m = BCMesh(L, 1)
+    # the rule itself, by the separation ratio in floating point (eq. def:sepRatio, def:diam)
+    for lev in range(L):
+        a = 2.0 ** -lev
+        bnd = [c for c in m.levels[lev] if m.on_boundary(lev, c)]
+        for c in m.levels[lev][::7]:
+            eta = [math.inf if b == c else math.sqrt(3.0) * a / math.dist(m.centre(lev, b), m.centre(lev, c))
+                   for b in bnd]
+            assert m.is_refined(lev, c) == (max(eta) > 0.5 + 1e-12)
+    n = 1 << L
+    cover = np.zeros((n, n, n), dtype=np.int32)
+    for lev, i, j, k in m.leaves:
+        s = 1 << (L - lev)
+        cover[i * s:(i + 1) * s, j * s:(j + 1) * s, k * s:(k + 1) * s] += 1
+    assert np.all(cover == 1)
+
+
+def test_neighbour_marking_balance_and_near_levels():
+    """Touching leaves differ by at most one level; near-field pairs by at most two (marking rule 1
+    refines in shells four cells thick), against L - 1 with the face rule."""
+    L = 6
+    m = BCMesh(L, 1)
+    lv = m.leaf_array()
+    size = 1 << (L - lv[:, 0])
+    lo = lv[:, 1:4] * size[:, None]
+    gaps = set()
+    for t in range(0, len(lv), 211):
+        lo2 = np.maximum(lo[t], lo)
+        hi2 = np.minimum(lo[t] + size[t], lo + size[:, None])
+        touch = np.all(lo2 <= hi2, axis=1)
+        assert np.all(np.abs(lv[touch, 0] - lv[t, 0]) <= 1)
+        lev, i, j, k = m.leaves[t]
+        gaps.update(abs(s[0] - lev) for s in m.near_leaf_sources(lev, (i, j, k)))
+    assert max(gaps) == 2
+
+
+def test_neighbour_marking_exact_cover_sampled():
+    """eq. spaceDecomp:OmOm for marking rule 1: for sampled target leaves, every source leaf is in
+    exactly one near block or one far block (interaction list of an ancestor pair)."""
+    L = 5
+    m = BCMesh(L, 1)
+    n = len(m.leaves)
+    desc = {}
+
+    def leaves_of(lev, c):
+        if (lev, c) not in desc:
+            desc[(lev, c)] = np.array([m.leaf_index[t] for t in m.leaf_descendants(lev, c)])
+        return desc[(lev, c)]
+
+    for t in range(0, n, 1453):
+        lev, i, j, k = m.leaves[t]
+        cov = np.zeros(n, dtype=np.int16)
+        np.add.at(cov, [m.leaf_index[s] for s in m.near_leaf_sources(lev, (i, j, k))], 1)
+        for lp in range(lev + 1):
+            anc = m.ancestor(lev, (i, j, k), lp)
+            for s in m.interaction_list(lp, anc):
+                cov[leaves_of(lp, s)] += 1
+        assert cov.min() == 1 and cov.max() == 1
