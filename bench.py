@@ -253,6 +253,48 @@ def measure_btv(bcv, torch, tree, f, args, dev):
                     "of du/dn; the representation formula gives u in the cube"}
 
 
+def measure_marking(bcv, torch, args, dev):
+    """The neighbour marking rule (Sec. 2) with the level-dependent near-field rule (Sec. 4) at the
+    same h and q: a mesh refined wherever a boundary cell is a neighbour, its near-field entries
+    assembled once at plan time (2 + L - l Gauss points per axis on a level-l leaf). FP64 and mixed
+    plans, `args.steps` timed applies each; the same Gaussian-mixture density recipe."""
+    import synth
+
+    tree = bcv.build_bc_tree(args.L, bcv.MARK_NEIGHBOR)
+    lv = tree.leaves().astype(np.int64)
+    f = torch.tensor(synth.leaf_density(lv, seed=0), device="cuda:%d" % dev)
+    out = {}
+    for prec in ("fp64", "mixed"):
+        t0 = time.perf_counter()
+        plan = bcv.plan_interactions(tree, q=args.q, device=dev, streams=args.streams, nearfield=bcv.NEAR_ASSEMBLED,
+                                     near_order=1, precision=bcv.MIXED_F32 if prec == "mixed" else bcv.FP64)
+        plan_s = time.perf_counter() - t0
+        u = torch.empty(plan.n_leaves, dtype=torch.float64, device="cuda:%d" % dev)
+        for _ in range(args.warmup):
+            bcv.vtv_apply(plan, f, u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            bcv.vtv_apply(plan, f, u)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / args.steps
+        out[prec] = {"ms_per_apply": ms, "value": plan.n_leaves / (ms * 1e-3), "plan_seconds": plan_s,
+                     "u": u.cpu().numpy()}
+        info = plan.info
+        del plan
+    vol = np.ldexp(1.0, -3 * lv[:, 0].astype(np.int32))
+    a, b = out["mixed"].pop("u"), out["fp64"].pop("u")
+    rel = float(np.sqrt(np.sum(vol * ((a - b) / vol) ** 2) / np.sum(vol * (b / vol) ** 2)))
+    return {"metric": "VtV cell-potentials/s, neighbour marking + level-dependent near-field rule, 1 GPU",
+            "unit": "cell-potentials/s", "n_leaves": int(len(lv)), "n_near_pairs": info["n_near"],
+            "n_near_ordered": info["n_near_ordered"], "n_touching_pairs": info["n_touch"],
+            "n_m2l_pairs": info["n_m2l"], "plan_device_bytes": info["device_bytes"], "fp64": out["fp64"],
+            "mixed": out["mixed"], "mixed_vs_fp64_rel_l2": rel,
+            "config": "unit cube, h = 1/%d (L = %d), marking 1 (refine when a neighbour has a face on the boundary), "
+                      "q = %d, near field assembled at plan time with 2 + L - l Gauss points per axis on a level-l "
+                      "leaf, %d stream(s)" % (1 << args.L, args.L, args.q, args.streams)}
+
+
 def batched(args):
     """64 unit-cube BC meshes, h drawn from {1/16, 1/32, 1/64} (default_rng(1234)), Gaussian-mixture
     density of seed m on mesh m, mixed precision (FP32 interaction phase): one forest plan with the
@@ -350,6 +392,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="mixed path without the touching-pair surrogate")
     ap.add_argument("--no-btv", action="store_true", help="skip the BtV (Algorithm 3) measurement")
+    ap.add_argument("--no-marking", action="store_true",
+                    help="skip the neighbour-marking / level-dependent near-field measurement")
     ap.add_argument("--batched", action="store_true",
                     help="the batched workload: 64 meshes in one forest plan and one graph launch")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -476,6 +520,9 @@ def main():
                              "tol": SURROGATE_TOL, "training": sur_report}
     if not args.no_btv:
         line["btv"] = measure_btv(bcv, torch, tree, f, args, dev)
+    if not args.no_marking:
+        line["neighbour_marking"] = measure_marking(bcv, torch, args, dev)
+        print("neighbour marking: %s" % json.dumps(line["neighbour_marking"]), file=sys.stderr)
         print("btv: %s" % json.dumps({k: line["btv"][k] for k in ("fp64", "mixed", "mixed_vs_fp64_rel_l2",
                                                                   "representation_formula_rel_err",
                                                                   "vtb_mixed_vs_fp64_rel")}),

@@ -52,10 +52,18 @@ typedef enum {
 
 /* Mesh description (Sec. 2, Boundary Concentrated Mesh, with cube cells on [0,1]^3).
  * Level 0 is the unit cube; level-l cells are cubes of side 2^-l. For l < L a cell is marked
- * (refined) iff it has a face on the boundary; every level-L cell is a leaf. */
+ * (refined) by the marking rule; every level-L cell is a leaf. */
+enum {
+    BCV_MARK_FACE = 0,     /* marked iff the cell has a face on the boundary (M_l = B_l) */
+    BCV_MARK_NEIGHBOR = 1  /* marked iff a neighbour (eq. def:neighbors, eta0 = 1/2) has a face on the
+                              boundary: the marking rule of Sec. 2. With cube cells this refines
+                              every cell within three cells of the boundary (all of levels 0-3), and
+                              near-field pairs differ by at most two levels (up to L - 1 with
+                              BCV_MARK_FACE) */
+};
 typedef struct {
     int L;       /* finest level, 2 <= L <= 9 (boundary leaves have side h = 2^-L) */
-    int marking; /* must be 0: the face-on-boundary marking rule */
+    int marking; /* BCV_MARK_FACE or BCV_MARK_NEIGHBOR */
 } bcv_mesh_desc;
 
 enum { BCV_NEAR_QUADRATURE = 0, BCV_NEAR_ASSEMBLED = 1 };
@@ -93,6 +101,12 @@ typedef struct {
     int m2l_max_slots;     /* longest slot list of one interaction task; longer lists are cut into
                               pieces whose partial sums are added in a fixed order (0 = 256;
                               else 16..65536) */
+    int near_order;        /* Gauss rule of the non-touching near-field pairs (Sec. 4, near-field
+                              quadrature: fixed order on the finest level, raised on coarser ones).
+                              0: 2x2x2 points on each cell. 1: a level-l leaf takes n_l = 2 + L - l
+                              points per axis, and a pair takes n_l^3 points on each of its two
+                              cells (the entry stays symmetric). 1 requires BCV_NEAR_ASSEMBLED (the
+                              plan computes the entries once, in FP64); far pairs are unchanged */
     int boundary;          /* 1: also build the BtV structures (boundary faces, their near lists
                               and touching integrals) so that bcv_btv_apply can run; single-mesh
                               trees only. 0: VtV only */
@@ -114,6 +128,7 @@ typedef struct {
     int64_t n_btv_near;   /* BtV near (leaf, face) pairs */
     int64_t n_btv_touch;  /* of which the closed cell and face meet (exact integrals) */
     int64_t n_vtb_near;   /* VtB near (face, source leaf) pairs */
+    int64_t n_near_ordered; /* near entries that took the level-dependent rule (opts.near_order 1) */
     int64_t device_bytes; /* device memory held by the plan */
     int32_t K;            /* expansion coefficients per cell, (q+1)(q+2)(q+3)/6 */
     int32_t L;
@@ -122,7 +137,7 @@ typedef struct {
 } bcv_plan_info;
 
 /* Build the BC octree of Sec. 2 on the host. desc and out must be non-NULL.
- * Errors: BCV_EINVAL (L outside 2..9, marking != 0), BCV_ENOMEM. */
+ * Errors: BCV_EINVAL (L outside 2..9, marking not 0 or 1), BCV_ENOMEM. */
 bcv_status bcv_build_bc_tree(const bcv_mesh_desc *desc, bcv_tree *out);
 
 /* A forest of n_meshes BC meshes for a batched apply: one tree, one plan and one apply (and one

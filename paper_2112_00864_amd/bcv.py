@@ -14,6 +14,7 @@ _lib = None
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTSUP, ESTATE = range(6)
 NEAR_QUADRATURE, NEAR_ASSEMBLED = 0, 1
+MARK_FACE, MARK_NEIGHBOR = 0, 1
 FP64, MIXED_F32 = 0, 1
 PART_NEAR, PART_FAR = 1, 2
 TOUCH_CLASSES = ("self", "face", "edge", "vertex", "face2", "edge2", "vertex2")
@@ -33,13 +34,14 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("eta0", ctypes.c_double), ("q", ctypes.c_int), ("precision", ctypes.c_int),
                 ("direct", ctypes.c_int), ("nearfield", ctypes.c_int), ("streams", ctypes.c_int),
                 ("surrogate", ctypes.c_void_p), ("surrogate_tol", ctypes.c_double), ("near_unit", ctypes.c_int),
-                ("m2l_max_slots", ctypes.c_int), ("boundary", ctypes.c_int)]
+                ("m2l_max_slots", ctypes.c_int), ("near_order", ctypes.c_int), ("boundary", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("n_leaves", "n_cells", "n_near", "n_touch", "n_m2l", "n_m2l_lanes",
                                               "n_offsets", "n_m2l_read_lanes", "n_faces", "n_btv_near",
-                                              "n_btv_touch", "n_vtb_near", "device_bytes")] + [
+                                              "n_btv_touch", "n_vtb_near", "n_near_ordered",
+                                              "device_bytes")] + [
         ("K", ctypes.c_int32), ("L", ctypes.c_int32), ("surrogate_classes", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
@@ -172,8 +174,12 @@ class Tree:
 
 
 def build_bc_forest(Ls, marking=0):
-    """One tree holding len(Ls) meshes; mesh m occupies [4m, 4m+1) x [0,1)^2 (see bcv.h)."""
-    descs = (MeshDesc * len(Ls))(*[MeshDesc(int(L), marking) for L in Ls])
+    """One tree holding len(Ls) meshes; mesh m occupies [4m, 4m+1) x [0,1)^2 (see bcv.h).
+    marking: one rule for every mesh, or a list with one per mesh."""
+    marks = list(marking) if isinstance(marking, (list, tuple)) else [marking] * len(Ls)
+    if len(marks) != len(Ls):
+        raise ValueError("one marking per mesh")
+    descs = (MeshDesc * len(Ls))(*[MeshDesc(int(L), int(mk)) for L, mk in zip(Ls, marks)])
     h = ctypes.c_void_p()
     _check(lib().bcv_build_bc_forest(len(Ls), descs, ctypes.byref(h)))
     return Tree(h)
@@ -212,17 +218,17 @@ class Plan:
 
 
 def _opts(q=6, eta0=0.5, direct=False, nearfield=NEAR_QUADRATURE, streams=2, precision=FP64, surrogate=None,
-          surrogate_tol=1e-7, near_unit=0, m2l_max_slots=0, boundary=False):
+          surrogate_tol=1e-7, near_unit=0, m2l_max_slots=0, boundary=False, near_order=0):
     return PlanOpts(eta0, q, precision, 1 if direct else 0, nearfield, streams,
                     surrogate.handle if surrogate is not None else None, surrogate_tol, near_unit, m2l_max_slots,
-                    1 if boundary else 0)
+                    near_order, 1 if boundary else 0)
 
 
 def plan_interactions(tree, q=6, eta0=0.5, direct=False, nearfield=NEAR_QUADRATURE, device=0, streams=2,
                       precision=FP64, surrogate=None, surrogate_tol=1e-7, near_unit=0, m2l_max_slots=0,
-                      boundary=False):
+                      boundary=False, near_order=0):
     opts = _opts(q, eta0, direct, nearfield, streams, precision, surrogate, surrogate_tol, near_unit, m2l_max_slots,
-                 boundary)
+                 boundary, near_order)
     h = ctypes.c_void_p()
     _check(lib().bcv_plan_interactions(tree.handle, ctypes.byref(opts), device, ctypes.byref(h)))
     return Plan(h, device)

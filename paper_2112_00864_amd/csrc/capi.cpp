@@ -9,8 +9,8 @@
 #include "quadrature.hpp"
 
 namespace bcv {
-bcv_tree_s *build_tree(int L);
-bcv_tree_s *build_forest(int n, const int *Ls);
+bcv_tree_s *build_tree(int L, int marking);
+bcv_tree_s *build_forest(int n, const int *Ls, const int *markings);
 bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int device);
 void destroy_plan(bcv_plan_s *p);
 void touching_integrals(int device, double out[kTouchClasses]);
@@ -78,6 +78,9 @@ void check_plan_opts(const bcv_plan_opts &o, int device)
     BCV_REQUIRE(o.m2l_max_slots == 0 || (o.m2l_max_slots >= 16 && o.m2l_max_slots <= 65536),
                 BCV_EINVAL, "m2l_max_slots must be 0 or 16..65536");
     BCV_REQUIRE(o.boundary == 0 || o.boundary == 1, BCV_EINVAL, "boundary must be 0 or 1");
+    BCV_REQUIRE(o.near_order == 0 || o.near_order == 1, BCV_EINVAL, "near_order must be 0 or 1");
+    BCV_REQUIRE(o.near_order == 0 || o.nearfield == BCV_NEAR_ASSEMBLED, BCV_EINVAL,
+                "near_order 1 needs the assembled near field (BCV_NEAR_ASSEMBLED)");
     if (o.surrogate) {
         check_mlp(o.surrogate);
         BCV_REQUIRE(o.surrogate_tol >= 0.0, BCV_EINVAL, "negative surrogate tolerance");
@@ -120,13 +123,14 @@ bcv_status bcv_build_bc_forest(int n_meshes, const bcv_mesh_desc *descs, bcv_tre
         BCV_REQUIRE(descs != nullptr && out != nullptr, BCV_EINVAL, "NULL argument");
         *out = nullptr;
         BCV_REQUIRE(n_meshes >= 1 && n_meshes <= 4096, BCV_EINVAL, "n_meshes must be in 1..4096");
-        std::vector<int> Ls(n_meshes);
+        std::vector<int> Ls(n_meshes), marks(n_meshes);
         for (int m = 0; m < n_meshes; ++m) {
             BCV_REQUIRE(descs[m].L >= 2 && descs[m].L <= 9, BCV_EINVAL, "L must be in 2..9");
-            BCV_REQUIRE(descs[m].marking == 0, BCV_EINVAL, "only the face-on-boundary marking rule (0) is supported");
+            BCV_REQUIRE(descs[m].marking == 0 || descs[m].marking == 1, BCV_EINVAL, "marking must be 0 or 1");
             Ls[m] = descs[m].L;
+            marks[m] = descs[m].marking;
         }
-        *out = bcv::build_forest(n_meshes, Ls.data());
+        *out = bcv::build_forest(n_meshes, Ls.data(), marks.data());
     });
 }
 
@@ -148,8 +152,8 @@ bcv_status bcv_build_bc_tree(const bcv_mesh_desc *desc, bcv_tree *out)
         BCV_REQUIRE(desc != nullptr && out != nullptr, BCV_EINVAL, "NULL argument");
         *out = nullptr;
         BCV_REQUIRE(desc->L >= 2 && desc->L <= 9, BCV_EINVAL, "L must be in 2..9");
-        BCV_REQUIRE(desc->marking == 0, BCV_EINVAL, "only the face-on-boundary marking rule (0) is supported");
-        *out = bcv::build_tree(desc->L);
+        BCV_REQUIRE(desc->marking == 0 || desc->marking == 1, BCV_EINVAL, "marking must be 0 or 1");
+        *out = bcv::build_tree(desc->L, desc->marking);
     });
 }
 
@@ -211,6 +215,7 @@ bcv_status bcv_plan_get_info(bcv_plan plan, bcv_plan_info *info)
         info->n_btv_near = plan->n_btv_near;
         info->n_btv_touch = plan->n_btv_touch;
         info->n_vtb_near = plan->n_vtb_near;
+        info->n_near_ordered = plan->n_near_ordered;
         info->device_bytes = plan->device_bytes;
         info->K = plan->K;
         info->L = plan->L;

@@ -122,6 +122,8 @@ struct bcv_plan_s {
     int device = 0;
     int L = 0, q = 0, K = 0;
     int direct = 0, nearfield = 0, precision = 0;
+    int near_order = 0;            // 1: level-dependent Gauss rule on the non-touching near pairs
+    int64_t n_near_ordered = 0;    // near entries that took it
     int64_t n_leaves = 0, n_cells = 0, n_near = 0, n_touch = 0, n_m2l = 0, n_m2l_lanes = 0, n_offsets = 0,
             n_m2l_read_lanes = 0;
     int64_t device_bytes = 0;

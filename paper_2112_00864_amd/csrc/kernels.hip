@@ -935,6 +935,45 @@ __global__ __launch_bounds__(256) void near_assemble_kernel(int64_t n_units, con
     for (int64_t e = un.begin + lane; e < un.end; e += kWave) val[e] = near_entry(col[e], gt, geom, tv);
 }
 
+// Level-dependent near-field rule (Sec. 4, near-field quadrature: fixed order on the finest level,
+// raised on coarser levels): the listed entries are non-touching pairs (t, s) whose cells carry n_t
+// and n_s Gauss points per axis; the entry is the n_t^3 x n_s^3-point tensor rule. One wave per
+// entry, the point pairs spread over the lanes. gx, gw: node and weight tables on [0, 1], row n
+// (16 wide) holding the n-point rule.
+__global__ __launch_bounds__(256) void near_assemble_ordered_kernel(int64_t n, const int64_t *__restrict__ entry,
+                                                                    const int32_t *__restrict__ target,
+                                                                    const uint32_t *__restrict__ col,
+                                                                    const double4 *__restrict__ geom,
+                                                                    const int8_t *__restrict__ order,
+                                                                    const double *__restrict__ gx,
+                                                                    const double *__restrict__ gw,
+                                                                    double *__restrict__ val)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (w >= n) return;  // uniform per wave
+    const int64_t e = entry[w];
+    const int32_t t = target[w], s = (int32_t)(col[e] & 0x0FFFFFFFu);
+    const double4 gt = geom[t], gs = geom[s];
+    const int nt = order[t], ns = order[s];
+    const int ps = ns * ns * ns, total = nt * nt * nt * ps;
+    const double *xt = gx + 16 * nt, *wt = gw + 16 * nt, *xs = gx + 16 * ns, *ws = gw + 16 * ns;
+    double acc = 0.0;
+    for (int i = lane; i < total; i += kWave) {
+        const int a = i / ps, b = i - a * ps;
+        const int a1 = a % nt, a2 = (a / nt) % nt, a3 = a / (nt * nt);
+        const int b1 = b % ns, b2 = (b / ns) % ns, b3 = b / (ns * ns);
+        const double dx = (gt.x + gt.w * xt[a1]) - (gs.x + gs.w * xs[b1]);
+        const double dy = (gt.y + gt.w * xt[a2]) - (gs.y + gs.w * xs[b2]);
+        const double dz = (gt.z + gt.w * xt[a3]) - (gs.z + gs.w * xs[b3]);
+        const double wgt = (wt[a1] * wt[a2] * wt[a3]) * (ws[b1] * ws[b2] * ws[b3]);
+        acc += wgt / sqrt(dx * dx + dy * dy + dz * dz);
+    }
+    acc = wave_sum(acc);
+    const double vt = gt.w * gt.w * gt.w, vs = gs.w * gs.w * gs.w;
+    if (lane == 0) val[e] = acc * vt * vs * kInv4Pi;
+}
+
 // ---- regular cube pairs (touching-integral self-similarity system) -------------------------------
 constexpr int kMaxGauss = 16;
 struct GaussRule {
@@ -1306,6 +1345,49 @@ void launch_near_assemble(const bcv_plan_s &p, hipStream_t st)
 }
 
 void gauss_legendre01(int n, double *x, double *w);
+
+namespace {
+// A device buffer freed on scope exit (plan-time temporaries).
+template <class T>
+struct TempBuffer {
+    T *d = nullptr;
+    explicit TempBuffer(const std::vector<T> &v)
+    {
+        if (v.empty()) return;
+        if (hipMalloc(&d, v.size() * sizeof(T)) != hipSuccess) fail(BCV_ENOMEM, "hipMalloc failed (plan temporary)");
+        const hipError_t e = hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(d);
+            d = nullptr;
+            BCV_HIP(e);
+        }
+    }
+    ~TempBuffer() { (void)hipFree(d); }
+    TempBuffer(const TempBuffer &) = delete;
+    TempBuffer &operator=(const TempBuffer &) = delete;
+};
+}  // namespace
+
+void launch_near_assemble_ordered(const bcv_plan_s &p, const std::vector<int64_t> &entry,
+                                  const std::vector<int32_t> &target, const std::vector<int8_t> &order)
+{
+    BCV_REQUIRE(entry.size() == target.size() && (int64_t)order.size() == p.n_leaves, BCV_ESTATE,
+                "internal: ordered near entries");
+    if (entry.empty()) return;
+    for (int8_t o : order) BCV_REQUIRE(o >= 1 && o <= kMaxGauss, BCV_ESTATE, "internal: Gauss order out of range");
+    std::vector<double> gx(16 * (kMaxGauss + 1), 0.0), gw(16 * (kMaxGauss + 1), 0.0);
+    for (int n = 1; n <= kMaxGauss; ++n) gauss_legendre01(n, &gx[16 * n], &gw[16 * n]);
+    const TempBuffer<int64_t> d_entry(entry);
+    const TempBuffer<int32_t> d_target(target);
+    const TempBuffer<int8_t> d_order(order);
+    const TempBuffer<double> d_gx(gx), d_gw(gw);
+    const int64_t n = (int64_t)entry.size();
+    near_assemble_ordered_kernel<<<(unsigned)((n + 3) / 4), 256, 0, nullptr>>>(
+        n, d_entry.d, d_target.d, p.d_col, reinterpret_cast<const double4 *>(p.d_leaf_geom), d_order.d, d_gx.d,
+        d_gw.d, p.d_val);
+    check_launch();
+    BCV_HIP(hipDeviceSynchronize());  // before the temporaries are freed
+}
 
 void regular_cube_pairs(const int *deltas, int n, int n_gauss, double *out)
 {

@@ -14,6 +14,11 @@ void launch_vtb(const bcv_plan_s &p, const double *f, double *uf, hipStream_t st
 
 // Stores every near-pair Galerkin entry of the plan in p.d_val (plan time).
 void launch_near_assemble(const bcv_plan_s &p, hipStream_t stream);
+// Overwrites the near entries d_val[entry[k]] (row target[k]; non-touching pairs) with the tensor
+// Gauss rule of order[t] points per axis on the target and order[s] on the source (plan time, on
+// the null stream; synchronizes). order: one per leaf, 1..16.
+void launch_near_assemble_ordered(const bcv_plan_s &p, const std::vector<int64_t> &entry,
+                                  const std::vector<int32_t> &target, const std::vector<int8_t> &order);
 
 // int_{[0,1]^3} int_{delta+[0,1]^3} 1/|x-y| dy dx for n non-touching integer offsets (host arrays:
 // deltas 3 per offset, out n), by an n_gauss-point Gauss-Legendre rule in each of the six variables,

@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <new>
 #include <vector>
 
 #include "internal.hpp"
@@ -261,7 +262,9 @@ struct M2LPlan {
     std::vector<M2LTask> tasks;
     std::vector<int32_t> targets;   // 64 per task
     std::vector<int32_t> slot_key;  // offset key per slot | gather bit 31, later the offset id | bit 31
-    std::vector<uint32_t> slot_src; // 64 per slot: source row | (offset in the lane's own list) << 31
+    // 64 per slot: source row | (offset in the lane's own list) << 31 (not zero-filled: every word
+    // is written by the builder, each task's block by one thread)
+    std::unique_ptr<uint32_t[]> slot_src;
     std::vector<M2LSplit> splits;
     int32_t n_pieces = 0;           // partial blocks of split tasks
     int32_t xcd_begin[kXcds + 1] = {};
@@ -444,16 +447,16 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, int32_t max_s
                   [](const Chunk &x, const Chunk &y) { return x.cells[0] < y.cells[0]; });
         for (auto &ch : level_chunks) chunks.push_back(std::move(ch));
     }
+    // Pass 1: each task's slots (the union of its targets' offsets, in slot order) and heads.
     struct Out {
         std::vector<int32_t> keys;  // offset key per slot | (the slot gathers) << 31
-        std::vector<uint32_t> src;  // 64 per slot
         uint64_t heads = 0;
         int64_t pairs = 0;
     };
     std::vector<Out> outs(chunks.size());
 #pragma omp parallel
     {
-        std::vector<std::vector<int32_t>> lane_keys(64);
+        std::vector<int32_t> keys;
         std::vector<char> used(15 * 15 * 15);
         std::vector<std::array<int, 5>> order;  // across 1, across 2, along parity, along, key
 #pragma omp for schedule(dynamic, 4)
@@ -463,8 +466,8 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, int32_t max_s
             const int nl = (int)ch.cells.size();
             std::fill(used.begin(), used.end(), 0);
             for (int lane = 0; lane < nl; ++lane) {
-                interaction_keys(t, g, ch.lev, ch.cells[lane], lane_keys[lane]);
-                for (int32_t key : lane_keys[lane]) used[key] = 1;
+                interaction_keys(t, g, ch.lev, ch.cells[lane], keys);
+                for (int32_t key : keys) used[key] = 1;
             }
             Out &o = outs[q];
             for (int lane = 0; lane < nl; ++lane) {  // heads: the previous lane is not `step` cells back
@@ -483,10 +486,33 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, int32_t max_s
                 order.push_back({d[u], d[v], ch.step == 2 ? d[ax] & 1 : 0, d[ax], key});
             }
             std::sort(order.begin(), order.end());
-            for (size_t k = 0; k < order.size(); ++k) {
-                const int key = order[k][4];
+            o.keys.resize(order.size());
+            for (size_t k = 0; k < order.size(); ++k) o.keys[k] = order[k][4];
+        }
+    }
+    std::vector<int64_t> chunk_base(chunks.size() + 1, 0);
+    for (size_t q = 0; q < chunks.size(); ++q) chunk_base[q + 1] = chunk_base[q] + (int64_t)outs[q].keys.size();
+    BCV_REQUIRE(chunk_base.back() < (int64_t)INT32_MAX, BCV_ENOTSUP, "interaction plan too large");
+    const int64_t n_slots = chunk_base.back();
+    m.slot_key.resize(n_slots);
+    m.slot_src.reset(new (std::nothrow) uint32_t[std::max<int64_t>(n_slots, 1) * 64]);
+    if (!m.slot_src) fail(BCV_ENOMEM, "host allocation failed for the interaction plan");
+    // Pass 2: every lane's source at every slot, written in place (first touch by the filling
+    // thread), and the gather bit.
+#pragma omp parallel
+    {
+        std::vector<std::vector<int32_t>> lane_keys(64);
+#pragma omp for schedule(dynamic, 4)
+        for (size_t q = 0; q < chunks.size(); ++q) {
+            const Chunk &ch = chunks[q];
+            const int nl = (int)ch.cells.size();
+            for (int lane = 0; lane < nl; ++lane) interaction_keys(t, g, ch.lev, ch.cells[lane], lane_keys[lane]);
+            Out &o = outs[q];
+            uint32_t *src = m.slot_src.get() + chunk_base[q] * 64;
+            for (size_t k = 0; k < o.keys.size(); ++k) {
+                const int key = o.keys[k];
                 const int d[3] = {key / 225 - 7, (key / 15) % 15 - 7, key % 15 - 7};
-                const size_t at = o.src.size();
+                uint32_t *at = src + k * 64;
                 for (int lane = 0; lane < 64; ++lane) {
                     int32_t s = -1;
                     bool valid = false;
@@ -497,14 +523,14 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, int32_t max_s
                         if (valid && s < 0) o.pairs = INT64_MIN;  // a listed source must exist
                     }
                     o.pairs += valid;
-                    o.src.push_back((uint32_t)(s >= 0 ? s : zero_row) | (valid ? 1u << 31 : 0u));
+                    at[lane] = (uint32_t)(s >= 0 ? s : zero_row) | (valid ? 1u << 31 : 0u);
                 }
                 // the slot can shift if every non-head lane finds its source one lane down
                 bool shift = k > 0;
                 for (int lane = 1; shift && lane < nl; ++lane)
                     if (!((o.heads >> lane) & 1))
-                        shift = (o.src[at + lane] & 0x7FFFFFFFu) == (o.src[at - 64 + lane - 1] & 0x7FFFFFFFu);
-                o.keys.push_back(shift ? key : (int32_t)((uint32_t)key | (1u << 31)));
+                        shift = (at[lane] & 0x7FFFFFFFu) == (at[lane - 64 - 1] & 0x7FFFFFFFu);
+                m.slot_key[chunk_base[q] + k] = shift ? key : (int32_t)((uint32_t)key | (1u << 31));
             }
         }
     }
@@ -517,8 +543,8 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, int32_t max_s
     std::vector<Piece> pieces;
     std::vector<M2LSplit> split_of_chunk(chunks.size(), M2LSplit{-1, 0, 0, 0});
     for (size_t q = 0; q < chunks.size(); ++q) {
-        const int32_t base = (int32_t)m.slot_key.size();
-        const int32_t n = (int32_t)outs[q].keys.size();
+        const int32_t base = (int32_t)chunk_base[q];
+        const int32_t n = (int32_t)(chunk_base[q + 1] - chunk_base[q]);
         const int32_t np = std::max<int32_t>(1, (n + max_slots - 1) / max_slots);
         if (np > 1) split_of_chunk[q] = M2LSplit{-1, m.n_pieces, np, 0};
         for (int32_t k = 0; k < np; ++k) {
@@ -526,14 +552,11 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, int32_t max_s
             pieces.push_back(
                 Piece{M2LTask{b, e - b, chunks[q].lev, np > 1 ? m.n_pieces + k : -1, outs[q].heads}, (int32_t)q});
             for (int32_t j = b; j < e; ++j)  // a piece's first slot always gathers
-                m.n_read_lanes += (j == b || outs[q].keys[j - base] < 0) ? 64 : __builtin_popcountll(outs[q].heads);
+                m.n_read_lanes += (j == b || m.slot_key[j] < 0) ? 64 : __builtin_popcountll(outs[q].heads);
         }
         if (np > 1) m.n_pieces += np;
-        m.slot_key.insert(m.slot_key.end(), outs[q].keys.begin(), outs[q].keys.end());
-        m.slot_src.insert(m.slot_src.end(), outs[q].src.begin(), outs[q].src.end());
         m.n_pairs += outs[q].pairs;
     }
-    BCV_REQUIRE(m.slot_key.size() < (size_t)INT32_MAX, BCV_ENOTSUP, "interaction plan too large");
     // XCD ranges: contiguous runs of pieces (spatially ordered, so an XCD's L2 sees neighbouring
     // sources) with about equal slot totals; inside a range the longest pieces go first.
     int64_t total = 0;
@@ -583,6 +606,18 @@ T *upload(bcv_plan_s *p, const std::vector<T> &v)
     if (hipMalloc(&d, bytes) != hipSuccess) fail(BCV_ENOMEM, "hipMalloc failed for a plan buffer");
     p->device_bytes += (int64_t)bytes;
     BCV_HIP(hipMemcpy(d, v.data(), bytes, hipMemcpyHostToDevice));
+    return d;
+}
+
+template <class T>
+T *upload(bcv_plan_s *p, const T *v, size_t count)
+{
+    if (count == 0) return nullptr;
+    T *d = nullptr;
+    const size_t bytes = count * sizeof(T);
+    if (hipMalloc(&d, bytes) != hipSuccess) fail(BCV_ENOMEM, "hipMalloc failed for a plan buffer");
+    p->device_bytes += (int64_t)bytes;
+    BCV_HIP(hipMemcpy(d, v, bytes, hipMemcpyHostToDevice));
     return d;
 }
 
@@ -762,6 +797,7 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
     p->K = ncoef(opts.q);
     p->direct = opts.direct;
     p->nearfield = opts.nearfield;
+    p->near_order = opts.near_order;
     p->precision = opts.precision;
     p->streams = opts.streams;
     if (p->streams == 2) {
@@ -805,8 +841,29 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
     p->d_leaf_cell = upload(p.get(), t.leaf_cell);
 
     NearCSR vol_near;  // kept for the VtB rows
+    // Level-dependent near-field rule: per-leaf Gauss orders and the entries that need them.
+    std::vector<int8_t> near_order;
+    std::vector<int64_t> ordered_entry;
+    std::vector<int32_t> ordered_target;
     {
         NearCSR near = build_near(t, grids, geo, opts.direct != 0);
+        if (opts.near_order == 1) {
+            // n_l = 2 + L - l points per axis, L the finest level of the leaf's mesh
+            near_order.resize(p->n_leaves);
+            for (int64_t l = 0; l < p->n_leaves; ++l) {
+                const int32_t c = t.leaf_cell[l];
+                const int m = (t.ijk[3 * c] >> t.level[c]) / 4;
+                near_order[l] = (int8_t)(2 + t.mesh_L[m] - t.level[c]);
+            }
+            for (int64_t n = 0; n < p->n_leaves; ++n)
+                for (int64_t e = near.split[n]; e < near.row[n + 1]; ++e) {  // the non-touching entries
+                    const int32_t s = (int32_t)(near.col[e] & 0x0FFFFFFFu);
+                    if (near_order[n] != 2 || near_order[s] != 2) {
+                        ordered_entry.push_back(e);
+                        ordered_target.push_back((int32_t)n);
+                    }
+                }
+        }
         p->n_near = (int64_t)near.col.size();
         p->n_touch = near.n_touch;
         p->d_split = upload(p.get(), near.split);
@@ -862,7 +919,7 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         p->d_tasks = upload(p.get(), m2l.tasks);
         p->d_task_targets = upload(p.get(), m2l.targets);
         p->d_slot_off = upload(p.get(), m2l.slot_key);
-        p->d_slot_src = upload(p.get(), m2l.slot_src);
+        p->d_slot_src = upload(p.get(), m2l.slot_src.get(), (size_t)m2l.slot_key.size() * 64);
         p->n_m2l_splits = (int64_t)m2l.splits.size();
         p->d_m2l_splits = upload(p.get(), m2l.splits);
         if (m2l.n_pieces > 0)
@@ -911,7 +968,9 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         p->d_val = alloc_zero<double>(p.get(), (size_t)p->n_near);
         launch_near_assemble(*p, nullptr);
         BCV_HIP(hipDeviceSynchronize());
+        if (opts.near_order == 1) launch_near_assemble_ordered(*p, ordered_entry, ordered_target, near_order);
     }
+    p->n_near_ordered = (int64_t)ordered_entry.size();
     BCV_HIP(hipDeviceSynchronize());
     return p.release();
 }

@@ -1,8 +1,11 @@
 // BC octree of the unit cube (Sec. 2, Boundary Concentrated Mesh, with cube cells).
 //
 // Level 0 is [0,1]^3. A level-l cell (i, j, k) is the cube [i, i+1] x [j, j+1] x [k, k+1] times 2^-l.
-// For l < L the marked cells M_l are those with a face on the boundary (B_l); the leaves of level l
-// are L_l = C_l minus M_l; C_{l+1} consists of the children of M_l; every level-L cell is a leaf.
+// For l < L the marked cells M_l are, by marking rule,
+//   0: the cells with a face on the boundary (B_l);
+//   1: the cells with a boundary cell among their neighbours, N(w) meeting B_l (the rule of Sec. 2);
+// the leaves of level l are L_l = C_l minus M_l; C_{l+1} consists of the children of M_l; every
+// level-L cell is a leaf.
 #include <algorithm>
 #include <numeric>
 
@@ -10,17 +13,31 @@
 
 namespace bcv {
 
-static bool on_boundary(int lev, int32_t i, int32_t j, int32_t k)
+// Cells between the cell and the nearest boundary plane, along the axis where it is closest (0
+// for a boundary cell).
+static int32_t boundary_distance(int lev, int32_t i, int32_t j, int32_t k)
 {
     const int32_t top = (1 << lev) - 1;
-    return i == 0 || j == 0 || k == 0 || i == top || j == top || k == top;
+    return std::min({i, j, k, top - i, top - j, top - k});
+}
+
+// Marking rule 1: does N(w) contain a boundary cell? Every boundary cell of level l exists (its
+// ancestors are boundary cells, which both rules refine). A boundary cell at integer offset o is a
+// neighbour iff |o|^2 < 12 (eq. def:neighbors with eta0 = 1/2 and rho = a sqrt(3)/2). A boundary
+// cell has a coordinate on a boundary plane, so its offset along that axis is at least d (the
+// distance above) and |o| >= d; the boundary cell straight across the closest plane has |o| = d.
+// So the test is d^2 < 12, i.e. d <= 3.
+static bool near_boundary(int lev, int32_t i, int32_t j, int32_t k)
+{
+    const int32_t d = boundary_distance(lev, i, j, k);
+    return d * d < 12;
 }
 
 // A forest of n unit-cube BC meshes with finest levels L[m]: mesh m occupies [4m, 4m + 1) x [0, 1)^2
 // (in units of a level-0 cell), so cells of different meshes are never neighbours at any level
 // (their integer offsets are at least 4 * 2^l - 2^l > sqrt(12) apart at level l) and the planner
 // treats the forest as one mesh. With n = 1 this is the single mesh of the unit cube.
-bcv_tree_s *build_forest(int n, const int *Ls)
+bcv_tree_s *build_forest(int n, const int *Ls, const int *markings)
 {
     auto *t = new bcv_tree_s;
     t->L = 0;
@@ -46,7 +63,9 @@ bcv_tree_s *build_forest(int n, const int *Ls)
         for (int32_t c = b; c < e; ++c) {
             const int32_t i = t->ijk[3 * c], j = t->ijk[3 * c + 1], k = t->ijk[3 * c + 2];
             const int m = (i >> lev) / 4;
-            if (lev >= Ls[m] || !on_boundary(lev, i - ((4 * m) << lev), j, k)) continue;
+            const int32_t il = i - ((4 * m) << lev);  // coordinates within mesh m
+            const bool mark = markings[m] ? near_boundary(lev, il, j, k) : boundary_distance(lev, il, j, k) == 0;
+            if (lev >= Ls[m] || !mark) continue;
             t->refined[c] = 1;
             t->first_child[c] = (int32_t)t->level.size();
             for (int ch = 0; ch < 8; ++ch)
@@ -71,7 +90,7 @@ bcv_tree_s *build_forest(int n, const int *Ls)
     return t;
 }
 
-bcv_tree_s *build_tree(int L) { return build_forest(1, &L); }
+bcv_tree_s *build_tree(int L, int marking) { return build_forest(1, &L, &marking); }
 
 // Boundary faces of the unit cube: the faces of level-L leaves in the planes x, y, z = 0 or 1
 // (a cell meeting the boundary has a face on it and is refined down to level L).

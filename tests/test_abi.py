@@ -26,18 +26,20 @@ def test_every_declared_symbol_is_exported():
         assert hasattr(lib, n), n
 
 
-@pytest.mark.parametrize("L", [2, 3, 4, 5])
-def test_tree_matches_oracle_mesh(L):
-    t = bcv.build_bc_tree(L)
-    assert np.array_equal(t.leaves().astype(np.int64), BCMesh(L).leaf_array())
+@pytest.mark.parametrize("L,marking", [(2, 0), (3, 0), (4, 0), (5, 0), (2, 1), (4, 1), (5, 1), (6, 1)])
+def test_tree_matches_oracle_mesh(L, marking):
+    """The library's tree against the oracle's mesh (which applies the marking rules by their
+    definitions: a face on the boundary, or a boundary cell among the neighbours)."""
+    t = bcv.build_bc_tree(L, marking)
+    assert np.array_equal(t.leaves().astype(np.int64), BCMesh(L, marking).leaf_array())
 
 
-@pytest.mark.parametrize("L", [2, 3, 5])
-def test_tree_faces_match_oracle(L):
+@pytest.mark.parametrize("L,marking", [(2, 0), (3, 0), (5, 0), (5, 1)])
+def test_tree_faces_match_oracle(L, marking):
     from oracle import boundary
 
-    t = bcv.build_bc_tree(L)
-    assert np.array_equal(t.faces().astype(np.int64), boundary.boundary_faces(BCMesh(L)))
+    t = bcv.build_bc_tree(L, marking)
+    assert np.array_equal(t.faces().astype(np.int64), boundary.boundary_faces(BCMesh(L, marking)))
 
 
 def test_forest_has_no_faces():
@@ -51,14 +53,16 @@ def test_tree_argument_errors():
         with pytest.raises(bcv.BCVError) as e:
             bcv.build_bc_tree(L)
         assert e.value.status == bcv.bcv.EINVAL
-    with pytest.raises(bcv.BCVError) as e:
-        bcv.build_bc_tree(4, marking=1)
-    assert e.value.status == bcv.bcv.EINVAL
+    for mk in (-1, 2):
+        with pytest.raises(bcv.BCVError) as e:
+            bcv.build_bc_tree(4, marking=mk)
+        assert e.value.status == bcv.bcv.EINVAL
 
 
 def test_plan_argument_errors_before_device_use():
     t = bcv.build_bc_tree(3)
-    for kw in ({"q": 5}, {"eta0": 0.4}):
+    for kw in ({"q": 5}, {"eta0": 0.4}, {"near_order": 2}, {"near_order": 1},  # 1 needs the assembled mode
+               {"near_order": 1, "nearfield": bcv.NEAR_QUADRATURE}):
         with pytest.raises(bcv.BCVError) as e:
             bcv.plan_interactions(t, **kw)
         assert e.value.status == bcv.bcv.EINVAL
@@ -89,6 +93,17 @@ def test_forest_leaves_are_the_meshes_leaves():
         loc = lv[mesh == m].copy()
         loc[:, 1] -= (4 * m) << loc[:, 0]
         assert np.array_equal(loc, BCMesh(L).leaf_array())
+
+
+def test_forest_with_both_markings():
+    Ls, marks = [5, 3, 4], [1, 0, 1]
+    t = bcv.build_bc_forest(Ls, marks)
+    lv = t.leaves().astype(np.int64)
+    mesh = t.leaf_mesh()
+    for m, (L, mk) in enumerate(zip(Ls, marks)):
+        loc = lv[mesh == m].copy()
+        loc[:, 1] -= (4 * m) << loc[:, 0]
+        assert np.array_equal(loc, BCMesh(L, mk).leaf_array())
 
 
 def test_forest_argument_errors():
