@@ -38,10 +38,10 @@ PEAK_HBM = 8.0e12  # bytes/s
 
 
 def m2l_flops_per_pair(q):
-    """Algorithmic flops of one interaction pair: one FMA (2 flops) per (alpha, beta), |alpha|+|beta| <= q."""
-    from math import comb
-
-    return 2 * comb(q + 6, 6)
+    """Algorithmic flops of one interaction pair in the harmonic reduction the kernels use: one FMA
+    (2 flops) per (alpha, beta) with alpha_z, beta_z <= 1 and |alpha| + |beta| <= q, i.e.
+    2 sum_{n+m<=q} (2n+1)(2m+1) (1064 at q = 6; the unreduced sums would be 2 C(q+6, 6) = 1848)."""
+    return 2 * sum((2 * n + 1) * (2 * m + 1) for n in range(q + 1) for m in range(q + 1 - n))
 
 
 def ncoef(d):
@@ -50,22 +50,22 @@ def ncoef(d):
 
 def m2l_kernel_names(q, mixed):
     """The interaction-phase launches of one apply (see launch_m2l in kernels.hip)."""
-    K = ncoef(q)
-    if not mixed:
-        if q == 8:
-            S = ncoef(q - 3)
-            return ["m2l_kernel<%d, double, 0, %d>" % (q, S), "m2l_kernel<%d, double, %d, %d>" % (q, S, K)]
-        blocks = [(0, K, 0, 4), (0, 10, 4, K)] if q == 4 else [(0, 35, 0, 10), (35, K, 0, 4), (0, 20, 10, K)]
-    elif q <= 6:
-        S = ncoef(q // 2 - 1)
-        blocks = [(0, K, 0, S), (0, ncoef(q - q // 2), S, K)]
+    R = (q + 1) ** 2
+    if mixed:
+        blocks = [(0, R, 0, R)] if q <= 6 else [(0, R, 0, 16), (0, 25, 16, R)]
+    elif q == 4:
+        blocks = [(0, R, 0, R)]
+    elif q == 6:
+        blocks = [(0, R, 0, 4), (0, 25, 4, 16), (0, 9, 16, R)]
     else:
-        blocks = [(0, 84, 0, 10), (84, K, 0, 4), (0, 56, 10, 35), (0, 20, 35, 84), (0, 4, 84, K)]
+        blocks = [(0, R, 0, 4), (0, 49, 4, 25), (0, 16, 25, R)]
+
     def waves(b):  # as launch_m2l_block: two waves per SIMD where the block's registers exceed 110
         return 2 if (b[1] - b[0] + b[3] - b[2]) * (1 if mixed else 2) > 110 else 4
 
-    return ["m2l_shift_kernel<%d, %s, %d, %d, %d, %d, %d>" % ((q, "float" if mixed else "double") + b + (waves(b),))
-            for b in blocks]
+    kind = "float" if mixed else "double"
+    return (["fold_moments_kernel<%d, %s>" % (q, kind)]
+            + ["m2l_shift_kernel<%d, %s, %d, %d, %d, %d, %d>" % ((q, kind) + b + (waves(b),)) for b in blocks])
 
 
 def near_flops(info, q):
@@ -176,9 +176,9 @@ def roofline(info, phase_avg, args, prec):
                      "peak": peak, "unit": "TFLOP/s"}
     near_name = "near_eval_kernel<%d, %s, %s>" % (args.q, "true" if args.nearfield == "assembled" else "false",
                                                   "true" if mixed and args.nearfield != "assembled" else "false")
-    # the interaction phase: FP32 copy of the moments (mixed), the interaction launches and the sum
-    # of the split tasks' pieces
-    m2l_names = ((["to_f32_kernel"] if mixed else []) + m2l_kernel_names(args.q, mixed)
+    # the interaction phase: the folded moments (FP32 in the mixed path), the interaction launches
+    # and the sum of the split tasks' pieces
+    m2l_names = (m2l_kernel_names(args.q, mixed)
                  + ["m2l_combine_kernel<%d>" % args.q])
     for roof_, names in ((m2l_roof, m2l_names), (near_roof, [near_name])):
         roof_["frac"] = roof_["achieved"] / roof_["peak"]

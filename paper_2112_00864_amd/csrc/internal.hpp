@@ -159,7 +159,8 @@ struct bcv_plan_s {
     double *d_M = nullptr;          // moments, (n_cells + 1) x K; the last row stays zero
     double *d_Lam = nullptr;        // local coefficients, n_cells x K
     double *d_G = nullptr;          // derivative tables, n_offsets x K
-    float *d_M32 = nullptr;         // BCV_MIXED_F32: FP32 copy of the moments, (n_cells + 1) x K
+    float *d_M32 = nullptr;         // BCV_MIXED_F32: folded moments in FP32, (n_cells + 1) x (q + 1)^2
+    double *d_Mr = nullptr;         // BCV_FP64: folded moments, (n_cells + 1) x (q + 1)^2
     float *d_G32 = nullptr;         // BCV_MIXED_F32: FP32 derivative tables
     int32_t *d_parents = nullptr;   // (marked cell, first child) pairs, grouped by level
     bcv::M2LTask *d_tasks = nullptr;

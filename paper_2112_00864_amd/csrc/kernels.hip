@@ -345,47 +345,138 @@ __global__ __launch_bounds__(kWave *tree_waves<Q>()) void l2l_kernel(int n_par, 
     }
 }
 
-// ---- M2L: 64 targets per wave, one uniform interaction offset per slot --------------------------
-// acc[a] += D^{a+b} g(o) * M_s^b for all |a| + |b| <= Q, straight-line code from the index tables.
-// A wave may hold only the coefficients a in [A0, A1) (acc[a - A0]); column b then touches
-// a in [A0, min(A1, ncoef(Q - |b|))), and a column with none of them is not loaded at all.
+// ---- M2L in the harmonic reduction ----------------------------------------------------------------
+// With the scaled coefficients (M^b = (-1)^|b| m^b / (b! a^|b|), Lambda^a = lambda^a a! a^|a|) the
+// interaction is Lambda^a = sum_{|a| + |b| <= Q} G_{a+b} M^b, G_g = a^|g| D^g G(x_w - x_w'). G is
+// harmonic, so G_{g + 2e_z} = -G_{g + 2e_x} - G_{g + 2e_y} (all three of degree |g| + 2). Hence,
+// exactly (the constraint |a| + |b| <= Q only involves degrees, which these maps keep):
+//  * the moments fold onto b_z <= 1: Mr^b = sum_k (-1)^k sum_{i + j = k} C(k, i)
+//    M^{b - 2i e_x - 2j e_y + 2k e_z}, and Lambda^a = sum_{b_z <= 1} G_{a+b} Mr^b;
+//  * Lambda^a for a_z >= 2 follows from the a_z <= 1 ones: with k = floor(a_z / 2),
+//    Lambda^a = (-1)^k sum_{i + j = k} C(k, i) Lambda^{a - 2k e_z + 2i e_x + 2j e_y}.
+// So the pair loop runs over a_z <= 1 and b_z <= 1 only: sum_{n + m <= Q} (2n + 1)(2m + 1) FMAs per
+// pair (532 at Q = 6, against C(Q + 6, 6) = 924 over all multi-indices), and a source row holds
+// (Q + 1)^2 folded moments instead of K.
+template <int Q>
+struct FoldTable {  // Mr^b = sum_t c[b][t] M^{src[b][t]} (full positions)
+    static constexpr int R = nreduced(Q), kTerms = (Q / 4 + 1) * (Q / 4 + 1) + 2;
+    int n[R], src[R][kTerms];
+    double c[R][kTerms];
+    constexpr FoldTable() : n{}, src{}, c{}
+    {
+        constexpr ReducedIndex<Q> ri{};
+        for (int b = 0; b < R; ++b) {
+            const int bx = ri.e[b][0], by = ri.e[b][1], bz = ri.e[b][2];
+            int cnt = 0;
+            double sign = 1.0;
+            for (int k = 0; 2 * k <= bx + by; ++k, sign = -sign) {
+                double binom = 1.0;  // C(k, i)
+                for (int i = 0; i <= k; ++i) {
+                    if (i > 0) binom = binom * (k - i + 1) / i;
+                    const int j = k - i;
+                    if (2 * i > bx || 2 * j > by) continue;
+                    src[b][cnt] = mi_index(bx - 2 * i, by - 2 * j, bz + 2 * k);
+                    c[b][cnt] = sign * binom;
+                    ++cnt;
+                }
+            }
+            n[b] = cnt;
+        }
+    }
+};
+
+template <int Q>
+struct ExpandTable {  // Lambda^a = sum_t c[a][t] Lambda~^{src[a][t]} (reduced positions), a full
+    static constexpr int K = ncoef(Q), kTerms = Q / 2 + 1;
+    int n[K], src[K][kTerms];
+    double c[K][kTerms];
+    constexpr ExpandTable() : n{}, src{}, c{}
+    {
+        constexpr MultiIndex<Q> mi{};
+        for (int a = 0; a < K; ++a) {
+            const int ax = mi.e[a][0], ay = mi.e[a][1], az = mi.e[a][2], k = az / 2;
+            const double sign = (k & 1) ? -1.0 : 1.0;
+            double binom = 1.0;
+            for (int i = 0; i <= k; ++i) {
+                if (i > 0) binom = binom * (k - i + 1) / i;
+                src[a][i] = ReducedIndex<Q>::index(ax + 2 * i, az - 2 * k, mi.deg[a]);
+                c[a][i] = sign * binom;
+            }
+            n[a] = k + 1;
+        }
+    }
+};
+
+template <int Q>
+struct RTables {
+    static constexpr ReducedIndex<Q> ri{};
+    static constexpr ExpandTable<Q> ex{};
+};
+
+template <int Q>
+__constant__ constexpr FoldTable<Q> kFold{};
+
+// Folded moments of every cell row (and the zero row), FP64 in, T out; one thread per coefficient.
+template <int Q, class T>
+__global__ __launch_bounds__(256) void fold_moments_kernel(int64_t n_rows, const double *__restrict__ M,
+                                                           T *__restrict__ Mr)
+{
+    constexpr int K = ncoef(Q), R = nreduced(Q);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_rows * R;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = i / R;
+        const int b = (int)(i - row * R);
+        const double *__restrict__ m = M + row * K;
+        double s = 0.0;
+        for (int t = 0; t < kFold<Q>.n[b]; ++t) s = fma(kFold<Q>.c[b][t], m[kFold<Q>.src[b][t]], s);
+        Mr[i] = (T)s;
+    }
+}
+
+// acc[a - A0] += G_{a+b} * Mr^b for the reduced a in [A0, A1) with |a| + |b| <= Q (straight-line
+// code from the index tables); column b touches a < min(A1, (Q - |b| + 1)^2).
 template <int Q, int A0, int B, class T, class GP, int... A>
 __device__ __forceinline__ void m2l_column(T *acc, GP G, T mb, std::integer_sequence<int, A...>)
 {
-    constexpr auto &mi = Tables<Q>::mi;
-    ((acc[A] = fma(G[mi.sum(A0 + A, B)], mb, acc[A])), ...);
+    constexpr auto &ri = RTables<Q>::ri;
+    ((acc[A] = fma(G[ri.sum(A0 + A, B)], mb, acc[A])), ...);
 }
 
-template <int Q, class T, int A0, int A1, int B>
-__device__ __forceinline__ void m2l_beta(T *acc, const T *__restrict__ G, const T *__restrict__ Ms)
-{
-    constexpr int n = ncoef(Q - Tables<Q>::mi.deg[B]);
-    constexpr int hi = n < A1 ? n : A1;
-    if constexpr (hi > A0) m2l_column<Q, A0, B>(acc, G, Ms[B], std::make_integer_sequence<int, hi - A0>{});
-}
-
-template <int Q, class T, int A0, int A1, int... B>
-__device__ __forceinline__ void m2l_all(T *acc, const T *__restrict__ G, const T *__restrict__ Ms,
-                                        std::integer_sequence<int, B...>)
-{
-    (m2l_beta<Q, T, A0, A1, B>(acc, G, Ms), ...);
-}
-
-// Block (a in [A0, A1)) x (b in [B0, B0 + NB)) of the same sums with the lane's source moments in
-// registers: m[b - B0] holds M_s^b.
 template <int Q, int A0, int A1, int B, class T>
 __device__ __forceinline__ void m2l_beta_reg(T *acc, const T *__restrict__ G, T mb)
 {
-    constexpr int n = ncoef(Q - Tables<Q>::mi.deg[B]);
+    constexpr int n = nreduced(Q - RTables<Q>::ri.deg[B]);
     constexpr int hi = n < A1 ? n : A1;
     if constexpr (hi > A0) m2l_column<Q, A0, B>(acc, G, mb, std::make_integer_sequence<int, hi - A0>{});
 }
 
+// Block (a in [A0, A1)) x (b in [B0, B0 + NB)) with the lane's folded source moments in registers:
+// m[b - B0] holds Mr^b.
 template <int Q, int A0, int A1, int B0, class T, int... Bs>
 __device__ __forceinline__ void m2l_block_reg(T *acc, const T *__restrict__ G, const T *m,
                                              std::integer_sequence<int, Bs...>)
 {
     (m2l_beta_reg<Q, A0, A1, B0 + Bs>(acc, G, m[Bs]), ...);
+}
+
+// Lambda^a (full position FA) from the reduced accumulators of the block starting at A0.
+template <int Q, int A0, int FA, class T, int... Ts>
+__device__ __forceinline__ double expand_one(const T *acc, std::integer_sequence<int, Ts...>)
+{
+    constexpr auto &ex = RTables<Q>::ex;
+    return (0.0 + ... + (ex.c[FA][Ts] * (double)acc[ex.src[FA][Ts] - A0]));
+}
+
+template <int Q, int A0, int FA0, bool kAdd, class T, int... Fs>
+__device__ __forceinline__ void store_expanded(const T *acc, double scale, double *__restrict__ dst, int64_t stride,
+                                               std::integer_sequence<int, Fs...>)
+{
+    constexpr auto &ex = RTables<Q>::ex;
+    ((kAdd ? (void)(dst[Fs * stride] += scale * expand_one<Q, A0, FA0 + Fs>(
+                        acc, std::make_integer_sequence<int, ex.n[FA0 + Fs]>{}))
+           : (void)(dst[Fs * stride] = scale * expand_one<Q, A0, FA0 + Fs>(
+                        acc, std::make_integer_sequence<int, ex.n[FA0 + Fs]>{}))),
+     ...);
 }
 
 // Lane l takes lane l - 1's value; lane 0 keeps its own (DPP wave shift right by one lane; a double
@@ -412,75 +503,30 @@ __device__ __forceinline__ int xcd_task(const XcdRanges &r)
     return t < r.begin[x + 1] ? t : -1;
 }
 
-// Gathering interaction kernel (FP64 at q = 8): every slot gathers the 64 lanes' source rows (the
-// zero row where the offset is outside a lane's list; slot words: source row | (offset in the
-// lane's list) << 31). The wave accumulates Lambda^a for a in [A0, A1), a range that fits the
-// register budget of two waves per SIMD.
-template <int Q, class T, int A0, int A1>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2, 2))) void m2l_kernel(
-    XcdRanges ranges, const M2LTask *__restrict__ tasks, const int32_t *__restrict__ targets,
-    const int32_t *__restrict__ slot_off, const uint32_t *__restrict__ slot_src, const T *__restrict__ G,
-    const T *__restrict__ M, int32_t zero_row, double *__restrict__ partial, double *__restrict__ Lam)
-{
-    constexpr int K = MultiIndex<Q>::K, NA = A1 - A0;
-    const int ti = xcd_task(ranges);
-    if (ti < 0) return;
-    const M2LTask task = tasks[ti];
-    const int lane = threadIdx.x;
-    T acc[NA];
-#pragma unroll
-    for (int a = 0; a < NA; ++a) acc[a] = T(0);
-    auto row_of = [zero_row](uint32_t word) { return (word >> 31) ? (int32_t)(word & 0x7FFFFFFFu) : zero_row; };
-    // the next slot's words are fetched one slot ahead
-    int32_t off_next = 0, src_next = zero_row;
-    if (task.n_slots > 0) {
-        off_next = slot_off[task.slot_begin];
-        src_next = row_of(slot_src[(int64_t)task.slot_begin * kWave + lane]);
-    }
-    for (int j = 0; j < task.n_slots; ++j) {
-        const int32_t ow = off_next, src = src_next;
-        if (j + 1 < task.n_slots) {
-            const int64_t nxt = (int64_t)task.slot_begin + j + 1;
-            off_next = slot_off[nxt];
-            src_next = row_of(slot_src[nxt * kWave + lane]);
-        }
-        const T *__restrict__ Gs = G + (int64_t)(ow & 0x7FFFFFFF) * K;
-        const T *__restrict__ Ms = M + (int64_t)src * K;
-        m2l_all<Q, T, A0, A1>(acc, Gs, Ms, std::make_integer_sequence<int, K>{});
-    }
-    const int32_t t = targets[(int64_t)ti * kWave + lane];
-    if (t < 0) return;
-    const double inv_a = ldexp(1.0, task.level);
-    if (task.out < 0) {
-#pragma unroll
-        for (int a = 0; a < NA; ++a) Lam[(int64_t)t * K + A0 + a] = (double)acc[a] * inv_a;
-    } else {  // [piece][a][lane]: coalesced
-        double *__restrict__ dst = partial + ((int64_t)task.out * K + A0) * kWave + lane;
-#pragma unroll
-        for (int a = 0; a < NA; ++a) dst[a * kWave] = (double)acc[a] * inv_a;
-    }
-}
-
-// Interaction kernel with lane shifts (FP32, and FP64 up to q = 6). The plan lays a task's targets along rows (lane l + 1
+// Interaction kernel with lane shifts. The plan lays a task's targets along rows (lane l + 1 one or
 // two cells after lane l, except at the task's head lanes) and orders its slots so that
-// consecutive offsets step by two cells along the same axis: at a slot without the gather bit
-// every lane's new source is the previous slot's source of the lane below, so the source moments
-// stay in registers, move up one lane by a DPP shift, and only the head lanes read a row, instead
-// of 64 lanes gathering 64 rows. Every slot names the real source of every lane (the zero row
-// where there is no cell) and, in bit 31, whether the offset is in the lane's list; only those
-// lanes accumulate. One launch covers the block a in [A0, A1), b in [B0, B1) of the sums
-// (|a| + |b| <= Q): the launches of a full interaction phase tile the triangle in blocks that fit
-// 128 registers, four waves per SIMD (the latency of the row reads at the start of each slot is
-// covered by the other waves), or two waves for the FP64 block of the high source orders (one
-// block of 40 + 148 registers ran faster than two of four waves each). The block with B0 = 0
-// writes Lambda^a, the others add to it and are launched after it.
+// consecutive offsets step by that many cells along the same axis: at a slot without the gather
+// bit every lane's new source is the previous slot's source of the lane below, so the folded source
+// moments stay in registers, move up one lane by a DPP shift, and only the head lanes read a row,
+// instead of 64 lanes gathering 64 rows. Every slot names the real source of every lane (the zero
+// row where there is no cell) and, in bit 31, whether the offset is in the lane's list; only those
+// lanes accumulate. One launch covers the block a in [A0, A1), b in [B0, B1) of the reduced sums;
+// [A0, A1) is a whole band of degrees, so the block expands its accumulators to every Lambda^a of
+// those degrees. The launches of a full interaction phase tile the reduced triangle in blocks that
+// fit 128 registers (four waves per SIMD, which covers the latency of the row reads at the start
+// of each slot) or 256 (two waves); the block with B0 = 0 writes Lambda^a, the others add to it and
+// are launched after it.
 template <int Q, class T, int A0, int A1, int B0, int B1, int kWaves>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kWaves, kWaves))) void m2l_shift_kernel(
     XcdRanges ranges, const M2LTask *__restrict__ tasks, const int32_t *__restrict__ targets,
     const int32_t *__restrict__ slot_off, const uint32_t *__restrict__ slot_src, const T *__restrict__ G,
-    const T *__restrict__ M, double *__restrict__ partial, double *__restrict__ Lam)
+    const T *__restrict__ Mr, double *__restrict__ partial, double *__restrict__ Lam)
 {
-    constexpr int K = MultiIndex<Q>::K, NA = A1 - A0, NB = B1 - B0;
+    constexpr int K = MultiIndex<Q>::K, R = nreduced(Q), NA = A1 - A0, NB = B1 - B0;
+    constexpr auto &ri = RTables<Q>::ri;
+    constexpr int D0 = ri.deg[A0], D1 = ri.deg[A1 - 1];
+    static_assert(A0 == D0 * D0 && A1 == (D1 + 1) * (D1 + 1), "the a range must be a band of whole degrees");
+    constexpr int FA0 = D0 == 0 ? 0 : ncoef(D0 - 1), FA1 = ncoef(D1);
     const int ti = xcd_task(ranges);
     if (ti < 0) return;
     const M2LTask task = tasks[ti];
@@ -505,7 +551,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kWaves, k
                 ow2 = slot_off[s0 + j + 2];
                 w2 = slot_src[(s0 + j + 2) * kWave + lane];
             }
-            const T *__restrict__ Ms = M + (int64_t)(w & 0x7FFFFFFFu) * K + B0;
+            const T *__restrict__ Ms = Mr + (int64_t)(w & 0x7FFFFFFFu) * R + B0;
             if (ow < 0 || j == 0) {  // gather the sources of all lanes
 #pragma unroll
                 for (int b = 0; b < NB; ++b) m[b] = Ms[b];
@@ -530,23 +576,12 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kWaves, k
     const int32_t t = targets[(int64_t)ti * kWave + lane];
     if (t < 0) return;
     const double inv_a = ldexp(1.0, task.level);
-    double *__restrict__ dst;
-    int64_t stride;
-    if (task.out < 0) {
-        dst = Lam + (int64_t)t * K + A0;
-        stride = 1;
-    } else {  // [piece][a][lane]: coalesced
-        dst = partial + ((int64_t)task.out * K + A0) * kWave + lane;
-        stride = kWave;
-    }
-#pragma unroll
-    for (int a = 0; a < NA; ++a) {
-        const double v = (double)acc[a] * inv_a;
-        if constexpr (B0 == 0)
-            dst[a * stride] = v;
-        else
-            dst[a * stride] += v;
-    }
+    if (task.out < 0)
+        store_expanded<Q, A0, FA0, (B0 > 0)>(acc, inv_a, Lam + (int64_t)t * K + FA0, 1,
+                                             std::make_integer_sequence<int, FA1 - FA0>{});
+    else  // [piece][a][lane]: coalesced
+        store_expanded<Q, A0, FA0, (B0 > 0)>(acc, inv_a, partial + ((int64_t)task.out * K + FA0) * kWave + lane, kWave,
+                                             std::make_integer_sequence<int, FA1 - FA0>{});
 }
 
 // Split tasks: Lambda_t = sum of the pieces' partial local coefficients, in piece order. Block
@@ -567,13 +602,6 @@ __global__ __launch_bounds__(256) void m2l_combine_kernel(const M2LSplit *__rest
     double s = 0.0;
     for (int k = 0; k < sp.count; ++k) s += src[(int64_t)k * K * kWave];
     Lam[(int64_t)t * K + a] = s;
-}
-
-// FP32 copy of the moments for the mixed-precision interaction phase.
-__global__ void to_f32_kernel(int64_t n, const double *__restrict__ in, float *__restrict__ out)
-{
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        out[i] = (float)in[i];
 }
 
 // ---- near field + evaluation: one wave per work unit --------------------------------------------
@@ -1075,64 +1103,50 @@ void launch_near(const bcv_plan_s &p, const double *f, const double *lam, int pa
     }
 }
 template <int Q, int A0, int A1, int B0, int B1, class T>
-void launch_m2l_block(const bcv_plan_s &p, const XcdRanges &ranges, const T *G, const T *M, hipStream_t st)
+void launch_m2l_block(const bcv_plan_s &p, const XcdRanges &ranges, const T *G, const T *Mr, hipStream_t st)
 {
     // four waves per SIMD (128 registers) where the block fits, else two
     constexpr int regs = (A1 - A0 + B1 - B0) * (int)(sizeof(T) / 4);
     m2l_shift_kernel<Q, T, A0, A1, B0, B1, (regs > 110 ? 2 : 4)><<<(unsigned)p.m2l_groups, kWave, 0, st>>>(
-        ranges, p.d_tasks, p.d_task_targets, p.d_slot_off, p.d_slot_src, G, M, p.d_m2l_partial, p.d_Lam);
+        ranges, p.d_tasks, p.d_task_targets, p.d_slot_off, p.d_slot_src, G, Mr, p.d_m2l_partial, p.d_Lam);
     check_launch();
 }
 
-// Interaction phase over all tasks: lane-shifting launches over blocks of the (a, b) triangle, split
-// by degree (n(d) = number of multi-indices of degree <= d) so that every block fits four waves per
-// SIMD; the blocks that write come first. FP64 at q = 8 (K = 165) gathers instead, in two launches
-// over the coefficient range (|a| <= 5, then 6 <= |a| <= 8) at two waves per SIMD.
+// Interaction phase over all tasks: lane-shifting launches over blocks of the reduced (a, b)
+// triangle, by degree bands (n(d) = (d + 1)^2 reduced multi-indices of degree <= d); the block that
+// writes comes first.
 template <int Q>
-void launch_m2l(const bcv_plan_s &p, const double *G, const double *M, hipStream_t st)
+void launch_m2l(const bcv_plan_s &p, const double *G, const double *Mr, hipStream_t st)
 {
-    constexpr int K = MultiIndex<Q>::K;
+    constexpr int R = nreduced(Q);
     XcdRanges ranges;
     for (int x = 0; x <= kXcds; ++x) ranges.begin[x] = p.xcd_begin[x];
     if constexpr (Q == 4) {
-        launch_m2l_block<Q, 0, K, 0, 4>(p, ranges, G, M, st);    // all a, |b| <= 1
-        launch_m2l_block<Q, 0, 10, 4, K>(p, ranges, G, M, st);   // |a| <= 2, |b| >= 2
+        launch_m2l_block<Q, 0, R, 0, R>(p, ranges, G, Mr, st);     // everything: 50 doubles
     } else if constexpr (Q == 6) {
-        launch_m2l_block<Q, 0, 35, 0, 10>(p, ranges, G, M, st);  // |a| <= 4, |b| <= 2
-        launch_m2l_block<Q, 35, K, 0, 4>(p, ranges, G, M, st);   // |a| >= 5, |b| <= 1
-        launch_m2l_block<Q, 0, 20, 10, K>(p, ranges, G, M, st);  // |a| <= 3, |b| >= 3 (two waves)
+        launch_m2l_block<Q, 0, R, 0, 4>(p, ranges, G, Mr, st);     // all a, |b| <= 1
+        launch_m2l_block<Q, 0, 25, 4, 16>(p, ranges, G, Mr, st);   // |a| <= 4, 2 <= |b| <= 3
+        launch_m2l_block<Q, 0, 9, 16, R>(p, ranges, G, Mr, st);    // |a| <= 2, |b| >= 4
     } else {
         static_assert(Q == 8, "orders 4, 6, 8");
-        const unsigned groups = (unsigned)p.m2l_groups;
-        const int32_t zero_row = (int32_t)p.n_cells;
-        constexpr int S = ncoef(Q - 3);
-        m2l_kernel<Q, double, 0, S><<<groups, kWave, 0, st>>>(ranges, p.d_tasks, p.d_task_targets, p.d_slot_off,
-                                                              p.d_slot_src, G, M, zero_row, p.d_m2l_partial, p.d_Lam);
-        check_launch();
-        m2l_kernel<Q, double, S, K><<<groups, kWave, 0, st>>>(ranges, p.d_tasks, p.d_task_targets, p.d_slot_off,
-                                                              p.d_slot_src, G, M, zero_row, p.d_m2l_partial, p.d_Lam);
-        check_launch();
+        launch_m2l_block<Q, 0, R, 0, 4>(p, ranges, G, Mr, st);     // all a, |b| <= 1 (two waves)
+        launch_m2l_block<Q, 0, 49, 4, 25>(p, ranges, G, Mr, st);   // |a| <= 6, 2 <= |b| <= 4 (two waves)
+        launch_m2l_block<Q, 0, 16, 25, R>(p, ranges, G, Mr, st);   // |a| <= 3, |b| >= 5 (two waves)
     }
 }
 
 template <int Q>
-void launch_m2l(const bcv_plan_s &p, const float *G, const float *M, hipStream_t st)
+void launch_m2l(const bcv_plan_s &p, const float *G, const float *Mr, hipStream_t st)
 {
-    constexpr int K = MultiIndex<Q>::K;
+    constexpr int R = nreduced(Q);
     XcdRanges ranges;
     for (int x = 0; x <= kXcds; ++x) ranges.begin[x] = p.xcd_begin[x];
     if constexpr (Q <= 6) {
-        // columns |b| < Q / 2 with every a; columns |b| >= Q / 2 reach only |a| <= Q - Q / 2
-        constexpr int S = ncoef(Q / 2 - 1);
-        launch_m2l_block<Q, 0, K, 0, S>(p, ranges, G, M, st);
-        launch_m2l_block<Q, 0, ncoef(Q - Q / 2), S, K>(p, ranges, G, M, st);
+        launch_m2l_block<Q, 0, R, 0, R>(p, ranges, G, Mr, st);     // everything: 2 (Q + 1)^2 floats
     } else {
         static_assert(Q == 8, "orders 4, 6, 8");
-        launch_m2l_block<Q, 0, 84, 0, 10>(p, ranges, G, M, st);   // |a| <= 6, |b| <= 2
-        launch_m2l_block<Q, 84, K, 0, 4>(p, ranges, G, M, st);    // |a| >= 7, |b| <= 1
-        launch_m2l_block<Q, 0, 56, 10, 35>(p, ranges, G, M, st);  // |a| <= 5, 3 <= |b| <= 4
-        launch_m2l_block<Q, 0, 20, 35, 84>(p, ranges, G, M, st);  // |a| <= 3, 5 <= |b| <= 6
-        launch_m2l_block<Q, 0, 4, 84, K>(p, ranges, G, M, st);    // |a| <= 1, 7 <= |b| <= 8
+        launch_m2l_block<Q, 0, R, 0, 16>(p, ranges, G, Mr, st);    // all a, |b| <= 3
+        launch_m2l_block<Q, 0, 25, 16, R>(p, ranges, G, Mr, st);   // |a| <= 4, |b| >= 4
     }
 }
 
@@ -1156,13 +1170,16 @@ void interaction_phase(const bcv_plan_s &p, hipStream_t st)
 {
     constexpr int K = MultiIndex<Q>::K;
     if (p.n_tasks == 0) return;
+    const int64_t n = (p.n_cells + 1) * nreduced(Q);
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
     if (p.precision == BCV_MIXED_F32) {
-        const int64_t n = (p.n_cells + 1) * K;
-        to_f32_kernel<<<(unsigned)std::min<int64_t>((n + 255) / 256, 65536), 256, 0, st>>>(n, p.d_M, p.d_M32);
+        fold_moments_kernel<Q, float><<<blocks, 256, 0, st>>>(p.n_cells + 1, p.d_M, p.d_M32);
         check_launch();
         launch_m2l<Q>(p, p.d_G32, p.d_M32, st);
     } else {
-        launch_m2l<Q>(p, p.d_G, p.d_M, st);
+        fold_moments_kernel<Q, double><<<blocks, 256, 0, st>>>(p.n_cells + 1, p.d_M, p.d_Mr);
+        check_launch();
+        launch_m2l<Q>(p, p.d_G, p.d_Mr, st);
     }
     if (p.n_m2l_splits > 0) {
         m2l_combine_kernel<Q><<<dim3((unsigned)p.n_m2l_splits, (K + 3) / 4), 256, 0, st>>>(

@@ -40,4 +40,46 @@ struct MultiIndex {
     }
 };
 
+// The multi-indices with a2 <= 1, |alpha| <= Q, in the same graded order: 2d + 1 of degree d, so
+// those of degree <= m occupy the first (m + 1)^2 positions. A homogeneous harmonic polynomial of
+// degree d is fixed by these 2d + 1 of its coefficients; the harmonic reduction of the interaction
+// phase (kernels.hip) works in this index set.
+constexpr int nreduced(int q) { return (q + 1) * (q + 1); }
+
+template <int Q>
+struct ReducedIndex {
+    static constexpr int R = nreduced(Q);
+    int e[R][3];
+    int deg[R];
+    int full[R];  // position in the full graded order
+    constexpr ReducedIndex() : e{}, deg{}, full{}
+    {
+        int n = 0;
+        for (int d = 0; d <= Q; ++d)
+            for (int i = d; i >= 0; --i)
+                for (int j = d - i; j >= 0; --j) {
+                    if (d - i - j > 1) continue;
+                    e[n][0] = i;
+                    e[n][1] = j;
+                    e[n][2] = d - i - j;
+                    deg[n] = d;
+                    full[n] = mi_index(i, j, d - i - j);
+                    ++n;
+                }
+    }
+    // Full position of alpha + beta (both given by reduced position).
+    constexpr int sum(int a, int b) const
+    {
+        return mi_index(e[a][0] + e[b][0], e[a][1] + e[b][1], e[a][2] + e[b][2]);
+    }
+    // Reduced position of the multi-index (i, d - i - k, k), k <= 1, of degree d: within a degree,
+    // a0 = d has one entry (a2 = 0) and every smaller a0 two (a2 = 0, then 1).
+    static constexpr int index(int i, int k, int d)
+    {
+        int n = d * d;  // entries of lower degree
+        for (int a = d; a > i; --a) n += (a == d ? 1 : 2);
+        return n + k;
+    }
+};
+
 }  // namespace bcv

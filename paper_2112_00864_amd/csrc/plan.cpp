@@ -930,7 +930,11 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         p->m2l_groups = (int64_t)kXcds * longest;
         p->d_M = alloc_zero<double>(p.get(), (size_t)(p->n_cells + 1) * p->K);
         p->d_Lam = alloc_zero<double>(p.get(), (size_t)p->n_cells * p->K);
-        if (p->precision == BCV_MIXED_F32) p->d_M32 = alloc_zero<float>(p.get(), (size_t)(p->n_cells + 1) * p->K);
+        const size_t n_folded = (size_t)(p->n_cells + 1) * (size_t)((p->q + 1) * (p->q + 1));
+        if (p->precision == BCV_MIXED_F32)
+            p->d_M32 = alloc_zero<float>(p.get(), n_folded);
+        else
+            p->d_Mr = alloc_zero<double>(p.get(), n_folded);
     }
 
     if (opts.boundary) {
@@ -985,7 +989,7 @@ void destroy_plan(bcv_plan_s *p)
     if (p->side) (void)hipStreamDestroy(p->side);
     void *bufs[] = {p->d_leaf_geom, p->d_leaf_cell, p->d_split, p->d_col, p->d_val, p->d_units,
                     p->d_splits, p->d_partial, p->d_M, p->d_Lam, p->d_G,
-                    p->d_M32, p->d_G32,
+                    p->d_M32, p->d_Mr, p->d_G32,
                     p->d_parents, p->d_tasks, p->d_task_targets, p->d_slot_off, p->d_slot_src,
                     p->d_m2l_splits, p->d_m2l_partial, p->d_faces, p->d_leaf_faces, p->d_btv_col,
                     p->d_btv_units, p->d_btv_splits, p->d_btv_partial, p->d_btv_touch, p->d_vtb_col,
