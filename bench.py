@@ -64,8 +64,7 @@ def m2l_kernel_names(q, mixed):
         return 2 if (b[1] - b[0] + b[3] - b[2]) * (1 if mixed else 2) > 110 else 4
 
     kind = "float" if mixed else "double"
-    return (["fold_moments_kernel<%d, %s>" % (q, kind)]
-            + ["m2l_shift_kernel<%d, %s, %d, %d, %d, %d, %d>" % ((q, kind) + b + (waves(b),)) for b in blocks])
+    return ["m2l_shift_kernel<%d, %s, %d, %d, %d, %d, %d>" % ((q, kind) + b + (waves(b),)) for b in blocks]
 
 
 def near_flops(info, q):
@@ -168,16 +167,17 @@ def roofline(info, phase_avg, args, prec):
     m2l_roof = {"bound": "alu", "achieved": info["n_m2l"] * m2l_flops_per_pair(args.q) / (m2l_ms * 1e-3) / 1e12,
                 "peak": peak, "unit": "TFLOP/s"}
     if args.nearfield == "assembled":
-        near_bytes = info["n_near"] * (8 + 4 + 8) + n * (8 * 2 + 8 + 8 + 32)
+        # entry (FP64, or FP32 in the mixed path) + column index + gathered f per pair
+        near_bytes = info["n_near"] * ((4 if mixed else 8) + 4 + 8) + n * (8 * 2 + 8 + 8 + 32)
         near_roof = {"bound": "hbm", "achieved": near_bytes / (near_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
                      "unit": "GB/s"}
     else:
         near_roof = {"bound": "alu", "achieved": near_flops(info, args.q) / (near_ms * 1e-3) / 1e12,
                      "peak": peak, "unit": "TFLOP/s"}
     near_name = "near_eval_kernel<%d, %s, %s>" % (args.q, "true" if args.nearfield == "assembled" else "false",
-                                                  "true" if mixed and args.nearfield != "assembled" else "false")
-    # the interaction phase: the folded moments (FP32 in the mixed path), the interaction launches
-    # and the sum of the split tasks' pieces
+                                                  "true" if mixed else "false")
+    # the interaction phase: the interaction launches (reading the folded moment rows that P2M and
+    # M2M write) and the sum of the split tasks' pieces
     m2l_names = (m2l_kernel_names(args.q, mixed)
                  + ["m2l_combine_kernel<%d>" % args.q])
     for roof_, names in ((m2l_roof, m2l_names), (near_roof, [near_name])):
@@ -383,7 +383,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--L", type=int, default=7)
     ap.add_argument("--q", type=int, default=6)
-    ap.add_argument("--nearfield", choices=["quadrature", "assembled"], default="quadrature")
+    ap.add_argument("--nearfield", choices=["quadrature", "assembled"], default="assembled",
+                    help="near-field entries stored once at plan time (assembled) or evaluated in every "
+                         "apply (quadrature); the other mode is measured too and reported beside")
     ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both",
                     help="both: time the FP64 and the mixed path on the same mesh and report the ratio")
     ap.add_argument("--streams", type=int, choices=[1, 2], default=2,
@@ -515,6 +517,15 @@ def main():
     if rel_l2 is not None:
         line["mixed_vs_fp64"] = {"rel_l2": rel_l2, "gate": REL_L2_GATE,
                                  "speedup": runs["fp64"]["ms"] / runs["mixed"]["ms"]}
+    # the same headline path with the other near-field mode (not the headline; for comparison)
+    other = "quadrature" if args.nearfield == "assembled" else "assembled"
+    other_nf = bcv.NEAR_QUADRATURE if other == "quadrature" else bcv.NEAR_ASSEMBLED
+    r_o = measure(bcv, torch, tree, f, args, dev, other_nf, head, surrogate if head == "mixed" else None)
+    line["other_near_mode"] = {"nearfield": other, "value": n / (r_o["ms"] * 1e-3), "ms_per_step": r_o["ms"],
+                               "phase_ms": r_o["phases"], "phase_ms_serial": r_o["phases_serial"],
+                               "plan_seconds": r_o["plan_s"], "plan_device_bytes": r_o["info"]["device_bytes"],
+                               "max_rel_diff_vs_headline": float(np.max(np.abs(r_o["u"] - h["u"]) / np.abs(h["u"])))}
+    print("%s with near field %s: step %.3f ms" % (head, other, r_o["ms"]), file=sys.stderr, flush=True)
     if surrogate is not None:
         line["surrogate"] = {"classes_from_network": runs["mixed"]["info"]["surrogate_classes"], "of": 6,
                              "tol": SURROGATE_TOL, "training": sur_report}

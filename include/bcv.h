@@ -69,10 +69,11 @@ typedef struct {
 enum { BCV_NEAR_QUADRATURE = 0, BCV_NEAR_ASSEMBLED = 1 };
 /* Arithmetic of the apply.
  * BCV_FP64: every phase in FP64.
- * BCV_MIXED_F32: the interaction phase (M2L) reads FP32 copies of the moments and derivative tables
- *   and accumulates in FP32; the non-touching near-field pairs evaluate their 64 kernel values in
- *   FP32 (per-axis differences formed in FP64); the touching (singular) pairs, the moments, the
- *   upward and downward passes, the evaluation and the final accumulation of u stay in FP64. */
+ * BCV_MIXED_F32: the interaction phase (M2L) reads FP32 copies of the (folded) moments and the
+ *   derivative tables and accumulates in FP32; the non-touching near-field pairs evaluate their 64
+ *   kernel values in FP32 (per-axis differences formed in FP64), or, assembled, are stored in FP32;
+ *   the touching (singular) pairs, the moments, the upward and downward passes, the evaluation and
+ *   the final accumulation of u stay in FP64. */
 enum { BCV_FP64 = 0, BCV_MIXED_F32 = 1 };
 
 /* Plan options. */
@@ -82,8 +83,9 @@ typedef struct {
     int precision; /* BCV_FP64 or BCV_MIXED_F32 */
     int direct;    /* 1: every leaf pair is treated as near (no far field; small meshes only) */
     int nearfield; /* BCV_NEAR_QUADRATURE: the apply evaluates every near-pair entry on the fly;
-                      BCV_NEAR_ASSEMBLED: the plan stores every near-pair entry (FP64) once and
-                      the apply multiplies by them */
+                      BCV_NEAR_ASSEMBLED: the plan stores every near-pair entry once (computed in
+                      FP64; stored in FP32 by BCV_MIXED_F32 plans, whose apply takes the touching
+                      pairs' exact values in FP64 instead) and the apply multiplies by them */
     int streams;   /* 1: every phase runs on the caller's stream, in Algorithm 1's order;
                       2: after the upward pass, the near field is forked to a plan-owned second
                       stream (default priority), runs concurrently with the interaction phase

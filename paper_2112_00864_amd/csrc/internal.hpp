@@ -152,7 +152,8 @@ struct bcv_plan_s {
     int32_t *d_leaf_cell = nullptr;
     int64_t *d_split = nullptr;     // per near row: first point-rule entry (touching entries come first)
     uint32_t *d_col = nullptr;      // source leaf | (touch class + 1) << 28
-    double *d_val = nullptr;        // assembled near entries (nearfield == ASSEMBLED)
+    double *d_val = nullptr;        // assembled near entries (nearfield == ASSEMBLED, FP64 plans)
+    float *d_val32 = nullptr;       // the same in FP32 (nearfield == ASSEMBLED, mixed plans)
     bcv::NearUnit *d_units = nullptr;   // near-field work units, longest first
     bcv::NearSplit *d_splits = nullptr; // targets whose row spans several units
     double *d_partial = nullptr;        // one partial near sum per unit of a split row

@@ -94,6 +94,74 @@ struct FaceKappaTable {
 template <int Q>
 __constant__ constexpr FaceKappaTable<Q> kFaceKappa{};
 
+// Harmonic folding of the moments (see the M2L section): Mr^b = sum_t c[b][t] M^{src[b][t]} over the
+// (Q + 1)^2 multi-indices b with b_z <= 1. The writers of the moments (P2M, the boundary P2M, M2M)
+// also write the folded rows the interaction phase reads; for the leaf moments this is the folded
+// kappa table.
+template <int Q>
+struct FoldTable {  // Mr^b = sum_t c[b][t] M^{src[b][t]} (full positions)
+    static constexpr int R = nreduced(Q), kTerms = (Q / 4 + 1) * (Q / 4 + 1) + 2;
+    int n[R], src[R][kTerms];
+    double c[R][kTerms];
+    constexpr FoldTable() : n{}, src{}, c{}
+    {
+        constexpr ReducedIndex<Q> ri{};
+        for (int b = 0; b < R; ++b) {
+            const int bx = ri.e[b][0], by = ri.e[b][1], bz = ri.e[b][2];
+            int cnt = 0;
+            double sign = 1.0;
+            for (int k = 0; 2 * k <= bx + by; ++k, sign = -sign) {
+                double binom = 1.0;  // C(k, i)
+                for (int i = 0; i <= k; ++i) {
+                    if (i > 0) binom = binom * (k - i + 1) / i;
+                    const int j = k - i;
+                    if (2 * i > bx || 2 * j > by) continue;
+                    src[b][cnt] = mi_index(bx - 2 * i, by - 2 * j, bz + 2 * k);
+                    c[b][cnt] = sign * binom;
+                    ++cnt;
+                }
+            }
+            n[b] = cnt;
+        }
+    }
+};
+
+
+template <int Q>
+struct FoldedKappaTable {
+    double v[nreduced(Q)];
+    constexpr FoldedKappaTable() : v{}
+    {
+        constexpr KappaTable<Q> kap{};
+        constexpr FoldTable<Q> fo{};
+        for (int b = 0; b < nreduced(Q); ++b)
+            for (int t = 0; t < fo.n[b]; ++t) v[b] += fo.c[b][t] * kap.v[fo.src[b][t]];
+    }
+};
+
+template <int Q>
+struct FoldedFaceKappaTable {
+    double phi[6][nreduced(Q)], psi[6][nreduced(Q)];
+    constexpr FoldedFaceKappaTable() : phi{}, psi{}
+    {
+        constexpr FaceKappaTable<Q> fk{};
+        constexpr FoldTable<Q> fo{};
+        for (int type = 0; type < 6; ++type)
+            for (int b = 0; b < nreduced(Q); ++b)
+                for (int t = 0; t < fo.n[b]; ++t) {
+                    phi[type][b] += fo.c[b][t] * fk.phi[type][fo.src[b][t]];
+                    psi[type][b] += fo.c[b][t] * fk.psi[type][fo.src[b][t]];
+                }
+    }
+};
+
+template <int Q>
+__constant__ constexpr FoldTable<Q> kFold{};
+template <int Q>
+__constant__ constexpr FoldedKappaTable<Q> kFoldedKappa{};
+template <int Q>
+__constant__ constexpr FoldedFaceKappaTable<Q> kFoldedFaceKappa{};
+
 // (1/4)^k / k! for k = 0..kMaxOrder (translation coefficients; the sign (-1)^k is applied by the caller).
 constexpr int kMaxOrder = 8;
 struct QuarterTable {
@@ -194,18 +262,23 @@ __device__ __forceinline__ double near_entry(uint32_t code, const double4 gt, co
     return point_rule(gt, gs);
 }
 
-// ---- P2M: M^b = f a^3 kappa_b on every leaf ------------------------------------------------------
-template <int Q>
+// ---- P2M: M^b = f a^3 kappa_b on every leaf, and the folded row Mr = f a^3 fold(kappa) ------------
+template <int Q, class TR>
 __global__ void p2m_kernel(int64_t n_leaves, const int32_t *__restrict__ leaf_cell, const double4 *__restrict__ geom,
-                           const double *__restrict__ f, double *__restrict__ M)
+                           const double *__restrict__ f, double *__restrict__ M, TR *__restrict__ Mr)
 {
-    constexpr int K = MultiIndex<Q>::K;
+    constexpr int K = MultiIndex<Q>::K, R = nreduced(Q);
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t leaf = idx / K;
-    const int b = (int)(idx - leaf * K);
+    const int64_t leaf = idx / (K + R);
+    const int b = (int)(idx - leaf * (K + R));
     if (leaf >= n_leaves) return;
     const double a = geom[leaf].w;
-    M[(int64_t)leaf_cell[leaf] * K + b] = f[leaf] * (a * a * a) * kKappa<Q>.v[b];
+    const double s = f[leaf] * (a * a * a);
+    const int64_t c = leaf_cell[leaf];
+    if (b < K)
+        M[c * K + b] = s * kKappa<Q>.v[b];
+    else
+        Mr[c * R + (b - K)] = (TR)(s * kFoldedKappa<Q>.v[b - K]);
 }
 
 // ---- M2M and L2L: one wave per marked cell, separable per-axis shifts through LDS -----------------
@@ -248,11 +321,11 @@ __device__ __forceinline__ void m2m_pass(const double *in0, const double *in1, d
     }
 }
 
-template <int Q>
+template <int Q, class TR>
 __global__ __launch_bounds__(kWave *tree_waves<Q>()) void m2m_kernel(int n_par, const int32_t *__restrict__ parents,
-                                                                      double *__restrict__ M)
+                                                                      double *__restrict__ M, TR *__restrict__ Mr)
 {
-    constexpr int K = MultiIndex<Q>::K;
+    constexpr int K = MultiIndex<Q>::K, R = nreduced(Q);
     __shared__ double buf[tree_waves<Q>()][14][K];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int pi = blockIdx.x * tree_waves<Q>() + wave;
@@ -286,8 +359,18 @@ __global__ __launch_bounds__(kWave *tree_waves<Q>()) void m2m_kernel(int n_par, 
             out[n] = acc;
         }
         n = 0;
-        for (int b = lane; b < K; b += kWave, ++n) M[(int64_t)cell * K + b] = out[n];
+        for (int b = lane; b < K; b += kWave, ++n) {
+            M[(int64_t)cell * K + b] = out[n];
+            B[0][b] = out[n];  // slot 0 is free since the x pass
+        }
     }
+    __syncthreads();
+    if (active)  // the folded row
+        for (int r = lane; r < R; r += kWave) {
+            double v = 0.0;
+            for (int t = 0; t < kFold<Q>.n[r]; ++t) v = fma(kFold<Q>.c[r][t], B[0][kFold<Q>.src[r][t]], v);
+            Mr[(int64_t)cell * R + r] = (TR)v;
+        }
 }
 
 // out_cs[a] = sum_{b >= a_AX} tau_cs^(b-a)/(b-a)! in[.., b, ..] for the two children cs (tau = -1/4, +1/4)
@@ -358,34 +441,6 @@ __global__ __launch_bounds__(kWave *tree_waves<Q>()) void l2l_kernel(int n_par, 
 // pair (532 at Q = 6, against C(Q + 6, 6) = 924 over all multi-indices), and a source row holds
 // (Q + 1)^2 folded moments instead of K.
 template <int Q>
-struct FoldTable {  // Mr^b = sum_t c[b][t] M^{src[b][t]} (full positions)
-    static constexpr int R = nreduced(Q), kTerms = (Q / 4 + 1) * (Q / 4 + 1) + 2;
-    int n[R], src[R][kTerms];
-    double c[R][kTerms];
-    constexpr FoldTable() : n{}, src{}, c{}
-    {
-        constexpr ReducedIndex<Q> ri{};
-        for (int b = 0; b < R; ++b) {
-            const int bx = ri.e[b][0], by = ri.e[b][1], bz = ri.e[b][2];
-            int cnt = 0;
-            double sign = 1.0;
-            for (int k = 0; 2 * k <= bx + by; ++k, sign = -sign) {
-                double binom = 1.0;  // C(k, i)
-                for (int i = 0; i <= k; ++i) {
-                    if (i > 0) binom = binom * (k - i + 1) / i;
-                    const int j = k - i;
-                    if (2 * i > bx || 2 * j > by) continue;
-                    src[b][cnt] = mi_index(bx - 2 * i, by - 2 * j, bz + 2 * k);
-                    c[b][cnt] = sign * binom;
-                    ++cnt;
-                }
-            }
-            n[b] = cnt;
-        }
-    }
-};
-
-template <int Q>
 struct ExpandTable {  // Lambda^a = sum_t c[a][t] Lambda~^{src[a][t]} (reduced positions), a full
     static constexpr int K = ncoef(Q), kTerms = Q / 2 + 1;
     int n[K], src[K][kTerms];
@@ -412,26 +467,6 @@ struct RTables {
     static constexpr ReducedIndex<Q> ri{};
     static constexpr ExpandTable<Q> ex{};
 };
-
-template <int Q>
-__constant__ constexpr FoldTable<Q> kFold{};
-
-// Folded moments of every cell row (and the zero row), FP64 in, T out; one thread per coefficient.
-template <int Q, class T>
-__global__ __launch_bounds__(256) void fold_moments_kernel(int64_t n_rows, const double *__restrict__ M,
-                                                           T *__restrict__ Mr)
-{
-    constexpr int K = ncoef(Q), R = nreduced(Q);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_rows * R;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t row = i / R;
-        const int b = (int)(i - row * R);
-        const double *__restrict__ m = M + row * K;
-        double s = 0.0;
-        for (int t = 0; t < kFold<Q>.n[b]; ++t) s = fma(kFold<Q>.c[b][t], m[kFold<Q>.src[b][t]], s);
-        Mr[i] = (T)s;
-    }
-}
 
 // acc[a - A0] += G_{a+b} * Mr^b for the reduced a in [A0, A1) with |a| + |b| <= Q (straight-line
 // code from the index tables); column b touches a < min(A1, (Q - |b| + 1)^2).
@@ -624,6 +659,7 @@ __global__ __launch_bounds__(256) void near_eval_kernel(int64_t n_units, const N
                                                         const int64_t *__restrict__ split,
                                                         const uint32_t *__restrict__ col,
                                                         const double *__restrict__ val,
+                                                        const float *__restrict__ val32,
                                                         const double4 *__restrict__ geom,
                                                         const double *__restrict__ f,
                                                         const double *__restrict__ Lam,
@@ -641,7 +677,7 @@ __global__ __launch_bounds__(256) void near_eval_kernel(int64_t n_units, const N
     double acc = 0.0;
     if (parts & BCV_PART_NEAR) {
         const int64_t e0 = un.begin, e1 = un.end;
-        if (kAssembled) {
+        if (kAssembled && !kMixed) {
             int64_t e = e0 + lane;
             for (; e + kWave < e1; e += 2 * kWave) {  // two pairs per lane per step
                 const uint32_t c0 = col[e], c1 = col[e + kWave];
@@ -650,6 +686,23 @@ __global__ __launch_bounds__(256) void near_eval_kernel(int64_t n_units, const N
                 acc = fma(v1, f[c1 & 0x0FFFFFFFu], acc);
             }
             if (e < e1) acc = fma(val[e], f[col[e] & 0x0FFFFFFFu], acc);
+        } else if (kAssembled) {  // FP32 entries; the touching pairs exact, in FP64
+            const int64_t es = min(max(split[t], e0), e1);
+            const double a_t = gt.w;
+            for (int64_t e = e0 + lane; e < es; e += kWave) {
+                const uint32_t code = col[e];
+                const int32_t s = (int32_t)(code & 0x0FFFFFFFu);
+                const double a = fmin(a_t, geom[s].w);
+                acc = fma(tv.v[(code >> 28) - 1] * (a * a) * (a * a) * a, f[s], acc);
+            }
+            int64_t e = es + lane;
+            for (; e + kWave < e1; e += 2 * kWave) {  // two pairs per lane per step
+                const uint32_t c0 = col[e], c1 = col[e + kWave];
+                const float v0 = val32[e], v1 = val32[e + kWave];
+                acc = fma((double)v0, f[c0 & 0x0FFFFFFFu], acc);
+                acc = fma((double)v1, f[c1 & 0x0FFFFFFFu], acc);
+            }
+            if (e < e1) acc = fma((double)val32[e], f[col[e] & 0x0FFFFFFFu], acc);
         } else {
             const int64_t es = min(max(split[t], e0), e1);
             const double a_t = gt.w;
@@ -738,24 +791,30 @@ __global__ __launch_bounds__(256) void eval_add_kernel(int64_t n_leaves, const d
 
 // Moments of every leaf from its boundary faces (zero for leaves without one): one thread per
 // (leaf, coefficient).
-template <int Q>
+template <int Q, class TR>
 __global__ void btv_p2m_kernel(int64_t n_leaves, const int32_t *__restrict__ leaf_cell,
                                const double4 *__restrict__ geom, const int32_t *__restrict__ leaf_faces,
                                const uint32_t *__restrict__ faces, const double *__restrict__ qf,
-                               const double *__restrict__ gf, double *__restrict__ M)
+                               const double *__restrict__ gf, double *__restrict__ M, TR *__restrict__ Mr)
 {
-    constexpr int K = MultiIndex<Q>::K;
+    constexpr int K = MultiIndex<Q>::K, R = nreduced(Q);
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t leaf = idx / K;
-    const int b = (int)(idx - leaf * K);
+    const int64_t leaf = idx / (K + R);
+    const int b = (int)(idx - leaf * (K + R));
     if (leaf >= n_leaves) return;
     const double a = geom[leaf].w;
     double m = 0.0;
     for (int32_t f = leaf_faces[leaf]; f < leaf_faces[leaf + 1]; ++f) {
         const int type = (int)(faces[f] >> 28);
-        m += a * (a * qf[f] * kFaceKappa<Q>.phi[type][b] - gf[f] * kFaceKappa<Q>.psi[type][b]);
+        if (b < K)
+            m += a * (a * qf[f] * kFaceKappa<Q>.phi[type][b] - gf[f] * kFaceKappa<Q>.psi[type][b]);
+        else
+            m += a * (a * qf[f] * kFoldedFaceKappa<Q>.phi[type][b - K] - gf[f] * kFoldedFaceKappa<Q>.psi[type][b - K]);
     }
-    M[(int64_t)leaf_cell[leaf] * K + b] = m;
+    if (b < K)
+        M[(int64_t)leaf_cell[leaf] * K + b] = m;
+    else
+        Mr[(int64_t)leaf_cell[leaf] * R + (b - K)] = (TR)m;
 }
 
 __device__ __forceinline__ double pick3(const double v[3], int d) { return d == 0 ? v[0] : (d == 1 ? v[1] : v[2]); }
@@ -1002,6 +1061,13 @@ __global__ __launch_bounds__(256) void near_assemble_ordered_kernel(int64_t n, c
     if (lane == 0) val[e] = acc * vt * vs * kInv4Pi;
 }
 
+// FP32 copy of the assembled entries (mixed precision).
+__global__ __launch_bounds__(256) void narrow_kernel(int64_t n, const double *__restrict__ in, float *__restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (float)in[i];
+}
+
 // ---- regular cube pairs (touching-integral self-similarity system) -------------------------------
 constexpr int kMaxGauss = 16;
 struct GaussRule {
@@ -1083,18 +1149,23 @@ void launch_near(const bcv_plan_s &p, const double *f, const double *lam, int pa
 {
     const unsigned blocks = (unsigned)((p.n_units + 3) / 4);
     const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
-    if (p.d_val)
+    const bool mixed = p.precision == BCV_MIXED_F32;
+    if (p.nearfield == BCV_NEAR_ASSEMBLED && mixed)
+        near_eval_kernel<Q, true, true><<<blocks, 256, 0, st>>>(p.n_units, p.d_units, p.d_split, p.d_col, nullptr,
+                                                                p.d_val32, geom, f, lam, p.d_leaf_cell,
+                                                                touch_values(p), parts, p.d_partial, u);
+    else if (p.nearfield == BCV_NEAR_ASSEMBLED)
         near_eval_kernel<Q, true, false><<<blocks, 256, 0, st>>>(p.n_units, p.d_units, p.d_split, p.d_col, p.d_val,
-                                                                 geom, f, lam, p.d_leaf_cell, touch_values(p),
-                                                                 parts, p.d_partial, u);
-    else if (p.precision == BCV_MIXED_F32)
+                                                                 nullptr, geom, f, lam, p.d_leaf_cell,
+                                                                 touch_values(p), parts, p.d_partial, u);
+    else if (mixed)
         near_eval_kernel<Q, false, true><<<blocks, 256, 0, st>>>(p.n_units, p.d_units, p.d_split, p.d_col, nullptr,
-                                                                 geom, f, lam, p.d_leaf_cell, touch_values(p),
-                                                                 parts, p.d_partial, u);
+                                                                 nullptr, geom, f, lam, p.d_leaf_cell,
+                                                                 touch_values(p), parts, p.d_partial, u);
     else
         near_eval_kernel<Q, false, false><<<blocks, 256, 0, st>>>(p.n_units, p.d_units, p.d_split, p.d_col, nullptr,
-                                                                  geom, f, lam, p.d_leaf_cell, touch_values(p),
-                                                                  parts, p.d_partial, u);
+                                                                  nullptr, geom, f, lam, p.d_leaf_cell,
+                                                                  touch_values(p), parts, p.d_partial, u);
     check_launch();
     if (p.n_splits > 0) {
         near_combine_kernel<Q><<<(unsigned)((p.n_splits + 3) / 4), 256, 0, st>>>(
@@ -1153,14 +1224,33 @@ void launch_m2l(const bcv_plan_s &p, const float *G, const float *Mr, hipStream_
 // Upward pass (M2M, l = L-1 .. 2; moments below level 2 are never used), interaction phase (M2L
 // with the FP32 copy of the moments in the mixed path) and downward pass (L2L), shared by the VtV
 // and BtV applies.
+// P2M with the folded rows (FP32 in the mixed path).
+template <int Q>
+void launch_p2m(const bcv_plan_s &p, const double *f, hipStream_t st)
+{
+    const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
+    const int64_t nthr = p.n_leaves * (MultiIndex<Q>::K + nreduced(Q));
+    const unsigned blocks = (unsigned)((nthr + 255) / 256);
+    if (p.precision == BCV_MIXED_F32)
+        p2m_kernel<Q, float><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, f, p.d_M, p.d_M32);
+    else
+        p2m_kernel<Q, double><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, f, p.d_M, p.d_Mr);
+    check_launch();
+}
+
 template <int Q>
 void upward_pass(const bcv_plan_s &p, hipStream_t st)
 {
     for (int lev = p.L - 1; lev >= 2; --lev) {
         const int n_par = p.parent_begin[lev + 1] - p.parent_begin[lev];
         if (n_par == 0) continue;
-        m2m_kernel<Q><<<(unsigned)((n_par + tree_waves<Q>() - 1) / tree_waves<Q>()), kWave * tree_waves<Q>(), 0, st>>>(
-            n_par, p.d_parents + 2 * p.parent_begin[lev], p.d_M);
+        const unsigned blocks = (unsigned)((n_par + tree_waves<Q>() - 1) / tree_waves<Q>());
+        if (p.precision == BCV_MIXED_F32)
+            m2m_kernel<Q, float><<<blocks, kWave * tree_waves<Q>(), 0, st>>>(
+                n_par, p.d_parents + 2 * p.parent_begin[lev], p.d_M, p.d_M32);
+        else
+            m2m_kernel<Q, double><<<blocks, kWave * tree_waves<Q>(), 0, st>>>(
+                n_par, p.d_parents + 2 * p.parent_begin[lev], p.d_M, p.d_Mr);
         check_launch();
     }
 }
@@ -1170,17 +1260,11 @@ void interaction_phase(const bcv_plan_s &p, hipStream_t st)
 {
     constexpr int K = MultiIndex<Q>::K;
     if (p.n_tasks == 0) return;
-    const int64_t n = (p.n_cells + 1) * nreduced(Q);
-    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
-    if (p.precision == BCV_MIXED_F32) {
-        fold_moments_kernel<Q, float><<<blocks, 256, 0, st>>>(p.n_cells + 1, p.d_M, p.d_M32);
-        check_launch();
+    // the folded moment rows were written with the moments (P2M, boundary P2M, M2M)
+    if (p.precision == BCV_MIXED_F32)
         launch_m2l<Q>(p, p.d_G32, p.d_M32, st);
-    } else {
-        fold_moments_kernel<Q, double><<<blocks, 256, 0, st>>>(p.n_cells + 1, p.d_M, p.d_Mr);
-        check_launch();
+    else
         launch_m2l<Q>(p, p.d_G, p.d_Mr, st);
-    }
     if (p.n_m2l_splits > 0) {
         m2l_combine_kernel<Q><<<dim3((unsigned)p.n_m2l_splits, (K + 3) / 4), 256, 0, st>>>(
             p.d_m2l_splits, p.d_task_targets, p.d_m2l_partial, p.d_Lam);
@@ -1211,9 +1295,7 @@ void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStre
     PhaseMarks marks(p);
     if (far) {
         marks.start(BCV_PHASE_P2M, st);
-        const int64_t nthr = p.n_leaves * K;
-        p2m_kernel<Q><<<(unsigned)((nthr + 255) / 256), 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, f, p.d_M);
-        check_launch();
+        launch_p2m<Q>(p, f, st);
         marks.stop(BCV_PHASE_P2M, st);
         marks.start(BCV_PHASE_M2M, st);
         upward_pass<Q>(p, st);
@@ -1262,9 +1344,14 @@ void btv_q(const bcv_plan_s &p, const double *qf, const double *gf, double *u, h
     const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
     const bool far = !p.direct;
     if (far) {
-        const int64_t nthr = p.n_leaves * K;
-        btv_p2m_kernel<Q><<<(unsigned)((nthr + 255) / 256), 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom,
-                                                                         p.d_leaf_faces, p.d_faces, qf, gf, p.d_M);
+        const int64_t nthr = p.n_leaves * (K + nreduced(Q));
+        const unsigned blocks = (unsigned)((nthr + 255) / 256);
+        if (p.precision == BCV_MIXED_F32)
+            btv_p2m_kernel<Q, float><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, p.d_leaf_faces,
+                                                             p.d_faces, qf, gf, p.d_M, p.d_M32);
+        else
+            btv_p2m_kernel<Q, double><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, p.d_leaf_faces,
+                                                              p.d_faces, qf, gf, p.d_M, p.d_Mr);
         check_launch();
         upward_pass<Q>(p, st);
         interaction_phase<Q>(p, st);
@@ -1297,9 +1384,7 @@ void vtb_q(const bcv_plan_s &p, const double *f, double *uf, hipStream_t st)
     const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
     const bool far = !p.direct;
     if (far) {
-        const int64_t nthr = p.n_leaves * K;
-        p2m_kernel<Q><<<(unsigned)((nthr + 255) / 256), 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, f, p.d_M);
-        check_launch();
+        launch_p2m<Q>(p, f, st);
         upward_pass<Q>(p, st);
         interaction_phase<Q>(p, st);
         downward_pass<Q>(p, st);
@@ -1358,6 +1443,13 @@ void launch_near_assemble(const bcv_plan_s &p, hipStream_t st)
     near_assemble_kernel<<<blocks, 256, 0, st>>>(p.n_units, p.d_units, p.d_col,
                                                  reinterpret_cast<const double4 *>(p.d_leaf_geom), touch_values(p),
                                                  p.d_val);
+    check_launch();
+}
+
+void launch_near_narrow(const bcv_plan_s &p, hipStream_t st)
+{
+    const unsigned blocks = (unsigned)std::min<int64_t>((p.n_near + 255) / 256, 65536);
+    if (p.n_near > 0) narrow_kernel<<<blocks, 256, 0, st>>>(p.n_near, p.d_val, p.d_val32);
     check_launch();
 }
 

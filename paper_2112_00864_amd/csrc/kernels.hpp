@@ -14,6 +14,8 @@ void launch_vtb(const bcv_plan_s &p, const double *f, double *uf, hipStream_t st
 
 // Stores every near-pair Galerkin entry of the plan in p.d_val (plan time).
 void launch_near_assemble(const bcv_plan_s &p, hipStream_t stream);
+// p.d_val32 = FP32 copy of p.d_val (plan time, mixed precision).
+void launch_near_narrow(const bcv_plan_s &p, hipStream_t stream);
 // Overwrites the near entries d_val[entry[k]] (row target[k]; non-touching pairs) with the tensor
 // Gauss rule of order[t] points per axis on the target and order[s] on the source (plan time, on
 // the null stream; synchronizes). order: one per leaf, 1..16.

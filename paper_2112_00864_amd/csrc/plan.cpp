@@ -973,6 +973,14 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         launch_near_assemble(*p, nullptr);
         BCV_HIP(hipDeviceSynchronize());
         if (opts.near_order == 1) launch_near_assemble_ordered(*p, ordered_entry, ordered_target, near_order);
+        if (p->precision == BCV_MIXED_F32) {  // the apply reads FP32 entries (touching pairs stay exact)
+            p->d_val32 = alloc_zero<float>(p.get(), (size_t)p->n_near);
+            launch_near_narrow(*p, nullptr);
+            BCV_HIP(hipDeviceSynchronize());
+            BCV_HIP(hipFree(p->d_val));
+            p->d_val = nullptr;
+            p->device_bytes -= (int64_t)(sizeof(double) * p->n_near);
+        }
     }
     p->n_near_ordered = (int64_t)ordered_entry.size();
     BCV_HIP(hipDeviceSynchronize());
@@ -987,7 +995,7 @@ void destroy_plan(bcv_plan_s *p)
     if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
     if (p->ev_join) (void)hipEventDestroy(p->ev_join);
     if (p->side) (void)hipStreamDestroy(p->side);
-    void *bufs[] = {p->d_leaf_geom, p->d_leaf_cell, p->d_split, p->d_col, p->d_val, p->d_units,
+    void *bufs[] = {p->d_leaf_geom, p->d_leaf_cell, p->d_split, p->d_col, p->d_val, p->d_val32, p->d_units,
                     p->d_splits, p->d_partial, p->d_M, p->d_Lam, p->d_G,
                     p->d_M32, p->d_Mr, p->d_G32,
                     p->d_parents, p->d_tasks, p->d_task_targets, p->d_slot_off, p->d_slot_src,

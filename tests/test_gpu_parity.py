@@ -144,6 +144,25 @@ def test_mixed_precision_full_size():
     assert e <= MIXED_TOL
 
 
+@pytest.mark.parametrize("L,q", [(4, 6), (7, 6)])
+def test_mixed_assembled_near_field(L, q):
+    """Mixed precision with the assembled near field (FP32 entries, touching pairs exact in FP64):
+    against the FP64 assembled apply (near part alone and total) and the mixed on-the-fly apply."""
+    m, lv = mesh(L)
+    f = synth.leaf_density(lv, seed=6)
+    t = bcv.build_bc_tree(L)
+    announce("mixed assembled L=%d q=%d" % (L, q))
+    a64 = bcv.plan_interactions(t, q=q, nearfield=bcv.NEAR_ASSEMBLED)
+    a32 = bcv.plan_interactions(t, q=q, nearfield=bcv.NEAR_ASSEMBLED, precision=bcv.MIXED_F32)
+    e_near = rel_l2(lv, gpu_apply(a32, f, bcv.PART_NEAR), gpu_apply(a64, f, bcv.PART_NEAR))
+    u64, u32 = gpu_apply(a64, f), gpu_apply(a32, f)
+    e = rel_l2(lv, u32, u64)
+    e_q = rel_l2(lv, u32, gpu_apply(bcv.plan_interactions(t, q=q, precision=bcv.MIXED_F32), f))
+    announce("mixed assembled L=%d rel-L2 near %.3e total %.3e vs mixed quadrature %.3e" % (L, e_near, e, e_q))
+    assert e_near <= 1e-7 and e <= MIXED_TOL and e_q <= MIXED_TOL
+    assert a32.info["device_bytes"] < a64.info["device_bytes"]
+
+
 def test_degenerate_densities():
     m, lv = mesh(3)
     plan = bcv.plan_interactions(bcv.build_bc_tree(3), q=6)
