@@ -268,17 +268,14 @@ __global__ void p2m_kernel(int64_t n_leaves, const int32_t *__restrict__ leaf_ce
                            const double *__restrict__ f, double *__restrict__ M, TR *__restrict__ Mr)
 {
     constexpr int K = MultiIndex<Q>::K, R = nreduced(Q);
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t leaf = idx / (K + R);
-    const int b = (int)(idx - leaf * (K + R));
+    const int64_t leaf = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;  // one wave per leaf
+    const int lane = threadIdx.x % kWave;
     if (leaf >= n_leaves) return;
     const double a = geom[leaf].w;
     const double s = f[leaf] * (a * a * a);
     const int64_t c = leaf_cell[leaf];
-    if (b < K)
-        M[c * K + b] = s * kKappa<Q>.v[b];
-    else
-        Mr[c * R + (b - K)] = (TR)(s * kFoldedKappa<Q>.v[b - K]);
+    for (int b = lane; b < K; b += kWave) M[c * K + b] = s * kKappa<Q>.v[b];
+    for (int b = lane; b < R; b += kWave) Mr[c * R + b] = (TR)(s * kFoldedKappa<Q>.v[b]);
 }
 
 // ---- M2M and L2L: one wave per marked cell, separable per-axis shifts through LDS -----------------
@@ -287,37 +284,23 @@ __global__ void p2m_kernel(int64_t n_leaves, const int32_t *__restrict__ leaf_ce
 //   L2L  Lam_c^a = 2^-|a| prod_i [ sum_{b_i >= a_i} tau_i^(b_i-a_i)/(b_i-a_i)! ] Lam_P^b
 // so the 8 children are combined pairwise along x, then y, then z (M2M), and the parent is
 // expanded along z, then y, then x (L2L): 14 one-dimensional passes per parent instead of 8 full
-// three-dimensional sums.
-// Parents per block (one wave each); fewer at q = 8 to keep the LDS buffers of a block small.
+// three-dimensional sums. Lane l owns the coefficients l, l + 64, ...: their multi-indices are read
+// once, and within a pass the index and weight of every term are shared by all the vectors the pass
+// treats. The 1-D weights come from a small LDS table.
+// Parents per block (one wave each).
 template <int Q>
 constexpr int tree_waves()
 {
-    return Q <= 6 ? 4 : 2;
+    return 4;
 }
 
-template <int Q, int AX>
-__device__ __forceinline__ int step_index(int a0, int a1, int a2, int v)  // index with component AX replaced by v
+// w[e][g] = (1/4)^(e-g)/(e-g)! 2^-g for g <= e (M2M); the L2L weights are w[k][0] = (1/4)^k/k!.
+template <int Q>
+__device__ __forceinline__ void fill_shift_weights(double (*w)[Q + 1])
 {
-    return AX == 0 ? mi_index(v, a1, a2) : (AX == 1 ? mi_index(a0, v, a2) : mi_index(a0, a1, v));
-}
-
-// out[b] = sum over the two children cs = 0, 1 along axis AX of sum_{g <= b_AX} (-tau)^(b-g)/(b-g)! 2^-g in_cs[.., g, ..]
-template <int Q, int AX>
-__device__ __forceinline__ void m2m_pass(const double *in0, const double *in1, double *out, int lane)
-{
-    constexpr auto &mi = Tables<Q>::mi;
-    constexpr int K = MultiIndex<Q>::K;
-    for (int b = lane; b < K; b += kWave) {
-        const int e[3] = {mi.e[b][0], mi.e[b][1], mi.e[b][2]};
-        double acc = 0.0;
-        for (int g = 0; g <= e[AX]; ++g) {
-            const int idx = step_index<Q, AX>(e[0], e[1], e[2], g);
-            const double w = kQuarter.v[e[AX] - g] * ldexp(1.0, -g);
-            // lower child (cs = 0): -tau = +1/4; upper child: -tau = -1/4
-            const double sgn = ((e[AX] - g) & 1) ? -1.0 : 1.0;
-            acc = fma(w, in0[idx] + sgn * in1[idx], acc);
-        }
-        out[b] = acc;
+    for (int i = threadIdx.x; i < (Q + 1) * (Q + 1); i += blockDim.x) {
+        const int e = i / (Q + 1), g = i % (Q + 1);
+        w[e][g] = g <= e ? kQuarter.v[e - g] * ldexp(1.0, -g) : 0.0;
     }
 }
 
@@ -325,12 +308,23 @@ template <int Q, class TR>
 __global__ __launch_bounds__(kWave *tree_waves<Q>()) void m2m_kernel(int n_par, const int32_t *__restrict__ parents,
                                                                       double *__restrict__ M, TR *__restrict__ Mr)
 {
-    constexpr int K = MultiIndex<Q>::K, R = nreduced(Q);
-    __shared__ double buf[tree_waves<Q>()][14][K];
+    constexpr int K = MultiIndex<Q>::K, R = nreduced(Q), NB = (K + kWave - 1) / kWave;
+    constexpr auto &mi = Tables<Q>::mi;
+    __shared__ double buf[tree_waves<Q>()][8][K];
+    __shared__ double w[Q + 1][Q + 1];
+    fill_shift_weights<Q>(w);
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int pi = blockIdx.x * tree_waves<Q>() + wave;
     const bool active = pi < n_par;
     double(*B)[K] = buf[wave];
+    int ex[NB], ey[NB], ez[NB];
+#pragma unroll
+    for (int n = 0; n < NB; ++n) {
+        const int b = lane + kWave * n;
+        ex[n] = b < K ? mi.e[b][0] : 0;
+        ey[n] = b < K ? mi.e[b][1] : 0;
+        ez[n] = b < K ? mi.e[b][2] : 0;
+    }
     int32_t cell = 0;
     if (active) {
         cell = parents[2 * pi];
@@ -338,72 +332,94 @@ __global__ __launch_bounds__(kWave *tree_waves<Q>()) void m2m_kernel(int n_par, 
         for (int n = lane; n < 8 * K; n += kWave) B[n / K][n % K] = src[n];
     }
     __syncthreads();
-    if (active)  // x: children (0,y,z) + (1,y,z) -> 4 vectors, slots 8..11 indexed by y + 2z
-        for (int yz = 0; yz < 4; ++yz) m2m_pass<Q, 0>(B[2 * yz], B[2 * yz + 1], B[8 + yz], lane);
-    __syncthreads();
-    if (active)  // y: slots 8 + (0,z), 8 + (1,z) -> slots 12 + z
-        for (int z = 0; z < 2; ++z) m2m_pass<Q, 1>(B[8 + 2 * z], B[8 + 2 * z + 1], B[12 + z], lane);
-    __syncthreads();
-    if (active) {  // z: slots 12, 13 -> parent moments
-        double out[(K + kWave - 1) / kWave];
-        constexpr auto &mi = Tables<Q>::mi;
-        int n = 0;
-        for (int b = lane; b < K; b += kWave, ++n) {
-            const int e[3] = {mi.e[b][0], mi.e[b][1], mi.e[b][2]};
-            double acc = 0.0;
-            for (int g = 0; g <= e[2]; ++g) {
-                const int idx = mi_index(e[0], e[1], g);
-                const double sgn = ((e[2] - g) & 1) ? -1.0 : 1.0;
-                acc = fma(kQuarter.v[e[2] - g] * ldexp(1.0, -g), B[12][idx] + sgn * B[13][idx], acc);
+    // x: children (0,y,z) + (1,y,z) -> 4 vectors indexed by y + 2z (lower child: -tau = +1/4)
+    double xo[NB][4] = {};
+    if (active)
+#pragma unroll
+        for (int n = 0; n < NB; ++n) {
+            if (lane + kWave * n >= K) continue;
+            for (int g = 0; g <= ex[n]; ++g) {
+                const int idx = mi_index(g, ey[n], ez[n]);
+                const double wt = w[ex[n]][g], sg = ((ex[n] - g) & 1) ? -wt : wt;
+#pragma unroll
+                for (int yz = 0; yz < 4; ++yz) xo[n][yz] += wt * B[2 * yz][idx] + sg * B[2 * yz + 1][idx];
             }
-            out[n] = acc;
         }
-        n = 0;
-        for (int b = lane; b < K; b += kWave, ++n) {
-            M[(int64_t)cell * K + b] = out[n];
-            B[0][b] = out[n];  // slot 0 is free since the x pass
+    __syncthreads();
+    if (active)
+#pragma unroll
+        for (int n = 0; n < NB; ++n)
+            if (lane + kWave * n < K)
+#pragma unroll
+                for (int yz = 0; yz < 4; ++yz) B[yz][lane + kWave * n] = xo[n][yz];
+    __syncthreads();
+    // y: vectors (0,z) + (1,z) -> 2 vectors indexed by z
+    double yo[NB][2] = {};
+    if (active)
+#pragma unroll
+        for (int n = 0; n < NB; ++n) {
+            if (lane + kWave * n >= K) continue;
+            for (int g = 0; g <= ey[n]; ++g) {
+                const int idx = mi_index(ex[n], g, ez[n]);
+                const double wt = w[ey[n]][g], sg = ((ey[n] - g) & 1) ? -wt : wt;
+#pragma unroll
+                for (int z = 0; z < 2; ++z) yo[n][z] += wt * B[2 * z][idx] + sg * B[2 * z + 1][idx];
+            }
         }
-    }
+    __syncthreads();
+    if (active)
+#pragma unroll
+        for (int n = 0; n < NB; ++n)
+            if (lane + kWave * n < K)
+#pragma unroll
+                for (int z = 0; z < 2; ++z) B[z][lane + kWave * n] = yo[n][z];
+    __syncthreads();
+    // z: vectors 0 + 1 -> the parent's moments; slot 2 keeps them for the folded row
+    if (active)
+#pragma unroll
+        for (int n = 0; n < NB; ++n) {
+            const int b = lane + kWave * n;
+            if (b >= K) continue;
+            double acc = 0.0;
+            for (int g = 0; g <= ez[n]; ++g) {
+                const int idx = mi_index(ex[n], ey[n], g);
+                const double wt = w[ez[n]][g], sg = ((ez[n] - g) & 1) ? -wt : wt;
+                acc += wt * B[0][idx] + sg * B[1][idx];
+            }
+            M[(int64_t)cell * K + b] = acc;
+            B[2][b] = acc;
+        }
     __syncthreads();
     if (active)  // the folded row
         for (int r = lane; r < R; r += kWave) {
             double v = 0.0;
-            for (int t = 0; t < kFold<Q>.n[r]; ++t) v = fma(kFold<Q>.c[r][t], B[0][kFold<Q>.src[r][t]], v);
+            for (int t = 0; t < kFold<Q>.n[r]; ++t) v = fma(kFold<Q>.c[r][t], B[2][kFold<Q>.src[r][t]], v);
             Mr[(int64_t)cell * R + r] = (TR)v;
         }
-}
-
-// out_cs[a] = sum_{b >= a_AX} tau_cs^(b-a)/(b-a)! in[.., b, ..] for the two children cs (tau = -1/4, +1/4)
-template <int Q, int AX>
-__device__ __forceinline__ void l2l_pass(const double *in, double *out0, double *out1, int lane)
-{
-    constexpr auto &mi = Tables<Q>::mi;
-    constexpr int K = MultiIndex<Q>::K;
-    for (int a = lane; a < K; a += kWave) {
-        const int e[3] = {mi.e[a][0], mi.e[a][1], mi.e[a][2]};
-        const int top = Q - mi.deg[a] + e[AX];
-        double lo = 0.0, hi = 0.0;
-        for (int b = e[AX]; b <= top; ++b) {
-            const double v = in[step_index<Q, AX>(e[0], e[1], e[2], b)] * kQuarter.v[b - e[AX]];
-            hi += v;
-            lo += ((b - e[AX]) & 1) ? -v : v;
-        }
-        out0[a] = lo;
-        out1[a] = hi;
-    }
 }
 
 template <int Q>
 __global__ __launch_bounds__(kWave *tree_waves<Q>()) void l2l_kernel(int n_par, const int32_t *__restrict__ parents,
                                                                       double *__restrict__ Lam)
 {
+    constexpr int K = MultiIndex<Q>::K, NB = (K + kWave - 1) / kWave;
     constexpr auto &mi = Tables<Q>::mi;
-    constexpr int K = MultiIndex<Q>::K;
-    __shared__ double buf[tree_waves<Q>()][15][K];
+    __shared__ double buf[tree_waves<Q>()][7][K];
+    __shared__ double w[Q + 1][Q + 1];
+    fill_shift_weights<Q>(w);
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int pi = blockIdx.x * tree_waves<Q>() + wave;
     const bool active = pi < n_par;
     double(*B)[K] = buf[wave];
+    int ex[NB], ey[NB], ez[NB], dg[NB];
+#pragma unroll
+    for (int n = 0; n < NB; ++n) {
+        const int a = lane + kWave * n;
+        ex[n] = a < K ? mi.e[a][0] : 0;
+        ey[n] = a < K ? mi.e[a][1] : 0;
+        ez[n] = a < K ? mi.e[a][2] : 0;
+        dg[n] = ex[n] + ey[n] + ez[n];
+    }
     int32_t child0 = 0;
     if (active) {
         child0 = parents[2 * pi + 1];
@@ -411,19 +427,66 @@ __global__ __launch_bounds__(kWave *tree_waves<Q>()) void l2l_kernel(int n_par, 
         for (int n = lane; n < K; n += kWave) B[0][n] = src[n];
     }
     __syncthreads();
-    if (active) l2l_pass<Q, 2>(B[0], B[1], B[2], lane);  // z: slots 1 + z
+    // out_lo[a] = sum_{b >= a_AX} (-1/4)^(b-a)/(b-a)! in[.., b, ..], out_hi the same with +1/4
+    if (active)  // z: slot 0 -> slots 1 + z
+#pragma unroll
+        for (int n = 0; n < NB; ++n) {
+            const int a = lane + kWave * n;
+            if (a >= K) continue;
+            double lo = 0.0, hi = 0.0;
+            for (int b = ez[n]; b <= Q - dg[n] + ez[n]; ++b) {
+                const double v = B[0][mi_index(ex[n], ey[n], b)] * w[b - ez[n]][0];
+                hi += v;
+                lo += ((b - ez[n]) & 1) ? -v : v;
+            }
+            B[1][a] = lo;
+            B[2][a] = hi;
+        }
     __syncthreads();
-    if (active)  // y: slot 1 + z -> slots 3 + y + 2z
-        for (int z = 0; z < 2; ++z) l2l_pass<Q, 1>(B[1 + z], B[3 + 2 * z], B[3 + 2 * z + 1], lane);
+    if (active)  // y: slots 1 + z -> slots 3 + y + 2z
+#pragma unroll
+        for (int n = 0; n < NB; ++n) {
+            const int a = lane + kWave * n;
+            if (a >= K) continue;
+            double lo[2] = {0.0, 0.0}, hi[2] = {0.0, 0.0};
+            for (int b = ey[n]; b <= Q - dg[n] + ey[n]; ++b) {
+                const int idx = mi_index(ex[n], b, ez[n]);
+                const double wt = w[b - ey[n]][0], sg = ((b - ey[n]) & 1) ? -wt : wt;
+#pragma unroll
+                for (int z = 0; z < 2; ++z) {
+                    hi[z] += wt * B[1 + z][idx];
+                    lo[z] += sg * B[1 + z][idx];
+                }
+            }
+#pragma unroll
+            for (int z = 0; z < 2; ++z) {
+                B[3 + 2 * z][a] = lo[z];
+                B[3 + 2 * z + 1][a] = hi[z];
+            }
+        }
     __syncthreads();
-    if (active)  // x: slot 3 + y + 2z -> slots 7 + x + 2y + 4z = 7 + child
-        for (int yz = 0; yz < 4; ++yz) l2l_pass<Q, 0>(B[3 + yz], B[7 + 2 * yz], B[7 + 2 * yz + 1], lane);
-    __syncthreads();
-    if (active) {
+    if (active) {  // x: slots 3 + y + 2z -> child x + 2y + 4z, added to the children's locals with 2^-|a|
         double *__restrict__ dst = Lam + (int64_t)child0 * K;  // 8 consecutive children
-        for (int n = lane; n < 8 * K; n += kWave) {
-            const int c = n / K, a = n % K;
-            dst[n] += B[7 + c][a] * ldexp(1.0, -mi.deg[a]);
+#pragma unroll
+        for (int n = 0; n < NB; ++n) {
+            const int a = lane + kWave * n;
+            if (a >= K) continue;
+            double lo[4] = {0.0, 0.0, 0.0, 0.0}, hi[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int b = ex[n]; b <= Q - dg[n] + ex[n]; ++b) {
+                const int idx = mi_index(b, ey[n], ez[n]);
+                const double wt = w[b - ex[n]][0], sg = ((b - ex[n]) & 1) ? -wt : wt;
+#pragma unroll
+                for (int yz = 0; yz < 4; ++yz) {
+                    hi[yz] += wt * B[3 + yz][idx];
+                    lo[yz] += sg * B[3 + yz][idx];
+                }
+            }
+            const double sc = ldexp(1.0, -dg[n]);
+#pragma unroll
+            for (int yz = 0; yz < 4; ++yz) {
+                dst[(int64_t)(2 * yz) * K + a] += lo[yz] * sc;
+                dst[(int64_t)(2 * yz + 1) * K + a] += hi[yz] * sc;
+            }
         }
     }
 }
@@ -798,23 +861,28 @@ __global__ void btv_p2m_kernel(int64_t n_leaves, const int32_t *__restrict__ lea
                                const double *__restrict__ gf, double *__restrict__ M, TR *__restrict__ Mr)
 {
     constexpr int K = MultiIndex<Q>::K, R = nreduced(Q);
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t leaf = idx / (K + R);
-    const int b = (int)(idx - leaf * (K + R));
+    const int64_t leaf = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;  // one wave per leaf
+    const int lane = threadIdx.x % kWave;
     if (leaf >= n_leaves) return;
     const double a = geom[leaf].w;
-    double m = 0.0;
-    for (int32_t f = leaf_faces[leaf]; f < leaf_faces[leaf + 1]; ++f) {
-        const int type = (int)(faces[f] >> 28);
-        if (b < K)
+    const int64_t c = leaf_cell[leaf];
+    const int32_t f0 = leaf_faces[leaf], f1 = leaf_faces[leaf + 1];
+    for (int b = lane; b < K; b += kWave) {
+        double m = 0.0;
+        for (int32_t f = f0; f < f1; ++f) {
+            const int type = (int)(faces[f] >> 28);
             m += a * (a * qf[f] * kFaceKappa<Q>.phi[type][b] - gf[f] * kFaceKappa<Q>.psi[type][b]);
-        else
-            m += a * (a * qf[f] * kFoldedFaceKappa<Q>.phi[type][b - K] - gf[f] * kFoldedFaceKappa<Q>.psi[type][b - K]);
+        }
+        M[c * K + b] = m;
     }
-    if (b < K)
-        M[(int64_t)leaf_cell[leaf] * K + b] = m;
-    else
-        Mr[(int64_t)leaf_cell[leaf] * R + (b - K)] = (TR)m;
+    for (int b = lane; b < R; b += kWave) {
+        double m = 0.0;
+        for (int32_t f = f0; f < f1; ++f) {
+            const int type = (int)(faces[f] >> 28);
+            m += a * (a * qf[f] * kFoldedFaceKappa<Q>.phi[type][b] - gf[f] * kFoldedFaceKappa<Q>.psi[type][b]);
+        }
+        Mr[c * R + b] = (TR)m;
+    }
 }
 
 __device__ __forceinline__ double pick3(const double v[3], int d) { return d == 0 ? v[0] : (d == 1 ? v[1] : v[2]); }
@@ -1229,8 +1297,7 @@ template <int Q>
 void launch_p2m(const bcv_plan_s &p, const double *f, hipStream_t st)
 {
     const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
-    const int64_t nthr = p.n_leaves * (MultiIndex<Q>::K + nreduced(Q));
-    const unsigned blocks = (unsigned)((nthr + 255) / 256);
+    const unsigned blocks = (unsigned)((p.n_leaves + 3) / 4);
     if (p.precision == BCV_MIXED_F32)
         p2m_kernel<Q, float><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, f, p.d_M, p.d_M32);
     else
@@ -1344,8 +1411,7 @@ void btv_q(const bcv_plan_s &p, const double *qf, const double *gf, double *u, h
     const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
     const bool far = !p.direct;
     if (far) {
-        const int64_t nthr = p.n_leaves * (K + nreduced(Q));
-        const unsigned blocks = (unsigned)((nthr + 255) / 256);
+        const unsigned blocks = (unsigned)((p.n_leaves + 3) / 4);
         if (p.precision == BCV_MIXED_F32)
             btv_p2m_kernel<Q, float><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, p.d_leaf_faces,
                                                              p.d_faces, qf, gf, p.d_M, p.d_M32);
