@@ -317,8 +317,9 @@ def batched(args):
         loc = lv[sel].copy()
         loc[:, 1] -= (4 * m) << loc[:, 0]
         f[sel] = synth.leaf_density(loc, seed=m)
-    tune, tune_ms = bcv.autotune(forest, n_applies=5, q=args.q, precision=bcv.MIXED_F32)
-    plan = bcv.plan_interactions(forest, q=args.q, precision=bcv.MIXED_F32, **tune)
+    nf = bcv.NEAR_ASSEMBLED if args.nearfield == "assembled" else bcv.NEAR_QUADRATURE
+    tune, tune_ms = bcv.autotune(forest, n_applies=5, q=args.q, precision=bcv.MIXED_F32, nearfield=nf)
+    plan = bcv.plan_interactions(forest, q=args.q, precision=bcv.MIXED_F32, nearfield=nf, **tune)
     setup_s = time.perf_counter() - t0
     n = plan.n_leaves
     fd = torch.tensor(f, device="cuda:0")
@@ -334,7 +335,8 @@ def batched(args):
     ms_graph = 1e3 * (time.perf_counter() - t0) / args.steps
     u_graph = ud.cpu().numpy()
     # the same meshes, one plan and one apply each
-    plans = [bcv.plan_interactions(bcv.build_bc_tree(L), q=args.q, precision=bcv.MIXED_F32) for L in Ls]
+    plans = [bcv.plan_interactions(bcv.build_bc_tree(L), q=args.q, precision=bcv.MIXED_F32, nearfield=nf)
+             for L in Ls]
     fs = [torch.tensor(f[mesh == m], device="cuda:0") for m in range(n_mesh)]
     us = [torch.empty_like(x) for x in fs]
     for p_, f_, u_ in zip(plans, fs, us):
@@ -366,7 +368,8 @@ def batched(args):
         "data": "synthetic",
         "config": {"workload": "batched VtV: 64 unit-cube BC meshes, h in {1/16,1/32,1/64} drawn by "
                                "default_rng(1234), Gaussian-mixture density seed m on mesh m, q=%d, mixed FP32 "
-                               "interaction phase, one forest plan, apply captured in one HIP graph" % args.q,
+                               "interaction phase, near field %s, one forest plan, apply captured in one HIP graph"
+                               % (args.q, args.nearfield),
                    "n_leaves": n, "meshes_by_h": {"1/%d" % (2 ** L): Ls.count(L) for L in (4, 5, 6)},
                    "autotuned": tune, "autotune_ms": tune_ms, "setup_seconds": setup_s},
         "separate_plans_ms_per_step": ms_seq,

@@ -58,13 +58,15 @@ def test_forest_equals_separate_meshes(precision):
     assert worst <= (1e-13 if precision == bcv.FP64 else 1e-6)
 
 
-def test_graph_replays_match_eager():
+@pytest.mark.parametrize("nearfield", [bcv.NEAR_QUADRATURE, bcv.NEAR_ASSEMBLED])
+def test_graph_replays_match_eager(nearfield):
     """Replays with other work and synchronisations between them; every replay equals the eager apply."""
     import torch
 
     forest = bcv.build_bc_forest(LS)
     lv, mesh, f = forest_density(forest, LS)
-    plan = bcv.plan_interactions(forest, q=6, precision=bcv.MIXED_F32)
+    announce("graph replays, nearfield mode %d" % nearfield)
+    plan = bcv.plan_interactions(forest, q=6, precision=bcv.MIXED_F32, nearfield=nearfield)
     fd = torch.tensor(f, device="cuda:0")
     ud = torch.full_like(fd, float("nan"))
     ref = torch.empty_like(fd)
