@@ -14,7 +14,14 @@ The far field of a leaf pair is therefore the order-q Taylor polynomial of G abo
 of the ancestors that meet in an interaction list, integrated with the same point rule as
 the near field; as q grows the result tends to O1 (oracle.direct).
 
-Expansion order q is fixed across levels (the paper's q_l schedule is not used here).
+Expansion order: fixed q by default. q_schedule=1 takes the paper's level-dependent orders
+q_l = q + (L - l) (Sec. 4, the FMM error discussion; q is the finest level's order). Reading of the
+passes with level-dependent orders, as Algorithm 1 prints them: a level-l cell carries moments and
+local coefficients of degree <= q_l; leaf moments are computed to q_l; M2M maps a child's moments
+(degree <= q_{l+1}) to the parent's degree <= q_l moments, so the parent's top-degree moments receive
+only the child's terms of lower degree; the interaction phase at level l truncates to
+|alpha| + |beta| <= q_l; L2L keeps the child's degrees <= q_{l+1}. q_levels gives the orders per
+level explicitly (a constant list is the fixed-q method).
 near_order=1 gives the near field the level-dependent Gauss rule of oracle.direct (n_l = 2 + L - l
 points per axis on a level-l leaf); the moments and the evaluation keep the 2x2x2 rule, so the
 result then tends to oracle.direct.apply_near_order as q grows.
@@ -32,10 +39,14 @@ _CHILD_POS = [(dx, dy, dz) for dz in (0, 1) for dy in (0, 1) for dx in (0, 1)]
 
 
 class FMM:
-    def __init__(self, mesh, q, near_order=0):
+    def __init__(self, mesh, q, near_order=0, q_schedule=0, q_levels=None):
         self.mesh = mesh
         self.q = q
         self.near_order = near_order
+        if q_levels is None:
+            q_levels = [q + (mesh.L - lev) if q_schedule else q for lev in range(mesh.L + 1)]
+        self.q_of = [int(v) for v in q_levels]
+        self.K_of = [n_coeffs(v) for v in self.q_of]
         self.K = n_coeffs(q)
         self.leaves = mesh.leaf_array()
         self.orders = None if near_order == 0 else direct.near_gauss_orders(self.leaves, mesh.L, near_order)
@@ -58,15 +69,15 @@ class FMM:
         return rows
 
     def _point_moments(self, lev, cells, chunk=8192):
-        """sum_g w_g (x_g - x_w)^b over the 2x2x2 points of level-lev cells: (n, K)."""
+        """sum_g w_g (x_g - x_w)^b over the 2x2x2 points of level-lev cells, |b| <= q_lev: (n, K_lev)."""
         a = self.mesh.side(lev)
         lo_all = np.asarray(cells, dtype=np.float64).reshape(-1, 3) * a
-        out = np.empty((len(lo_all), self.K))
+        out = np.empty((len(lo_all), self.K_of[lev]))
         for s in range(0, len(lo_all), chunk):
             lo = lo_all[s : s + chunk]
             pts, w = direct.gauss_points(lo, np.full(len(lo), a))
             centre = lo + 0.5 * a
-            mono = monomials(pts - centre[:, None, :], self.q)  # (n, 8, K)
+            mono = monomials(pts - centre[:, None, :], self.q_of[lev])  # (n, 8, K_lev)
             out[s : s + chunk] = mono.sum(axis=1) * w[:, None]
         return out
 
@@ -76,15 +87,21 @@ class FMM:
         return np.array([(p - 0.5) * a / 2.0 for p in pos])
 
     def _m2m(self, lev, pos):
+        """Parent (level lev, degree <= q_lev) from child (degree <= q_{lev+1}) moments."""
         key = ("m2m", lev, pos)
         if key not in self._cache:
-            self._cache[key] = m2m_matrix(self._child_offset(lev, pos), self.q)
+            qp, qc = self.q_of[lev], self.q_of[lev + 1]
+            M = m2m_matrix(self._child_offset(lev, pos), max(qp, qc))
+            self._cache[key] = M[: self.K_of[lev], : self.K_of[lev + 1]]
         return self._cache[key]
 
     def _l2l(self, lev, pos):
+        """Child (level lev + 1, degree <= q_{lev+1}) from parent (degree <= q_lev) locals."""
         key = ("l2l", lev, pos)
         if key not in self._cache:
-            self._cache[key] = l2l_matrix(self._child_offset(lev, pos), self.q)
+            qp, qc = self.q_of[lev], self.q_of[lev + 1]
+            Lm = l2l_matrix(self._child_offset(lev, pos), max(qp, qc))
+            self._cache[key] = Lm[: self.K_of[lev + 1], : self.K_of[lev]]
         return self._cache[key]
 
     def _m2l(self, lev, offsets):
@@ -92,7 +109,7 @@ class FMM:
         need = [o for o in set(offsets) if ("m2l", lev, o) not in self._cache]
         if need:
             a = self.mesh.side(lev)
-            Ts = m2l_matrix(np.array(need, dtype=np.float64) * a, self.q)
+            Ts = m2l_matrix(np.array(need, dtype=np.float64) * a, self.q_of[lev])
             for o, T in zip(need, Ts):
                 self._cache[("m2l", lev, o)] = T
         return [self._cache[("m2l", lev, o)] for o in offsets]
@@ -115,7 +132,7 @@ class FMM:
     def moments(self, f):
         """Moment calculation: m_w = sum_g w_g f_w (x_g - x_w)^b for every leaf, by level."""
         mesh = self.mesh
-        m = [np.zeros((len(mesh.levels[lev]), self.K)) for lev in range(mesh.L + 1)]
+        m = [np.zeros((len(mesh.levels[lev]), self.K_of[lev])) for lev in range(mesh.L + 1)]
         for lev, (pos, idx) in enumerate(self._rows):
             if len(pos):
                 cells = [mesh.levels[lev][p] for p in pos]
@@ -140,7 +157,7 @@ class FMM:
             par, kids = self._children_rows(lev)
             if len(par) == 0:
                 continue
-            acc = np.zeros((len(par), self.K))
+            acc = np.zeros((len(par), self.K_of[lev]))
             for pos in _CHILD_POS:
                 acc += m[lev + 1][kids[pos]] @ self._m2m(lev, pos).T
             m[lev][par] = acc
@@ -149,7 +166,7 @@ class FMM:
     def interaction(self, m):
         """Interaction phase: lambda_w = sum_{w' in I(w)} T(w, w') m_w' for every cell."""
         mesh = self.mesh
-        lam = [np.zeros((len(mesh.levels[lev]), self.K)) for lev in range(mesh.L + 1)]
+        lam = [np.zeros((len(mesh.levels[lev]), self.K_of[lev])) for lev in range(mesh.L + 1)]
         for lev in range(mesh.L + 1):
             groups = {}
             idx = mesh.index[lev]
@@ -201,7 +218,7 @@ class FMM:
             return memo[key]
         mesh = self.mesh
         srcs = mesh.interaction_list(lev, c)
-        lam = np.zeros(self.K)
+        lam = np.zeros(self.K_of[lev])
         if srcs:
             offs = [(c[0] - s[0], c[1] - s[1], c[2] - s[2]) for s in srcs]
             idx = mesh.index[lev]
@@ -228,6 +245,6 @@ class FMM:
         return u
 
 
-def apply(mesh, f, q, targets=None, near_order=0):
-    fm = FMM(mesh, q, near_order)
+def apply(mesh, f, q, targets=None, near_order=0, q_schedule=0):
+    fm = FMM(mesh, q, near_order, q_schedule)
     return fm.apply(f) if targets is None else fm.apply_sampled(f, targets)
