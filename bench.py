@@ -295,6 +295,50 @@ def measure_marking(bcv, torch, args, dev):
                       "leaf, %d stream(s)" % (1 << args.L, args.L, args.q, args.streams)}
 
 
+def measure_schedule(bcv, torch, tree, f, args, dev, u_ref):
+    """Level-dependent expansion orders q_l = 4 + L - l (Sec. 4) on the same mesh and density: FP64
+    and mixed plans, `args.steps` timed applies each; compared with the headline's FP64 apply at the
+    fixed order (rel-L2 of the cell averages)."""
+    q0 = 4
+    if q0 + args.L - 2 > 10:
+        return None
+    lv = tree.leaves().astype(np.int64)
+    nf = bcv.NEAR_ASSEMBLED if args.nearfield == "assembled" else bcv.NEAR_QUADRATURE
+    out = {}
+    for prec in ("fp64", "mixed"):
+        t0 = time.perf_counter()
+        plan = bcv.plan_interactions(tree, q=q0, q_schedule=1, device=dev, streams=args.streams, nearfield=nf,
+                                     precision=bcv.MIXED_F32 if prec == "mixed" else bcv.FP64)
+        plan_s = time.perf_counter() - t0
+        u = torch.empty(plan.n_leaves, dtype=torch.float64, device="cuda:%d" % dev)
+        for _ in range(args.warmup):
+            bcv.vtv_apply(plan, f, u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            bcv.vtv_apply(plan, f, u)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / args.steps
+        out[prec] = {"ms_per_apply": ms, "value": plan.n_leaves / (ms * 1e-3), "plan_seconds": plan_s,
+                     "u": u.cpu().numpy()}
+        info = plan.info
+        del plan
+    vol = np.ldexp(1.0, -3 * lv[:, 0].astype(np.int32))
+
+    def rel(a, b):
+        return float(np.sqrt(np.sum(vol * ((a - b) / vol) ** 2) / np.sum(vol * (b / vol) ** 2)))
+
+    a, b = out["mixed"].pop("u"), out["fp64"].pop("u")
+    res = {"metric": "VtV cell-potentials/s, level-dependent orders q_l = 4 + L - l, 1 GPU",
+           "unit": "cell-potentials/s", "orders": {"level %d" % l: q0 + args.L - l for l in range(args.L, 1, -1)},
+           "n_m2l_pairs": info["n_m2l"], "plan_device_bytes": info["device_bytes"], "fp64": out["fp64"],
+           "mixed": out["mixed"], "mixed_vs_fp64_rel_l2": rel(a, b)}
+    if u_ref is not None:
+        res["fp64_vs_fixed_order_fp64_rel_l2"] = rel(b, u_ref)
+        res["fixed_order"] = args.q
+    return res
+
+
 def batched(args):
     """64 unit-cube BC meshes, h drawn from {1/16, 1/32, 1/64} (default_rng(1234)), Gaussian-mixture
     density of seed m on mesh m, mixed precision (FP32 interaction phase): one forest plan with the
@@ -397,6 +441,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="mixed path without the touching-pair surrogate")
     ap.add_argument("--no-btv", action="store_true", help="skip the BtV (Algorithm 3) measurement")
+    ap.add_argument("--no-schedule", action="store_true",
+                    help="skip the level-dependent expansion order measurement")
     ap.add_argument("--no-marking", action="store_true",
                     help="skip the neighbour-marking / level-dependent near-field measurement")
     ap.add_argument("--batched", action="store_true",
@@ -534,6 +580,11 @@ def main():
                              "tol": SURROGATE_TOL, "training": sur_report}
     if not args.no_btv:
         line["btv"] = measure_btv(bcv, torch, tree, f, args, dev)
+    if not args.no_schedule:
+        sched = measure_schedule(bcv, torch, tree, f, args, dev, runs["fp64"]["u"] if "fp64" in runs else None)
+        if sched is not None:
+            line["level_orders"] = sched
+            print("level orders: %s" % json.dumps(sched), file=sys.stderr)
     if not args.no_marking:
         line["neighbour_marking"] = measure_marking(bcv, torch, args, dev)
         print("neighbour marking: %s" % json.dumps(line["neighbour_marking"]), file=sys.stderr)

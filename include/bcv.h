@@ -103,6 +103,14 @@ typedef struct {
     int m2l_max_slots;     /* longest slot list of one interaction task; longer lists are cut into
                               pieces whose partial sums are added in a fixed order (0 = 256;
                               else 16..65536) */
+    int q_schedule;        /* 0: the expansion order q on every level. 1: level-dependent orders
+                              q_l = q + L - l (Sec. 4, the FMM error with level-dependent orders;
+                              q is the finest level's): a level-l cell carries moments and local
+                              coefficients of degree <= q_l, M2M maps a child's degree <= q_{l+1}
+                              moments to the parent's degree <= q_l ones, the interaction phase at
+                              level l truncates at |alpha| + |beta| <= q_l, and L2L keeps the
+                              child's degrees <= q_{l+1}. Requires q + L - 2 <= 10 and a single-mesh
+                              tree, and is not combined with opts.boundary */
     int near_order;        /* Gauss rule of the non-touching near-field pairs (Sec. 4, near-field
                               quadrature: fixed order on the finest level, raised on coarser ones).
                               0: 2x2x2 points on each cell. 1: a level-l leaf takes n_l = 2 + L - l

@@ -34,7 +34,8 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("eta0", ctypes.c_double), ("q", ctypes.c_int), ("precision", ctypes.c_int),
                 ("direct", ctypes.c_int), ("nearfield", ctypes.c_int), ("streams", ctypes.c_int),
                 ("surrogate", ctypes.c_void_p), ("surrogate_tol", ctypes.c_double), ("near_unit", ctypes.c_int),
-                ("m2l_max_slots", ctypes.c_int), ("near_order", ctypes.c_int), ("boundary", ctypes.c_int)]
+                ("m2l_max_slots", ctypes.c_int), ("q_schedule", ctypes.c_int), ("near_order", ctypes.c_int),
+                ("boundary", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -218,17 +219,17 @@ class Plan:
 
 
 def _opts(q=6, eta0=0.5, direct=False, nearfield=NEAR_QUADRATURE, streams=2, precision=FP64, surrogate=None,
-          surrogate_tol=1e-7, near_unit=0, m2l_max_slots=0, boundary=False, near_order=0):
+          surrogate_tol=1e-7, near_unit=0, m2l_max_slots=0, boundary=False, near_order=0, q_schedule=0):
     return PlanOpts(eta0, q, precision, 1 if direct else 0, nearfield, streams,
                     surrogate.handle if surrogate is not None else None, surrogate_tol, near_unit, m2l_max_slots,
-                    near_order, 1 if boundary else 0)
+                    q_schedule, near_order, 1 if boundary else 0)
 
 
 def plan_interactions(tree, q=6, eta0=0.5, direct=False, nearfield=NEAR_QUADRATURE, device=0, streams=2,
                       precision=FP64, surrogate=None, surrogate_tol=1e-7, near_unit=0, m2l_max_slots=0,
-                      boundary=False, near_order=0):
+                      boundary=False, near_order=0, q_schedule=0):
     opts = _opts(q, eta0, direct, nearfield, streams, precision, surrogate, surrogate_tol, near_unit, m2l_max_slots,
-                 boundary, near_order)
+                 boundary, near_order, q_schedule)
     h = ctypes.c_void_p()
     _check(lib().bcv_plan_interactions(tree.handle, ctypes.byref(opts), device, ctypes.byref(h)))
     return Plan(h, device)

@@ -79,6 +79,9 @@ void check_plan_opts(const bcv_plan_opts &o, int device)
                 BCV_EINVAL, "m2l_max_slots must be 0 or 16..65536");
     BCV_REQUIRE(o.boundary == 0 || o.boundary == 1, BCV_EINVAL, "boundary must be 0 or 1");
     BCV_REQUIRE(o.near_order == 0 || o.near_order == 1, BCV_EINVAL, "near_order must be 0 or 1");
+    BCV_REQUIRE(o.q_schedule == 0 || o.q_schedule == 1, BCV_EINVAL, "q_schedule must be 0 or 1");
+    BCV_REQUIRE(o.q_schedule == 0 || o.boundary == 0, BCV_ENOTSUP,
+                "level-dependent orders are not combined with the boundary (BtV/VtB) structures");
     BCV_REQUIRE(o.near_order == 0 || o.nearfield == BCV_NEAR_ASSEMBLED, BCV_EINVAL,
                 "near_order 1 needs the assembled near field (BCV_NEAR_ASSEMBLED)");
     if (o.surrogate) {

@@ -52,6 +52,9 @@ struct M2LSplit {
 
 // Tasks are dealt to the 8 XCDs in contiguous ranges of about equal work.
 constexpr int kXcds = 8;
+// Deepest supported level, and the largest expansion order of any level (q_schedule).
+constexpr int kMaxLevel = 9;
+constexpr int kMaxSchedQ = 10;
 
 // One wave's share of the near field: entries [begin, end) of the near row of `target`. Rows
 // longer than a unit (the coarse leaves, whose extended neighbour lists reach thousands of fine
@@ -123,6 +126,12 @@ struct bcv_plan_s {
     int L = 0, q = 0, K = 0;
     int direct = 0, nearfield = 0, precision = 0;
     int near_order = 0;            // 1: level-dependent Gauss rule on the non-touching near pairs
+    // Expansion orders per level: q_level[l] = q (fixed) or q + L - l (q_schedule = 1). K is the row
+    // stride of the moment and local arrays, ncoef(max order); R = (max order + 1)^2 that of the
+    // folded rows.
+    int q_schedule = 0;
+    int q_level[bcv::kMaxLevel + 1] = {};
+    int R = 0;
     int64_t n_near_ordered = 0;    // near entries that took it
     int64_t n_leaves = 0, n_cells = 0, n_near = 0, n_touch = 0, n_m2l = 0, n_m2l_lanes = 0, n_offsets = 0,
             n_m2l_read_lanes = 0;
@@ -146,6 +155,9 @@ struct bcv_plan_s {
     int64_t n_units = 0, n_splits = 0;
     int64_t n_m2l_splits = 0, m2l_groups = 0;  // split tasks; workgroups of the interaction kernel
     int32_t xcd_begin[bcv::kXcds + 1] = {};     // task range of each XCD
+    // q_schedule: the tasks of level l are [level_xcd[l][0], level_xcd[l][kXcds]), cut into XCD
+    // ranges like xcd_begin, and launched level by level
+    int32_t level_xcd[bcv::kMaxLevel + 1][bcv::kXcds + 1] = {};
 
     // Device buffers (owned).
     double *d_leaf_geom = nullptr;  // 4 per leaf: lower corner x, y, z and side

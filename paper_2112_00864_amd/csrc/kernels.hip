@@ -28,6 +28,19 @@ constexpr double kNode0 = 0.21132486540518711775;  // 1/2 - 1/(2 sqrt 3): 2-poin
 constexpr double kNode1 = 0.78867513459481288225;  // 1/2 + 1/(2 sqrt 3)
 constexpr double kInv4Pi = 0.079577471545947667884;
 
+// Expansion sizes per level (level-dependent orders) and the row strides of the coefficient arrays.
+struct LevelOrders {
+    int32_t k[kMaxLevel + 1];  // ncoef(q_l)
+    int32_t r[kMaxLevel + 1];  // (q_l + 1)^2, folded rows
+    int32_t ldk, ldr;          // row strides of the moment / local arrays and of the folded rows
+};
+
+// Level of a cell from its side a = 2^-l (the exponent field of the double).
+__device__ __forceinline__ int level_of_side(double a)
+{
+    return 1023 - (int)((__double_as_longlong(a) >> 52) & 0x7FF);
+}
+
 // mu(e)/e! per axis, mu(e) = (1/2)(xi^e + (-xi)^e), xi = 1/(2 sqrt 3) so xi^2 = 1/12.
 constexpr double kappa_axis_ce(int e)
 {
@@ -100,7 +113,14 @@ __constant__ constexpr FaceKappaTable<Q> kFaceKappa{};
 // kappa table.
 template <int Q>
 struct FoldTable {  // Mr^b = sum_t c[b][t] M^{src[b][t]} (full positions)
-    static constexpr int R = nreduced(Q), kTerms = (Q / 4 + 1) * (Q / 4 + 1) + 2;
+    static constexpr int fold_terms()
+    {
+        int best = 1;
+        for (int bx = 0; bx <= Q; ++bx)
+            for (int by = 0; bx + by <= Q; ++by) best = std::max(best, (bx / 2 + 1) * (by / 2 + 1));
+        return best;
+    }
+    static constexpr int R = nreduced(Q), kTerms = fold_terms();
     int n[R], src[R][kTerms];
     double c[R][kTerms];
     constexpr FoldTable() : n{}, src{}, c{}
@@ -163,7 +183,7 @@ template <int Q>
 __constant__ constexpr FoldedFaceKappaTable<Q> kFoldedFaceKappa{};
 
 // (1/4)^k / k! for k = 0..kMaxOrder (translation coefficients; the sign (-1)^k is applied by the caller).
-constexpr int kMaxOrder = 8;
+constexpr int kMaxOrder = 12;
 struct QuarterTable {
     double v[kMaxOrder + 1];
     constexpr QuarterTable() : v{}
@@ -263,19 +283,22 @@ __device__ __forceinline__ double near_entry(uint32_t code, const double4 gt, co
 }
 
 // ---- P2M: M^b = f a^3 kappa_b on every leaf, and the folded row Mr = f a^3 fold(kappa) ------------
+// Q: the largest order of any level; a level-l leaf writes its ncoef(q_l) and (q_l + 1)^2 leading
+// coefficients (the tables are graded, so those are the order-q_l tables).
 template <int Q, class TR>
 __global__ void p2m_kernel(int64_t n_leaves, const int32_t *__restrict__ leaf_cell, const double4 *__restrict__ geom,
-                           const double *__restrict__ f, double *__restrict__ M, TR *__restrict__ Mr)
+                           const double *__restrict__ f, double *__restrict__ M, TR *__restrict__ Mr,
+                           const LevelOrders lo)
 {
-    constexpr int K = MultiIndex<Q>::K, R = nreduced(Q);
     const int64_t leaf = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;  // one wave per leaf
     const int lane = threadIdx.x % kWave;
     if (leaf >= n_leaves) return;
     const double a = geom[leaf].w;
+    const int lev = level_of_side(a);
     const double s = f[leaf] * (a * a * a);
     const int64_t c = leaf_cell[leaf];
-    for (int b = lane; b < K; b += kWave) M[c * K + b] = s * kKappa<Q>.v[b];
-    for (int b = lane; b < R; b += kWave) Mr[c * R + b] = (TR)(s * kFoldedKappa<Q>.v[b]);
+    for (int b = lane; b < lo.k[lev]; b += kWave) M[c * lo.ldk + b] = s * kKappa<Q>.v[b];
+    for (int b = lane; b < lo.r[lev]; b += kWave) Mr[c * lo.ldr + b] = (TR)(s * kFoldedKappa<Q>.v[b]);
 }
 
 // ---- M2M and L2L: one wave per marked cell, separable per-axis shifts through LDS -----------------
@@ -304,9 +327,11 @@ __device__ __forceinline__ void fill_shift_weights(double (*w)[Q + 1])
     }
 }
 
+// Children rows hold moments up to their own order (zero beyond): the parent's order Q covers them.
 template <int Q, class TR>
 __global__ __launch_bounds__(kWave *tree_waves<Q>()) void m2m_kernel(int n_par, const int32_t *__restrict__ parents,
-                                                                      double *__restrict__ M, TR *__restrict__ Mr)
+                                                                      double *__restrict__ M, TR *__restrict__ Mr,
+                                                                      int32_t ldk, int32_t ldr)
 {
     constexpr int K = MultiIndex<Q>::K, R = nreduced(Q), NB = (K + kWave - 1) / kWave;
     constexpr auto &mi = Tables<Q>::mi;
@@ -328,8 +353,8 @@ __global__ __launch_bounds__(kWave *tree_waves<Q>()) void m2m_kernel(int n_par, 
     int32_t cell = 0;
     if (active) {
         cell = parents[2 * pi];
-        const double *__restrict__ src = M + (int64_t)parents[2 * pi + 1] * K;  // 8 consecutive children
-        for (int n = lane; n < 8 * K; n += kWave) B[n / K][n % K] = src[n];
+        const double *__restrict__ src = M + (int64_t)parents[2 * pi + 1] * ldk;  // 8 consecutive children
+        for (int n = lane; n < 8 * K; n += kWave) B[n / K][n % K] = src[(int64_t)(n / K) * ldk + n % K];
     }
     __syncthreads();
     // x: children (0,y,z) + (1,y,z) -> 4 vectors indexed by y + 2z (lower child: -tau = +1/4)
@@ -386,7 +411,7 @@ __global__ __launch_bounds__(kWave *tree_waves<Q>()) void m2m_kernel(int n_par, 
                 const double wt = w[ez[n]][g], sg = ((ez[n] - g) & 1) ? -wt : wt;
                 acc += wt * B[0][idx] + sg * B[1][idx];
             }
-            M[(int64_t)cell * K + b] = acc;
+            M[(int64_t)cell * ldk + b] = acc;
             B[2][b] = acc;
         }
     __syncthreads();
@@ -394,13 +419,15 @@ __global__ __launch_bounds__(kWave *tree_waves<Q>()) void m2m_kernel(int n_par, 
         for (int r = lane; r < R; r += kWave) {
             double v = 0.0;
             for (int t = 0; t < kFold<Q>.n[r]; ++t) v = fma(kFold<Q>.c[r][t], B[2][kFold<Q>.src[r][t]], v);
-            Mr[(int64_t)cell * R + r] = (TR)v;
+            Mr[(int64_t)cell * ldr + r] = (TR)v;
         }
 }
 
+// Q: the parent's order; the children keep their first k_child coefficients (their own order).
 template <int Q>
 __global__ __launch_bounds__(kWave *tree_waves<Q>()) void l2l_kernel(int n_par, const int32_t *__restrict__ parents,
-                                                                      double *__restrict__ Lam)
+                                                                      double *__restrict__ Lam, int32_t ldk,
+                                                                      int32_t k_child)
 {
     constexpr int K = MultiIndex<Q>::K, NB = (K + kWave - 1) / kWave;
     constexpr auto &mi = Tables<Q>::mi;
@@ -423,7 +450,7 @@ __global__ __launch_bounds__(kWave *tree_waves<Q>()) void l2l_kernel(int n_par, 
     int32_t child0 = 0;
     if (active) {
         child0 = parents[2 * pi + 1];
-        const double *__restrict__ src = Lam + (int64_t)parents[2 * pi] * K;
+        const double *__restrict__ src = Lam + (int64_t)parents[2 * pi] * ldk;
         for (int n = lane; n < K; n += kWave) B[0][n] = src[n];
     }
     __syncthreads();
@@ -466,11 +493,11 @@ __global__ __launch_bounds__(kWave *tree_waves<Q>()) void l2l_kernel(int n_par, 
         }
     __syncthreads();
     if (active) {  // x: slots 3 + y + 2z -> child x + 2y + 4z, added to the children's locals with 2^-|a|
-        double *__restrict__ dst = Lam + (int64_t)child0 * K;  // 8 consecutive children
+        double *__restrict__ dst = Lam + (int64_t)child0 * ldk;  // 8 consecutive children
 #pragma unroll
         for (int n = 0; n < NB; ++n) {
             const int a = lane + kWave * n;
-            if (a >= K) continue;
+            if (a >= k_child) continue;
             double lo[4] = {0.0, 0.0, 0.0, 0.0}, hi[4] = {0.0, 0.0, 0.0, 0.0};
             for (int b = ex[n]; b <= Q - dg[n] + ex[n]; ++b) {
                 const int idx = mi_index(b, ey[n], ez[n]);
@@ -484,8 +511,8 @@ __global__ __launch_bounds__(kWave *tree_waves<Q>()) void l2l_kernel(int n_par, 
             const double sc = ldexp(1.0, -dg[n]);
 #pragma unroll
             for (int yz = 0; yz < 4; ++yz) {
-                dst[(int64_t)(2 * yz) * K + a] += lo[yz] * sc;
-                dst[(int64_t)(2 * yz + 1) * K + a] += hi[yz] * sc;
+                dst[(int64_t)(2 * yz) * ldk + a] += lo[yz] * sc;
+                dst[(int64_t)(2 * yz + 1) * ldk + a] += hi[yz] * sc;
             }
         }
     }
@@ -618,9 +645,9 @@ template <int Q, class T, int A0, int A1, int B0, int B1, int kWaves>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kWaves, kWaves))) void m2l_shift_kernel(
     XcdRanges ranges, const M2LTask *__restrict__ tasks, const int32_t *__restrict__ targets,
     const int32_t *__restrict__ slot_off, const uint32_t *__restrict__ slot_src, const T *__restrict__ G,
-    const T *__restrict__ Mr, double *__restrict__ partial, double *__restrict__ Lam)
+    const T *__restrict__ Mr, double *__restrict__ partial, double *__restrict__ Lam, int32_t ldr, int32_t ldk)
 {
-    constexpr int K = MultiIndex<Q>::K, R = nreduced(Q), NA = A1 - A0, NB = B1 - B0;
+    constexpr int NA = A1 - A0, NB = B1 - B0;
     constexpr auto &ri = RTables<Q>::ri;
     constexpr int D0 = ri.deg[A0], D1 = ri.deg[A1 - 1];
     static_assert(A0 == D0 * D0 && A1 == (D1 + 1) * (D1 + 1), "the a range must be a band of whole degrees");
@@ -649,7 +676,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kWaves, k
                 ow2 = slot_off[s0 + j + 2];
                 w2 = slot_src[(s0 + j + 2) * kWave + lane];
             }
-            const T *__restrict__ Ms = Mr + (int64_t)(w & 0x7FFFFFFFu) * R + B0;
+            const T *__restrict__ Ms = Mr + (int64_t)(w & 0x7FFFFFFFu) * ldr + B0;
             if (ow < 0 || j == 0) {  // gather the sources of all lanes
 #pragma unroll
                 for (int b = 0; b < NB; ++b) m[b] = Ms[b];
@@ -662,7 +689,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kWaves, k
                 }
             }
             if (w >> 31)
-                m2l_block_reg<Q, A0, A1, B0>(acc, G + (int64_t)(ow & 0x7FFFFFFF) * K, m,
+                m2l_block_reg<Q, A0, A1, B0>(acc, G + (int64_t)(ow & 0x7FFFFFFF) * ldk, m,
                                              std::make_integer_sequence<int, NB>{});
             ow = ow1, w = w1, ow1 = ow2, w1 = w2;
         }
@@ -675,31 +702,31 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kWaves, k
     if (t < 0) return;
     const double inv_a = ldexp(1.0, task.level);
     if (task.out < 0)
-        store_expanded<Q, A0, FA0, (B0 > 0)>(acc, inv_a, Lam + (int64_t)t * K + FA0, 1,
+        store_expanded<Q, A0, FA0, (B0 > 0)>(acc, inv_a, Lam + (int64_t)t * ldk + FA0, 1,
                                              std::make_integer_sequence<int, FA1 - FA0>{});
     else  // [piece][a][lane]: coalesced
-        store_expanded<Q, A0, FA0, (B0 > 0)>(acc, inv_a, partial + ((int64_t)task.out * K + FA0) * kWave + lane, kWave,
-                                             std::make_integer_sequence<int, FA1 - FA0>{});
+        store_expanded<Q, A0, FA0, (B0 > 0)>(acc, inv_a, partial + ((int64_t)task.out * ldk + FA0) * kWave + lane,
+                                             kWave, std::make_integer_sequence<int, FA1 - FA0>{});
 }
 
 // Split tasks: Lambda_t = sum of the pieces' partial local coefficients, in piece order. Block
-// (split, g) handles coefficients 4g .. 4g + 3 of the split's 64 targets, one thread per (a, lane).
-template <int Q>
+// (split, g) handles coefficients 4g .. 4g + 3 of the split's 64 targets, one thread per (a, lane);
+// a task of level l has ncoef(q_l) coefficients.
 __global__ __launch_bounds__(256) void m2l_combine_kernel(const M2LSplit *__restrict__ splits,
+                                                          const M2LTask *__restrict__ tasks,
                                                           const int32_t *__restrict__ targets,
                                                           const double *__restrict__ partial,
-                                                          double *__restrict__ Lam)
+                                                          double *__restrict__ Lam, const LevelOrders lo)
 {
-    constexpr int K = MultiIndex<Q>::K;
     const M2LSplit sp = splits[blockIdx.x];
     const int lane = threadIdx.x & (kWave - 1);
     const int a = 4 * (int)blockIdx.y + (int)(threadIdx.x / kWave);
     const int32_t t = targets[(int64_t)sp.task * kWave + lane];
-    if (t < 0 || a >= K) return;
-    const double *__restrict__ src = partial + ((int64_t)sp.first * K + a) * kWave + lane;
+    if (t < 0 || a >= lo.k[tasks[sp.task].level]) return;
+    const double *__restrict__ src = partial + ((int64_t)sp.first * lo.ldk + a) * kWave + lane;
     double s = 0.0;
-    for (int k = 0; k < sp.count; ++k) s += src[(int64_t)k * K * kWave];
-    Lam[(int64_t)t * K + a] = s;
+    for (int k = 0; k < sp.count; ++k) s += src[(int64_t)k * lo.ldk * kWave];
+    Lam[(int64_t)t * lo.ldk + a] = s;
 }
 
 // ---- near field + evaluation: one wave per work unit --------------------------------------------
@@ -708,12 +735,13 @@ __global__ __launch_bounds__(256) void m2l_combine_kernel(const M2LSplit *__rest
 // point-rule loop fetches the next pair's source while it evaluates the current one. A unit that
 // is its target's whole row writes u (adding the evaluation phase when Lam is given); the units
 // of a longer row write partial sums that near_combine_kernel adds up.
+// u_w += a^3 sum_a kappa_a Lambda^a over the leaf's n coefficients (its level's order; the kappa
+// table is graded, so its first n entries are those of that order).
 template <int Q>
-__device__ __forceinline__ double eval_far(const double *__restrict__ lam, double a, int lane)
+__device__ __forceinline__ double eval_far(const double *__restrict__ lam, double a, int lane, int n)
 {
-    constexpr int K = MultiIndex<Q>::K;
     double s = 0.0;
-    for (int k = lane; k < K; k += kWave) s = fma(kKappa<Q>.v[k], lam[k], s);
+    for (int k = lane; k < n; k += kWave) s = fma(kKappa<Q>.v[k], lam[k], s);
     return s * (a * a * a);
 }
 
@@ -728,7 +756,7 @@ __global__ __launch_bounds__(256) void near_eval_kernel(int64_t n_units, const N
                                                         const double *__restrict__ Lam,
                                                         const int32_t *__restrict__ leaf_cell, TouchValues tv,
                                                         int parts, double *__restrict__ partial,
-                                                        double *__restrict__ u)
+                                                        double *__restrict__ u, const LevelOrders lo)
 {
     constexpr int K = MultiIndex<Q>::K;
     const int lane = threadIdx.x & (kWave - 1);
@@ -796,7 +824,7 @@ __global__ __launch_bounds__(256) void near_eval_kernel(int64_t n_units, const N
         }
     }
     if (un.out < 0 && (parts & BCV_PART_FAR) && Lam != nullptr)
-        acc += eval_far<Q>(Lam + (int64_t)leaf_cell[t] * K, gt.w, lane);
+        acc += eval_far<Q>(Lam + (int64_t)leaf_cell[t] * lo.ldk, gt.w, lane, lo.k[level_of_side(gt.w)]);
     acc = wave_sum(acc);
     if (lane == 0) {
         if (un.out < 0)
@@ -813,15 +841,17 @@ __global__ __launch_bounds__(256) void near_combine_kernel(int64_t n_splits, con
                                                            const double4 *__restrict__ geom,
                                                            const double *__restrict__ Lam,
                                                            const int32_t *__restrict__ leaf_cell,
-                                                           double *__restrict__ u)
+                                                           double *__restrict__ u, const LevelOrders lo)
 {
-    constexpr int K = MultiIndex<Q>::K;
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
     if (w >= n_splits) return;  // uniform per wave
     const NearSplit sp = splits[w];
     double far = 0.0;
-    if (Lam != nullptr) far = wave_sum(eval_far<Q>(Lam + (int64_t)leaf_cell[sp.target] * K, geom[sp.target].w, lane));
+    if (Lam != nullptr) {
+        const double a = geom[sp.target].w;
+        far = wave_sum(eval_far<Q>(Lam + (int64_t)leaf_cell[sp.target] * lo.ldk, a, lane, lo.k[level_of_side(a)]));
+    }
     if (lane == 0) {
         double acc = 0.0;
         for (int k = 0; k < sp.count; ++k) acc += partial[sp.first + k];
@@ -834,20 +864,14 @@ template <int Q>
 __global__ __launch_bounds__(256) void eval_add_kernel(int64_t n_leaves, const double4 *__restrict__ geom,
                                                        const double *__restrict__ Lam,
                                                        const int32_t *__restrict__ leaf_cell,
-                                                       double *__restrict__ u)
+                                                       double *__restrict__ u, const LevelOrders lo)
 {
-    constexpr int K = MultiIndex<Q>::K;
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t t = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
     if (t >= n_leaves) return;
-    const double *__restrict__ lam = Lam + (int64_t)leaf_cell[t] * K;
-    double s = 0.0;
-    for (int a = lane; a < K; a += kWave) s = fma(kKappa<Q>.v[a], lam[a], s);
-    s = wave_sum(s);
-    if (lane == 0) {
-        const double a = geom[t].w;
-        u[t] = fma(s, a * a * a, u[t]);
-    }
+    const double a = geom[t].w;
+    const double s = wave_sum(eval_far<Q>(Lam + (int64_t)leaf_cell[t] * lo.ldk, a, lane, lo.k[level_of_side(a)]));
+    if (lane == 0) u[t] += s;
 }
 
 // ---- BtV (Algorithm 3): boundary moments and the near field of boundary faces --------------------
@@ -975,7 +999,7 @@ __global__ __launch_bounds__(256) void btv_near_kernel(int64_t n_units, const Ne
             acc += sv * q - dv * g;
         }
     }
-    if (un.out < 0 && Lam != nullptr) acc += eval_far<Q>(Lam + (int64_t)leaf_cell[t] * K, gt.w, lane);
+    if (un.out < 0 && Lam != nullptr) acc += eval_far<Q>(Lam + (int64_t)leaf_cell[t] * K, gt.w, lane, K);
     acc = wave_sum(acc);
     if (lane == 0) {
         if (un.out < 0)
@@ -1212,34 +1236,58 @@ struct PhaseMarks {
     }
 };
 
-template <int Q>
-void launch_near(const bcv_plan_s &p, const double *f, const double *lam, int parts, double *u, hipStream_t st)
+LevelOrders level_orders(const bcv_plan_s &p)
 {
+    LevelOrders lo{};
+    for (int l = 0; l <= kMaxLevel; ++l) {
+        lo.k[l] = ncoef(p.q_level[l]);
+        lo.r[l] = nreduced(p.q_level[l]);
+    }
+    lo.ldk = p.K;
+    lo.ldr = p.R;
+    return lo;
+}
+
+template <int Q>
+void launch_near_q(const bcv_plan_s &p, const double *f, const double *lam, int parts, double *u, hipStream_t st)
+{
+    const LevelOrders lo = level_orders(p);
     const unsigned blocks = (unsigned)((p.n_units + 3) / 4);
     const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
     const bool mixed = p.precision == BCV_MIXED_F32;
     if (p.nearfield == BCV_NEAR_ASSEMBLED && mixed)
         near_eval_kernel<Q, true, true><<<blocks, 256, 0, st>>>(p.n_units, p.d_units, p.d_split, p.d_col, nullptr,
                                                                 p.d_val32, geom, f, lam, p.d_leaf_cell,
-                                                                touch_values(p), parts, p.d_partial, u);
+                                                                touch_values(p), parts, p.d_partial, u, lo);
     else if (p.nearfield == BCV_NEAR_ASSEMBLED)
         near_eval_kernel<Q, true, false><<<blocks, 256, 0, st>>>(p.n_units, p.d_units, p.d_split, p.d_col, p.d_val,
                                                                  nullptr, geom, f, lam, p.d_leaf_cell,
-                                                                 touch_values(p), parts, p.d_partial, u);
+                                                                 touch_values(p), parts, p.d_partial, u, lo);
     else if (mixed)
         near_eval_kernel<Q, false, true><<<blocks, 256, 0, st>>>(p.n_units, p.d_units, p.d_split, p.d_col, nullptr,
                                                                  nullptr, geom, f, lam, p.d_leaf_cell,
-                                                                 touch_values(p), parts, p.d_partial, u);
+                                                                 touch_values(p), parts, p.d_partial, u, lo);
     else
         near_eval_kernel<Q, false, false><<<blocks, 256, 0, st>>>(p.n_units, p.d_units, p.d_split, p.d_col, nullptr,
                                                                   nullptr, geom, f, lam, p.d_leaf_cell,
-                                                                  touch_values(p), parts, p.d_partial, u);
+                                                                  touch_values(p), parts, p.d_partial, u, lo);
     check_launch();
     if (p.n_splits > 0) {
         near_combine_kernel<Q><<<(unsigned)((p.n_splits + 3) / 4), 256, 0, st>>>(
-            p.n_splits, p.d_splits, p.d_partial, geom, (parts & BCV_PART_FAR) ? lam : nullptr, p.d_leaf_cell, u);
+            p.n_splits, p.d_splits, p.d_partial, geom, (parts & BCV_PART_FAR) ? lam : nullptr, p.d_leaf_cell, u, lo);
         check_launch();
     }
+}
+
+// With level-dependent orders the evaluation reads each leaf's own number of coefficients from the
+// largest-order tables.
+template <int Q>
+void launch_near(const bcv_plan_s &p, const double *f, const double *lam, int parts, double *u, hipStream_t st)
+{
+    if (p.q_schedule)
+        launch_near_q<kMaxSchedQ>(p, f, lam, parts, u, st);
+    else
+        launch_near_q<Q>(p, f, lam, parts, u, st);
 }
 template <int Q, int A0, int A1, int B0, int B1, class T>
 void launch_m2l_block(const bcv_plan_s &p, const XcdRanges &ranges, const T *G, const T *Mr, hipStream_t st)
@@ -1247,7 +1295,7 @@ void launch_m2l_block(const bcv_plan_s &p, const XcdRanges &ranges, const T *G, 
     // four waves per SIMD (128 registers) where the block fits, else two
     constexpr int regs = (A1 - A0 + B1 - B0) * (int)(sizeof(T) / 4);
     m2l_shift_kernel<Q, T, A0, A1, B0, B1, (regs > 110 ? 2 : 4)><<<(unsigned)p.m2l_groups, kWave, 0, st>>>(
-        ranges, p.d_tasks, p.d_task_targets, p.d_slot_off, p.d_slot_src, G, Mr, p.d_m2l_partial, p.d_Lam);
+        ranges, p.d_tasks, p.d_task_targets, p.d_slot_off, p.d_slot_src, G, Mr, p.d_m2l_partial, p.d_Lam, p.R, p.K);
     check_launch();
 }
 
@@ -1292,16 +1340,112 @@ void launch_m2l(const bcv_plan_s &p, const float *G, const float *Mr, hipStream_
 // Upward pass (M2M, l = L-1 .. 2; moments below level 2 are never used), interaction phase (M2L
 // with the FP32 copy of the moments in the mixed path) and downward pass (L2L), shared by the VtV
 // and BtV applies.
+// ---- level-dependent orders: the per-level kernels are chosen at run time --------------------------
+template <class F>
+void with_order(int q, F &&f)
+{
+    switch (q) {
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 5: f(std::integral_constant<int, 5>{}); break;
+    case 6: f(std::integral_constant<int, 6>{}); break;
+    case 7: f(std::integral_constant<int, 7>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 9: f(std::integral_constant<int, 9>{}); break;
+    case 10: f(std::integral_constant<int, 10>{}); break;
+    default: fail(BCV_ENOTSUP, "expansion order not compiled");
+    }
+}
+
+// Interaction blocks for any order, generated: bands of source degrees from 0 upward, each with the
+// target degrees it reaches (0 .. Q - d0); a band grows while its registers fit the budget (W words
+// per value: 1 for float, 2 for double) and its target degrees are cut into bands where even one
+// source degree would not fit. Every block's target range is a band of whole degrees; the blocks of
+// the first source band write Lambda, the rest add.
+struct BlockSpec {
+    int a0, a1, b0, b1;
+};
+template <int Q, int W>
+struct BlockPlanTable {
+    static constexpr int kBudget = (W == 1 ? 100 : 200) - (Q >= 9 ? 12 * W : 0);  // fewer spare registers at high Q
+    BlockSpec b[32];
+    int n;
+    constexpr BlockPlanTable() : b{}, n(0)
+    {
+        int d0 = 0;
+        while (d0 <= Q) {
+            const int na = (Q - d0 + 1) * (Q - d0 + 1);
+            int d1 = d0;
+            while (d1 + 1 <= Q && (na + (d1 + 2) * (d1 + 2) - d0 * d0) * W <= kBudget) ++d1;
+            const int nb = (d1 + 1) * (d1 + 1) - d0 * d0;
+            if ((na + nb) * W <= kBudget) {
+                b[n++] = BlockSpec{0, na, d0 * d0, (d1 + 1) * (d1 + 1)};
+            } else {
+                int e0 = 0;
+                while (e0 <= Q - d0) {
+                    int e1 = e0;
+                    while (e1 + 1 <= Q - d0 && ((e1 + 2) * (e1 + 2) - e0 * e0 + nb) * W <= kBudget) ++e1;
+                    b[n++] = BlockSpec{e0 * e0, (e1 + 1) * (e1 + 1), d0 * d0, (d1 + 1) * (d1 + 1)};
+                    e0 = e1 + 1;
+                }
+            }
+            d0 = d1 + 1;
+        }
+    }
+};
+template <int Q, int W>
+constexpr BlockPlanTable<Q, W> kBlocks{};
+
+template <int Q, class T, int I>
+void launch_level_block(const bcv_plan_s &p, const XcdRanges &ranges, unsigned groups, const T *G, const T *Mr,
+                        hipStream_t st)
+{
+    constexpr int W = (int)(sizeof(T) / 4);
+    constexpr BlockSpec bs = kBlocks<Q, W>.b[I];
+    constexpr int regs = (bs.a1 - bs.a0 + bs.b1 - bs.b0) * W;
+    m2l_shift_kernel<Q, T, bs.a0, bs.a1, bs.b0, bs.b1, (regs > 110 ? 2 : 4)><<<groups, kWave, 0, st>>>(
+        ranges, p.d_tasks, p.d_task_targets, p.d_slot_off, p.d_slot_src, G, Mr, p.d_m2l_partial, p.d_Lam, p.R, p.K);
+    check_launch();
+}
+
+template <int Q, class T, int... I>
+void launch_level_blocks(const bcv_plan_s &p, const XcdRanges &ranges, unsigned groups, const T *G, const T *Mr,
+                         hipStream_t st, std::integer_sequence<int, I...>)
+{
+    (launch_level_block<Q, T, I>(p, ranges, groups, G, Mr, st), ...);
+}
+
+// The interaction tasks of one level at that level's order.
+template <int Q, class T>
+void launch_m2l_level(const bcv_plan_s &p, int lev, const T *G, const T *Mr, hipStream_t st)
+{
+    XcdRanges ranges;
+    int32_t longest = 0;
+    for (int x = 0; x <= kXcds; ++x) ranges.begin[x] = p.level_xcd[lev][x];
+    for (int x = 0; x < kXcds; ++x) longest = std::max(longest, ranges.begin[x + 1] - ranges.begin[x]);
+    if (longest == 0) return;
+    launch_level_blocks<Q, T>(p, ranges, (unsigned)(kXcds * longest), G, Mr, st,
+                              std::make_integer_sequence<int, kBlocks<Q, (int)(sizeof(T) / 4)>.n>{});
+}
+
 // P2M with the folded rows (FP32 in the mixed path).
 template <int Q>
 void launch_p2m(const bcv_plan_s &p, const double *f, hipStream_t st)
 {
     const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
     const unsigned blocks = (unsigned)((p.n_leaves + 3) / 4);
-    if (p.precision == BCV_MIXED_F32)
-        p2m_kernel<Q, float><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, f, p.d_M, p.d_M32);
-    else
-        p2m_kernel<Q, double><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, f, p.d_M, p.d_Mr);
+    const LevelOrders lo = level_orders(p);
+    constexpr int QT = Q > kMaxSchedQ ? Q : kMaxSchedQ;  // tables large enough for every level's order
+    if (p.precision == BCV_MIXED_F32) {
+        if (p.q_schedule)
+            p2m_kernel<QT, float><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, f, p.d_M, p.d_M32, lo);
+        else
+            p2m_kernel<Q, float><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, f, p.d_M, p.d_M32, lo);
+    } else {
+        if (p.q_schedule)
+            p2m_kernel<QT, double><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, f, p.d_M, p.d_Mr, lo);
+        else
+            p2m_kernel<Q, double><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, f, p.d_M, p.d_Mr, lo);
+    }
     check_launch();
 }
 
@@ -1311,30 +1455,47 @@ void upward_pass(const bcv_plan_s &p, hipStream_t st)
     for (int lev = p.L - 1; lev >= 2; --lev) {
         const int n_par = p.parent_begin[lev + 1] - p.parent_begin[lev];
         if (n_par == 0) continue;
-        const unsigned blocks = (unsigned)((n_par + tree_waves<Q>() - 1) / tree_waves<Q>());
-        if (p.precision == BCV_MIXED_F32)
-            m2m_kernel<Q, float><<<blocks, kWave * tree_waves<Q>(), 0, st>>>(
-                n_par, p.d_parents + 2 * p.parent_begin[lev], p.d_M, p.d_M32);
+        auto run = [&](auto qc) {
+            constexpr int QP = decltype(qc)::value;  // the parents' order
+            const unsigned blocks = (unsigned)((n_par + tree_waves<QP>() - 1) / tree_waves<QP>());
+            if (p.precision == BCV_MIXED_F32)
+                m2m_kernel<QP, float><<<blocks, kWave * tree_waves<QP>(), 0, st>>>(
+                    n_par, p.d_parents + 2 * p.parent_begin[lev], p.d_M, p.d_M32, p.K, p.R);
+            else
+                m2m_kernel<QP, double><<<blocks, kWave * tree_waves<QP>(), 0, st>>>(
+                    n_par, p.d_parents + 2 * p.parent_begin[lev], p.d_M, p.d_Mr, p.K, p.R);
+            check_launch();
+        };
+        if (p.q_schedule)
+            with_order(p.q_level[lev], run);
         else
-            m2m_kernel<Q, double><<<blocks, kWave * tree_waves<Q>(), 0, st>>>(
-                n_par, p.d_parents + 2 * p.parent_begin[lev], p.d_M, p.d_Mr);
-        check_launch();
+            run(std::integral_constant<int, Q>{});
     }
 }
 
 template <int Q>
 void interaction_phase(const bcv_plan_s &p, hipStream_t st)
 {
-    constexpr int K = MultiIndex<Q>::K;
     if (p.n_tasks == 0) return;
     // the folded moment rows were written with the moments (P2M, boundary P2M, M2M)
-    if (p.precision == BCV_MIXED_F32)
+    const bool mixed = p.precision == BCV_MIXED_F32;
+    if (p.q_schedule) {
+        for (int lev = p.L; lev >= 2; --lev)
+            with_order(p.q_level[lev], [&](auto qc) {
+                constexpr int QL = decltype(qc)::value;
+                if (mixed)
+                    launch_m2l_level<QL, float>(p, lev, p.d_G32, p.d_M32, st);
+                else
+                    launch_m2l_level<QL, double>(p, lev, p.d_G, p.d_Mr, st);
+            });
+    } else if (mixed) {
         launch_m2l<Q>(p, p.d_G32, p.d_M32, st);
-    else
+    } else {
         launch_m2l<Q>(p, p.d_G, p.d_Mr, st);
+    }
     if (p.n_m2l_splits > 0) {
-        m2l_combine_kernel<Q><<<dim3((unsigned)p.n_m2l_splits, (K + 3) / 4), 256, 0, st>>>(
-            p.d_m2l_splits, p.d_task_targets, p.d_m2l_partial, p.d_Lam);
+        m2l_combine_kernel<<<dim3((unsigned)p.n_m2l_splits, (unsigned)((p.K + 3) / 4)), 256, 0, st>>>(
+            p.d_m2l_splits, p.d_tasks, p.d_task_targets, p.d_m2l_partial, p.d_Lam, level_orders(p));
         check_launch();
     }
 }
@@ -1345,9 +1506,17 @@ void downward_pass(const bcv_plan_s &p, hipStream_t st)
     for (int lev = 2; lev < p.L; ++lev) {
         const int n_par = p.parent_begin[lev + 1] - p.parent_begin[lev];
         if (n_par == 0) continue;
-        l2l_kernel<Q><<<(unsigned)((n_par + tree_waves<Q>() - 1) / tree_waves<Q>()), kWave * tree_waves<Q>(), 0, st>>>(
-            n_par, p.d_parents + 2 * p.parent_begin[lev], p.d_Lam);
-        check_launch();
+        auto run = [&](auto qc) {
+            constexpr int QP = decltype(qc)::value;  // the parents' order
+            l2l_kernel<QP><<<(unsigned)((n_par + tree_waves<QP>() - 1) / tree_waves<QP>()), kWave * tree_waves<QP>(), 0,
+                             st>>>(n_par, p.d_parents + 2 * p.parent_begin[lev], p.d_Lam, p.K,
+                                   ncoef(p.q_level[lev + 1]));
+            check_launch();
+        };
+        if (p.q_schedule)
+            with_order(p.q_level[lev], run);
+        else
+            run(std::integral_constant<int, Q>{});
     }
 }
 
@@ -1388,8 +1557,12 @@ void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStre
     if (fork) {
         BCV_HIP(hipStreamWaitEvent(st, p.ev_join, 0));
         marks.start(BCV_PHASE_EVAL, st);
-        eval_add_kernel<Q><<<(unsigned)((p.n_leaves + 3) / 4), 256, 0, st>>>(p.n_leaves, geom, p.d_Lam,
-                                                                             p.d_leaf_cell, u);
+        const unsigned eblocks = (unsigned)((p.n_leaves + 3) / 4);
+        if (p.q_schedule)
+            eval_add_kernel<kMaxSchedQ><<<eblocks, 256, 0, st>>>(p.n_leaves, geom, p.d_Lam, p.d_leaf_cell, u,
+                                                                 level_orders(p));
+        else
+            eval_add_kernel<Q><<<eblocks, 256, 0, st>>>(p.n_leaves, geom, p.d_Lam, p.d_leaf_cell, u, level_orders(p));
         check_launch();
         marks.stop(BCV_PHASE_EVAL, st);
     } else {
@@ -1435,7 +1608,7 @@ void btv_q(const bcv_plan_s &p, const double *qf, const double *gf, double *u, h
     check_launch();
     if (p.n_btv_splits > 0) {
         near_combine_kernel<Q><<<(unsigned)((p.n_btv_splits + 3) / 4), 256, 0, st>>>(
-            p.n_btv_splits, p.d_btv_splits, p.d_btv_partial, geom, lam, p.d_leaf_cell, u);
+            p.n_btv_splits, p.d_btv_splits, p.d_btv_partial, geom, lam, p.d_leaf_cell, u, level_orders(p));
         check_launch();
     }
 }

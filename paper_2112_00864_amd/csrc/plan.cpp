@@ -268,6 +268,7 @@ struct M2LPlan {
     std::vector<M2LSplit> splits;
     int32_t n_pieces = 0;           // partial blocks of split tasks
     int32_t xcd_begin[kXcds + 1] = {};
+    int32_t level_xcd[kMaxLevel + 1][kXcds + 1] = {};  // per_level: the XCD ranges of each level's tasks
     int64_t n_pairs = 0;
     int64_t n_read_lanes = 0;       // lanes that read their source row in a lane-shifting kernel
 };
@@ -315,7 +316,10 @@ uint64_t hash_keys(const std::vector<int32_t> &keys)
 // the slots where it fails (and the first one) as gathering. Every slot records the source row of
 // every lane (the zero row where there is no cell) and, in bit 31, whether the offset is in that
 // lane's own list.
-M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, int32_t max_slots)
+// max_slots: the longest slot list of a task piece, per level. per_level: each level's tasks get XCD
+// ranges of their own (the levels are launched one by one, at their own expansion orders).
+M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, const std::vector<int32_t> &max_slots,
+                  bool per_level = false)
 {
     M2LPlan m;
     const int32_t zero_row = (int32_t)t.n_cells();
@@ -545,7 +549,8 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, int32_t max_s
     for (size_t q = 0; q < chunks.size(); ++q) {
         const int32_t base = (int32_t)chunk_base[q];
         const int32_t n = (int32_t)(chunk_base[q + 1] - chunk_base[q]);
-        const int32_t np = std::max<int32_t>(1, (n + max_slots - 1) / max_slots);
+        const int32_t ms = max_slots[chunks[q].lev];
+        const int32_t np = std::max<int32_t>(1, (n + ms - 1) / ms);
         if (np > 1) split_of_chunk[q] = M2LSplit{-1, m.n_pieces, np, 0};
         for (int32_t k = 0; k < np; ++k) {
             const int32_t b = base + (int32_t)((int64_t)n * k / np), e = base + (int32_t)((int64_t)n * (k + 1) / np);
@@ -558,23 +563,39 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, int32_t max_s
         m.n_pairs += outs[q].pairs;
     }
     // XCD ranges: contiguous runs of pieces (spatially ordered, so an XCD's L2 sees neighbouring
-    // sources) with about equal slot totals; inside a range the longest pieces go first.
-    int64_t total = 0;
-    for (const Piece &pc : pieces) total += pc.task.n_slots;
-    std::vector<size_t> cut(kXcds + 1, pieces.size());
-    cut[0] = 0;
-    {
+    // sources) with about equal slot totals; inside a range the longest pieces go first. per_level:
+    // each level's pieces (contiguous: the chunks go level by level) get ranges of their own.
+    auto deal = [&](size_t pb, size_t pe, int32_t *begin) {
+        int64_t total = 0;
+        for (size_t i = pb; i < pe; ++i) total += pieces[i].task.n_slots;
+        std::vector<size_t> cut(kXcds + 1, pe);
+        cut[0] = pb;
         int64_t acc = 0;
         int x = 1;
-        for (size_t i = 0; i < pieces.size() && x < kXcds; ++i) {
+        for (size_t i = pb; i < pe && x < kXcds; ++i) {
             acc += pieces[i].task.n_slots;
             while (x < kXcds && acc * kXcds >= total * x) cut[x++] = i + 1;
         }
+        for (int y = 0; y < kXcds; ++y)
+            std::stable_sort(pieces.begin() + cut[y], pieces.begin() + cut[y + 1],
+                             [](const Piece &a, const Piece &b) { return a.task.n_slots > b.task.n_slots; });
+        for (int y = 0; y <= kXcds; ++y) begin[y] = (int32_t)cut[y];
+    };
+    if (!per_level) {
+        deal(0, pieces.size(), m.xcd_begin);
+    } else {
+        BCV_REQUIRE(t.L <= kMaxLevel, BCV_ENOTSUP, "too many levels");
+        size_t pb = 0;
+        for (int lev = t.L; lev >= 0; --lev) {
+            size_t pe = pb;
+            while (pe < pieces.size() && pieces[pe].task.level == lev) ++pe;
+            deal(pb, pe, m.level_xcd[lev]);
+            pb = pe;
+        }
+        BCV_REQUIRE(pb == pieces.size(), BCV_ESTATE, "internal: interaction tasks not grouped by level");
+        m.xcd_begin[0] = 0;
+        for (int x = 1; x <= kXcds; ++x) m.xcd_begin[x] = (int32_t)pieces.size();
     }
-    for (int x = 0; x < kXcds; ++x)
-        std::stable_sort(pieces.begin() + cut[x], pieces.begin() + cut[x + 1],
-                         [](const Piece &a, const Piece &b) { return a.task.n_slots > b.task.n_slots; });
-    for (int x = 0; x <= kXcds; ++x) m.xcd_begin[x] = (int32_t)cut[x];
     for (const Piece &pc : pieces) {
         const int32_t ti = (int32_t)m.tasks.size();
         m.tasks.push_back(pc.task);
@@ -794,7 +815,7 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
     p->device = device;
     p->L = t.L;
     p->q = opts.q;
-    p->K = ncoef(opts.q);
+
     p->direct = opts.direct;
     p->nearfield = opts.nearfield;
     p->near_order = opts.near_order;
@@ -805,6 +826,19 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         BCV_HIP(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
         BCV_HIP(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
     }
+    // expansion orders per level and the row strides of the coefficient arrays
+    p->q_schedule = opts.q_schedule;
+    int q_max = opts.q;
+    for (int lev = 0; lev <= kMaxLevel; ++lev) {
+        p->q_level[lev] = opts.q_schedule ? opts.q + t.L - std::max(lev, 2) : opts.q;
+        if (lev <= t.L) q_max = std::max(q_max, p->q_level[lev]);
+    }
+    if (opts.q_schedule) {
+        BCV_REQUIRE(t.n_meshes == 1, BCV_ENOTSUP, "level-dependent orders: single-mesh trees only");
+        BCV_REQUIRE(q_max <= kMaxSchedQ, BCV_EINVAL, "level-dependent orders: q + L - 2 must not exceed 10");
+    }
+    p->K = ncoef(q_max);
+    p->R = (q_max + 1) * (q_max + 1);
     p->n_leaves = t.n_leaves();
     p->n_cells = t.n_cells();
     BCV_REQUIRE(p->n_leaves < (1 << 28), BCV_ENOTSUP, "more than 2^28 leaves");
@@ -892,7 +926,15 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         p->parent_begin[t.L + 1] = (int32_t)parents.size() / 2;
         p->d_parents = upload(p.get(), parents);
 
-        M2LPlan m2l = build_m2l(t, grids, opts.m2l_max_slots > 0 ? opts.m2l_max_slots : kDefaultMaxSlots);
+        // Longest slot list per task piece. With level-dependent orders a coarse level's slot costs
+        // (q_l / q)^4 times more and its few tasks would run as a handful of long waves: its pieces
+        // are halved per order above q (at least 8 slots), so more waves share the work.
+        const int32_t slots = opts.m2l_max_slots > 0 ? opts.m2l_max_slots : kDefaultMaxSlots;
+        std::vector<int32_t> level_slots(t.L + 1, slots);
+        if (opts.q_schedule)
+            for (int lev = 0; lev <= t.L; ++lev)
+                level_slots[lev] = std::max<int32_t>(8, slots >> std::min(16, p->q_level[lev] - opts.q));
+        M2LPlan m2l = build_m2l(t, grids, level_slots, opts.q_schedule != 0);
         std::vector<int32_t> id_of_key(15 * 15 * 15, -1);
         for (int32_t key : m2l.slot_key) id_of_key[key & 0x7FFFFFFF] = 0;
         std::vector<double> G;
@@ -903,7 +945,7 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
             const int o[3] = {key / 225 - 7, (key / 15) % 15 - 7, key % 15 - 7};
             const size_t at = G.size();
             G.resize(at + p->K);
-            derivative_table(p->q, o, &G[at]);
+            derivative_table(q_max, o, &G[at]);  // a level of order q_l reads the first ncoef(q_l) entries
         }
         for (int32_t &s : m2l.slot_key) s = id_of_key[s & 0x7FFFFFFF] | (s & (int32_t)0x80000000);
         p->n_offsets = n_off;
@@ -928,9 +970,11 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         for (int x = 0; x <= kXcds; ++x) p->xcd_begin[x] = m2l.xcd_begin[x];
         for (int x = 0; x < kXcds; ++x) longest = std::max(longest, m2l.xcd_begin[x + 1] - m2l.xcd_begin[x]);
         p->m2l_groups = (int64_t)kXcds * longest;
+        for (int lev = 0; lev <= kMaxLevel; ++lev)
+            for (int x = 0; x <= kXcds; ++x) p->level_xcd[lev][x] = m2l.level_xcd[lev][x];
         p->d_M = alloc_zero<double>(p.get(), (size_t)(p->n_cells + 1) * p->K);
         p->d_Lam = alloc_zero<double>(p.get(), (size_t)p->n_cells * p->K);
-        const size_t n_folded = (size_t)(p->n_cells + 1) * (size_t)((p->q + 1) * (p->q + 1));
+        const size_t n_folded = (size_t)(p->n_cells + 1) * (size_t)p->R;
         if (p->precision == BCV_MIXED_F32)
             p->d_M32 = alloc_zero<float>(p.get(), n_folded);
         else

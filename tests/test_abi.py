@@ -62,10 +62,16 @@ def test_tree_argument_errors():
 def test_plan_argument_errors_before_device_use():
     t = bcv.build_bc_tree(3)
     for kw in ({"q": 5}, {"eta0": 0.4}, {"near_order": 2}, {"near_order": 1},  # 1 needs the assembled mode
-               {"near_order": 1, "nearfield": bcv.NEAR_QUADRATURE}):
+               {"near_order": 1, "nearfield": bcv.NEAR_QUADRATURE}, {"q_schedule": 2}):
         with pytest.raises(bcv.BCVError) as e:
             bcv.plan_interactions(t, **kw)
         assert e.value.status == bcv.bcv.EINVAL
+
+
+def test_schedule_is_not_combined_with_the_boundary_structures():
+    with pytest.raises(bcv.BCVError) as e:
+        bcv.plan_interactions(bcv.build_bc_tree(3), q=4, q_schedule=1, boundary=True)
+    assert e.value.status == bcv.bcv.ENOTSUP
 
 
 def test_null_handles():
