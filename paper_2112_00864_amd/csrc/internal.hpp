@@ -162,6 +162,7 @@ struct bcv_plan_s {
     // Device buffers (owned).
     double *d_leaf_geom = nullptr;  // 4 per leaf: lower corner x, y, z and side
     int32_t *d_leaf_cell = nullptr;
+    int32_t *d_cell_leaf = nullptr;  // per cell: its leaf number, -1 for a marked cell (far-field plans)
     int64_t *d_split = nullptr;     // per near row: first point-rule entry (touching entries come first)
     uint32_t *d_col = nullptr;      // source leaf | (touch class + 1) << 28
     double *d_val = nullptr;        // assembled near entries (nearfield == ASSEMBLED, FP64 plans)

@@ -182,6 +182,38 @@ __constant__ constexpr FoldedKappaTable<Q> kFoldedKappa{};
 template <int Q>
 __constant__ constexpr FoldedFaceKappaTable<Q> kFoldedFaceKappa{};
 
+// Moments of a parent whose 8 children are leaves with densities f_c (side a each): the children's
+// moments f_c a^3 kappa translated by M2M (separable per axis) give
+//     M_P^b = a^3 sum_c f_c W[c][b],   W[c][b] = prod_i w1(c_i, b_i),
+//     w1(s, e) = sum_{g <= e} (+-1/4)^(e-g)/(e-g)! 2^-g kappa1(g)   (+ for the lower child, s = 0),
+// and the folded row likewise with Wr = fold(W).
+template <int Q>
+struct LeafParentTable {
+    double W[8][ncoef(Q)], Wr[8][nreduced(Q)];
+    constexpr LeafParentTable() : W{}, Wr{}
+    {
+        constexpr MultiIndex<Q> mi{};
+        constexpr FoldTable<Q> fo{};
+        double w1[2][Q + 1] = {};
+        for (int side = 0; side < 2; ++side)
+            for (int e = 0; e <= Q; ++e)
+                for (int g = 0; g <= e; ++g) {
+                    double t = kappa_axis_ce(g);
+                    for (int k = 1; k <= e - g; ++k) t *= (side ? -0.25 : 0.25) / k;
+                    for (int k = 0; k < g; ++k) t *= 0.5;
+                    w1[side][e] += t;
+                }
+        for (int c = 0; c < 8; ++c) {
+            for (int b = 0; b < ncoef(Q); ++b)
+                W[c][b] = w1[c & 1][mi.e[b][0]] * w1[(c >> 1) & 1][mi.e[b][1]] * w1[(c >> 2) & 1][mi.e[b][2]];
+            for (int r = 0; r < nreduced(Q); ++r)
+                for (int t = 0; t < fo.n[r]; ++t) Wr[c][r] += fo.c[r][t] * W[c][fo.src[r][t]];
+        }
+    }
+};
+template <int Q>
+__constant__ constexpr LeafParentTable<Q> kLeafParent{};
+
 // (1/4)^k / k! for k = 0..kMaxOrder (translation coefficients; the sign (-1)^k is applied by the caller).
 constexpr int kMaxOrder = 12;
 struct QuarterTable {
@@ -285,10 +317,12 @@ __device__ __forceinline__ double near_entry(uint32_t code, const double4 gt, co
 // ---- P2M: M^b = f a^3 kappa_b on every leaf, and the folded row Mr = f a^3 fold(kappa) ------------
 // Q: the largest order of any level; a level-l leaf writes its ncoef(q_l) and (q_l + 1)^2 leading
 // coefficients (the tables are graded, so those are the order-q_l tables).
+// Leaves of level skip_level write only their folded rows (their parents' moments come from
+// m2m_leaves_kernel); -1 = none.
 template <int Q, class TR>
 __global__ void p2m_kernel(int64_t n_leaves, const int32_t *__restrict__ leaf_cell, const double4 *__restrict__ geom,
                            const double *__restrict__ f, double *__restrict__ M, TR *__restrict__ Mr,
-                           const LevelOrders lo)
+                           const LevelOrders lo, int skip_level)
 {
     const int64_t leaf = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;  // one wave per leaf
     const int lane = threadIdx.x % kWave;
@@ -297,8 +331,46 @@ __global__ void p2m_kernel(int64_t n_leaves, const int32_t *__restrict__ leaf_ce
     const int lev = level_of_side(a);
     const double s = f[leaf] * (a * a * a);
     const int64_t c = leaf_cell[leaf];
-    for (int b = lane; b < lo.k[lev]; b += kWave) M[c * lo.ldk + b] = s * kKappa<Q>.v[b];
+    if (lev != skip_level)
+        for (int b = lane; b < lo.k[lev]; b += kWave) M[c * lo.ldk + b] = s * kKappa<Q>.v[b];
     for (int b = lane; b < lo.r[lev]; b += kWave) Mr[c * lo.ldr + b] = (TR)(s * kFoldedKappa<Q>.v[b]);
+}
+
+// M2M for parents whose 8 children are leaves, straight from the children's densities (one wave
+// per parent; see LeafParentTable).
+template <int Q, class TR>
+__global__ __launch_bounds__(256) void m2m_leaves_kernel(int n_par, const int32_t *__restrict__ parents,
+                                                         const int32_t *__restrict__ cell_leaf,
+                                                         const double4 *__restrict__ geom,
+                                                         const double *__restrict__ f, double *__restrict__ M,
+                                                         TR *__restrict__ Mr, int32_t ldk, int32_t ldr)
+{
+    constexpr int K = MultiIndex<Q>::K, R = nreduced(Q);
+    const int pi = (int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
+    const int lane = threadIdx.x % kWave;
+    if (pi >= n_par) return;
+    const int32_t cell = parents[2 * pi], child0 = parents[2 * pi + 1];
+    double fc[8];
+    double a = 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int32_t leaf = cell_leaf[child0 + c];
+        fc[c] = f[leaf];
+        a = geom[leaf].w;
+    }
+    const double a3 = a * a * a;
+    for (int b = lane; b < K; b += kWave) {
+        double v = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) v = fma(fc[c], kLeafParent<Q>.W[c][b], v);
+        M[(int64_t)cell * ldk + b] = v * a3;
+    }
+    for (int r = lane; r < R; r += kWave) {
+        double v = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) v = fma(fc[c], kLeafParent<Q>.Wr[c][r], v);
+        Mr[(int64_t)cell * ldr + r] = (TR)(v * a3);
+    }
 }
 
 // ---- M2M and L2L: one wave per marked cell, separable per-axis shifts through LDS -----------------
@@ -1428,33 +1500,54 @@ void launch_m2l_level(const bcv_plan_s &p, int lev, const T *G, const T *Mr, hip
 }
 
 // P2M with the folded rows (FP32 in the mixed path).
+// fused: the finest level's leaves write only their folded rows, and upward_pass computes their
+// parents' moments from f (fixed orders only).
 template <int Q>
-void launch_p2m(const bcv_plan_s &p, const double *f, hipStream_t st)
+void launch_p2m(const bcv_plan_s &p, const double *f, hipStream_t st, bool fused = false)
 {
+    const int skip = fused && !p.q_schedule ? p.L : -1;
     const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
     const unsigned blocks = (unsigned)((p.n_leaves + 3) / 4);
     const LevelOrders lo = level_orders(p);
     constexpr int QT = Q > kMaxSchedQ ? Q : kMaxSchedQ;  // tables large enough for every level's order
     if (p.precision == BCV_MIXED_F32) {
         if (p.q_schedule)
-            p2m_kernel<QT, float><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, f, p.d_M, p.d_M32, lo);
+            p2m_kernel<QT, float><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, f, p.d_M, p.d_M32, lo,
+                                                          skip);
         else
-            p2m_kernel<Q, float><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, f, p.d_M, p.d_M32, lo);
+            p2m_kernel<Q, float><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, f, p.d_M, p.d_M32, lo,
+                                                         skip);
     } else {
         if (p.q_schedule)
-            p2m_kernel<QT, double><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, f, p.d_M, p.d_Mr, lo);
+            p2m_kernel<QT, double><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, f, p.d_M, p.d_Mr, lo,
+                                                           skip);
         else
-            p2m_kernel<Q, double><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, f, p.d_M, p.d_Mr, lo);
+            p2m_kernel<Q, double><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, f, p.d_M, p.d_Mr, lo,
+                                                          skip);
     }
     check_launch();
 }
 
+// f_fused: the densities, when launch_p2m skipped the finest level's full moments (fixed orders).
 template <int Q>
-void upward_pass(const bcv_plan_s &p, hipStream_t st)
+void upward_pass(const bcv_plan_s &p, hipStream_t st, const double *f_fused = nullptr)
 {
     for (int lev = p.L - 1; lev >= 2; --lev) {
         const int n_par = p.parent_begin[lev + 1] - p.parent_begin[lev];
         if (n_par == 0) continue;
+        if (f_fused != nullptr && !p.q_schedule && lev == p.L - 1) {  // every child is a level-L leaf
+            const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
+            const unsigned blocks = (unsigned)((n_par + 3) / 4);
+            const int32_t *par = p.d_parents + 2 * p.parent_begin[lev];
+            if (p.precision == BCV_MIXED_F32)
+                m2m_leaves_kernel<Q, float><<<blocks, 256, 0, st>>>(n_par, par, p.d_cell_leaf, geom, f_fused, p.d_M,
+                                                                    p.d_M32, p.K, p.R);
+            else
+                m2m_leaves_kernel<Q, double><<<blocks, 256, 0, st>>>(n_par, par, p.d_cell_leaf, geom, f_fused, p.d_M,
+                                                                     p.d_Mr, p.K, p.R);
+            check_launch();
+            continue;
+        }
         auto run = [&](auto qc) {
             constexpr int QP = decltype(qc)::value;  // the parents' order
             const unsigned blocks = (unsigned)((n_par + tree_waves<QP>() - 1) / tree_waves<QP>());
@@ -1531,10 +1624,10 @@ void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStre
     PhaseMarks marks(p);
     if (far) {
         marks.start(BCV_PHASE_P2M, st);
-        launch_p2m<Q>(p, f, st);
+        launch_p2m<Q>(p, f, st, true);
         marks.stop(BCV_PHASE_P2M, st);
         marks.start(BCV_PHASE_M2M, st);
-        upward_pass<Q>(p, st);
+        upward_pass<Q>(p, st, f);
         marks.stop(BCV_PHASE_M2M, st);
         if (fork) {
             // Near field on the side stream, concurrently with the interaction phase. It is forked
@@ -1623,8 +1716,8 @@ void vtb_q(const bcv_plan_s &p, const double *f, double *uf, hipStream_t st)
     const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
     const bool far = !p.direct;
     if (far) {
-        launch_p2m<Q>(p, f, st);
-        upward_pass<Q>(p, st);
+        launch_p2m<Q>(p, f, st, true);
+        upward_pass<Q>(p, st, f);
         interaction_phase<Q>(p, st);
         downward_pass<Q>(p, st);
     }

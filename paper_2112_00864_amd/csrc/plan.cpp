@@ -925,6 +925,7 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         }
         p->parent_begin[t.L + 1] = (int32_t)parents.size() / 2;
         p->d_parents = upload(p.get(), parents);
+        p->d_cell_leaf = upload(p.get(), t.leaf_of_cell);
 
         // Longest slot list per task piece. With level-dependent orders a coarse level's slot costs
         // (q_l / q)^4 times more and its few tasks would run as a handful of long waves: its pieces
@@ -1039,7 +1040,7 @@ void destroy_plan(bcv_plan_s *p)
     if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
     if (p->ev_join) (void)hipEventDestroy(p->ev_join);
     if (p->side) (void)hipStreamDestroy(p->side);
-    void *bufs[] = {p->d_leaf_geom, p->d_leaf_cell, p->d_split, p->d_col, p->d_val, p->d_val32, p->d_units,
+    void *bufs[] = {p->d_leaf_geom, p->d_leaf_cell, p->d_cell_leaf, p->d_split, p->d_col, p->d_val, p->d_val32, p->d_units,
                     p->d_splits, p->d_partial, p->d_M, p->d_Lam, p->d_G,
                     p->d_M32, p->d_Mr, p->d_G32,
                     p->d_parents, p->d_tasks, p->d_task_targets, p->d_slot_off, p->d_slot_src,
