@@ -496,10 +496,15 @@ __global__ __launch_bounds__(kWave *tree_waves<Q>()) void m2m_kernel(int n_par, 
 }
 
 // Q: the parent's order; the children keep their first k_child coefficients (their own order).
-template <int Q>
+// kEval (parents whose children are leaves): instead of storing the children's locals, evaluate them
+// at once, u_c += a^3 sum_a kappa_a (Lambda_c^a + the parent's contribution).
+template <int Q, bool kEval = false>
 __global__ __launch_bounds__(kWave *tree_waves<Q>()) void l2l_kernel(int n_par, const int32_t *__restrict__ parents,
                                                                       double *__restrict__ Lam, int32_t ldk,
-                                                                      int32_t k_child)
+                                                                      int32_t k_child,
+                                                                      const int32_t *__restrict__ cell_leaf = nullptr,
+                                                                      const double4 *__restrict__ geom = nullptr,
+                                                                      double *__restrict__ u = nullptr)
 {
     constexpr int K = MultiIndex<Q>::K, NB = (K + kWave - 1) / kWave;
     constexpr auto &mi = Tables<Q>::mi;
@@ -566,6 +571,7 @@ __global__ __launch_bounds__(kWave *tree_waves<Q>()) void l2l_kernel(int n_par, 
     __syncthreads();
     if (active) {  // x: slots 3 + y + 2z -> child x + 2y + 4z, added to the children's locals with 2^-|a|
         double *__restrict__ dst = Lam + (int64_t)child0 * ldk;  // 8 consecutive children
+        double ev[8] = {};  // kEval: each child's partial evaluation sum over this lane's coefficients
 #pragma unroll
         for (int n = 0; n < NB; ++n) {
             const int a = lane + kWave * n;
@@ -581,10 +587,30 @@ __global__ __launch_bounds__(kWave *tree_waves<Q>()) void l2l_kernel(int n_par, 
                 }
             }
             const double sc = ldexp(1.0, -dg[n]);
+            if constexpr (kEval) {
+                const double kap = kKappa<Q>.v[a];
 #pragma unroll
-            for (int yz = 0; yz < 4; ++yz) {
-                dst[(int64_t)(2 * yz) * ldk + a] += lo[yz] * sc;
-                dst[(int64_t)(2 * yz + 1) * ldk + a] += hi[yz] * sc;
+                for (int yz = 0; yz < 4; ++yz) {
+                    ev[2 * yz] = fma(kap, dst[(int64_t)(2 * yz) * ldk + a] + lo[yz] * sc, ev[2 * yz]);
+                    ev[2 * yz + 1] = fma(kap, dst[(int64_t)(2 * yz + 1) * ldk + a] + hi[yz] * sc, ev[2 * yz + 1]);
+                }
+            } else {
+#pragma unroll
+                for (int yz = 0; yz < 4; ++yz) {
+                    dst[(int64_t)(2 * yz) * ldk + a] += lo[yz] * sc;
+                    dst[(int64_t)(2 * yz + 1) * ldk + a] += hi[yz] * sc;
+                }
+            }
+        }
+        if constexpr (kEval) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const double v = wave_sum(ev[c]);
+                if (lane == 0) {
+                    const int32_t leaf = cell_leaf[child0 + c];
+                    const double a = geom[leaf].w;
+                    u[leaf] = fma(v, a * a * a, u[leaf]);
+                }
             }
         }
     }
@@ -936,12 +962,14 @@ template <int Q>
 __global__ __launch_bounds__(256) void eval_add_kernel(int64_t n_leaves, const double4 *__restrict__ geom,
                                                        const double *__restrict__ Lam,
                                                        const int32_t *__restrict__ leaf_cell,
-                                                       double *__restrict__ u, const LevelOrders lo)
+                                                       double *__restrict__ u, const LevelOrders lo,
+                                                       int skip_level)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t t = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
     if (t >= n_leaves) return;
     const double a = geom[t].w;
+    if (level_of_side(a) == skip_level) return;  // evaluated by the fused last L2L
     const double s = wave_sum(eval_far<Q>(Lam + (int64_t)leaf_cell[t] * lo.ldk, a, lane, lo.k[level_of_side(a)]));
     if (lane == 0) u[t] += s;
 }
@@ -1593,10 +1621,11 @@ void interaction_phase(const bcv_plan_s &p, hipStream_t st)
     }
 }
 
+// skip_last: the last level's L2L is left to l2l_eval (fused with the evaluation of the finest leaves).
 template <int Q>
-void downward_pass(const bcv_plan_s &p, hipStream_t st)
+void downward_pass(const bcv_plan_s &p, hipStream_t st, bool skip_last = false)
 {
-    for (int lev = 2; lev < p.L; ++lev) {
+    for (int lev = 2; lev < (skip_last ? p.L - 1 : p.L); ++lev) {
         const int n_par = p.parent_begin[lev + 1] - p.parent_begin[lev];
         if (n_par == 0) continue;
         auto run = [&](auto qc) {
@@ -1621,6 +1650,8 @@ void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStre
     const bool far = (parts & BCV_PART_FAR) && !p.direct;
     const bool near = (parts & BCV_PART_NEAR) != 0;
     const bool fork = far && near && p.streams == 2;
+    // fixed orders, and parents on level L - 1 (whose children are all leaves of level L)
+    const bool fuse_last = fork && !p.q_schedule && p.L - 1 >= 2 && p.parent_begin[p.L] > p.parent_begin[p.L - 1];
     PhaseMarks marks(p);
     if (far) {
         marks.start(BCV_PHASE_P2M, st);
@@ -1644,18 +1675,27 @@ void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStre
         interaction_phase<Q>(p, st);
         marks.stop(BCV_PHASE_M2L, st);
         marks.start(BCV_PHASE_L2L, st);
-        downward_pass<Q>(p, st);
+        downward_pass<Q>(p, st, fork && fuse_last);
         marks.stop(BCV_PHASE_L2L, st);
     }
     if (fork) {
         BCV_HIP(hipStreamWaitEvent(st, p.ev_join, 0));
         marks.start(BCV_PHASE_EVAL, st);
+        if (fuse_last) {  // the last level's L2L fused with the evaluation of its leaf children
+            const int lev = p.L - 1;
+            const int n_par = p.parent_begin[lev + 1] - p.parent_begin[lev];
+            l2l_kernel<Q, true><<<(unsigned)((n_par + tree_waves<Q>() - 1) / tree_waves<Q>()), kWave * tree_waves<Q>(), 0,
+                                  st>>>(n_par, p.d_parents + 2 * p.parent_begin[lev], p.d_Lam, p.K, p.K, p.d_cell_leaf,
+                                        geom, u);
+            check_launch();
+        }
         const unsigned eblocks = (unsigned)((p.n_leaves + 3) / 4);
         if (p.q_schedule)
             eval_add_kernel<kMaxSchedQ><<<eblocks, 256, 0, st>>>(p.n_leaves, geom, p.d_Lam, p.d_leaf_cell, u,
-                                                                 level_orders(p));
+                                                                 level_orders(p), -1);
         else
-            eval_add_kernel<Q><<<eblocks, 256, 0, st>>>(p.n_leaves, geom, p.d_Lam, p.d_leaf_cell, u, level_orders(p));
+            eval_add_kernel<Q><<<eblocks, 256, 0, st>>>(p.n_leaves, geom, p.d_Lam, p.d_leaf_cell, u, level_orders(p),
+                                                        fuse_last ? p.L : -1);
         check_launch();
         marks.stop(BCV_PHASE_EVAL, st);
     } else {
