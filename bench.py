@@ -179,7 +179,7 @@ def roofline(info, phase_avg, args, prec):
     # the interaction phase: the interaction launches (reading the folded moment rows that P2M and
     # M2M write) and the sum of the split tasks' pieces
     m2l_names = (m2l_kernel_names(args.q, mixed)
-                 + ["m2l_combine_kernel<%d>" % args.q])
+                 + ["m2l_combine_kernel"])
     for roof_, names in ((m2l_roof, m2l_names), (near_roof, [near_name])):
         roof_["frac"] = roof_["achieved"] / roof_["peak"]
         # HBM bytes per apply (PMC, summed over the launches), None if stale
