@@ -1411,14 +1411,11 @@ void launch_m2l(const bcv_plan_s &p, const double *G, const double *Mr, hipStrea
     if constexpr (Q == 4) {
         launch_m2l_block<Q, 0, R, 0, R>(p, ranges, G, Mr, st);     // everything: 50 doubles
     } else if constexpr (Q == 6) {
-        launch_m2l_block<Q, 0, R, 0, 4>(p, ranges, G, Mr, st);     // all a, |b| <= 1
-        launch_m2l_block<Q, 0, 25, 4, 16>(p, ranges, G, Mr, st);   // |a| <= 4, 2 <= |b| <= 3
-        launch_m2l_block<Q, 0, 9, 16, R>(p, ranges, G, Mr, st);    // |a| <= 2, |b| >= 4
+        launch_m2l_block<Q, 0, R, 0, R>(p, ranges, G, Mr, st);     // everything: 98 doubles (two waves)
     } else {
         static_assert(Q == 8, "orders 4, 6, 8");
-        launch_m2l_block<Q, 0, R, 0, 4>(p, ranges, G, Mr, st);     // all a, |b| <= 1 (two waves)
-        launch_m2l_block<Q, 0, 49, 4, 25>(p, ranges, G, Mr, st);   // |a| <= 6, 2 <= |b| <= 4 (two waves)
-        launch_m2l_block<Q, 0, 16, 25, R>(p, ranges, G, Mr, st);   // |a| <= 3, |b| >= 5 (two waves)
+        launch_m2l_block<Q, 0, R, 0, 36>(p, ranges, G, Mr, st);    // all a, |b| <= 5 (two waves)
+        launch_m2l_block<Q, 0, 9, 36, R>(p, ranges, G, Mr, st);    // |a| <= 2, |b| >= 6
     }
 }
 
@@ -1466,7 +1463,10 @@ struct BlockSpec {
 };
 template <int Q, int W>
 struct BlockPlanTable {
-    static constexpr int kBudget = (W == 1 ? 100 : 200) - (Q >= 9 ? 12 * W : 0);  // fewer spare registers at high Q
+    // FP64 blocks may take nearly all 256 registers (two waves): fewer launches re-read fewer rows,
+    // which measured faster than three four-wave blocks at orders 6 and 8; fewer spare registers at
+    // high Q
+    static constexpr int kBudget = W == 1 ? (Q >= 9 ? 88 : 100) : (Q >= 9 ? 176 : 234);
     BlockSpec b[32];
     int n;
     constexpr BlockPlanTable() : b{}, n(0)
