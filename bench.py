@@ -56,9 +56,9 @@ def m2l_kernel_names(q, mixed):
     elif q == 4:
         blocks = [(0, R, 0, R)]
     elif q == 6:
-        blocks = [(0, R, 0, 4), (0, 25, 4, 16), (0, 9, 16, R)]
+        blocks = [(0, R, 0, R)]
     else:
-        blocks = [(0, R, 0, 4), (0, 49, 4, 25), (0, 16, 25, R)]
+        blocks = [(0, R, 0, 36), (0, 9, 36, R)]
 
     def waves(b):  # as launch_m2l_block: two waves per SIMD where the block's registers exceed 110
         return 2 if (b[1] - b[0] + b[3] - b[2]) * (1 if mixed else 2) > 110 else 4

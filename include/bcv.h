@@ -101,8 +101,8 @@ typedef struct {
     int near_unit;         /* work-unit size of the near field: rows longer than this many entries are
                               cut into pieces of about equal length (0 = 512; else 64..65536) */
     int m2l_max_slots;     /* longest slot list of one interaction task; longer lists are cut into
-                              pieces whose partial sums are added in a fixed order (0 = 256;
-                              else 16..65536) */
+                              pieces whose partial sums are added in a fixed order (0 = 320, or 256 with
+                              q_schedule = 1; else 16..65536) */
     int q_schedule;        /* 0: the expansion order q on every level. 1: level-dependent orders
                               q_l = q + L - l (Sec. 4, the FMM error with level-dependent orders;
                               q is the finest level's): a level-l cell carries moments and local
@@ -230,7 +230,7 @@ bcv_status bcv_graph_launch(bcv_graph graph, void *hip_stream);
 void bcv_graph_destroy(bcv_graph graph);
 
 /* Autotuner of the plan's work decomposition: for the tree and base options, builds plans with
- * candidate near_unit (256, 512, 1024, 2048) and then m2l_max_slots (128, 256, 512, 1024) values,
+ * candidate near_unit (256, 512, 1024, 2048) and then m2l_max_slots (128, 256, 320, 512, 1024) values,
  * times n_applies applies of each (HIP events, after two warm-up applies, density 1) on `device`,
  * and returns the options of the fastest plan in *best and its milliseconds per apply in *best_ms
  * (host). Allocates and frees plans and buffers. Errors: as bcv_plan_interactions. */

@@ -114,7 +114,7 @@ double autotune(const bcv_tree_s &t, const bcv_plan_opts &base, int device, int 
             const double ms = time_plan(t, o, device, n_applies, f, u, st);
             if (ms < best_ms) best_ms = ms, best = o;
         }
-        for (int slots : {128, 256, 512, 1024}) {
+        for (int slots : {128, 256, 320, 512, 1024}) {
             bcv_plan_opts o = best;
             o.m2l_max_slots = slots;
             const double ms = time_plan(t, o, device, n_applies, f, u, st);
