@@ -462,8 +462,8 @@ def main():
         print(json.dumps({"copy_bytes_per_dispatch": n * 8}))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the box has one MI355X and this build runs no multi-GPU path",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (a batch of meshes would "
+              "shard by mesh, one large mesh by Morton range of leaves)", file=sys.stderr)
         sys.exit(2)
 
     if args.batched:

@@ -46,7 +46,7 @@ typedef enum {
     BCV_EINVAL = 1,  /* an argument is out of range or a required pointer is NULL */
     BCV_ENOMEM = 2,  /* host or device allocation failed */
     BCV_EDEVICE = 3, /* a HIP call failed; bcv_last_error() carries the HIP message */
-    BCV_ENOTSUP = 4, /* valid request that this build does not implement */
+    BCV_ENOTSUP = 4, /* valid request that the library does not implement */
     BCV_ESTATE = 5   /* a handle is not a live object of the expected kind */
 } bcv_status;
 
@@ -301,7 +301,7 @@ bcv_status bcv_touching_integrals(int device, double *out);
  * A small network (features -> width -> width -> 2, SiLU, FP32, trained on the GPU by the library's
  * own forward, backward and Adam kernels) that corrects a low-order quadrature of the Galerkin
  * integral of 1/|x-y| over two touching cubes to the accuracy of the high-order quadrature, which
- * stays the fallback and the judge (Sec. 3: singular near-field entries by singularity-removing
+ * stays the fallback and the reference of its error estimate (Sec. 3: singular near-field entries by singularity-removing
  * transforms and tensor Gauss rules).
  *
  * Canonical touching pair: A = [0,1]^3 is the smaller cube; B is a cube of side rho in [1, 2]

@@ -1,6 +1,6 @@
 // High-order quadrature of the Galerkin integral of 1/|x - y| over two axis-aligned boxes.
 //
-// This generates the training data of the touching-pair surrogate and judges its predictions
+// This generates the training data of the touching-pair surrogate and checks its predictions
 // (Sec. 3 computes singular near-field entries with singularity-removing transforms followed by
 // tensor Gauss rules; this is a scheme of the same kind for boxes). With u = x - y,
 //

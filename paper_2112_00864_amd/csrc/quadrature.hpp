@@ -1,4 +1,4 @@
-// High-order box-pair quadrature (quadrature.hip): the training data and the error judge of the
+// High-order box-pair quadrature (quadrature.hip): the training data and the error reference of the
 // touching-pair surrogate.
 #pragma once
 #include <hip/hip_runtime.h>

@@ -131,7 +131,7 @@ def test_training_reaches_the_gate(trained):
 
 def test_surrogate_gain_over_quadrature(trained):
     """Fresh pairs: accepted values within 1e-7 of the high-order quadrature. Reports the cost
-    against the high-order quadrature (the judge) and against the plain quadrature at order 6,
+    against the high-order quadrature (the error reference) and against the plain quadrature at order 6,
     the lowest order that meets 1e-7 on its own for this family."""
     net, _ = trained
     rng = np.random.default_rng(99)
