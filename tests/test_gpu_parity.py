@@ -163,6 +163,33 @@ def test_mixed_assembled_near_field(L, q):
     assert a32.info["device_bytes"] < a64.info["device_bytes"]
 
 
+@pytest.mark.parametrize("precision", [bcv.FP64, bcv.MIXED_F32])
+def test_work_decomposition_does_not_change_the_result(precision):
+    """Near units of 64 entries and interaction pieces of 16 slots (many split tasks and combine
+    steps), of 128 / 40, the defaults, and one piece per row / task: every decomposition against
+    the oracle (FP64: <= 1e-10; mixed: <= 1e-6), and the FP64 ones against each other to rounding."""
+    L, q = 4, 6
+    m, lv = mesh(L)
+    f = synth.leaf_density(lv, seed=3)
+    ref = fmm.FMM(m, q).apply(f)
+    tree = bcv.build_bc_tree(L)
+    us = []
+    for unit, slots in [(0, 0), (64, 16), (128, 40), (65536, 65536)]:
+        for nf in (bcv.NEAR_QUADRATURE, bcv.NEAR_ASSEMBLED):
+            announce("decomposition near_unit=%d m2l_max_slots=%d nearfield=%d precision=%d"
+                     % (unit, slots, nf, precision))
+            plan = bcv.plan_interactions(tree, q=q, nearfield=nf, precision=precision, near_unit=unit,
+                                         m2l_max_slots=slots)
+            u = gpu_apply(plan, f)
+            e = rel_l2(lv, u, ref)
+            announce("  rel-L2 vs O2 %.3e" % e)
+            assert e <= (TOL if precision == bcv.FP64 else 1e-6)
+            us.append(u)
+    if precision == bcv.FP64:
+        for u in us[1:]:
+            assert np.max(np.abs(u - us[0]) / np.abs(us[0])) < 1e-13
+
+
 def test_degenerate_densities():
     m, lv = mesh(3)
     plan = bcv.plan_interactions(bcv.build_bc_tree(3), q=6)
