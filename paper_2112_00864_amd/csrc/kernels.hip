@@ -1392,9 +1392,11 @@ void launch_near(const bcv_plan_s &p, const double *f, const double *lam, int pa
 template <int Q, int A0, int A1, int B0, int B1, class T>
 void launch_m2l_block(const bcv_plan_s &p, const XcdRanges &ranges, const T *G, const T *Mr, hipStream_t st)
 {
-    // four waves per SIMD (128 registers) where the block fits, else two
+    // four waves per SIMD (128 registers) where the block fits, else two; eight (64 registers) for the
+    // smallest blocks up to order 8 (the FP32 order-4 block: 17% faster than at four waves; above
+    // order 8 their expansion epilogue spills at 64)
     constexpr int regs = (A1 - A0 + B1 - B0) * (int)(sizeof(T) / 4);
-    m2l_shift_kernel<Q, T, A0, A1, B0, B1, (regs > 110 ? 2 : 4)><<<(unsigned)p.m2l_groups, kWave, 0, st>>>(
+    m2l_shift_kernel<Q, T, A0, A1, B0, B1, (regs > 110 ? 2 : (regs <= 50 && Q <= 8 ? 8 : 4))><<<(unsigned)p.m2l_groups, kWave, 0, st>>>(
         ranges, p.d_tasks, p.d_task_targets, p.d_slot_off, p.d_slot_src, G, Mr, p.d_m2l_partial, p.d_Lam, p.R, p.K);
     check_launch();
 }
@@ -1502,7 +1504,7 @@ void launch_level_block(const bcv_plan_s &p, const XcdRanges &ranges, unsigned g
     constexpr int W = (int)(sizeof(T) / 4);
     constexpr BlockSpec bs = kBlocks<Q, W>.b[I];
     constexpr int regs = (bs.a1 - bs.a0 + bs.b1 - bs.b0) * W;
-    m2l_shift_kernel<Q, T, bs.a0, bs.a1, bs.b0, bs.b1, (regs > 110 ? 2 : 4)><<<groups, kWave, 0, st>>>(
+    m2l_shift_kernel<Q, T, bs.a0, bs.a1, bs.b0, bs.b1, (regs > 110 ? 2 : (regs <= 50 && Q <= 8 ? 8 : 4))><<<groups, kWave, 0, st>>>(
         ranges, p.d_tasks, p.d_task_targets, p.d_slot_off, p.d_slot_src, G, Mr, p.d_m2l_partial, p.d_Lam, p.R, p.K);
     check_launch();
 }
