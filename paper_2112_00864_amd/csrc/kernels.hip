@@ -318,22 +318,25 @@ __device__ __forceinline__ double near_entry(uint32_t code, const double4 gt, co
 // Q: the largest order of any level; a level-l leaf writes its ncoef(q_l) and (q_l + 1)^2 leading
 // coefficients (the tables are graded, so those are the order-q_l tables).
 // Leaves of level skip_level write only their folded rows (their parents' moments come from
-// m2m_leaves_kernel); -1 = none.
+// m2m_leaves_kernel); -1 = none. One thread per (leaf, j), j < ldr: it writes folded coefficient j
+// and full coefficients j, j + ldr, ... of its leaf, so a row's stores are contiguous.
 template <int Q, class TR>
-__global__ void p2m_kernel(int64_t n_leaves, const int32_t *__restrict__ leaf_cell, const double4 *__restrict__ geom,
-                           const double *__restrict__ f, double *__restrict__ M, TR *__restrict__ Mr,
-                           const LevelOrders lo, int skip_level)
+__global__ __launch_bounds__(256) void p2m_kernel(int64_t n_leaves, const int32_t *__restrict__ leaf_cell,
+                                                  const double4 *__restrict__ geom, const double *__restrict__ f,
+                                                  double *__restrict__ M, TR *__restrict__ Mr, const LevelOrders lo,
+                                                  int skip_level)
 {
-    const int64_t leaf = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;  // one wave per leaf
-    const int lane = threadIdx.x % kWave;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t leaf = idx / lo.ldr;
+    const int j = (int)(idx - leaf * lo.ldr);
     if (leaf >= n_leaves) return;
     const double a = geom[leaf].w;
     const int lev = level_of_side(a);
     const double s = f[leaf] * (a * a * a);
     const int64_t c = leaf_cell[leaf];
+    if (j < lo.r[lev]) Mr[c * lo.ldr + j] = (TR)(s * kFoldedKappa<Q>.v[j]);
     if (lev != skip_level)
-        for (int b = lane; b < lo.k[lev]; b += kWave) M[c * lo.ldk + b] = s * kKappa<Q>.v[b];
-    for (int b = lane; b < lo.r[lev]; b += kWave) Mr[c * lo.ldr + b] = (TR)(s * kFoldedKappa<Q>.v[b]);
+        for (int b = j; b < lo.k[lev]; b += lo.ldr) M[c * lo.ldk + b] = s * kKappa<Q>.v[b];
 }
 
 // M2M for parents whose 8 children are leaves, straight from the children's densities (one wave
@@ -1537,7 +1540,7 @@ void launch_p2m(const bcv_plan_s &p, const double *f, hipStream_t st, bool fused
 {
     const int skip = fused && !p.q_schedule ? p.L : -1;
     const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
-    const unsigned blocks = (unsigned)((p.n_leaves + 3) / 4);
+    const unsigned blocks = (unsigned)((p.n_leaves * (int64_t)p.R + 255) / 256);
     const LevelOrders lo = level_orders(p);
     constexpr int QT = Q > kMaxSchedQ ? Q : kMaxSchedQ;  // tables large enough for every level's order
     if (p.precision == BCV_MIXED_F32) {
