@@ -961,20 +961,39 @@ __global__ __launch_bounds__(256) void near_combine_kernel(int64_t n_splits, con
 }
 
 // ---- evaluation phase alone (near field computed concurrently): u += a^3 sum_a kappa_a Lambda^a --
+// One wave per leaf.
 template <int Q>
 __global__ __launch_bounds__(256) void eval_add_kernel(int64_t n_leaves, const double4 *__restrict__ geom,
                                                        const double *__restrict__ Lam,
                                                        const int32_t *__restrict__ leaf_cell,
-                                                       double *__restrict__ u, const LevelOrders lo,
-                                                       int skip_level)
+                                                       double *__restrict__ u, const LevelOrders lo)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t t = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
     if (t >= n_leaves) return;
     const double a = geom[t].w;
-    if (level_of_side(a) == skip_level) return;  // evaluated by the fused last L2L
     const double s = wave_sum(eval_far<Q>(Lam + (int64_t)leaf_cell[t] * lo.ldk, a, lane, lo.k[level_of_side(a)]));
     if (lane == 0) u[t] += s;
+}
+
+// The same for the leaves off skip_level, whose leaves the fused last L2L evaluates: one thread per
+// leaf, so that those (most of them) leave at once and the few others read their own rows.
+template <int Q>
+__global__ __launch_bounds__(256) void eval_add_rest_kernel(int64_t n_leaves, const double4 *__restrict__ geom,
+                                                            const double *__restrict__ Lam,
+                                                            const int32_t *__restrict__ leaf_cell,
+                                                            double *__restrict__ u, const LevelOrders lo,
+                                                            int skip_level)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_leaves) return;
+    const double a = geom[t].w;
+    const int lev = level_of_side(a);
+    if (lev == skip_level) return;
+    const double *__restrict__ lam = Lam + (int64_t)leaf_cell[t] * lo.ldk;
+    double s = 0.0;
+    for (int k = 0; k < lo.k[lev]; ++k) s = fma(kKappa<Q>.v[k], lam[k], s);
+    u[t] = fma(s, a * a * a, u[t]);
 }
 
 // ---- BtV (Algorithm 3): boundary moments and the near field of boundary faces --------------------
@@ -1694,13 +1713,15 @@ void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStre
                                         geom, u);
             check_launch();
         }
-        const unsigned eblocks = (unsigned)((p.n_leaves + 3) / 4);
         if (p.q_schedule)
-            eval_add_kernel<kMaxSchedQ><<<eblocks, 256, 0, st>>>(p.n_leaves, geom, p.d_Lam, p.d_leaf_cell, u,
-                                                                 level_orders(p), -1);
+            eval_add_kernel<kMaxSchedQ><<<(unsigned)((p.n_leaves + 3) / 4), 256, 0, st>>>(
+                p.n_leaves, geom, p.d_Lam, p.d_leaf_cell, u, level_orders(p));
+        else if (fuse_last)
+            eval_add_rest_kernel<Q><<<(unsigned)((p.n_leaves + 255) / 256), 256, 0, st>>>(
+                p.n_leaves, geom, p.d_Lam, p.d_leaf_cell, u, level_orders(p), p.L);
         else
-            eval_add_kernel<Q><<<eblocks, 256, 0, st>>>(p.n_leaves, geom, p.d_Lam, p.d_leaf_cell, u, level_orders(p),
-                                                        fuse_last ? p.L : -1);
+            eval_add_kernel<Q><<<(unsigned)((p.n_leaves + 3) / 4), 256, 0, st>>>(p.n_leaves, geom, p.d_Lam,
+                                                                              p.d_leaf_cell, u, level_orders(p));
         check_launch();
         marks.stop(BCV_PHASE_EVAL, st);
     } else {
