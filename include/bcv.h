@@ -101,8 +101,8 @@ typedef struct {
     int near_unit;         /* work-unit size of the near field: rows longer than this many entries are
                               cut into pieces of about equal length (0 = 512; else 64..65536) */
     int m2l_max_slots;     /* longest slot list of one interaction task; longer lists are cut into
-                              pieces whose partial sums are added in a fixed order (0 = 320, or 256 with
-                              q_schedule = 1; else 16..65536) */
+                              pieces whose partial sums are added in a fixed order (0 = 320, or 256
+                              with q_schedule = 1 or under 2^20 slots in all; else 16..65536) */
     int q_schedule;        /* 0: the expansion order q on every level. 1: level-dependent orders
                               q_l = q + L - l (Sec. 4, the FMM error with level-dependent orders;
                               q is the finest level's): a level-l cell carries moments and local

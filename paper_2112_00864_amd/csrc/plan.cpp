@@ -277,7 +277,8 @@ struct M2LPlan {
 // lanes belong to many signature classes) are cut into pieces so that no wave outlasts the others.
 // Most tasks of a face-marked mesh hold 224-287 slots; at 320 those stay whole (measured 3.5% faster
 // than 256 at h = 1/128 and 1/256; shorter pieces add partial sums and gathering first slots). With
-// level-dependent orders each level is its own launch, and 256 measured faster (4% in FP64).
+// level-dependent orders each level is its own launch, and 256 measured faster (4% in FP64); so
+// did small meshes, whose few tasks need the shorter pieces to fill the GPU.
 constexpr int kDefaultMaxSlots = 320;
 constexpr int kDefaultMaxSlotsSchedule = 256;
 
@@ -322,8 +323,10 @@ uint64_t hash_keys(const std::vector<int32_t> &keys)
 // lane's own list.
 // max_slots: the longest slot list of a task piece, per level. per_level: each level's tasks get XCD
 // ranges of their own (the levels are launched one by one, at their own expansion orders).
+// small_slots > 0: the limit for phases of fewer than 2^20 slots (about 256 per wave slot of the
+// GPU), where shorter pieces give more waves.
 M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, const std::vector<int32_t> &max_slots,
-                  bool per_level = false)
+                  bool per_level = false, int32_t small_slots = 0)
 {
     M2LPlan m;
     const int32_t zero_row = (int32_t)t.n_cells();
@@ -553,7 +556,8 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, const std::ve
     for (size_t q = 0; q < chunks.size(); ++q) {
         const int32_t base = (int32_t)chunk_base[q];
         const int32_t n = (int32_t)(chunk_base[q + 1] - chunk_base[q]);
-        const int32_t ms = max_slots[chunks[q].lev];
+        const int32_t ms = small_slots > 0 && n_slots < (1 << 20) ? std::min(small_slots, max_slots[chunks[q].lev])
+                                                                   : max_slots[chunks[q].lev];
         const int32_t np = std::max<int32_t>(1, (n + ms - 1) / ms);
         if (np > 1) split_of_chunk[q] = M2LSplit{-1, m.n_pieces, np, 0};
         for (int32_t k = 0; k < np; ++k) {
@@ -940,7 +944,8 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         if (opts.q_schedule)
             for (int lev = 0; lev <= t.L; ++lev)
                 level_slots[lev] = std::max<int32_t>(8, slots >> std::min(16, p->q_level[lev] - opts.q));
-        M2LPlan m2l = build_m2l(t, grids, level_slots, opts.q_schedule != 0);
+        M2LPlan m2l = build_m2l(t, grids, level_slots, opts.q_schedule != 0,
+                                opts.m2l_max_slots == 0 && !opts.q_schedule ? kDefaultMaxSlotsSchedule : 0);
         std::vector<int32_t> id_of_key(15 * 15 * 15, -1);
         for (int32_t key : m2l.slot_key) id_of_key[key & 0x7FFFFFFF] = 0;
         std::vector<double> G;
