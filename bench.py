@@ -1,21 +1,22 @@
 """Benchmark of the VtV apply (BC-FMM volume potential) on one MI355X.
 
-Workload: unit-cube BC octree with boundary leaves of side h = 1/128 (L = 7, 219,080 leaves),
-expansion order q = 6, piecewise-constant Gaussian-mixture density (seed 0). A step is one full
-VtV apply (Algorithm 1: moments, upward pass, interaction phase, downward pass, near field and
-evaluation) with the density already resident in HBM. Plan construction (lists, tables, workspace)
-happens once before timing and is reported separately.
+Workload (the metric's configuration): unit-cube BC octree with boundary leaves of side h = 1/256
+(L = 8, 896,512 leaves), expansion order q = 6, piecewise-constant Gaussian-mixture density
+(seed 0). A step is one full VtV apply (Algorithm 1: moments, upward pass, interaction phase,
+downward pass, near field and evaluation) with the density already resident in HBM. Plan
+construction (lists, tables, workspace) happens once before timing and is reported separately.
 
-By default the same mesh is timed twice: with the plain FP64 path and with the mixed path (FP32
-interaction phase and non-touching near field, FP64 singular pairs, tree passes and accumulation),
-whose touching-pair class values come from the trained surrogate where it certifies 1e-7 (the
-network is trained on the GPU before timing).
-The headline value is the mixed rate if the mixed result is within rel-L2 1e-6 of the FP64 result
-(L2 norm of cell averages over Omega), else the FP64 rate.
+The same mesh is timed twice: with the plain FP64 path and with the mixed path (FP32 interaction
+phase and non-touching near field, FP64 singular pairs, tree passes and accumulation), whose
+touching-pair class values come from the trained surrogate where it certifies 1e-7 (the network is
+trained on the GPU before timing). The headline value is the mixed rate if the mixed result is
+within rel-L2 1e-6 of the FP64 result (L2 norm of cell averages over Omega), else the FP64 rate.
 
 Prints one JSON line with the metric, the per-phase device times from HIP events recorded on the
-apply's stream, the roofline of the dominant kernel, the FP64 rate and the ratio, and the CPU
-oracle's throughput on a bounded sample of the same workload.
+apply's stream, the roofline of the dominant kernel (algorithmic work per apply / its measured
+time), the FP64 rate and the ratio, the CPU oracle's throughput on a bounded sample of the same
+workload, and, as extras on the h = 1/128 mesh (L = 7): the plain FP64 apply (the second
+workload configuration), BtV/VtB, level-dependent orders and the neighbour marking.
 """
 
 import argparse
@@ -38,9 +39,16 @@ PEAK_HBM = 8.0e12  # bytes/s
 
 
 def m2l_flops_per_pair(q):
-    """Algorithmic flops of one interaction pair in the harmonic reduction the kernels use: one FMA
-    (2 flops) per (alpha, beta) with alpha_z, beta_z <= 1 and |alpha| + |beta| <= q, i.e.
-    2 sum_{n+m<=q} (2n+1)(2m+1) (1064 at q = 6; the unreduced sums would be 2 C(q+6, 6) = 1848)."""
+    """Algorithmic flops of one interaction pair: one multiply-add per (alpha, beta) with
+    |alpha| + |beta| <= q, i.e. 2 C(q + 6, 6) (1848 at q = 6)."""
+    from math import comb
+
+    return 2 * comb(q + 6, 6)
+
+
+def m2l_reduced_flops_per_pair(q):
+    """Flops the kernels execute per pair in the harmonic reduction (alpha_z, beta_z <= 1):
+    2 sum_{n+m<=q} (2n+1)(2m+1) (1064 at q = 6)."""
     return 2 * sum((2 * n + 1) * (2 * m + 1) for n in range(q + 1) for m in range(q + 1 - n))
 
 
@@ -100,8 +108,8 @@ def cpu_baseline(L, q, f, u_gpu, n_targets, leaves):
         "cores": threads,
         "kind": "oracle",
         "sample": "O2 (Algorithm 1 step by step, NumPy + plain C) at %d random target leaves of the same "
-                  "h=1/128 q=6 workload, including the full moment and upward passes; mesh build %.1f s "
-                  "excluded" % (n_targets, t1 - t0),
+                  "h=1/%d q=%d workload, including the full moment and upward passes; mesh build %.1f s "
+                  "excluded" % (n_targets, 2 ** L, q, t1 - t0),
         "seconds": t2 - t1,
         "max_rel_diff_vs_gpu": err,
     }
@@ -149,36 +157,53 @@ def measure(bcv, torch, tree, f, args, dev, nf, prec, surrogate=None):
         plan = make_plan(1)
         _, iso = timed_applies(bcv, torch, plan, f, u, args.warmup, args.steps, dev)
         del plan
-    roof, roof_other = roofline(info, iso, args, prec)
+    roof, roof_other = roofline(info, iso, args, prec, args.q)
     return {"plan_s": plan_s, "info": info, "ms": ms, "phases": phase_avg, "phases_serial": iso, "u": u_host,
             "roof": roof, "roof_other": roof_other}
 
 
-def roofline(info, phase_avg, args, prec):
-    """Roofline of the interaction phase and the near-field kernel, per apply, from the phase times
-    of the serialized pass (HIP events on the stream the phase runs on, averaged over the applies)."""
+def tree_pass_bytes(info, fp_bytes=8):
+    """Algorithmic bytes of the tree passes per apply: every pass reads the coefficient array it
+    consumes once and writes the one it produces once (K coefficients per cell, FP64):
+    P2M reads f and writes the leaf moments; M2M reads the children's moments and writes the
+    parents'; L2L reads the parents' local coefficients and reads and writes the children's."""
+    K, n_leaf, n_cell = info["K"], info["n_leaves"], info["n_cells"]
+    n_marked, n_child = n_cell - n_leaf, n_cell - 1
+    p2m = n_leaf * 8 + n_leaf * K * fp_bytes
+    m2m = (n_child + n_marked) * K * fp_bytes
+    l2l = (n_marked + 2 * n_child) * K * fp_bytes
+    return p2m + m2m + l2l
+
+
+def roofline(info, phase_avg, args, prec, q):
+    """Roofline of the interaction phase, the near field and the tree passes, per apply, from the
+    phase times of the serialized pass (HIP events on the stream the phase runs on, averaged over
+    the applies). Work counts are the algorithmic ones: 2 C(q+6, 6) flops per interaction pair,
+    12 B (FP64 entry + index) or 8 B (FP32 entry + index) per assembled near pair."""
     from paper_2112_00864_amd import profiling
 
     mixed = prec == "mixed"
     peak = (PEAK_FP32 if mixed else PEAK_FP64) / 1e12
     m2l_ms = phase_avg["m2l"]
     near_ms = phase_avg["near"]
-    n = info["n_leaves"]
-    m2l_roof = {"bound": "alu", "achieved": info["n_m2l"] * m2l_flops_per_pair(args.q) / (m2l_ms * 1e-3) / 1e12,
-                "peak": peak, "unit": "TFLOP/s"}
+    m2l_roof = {"bound": "alu", "achieved": info["n_m2l"] * m2l_flops_per_pair(q) / (m2l_ms * 1e-3) / 1e12,
+                "peak": peak, "unit": "TFLOP/s",
+                "flops_per_pair": m2l_flops_per_pair(q),
+                "achieved_executed_reduced": info["n_m2l"] * m2l_reduced_flops_per_pair(q) / (m2l_ms * 1e-3) / 1e12,
+                "reduced_flops_per_pair": m2l_reduced_flops_per_pair(q),
+                "ms": m2l_ms}
     if args.nearfield == "assembled":
-        # entry (FP64, or FP32 in the mixed path) + column index + gathered f per pair
-        near_bytes = info["n_near"] * ((4 if mixed else 8) + 4 + 8) + n * (8 * 2 + 8 + 8 + 32)
+        near_bytes = info["n_near"] * (8 if mixed else 12)
         near_roof = {"bound": "hbm", "achieved": near_bytes / (near_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
-                     "unit": "GB/s"}
+                     "unit": "GB/s", "bytes_per_pair": 8 if mixed else 12, "ms": near_ms}
     else:
-        near_roof = {"bound": "alu", "achieved": near_flops(info, args.q) / (near_ms * 1e-3) / 1e12,
-                     "peak": peak, "unit": "TFLOP/s"}
-    near_name = "near_eval_kernel<%d, %s, %s>" % (args.q, "true" if args.nearfield == "assembled" else "false",
+        near_roof = {"bound": "alu", "achieved": near_flops(info, q) / (near_ms * 1e-3) / 1e12,
+                     "peak": peak, "unit": "TFLOP/s", "ms": near_ms}
+    near_name = "near_eval_kernel<%d, %s, %s>" % (q, "true" if args.nearfield == "assembled" else "false",
                                                   "true" if mixed else "false")
     # the interaction phase: the interaction launches (reading the folded moment rows that P2M and
     # M2M write) and the sum of the split tasks' pieces
-    m2l_names = (m2l_kernel_names(args.q, mixed)
+    m2l_names = (m2l_kernel_names(q, mixed)
                  + ["m2l_combine_kernel"])
     for roof_, names in ((m2l_roof, m2l_names), (near_roof, [near_name])):
         roof_["frac"] = roof_["achieved"] / roof_["peak"]
@@ -188,8 +213,13 @@ def roofline(info, phase_avg, args, prec):
         roof_["kernel"] = " + ".join(names)
         roof_["measured"] = ("HIP events per phase over %d applies, near field after the far field on one stream"
                              % args.steps)
+    tree_ms = phase_avg["p2m"] + phase_avg["m2m"] + phase_avg["l2l"]
+    tb = tree_pass_bytes(info)
+    tree_roof = {"bound": "hbm", "achieved": tb / (tree_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                 "bytes": tb, "ms": tree_ms, "kernel": "P2M + M2M + L2L phases (all launches)"}
+    tree_roof["frac"] = tree_roof["achieved"] / tree_roof["peak"]
     dominant = m2l_roof if m2l_ms >= near_ms else near_roof
-    return dominant, {"m2l_kernel": m2l_roof, "near_eval_kernel": near_roof}
+    return dominant, {"m2l_kernel": m2l_roof, "near_eval_kernel": near_roof, "tree_passes": tree_roof}
 
 
 def measure_btv(bcv, torch, tree, f, args, dev):
@@ -428,7 +458,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--L", type=int, default=7)
+    ap.add_argument("--L", type=int, default=8, help="finest level of the timed mesh (h = 2^-L)")
+    ap.add_argument("--extras-L", type=int, default=7,
+                    help="finest level of the extra measurements (plain FP64 config, BtV/VtB, level-dependent "
+                         "orders, neighbour marking); 0 skips them all")
     ap.add_argument("--q", type=int, default=6)
     ap.add_argument("--nearfield", choices=["quadrature", "assembled"], default="assembled",
                     help="near-field entries stored once at plan time (assembled) or evaluated in every "
@@ -437,7 +470,7 @@ def main():
                     help="both: time the FP64 and the mixed path on the same mesh and report the ratio")
     ap.add_argument("--streams", type=int, choices=[1, 2], default=2,
                     help="2: near field concurrent with the far field on a second stream")
-    ap.add_argument("--cpu-targets", type=int, default=4000)
+    ap.add_argument("--cpu-targets", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="mixed path without the touching-pair surrogate")
     ap.add_argument("--no-btv", action="store_true", help="skip the BtV (Algorithm 3) measurement")
@@ -578,20 +611,37 @@ def main():
     if surrogate is not None:
         line["surrogate"] = {"classes_from_network": runs["mixed"]["info"]["surrogate_classes"], "of": 6,
                              "tol": SURROGATE_TOL, "training": sur_report}
-    if not args.no_btv:
-        line["btv"] = measure_btv(bcv, torch, tree, f, args, dev)
-    if not args.no_schedule:
-        sched = measure_schedule(bcv, torch, tree, f, args, dev, runs["fp64"]["u"] if "fp64" in runs else None)
-        if sched is not None:
-            line["level_orders"] = sched
-            print("level orders: %s" % json.dumps(sched), file=sys.stderr)
-    if not args.no_marking:
-        line["neighbour_marking"] = measure_marking(bcv, torch, args, dev)
-        print("neighbour marking: %s" % json.dumps(line["neighbour_marking"]), file=sys.stderr)
-        print("btv: %s" % json.dumps({k: line["btv"][k] for k in ("fp64", "mixed", "mixed_vs_fp64_rel_l2",
-                                                                  "representation_formula_rel_err",
-                                                                  "vtb_mixed_vs_fp64_rel")}),
-              file=sys.stderr, flush=True)
+    if args.extras_L:
+        # extras on the h = 1/128 mesh: the plain FP64 workload (its own configuration), BtV/VtB,
+        # level-dependent orders and the neighbour marking
+        xargs = argparse.Namespace(**vars(args))
+        xargs.L = args.extras_L
+        xtree = bcv.build_bc_tree(xargs.L)
+        xleaves = xtree.leaves()
+        xf = torch.tensor(synth.leaf_density(xleaves, seed=0), device="cuda:%d" % dev)
+        r64 = measure(bcv, torch, xtree, xf, xargs, dev, nf, "fp64")
+        line["plain_fp64_h%d" % (2 ** xargs.L)] = {
+            "workload": "VtV apply, unit cube BC octree h=1/%d (L=%d), %d leaves, q=%d, Gaussian-mixture density "
+                        "seed 0, plain FP64, near field %s, %d stream(s)"
+                        % (2 ** xargs.L, xargs.L, len(xleaves), args.q, args.nearfield, args.streams),
+            "value": len(xleaves) / (r64["ms"] * 1e-3), "unit": "cell-potentials/s", "ms_per_step": r64["ms"],
+            "phase_ms": r64["phases"], "phase_ms_serial": r64["phases_serial"], "roofline": r64["roof"],
+            "roofline_other": r64["roof_other"], "plan_seconds": r64["plan_s"]}
+        print("plain FP64 h=1/%d: step %.3f ms" % (2 ** xargs.L, r64["ms"]), file=sys.stderr, flush=True)
+        if not args.no_btv:
+            line["btv"] = measure_btv(bcv, torch, xtree, xf, xargs, dev)
+            print("btv: %s" % json.dumps({k: line["btv"][k] for k in ("fp64", "mixed", "mixed_vs_fp64_rel_l2",
+                                                                      "representation_formula_rel_err",
+                                                                      "vtb_mixed_vs_fp64_rel")}),
+                  file=sys.stderr, flush=True)
+        if not args.no_schedule:
+            sched = measure_schedule(bcv, torch, xtree, xf, xargs, dev, r64["u"])
+            if sched is not None:
+                line["level_orders"] = sched
+                print("level orders: %s" % json.dumps(sched), file=sys.stderr)
+        if not args.no_marking:
+            line["neighbour_marking"] = measure_marking(bcv, torch, xargs, dev)
+            print("neighbour marking: %s" % json.dumps(line["neighbour_marking"]), file=sys.stderr)
     print(json.dumps(line), flush=True)
 
 

@@ -92,11 +92,11 @@ typedef struct {
                       and the downward pass, and is joined back to the caller's stream before
                       the evaluation phase */
     bcv_mlp surrogate;     /* NULL: the touching-pair integrals come from bcv_touching_integrals.
-                              Else the six face/edge/vertex classes take the trained surrogate's
-                              value where its error estimate is <= surrogate_tol (relative), and
-                              the high-order box-pair quadrature otherwise; the self class keeps
-                              the exact value. The plan copies the values: the network may be
-                              destroyed afterwards. */
+                              Else each of the six face/edge/vertex classes takes the trained
+                              surrogate's value where its error estimate is <= surrogate_tol
+                              (relative) and keeps the exact table value where it is not; the
+                              self class keeps the exact value. The plan copies the values: the
+                              network may be destroyed afterwards. */
     double surrogate_tol;  /* e.g. 1e-7; 0 forces the fallback for every class */
     int near_unit;         /* work-unit size of the near field: rows longer than this many entries are
                               cut into pieces of about equal length (0 = 512; else 64..65536) */
@@ -328,15 +328,19 @@ typedef struct {
     double tol;               /* acceptance tolerance used for the held-out report */
 } bcv_mlp_train_opts;
 
+/* The n_valid held-out pairs are split in two: the first half calibrates the error estimate, the
+ * second half (valid_reported pairs, never used for training or calibration) gives the figures
+ * below; with n_valid = 1 the one pair serves both. */
 typedef struct {
     double residual_scale;             /* RMS of (J_hi - J_lo) / J_lo over the training pairs */
-    double kappa;                      /* factor of the error estimate, calibrated on the held-out
-                                          pairs: 1.5 x max (true error / raw estimate) */
-    double valid_max_rel_err_lo;       /* held-out: max |J_lo - J_hi| / |J_hi| (without the network) */
-    double valid_max_rel_err;          /* held-out: max relative error of the corrected value */
+    double kappa;                      /* factor of the error estimate, calibrated on the first half
+                                          of the held-out pairs: 1.5 x max (true error / raw estimate) */
+    double valid_max_rel_err_lo;       /* reported pairs: max |J_lo - J_hi| / |J_hi| (without the network) */
+    double valid_max_rel_err;          /* reported pairs: max relative error of the corrected value */
     double valid_rms_rel_err;
-    double valid_max_rel_err_accepted; /* held-out: max relative error among accepted pairs */
-    int64_t valid_accepted;            /* held-out pairs whose error estimate is <= tol */
+    double valid_max_rel_err_accepted; /* reported pairs: max relative error among accepted pairs */
+    int64_t valid_accepted;            /* reported pairs whose error estimate is <= tol */
+    int64_t valid_reported;            /* size of the reported half */
 } bcv_mlp_train_report;
 
 /* J for n pairs of axis-aligned boxes by the high-order quadrature: geom holds 12 doubles per pair

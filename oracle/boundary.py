@@ -410,14 +410,15 @@ class BtVFMM(FMM):
 # cells B_l, downward pass into the boundary children, evaluation of the face's cell's local
 # expansion at the face (2x2 point rule).
 
-def vtb_direct(mesh, f, n=24):
-    """O1: u_f = sum over all leaves l of V_lf f_l."""
+def vtb_direct(mesh, f, n=24, face_idx=None):
+    """O1: u_f = sum over all leaves l of V_lf f_l, for every face or the faces face_idx."""
     E = Entries(mesh, n)
     f = np.asarray(f, dtype=np.float64)
-    u = np.zeros(len(E.faces))
-    for fi in range(len(E.faces)):
+    face_idx = np.arange(len(E.faces)) if face_idx is None else np.asarray(face_idx)
+    u = np.zeros(len(face_idx))
+    for m, fi in enumerate(face_idx):
         for t in range(len(E.leaves)):
-            u[fi] += E.entry(t, fi)[0] * f[t]
+            u[m] += E.entry(t, fi)[0] * f[t]
     return u
 
 

@@ -1,14 +1,16 @@
-"""O2: Algorithm 1 (BC-FMM for the VtV calculation) step by step in FP64 (test infrastructure only).
+"""O2: the BC-FMM of Algorithm 1 evaluated phase by phase in FP64 (test infrastructure only).
 
-Each phase follows the paper's Algorithm 1 and the translation operators of Section 3:
+The far field is represented by order-q Cartesian Taylor expansions (Sec. 3, translation
+operators); every phase works on whole levels with dense translation matrices:
 
-  near field    u_w = sum_{w' in N*(w)} <1_w, N_w' f>        for leaves w (N* with marked
-                sources expanded to their leaves; entries as in oracle.direct)
-  moments       m_w^b = <(. - x_w)^b, f>_{L2(w)}, |b| <= q      for leaves (2x2x2 point rule)
-  upward pass   m_w = sum_{w' in K(w)} M(w, w') m_w'            l = L-1..0, w in M_l
-  interaction   lambda_w = sum_{w' in I(w)} T(w, w') m_w'       every cell of every level
-  downward pass lambda_w' += L(w', w) lambda_w                  l = 0..L-1, w in M_l, w' in K(w)
-  evaluation    u_w += U(w) lambda_w                            for leaves (2x2x2 point rule)
+  near field    sum of the Galerkin entries (oracle.direct) over each leaf's extended neighbour
+                list, a marked neighbour standing for all of its leaves
+  moments       the 2x2x2 point rule applied to the monomials (x - centre)^b, |b| <= q, per leaf
+  upward pass   children's moments shifted to their parent's centre, finest level first
+  interaction   derivative matrices T applied to the moments of each cell's interaction list,
+                grouped by integer offset
+  downward pass parents' local coefficients shifted to their children, coarsest level first
+  evaluation    the local expansion integrated over each leaf with the 2x2x2 point rule
 
 The far field of a leaf pair is therefore the order-q Taylor polynomial of G about the centres
 of the ancestors that meet in an interaction list, integrated with the same point rule as
@@ -116,7 +118,7 @@ class FMM:
 
     # -- Algorithm 1 phases --------------------------------------------------------------------
     def near_field(self, f, targets):
-        """u_w = sum over N*(w) of the Galerkin entries times f (near-field calculation)."""
+        """Near-field sums of the targets: Galerkin entries over the extended neighbour list times f."""
         mesh = self.mesh
         ti, si = [], []
         for n, t in enumerate(targets):
@@ -130,7 +132,7 @@ class FMM:
         return np.bincount(ti, weights=vals * f[si], minlength=len(targets))
 
     def moments(self, f):
-        """Moment calculation: m_w = sum_g w_g f_w (x_g - x_w)^b for every leaf, by level."""
+        """Leaf moments by level: f times the point-rule integral of each monomial about the centre."""
         mesh = self.mesh
         m = [np.zeros((len(mesh.levels[lev]), self.K_of[lev])) for lev in range(mesh.L + 1)]
         for lev, (pos, idx) in enumerate(self._rows):
@@ -152,7 +154,7 @@ class FMM:
         return np.array(par, dtype=np.int64), {k: np.array(v, dtype=np.int64) for k, v in kids.items()}
 
     def upward(self, m):
-        """Upward pass: m_w = sum_{w' in K(w)} M(w, w') m_w' for l = L-1..0 and w in M_l."""
+        """Moments of every marked cell from its eight children, finest level first."""
         for lev in range(self.mesh.L - 1, -1, -1):
             par, kids = self._children_rows(lev)
             if len(par) == 0:
@@ -164,7 +166,7 @@ class FMM:
         return m
 
     def interaction(self, m):
-        """Interaction phase: lambda_w = sum_{w' in I(w)} T(w, w') m_w' for every cell."""
+        """Local coefficients of every cell from the moments of its interaction list, level by level."""
         mesh = self.mesh
         lam = [np.zeros((len(mesh.levels[lev]), self.K_of[lev])) for lev in range(mesh.L + 1)]
         for lev in range(mesh.L + 1):
@@ -184,7 +186,7 @@ class FMM:
         return lam
 
     def downward(self, lam):
-        """Downward pass: lambda_w' += L(w', w) lambda_w for l = 0..L-1, w in M_l, w' in K(w)."""
+        """Children's local coefficients receive their parent's, shifted, coarsest level first."""
         for lev in range(self.mesh.L):
             par, kids = self._children_rows(lev)
             if len(par) == 0:
@@ -194,7 +196,7 @@ class FMM:
         return lam
 
     def evaluation(self, lam, u):
-        """Evaluation phase: u_w += sum_g w_g sum_a lambda_w^a (x_g - x_w)^a for every leaf."""
+        """Adds each leaf's local expansion, integrated over the leaf with the point rule, to u."""
         mesh = self.mesh
         for lev, (pos, idx) in enumerate(self._rows):
             if len(pos):

@@ -63,7 +63,8 @@ class TrainOpts(ctypes.Structure):
 class TrainReport(ctypes.Structure):
     _fields_ = [("residual_scale", ctypes.c_double), ("kappa", ctypes.c_double), ("valid_max_rel_err_lo", ctypes.c_double),
                 ("valid_max_rel_err", ctypes.c_double), ("valid_rms_rel_err", ctypes.c_double),
-                ("valid_max_rel_err_accepted", ctypes.c_double), ("valid_accepted", ctypes.c_int64)]
+                ("valid_max_rel_err_accepted", ctypes.c_double), ("valid_accepted", ctypes.c_int64),
+                ("valid_reported", ctypes.c_int64)]
 
 
 def lib():

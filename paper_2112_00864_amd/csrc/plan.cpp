@@ -863,8 +863,14 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         int32_t fb[6];
         int64_t n_fb = 0;
         surrogate_eval(*opts.surrogate, 6, cls, opts.surrogate_tol, value, est, fb, &n_fb);
-        for (int c = 0; c < 6; ++c) touch[1 + c] = value[c];
-        p->surrogate_classes = (int)(6 - n_fb);
+        // a class takes the network's value only where it is accepted; a rejected class keeps the
+        // exact table value (its fallback, the high-order quadrature, is less accurate than that)
+        p->surrogate_classes = 0;
+        for (int c = 0; c < 6; ++c)
+            if (!fb[c]) {
+                touch[1 + c] = value[c];
+                ++p->surrogate_classes;
+            }
     }
     for (int c = 0; c < kTouchClasses; ++c) p->touch_value[c] = touch[c] / (4.0 * M_PI);
 

@@ -107,9 +107,9 @@ def test_mlp_forward_and_gradient_against_fp64_reference(width):
     gerr = np.max(np.abs(g - gr)) / np.max(np.abs(gr))
     announce("width %d: forward max rel err %.2e; loss %.6e vs %.6e; gradient max rel err %.2e"
              % (width, ferr, loss, lr_, gerr))
-    assert ferr <= 1e-5
+    assert ferr <= 2e-6
     assert abs(loss - lr_) <= 1e-5 * abs(lr_)
-    assert gerr <= 1e-4
+    assert gerr <= 2e-6
 
 
 @pytest.fixture(scope="module")
@@ -129,10 +129,12 @@ def test_training_reaches_the_gate(trained):
     assert rep["valid_max_rel_err_accepted"] <= TOL
 
 
-def test_surrogate_gain_over_quadrature(trained):
-    """Fresh pairs: accepted values within 1e-7 of the high-order quadrature. Reports the cost
-    against the high-order quadrature (the error reference) and against the plain quadrature at order 6,
-    the lowest order that meets 1e-7 on its own for this family."""
+def test_surrogate_accuracy_and_cost(trained):
+    """Fresh pairs: accepted values within 1e-7 of the high-order quadrature, fallbacks equal to it.
+    Reports (does not assert) the cost against the high-order quadrature (the error reference) and
+    against the plain quadrature at order 6, the lowest order that meets 1e-7 on its own for this
+    family of axis-aligned cubes: there the network gains nothing (it runs the order-5 quadrature
+    first, and the rejected pairs pay the order-16 one on top)."""
     net, _ = trained
     rng = np.random.default_rng(99)
     n = 100000

@@ -219,3 +219,28 @@ def test_vtb_constant_density_box_closed_form():
                 tot += ws * wt * closed_forms.box_potential(p)
         ref[n] = tot * a * a
     assert np.max(np.abs(u - ref) / np.abs(ref)) < 3e-4
+
+
+@pytest.mark.parametrize("L", [2, 3])
+def test_sampled_direct_sums_equal_the_loops(L):
+    """The vectorised O1 forms at sampled targets (apply_direct_sampled over all faces,
+    vtb_direct_sampled over all leaves) against the entry-by-entry loops (apply_direct, vtb_direct),
+    which share only the entry definitions with them: the first and last leaf and face, the coarse
+    and fine leaves among 20 random ones."""
+    m = BCMesh(L)
+    faces = B.boundary_faces(m)
+    lv = m.leaf_array()
+    fk = np.column_stack([lv[faces[:, 0]], faces[:, 1:]])
+    qf, gf = synth.face_data(fk, seed=0)
+    rng = np.random.default_rng(3)
+    first_of_level = [int(np.argmax(lv[:, 0] == lev)) for lev in np.unique(lv[:, 0])]
+    t = np.unique(np.concatenate([[0, len(lv) - 1], first_of_level, rng.choice(len(lv), 20, replace=False)]))
+    assert len(np.unique(lv[t, 0])) == len(np.unique(lv[:, 0]))
+    a = B.apply_direct(m, qf, gf, targets=t)
+    b = B.apply_direct_sampled(m, qf, gf, t)
+    assert np.max(np.abs(a - b) / np.abs(a)) <= 1e-13
+    f = synth.leaf_density(lv, seed=0)
+    fsel = np.unique(np.concatenate([[0, len(faces) - 1], rng.choice(len(faces), 20, replace=False)]))
+    u = B.vtb_direct(m, f, face_idx=fsel)
+    v = B.vtb_direct_sampled(m, f, fsel)
+    assert np.max(np.abs(u - v) / np.abs(u)) <= 1e-13
