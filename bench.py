@@ -208,7 +208,7 @@ def roofline(info, phase_avg, args, prec, q):
     for roof_, names in ((m2l_roof, m2l_names), (near_roof, [near_name])):
         roof_["frac"] = roof_["achieved"] / roof_["peak"]
         # HBM bytes per apply (PMC, summed over the launches), None if stale
-        traffic = [profiling.traffic_for(n) for n in names]
+        traffic = [profiling.traffic_for(n, args.L, q) for n in names]
         roof_["traffic"] = None if None in traffic else sum(traffic)
         roof_["kernel"] = " + ".join(names)
         roof_["measured"] = ("HIP events per phase over %d applies, near field after the far field on one stream"
