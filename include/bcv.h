@@ -361,6 +361,19 @@ bcv_status bcv_mlp_get_params(bcv_mlp mlp, float *params);
 bcv_status bcv_mlp_set_params(bcv_mlp mlp, const float *params);
 /* Y [n x 2] = network(X [n x 6]) with the GPU kernels (host arrays). */
 bcv_status bcv_mlp_forward(bcv_mlp mlp, int64_t n, const float *X, float *Y);
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): bcv_mlp_forward on device arrays, allocating nothing.
+ *   X_dev: device, n x 6 floats (row-major features); Y_dev: device, n x 2 floats, OVERWRITTEN;
+ *   both owned by the caller, on the network's device; hip_stream: a hipStream_t there (NULL = null
+ *   stream). Stream-ordered and asynchronous; the same kernels, in the same order, as
+ *   bcv_mlp_forward, so the outputs are identical.
+ * The hidden activations live in a fixed workspace the library holds in a static device array
+ * (12 MiB per GPU it runs on, kept until the process ends): n x width must not exceed 2^20
+ * (n <= 8192 at width 128), else BCV_EINVAL. Every call on one GPU shares that GPU's workspace
+ * (the first call on a device looks its address up): calls that overlap in time on one GPU race
+ * and give wrong results; serialise them (one stream, or events). n = 0 does nothing.
+ * Errors: BCV_EINVAL (NULL pointers with n > 0, n too large), BCV_ESTATE (bad handle), BCV_EDEVICE. */
+bcv_status bcv_mlp_forward_noalloc(bcv_mlp mlp, int64_t n, const float *X_dev, float *Y_dev, void *hip_stream);
 /* Training loss of the batch (X [n x 6], targets r [n]) and its gradient with respect to every
  * parameter (host arrays; grad has bcv_mlp_num_params floats), with the GPU kernels:
  *   loss = mean (y0 - r)^2 + 0.1 mean (y1 - log(|y0 - r| + 1e-5))^2, the second term with y0 fixed. */

@@ -104,6 +104,7 @@ def lib():
         L.bcv_mlp_get_params.argtypes = [vp, fp]
         L.bcv_mlp_set_params.argtypes = [vp, fp]
         L.bcv_mlp_forward.argtypes = [vp, ctypes.c_int64, fp, fp]
+        L.bcv_mlp_forward_noalloc.argtypes = [vp, ctypes.c_int64, vp, vp, vp]
         L.bcv_mlp_loss_grad.argtypes = [vp, ctypes.c_int64, fp, fp, dp, fp]
         L.bcv_mlp_train.argtypes = [vp, ctypes.POINTER(TrainOpts), ctypes.POINTER(TrainReport)]
         L.bcv_surrogate_eval.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(TouchPair), ctypes.c_double, dp, dp,
@@ -123,7 +124,8 @@ def lib():
                      "bcv_plan_get_info", "bcv_vtv_apply", "bcv_vtv_apply_parts", "bcv_vtb_apply", "bcv_btv_apply",
                      "bcv_touching_integrals", "bcv_plan_enable_timing", "bcv_plan_phase_times",
                      "bcv_box_pair_integrals", "bcv_touch_pair_quadrature", "bcv_mlp_create", "bcv_mlp_num_params",
-                     "bcv_mlp_get_params", "bcv_mlp_set_params", "bcv_mlp_forward", "bcv_mlp_loss_grad",
+                     "bcv_mlp_get_params", "bcv_mlp_set_params", "bcv_mlp_forward", "bcv_mlp_forward_noalloc",
+                     "bcv_mlp_loss_grad",
                      "bcv_mlp_train", "bcv_surrogate_eval", "bcv_mlp_save", "bcv_mlp_load", "bcv_build_bc_forest",
                      "bcv_tree_leaf_mesh", "bcv_vtv_graph_create", "bcv_graph_launch", "bcv_autotune"):
             getattr(L, name).restype = ctypes.c_int
@@ -377,6 +379,21 @@ class MLP:
         Y = np.empty((len(X), 2), dtype=np.float32)
         _check(lib().bcv_mlp_forward(self._h, len(X), _fp(X), _fp(Y)))
         return Y
+
+    def forward_noalloc(self, X, Y, stream=None):
+        """Y <- network(X) on device tensors (X: contiguous float32 CUDA [n, 6], Y: [n, 2]) with the
+        library's fixed workspace: no allocation, stream-ordered (bcv_mlp_forward_noalloc)."""
+        import torch
+
+        for name, t, cols in (("X", X, 6), ("Y", Y, 2)):
+            if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+                    and t.dim() == 2 and t.shape[1] == cols and t.device.index == self.device):
+                raise ValueError("%s must be a contiguous float32 CUDA tensor [n, %d] on cuda:%d"
+                                 % (name, cols, self.device))
+        if X.shape[0] != Y.shape[0]:
+            raise ValueError("X and Y must have the same number of rows")
+        _check(lib().bcv_mlp_forward_noalloc(self._h, X.shape[0], ctypes.c_void_p(X.data_ptr()),
+                                             ctypes.c_void_p(Y.data_ptr()), _stream(stream, self.device)))
 
     def loss_grad(self, X, r):
         X = np.ascontiguousarray(X, dtype=np.float32).reshape(-1, 6)

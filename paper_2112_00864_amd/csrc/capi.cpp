@@ -395,6 +395,15 @@ bcv_status bcv_mlp_forward(bcv_mlp mlp, int64_t n, const float *X, float *Y)
     });
 }
 
+bcv_status bcv_mlp_forward_noalloc(bcv_mlp mlp, int64_t n, const float *X_dev, float *Y_dev, void *hip_stream)
+{
+    return guard([&] {
+        check_mlp(mlp);
+        BCV_REQUIRE(n >= 0 && (n == 0 || (X_dev != nullptr && Y_dev != nullptr)), BCV_EINVAL, "bad arguments");
+        on_device(mlp->device, [&] { bcv::mlp_forward_noalloc(*mlp, n, X_dev, Y_dev, (hipStream_t)hip_stream); });
+    });
+}
+
 bcv_status bcv_mlp_loss_grad(bcv_mlp mlp, int64_t n, const float *X, const float *r, double *loss, float *grad)
 {
     return guard([&] {

@@ -106,6 +106,7 @@ void mlp_destroy(bcv_mlp_s *net);
 void mlp_get_params(const bcv_mlp_s &net, float *host);
 void mlp_set_params(bcv_mlp_s &net, const float *host);
 void mlp_forward_host(const bcv_mlp_s &net, int64_t n, const float *X, float *Y);
+void mlp_forward_noalloc(const bcv_mlp_s &net, int64_t n, const float *X, float *Y, hipStream_t st);
 double mlp_loss_grad_host(const bcv_mlp_s &net, int64_t n, const float *X, const float *r, float *grad);
 void mlp_train(bcv_mlp_s &net, const bcv_mlp_train_opts &o, bcv_mlp_train_report *rep);
 void surrogate_eval(const bcv_mlp_s &net, int64_t n, const bcv_touch_pair *pairs, double tol, double *value,

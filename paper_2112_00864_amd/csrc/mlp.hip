@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
+#include <string>
 
 #include "common.hpp"
 #include "mlp.hpp"
@@ -215,6 +217,34 @@ void adam_step(int64_t n, float *p, const float *g, float *m, float *v, float lr
 {
     adam_kernel<<<grid_for(n), 256, 0, st>>>(n, p, g, m, v, lr_t, b1, b2, eps);
     BCV_HIP(hipGetLastError());
+}
+
+// ---- fixed inference workspace (bcv_mlp_forward_noalloc) ---------------------------------------
+// Three activation buffers of kNoAllocFloats floats each, in one statically allocated device array
+// that every GPU the library runs on holds until the process ends. Its device address is looked up
+// once per device, with that device current, and only that address is used from the host: the
+// array's name is a host-side stand-in, not a device address.
+static __device__ __align__(256) float scratch[3 * kNoAllocFloats];
+
+float *noalloc_workspace(int device)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static float *ptr[kMaxDevices] = {};
+    BCV_REQUIRE(device >= 0 && device < kMaxDevices, BCV_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lock(mu);
+    if (ptr[device] == nullptr) {
+        int prev = 0;
+        BCV_HIP(hipGetDevice(&prev));
+        BCV_HIP(hipSetDevice(device));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        BCV_HIP(hipSetDevice(prev));
+        if (e != hipSuccess) fail(BCV_EDEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+        BCV_REQUIRE(p != nullptr, BCV_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        ptr[device] = static_cast<float *>(p);
+    }
+    return ptr[device];
 }
 
 void gather_rows(int B, int d, const int32_t *idx, const float *in, float *out, hipStream_t st)

@@ -33,6 +33,12 @@ void loss_grad(int B, const float *Y, const float *r, float w_err, float eps, fl
 void adam_step(int64_t n, float *p, const float *g, float *m, float *v, float lr_t, float b1, float b2, float eps,
                hipStream_t st);
 
+// Device address, on `device`, of the library's fixed inference workspace: 3 * kNoAllocFloats
+// floats (three activation buffers of rows x width <= kNoAllocFloats), looked up on the first call
+// per device (sets and restores the current device; no allocation).
+constexpr int64_t kNoAllocFloats = int64_t(1) << 20;
+float *noalloc_workspace(int device);
+
 // out[i] = in[idx[i]] for B rows of width d.
 void gather_rows(int B, int d, const int32_t *idx, const float *in, float *out, hipStream_t st);
 

@@ -250,6 +250,22 @@ void mlp_forward_host(const bcv_mlp_s &net, int64_t n, const float *X, float *Y)
     BCV_HIP(hipMemcpy(Y, w.Y.p, (size_t)n * kMlpOut * sizeof(float), hipMemcpyDeviceToHost));
 }
 
+void mlp_forward_noalloc(const bcv_mlp_s &net, int64_t n, const float *X, float *Y, hipStream_t st)
+{
+    BCV_REQUIRE(n >= 0 && n * net.width <= kNoAllocFloats, BCV_EINVAL,
+                "batch too large for the fixed workspace: rows x width must not exceed 2^20");
+    if (n == 0) return;
+    float *ws = noalloc_workspace(net.device);
+    float *Z = ws, *H1 = ws + kNoAllocFloats, *H2 = ws + 2 * kNoAllocFloats;
+    const Layout l = layout(net.d_in, net.width);
+    const float *P = net.d_params;
+    const int W = net.width, B = (int)n;
+    // the layers of forward(), with both pre-activations in one buffer (inference never reads them)
+    gemm(false, false, B, W, net.d_in, X, net.d_in, P + l.w1, W, P + l.b1, false, Z, W, H1, st);
+    gemm(false, false, B, W, W, H1, W, P + l.w2, W, P + l.b2, false, Z, W, H2, st);
+    gemm(false, false, B, kMlpOut, W, H2, W, P + l.w3, kMlpOut, P + l.b3, false, Y, kMlpOut, nullptr, st);
+}
+
 double mlp_loss_grad_host(const bcv_mlp_s &net, int64_t n, const float *X, const float *r, float *grad)
 {
     BCV_REQUIRE(n > 0 && n <= INT32_MAX, BCV_EINVAL, "batch size must be 1..2^31-1");
