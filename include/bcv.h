@@ -74,13 +74,19 @@ enum { BCV_NEAR_QUADRATURE = 0, BCV_NEAR_ASSEMBLED = 1 };
  *   kernel values in FP32 (per-axis differences formed in FP64), or, assembled, are stored in FP32;
  *   the touching (singular) pairs, the moments, the upward and downward passes, the evaluation and
  *   the final accumulation of u stay in FP64. */
-enum { BCV_FP64 = 0, BCV_MIXED_F32 = 1 };
+/* BCV_MIXED_SPLIT16: as BCV_MIXED_F32, but the VtV apply's interaction phase runs on the matrix
+ *   cores (MFMA): every FP32 operand is split into two FP16 numbers (hi + lo), the three products
+ *   hi*hi + hi*lo + lo*hi are accumulated in FP32 (about 22 significant bits per operand). The folded
+ *   moments are scaled by the cell volume and by the power of two at or above max |f| before the split.
+ *   Fixed q = 6 only (q_schedule = 0); BtV and VtB applies of such a plan run their interaction
+ *   phase as BCV_MIXED_F32 does. */
+enum { BCV_FP64 = 0, BCV_MIXED_F32 = 1, BCV_MIXED_SPLIT16 = 2 };
 
 /* Plan options. */
 typedef struct {
     double eta0;   /* separation parameter of the neighbour test (eq. def:neighbors); must be 0.5 */
     int q;         /* expansion order, |alpha| + |beta| <= q (Sec. 3); supported: 4, 6, 8 */
-    int precision; /* BCV_FP64 or BCV_MIXED_F32 */
+    int precision; /* BCV_FP64, BCV_MIXED_F32 or BCV_MIXED_SPLIT16 */
     int direct;    /* 1: every leaf pair is treated as near (no far field; small meshes only) */
     int nearfield; /* BCV_NEAR_QUADRATURE: the apply evaluates every near-pair entry on the fly;
                       BCV_NEAR_ASSEMBLED: the plan stores every near-pair entry once (computed in

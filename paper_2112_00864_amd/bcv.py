@@ -15,7 +15,7 @@ _lib = None
 OK, EINVAL, ENOMEM, EDEVICE, ENOTSUP, ESTATE = range(6)
 NEAR_QUADRATURE, NEAR_ASSEMBLED = 0, 1
 MARK_FACE, MARK_NEIGHBOR = 0, 1
-FP64, MIXED_F32 = 0, 1
+FP64, MIXED_F32, MIXED_SPLIT16 = 0, 1, 2
 PART_NEAR, PART_FAR = 1, 2
 TOUCH_CLASSES = ("self", "face", "edge", "vertex", "face2", "edge2", "vertex2")
 

@@ -67,8 +67,8 @@ void check_plan_opts(const bcv_plan_opts &o, int device)
 {
     BCV_REQUIRE(o.eta0 == 0.5, BCV_EINVAL, "eta0 must be 0.5");
     BCV_REQUIRE(o.q == 4 || o.q == 6 || o.q == 8, BCV_EINVAL, "q must be 4, 6 or 8");
-    BCV_REQUIRE(o.precision == BCV_FP64 || o.precision == BCV_MIXED_F32, BCV_EINVAL,
-                "precision must be BCV_FP64 or BCV_MIXED_F32");
+    BCV_REQUIRE(o.precision == BCV_FP64 || o.precision == BCV_MIXED_F32 || o.precision == BCV_MIXED_SPLIT16,
+                BCV_EINVAL, "precision must be BCV_FP64, BCV_MIXED_F32 or BCV_MIXED_SPLIT16");
     BCV_REQUIRE(o.direct == 0 || o.direct == 1, BCV_EINVAL, "direct must be 0 or 1");
     BCV_REQUIRE(o.nearfield == BCV_NEAR_QUADRATURE || o.nearfield == BCV_NEAR_ASSEMBLED, BCV_EINVAL,
                 "unknown nearfield mode");

@@ -159,6 +159,7 @@ struct bcv_plan_s {
     // q_schedule: the tasks of level l are [level_xcd[l][0], level_xcd[l][kXcds]), cut into XCD
     // ranges like xcd_begin, and launched level by level
     int32_t level_xcd[bcv::kMaxLevel + 1][bcv::kXcds + 1] = {};
+    int32_t lvl_start[bcv::kMaxLevel + 2] = {};  // first cell of each level (cells are numbered level by level)
 
     // Device buffers (owned).
     double *d_leaf_geom = nullptr;  // 4 per leaf: lower corner x, y, z and side
@@ -182,6 +183,11 @@ struct bcv_plan_s {
     int32_t *d_task_targets = nullptr;  // 64 per task, -1 = idle lane
     int32_t *d_slot_off = nullptr;      // offset id per slot | (the slot gathers) << 31
     uint32_t *d_slot_src = nullptr;     // 64 per slot: source row (n_cells: none) | (in the lane's list) << 31
+    uint64_t *d_slot_mask = nullptr;    // BCV_MIXED_SPLIT16: per slot, bit t = the offset is in target t's list
+    uint32_t *d_m2l_A = nullptr;        // BCV_MIXED_SPLIT16: per offset, the matrix-core A operands (see kernels.hip)
+    float *d_G48 = nullptr;             // BCV_MIXED_SPLIT16: per offset, the one entry handled off the matrix cores
+    uint16_t *d_M16 = nullptr;          // BCV_MIXED_SPLIT16: folded moments as FP16 hi/lo rows, (n_cells + 1) x 128
+    float *d_fscale = nullptr;          // BCV_MIXED_SPLIT16: partial maxima of |f| (256) and the scale (1)
     bcv::M2LSplit *d_m2l_splits = nullptr;
     double *d_m2l_partial = nullptr;    // 64 x K per piece of a split task
 

@@ -830,6 +830,243 @@ __global__ __launch_bounds__(256) void m2l_combine_kernel(const M2LSplit *__rest
     Lam[(int64_t)t * lo.ldk + a] = s;
 }
 
+// ---- interaction phase on the matrix cores (BCV_MIXED_SPLIT16, q = 6) ------------------------------
+// For one slot (one offset o_k shared by the task's 64 targets) the reduced interaction is a matrix
+// product
+//     Lr[a][t] += sum_b T_k[a][b] Mr[b][src(t)],   T_k[a][b] = 4 pi G_{a+b}(o_k) where |a| + |b| <= 6,
+// over the 49 reduced multi-indices a, b (degree-major: the (d + 1)^2 of degree <= d come first). It
+// runs as v_mfma_f32_16x16x32_f16: the 64 targets form four column sets of 16 (target t = 4n + T is
+// column n of set T), b is cut into two K-chunks (b < 32 and 32 <= b < 64, zero beyond 48) and a into
+// row blocks of 16. The degree truncation leaves four nonzero tiles (row block, chunk) = (0, 0), (0, 1),
+// (1, 0), (2, 0); row a = 48 (degree 6) meets b = 0 only and runs on the vector units.
+// Precision: every FP32 operand x is split into hi = fp16(x) and lo = fp16(x - hi), and the products
+// hi*hi, hi*lo and lo*hi accumulate in FP32 (the lo*lo term, about 2^-22 relative, is dropped).
+// Lane layout of the instruction: A[i][k] in lane i + 16 (k / 8), element k % 8; B[k][n] in lane
+// n + 16 (k / 8), element k % 8; D[i][n] in lane n + 16 (i / 4), element i % 4.
+// Source rows: a cell's folded moments times 2^(3 level) / S (S the power of two at or above max |f|,
+// so every value is at most a few units), as FP16 hi[64] then lo[64] (kSplitRowHalves). Lane
+// (n, g = lane / 16) of set T holds the g-th 8 values of both chunks of target 4n + T's source, hi and
+// lo: four 16-byte words.
+// Shifts: at a shifting slot target t takes target t - 1's previous source (the lane-shift kernel's
+// relation). With t = 4n + T that is set T - 1 -> set T for T >= 1, the same lanes (a renaming of
+// register sets), and set 3 -> set 0 one column up (DPP row_shr:1 inside each 16-lane row); column 0
+// of set 0 is target 0, always a head lane, which reads its row. The renaming rotates four register
+// sets and is unrolled over four slots: at slot j logical set T is buffer (T - j) mod 4.
+typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kSplitTiles = 4;
+constexpr int kTileBlock[kSplitTiles] = {0, 0, 1, 2};   // row block of each tile
+constexpr int kTileChunk[kSplitTiles] = {0, 1, 0, 0};   // K-chunk of each tile
+constexpr int kTileGroups[kSplitTiles] = {4, 3, 2, 1};  // k-groups of 8 that hold nonzero entries
+
+struct SrcPart {  // this lane's 8 values of both chunks, hi and lo
+    u4_t h0, h1, l0, l1;
+};
+
+__device__ __forceinline__ uint32_t row_shr1(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x111, 0xf, 0xf, false);
+}
+__device__ __forceinline__ u4_t row_shr1(u4_t v)
+{
+    return u4_t{row_shr1(v.x), row_shr1(v.y), row_shr1(v.z), row_shr1(v.w)};
+}
+__device__ __forceinline__ SrcPart row_shr1(const SrcPart &s)
+{
+    return SrcPart{row_shr1(s.h0), row_shr1(s.h1), row_shr1(s.l0), row_shr1(s.l1)};
+}
+__device__ __forceinline__ SrcPart load_src(const u4_t *__restrict__ rows, uint32_t row, int g)
+{
+    const u4_t *r = rows + (size_t)row * (kSplitRowHalves / 8);
+    return SrcPart{r[g], r[4 + g], r[8 + g], r[12 + g]};
+}
+__device__ __forceinline__ h8_t as_h8(u4_t v) { return __builtin_bit_cast(h8_t, v); }
+__device__ __forceinline__ f4_t mfma3(u4_t ah, u4_t al, u4_t bh, u4_t bl, f4_t c)
+{
+    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_h8(ah), as_h8(bh), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_h8(ah), as_h8(bl), c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(as_h8(al), as_h8(bh), c, 0, 0, 0);
+}
+
+// Partial maxima of |f|: block b writes the maximum over its grid-stride share (kFscaleParts blocks).
+__global__ __launch_bounds__(256) void fmax_partial_kernel(int64_t n, const double *__restrict__ f,
+                                                           float *__restrict__ part)
+{
+    __shared__ float sm[256];
+    float m = 0.0f;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        m = fmaxf(m, (float)fabs(f[i]));
+    sm[threadIdx.x] = m;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) sm[threadIdx.x] = fmaxf(sm[threadIdx.x], sm[threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+struct LevelStarts {
+    int32_t s[kMaxLevel + 2];
+    int32_t L;
+};
+
+// FP16 hi/lo rows from the FP32 folded rows: row c of level l gets Mr * 2^(3 l) / S, S = the power of two
+// at or above max |f| (from the partial maxima; 1 for f = 0), which block 0 also stores after them.
+// One thread per (row, j < 64); entries j >= ldr are zero.
+__global__ __launch_bounds__(256) void split_rows_kernel(int64_t n_rows, const float *__restrict__ rows32,
+                                                         int32_t ldr, uint16_t *__restrict__ rows16,
+                                                         float *__restrict__ fscale, const LevelStarts ls)
+{
+    __shared__ float sm[kFscaleParts];
+    sm[threadIdx.x] = fscale[threadIdx.x];
+    __syncthreads();
+    for (int h = kFscaleParts / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) sm[threadIdx.x] = fmaxf(sm[threadIdx.x], sm[threadIdx.x + h]);
+        __syncthreads();
+    }
+    int e = 0;
+    (void)frexpf(sm[0], &e);  // sm[0] = m 2^e, 1/2 <= m < 1
+    const float S = sm[0] > 0.0f ? ldexpf(1.0f, e) : 1.0f;
+    if (blockIdx.x == 0 && threadIdx.x == 0) fscale[kFscaleParts] = S;
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t row = idx >> 6;
+    const int j = (int)(idx & 63);
+    if (row >= n_rows) return;
+    int lev = 0;
+    while (lev < ls.L && row >= ls.s[lev + 1]) ++lev;
+    const float v = j < ldr ? rows32[row * ldr + j] * ldexpf(1.0f / S, 3 * lev) : 0.0f;
+    const _Float16 hi = (_Float16)v;
+    const _Float16 lo = (_Float16)(v - (float)hi);
+    rows16[row * kSplitRowHalves + j] = __builtin_bit_cast(uint16_t, hi);
+    rows16[row * kSplitRowHalves + 64 + j] = __builtin_bit_cast(uint16_t, lo);
+}
+
+template <int Q>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2, 2))) void m2l_mfma_kernel(
+    XcdRanges ranges, const M2LTask *__restrict__ tasks, const int32_t *__restrict__ targets,
+    const int32_t *__restrict__ slot_off, const uint32_t *__restrict__ slot_src, const uint64_t *__restrict__ slot_mask,
+    const u4_t *__restrict__ Atab, const float *__restrict__ G48, const u4_t *__restrict__ rows,
+    const float *__restrict__ fscale, double *__restrict__ partial, double *__restrict__ Lam, int32_t ldk)
+{
+    static_assert(Q == 6, "the tile set is that of q = 6");
+    constexpr int R = nreduced(Q), FA1 = ncoef(Q);
+    __shared__ float tr[R][kWave + 1];
+    const int ti = xcd_task(ranges);
+    if (ti < 0) return;
+    const M2LTask task = tasks[ti];
+    const int lane = threadIdx.x, n = lane & 15, g = lane >> 4;
+    const int32_t my_target = targets[(int64_t)ti * kWave + lane];
+    const uint64_t idle = __ballot(my_target < 0);                          // targets without a cell
+    const uint32_t heads4 = (uint32_t)((task.heads >> (4 * n)) & 0xFull);   // bit T: target 4n + T is a head
+    const int nsl = task.n_slots;
+    const int64_t s0 = task.slot_begin;
+    f4_t acc[3][4];
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int T = 0; T < 4; ++T) acc[b][T] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
+    float acc48[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    SrcPart buf[4];
+    const u4_t zero4 = u4_t{0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int T = 0; T < 4; ++T) buf[T] = SrcPart{zero4, zero4, zero4, zero4};
+
+    // The slot loop runs in groups of four (the rotation period); slots past the end of the list
+    // are idle (zero operands, nothing read), so that every group has the same straight-line code.
+    // A operands: a lane's k-groups beyond kTileGroups hold zeros for every offset, so those
+    // registers are cleared once and never loaded. The slot words (offset, mask, the four source
+    // words of the lane's targets) are read one slot ahead.
+    u4_t ah[kSplitTiles], al[kSplitTiles];
+#pragma unroll
+    for (int tl = 0; tl < kSplitTiles; ++tl) ah[tl] = al[tl] = zero4;
+    struct SlotWords {
+        int32_t ow;
+        uint64_t mk;
+        u4_t w;
+    };
+    auto load_words = [&](int j) {
+        SlotWords sw{0, 0ull, zero4};
+        if (j < nsl) {
+            const int64_t sl = s0 + j;
+            sw.ow = slot_off[sl];
+            sw.mk = slot_mask[sl];
+            if (sw.ow < 0 || heads4) sw.w = *reinterpret_cast<const u4_t *>(slot_src + sl * kWave + 4 * n);
+        }
+        return sw;
+    };
+    auto body = [&](int j, auto rot_c, const SlotWords &sw) {
+        constexpr int ROT = decltype(rot_c)::value;  // logical set T is buf[(T + ROT) & 3]
+        const bool live = j < nsl;
+        const int off = sw.ow & 0x7FFFFFFF;
+#pragma unroll
+        for (int tl = 0; tl < kSplitTiles; ++tl)
+            if (live && g < kTileGroups[tl]) {
+                const u4_t *p = Atab + ((int64_t)(off * kSplitTiles + tl) * 2) * kWave + lane;
+                ah[tl] = p[0];
+                al[tl] = p[kWave];
+            }
+        const float g48 = live ? G48[off] : 0.0f;
+        const bool gather = live && sw.ow < 0;  // the plan sets the gather bit on every piece's first slot
+        if (!gather) buf[ROT] = row_shr1(buf[ROT]);  // old set 3 -> new set 0, one column up
+        const uint32_t need = gather ? 0xFu : (live ? heads4 : 0u);
+#pragma unroll
+        for (int T = 0; T < 4; ++T)
+            if ((need >> T) & 1u) buf[(T + ROT) & 3] = load_src(rows, sw.w[T] & 0x7FFFFFFFu, g);
+        // targets whose list lacks the offset take a zero column (a full slot keeps every column;
+        // an idle slot none)
+        const uint32_t mbits = live ? ((uint32_t)((sw.mk >> (4 * n)) & 0xFull) | ((sw.mk | idle) == ~0ull ? 0xFu : 0u))
+                                    : 0u;
+#pragma unroll
+        for (int T = 0; T < 4; ++T) {
+            const uint32_t keep = 0u - ((mbits >> T) & 1u);
+            const SrcPart &v = buf[(T + ROT) & 3];
+            const SrcPart x{v.h0 & keep, v.h1 & keep, v.l0 & keep, v.l1 & keep};
+            acc[0][T] = mfma3(ah[0], al[0], x.h0, x.l0, acc[0][T]);
+            acc[1][T] = mfma3(ah[2], al[2], x.h0, x.l0, acc[1][T]);
+            acc[2][T] = mfma3(ah[3], al[3], x.h0, x.l0, acc[2][T]);
+            acc[0][T] = mfma3(ah[1], al[1], x.h1, x.l1, acc[0][T]);
+            const h8_t bh = as_h8(x.h0), bl = as_h8(x.l0);
+            acc48[T] = fmaf(g48, (float)bh[0] + (float)bl[0], acc48[T]);
+        }
+    };
+    SlotWords w0 = load_words(0), w1;
+    for (int j = 0; j < nsl; j += 4) {
+        w1 = load_words(j + 1);
+        body(j, std::integral_constant<int, 0>{}, w0);
+        w0 = load_words(j + 2);
+        body(j + 1, std::integral_constant<int, 3>{}, w1);
+        w1 = load_words(j + 3);
+        body(j + 2, std::integral_constant<int, 2>{}, w0);
+        w0 = load_words(j + 4);
+        body(j + 3, std::integral_constant<int, 1>{}, w1);
+    }
+    // transpose through LDS: tr[a][t], then lane t expands its 49 reduced coefficients
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int T = 0; T < 4; ++T)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) tr[16 * b + 4 * g + e][4 * n + T] = acc[b][T][e];
+    if (g == 0)
+#pragma unroll
+        for (int T = 0; T < 4; ++T) tr[R - 1][4 * n + T] = acc48[T];
+    __syncthreads();
+    float lr[R];
+#pragma unroll
+    for (int a = 0; a < R; ++a) lr[a] = tr[a][lane];
+    if (my_target < 0) return;
+    // Lambda = a^-1 (S 2^(-3 level) / (4 pi)) lr with a = 2^-level
+    const double scale = (double)fscale[kFscaleParts] * ldexp(kInv4Pi, -2 * task.level);
+    if (task.out < 0)
+        store_expanded<Q, 0, 0, false>(lr, scale, Lam + (int64_t)my_target * ldk, 1,
+                                       std::make_integer_sequence<int, FA1>{});
+    else
+        store_expanded<Q, 0, 0, false>(lr, scale, partial + (int64_t)task.out * ldk * kWave + lane, kWave,
+                                       std::make_integer_sequence<int, FA1>{});
+}
+
 // ---- near field + evaluation: one wave per work unit --------------------------------------------
 // Row t of the near CSR holds the touching pairs in [row[t], split[t]) and the point-rule pairs in
 // [split[t], row[t+1]); a unit covers a range of one row. Touching pairs cost one FMA; the
@@ -1376,7 +1613,7 @@ void launch_near_q(const bcv_plan_s &p, const double *f, const double *lam, int 
     const LevelOrders lo = level_orders(p);
     const unsigned blocks = (unsigned)((p.n_units + 3) / 4);
     const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
-    const bool mixed = p.precision == BCV_MIXED_F32;
+    const bool mixed = p.precision != BCV_FP64;
     if (p.nearfield == BCV_NEAR_ASSEMBLED && mixed)
         near_eval_kernel<Q, true, true><<<blocks, 256, 0, st>>>(p.n_units, p.d_units, p.d_split, p.d_col, nullptr,
                                                                 p.d_val32, geom, f, lam, p.d_leaf_cell,
@@ -1456,6 +1693,25 @@ void launch_m2l(const bcv_plan_s &p, const float *G, const float *Mr, hipStream_
         launch_m2l_block<Q, 0, R, 0, 16>(p, ranges, G, Mr, st);    // all a, |b| <= 3
         launch_m2l_block<Q, 0, 25, 16, R>(p, ranges, G, Mr, st);   // |a| <= 4, |b| >= 4
     }
+}
+
+// Interaction phase on the matrix cores (BCV_MIXED_SPLIT16): FP16 hi/lo rows from the FP32 folded
+// rows (which P2M and M2M wrote), then one launch over all tasks.
+void launch_m2l_split16(const bcv_plan_s &p, hipStream_t st)
+{
+    LevelStarts ls{};
+    for (int l = 0; l <= kMaxLevel + 1; ++l) ls.s[l] = p.lvl_start[l];
+    ls.L = p.L;
+    split_rows_kernel<<<(unsigned)((p.n_cells * 64 + 255) / 256), 256, 0, st>>>(p.n_cells, p.d_M32, p.R, p.d_M16,
+                                                                                p.d_fscale, ls);
+    check_launch();
+    XcdRanges ranges;
+    for (int x = 0; x <= kXcds; ++x) ranges.begin[x] = p.xcd_begin[x];
+    m2l_mfma_kernel<6><<<(unsigned)p.m2l_groups, kWave, 0, st>>>(
+        ranges, p.d_tasks, p.d_task_targets, p.d_slot_off, p.d_slot_src, p.d_slot_mask,
+        reinterpret_cast<const u4_t *>(p.d_m2l_A), p.d_G48, reinterpret_cast<const u4_t *>(p.d_M16), p.d_fscale,
+        p.d_m2l_partial, p.d_Lam, p.K);
+    check_launch();
 }
 
 // Upward pass (M2M, l = L-1 .. 2; moments below level 2 are never used), interaction phase (M2L
@@ -1562,7 +1818,7 @@ void launch_p2m(const bcv_plan_s &p, const double *f, hipStream_t st, bool fused
     const unsigned blocks = (unsigned)((p.n_leaves * (int64_t)p.R + 255) / 256);
     const LevelOrders lo = level_orders(p);
     constexpr int QT = Q > kMaxSchedQ ? Q : kMaxSchedQ;  // tables large enough for every level's order
-    if (p.precision == BCV_MIXED_F32) {
+    if (p.precision != BCV_FP64) {
         if (p.q_schedule)
             p2m_kernel<QT, float><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, f, p.d_M, p.d_M32, lo,
                                                           skip);
@@ -1591,7 +1847,7 @@ void upward_pass(const bcv_plan_s &p, hipStream_t st, const double *f_fused = nu
             const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
             const unsigned blocks = (unsigned)((n_par + 3) / 4);
             const int32_t *par = p.d_parents + 2 * p.parent_begin[lev];
-            if (p.precision == BCV_MIXED_F32)
+            if (p.precision != BCV_FP64)
                 m2m_leaves_kernel<Q, float><<<blocks, 256, 0, st>>>(n_par, par, p.d_cell_leaf, geom, f_fused, p.d_M,
                                                                     p.d_M32, p.K, p.R);
             else
@@ -1603,7 +1859,7 @@ void upward_pass(const bcv_plan_s &p, hipStream_t st, const double *f_fused = nu
         auto run = [&](auto qc) {
             constexpr int QP = decltype(qc)::value;  // the parents' order
             const unsigned blocks = (unsigned)((n_par + tree_waves<QP>() - 1) / tree_waves<QP>());
-            if (p.precision == BCV_MIXED_F32)
+            if (p.precision != BCV_FP64)
                 m2m_kernel<QP, float><<<blocks, kWave * tree_waves<QP>(), 0, st>>>(
                     n_par, p.d_parents + 2 * p.parent_begin[lev], p.d_M, p.d_M32, p.K, p.R);
             else
@@ -1618,13 +1874,20 @@ void upward_pass(const bcv_plan_s &p, hipStream_t st, const double *f_fused = nu
     }
 }
 
+// matrix_cores: the VtV apply of a BCV_MIXED_SPLIT16 plan (which ran fmax_partial_kernel over f);
+// the BtV and VtB applies of such a plan take the FP32 lane-shift kernels.
 template <int Q>
-void interaction_phase(const bcv_plan_s &p, hipStream_t st)
+void interaction_phase(const bcv_plan_s &p, hipStream_t st, bool matrix_cores = false)
 {
     if (p.n_tasks == 0) return;
     // the folded moment rows were written with the moments (P2M, boundary P2M, M2M)
-    const bool mixed = p.precision == BCV_MIXED_F32;
-    if (p.q_schedule) {
+    const bool mixed = p.precision != BCV_FP64;
+    if (matrix_cores && p.precision == BCV_MIXED_SPLIT16) {
+        if constexpr (Q == 6)
+            launch_m2l_split16(p, st);
+        else
+            fail(BCV_ENOTSUP, "BCV_MIXED_SPLIT16 supports q = 6 only");
+    } else if (p.q_schedule) {
         for (int lev = p.L; lev >= 2; --lev)
             with_order(p.q_level[lev], [&](auto qc) {
                 constexpr int QL = decltype(qc)::value;
@@ -1677,8 +1940,13 @@ void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStre
     // fixed orders, and parents on level L - 1 (whose children are all leaves of level L)
     const bool fuse_last = fork && !p.q_schedule && p.L - 1 >= 2 && p.parent_begin[p.L] > p.parent_begin[p.L - 1];
     PhaseMarks marks(p);
+    const bool split16 = far && p.precision == BCV_MIXED_SPLIT16;
     if (far) {
         marks.start(BCV_PHASE_P2M, st);
+        if (split16) {  // the scale of the FP16 moment rows
+            fmax_partial_kernel<<<kFscaleParts, 256, 0, st>>>(p.n_leaves, f, p.d_fscale);
+            check_launch();
+        }
         launch_p2m<Q>(p, f, st, true);
         marks.stop(BCV_PHASE_P2M, st);
         marks.start(BCV_PHASE_M2M, st);
@@ -1696,7 +1964,7 @@ void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStre
             BCV_HIP(hipEventRecord(p.ev_join, p.side));
         }
         marks.start(BCV_PHASE_M2L, st);
-        interaction_phase<Q>(p, st);
+        interaction_phase<Q>(p, st, split16);
         marks.stop(BCV_PHASE_M2L, st);
         marks.start(BCV_PHASE_L2L, st);
         downward_pass<Q>(p, st, fork && fuse_last);
@@ -1744,7 +2012,7 @@ void btv_q(const bcv_plan_s &p, const double *qf, const double *gf, double *u, h
     const bool far = !p.direct;
     if (far) {
         const unsigned blocks = (unsigned)((p.n_leaves + 3) / 4);
-        if (p.precision == BCV_MIXED_F32)
+        if (p.precision != BCV_FP64)
             btv_p2m_kernel<Q, float><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, p.d_leaf_faces,
                                                              p.d_faces, qf, gf, p.d_M, p.d_M32);
         else
@@ -1757,7 +2025,7 @@ void btv_q(const bcv_plan_s &p, const double *qf, const double *gf, double *u, h
     }
     const double *lam = far ? p.d_Lam : nullptr;
     const unsigned blocks = (unsigned)((p.n_btv_units + 3) / 4);
-    if (p.precision == BCV_MIXED_F32)
+    if (p.precision != BCV_FP64)
         btv_near_kernel<Q, true><<<blocks, 256, 0, st>>>(p.n_btv_units, p.d_btv_units, p.d_btv_col, p.d_faces, geom, qf,
                                                          gf, p.d_btv_touch, lam, p.d_leaf_cell, p.d_btv_partial, u);
     else
@@ -1789,7 +2057,7 @@ void vtb_q(const bcv_plan_s &p, const double *f, double *uf, hipStream_t st)
     }
     const double *lam = far ? p.d_Lam : nullptr;
     const unsigned blocks = (unsigned)((p.n_vtb_units + 3) / 4);
-    if (p.precision == BCV_MIXED_F32)
+    if (p.precision != BCV_FP64)
         vtb_near_kernel<Q, true><<<blocks, 256, 0, st>>>(p.n_vtb_units, p.d_vtb_units, p.d_vtb_col, p.d_faces, geom, f,
                                                          p.d_btv_touch, lam, p.d_leaf_cell, p.d_vtb_partial, uf);
     else
@@ -1894,6 +2162,34 @@ void launch_near_assemble_ordered(const bcv_plan_s &p, const std::vector<int64_t
         d_gw.d, p.d_val);
     check_launch();
     BCV_HIP(hipDeviceSynchronize());  // before the temporaries are freed
+}
+
+void split16_tables(int K, const std::vector<double> &G, int n_off, std::vector<uint16_t> &A, std::vector<float> &G48)
+{
+    constexpr int Q = 6, R = nreduced(Q);
+    constexpr ReducedIndex<Q> ri{};
+    if (K < ncoef(Q) || (int64_t)G.size() < (int64_t)n_off * K) fail(BCV_ESTATE, "internal: derivative tables too small");
+    A.assign((size_t)n_off * kSplitTiles * 2 * kWave * 8, 0);
+    G48.assign((size_t)std::max(n_off, 1), 0.0f);
+    const double four_pi = 4.0 * M_PI;
+    for (int o = 0; o < n_off; ++o) {
+        const double *Go = &G[(size_t)o * K];
+        for (int tl = 0; tl < kSplitTiles; ++tl)
+            for (int lane = 0; lane < kWave; ++lane)
+                for (int jj = 0; jj < 8; ++jj) {
+                    const int a = 16 * kTileBlock[tl] + (lane & 15);
+                    const int b = 32 * kTileChunk[tl] + 8 * (lane >> 4) + jj;
+                    const double v = (a < R && b < R && ri.deg[a] + ri.deg[b] <= Q) ? four_pi * Go[ri.sum(a, b)] : 0.0;
+                    if (v != 0.0 && (lane >> 4) >= kTileGroups[tl])
+                        fail(BCV_ESTATE, "internal: a nonzero interaction entry outside the loaded k-groups");
+                    const _Float16 hi = (_Float16)v;
+                    const _Float16 lo = (_Float16)(v - (double)hi);
+                    const size_t at = (((size_t)o * kSplitTiles + tl) * 2) * kWave * 8 + (size_t)lane * 8 + jj;
+                    A[at] = __builtin_bit_cast(uint16_t, hi);
+                    A[at + (size_t)kWave * 8] = __builtin_bit_cast(uint16_t, lo);
+                }
+        G48[o] = (float)(four_pi * Go[ri.sum(R - 1, 0)]);
+    }
 }
 
 void regular_cube_pairs(const int *deltas, int n, int n_gauss, double *out)

@@ -1,5 +1,7 @@
 // Launchers of the device kernels (kernels.hip, singular.hip).
 #pragma once
+#include <vector>
+
 #include "internal.hpp"
 
 namespace bcv {
@@ -11,6 +13,14 @@ void launch_apply(const bcv_plan_s &p, const double *f, double *u, int parts, hi
 void launch_btv(const bcv_plan_s &p, const double *qf, const double *gf, double *u, hipStream_t stream);
 // VtB apply (Algorithm 2): uf = <1_f, N f> on every boundary face from leaf densities f.
 void launch_vtb(const bcv_plan_s &p, const double *f, double *uf, hipStream_t stream);
+
+// Matrix-core interaction phase (BCV_MIXED_SPLIT16, q = 6): a folded moment row holds
+// kSplitRowHalves FP16 values (hi[64], lo[64]); the maxima of |f| are reduced in kFscaleParts parts.
+constexpr int kSplitRowHalves = 128;
+constexpr int kFscaleParts = 256;
+// The A operands of every offset (FP16 bits, in the lane layout of the kernel) and the one entry per
+// offset that runs on the vector units, from the FP64 derivative tables G (n_off x K).
+void split16_tables(int K, const std::vector<double> &G, int n_off, std::vector<uint16_t> &A, std::vector<float> &G48);
 
 // Stores every near-pair Galerkin entry of the plan in p.d_val (plan time).
 void launch_near_assemble(const bcv_plan_s &p, hipStream_t stream);

@@ -564,8 +564,9 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, const std::ve
             const int32_t b = base + (int32_t)((int64_t)n * k / np), e = base + (int32_t)((int64_t)n * (k + 1) / np);
             pieces.push_back(
                 Piece{M2LTask{b, e - b, chunks[q].lev, np > 1 ? m.n_pieces + k : -1, outs[q].heads}, (int32_t)q});
-            for (int32_t j = b; j < e; ++j)  // a piece's first slot always gathers
-                m.n_read_lanes += (j == b || m.slot_key[j] < 0) ? 64 : __builtin_popcountll(outs[q].heads);
+            if (e > b) m.slot_key[b] = (int32_t)((uint32_t)m.slot_key[b] | (1u << 31));  // a piece starts by gathering
+            for (int32_t j = b; j < e; ++j)
+                m.n_read_lanes += m.slot_key[j] < 0 ? 64 : __builtin_popcountll(outs[q].heads);
         }
         if (np > 1) m.n_pieces += np;
         m.n_pairs += outs[q].pairs;
@@ -828,6 +829,10 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
     p->nearfield = opts.nearfield;
     p->near_order = opts.near_order;
     p->precision = opts.precision;
+    if (opts.precision == BCV_MIXED_SPLIT16)
+        BCV_REQUIRE(opts.q == 6 && !opts.q_schedule, BCV_ENOTSUP,
+                    "BCV_MIXED_SPLIT16 supports the fixed order q = 6 only");
+    for (int lev = 0; lev <= t.L + 1 && lev <= kMaxLevel + 1; ++lev) p->lvl_start[lev] = t.lvl_start[lev];
     p->streams = opts.streams;
     if (p->streams == 2) {
         BCV_HIP(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
@@ -971,9 +976,27 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         p->n_m2l_read_lanes = m2l.n_read_lanes;
         p->n_tasks = (int64_t)m2l.tasks.size();
         p->d_G = upload(p.get(), G);
-        if (p->precision == BCV_MIXED_F32) {
+        if (p->precision != BCV_FP64) {
             std::vector<float> G32(G.begin(), G.end());
             p->d_G32 = upload(p.get(), G32);
+        }
+        if (p->precision == BCV_MIXED_SPLIT16) {
+            // matrix-core operands of every offset, and per slot the targets whose list holds it
+            std::vector<uint16_t> A;
+            std::vector<float> G48;
+            split16_tables(p->K, G, n_off, A, G48);
+            p->d_m2l_A = reinterpret_cast<uint32_t *>(upload(p.get(), A));
+            p->d_G48 = upload(p.get(), G48);
+            const int64_t n_slots = (int64_t)m2l.slot_key.size();
+            std::vector<uint64_t> mask(std::max<int64_t>(n_slots, 1), 0);
+#pragma omp parallel for schedule(static)
+            for (int64_t sl = 0; sl < n_slots; ++sl) {
+                uint64_t mk = 0;
+                for (int lane = 0; lane < 64; ++lane)
+                    if (m2l.slot_src[sl * 64 + lane] >> 31) mk |= 1ull << lane;
+                mask[sl] = mk;
+            }
+            p->d_slot_mask = upload(p.get(), mask);
         }
         p->d_tasks = upload(p.get(), m2l.tasks);
         p->d_task_targets = upload(p.get(), m2l.targets);
@@ -992,10 +1015,14 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         p->d_M = alloc_zero<double>(p.get(), (size_t)(p->n_cells + 1) * p->K);
         p->d_Lam = alloc_zero<double>(p.get(), (size_t)p->n_cells * p->K);
         const size_t n_folded = (size_t)(p->n_cells + 1) * (size_t)p->R;
-        if (p->precision == BCV_MIXED_F32)
+        if (p->precision != BCV_FP64)
             p->d_M32 = alloc_zero<float>(p.get(), n_folded);
         else
             p->d_Mr = alloc_zero<double>(p.get(), n_folded);
+        if (p->precision == BCV_MIXED_SPLIT16) {
+            p->d_M16 = alloc_zero<uint16_t>(p.get(), (size_t)(p->n_cells + 1) * kSplitRowHalves);
+            p->d_fscale = alloc_zero<float>(p.get(), kFscaleParts + 1);
+        }
     }
 
     if (opts.boundary) {
@@ -1034,7 +1061,7 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         launch_near_assemble(*p, nullptr);
         BCV_HIP(hipDeviceSynchronize());
         if (opts.near_order == 1) launch_near_assemble_ordered(*p, ordered_entry, ordered_target, near_order);
-        if (p->precision == BCV_MIXED_F32) {  // the apply reads FP32 entries (touching pairs stay exact)
+        if (p->precision != BCV_FP64) {  // the apply reads FP32 entries (touching pairs stay exact)
             p->d_val32 = alloc_zero<float>(p.get(), (size_t)p->n_near);
             launch_near_narrow(*p, nullptr);
             BCV_HIP(hipDeviceSynchronize());
@@ -1060,6 +1087,7 @@ void destroy_plan(bcv_plan_s *p)
                     p->d_splits, p->d_partial, p->d_M, p->d_Lam, p->d_G,
                     p->d_M32, p->d_Mr, p->d_G32,
                     p->d_parents, p->d_tasks, p->d_task_targets, p->d_slot_off, p->d_slot_src,
+                    p->d_slot_mask, p->d_m2l_A, p->d_G48, p->d_M16, p->d_fscale,
                     p->d_m2l_splits, p->d_m2l_partial, p->d_faces, p->d_leaf_faces, p->d_btv_col,
                     p->d_btv_units, p->d_btv_splits, p->d_btv_partial, p->d_btv_touch, p->d_vtb_col,
                     p->d_vtb_units, p->d_vtb_splits, p->d_vtb_partial};
