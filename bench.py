@@ -36,6 +36,7 @@ PEAK_FP32 = 157.3e12  # MI355X FP32 vector peak, FLOP/s
 REL_L2_GATE = 1e-6  # the mixed path counts only if its rel-L2 against the FP64 path is within this
 SURROGATE_TOL = 1e-7  # touching-pair surrogate: accepted where its calibrated error estimate is below this
 PEAK_HBM = 8.0e12  # bytes/s
+PEAK_F16_MFMA = 2.5e15  # MI355X dense FP16 matrix peak, FLOP/s
 
 
 def m2l_flops_per_pair(q):
@@ -138,10 +139,11 @@ def measure(bcv, torch, tree, f, args, dev, nf, prec, surrogate=None):
     from a second timed pass in which the near field runs after the far field on one stream, so
     that every phase's kernels have the GPU to themselves (with two streams the near-field and
     interaction kernels share the compute units and their durations say nothing about either)."""
+    precision = {"fp64": bcv.FP64, "mixed": bcv.MIXED_F32, "split16": bcv.MIXED_SPLIT16}[prec]
+
     def make_plan(streams):
         return bcv.plan_interactions(tree, q=args.q, nearfield=nf, device=dev, streams=streams,
-                                     precision=bcv.MIXED_F32 if prec == "mixed" else bcv.FP64,
-                                     surrogate=surrogate, surrogate_tol=SURROGATE_TOL)
+                                     precision=precision, surrogate=surrogate, surrogate_tol=SURROGATE_TOL)
 
     t0 = time.perf_counter()
     plan = make_plan(args.streams)
@@ -182,7 +184,7 @@ def roofline(info, phase_avg, args, prec, q):
     12 B (FP64 entry + index) or 8 B (FP32 entry + index) per assembled near pair."""
     from paper_2112_00864_amd import profiling
 
-    mixed = prec == "mixed"
+    mixed = prec != "fp64"
     peak = (PEAK_FP32 if mixed else PEAK_FP64) / 1e12
     m2l_ms = phase_avg["m2l"]
     near_ms = phase_avg["near"]
@@ -192,6 +194,12 @@ def roofline(info, phase_avg, args, prec, q):
                 "achieved_executed_reduced": info["n_m2l"] * m2l_reduced_flops_per_pair(q) / (m2l_ms * 1e-3) / 1e12,
                 "reduced_flops_per_pair": m2l_reduced_flops_per_pair(q),
                 "ms": m2l_ms}
+    if prec == "split16":
+        # matrix cores: 48 v_mfma_f32_16x16x32_f16 per slot (4 target sets x 4 tiles x 3 split products)
+        executed = info["n_m2l_lanes"] // 64 * 48 * 2 * 16 * 16 * 32
+        m2l_roof.update({"bound": "mfma", "peak": PEAK_F16_MFMA / 1e12,
+                         "mfma_executed_tflops": executed / (m2l_ms * 1e-3) / 1e12,
+                         "mfma_utilisation": executed / (m2l_ms * 1e-3) / PEAK_F16_MFMA})
     if args.nearfield == "assembled":
         near_bytes = info["n_near"] * (8 if mixed else 12)
         near_roof = {"bound": "hbm", "achieved": near_bytes / (near_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
@@ -203,8 +211,10 @@ def roofline(info, phase_avg, args, prec, q):
                                                   "true" if mixed else "false")
     # the interaction phase: the interaction launches (reading the folded moment rows that P2M and
     # M2M write) and the sum of the split tasks' pieces
-    m2l_names = (m2l_kernel_names(q, mixed)
-                 + ["m2l_combine_kernel"])
+    if prec == "split16":
+        m2l_names = ["split_rows_kernel", "m2l_mfma_kernel<%d>" % q, "m2l_combine_kernel"]
+    else:
+        m2l_names = m2l_kernel_names(q, mixed) + ["m2l_combine_kernel"]
     for roof_, names in ((m2l_roof, m2l_names), (near_roof, [near_name])):
         roof_["frac"] = roof_["achieved"] / roof_["peak"]
         # HBM bytes per apply (PMC, summed over the launches), None if stale
@@ -473,6 +483,8 @@ def main():
     ap.add_argument("--cpu-targets", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="mixed path without the touching-pair surrogate")
+    ap.add_argument("--no-split16", action="store_true",
+                    help="skip the mixed apply with the interaction phase on the matrix cores")
     ap.add_argument("--no-btv", action="store_true", help="skip the BtV (Algorithm 3) measurement")
     ap.add_argument("--no-schedule", action="store_true",
                     help="skip the level-dependent expansion order measurement")
@@ -608,6 +620,22 @@ def main():
                                "plan_seconds": r_o["plan_s"], "plan_device_bytes": r_o["info"]["device_bytes"],
                                "max_rel_diff_vs_headline": float(np.max(np.abs(r_o["u"] - h["u"]) / np.abs(h["u"])))}
     print("%s with near field %s: step %.3f ms" % (head, other, r_o["ms"]), file=sys.stderr, flush=True)
+    if "mixed" in runs and args.q == 6 and not args.no_split16:
+        # the same mixed apply with the interaction phase on the matrix cores (split FP16)
+        r16 = measure(bcv, torch, tree, f, args, dev, nf, "split16", surrogate)
+        u16 = r16["u"]
+        w = 0.125 ** leaves[:, 0].astype(np.float64)
+        ref64 = runs["fp64"]["u"] if "fp64" in runs else None
+        line["matrix_cores"] = {
+            "precision": "BCV_MIXED_SPLIT16: interaction phase as v_mfma_f32_16x16x32_f16 with FP16 hi/lo "
+                         "operands (3 products, FP32 accumulation); the rest as the mixed path",
+            "value": n / (r16["ms"] * 1e-3), "ms_per_step": r16["ms"], "phase_ms": r16["phases"],
+            "phase_ms_serial": r16["phases_serial"], "roofline": r16["roof"],
+            "rel_l2_vs_fp64": None if ref64 is None else float(
+                np.sqrt(np.sum(w * ((u16 - ref64) / w) ** 2) / np.sum(w * (ref64 / w) ** 2))),
+            "vs_headline_mixed": runs["mixed"]["ms"] / r16["ms"]}
+        print("split16: step %.3f ms; phases %s" % (r16["ms"], json.dumps(r16["phases_serial"])), file=sys.stderr,
+              flush=True)
     if surrogate is not None:
         line["surrogate"] = {"classes_from_network": runs["mixed"]["info"]["surrogate_classes"], "of": 6,
                              "tol": SURROGATE_TOL, "training": sur_report}

@@ -154,6 +154,7 @@ struct bcv_plan_s {
     std::vector<int32_t> parent_begin;  // per level l: range of marked cells of level l in d_parents
     int64_t n_tasks = 0;
     int64_t n_units = 0, n_splits = 0;
+    int32_t near_xcd[bcv::kXcds + 1] = {};     // near-field units of each XCD (contiguous target ranges)
     int64_t n_m2l_splits = 0, m2l_groups = 0;  // split tasks; workgroups of the interaction kernel
     int32_t xcd_begin[bcv::kXcds + 1] = {};     // task range of each XCD
     // q_schedule: the tasks of level l are [level_xcd[l][0], level_xcd[l][kXcds]), cut into XCD
@@ -166,7 +167,8 @@ struct bcv_plan_s {
     int32_t *d_leaf_cell = nullptr;
     int32_t *d_cell_leaf = nullptr;  // per cell: its leaf number, -1 for a marked cell (far-field plans)
     int64_t *d_split = nullptr;     // per near row: first point-rule entry (touching entries come first)
-    uint32_t *d_col = nullptr;      // source leaf | (touch class + 1) << 28
+    uint32_t *d_col = nullptr;      // source leaf | code << 28: code = touch class + 1 (0: not touching),
+                                    // + 8 where the source is the smaller cube of a touching pair
     double *d_val = nullptr;        // assembled near entries (nearfield == ASSEMBLED, FP64 plans)
     float *d_val32 = nullptr;       // the same in FP32 (nearfield == ASSEMBLED, mixed plans)
     bcv::NearUnit *d_units = nullptr;   // near-field work units, longest first

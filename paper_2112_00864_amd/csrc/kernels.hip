@@ -309,7 +309,7 @@ __device__ __forceinline__ double near_entry(uint32_t code, const double4 gt, co
     const double4 gs = geom[s];
     if (cls) {
         const double a = fmin(gt.w, gs.w);
-        return tv.v[cls - 1] * (a * a) * (a * a) * a;
+        return tv.v[(cls & 7u) - 1] * (a * a) * (a * a) * a;
     }
     return point_rule(gt, gs);
 }
@@ -1083,8 +1083,39 @@ __device__ __forceinline__ double eval_far(const double *__restrict__ lam, doubl
     return s * (a * a * a);
 }
 
+// Exact entry of a touching pair from its code (class + 1, + 8 if the source is the smaller cube) and
+// the target's side: C_class a_small^5 / (4 pi), a_small = a_t / 2 for a smaller source (ratio 2).
+__device__ __forceinline__ double touch_entry(uint32_t code, double a_t, const TouchValues &tv)
+{
+    const uint32_t cls = code >> 28;
+    const double a = (cls & 8u) ? 0.5 * a_t : a_t;
+    return tv.v[(cls & 7u) - 1] * (a * a) * (a * a) * a;
+}
+
+// sum over entries e in [e0, e1) of val[e] f[source(e)], this lane's share (the wave sums the lanes):
+// entries e0 + lane + 64 k, four per lane per step.
+template <class V>
+__device__ __forceinline__ double assembled_dot(const uint32_t *__restrict__ col, const V *__restrict__ val,
+                                                const double *__restrict__ f, int64_t e0, int64_t e1, int lane,
+                                                double acc)
+{
+    int64_t e = e0 + lane;
+    for (; e + 3 * kWave < e1; e += 4 * kWave) {
+        uint32_t c[4];
+        double v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) c[k] = col[e + k * kWave], v[k] = (double)val[e + k * kWave];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc = fma(v[k], f[c[k] & 0x0FFFFFFFu], acc);
+    }
+    for (; e < e1; e += kWave) acc = fma((double)val[e], f[col[e] & 0x0FFFFFFFu], acc);
+    return acc;
+}
+
+// Units are dealt to the XCDs in contiguous target ranges (XcdRanges over units): workgroup b runs on
+// XCD b mod 8 and its 4 waves take units begin[x] + 4 (b / 8) + wave.
 template <int Q, bool kAssembled, bool kMixed>
-__global__ __launch_bounds__(256) void near_eval_kernel(int64_t n_units, const NearUnit *__restrict__ units,
+__global__ __launch_bounds__(256) void near_eval_kernel(XcdRanges xr, const NearUnit *__restrict__ units,
                                                         const int64_t *__restrict__ split,
                                                         const uint32_t *__restrict__ col,
                                                         const double *__restrict__ val,
@@ -1098,8 +1129,9 @@ __global__ __launch_bounds__(256) void near_eval_kernel(int64_t n_units, const N
 {
     constexpr int K = MultiIndex<Q>::K;
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
-    if (w >= n_units) return;  // uniform per wave
+    const int x = (int)(blockIdx.x % kXcds);
+    const int64_t w = xr.begin[x] + (int64_t)(blockIdx.x / kXcds) * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (w >= xr.begin[x + 1]) return;  // uniform per wave
     const NearUnit un = units[w];
     const int32_t t = un.target;
     const double4 gt = geom[t];
@@ -1107,39 +1139,21 @@ __global__ __launch_bounds__(256) void near_eval_kernel(int64_t n_units, const N
     if (parts & BCV_PART_NEAR) {
         const int64_t e0 = un.begin, e1 = un.end;
         if (kAssembled && !kMixed) {
-            int64_t e = e0 + lane;
-            for (; e + kWave < e1; e += 2 * kWave) {  // two pairs per lane per step
-                const uint32_t c0 = col[e], c1 = col[e + kWave];
-                const double v0 = val[e], v1 = val[e + kWave];
-                acc = fma(v0, f[c0 & 0x0FFFFFFFu], acc);
-                acc = fma(v1, f[c1 & 0x0FFFFFFFu], acc);
-            }
-            if (e < e1) acc = fma(val[e], f[col[e] & 0x0FFFFFFFu], acc);
+            acc = assembled_dot(col, val, f, e0, e1, lane, acc);
         } else if (kAssembled) {  // FP32 entries; the touching pairs exact, in FP64
             const int64_t es = min(max(split[t], e0), e1);
             const double a_t = gt.w;
             for (int64_t e = e0 + lane; e < es; e += kWave) {
                 const uint32_t code = col[e];
-                const int32_t s = (int32_t)(code & 0x0FFFFFFFu);
-                const double a = fmin(a_t, geom[s].w);
-                acc = fma(tv.v[(code >> 28) - 1] * (a * a) * (a * a) * a, f[s], acc);
+                acc = fma(touch_entry(code, a_t, tv), f[code & 0x0FFFFFFFu], acc);
             }
-            int64_t e = es + lane;
-            for (; e + kWave < e1; e += 2 * kWave) {  // two pairs per lane per step
-                const uint32_t c0 = col[e], c1 = col[e + kWave];
-                const float v0 = val32[e], v1 = val32[e + kWave];
-                acc = fma((double)v0, f[c0 & 0x0FFFFFFFu], acc);
-                acc = fma((double)v1, f[c1 & 0x0FFFFFFFu], acc);
-            }
-            if (e < e1) acc = fma((double)val32[e], f[col[e] & 0x0FFFFFFFu], acc);
+            acc = assembled_dot(col, val32, f, es, e1, lane, acc);
         } else {
             const int64_t es = min(max(split[t], e0), e1);
             const double a_t = gt.w;
             for (int64_t e = e0 + lane; e < es; e += kWave) {  // touching pairs
                 const uint32_t code = col[e];
-                const int32_t s = (int32_t)(code & 0x0FFFFFFFu);
-                const double a = fmin(a_t, geom[s].w);
-                acc = fma(tv.v[(code >> 28) - 1] * (a * a) * (a * a) * a, f[s], acc);
+                acc = fma(touch_entry(code, a_t, tv), f[code & 0x0FFFFFFFu], acc);
             }
             int64_t e = es + lane;
             double4 gs_next = make_double4(0.0, 0.0, 0.0, 1.0);
@@ -1185,16 +1199,14 @@ __global__ __launch_bounds__(256) void near_combine_kernel(int64_t n_splits, con
     const int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
     if (w >= n_splits) return;  // uniform per wave
     const NearSplit sp = splits[w];
-    double far = 0.0;
+    double v = 0.0;
     if (Lam != nullptr) {
         const double a = geom[sp.target].w;
-        far = wave_sum(eval_far<Q>(Lam + (int64_t)leaf_cell[sp.target] * lo.ldk, a, lane, lo.k[level_of_side(a)]));
+        v = eval_far<Q>(Lam + (int64_t)leaf_cell[sp.target] * lo.ldk, a, lane, lo.k[level_of_side(a)]);
     }
-    if (lane == 0) {
-        double acc = 0.0;
-        for (int k = 0; k < sp.count; ++k) acc += partial[sp.first + k];
-        u[sp.target] = acc + far;
-    }
+    for (int k = lane; k < sp.count; k += kWave) v += partial[sp.first + k];  // fixed order per lane
+    v = wave_sum(v);
+    if (lane == 0) u[sp.target] = v;
 }
 
 // ---- evaluation phase alone (near field computed concurrently): u += a^3 sum_a kappa_a Lambda^a --
@@ -1611,23 +1623,27 @@ template <int Q>
 void launch_near_q(const bcv_plan_s &p, const double *f, const double *lam, int parts, double *u, hipStream_t st)
 {
     const LevelOrders lo = level_orders(p);
-    const unsigned blocks = (unsigned)((p.n_units + 3) / 4);
+    XcdRanges xr;
+    int32_t longest = 0;
+    for (int x = 0; x <= kXcds; ++x) xr.begin[x] = p.near_xcd[x];
+    for (int x = 0; x < kXcds; ++x) longest = std::max(longest, xr.begin[x + 1] - xr.begin[x]);
+    const unsigned blocks = (unsigned)(kXcds * ((longest + 3) / 4));
     const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
     const bool mixed = p.precision != BCV_FP64;
     if (p.nearfield == BCV_NEAR_ASSEMBLED && mixed)
-        near_eval_kernel<Q, true, true><<<blocks, 256, 0, st>>>(p.n_units, p.d_units, p.d_split, p.d_col, nullptr,
+        near_eval_kernel<Q, true, true><<<blocks, 256, 0, st>>>(xr, p.d_units, p.d_split, p.d_col, nullptr,
                                                                 p.d_val32, geom, f, lam, p.d_leaf_cell,
                                                                 touch_values(p), parts, p.d_partial, u, lo);
     else if (p.nearfield == BCV_NEAR_ASSEMBLED)
-        near_eval_kernel<Q, true, false><<<blocks, 256, 0, st>>>(p.n_units, p.d_units, p.d_split, p.d_col, p.d_val,
+        near_eval_kernel<Q, true, false><<<blocks, 256, 0, st>>>(xr, p.d_units, p.d_split, p.d_col, p.d_val,
                                                                  nullptr, geom, f, lam, p.d_leaf_cell,
                                                                  touch_values(p), parts, p.d_partial, u, lo);
     else if (mixed)
-        near_eval_kernel<Q, false, true><<<blocks, 256, 0, st>>>(p.n_units, p.d_units, p.d_split, p.d_col, nullptr,
+        near_eval_kernel<Q, false, true><<<blocks, 256, 0, st>>>(xr, p.d_units, p.d_split, p.d_col, nullptr,
                                                                  nullptr, geom, f, lam, p.d_leaf_cell,
                                                                  touch_values(p), parts, p.d_partial, u, lo);
     else
-        near_eval_kernel<Q, false, false><<<blocks, 256, 0, st>>>(p.n_units, p.d_units, p.d_split, p.d_col, nullptr,
+        near_eval_kernel<Q, false, false><<<blocks, 256, 0, st>>>(xr, p.d_units, p.d_split, p.d_col, nullptr,
                                                                   nullptr, geom, f, lam, p.d_leaf_cell,
                                                                   touch_values(p), parts, p.d_partial, u, lo);
     check_launch();

@@ -76,7 +76,7 @@ const std::vector<std::array<int, 3>> &stencil()
     return s;
 }
 
-constexpr uint32_t kBadTouch = 15u;
+constexpr uint32_t kBadTouch = 0xFFu;
 
 // Touch code of two cubes given at level-L resolution: 0 if the closed cubes are disjoint, else
 // 1 + class (0 self, 1 face, 2 edge, 3 vertex with equal sides; 4 face, 5 edge, 6 vertex with
@@ -193,10 +193,11 @@ NearCSR build_near(const bcv_tree_s &t, const std::vector<Grid> &g, const LeafGe
             codes.resize(src.size());
             for (size_t e = 0; e < src.size(); ++e) {
                 const int32_t s = src[e];
-                const uint32_t tc = touch_code(&geo.lo[3 * n], geo.size[n], &geo.lo[3 * s], geo.size[s]);
+                uint32_t tc = touch_code(&geo.lo[3 * n], geo.size[n], &geo.lo[3 * s], geo.size[s]);
                 bad += tc == kBadTouch;
                 touch += tc != 0;
-                codes[e] = (uint32_t)s | (tc << 28);
+                if (tc != 0 && tc != kBadTouch && geo.size[s] < geo.size[n]) tc |= 8u;  // the source is the smaller cube
+                codes[e] = (uint32_t)s | ((tc & 15u) << 28);
             }
             // touching pairs first (they are cheap), then by source leaf
             std::sort(codes.begin(), codes.end(), [](uint32_t a, uint32_t b) {
@@ -224,9 +225,13 @@ struct NearUnits {
     std::vector<NearUnit> units;
     std::vector<NearSplit> splits;
     int64_t n_partial = 0;
+    int32_t xcd_begin[kXcds + 1] = {};  // with xcd ranges: the units of XCD x are [xcd_begin[x], xcd_begin[x + 1])
 };
 
-NearUnits build_near_units(const NearCSR &near, int64_t n_leaves, int64_t unit)
+// xcd: the units are grouped in kXcds contiguous target ranges (leaf order, so spatially compact)
+// of about equal entry counts, one per XCD, so that each XCD's L2 holds the densities of its own
+// region; within a range the longest units come first. Otherwise all units are longest first.
+NearUnits build_near_units(const NearCSR &near, int64_t n_leaves, int64_t unit, bool xcd = false)
 {
     NearUnits r;
     for (int64_t t = 0; t < n_leaves; ++t) {
@@ -243,8 +248,24 @@ NearUnits build_near_units(const NearCSR &near, int64_t n_leaves, int64_t unit)
                                        (int32_t)(r.n_partial + k)});
         r.n_partial += pieces;
     }
-    std::stable_sort(r.units.begin(), r.units.end(),
-                     [](const NearUnit &x, const NearUnit &y) { return x.end - x.begin > y.end - y.begin; });
+    const auto longer = [](const NearUnit &x, const NearUnit &y) { return x.end - x.begin > y.end - y.begin; };
+    if (xcd) {
+        // units are in target order here; cut them at equal shares of the entries
+        const int64_t total = near.row[n_leaves];
+        int64_t acc = 0;
+        int x = 0;
+        r.xcd_begin[0] = 0;
+        for (size_t k = 0; k < r.units.size(); ++k) {
+            while (x < kXcds - 1 && acc >= total * (x + 1) / kXcds) r.xcd_begin[++x] = (int32_t)k;
+            acc += r.units[k].end - r.units[k].begin;
+        }
+        while (x < kXcds) r.xcd_begin[++x] = (int32_t)r.units.size();
+        BCV_REQUIRE(r.units.size() < (size_t)INT32_MAX, BCV_ENOTSUP, "near field too large");
+        for (int y = 0; y < kXcds; ++y)
+            std::stable_sort(r.units.begin() + r.xcd_begin[y], r.units.begin() + r.xcd_begin[y + 1], longer);
+    } else {
+        std::stable_sort(r.units.begin(), r.units.end(), longer);
+    }
     // every entry of every row is covered by exactly one unit
     std::vector<int64_t> covered(n_leaves, 0);
     for (const NearUnit &u : r.units) {
@@ -921,8 +942,10 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         p->n_touch = near.n_touch;
         p->d_split = upload(p.get(), near.split);
         p->d_col = upload(p.get(), near.col);
-        const NearUnits nu = build_near_units(near, p->n_leaves, opts.near_unit > 0 ? opts.near_unit : kDefaultNearUnit);
+        const NearUnits nu =
+            build_near_units(near, p->n_leaves, opts.near_unit > 0 ? opts.near_unit : kDefaultNearUnit, true);
         p->n_units = (int64_t)nu.units.size();
+        for (int x = 0; x <= kXcds; ++x) p->near_xcd[x] = nu.xcd_begin[x];
         p->n_splits = (int64_t)nu.splits.size();
         p->d_units = upload(p.get(), nu.units);
         p->d_splits = upload(p.get(), nu.splits);
