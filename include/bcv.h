@@ -50,9 +50,13 @@ typedef enum {
     BCV_ESTATE = 5   /* a handle is not a live object of the expected kind */
 } bcv_status;
 
-/* Mesh description (Sec. 2, Boundary Concentrated Mesh, with cube cells on [0,1]^3).
- * Level 0 is the unit cube; level-l cells are cubes of side 2^-l. For l < L a cell is marked
- * (refined) by the marking rule; every level-L cell is a leaf. */
+/* Mesh description (Sec. 2, Boundary Concentrated Mesh, with cube cells).
+ * Level 0 is the domain cube; level-l cells are cubes of side s 2^-l (s the side of the domain). For
+ * l < L a cell is marked (refined) by the marking rule; every level-L cell is a leaf. */
+enum {
+    BCV_GEOM_BOX = 0, /* the axis-aligned cube [lo, hi] (all of lo and hi zero: the unit cube [0,1]^3) */
+    BCV_GEOM_BALL = 1 /* a cube-to-ball mapped mesh: not built (BCV_ENOTSUP) */
+};
 enum {
     BCV_MARK_FACE = 0,     /* marked iff the cell has a face on the boundary (M_l = B_l) */
     BCV_MARK_NEIGHBOR = 1  /* marked iff a neighbour (eq. def:neighbors, eta0 = 1/2) has a face on the
@@ -62,9 +66,16 @@ enum {
                               BCV_MARK_FACE) */
 };
 typedef struct {
-    int L;       /* finest level, 2 <= L <= 9 (boundary leaves have side h = 2^-L) */
-    int marking; /* BCV_MARK_FACE or BCV_MARK_NEIGHBOR */
+    int geometry;     /* BCV_GEOM_BOX */
+    double lo[3];     /* lower corner of the domain cube */
+    double hi[3];     /* upper corner; hi - lo must be the same positive side s on all three axes */
+    int L;            /* finest level, 2 <= L <= 9 (boundary leaves have side h = s 2^-L) */
+    int marking;      /* BCV_MARK_FACE or BCV_MARK_NEIGHBOR */
 } bcv_mesh_desc;
+/* Every operator scales exactly with the side: on the cube of side s the VtV entries are s^5 times
+ * those of the unit cube (u = <1_w, N f>: volumes s^3 twice, the kernel 1/s), the VtB ones s^4, the
+ * BtV single-layer ones s^4 and the double-layer ones s^3; a translation changes nothing. The library
+ * computes on the unit cube and applies these factors. */
 
 enum { BCV_NEAR_QUADRATURE = 0, BCV_NEAR_ASSEMBLED = 1 };
 /* Arithmetic of the apply.
@@ -85,7 +96,10 @@ enum { BCV_FP64 = 0, BCV_MIXED_F32 = 1, BCV_MIXED_SPLIT16 = 2 };
 /* Plan options. */
 typedef struct {
     double eta0;   /* separation parameter of the neighbour test (eq. def:neighbors); must be 0.5 */
-    int q;         /* expansion order, |alpha| + |beta| <= q (Sec. 3); supported: 4, 6, 8 */
+    int q;         /* expansion order, |alpha| + |beta| <= q (Sec. 3): 4..10. Orders 4, 6 and 8 have
+                      their own interaction kernels; 5, 7, 9 and 10 run the level-by-level kernels of
+                      q_schedule with the same order on every level (single-mesh trees, no
+                      opts.boundary) */
     int precision; /* BCV_FP64, BCV_MIXED_F32 or BCV_MIXED_SPLIT16 */
     int direct;    /* 1: every leaf pair is treated as near (no far field; small meshes only) */
     int nearfield; /* BCV_NEAR_QUADRATURE: the apply evaluates every near-pair entry on the fly;
@@ -153,7 +167,8 @@ typedef struct {
 } bcv_plan_info;
 
 /* Build the BC octree of Sec. 2 on the host. desc and out must be non-NULL.
- * Errors: BCV_EINVAL (L outside 2..9, marking not 0 or 1), BCV_ENOMEM. */
+ * Errors: BCV_EINVAL (L outside 2..9, marking not 0 or 1, a box that is not a cube of positive side),
+ * BCV_ENOTSUP (geometry BCV_GEOM_BALL), BCV_ENOMEM. */
 bcv_status bcv_build_bc_tree(const bcv_mesh_desc *desc, bcv_tree *out);
 
 /* A forest of n_meshes BC meshes for a batched apply: one tree, one plan and one apply (and one
@@ -170,8 +185,16 @@ bcv_status bcv_tree_leaf_mesh(bcv_tree tree, int32_t *mesh_of_leaf);
 /* Number of leaves (host integer). */
 bcv_status bcv_tree_num_leaves(bcv_tree tree, int64_t *n);
 
-/* Copy (level, i, j, k) of every leaf, in leaf order, into level_ijk (host, n_leaves x 4 int32). */
-bcv_status bcv_tree_leaves(bcv_tree tree, int32_t *level_ijk);
+/* Per leaf, in leaf order (host arrays, each may be NULL):
+ *   level_ijk: n_leaves x 4 int32, (level, i, j, k) in units of the level's cell side (forests: the
+ *              index space of bcv_build_bc_forest);
+ *   gauss_xyz: n_leaves x 8 x 3 doubles, the 2x2x2 Gauss-Legendre points of the leaf in physical
+ *              coordinates (x fastest: point g has offsets 1/2 -+ 1/(2 sqrt 3) of the side, bit 0 of g
+ *              along x, bit 1 along y, bit 2 along z), the points of the point rule, the moments and
+ *              the evaluation (Sec. 3 with this reading of the integrals);
+ *   gauss_w:   n_leaves x 8 doubles, their weights |w|/8.
+ * Errors: BCV_EINVAL (tree NULL), BCV_ESTATE. */
+bcv_status bcv_tree_leaves(bcv_tree tree, int32_t *level_ijk, double *gauss_xyz, double *gauss_w);
 
 void bcv_tree_destroy(bcv_tree tree);
 
@@ -195,6 +218,17 @@ void bcv_plan_destroy(bcv_plan plan);
  * Stream-ordered and asynchronous: returns after enqueueing; allocates nothing.
  * f_dev and u_dev must not overlap. Errors: BCV_EINVAL (NULL pointers), BCV_ESTATE, BCV_EDEVICE. */
 bcv_status bcv_vtv_apply(bcv_plan plan, const double *f_dev, double *u_dev, void *hip_stream);
+
+/* Applies of several plans, one after another on one stream (Algorithm 1 for each mesh):
+ *   plans: host array of n plan handles, all on the same device;
+ *   f_dev, u_dev: host arrays of n device pointers; plan i reads f_dev[i] and overwrites u_dev[i]
+ *   (n_leaves of plan i doubles each, leaf order), as bcv_vtv_apply does.
+ * Stream-ordered, asynchronous, allocates nothing. Many small meshes run faster as one forest
+ * (bcv_build_bc_forest: one plan, one apply, optionally one graph). 1 <= n <= 4096.
+ * Errors: BCV_EINVAL (NULL arrays or pointers, n out of range, plans on different devices),
+ * BCV_ESTATE, BCV_EDEVICE. */
+bcv_status bcv_vtv_apply_batched(const bcv_plan *plans, int n, const double *const *f_dev, double *const *u_dev,
+                                 void *hip_stream);
 
 /* The same apply restricted to parts of Algorithm 1, for testing and timing:
  * parts = BCV_PART_NEAR (near field only), BCV_PART_FAR (moments through evaluation only),

@@ -26,8 +26,21 @@ class BCVError(RuntimeError):
         self.status = status
 
 
+GEOM_BOX, GEOM_BALL = 0, 1
+
+
 class MeshDesc(ctypes.Structure):
-    _fields_ = [("L", ctypes.c_int), ("marking", ctypes.c_int)]
+    _fields_ = [("geometry", ctypes.c_int), ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("L", ctypes.c_int), ("marking", ctypes.c_int)]
+
+
+def _mesh_desc(L, marking, lo=None, hi=None, geometry=GEOM_BOX):
+    d = MeshDesc()
+    d.geometry, d.L, d.marking = int(geometry), int(L), int(marking)
+    for ax in range(3):
+        d.lo[ax] = 0.0 if lo is None else float(lo[ax])
+        d.hi[ax] = 0.0 if hi is None else float(hi[ax])
+    return d
 
 
 class PlanOpts(ctypes.Structure):
@@ -76,7 +89,10 @@ def lib():
         vp, i64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)
         L.bcv_build_bc_tree.argtypes = [ctypes.POINTER(MeshDesc), ctypes.POINTER(vp)]
         L.bcv_tree_num_leaves.argtypes = [vp, i64p]
-        L.bcv_tree_leaves.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+        L.bcv_tree_leaves.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double)]
+        L.bcv_vtv_apply_batched.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                            vp]
         L.bcv_tree_destroy.argtypes = [vp]
         L.bcv_tree_destroy.restype = None
         L.bcv_plan_interactions.argtypes = [vp, ctypes.POINTER(PlanOpts), ctypes.c_int, ctypes.POINTER(vp)]
@@ -121,7 +137,7 @@ def lib():
                                    dp]
         L.bcv_last_error.restype = ctypes.c_char_p
         for name in ("bcv_build_bc_tree", "bcv_tree_num_leaves", "bcv_tree_leaves", "bcv_plan_interactions",
-                     "bcv_plan_get_info", "bcv_vtv_apply", "bcv_vtv_apply_parts", "bcv_vtb_apply", "bcv_btv_apply",
+                     "bcv_plan_get_info", "bcv_vtv_apply", "bcv_vtv_apply_batched", "bcv_vtv_apply_parts", "bcv_vtb_apply", "bcv_btv_apply",
                      "bcv_touching_integrals", "bcv_plan_enable_timing", "bcv_plan_phase_times",
                      "bcv_box_pair_integrals", "bcv_touch_pair_quadrature", "bcv_mlp_create", "bcv_mlp_num_params",
                      "bcv_mlp_get_params", "bcv_mlp_set_params", "bcv_mlp_forward", "bcv_mlp_forward_noalloc",
@@ -168,8 +184,16 @@ class Tree:
     def leaves(self):
         """(level, i, j, k) per leaf in leaf order, int32 (n, 4)."""
         out = np.empty((self.num_leaves(), 4), dtype=np.int32)
-        _check(lib().bcv_tree_leaves(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        _check(lib().bcv_tree_leaves(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), None, None))
         return out
+
+    def gauss_points(self):
+        """The 2x2x2 Gauss points of every leaf in physical coordinates, (n, 8, 3), and their weights (n, 8)."""
+        n = self.num_leaves()
+        xyz = np.empty((n, 8, 3))
+        w = np.empty((n, 8))
+        _check(lib().bcv_tree_leaves(self._h, None, _dp(xyz), _dp(w)))
+        return xyz, w
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -177,20 +201,23 @@ class Tree:
             self._h = None
 
 
-def build_bc_forest(Ls, marking=0):
+def build_bc_forest(Ls, marking=0, boxes=None):
     """One tree holding len(Ls) meshes; mesh m occupies [4m, 4m+1) x [0,1)^2 (see bcv.h).
-    marking: one rule for every mesh, or a list with one per mesh."""
+    marking: one rule for every mesh, or a list with one per mesh. boxes: None (unit cubes) or one
+    (lo, hi) cube per mesh."""
     marks = list(marking) if isinstance(marking, (list, tuple)) else [marking] * len(Ls)
     if len(marks) != len(Ls):
         raise ValueError("one marking per mesh")
-    descs = (MeshDesc * len(Ls))(*[MeshDesc(int(L), int(mk)) for L, mk in zip(Ls, marks)])
+    boxes = [(None, None)] * len(Ls) if boxes is None else list(boxes)
+    descs = (MeshDesc * len(Ls))(*[_mesh_desc(L, mk, lo, hi) for L, mk, (lo, hi) in zip(Ls, marks, boxes)])
     h = ctypes.c_void_p()
     _check(lib().bcv_build_bc_forest(len(Ls), descs, ctypes.byref(h)))
     return Tree(h)
 
 
-def build_bc_tree(L, marking=0):
-    desc = MeshDesc(L, marking)
+def build_bc_tree(L, marking=0, lo=None, hi=None, geometry=GEOM_BOX):
+    """BC octree of the cube [lo, hi] (default: the unit cube)."""
+    desc = _mesh_desc(L, marking, lo, hi, geometry)
     h = ctypes.c_void_p()
     _check(lib().bcv_build_bc_tree(ctypes.byref(desc), ctypes.byref(h)))
     return Tree(h)
@@ -260,6 +287,19 @@ def vtv_apply(plan, f, u, stream=None):
     n = plan.n_leaves
     _check(lib().bcv_vtv_apply(plan.handle, _dev_ptr(f, n, plan.device, "f"), _dev_ptr(u, n, plan.device, "u"),
                                _stream(stream, plan.device)))
+
+
+def vtv_apply_batched(plans, fs, us, stream=None):
+    """u_i <- VtV potential of f_i for every plan i, one after another on one stream
+    (bcv_vtv_apply_batched); fs, us: float64 device tensors, one per plan."""
+    n = len(plans)
+    if not (len(fs) == n and len(us) == n and n > 0):
+        raise ValueError("one density and one potential per plan")
+    dev = plans[0].device
+    hp = (ctypes.c_void_p * n)(*[p.handle for p in plans])
+    fp = (ctypes.c_void_p * n)(*[_dev_ptr(f, p.n_leaves, p.device, "f") for p, f in zip(plans, fs)])
+    up = (ctypes.c_void_p * n)(*[_dev_ptr(u, p.n_leaves, p.device, "u") for p, u in zip(plans, us)])
+    _check(lib().bcv_vtv_apply_batched(hp, n, fp, up, _stream(stream, dev)))
 
 
 def vtv_apply_parts(plan, f, u, parts, stream=None):

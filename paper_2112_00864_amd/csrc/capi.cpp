@@ -1,5 +1,6 @@
 // extern "C" entry points of bcv.h: argument checks, handle checks, and translation of C++
 // exceptions into bcv_status plus a thread-local message.
+#include <cmath>
 #include <new>
 #include <string>
 #include <vector>
@@ -10,7 +11,7 @@
 
 namespace bcv {
 bcv_tree_s *build_tree(int L, int marking);
-bcv_tree_s *build_forest(int n, const int *Ls, const int *markings);
+bcv_tree_s *build_forest(int n, const int *Ls, const int *markings, const double *lo, const double *side);
 bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int device);
 void destroy_plan(bcv_plan_s *p);
 void touching_integrals(int device, double out[kTouchClasses]);
@@ -63,10 +64,35 @@ void check_device(int device)
     BCV_REQUIRE(device >= 0 && device < n_dev, BCV_EINVAL, "no such HIP device");
 }
 
+// A mesh description: level, marking rule and a cube domain; writes the cube's lower corner and side.
+void check_mesh_desc(const bcv_mesh_desc &d, double lo[3], double *side)
+{
+    BCV_REQUIRE(d.L >= 2 && d.L <= 9, BCV_EINVAL, "L must be in 2..9");
+    BCV_REQUIRE(d.marking == 0 || d.marking == 1, BCV_EINVAL, "marking must be 0 or 1");
+    BCV_REQUIRE(d.geometry != BCV_GEOM_BALL, BCV_ENOTSUP, "cube-to-ball mapped meshes are not built");
+    BCV_REQUIRE(d.geometry == BCV_GEOM_BOX, BCV_EINVAL, "geometry must be BCV_GEOM_BOX");
+    bool unit = true;
+    for (int ax = 0; ax < 3; ++ax) unit = unit && d.lo[ax] == 0.0 && d.hi[ax] == 0.0;
+    if (unit) {
+        lo[0] = lo[1] = lo[2] = 0.0;
+        *side = 1.0;
+        return;
+    }
+    const double s = d.hi[0] - d.lo[0];
+    BCV_REQUIRE(std::isfinite(s) && s > 0.0, BCV_EINVAL, "the box must have a positive side");
+    for (int ax = 0; ax < 3; ++ax) {
+        BCV_REQUIRE(std::isfinite(d.lo[ax]) && std::isfinite(d.hi[ax]), BCV_EINVAL, "the box must be finite");
+        BCV_REQUIRE(std::fabs((d.hi[ax] - d.lo[ax]) - s) <= 1e-12 * s, BCV_EINVAL,
+                    "the box must be a cube (the same side on every axis)");
+        lo[ax] = d.lo[ax];
+    }
+    *side = s;
+}
+
 void check_plan_opts(const bcv_plan_opts &o, int device)
 {
     BCV_REQUIRE(o.eta0 == 0.5, BCV_EINVAL, "eta0 must be 0.5");
-    BCV_REQUIRE(o.q == 4 || o.q == 6 || o.q == 8, BCV_EINVAL, "q must be 4, 6 or 8");
+    BCV_REQUIRE(o.q >= 4 && o.q <= 10, BCV_EINVAL, "q must be in 4..10");
     BCV_REQUIRE(o.precision == BCV_FP64 || o.precision == BCV_MIXED_F32 || o.precision == BCV_MIXED_SPLIT16,
                 BCV_EINVAL, "precision must be BCV_FP64, BCV_MIXED_F32 or BCV_MIXED_SPLIT16");
     BCV_REQUIRE(o.direct == 0 || o.direct == 1, BCV_EINVAL, "direct must be 0 or 1");
@@ -82,6 +108,8 @@ void check_plan_opts(const bcv_plan_opts &o, int device)
     BCV_REQUIRE(o.q_schedule == 0 || o.q_schedule == 1, BCV_EINVAL, "q_schedule must be 0 or 1");
     BCV_REQUIRE(o.q_schedule == 0 || o.boundary == 0, BCV_ENOTSUP,
                 "level-dependent orders are not combined with the boundary (BtV/VtB) structures");
+    BCV_REQUIRE(o.q == 4 || o.q == 6 || o.q == 8 || o.boundary == 0, BCV_ENOTSUP,
+                "the boundary (BtV/VtB) structures need q = 4, 6 or 8");
     BCV_REQUIRE(o.near_order == 0 || o.nearfield == BCV_NEAR_ASSEMBLED, BCV_EINVAL,
                 "near_order 1 needs the assembled near field (BCV_NEAR_ASSEMBLED)");
     if (o.surrogate) {
@@ -127,13 +155,13 @@ bcv_status bcv_build_bc_forest(int n_meshes, const bcv_mesh_desc *descs, bcv_tre
         *out = nullptr;
         BCV_REQUIRE(n_meshes >= 1 && n_meshes <= 4096, BCV_EINVAL, "n_meshes must be in 1..4096");
         std::vector<int> Ls(n_meshes), marks(n_meshes);
+        std::vector<double> lo(3 * (size_t)n_meshes), side(n_meshes);
         for (int m = 0; m < n_meshes; ++m) {
-            BCV_REQUIRE(descs[m].L >= 2 && descs[m].L <= 9, BCV_EINVAL, "L must be in 2..9");
-            BCV_REQUIRE(descs[m].marking == 0 || descs[m].marking == 1, BCV_EINVAL, "marking must be 0 or 1");
+            check_mesh_desc(descs[m], &lo[3 * (size_t)m], &side[m]);
             Ls[m] = descs[m].L;
             marks[m] = descs[m].marking;
         }
-        *out = bcv::build_forest(n_meshes, Ls.data(), marks.data());
+        *out = bcv::build_forest(n_meshes, Ls.data(), marks.data(), lo.data(), side.data());
     });
 }
 
@@ -154,9 +182,10 @@ bcv_status bcv_build_bc_tree(const bcv_mesh_desc *desc, bcv_tree *out)
     return guard([&] {
         BCV_REQUIRE(desc != nullptr && out != nullptr, BCV_EINVAL, "NULL argument");
         *out = nullptr;
-        BCV_REQUIRE(desc->L >= 2 && desc->L <= 9, BCV_EINVAL, "L must be in 2..9");
-        BCV_REQUIRE(desc->marking == 0 || desc->marking == 1, BCV_EINVAL, "marking must be 0 or 1");
-        *out = bcv::build_tree(desc->L, desc->marking);
+        double lo[3], side = 1.0;
+        check_mesh_desc(*desc, lo, &side);
+        const int L = desc->L, marking = desc->marking;
+        *out = bcv::build_forest(1, &L, &marking, lo, &side);
     });
 }
 
@@ -169,16 +198,49 @@ bcv_status bcv_tree_num_leaves(bcv_tree tree, int64_t *n)
     });
 }
 
-bcv_status bcv_tree_leaves(bcv_tree tree, int32_t *level_ijk)
+bcv_status bcv_tree_leaves(bcv_tree tree, int32_t *level_ijk, double *gauss_xyz, double *gauss_w)
 {
     return guard([&] {
         check_tree(tree);
-        BCV_REQUIRE(level_ijk != nullptr, BCV_EINVAL, "NULL argument");
+        const double node[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
         for (int64_t l = 0; l < tree->n_leaves(); ++l) {
             const int32_t c = tree->leaf_cell[l];
-            level_ijk[4 * l] = tree->level[c];
-            for (int ax = 0; ax < 3; ++ax) level_ijk[4 * l + 1 + ax] = tree->ijk[3 * c + ax];
+            const int lev = tree->level[c];
+            if (level_ijk) {
+                level_ijk[4 * l] = lev;
+                for (int ax = 0; ax < 3; ++ax) level_ijk[4 * l + 1 + ax] = tree->ijk[3 * c + ax];
+            }
+            if (!gauss_xyz && !gauss_w) continue;
+            const int m = (tree->ijk[3 * c] >> lev) / 4;  // mesh m occupies [4m, 4m + 1) in level-0 units
+            const double s = tree->mesh_side[m], a = std::ldexp(s, -lev);
+            const int64_t local[3] = {tree->ijk[3 * c] - ((int64_t)4 * m << lev), tree->ijk[3 * c + 1],
+                                      tree->ijk[3 * c + 2]};
+            for (int g = 0; g < 8; ++g) {
+                if (gauss_xyz)
+                    for (int ax = 0; ax < 3; ++ax)
+                        gauss_xyz[(8 * l + g) * 3 + ax] =
+                            tree->mesh_lo[3 * m + ax] + a * ((double)local[ax] + node[(g >> ax) & 1]);
+                if (gauss_w) gauss_w[8 * l + g] = a * a * a * 0.125;
+            }
         }
+    });
+}
+
+bcv_status bcv_vtv_apply_batched(const bcv_plan *plans, int n, const double *const *f_dev, double *const *u_dev,
+                                 void *hip_stream)
+{
+    return guard([&] {
+        BCV_REQUIRE(plans != nullptr && f_dev != nullptr && u_dev != nullptr, BCV_EINVAL, "NULL argument");
+        BCV_REQUIRE(n >= 1 && n <= 4096, BCV_EINVAL, "n must be in 1..4096");
+        for (int i = 0; i < n; ++i) {
+            check_plan(plans[i]);
+            BCV_REQUIRE(f_dev[i] != nullptr && u_dev[i] != nullptr, BCV_EINVAL, "NULL density or potential pointer");
+            BCV_REQUIRE(plans[i]->device == plans[0]->device, BCV_EINVAL, "the plans live on different devices");
+        }
+        on_device(plans[0]->device, [&] {
+            for (int i = 0; i < n; ++i)
+                bcv::launch_apply(*plans[i], f_dev[i], u_dev[i], BCV_PART_NEAR | BCV_PART_FAR, (hipStream_t)hip_stream);
+        });
     });
 }
 

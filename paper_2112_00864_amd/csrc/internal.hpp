@@ -24,6 +24,9 @@ struct bcv_tree_s {
     // and has finest level mesh_L[m].
     int n_meshes = 1;
     std::vector<int> mesh_L;
+    // Physical domain of each mesh: the cube with lower corner mesh_lo[3m..3m+2] and side mesh_side[m]
+    // (the unit cube unless the description says otherwise).
+    std::vector<double> mesh_lo, mesh_side;
 
     int64_t n_cells() const { return (int64_t)level.size(); }
     int64_t n_leaves() const { return (int64_t)leaf_cell.size(); }
@@ -138,6 +141,7 @@ struct bcv_plan_s {
             n_m2l_read_lanes = 0;
     int64_t device_bytes = 0;
     double touch_value[bcv::kTouchClasses];  // touching integrals / (4 pi), smaller side 1
+    double *d_uscale = nullptr;  // per leaf: side^5 of its mesh, when some mesh is not the unit cube (else NULL)
     int surrogate_classes = 0;               // classes whose value came from the surrogate
 
     // Second stream for the near field (streams == 2) and its fork/join events.

@@ -1209,6 +1209,13 @@ __global__ __launch_bounds__(256) void near_combine_kernel(int64_t n_splits, con
     if (lane == 0) u[sp.target] = v;
 }
 
+// u[i] *= scale[i] (the side^5 factor of a domain that is not the unit cube).
+__global__ __launch_bounds__(256) void scale_kernel(int64_t n, const double *__restrict__ scale, double *__restrict__ u)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) u[i] *= scale[i];
+}
+
 // ---- evaluation phase alone (near field computed concurrently): u += a^3 sum_a kappa_a Lambda^a --
 // One wave per leaf.
 template <int Q>
@@ -2014,6 +2021,10 @@ void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStre
         launch_near<Q>(p, f, far ? p.d_Lam : nullptr, (near ? BCV_PART_NEAR : 0) | (far ? BCV_PART_FAR : 0), u, st);
         marks.stop(BCV_PHASE_NEAR, st);
     }
+    if (p.d_uscale != nullptr) {  // domains of side s != 1: u = s^5 u(unit cube)
+        scale_kernel<<<(unsigned)((p.n_leaves + 255) / 256), 256, 0, st>>>(p.n_leaves, p.d_uscale, u);
+        check_launch();
+    }
     marks.finish(st);
 }
 
@@ -2111,6 +2122,10 @@ void launch_btv(const bcv_plan_s &p, const double *qf, const double *gf, double 
 
 void launch_apply(const bcv_plan_s &p, const double *f, double *u, int parts, hipStream_t st)
 {
+    if (p.q_schedule) {  // every phase picks its kernels by the level's order (the template order is unused)
+        apply_q<4>(p, f, u, parts, st);
+        return;
+    }
     switch (p.q) {
     case 4: apply_q<4>(p, f, u, parts, st); break;
     case 6: apply_q<6>(p, f, u, parts, st); break;

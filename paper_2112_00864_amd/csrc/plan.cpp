@@ -860,17 +860,25 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         BCV_HIP(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
         BCV_HIP(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
     }
-    // expansion orders per level and the row strides of the coefficient arrays
-    p->q_schedule = opts.q_schedule;
+    // expansion orders per level and the row strides of the coefficient arrays. Orders without
+    // kernels of their own (fixed q other than 4, 6, 8) run the level-by-level kernels of the
+    // level-dependent orders with the same order on every level.
+    const bool per_level = opts.q_schedule || !(opts.q == 4 || opts.q == 6 || opts.q == 8);
+    p->q_schedule = per_level;
     int q_max = opts.q;
     for (int lev = 0; lev <= kMaxLevel; ++lev) {
         p->q_level[lev] = opts.q_schedule ? opts.q + t.L - std::max(lev, 2) : opts.q;
         if (lev <= t.L) q_max = std::max(q_max, p->q_level[lev]);
     }
-    if (opts.q_schedule) {
-        BCV_REQUIRE(t.n_meshes == 1, BCV_ENOTSUP, "level-dependent orders: single-mesh trees only");
+    if (per_level) {
+        BCV_REQUIRE(t.n_meshes == 1, BCV_ENOTSUP,
+                    "level-dependent orders and fixed orders other than 4, 6, 8: single-mesh trees only");
         BCV_REQUIRE(q_max <= kMaxSchedQ, BCV_EINVAL, "level-dependent orders: q + L - 2 must not exceed 10");
     }
+    // meshes whose cube is not the unit cube: the apply scales u by side^5 (boundary plans: unit side only)
+    bool scaled = false;
+    for (int m = 0; m < t.n_meshes; ++m) scaled = scaled || t.mesh_side[m] != 1.0;
+    BCV_REQUIRE(!scaled || !opts.boundary, BCV_ENOTSUP, "the boundary (BtV/VtB) structures need a domain of side 1");
     p->K = ncoef(q_max);
     p->R = (q_max + 1) * (q_max + 1);
     p->n_leaves = t.n_leaves();
@@ -913,6 +921,15 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
     }
     p->d_leaf_geom = upload(p.get(), lg);
     p->d_leaf_cell = upload(p.get(), t.leaf_cell);
+    if (scaled) {
+        std::vector<double> us(p->n_leaves);
+        for (int64_t l = 0; l < p->n_leaves; ++l) {
+            const int32_t c = t.leaf_cell[l];
+            const double sd = t.mesh_side[(t.ijk[3 * c] >> t.level[c]) / 4];
+            us[l] = sd * sd * sd * sd * sd;
+        }
+        p->d_uscale = upload(p.get(), us);
+    }
 
     NearCSR vol_near;  // kept for the VtB rows
     // Level-dependent near-field rule: per-leaf Gauss orders and the entries that need them.
@@ -973,13 +990,13 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         // (q_l / q)^4 times more and its few tasks would run as a handful of long waves: its pieces
         // are halved per order above q (at least 8 slots), so more waves share the work.
         const int32_t slots = opts.m2l_max_slots > 0 ? opts.m2l_max_slots
-                                                     : (opts.q_schedule ? kDefaultMaxSlotsSchedule : kDefaultMaxSlots);
+                                                     : (per_level ? kDefaultMaxSlotsSchedule : kDefaultMaxSlots);
         std::vector<int32_t> level_slots(t.L + 1, slots);
-        if (opts.q_schedule)
+        if (per_level)
             for (int lev = 0; lev <= t.L; ++lev)
                 level_slots[lev] = std::max<int32_t>(8, slots >> std::min(16, p->q_level[lev] - opts.q));
-        M2LPlan m2l = build_m2l(t, grids, level_slots, opts.q_schedule != 0,
-                                opts.m2l_max_slots == 0 && !opts.q_schedule ? kDefaultMaxSlotsSchedule : 0);
+        M2LPlan m2l = build_m2l(t, grids, level_slots, per_level,
+                                opts.m2l_max_slots == 0 && !per_level ? kDefaultMaxSlotsSchedule : 0);
         std::vector<int32_t> id_of_key(15 * 15 * 15, -1);
         for (int32_t key : m2l.slot_key) id_of_key[key & 0x7FFFFFFF] = 0;
         std::vector<double> G;
@@ -1110,7 +1127,7 @@ void destroy_plan(bcv_plan_s *p)
                     p->d_splits, p->d_partial, p->d_M, p->d_Lam, p->d_G,
                     p->d_M32, p->d_Mr, p->d_G32,
                     p->d_parents, p->d_tasks, p->d_task_targets, p->d_slot_off, p->d_slot_src,
-                    p->d_slot_mask, p->d_m2l_A, p->d_G48, p->d_M16, p->d_fscale,
+                    p->d_slot_mask, p->d_m2l_A, p->d_G48, p->d_M16, p->d_fscale, p->d_uscale,
                     p->d_m2l_splits, p->d_m2l_partial, p->d_faces, p->d_leaf_faces, p->d_btv_col,
                     p->d_btv_units, p->d_btv_splits, p->d_btv_partial, p->d_btv_touch, p->d_vtb_col,
                     p->d_vtb_units, p->d_vtb_splits, p->d_vtb_partial};

@@ -1,6 +1,8 @@
-// BC octree of the unit cube (Sec. 2, Boundary Concentrated Mesh, with cube cells).
+// BC octree of a cube (Sec. 2, Boundary Concentrated Mesh, with cube cells).
 //
-// Level 0 is [0,1]^3. A level-l cell (i, j, k) is the cube [i, i+1] x [j, j+1] x [k, k+1] times 2^-l.
+// In reference coordinates level 0 is [0,1]^3 and a level-l cell (i, j, k) is the cube
+// [i, i+1] x [j, j+1] x [k, k+1] times 2^-l; the physical domain is lo + side [0,1]^3 (mesh_lo,
+// mesh_side), and every operator follows from the reference one by the scalings stated in bcv.h.
 // For l < L the marked cells M_l are, by marking rule,
 //   0: the cells with a face on the boundary (B_l);
 //   1: the cells with a boundary cell among their neighbours, N(w) meeting B_l (the rule of Sec. 2);
@@ -37,13 +39,18 @@ static bool near_boundary(int lev, int32_t i, int32_t j, int32_t k)
 // (in units of a level-0 cell), so cells of different meshes are never neighbours at any level
 // (their integer offsets are at least 4 * 2^l - 2^l > sqrt(12) apart at level l) and the planner
 // treats the forest as one mesh. With n = 1 this is the single mesh of the unit cube.
-bcv_tree_s *build_forest(int n, const int *Ls, const int *markings)
+// lo (3 per mesh) and side (1 per mesh) place each mesh's cube in physical space; NULL: unit cubes.
+bcv_tree_s *build_forest(int n, const int *Ls, const int *markings, const double *lo, const double *side)
 {
     auto *t = new bcv_tree_s;
     t->L = 0;
     for (int m = 0; m < n; ++m) t->L = std::max(t->L, Ls[m]);
     t->n_meshes = n;
     t->mesh_L.assign(Ls, Ls + n);
+    t->mesh_lo.assign(3 * (size_t)n, 0.0);
+    t->mesh_side.assign(n, 1.0);
+    if (lo) std::copy(lo, lo + 3 * n, t->mesh_lo.begin());
+    if (side) std::copy(side, side + n, t->mesh_side.begin());
     auto push = [&](int32_t i, int32_t j, int32_t k, int lev, int32_t par) {
         t->ijk.push_back(i);
         t->ijk.push_back(j);
@@ -90,7 +97,7 @@ bcv_tree_s *build_forest(int n, const int *Ls, const int *markings)
     return t;
 }
 
-bcv_tree_s *build_tree(int L, int marking) { return build_forest(1, &L, &marking); }
+bcv_tree_s *build_tree(int L, int marking) { return build_forest(1, &L, &marking, nullptr, nullptr); }
 
 // Boundary faces of the unit cube: the faces of level-L leaves in the planes x, y, z = 0 or 1
 // (a cell meeting the boundary has a face on it and is refined down to level L).

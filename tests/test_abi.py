@@ -61,7 +61,7 @@ def test_tree_argument_errors():
 
 def test_plan_argument_errors_before_device_use():
     t = bcv.build_bc_tree(3)
-    for kw in ({"q": 5}, {"eta0": 0.4}, {"near_order": 2}, {"near_order": 1},  # 1 needs the assembled mode
+    for kw in ({"q": 3}, {"eta0": 0.4}, {"near_order": 2}, {"near_order": 1},  # 1 needs the assembled mode
                {"near_order": 1, "nearfield": bcv.NEAR_QUADRATURE}, {"q_schedule": 2}):
         with pytest.raises(bcv.BCVError) as e:
             bcv.plan_interactions(t, **kw)
@@ -116,4 +116,43 @@ def test_forest_argument_errors():
     for Ls in ([], [1], [10], [3, 0]):
         with pytest.raises(bcv.BCVError) as e:
             bcv.build_bc_forest(Ls)
+        assert e.value.status == bcv.bcv.EINVAL
+
+
+def test_mesh_geometry_arguments():
+    """Geometry: a cube box is accepted, a non-cube box or a zero side is refused, the ball map is
+    not built (BCV_ENOTSUP)."""
+    t = bcv.build_bc_tree(3, lo=(1.0, -2.0, 0.5), hi=(3.0, 0.0, 2.5))
+    assert t.num_leaves() == len(BCMesh(3).leaf_array())
+    for lo, hi in (((0, 0, 0), (1, 2, 1)), ((0, 0, 0), (0, 1, 1)), ((1, 1, 1), (0, 0, 0))):
+        with pytest.raises(bcv.BCVError) as e:
+            bcv.build_bc_tree(3, lo=lo, hi=hi)
+        assert e.value.status == bcv.bcv.EINVAL
+    with pytest.raises(bcv.BCVError) as e:
+        bcv.build_bc_tree(3, geometry=bcv.GEOM_BALL)
+    assert e.value.status == bcv.bcv.ENOTSUP
+
+
+@pytest.mark.parametrize("lo,side", [((0.0, 0.0, 0.0), 1.0), ((1.0, -2.0, 0.5), 2.0)])
+def test_gauss_points_match_oracle(lo, side):
+    """The library's Gauss points and weights against the oracle's point rule on the unit cube,
+    mapped to the cube lo + side [0,1]^3."""
+    from oracle import direct
+
+    L = 4
+    hi = tuple(x + side for x in lo)
+    t = bcv.build_bc_tree(L, lo=lo, hi=hi)
+    xyz, w = t.gauss_points()
+    lv = BCMesh(L).leaf_array()
+    a = np.ldexp(1.0, -lv[:, 0].astype(np.int32))
+    pts, wo = direct.gauss_points(lv[:, 1:4] * a[:, None], a)
+    assert np.allclose(xyz, np.asarray(lo) + side * pts, rtol=0, atol=1e-15 * side)
+    assert np.allclose(w, side ** 3 * np.broadcast_to(wo[:, None], w.shape), rtol=1e-15, atol=0)
+
+
+def test_order_range():
+    t = bcv.build_bc_tree(3)
+    for q in (3, 11):
+        with pytest.raises(bcv.BCVError) as e:
+            bcv.plan_interactions(t, q=q)
         assert e.value.status == bcv.bcv.EINVAL
