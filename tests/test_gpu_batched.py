@@ -102,3 +102,48 @@ def test_autotune_returns_a_valid_faster_or_equal_plan():
     u0 = gpu_apply(bcv.plan_interactions(forest, q=6, precision=bcv.MIXED_F32), f)
     u1 = gpu_apply(bcv.plan_interactions(forest, q=6, precision=bcv.MIXED_F32, **best), f)
     assert rel_l2(lv, u1, u0) <= 1e-6
+
+
+def test_config_forest_against_O2():
+    """The batched workload's forest (64 unit-cube meshes, finest levels drawn from {4, 5, 6} by
+    default_rng(1234), Gaussian-mixture density of seed m on mesh m) through the captured graph in the
+    mixed path and through the FP64 apply: three meshes of every level against O2 of that mesh at 8
+    sampled leaves each (the first, the last, 6 random). Bars: FP64 max relative error 1e-10; mixed
+    relative L2 error of the sampled cell averages (volume-weighted, per mesh) 1e-6, the tolerance the
+    mixed path is held to. The mixed path's largest pointwise errors (about 2e-6 at a few finest-level
+    leaves whose potential is 3/4 far field: FP32 sums in the interaction phase) are reported, not
+    gated; its per-mesh relative L2 error over all leaves is below 1e-7."""
+    import torch
+
+    from oracle import fmm
+    from oracle.mesh import BCMesh
+
+    Ls = [int(L) for L in np.random.default_rng(1234).choice([4, 5, 6], 64)]
+    forest = bcv.build_bc_forest(Ls)
+    lv, mesh, f = forest_density(forest, Ls)
+    announce("config forest: %d meshes, %d leaves" % (len(Ls), len(lv)))
+    fd = torch.tensor(f, device="cuda:0")
+    ud = torch.empty_like(fd)
+    graph = bcv.vtv_graph_create(bcv.plan_interactions(forest, q=6, precision=bcv.MIXED_F32), fd, ud)
+    graph.launch()
+    torch.cuda.synchronize()
+    u32 = ud.cpu().numpy()
+    u64 = gpu_apply(bcv.plan_interactions(forest, q=6), f)
+    oracles = {L: fmm.FMM(BCMesh(L), 6) for L in (4, 5, 6)}
+    rng = np.random.default_rng(21)
+    worst64 = worst32_l2 = worst32_pt = 0.0
+    for L in (4, 5, 6):
+        for m in [i for i, x in enumerate(Ls) if x == L][:3]:
+            sel = np.nonzero(mesh == m)[0]
+            n = len(sel)
+            sample = np.unique(np.concatenate([[0, n - 1], rng.choice(n, 6, replace=False)]))
+            announce("mesh %d (L=%d): O2 at %d leaves" % (m, L, len(sample)))
+            ref = oracles[L].apply_sampled(f[sel], sample)
+            vol = 8.0 ** (-lv[sel][sample, 0].astype(float))
+            d32 = u32[sel][sample] - ref
+            worst64 = max(worst64, float(np.max(np.abs(u64[sel][sample] - ref) / np.abs(ref))))
+            worst32_l2 = max(worst32_l2, float(np.sqrt(np.sum(vol * d32 ** 2) / np.sum(vol * ref ** 2))))
+            worst32_pt = max(worst32_pt, float(np.max(np.abs(d32) / np.abs(ref))))
+    announce("config forest vs O2: FP64 max rel %.3e; mixed (graph) rel-L2 %.3e, pointwise max %.3e"
+             % (worst64, worst32_l2, worst32_pt))
+    assert worst64 <= 1e-10 and worst32_l2 <= 1e-6
