@@ -8,13 +8,17 @@ it; the two meet only through the seeded densities of the `synth` package.
 Contents (each function cites the passage of the paper it follows):
   mesh.py      BC refinement (Sec. 2: B_l, M_l, L_l, C_{l+1}, L*_l), neighbours (eq. def:neighbors),
                interaction lists (Sec. 2), extended neighbour lists N* (Sec. 3, Lemma 1).
-  touching.py  exact integrals of 1/|x-y| over touching cube pairs (convolution + Duffy).
+  touching.py  exact integrals of 1/|x-y| over touching cube pairs (convolution + Duffy), also
+               with Legendre polynomial weights on both boxes.
   taylor.py    multi-indices and Taylor coefficients of 1/|r+h| (binomial series).
   direct.py    O1: u = A f by direct O(N^2) evaluation of the Galerkin entries.
   fmm.py       O2: Algorithm 1 step by step (near field, moments, upward pass, interaction
                phase, downward pass, evaluation) in FP64.
   mlp.py       the touching-pair surrogate's network in FP64: forward pass, training loss and its
                gradient by the chain rule (reference for the GPU kernels' gradients).
+  basis.py     degree-p leaf bases (p_l = L - l, Legendre tensor polynomials): O1 and O2 with
+               polynomial leaf spaces, entry blocks (exact where the cubes touch, via
+               touching.box_pair_poly), projection of a density onto the leaf spaces.
   boundary.py  BtV (Algorithm 3): single- and double-layer entries of (leaf, boundary face) pairs
                (exact by convolution where they touch, point rule elsewhere), O1 by direct
                summation and O2 step by step.

@@ -155,3 +155,89 @@ def classify(lo_t, size_t, lo_s, size_s):
     if big != 2 * small or n_contact == 0:
         raise AssertionError("touching cells violate 2:1 balance")
     return ("face2", "edge2", "vertex2")[n_contact - 1]
+
+
+# -- polynomial weights (degree-p leaf bases) ------------------------------------------------------
+#
+# With tensor-product weights P(x) = prod_i P_{a_i}(.) on A and Q(y) = prod_i P_{b_i}(.) on B the
+# same reduction holds with a weighted overlap per axis:
+#
+#   int_A int_B P(x) Q(y) / |x - y| dy dx = int_{R^3} prod_i c_i(u_i) / |u| du,
+#   c_i(u) = int over [alo_i, ahi_i] cap [blo_i + u, bhi_i + u] of p_i(x) q_i(x - u) dx,
+#
+# and c_i is a polynomial in u between the same kinks (the limits move linearly with u), of degree
+# at most deg p_i + deg q_i + 1. Each c_i(u) is itself computed by Gauss-Legendre on the overlap
+# interval with enough nodes to be exact.
+
+
+def legendre_table(t, p):
+    """P_k(t) for k = 0..p (three-term recurrence): array (p + 1,) + t.shape."""
+    t = np.asarray(t, dtype=np.float64)
+    out = [np.ones_like(t), t.copy()]
+    for k in range(1, p):
+        out.append(((2 * k + 1) * t * out[k] - k * out[k - 1]) / (k + 1))
+    return np.stack(out[: p + 1])
+
+
+def _weighted_overlap(u, alo, ahi, blo, bhi, pa, pb):
+    """c^{ab}(u) for all a <= pa, b <= pb at points u (any shape): array u.shape + (pa + 1, pb + 1).
+
+    The weights are the Legendre polynomials of each box's own axis, P_a(2(x - ca)/sa) on A and
+    P_b(2(y - cb)/sb) on B (y = x - u)."""
+    u = np.asarray(u, dtype=np.float64)
+    lo = np.maximum(alo, blo + u)
+    hi = np.minimum(ahi, bhi + u)
+    ln = np.maximum(hi - lo, 0.0)
+    m = (pa + pb) // 2 + 1
+    t, w = np.polynomial.legendre.leggauss(m)
+    t, w = 0.5 * (t + 1.0), 0.5 * w
+    x = lo[..., None] + ln[..., None] * t  # u.shape + (m,)
+    ca, sa = 0.5 * (alo + ahi), ahi - alo
+    cb, sb = 0.5 * (blo + bhi), bhi - blo
+    Pa = legendre_table(2.0 * (x - ca) / sa, pa)  # (pa+1,) + u.shape + (m,)
+    Pb = legendre_table(2.0 * (x - u[..., None] - cb) / sb, pb)
+    return np.einsum("a...k,b...k,k,...->...ab", Pa, Pb, w, ln)
+
+
+def box_pair_poly(a_lo, a_hi, b_lo, b_hi, pa, pb, n=30):
+    """int_A int_B P_alpha(x) P_beta(y) / |x - y| dy dx for all alpha in [0, pa]^3, beta in [0, pb]^3,
+    with P_alpha(x) = prod_i P_{alpha_i}(2 (x_i - centre_i)/side_i) the Legendre tensor polynomial of
+    each box: array (pa+1,)*3 + (pb+1,)*3 indexed [ax, ay, az, bx, by, bz]. Degree 0 is
+    box_pair_integral."""
+    a_lo, a_hi, b_lo, b_hi = (np.asarray(v, dtype=np.float64) for v in (a_lo, a_hi, b_lo, b_hi))
+    breaks = [_axis_breaks(a_lo[i], a_hi[i], b_lo[i], b_hi[i]) for i in range(3)]
+    g, gw = _gauss01(n)
+    total = np.zeros((pa + 1,) * 3 + (pb + 1,) * 3)
+    for ix in range(len(breaks[0]) - 1):
+        for iy in range(len(breaks[1]) - 1):
+            for iz in range(len(breaks[2]) - 1):
+                lo = np.array([breaks[0][ix], breaks[1][iy], breaks[2][iz]])
+                hi = np.array([breaks[0][ix + 1], breaks[1][iy + 1], breaks[2][iz + 1]])
+                total += _sub_box_poly(lo, hi, a_lo, a_hi, b_lo, b_hi, pa, pb, g, gw)
+    return total
+
+
+def _sub_box_poly(lo, hi, a_lo, a_hi, b_lo, b_hi, pa, pb, g, gw):
+    h = hi - lo
+    ov = lambda ax, u: _weighted_overlap(u, a_lo[ax], a_hi[ax], b_lo[ax], b_hi[ax], pa, pb)  # noqa: E731
+    corner_at_origin = all(lo[i] == 0.0 or hi[i] == 0.0 for i in range(3))
+    if not corner_at_origin:
+        u = [lo[i] + h[i] * g for i in range(3)]
+        C = [ov(i, u[i]) * (gw * h[i])[:, None, None] for i in range(3)]  # (n, pa+1, pb+1) per axis
+        R = 1.0 / np.sqrt(u[0][:, None, None] ** 2 + u[1][None, :, None] ** 2 + u[2][None, None, :] ** 2)
+        return np.einsum("xyz,xad,ybe,zcf->abcdef", R, C[0], C[1], C[2], optimize=True)
+    sigma = np.array([1.0 if lo[i] == 0.0 else -1.0 for i in range(3)])
+    out = np.zeros((pa + 1,) * 3 + (pb + 1,) * 3)
+    for kax in range(3):
+        # Duffy pyramid with axis kax largest: v_k = h_k t, v_j = h_j t s_j; Jacobian h1 h2 h3 t^2,
+        # |u| = t rho(s), so the integrand is t * numerator / rho.
+        j1, j2 = [j for j in range(3) if j != kax]
+        Ck = ov(kax, sigma[kax] * h[kax] * g) * (gw * g * h[0] * h[1] * h[2])[:, None, None]  # (t, a, b)
+        C1 = ov(j1, sigma[j1] * h[j1] * g[:, None] * g[None, :]) * gw[None, :, None, None]  # (t, s1, a, b)
+        C2 = ov(j2, sigma[j2] * h[j2] * g[:, None] * g[None, :]) * gw[None, :, None, None]  # (t, s2, a, b)
+        rho = np.sqrt(h[kax] ** 2 + (h[j1] * g[:, None]) ** 2 + (h[j2] * g[None, :]) ** 2)  # (s1, s2)
+        T = np.einsum("uv,tab,tucd,tvef->acebdf", 1.0 / rho, Ck, C1, C2, optimize=True)
+        # T is indexed [a_k, a_j1, a_j2, b_k, b_j1, b_j2]: put the axes back in x, y, z order
+        perm = np.argsort([kax, j1, j2])
+        out += T.transpose(list(perm) + [3 + q for q in perm])
+    return out
