@@ -379,6 +379,50 @@ def measure_schedule(bcv, torch, tree, f, args, dev, u_ref):
     return res
 
 
+def measure_basis(bcv, torch, args, dev):
+    """Degree-p leaf bases p_l = L - l (Sec. 4), FP64, q = args.q, on the unit-cube mesh of level
+    args.basis_L: the projection of the seed-0 Gaussian mixture onto every leaf's Legendre
+    polynomials as input, `args.steps` applies timed after `args.warmup`, with per-phase HIP events
+    (one stream). Roofline of the near field (block rows streamed from HBM): 8 B per block entry +
+    12 B per column (index and gathered coefficient) + 8 B per output coefficient."""
+    import synth
+
+    L = args.basis_L
+    tree = bcv.build_bc_tree(L)
+    lv = tree.leaves().astype(np.int64)
+    c, w = synth.gaussian_mixture_params(0)
+    coef, off = synth.legendre_coefficients(lv, L, lambda x: synth.gaussian_mixture(x, c, w))
+    nl = len(lv)
+    nb = np.diff(off)
+    f = np.empty(off[-1])
+    f[:nl] = coef[off[:-1]]  # the library's layout: degree-0 coefficients first, then the rest leaf by leaf
+    hi = np.concatenate([[0], np.cumsum(nb - 1)])
+    for k in np.nonzero(nb > 1)[0]:
+        f[nl + hi[k] : nl + hi[k + 1]] = coef[off[k] + 1 : off[k + 1]]
+    t0 = time.perf_counter()
+    plan = bcv.plan_interactions(tree, q=args.q, device=dev, streams=1, basis_degree=1)
+    plan_s = time.perf_counter() - t0
+    fd = torch.tensor(f, device="cuda:%d" % dev)
+    ud = torch.empty_like(fd)
+    ms, phases = timed_applies(bcv, torch, plan, fd, ud, args.warmup, args.steps, dev)
+    info = plan.info
+    near_bytes = 8 * info["n_basis_vals"] + 12 * info["n_basis_cols"] + 8 * info["n_dofs"]
+    near_ms = phases["near"]
+    res = {"metric": "VtV coefficient-potentials/s, degree-p leaf bases p_l = L - l, FP64, 1 GPU",
+           "unit": "coefficient-potentials/s", "workload": "unit cube BC octree h=1/%d (L=%d), %d leaves, %d basis "
+           "coefficients (degrees 0..%d), q=%d, projected Gaussian-mixture density seed 0, near field assembled, "
+           "1 stream" % (2 ** L, L, nl, info["n_dofs"], int(L - lv[:, 0].min()), args.q),
+           "value": info["n_dofs"] / (ms * 1e-3), "cell_potentials_per_s": nl / (ms * 1e-3), "ms_per_apply": ms,
+           "phase_ms": phases, "plan_seconds": plan_s, "plan_device_bytes": info["device_bytes"],
+           "n_near_pairs": info["n_near"], "n_block_entries": info["n_basis_vals"],
+           "n_block_columns": info["n_basis_cols"],
+           "near_roofline": {"bound": "hbm", "bytes": near_bytes, "ms": near_ms,
+                             "achieved": near_bytes / (near_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                             "frac": near_bytes / (near_ms * 1e-3) / PEAK_HBM}}
+    del plan
+    return res
+
+
 def batched(args):
     """64 unit-cube BC meshes, h drawn from {1/16, 1/32, 1/64} (default_rng(1234)), Gaussian-mixture
     density of seed m on mesh m, mixed precision (FP32 interaction phase): one forest plan with the
@@ -473,6 +517,8 @@ def main():
                     help="finest level of the extra measurements (plain FP64 config, BtV/VtB, level-dependent "
                          "orders, neighbour marking); 0 skips them all")
     ap.add_argument("--q", type=int, default=6)
+    ap.add_argument("--basis-L", type=int, default=7,
+                    help="finest level of the degree-p leaf basis measurement (0 skips it)")
     ap.add_argument("--nearfield", choices=["quadrature", "assembled"], default="assembled",
                     help="near-field entries stored once at plan time (assembled) or evaluated in every "
                          "apply (quadrature); the other mode is measured too and reported beside")
@@ -670,6 +716,9 @@ def main():
         if not args.no_marking:
             line["neighbour_marking"] = measure_marking(bcv, torch, xargs, dev)
             print("neighbour marking: %s" % json.dumps(line["neighbour_marking"]), file=sys.stderr)
+    if args.basis_L:
+        line["degree_bases"] = measure_basis(bcv, torch, args, dev)
+        print("degree bases: %s" % json.dumps(line["degree_bases"]), file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
 
 

@@ -140,6 +140,24 @@ typedef struct {
     int boundary;          /* 1: also build the BtV structures (boundary faces, their near lists
                               and touching integrals) so that bcv_btv_apply can run; single-mesh
                               trees only. 0: VtV only */
+    int basis_degree;      /* leaf bases (Sec. 1.2, the space S_h with degree-p_w polynomials on each
+                              leaf). 0: degree 0, the indicator of each leaf (one unknown per leaf).
+                              1: p_w = L - l on a leaf of level l (Sec. 4, approximation errors: this
+                              choice with degree 0 on the finest level gives the O(h) best
+                              approximation), basis phi^alpha_w(x) = prod_i P_{alpha_i}(2 (x_i - c_i)/a)
+                              (Legendre, centre c and side a of w), |alpha| <= p_w, ncoef(p_w) =
+                              (p_w+1)(p_w+2)(p_w+3)/6 unknowns per leaf; f holds the coefficients of the
+                              density in this basis and u receives u_(w,alpha) = <phi^alpha_w, N f>.
+                              Every leaf then carries the tensor Gauss rule of p_w + 2 points per
+                              axis for its non-touching pairs, moments and evaluation; touching pairs
+                              are exact (bcv_touching_basis_block). Layout of f and u: entries
+                              0 .. n_leaves-1 are the alpha = 0 coefficients in leaf order, followed
+                              by the alpha = 1 .. ncoef(p_w)-1 coefficients of every leaf with
+                              p_w > 0, leaf by leaf (alpha in the graded order of
+                              bcv_touching_basis_block); n_dofs in bcv_plan_info. The near field is
+                              assembled at plan time (opts.nearfield is ignored). Requires
+                              BCV_FP64, a fixed q of 4, 6 or 8, a single mesh of side 1, no surrogate,
+                              no opts.boundary, and L - (coarsest leaf level) <= 8 */
 } bcv_plan_opts;
 
 /* Sizes of a plan (all counts, no pointers). */
@@ -164,6 +182,11 @@ typedef struct {
     int32_t L;
     int32_t surrogate_classes; /* touching classes whose value came from the surrogate (0..6) */
     int32_t pad;
+    int64_t n_dofs;       /* length of f and u: n_leaves, or with opts.basis_degree = 1 the number of
+                             basis coefficients of all leaves */
+    int64_t n_basis_vals; /* near-field block entries held by a plan with opts.basis_degree = 1 */
+    int64_t n_basis_cols; /* their distinct columns: per target leaf, the coefficients of its near
+                             sources (shared by the target's rows) */
 } bcv_plan_info;
 
 /* Build the BC octree of Sec. 2 on the host. desc and out must be non-NULL.
@@ -336,6 +359,20 @@ bcv_status bcv_boundary_touching_integrals(double *V, double *K);
  * the cube (splitting both cubes into halves) with regular pairs integrated by a 6-D Gauss rule.
  * out: host, 7 doubles. Errors: BCV_EINVAL, BCV_EDEVICE. */
 bcv_status bcv_touching_integrals(int device, double *out);
+
+/* Exact touching block of the degree-p leaf bases (Sec. 1.2, the finite element space with
+ * polynomials on each leaf; bcv_plan_opts.basis_degree): int_t int_s phi^alpha_t(x) phi^beta_s(y)
+ * / |x - y| dy dx for two touching cubes t, s of sides side_t, side_s in {1, 2} (units of the smaller
+ * side: (1, 1), (1, 2) or (2, 1)), with s's lower corner at `offset` (3 ints, same units) from t's,
+ * phi^alpha_w(x) = prod_i P_{alpha_i}(2 (x_i - c_i)/a) (Legendre, centre c and side a of w), all
+ * |alpha| <= p_t, |beta| <= p_s in the graded order of the coefficients (total degree, then alpha_x
+ * descending, then alpha_y descending). Scale: entries of cubes with smaller side a are the values
+ * times a^5 (and 1/(4 pi) for the kernel G). Computed on the host, once per process and degree,
+ * from the self-similarity of the cube (halving both cubes, the weights re-expanded on the halves)
+ * with regular pairs integrated by a 6-D Gauss rule; no device is used. out: host,
+ * ncoef(p_t) x ncoef(p_s) doubles, row-major, ncoef(p) = (p+1)(p+2)(p+3)/6. Errors: BCV_EINVAL
+ * (NULL, degrees outside 0..8, sides or offset of cubes that do not touch or that overlap). */
+bcv_status bcv_touching_basis_block(int p_t, int p_s, int side_t, int side_s, const int *offset, double *out);
 
 /* ---- Touching-pair surrogate -------------------------------------------------------------
  * A small network (features -> width -> width -> 2, SiLU, FP32, trained on the GPU by the library's

@@ -39,4 +39,6 @@ def lib():
         _lib.o1_gauss_rule.argtypes = [f64p, ctypes.c_double, ctypes.c_int, f64p, ctypes.c_double, ctypes.c_int, f64p,
                                        f64p]
         _lib.o1_gauss_rule.restype = ctypes.c_double
+        _lib.o1_point_potential.argtypes = [ctypes.c_int64, f64p, ctypes.c_int64, f64p, f64p, f64p]
+        _lib.o1_point_potential.restype = None
     return _lib

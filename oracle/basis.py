@@ -26,7 +26,7 @@ Coefficient vectors are flat, leaf-major: leaf w's n_p(p_w) coefficients at offs
 
 import numpy as np
 
-from . import fmm, touching
+from . import _clib, fmm, touching
 from .taylor import monomials
 
 FOUR_PI = 4.0 * np.pi
@@ -79,6 +79,16 @@ def _select(full, pa, pb):
     ib = basis_indices(pb)
     A = np.array([[full[a + b] for b in ib] for a in ia])
     return A
+
+
+def _point_potential(X, Y, q):
+    """v(x_g) = sum_h q_h / |x_g - y_h| (plain C loop, oracle/o1.c)."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    out = np.empty(len(X))
+    _clib.lib().o1_point_potential(len(X), X, len(Y), Y, q, out)
+    return out
 
 
 _TOUCH = {}
@@ -160,8 +170,7 @@ def apply_direct(mesh, F, targets=None, degree_zero=False):
         hi = np.minimum(lf.lo_int[t] + lf.size[t], lf.lo_int + lf.size[:, None])
         tch = np.all(lo <= hi, axis=1)  # closed cubes intersect
         far_pts = ~tch[owner]
-        K = 1.0 / np.sqrt(((X[:, None, :] - Y[None, far_pts, :]) ** 2).sum(axis=2))
-        v = K @ q[far_pts] / FOUR_PI
+        v = _point_potential(X, Y[far_pts], q[far_pts]) / FOUR_PI
         u = PX.T @ (WX * v)
         for s in np.nonzero(tch)[0]:
             u = u + lf.block(t, s) @ F[lf.off[s] : lf.off[s + 1]]
@@ -178,29 +187,52 @@ class BasisFMM(fmm.FMM):
         self.lf = Leaves(mesh, degree_zero)
 
     def near_field_basis(self, F, targets):
+        """Near-field coefficients of the targets: sum over the extended neighbour list (marked
+        neighbours expanded to their leaves) of the entry blocks times F. The non-touching sources
+        enter through their densities at their Gauss points, q_h = W_h f_h(y_h), so that the sum of
+        their blocks is Phi_t^T (W_t * sum_s K(x, y_s) q_s) (the same products, associated
+        differently); touching sources use their exact blocks."""
         lf = self.lf
         mesh = self.mesh
         out = []
         for t in targets:
             lev, i, j, k = mesh.leaves[t]
-            u = np.zeros(lf.off[t + 1] - lf.off[t])
-            for s in mesh.near_leaf_sources(lev, (i, j, k)):
-                si = mesh.leaf_index[s]
-                u += lf.block(t, si) @ F[lf.off[si] : lf.off[si + 1]]
+            src = np.array([mesh.leaf_index[s] for s in mesh.near_leaf_sources(lev, (i, j, k))], dtype=np.int64)
+            lo = np.maximum(lf.lo_int[t], lf.lo_int[src])
+            hi = np.minimum(lf.lo_int[t] + lf.size[t], lf.lo_int[src] + lf.size[src][:, None])
+            tch = np.all(lo <= hi, axis=1)
+            X, WX, PX = lf.points(t)
+            far = src[~tch]
+            ys, qs = [], []
+            for p in np.unique(lf.p[far]):
+                grp = far[lf.p[far] == p]
+                Yr, Wr, Pr = leaf_points(np.zeros(3), 1.0, int(p))  # reference points of the unit cube
+                a = lf.a[grp]
+                ys.append((lf.lo[grp][:, None, :] + a[:, None, None] * Yr[None]).reshape(-1, 3))
+                Fs = np.stack([F[lf.off[s] : lf.off[s + 1]] for s in grp])  # (n, nb)
+                qs.append(((Fs @ Pr.T) * Wr[None, :] * (a ** 3)[:, None]).ravel())
+            v = _point_potential(X, np.concatenate(ys), np.concatenate(qs)) if ys else np.zeros(len(X))
+            u = PX.T @ (WX * v) / FOUR_PI
+            for s in src[tch]:
+                u = u + lf.block(t, s) @ F[lf.off[s] : lf.off[s + 1]]
             out.append(u)
         return out
 
     def moments_basis(self, F):
-        """m^gamma of every leaf with the leaf's rule: sum_g w_g (y_g - c)^gamma f_h(y_g)."""
+        """m^gamma of every leaf with the leaf's rule: sum_g w_g (y_g - c)^gamma f_h(y_g), level by
+        level (the leaves of a level share their degree and rule)."""
         mesh = self.mesh
         lf = self.lf
         m = [np.zeros((len(mesh.levels[lev]), self.K_of[lev])) for lev in range(mesh.L + 1)]
-        for w in range(len(lf.lv)):
-            lev = int(lf.lv[w, 0])
-            Y, WY, PY = lf.points(w)
-            centre = lf.lo[w] + 0.5 * lf.a[w]
-            fv = PY @ F[lf.off[w] : lf.off[w + 1]]
-            m[lev][mesh.index[lev][tuple(lf.lv[w, 1:])]] = (WY * fv) @ monomials(Y - centre, self.q_of[lev])
+        for lev, (pos, idx) in enumerate(self._rows):
+            if len(pos) == 0:
+                continue
+            p = int(lf.p[idx[0]])
+            a = float(lf.a[idx[0]])
+            Yr, Wr, Pr = leaf_points(np.zeros(3), 1.0, p)
+            Fs = np.stack([F[lf.off[w] : lf.off[w + 1]] for w in idx])  # (n, nb)
+            vals = (Fs @ Pr.T) * Wr[None, :] * a ** 3  # (n, P): w_g f_h(y_g)
+            m[lev][pos] = vals @ monomials(a * (Yr - 0.5), self.q_of[lev])
         return m
 
     def _evaluate(self, w, lam_w):

@@ -136,3 +136,19 @@ int o1_apply(int64_t n, const int64_t *lo_int, const int64_t *size, const double
     }
     return bad;
 }
+
+/* Potential sums of the degree-p leaf bases (oracle/basis.py): out[g] = sum_h q[h] / |x_g - y_h|
+ * for nx points x and ny weighted source points (y_h, q_h), 3 coordinates per point. Plain loop,
+ * OpenMP over the target points (each sum in a fixed order). */
+void o1_point_potential(int64_t nx, const double *x, int64_t ny, const double *y, const double *q, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t g = 0; g < nx; ++g) {
+        double acc = 0.0;
+        for (int64_t h = 0; h < ny; ++h) {
+            const double d0 = x[3 * g] - y[3 * h], d1 = x[3 * g + 1] - y[3 * h + 1], d2 = x[3 * g + 2] - y[3 * h + 2];
+            acc += q[h] / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        }
+        out[g] = acc;
+    }
+}

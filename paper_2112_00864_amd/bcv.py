@@ -48,7 +48,7 @@ class PlanOpts(ctypes.Structure):
                 ("direct", ctypes.c_int), ("nearfield", ctypes.c_int), ("streams", ctypes.c_int),
                 ("surrogate", ctypes.c_void_p), ("surrogate_tol", ctypes.c_double), ("near_unit", ctypes.c_int),
                 ("m2l_max_slots", ctypes.c_int), ("q_schedule", ctypes.c_int), ("near_order", ctypes.c_int),
-                ("boundary", ctypes.c_int)]
+                ("boundary", ctypes.c_int), ("basis_degree", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -56,7 +56,8 @@ class PlanInfo(ctypes.Structure):
                                               "n_offsets", "n_m2l_read_lanes", "n_faces", "n_btv_near",
                                               "n_btv_touch", "n_vtb_near", "n_near_ordered",
                                               "device_bytes")] + [
-        ("K", ctypes.c_int32), ("L", ctypes.c_int32), ("surrogate_classes", ctypes.c_int32), ("pad", ctypes.c_int32)]
+        ("K", ctypes.c_int32), ("L", ctypes.c_int32), ("surrogate_classes", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("n_dofs", ctypes.c_int64), ("n_basis_vals", ctypes.c_int64), ("n_basis_cols", ctypes.c_int64)]
 
 
 CONTACT_FACE, CONTACT_EDGE, CONTACT_VERTEX = 1, 2, 3
@@ -109,6 +110,8 @@ def lib():
         L.bcv_plan_enable_timing.argtypes = [vp, ctypes.c_int]
         L.bcv_plan_phase_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i64p]
         L.bcv_touching_integrals.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+        L.bcv_touching_basis_block.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                               ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
         dp, fp, i32p = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int32)
         L.bcv_box_pair_integrals.argtypes = [ctypes.c_int, ctypes.c_int64, dp, ctypes.c_int, dp]
         L.bcv_touch_pair_quadrature.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.POINTER(TouchPair), ctypes.c_int,
@@ -239,6 +242,11 @@ class Plan:
     def n_leaves(self):
         return self.info["n_leaves"]
 
+    @property
+    def n_dofs(self):
+        """Length of f and u: n_leaves, or the basis coefficients of all leaves (basis_degree=1)."""
+        return self.info["n_dofs"]
+
     def destroy(self):
         if getattr(self, "_h", None) and _lib is not None:
             _lib.bcv_plan_destroy(self._h)
@@ -249,17 +257,17 @@ class Plan:
 
 
 def _opts(q=6, eta0=0.5, direct=False, nearfield=NEAR_QUADRATURE, streams=2, precision=FP64, surrogate=None,
-          surrogate_tol=1e-7, near_unit=0, m2l_max_slots=0, boundary=False, near_order=0, q_schedule=0):
+          surrogate_tol=1e-7, near_unit=0, m2l_max_slots=0, boundary=False, near_order=0, q_schedule=0, basis_degree=0):
     return PlanOpts(eta0, q, precision, 1 if direct else 0, nearfield, streams,
                     surrogate.handle if surrogate is not None else None, surrogate_tol, near_unit, m2l_max_slots,
-                    q_schedule, near_order, 1 if boundary else 0)
+                    q_schedule, near_order, 1 if boundary else 0, basis_degree)
 
 
 def plan_interactions(tree, q=6, eta0=0.5, direct=False, nearfield=NEAR_QUADRATURE, device=0, streams=2,
                       precision=FP64, surrogate=None, surrogate_tol=1e-7, near_unit=0, m2l_max_slots=0,
-                      boundary=False, near_order=0, q_schedule=0):
+                      boundary=False, near_order=0, q_schedule=0, basis_degree=0):
     opts = _opts(q, eta0, direct, nearfield, streams, precision, surrogate, surrogate_tol, near_unit, m2l_max_slots,
-                 boundary, near_order, q_schedule)
+                 boundary, near_order, q_schedule, basis_degree)
     h = ctypes.c_void_p()
     _check(lib().bcv_plan_interactions(tree.handle, ctypes.byref(opts), device, ctypes.byref(h)))
     return Plan(h, device)
@@ -283,8 +291,9 @@ def _stream(stream, device):
 
 
 def vtv_apply(plan, f, u, stream=None):
-    """u <- VtV potential of density f (device tensors in leaf order); stream-ordered."""
-    n = plan.n_leaves
+    """u <- VtV potential of density f (device tensors of plan.n_dofs values: leaf order, or the
+    basis layout of basis_degree=1 plans); stream-ordered."""
+    n = plan.n_dofs
     _check(lib().bcv_vtv_apply(plan.handle, _dev_ptr(f, n, plan.device, "f"), _dev_ptr(u, n, plan.device, "u"),
                                _stream(stream, plan.device)))
 
@@ -297,13 +306,13 @@ def vtv_apply_batched(plans, fs, us, stream=None):
         raise ValueError("one density and one potential per plan")
     dev = plans[0].device
     hp = (ctypes.c_void_p * n)(*[p.handle for p in plans])
-    fp = (ctypes.c_void_p * n)(*[_dev_ptr(f, p.n_leaves, p.device, "f") for p, f in zip(plans, fs)])
-    up = (ctypes.c_void_p * n)(*[_dev_ptr(u, p.n_leaves, p.device, "u") for p, u in zip(plans, us)])
+    fp = (ctypes.c_void_p * n)(*[_dev_ptr(f, p.n_dofs, p.device, "f") for p, f in zip(plans, fs)])
+    up = (ctypes.c_void_p * n)(*[_dev_ptr(u, p.n_dofs, p.device, "u") for p, u in zip(plans, us)])
     _check(lib().bcv_vtv_apply_batched(hp, n, fp, up, _stream(stream, dev)))
 
 
 def vtv_apply_parts(plan, f, u, parts, stream=None):
-    n = plan.n_leaves
+    n = plan.n_dofs
     _check(lib().bcv_vtv_apply_parts(plan.handle, _dev_ptr(f, n, plan.device, "f"),
                                      _dev_ptr(u, n, plan.device, "u"), _stream(stream, plan.device), parts))
 
@@ -351,6 +360,20 @@ def plan_phase_times(plan):
 def touching_integrals(device=0):
     out = np.empty(7)
     _check(lib().bcv_touching_integrals(device, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out
+
+
+def n_basis(p):
+    return (p + 1) * (p + 2) * (p + 3) // 6
+
+
+def touching_basis_block(p_t, p_s, side_t, side_s, offset):
+    """Exact touching block of the degree-p leaf bases (unit scale, without 1/(4 pi)): an array
+    (n_basis(p_t), n_basis(p_s)); see bcv_touching_basis_block."""
+    out = np.empty((n_basis(p_t), n_basis(p_s)))
+    off = (ctypes.c_int * 3)(*[int(v) for v in offset])
+    _check(lib().bcv_touching_basis_block(p_t, p_s, side_t, side_s, off,
+                                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return out
 
 
@@ -504,7 +527,7 @@ class Graph:
 
 
 def vtv_graph_create(plan, f, u):
-    n = plan.n_leaves
+    n = plan.n_dofs
     h = ctypes.c_void_p()
     _check(lib().bcv_vtv_graph_create(plan.handle, _dev_ptr(f, n, plan.device, "f"), _dev_ptr(u, n, plan.device, "u"),
                                       ctypes.byref(h)))

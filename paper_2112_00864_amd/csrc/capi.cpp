@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "multiindex.hpp"
 #include "kernels.hpp"
 #include "quadrature.hpp"
 
@@ -112,6 +113,11 @@ void check_plan_opts(const bcv_plan_opts &o, int device)
                 "the boundary (BtV/VtB) structures need q = 4, 6 or 8");
     BCV_REQUIRE(o.near_order == 0 || o.nearfield == BCV_NEAR_ASSEMBLED, BCV_EINVAL,
                 "near_order 1 needs the assembled near field (BCV_NEAR_ASSEMBLED)");
+    BCV_REQUIRE(o.basis_degree == 0 || o.basis_degree == 1, BCV_EINVAL, "basis_degree must be 0 or 1");
+    BCV_REQUIRE(o.basis_degree == 0 || (o.precision == BCV_FP64 && !o.q_schedule &&
+                                        (o.q == 4 || o.q == 6 || o.q == 8) && !o.boundary && !o.surrogate),
+                BCV_ENOTSUP,
+                "degree-p leaf bases need BCV_FP64, a fixed q of 4, 6 or 8, no boundary structures and no surrogate");
     if (o.surrogate) {
         check_mlp(o.surrogate);
         BCV_REQUIRE(o.surrogate_tol >= 0.0, BCV_EINVAL, "negative surrogate tolerance");
@@ -286,6 +292,9 @@ bcv_status bcv_plan_get_info(bcv_plan plan, bcv_plan_info *info)
         info->L = plan->L;
         info->surrogate_classes = plan->surrogate_classes;
         info->pad = 0;
+        info->n_dofs = plan->basis ? plan->n_dofs : plan->n_leaves;
+        info->n_basis_vals = plan->n_bvals;
+        info->n_basis_cols = plan->n_bcols;
     });
 }
 
@@ -384,6 +393,34 @@ bcv_status bcv_touching_integrals(int device, double *out)
         BCV_HIP(hipGetDeviceCount(&n_dev));
         BCV_REQUIRE(device >= 0 && device < n_dev, BCV_EINVAL, "no such HIP device");
         on_device(device, [&] { bcv::touching_integrals(device, out); });
+    });
+}
+
+bcv_status bcv_touching_basis_block(int p_t, int p_s, int side_t, int side_s, const int *offset, double *out)
+{
+    return guard([&] {
+        BCV_REQUIRE(offset != nullptr && out != nullptr, BCV_EINVAL, "NULL argument");
+        BCV_REQUIRE(p_t >= 0 && p_s >= 0 && p_t <= bcv::kMaxBasisDegree && p_s <= bcv::kMaxBasisDegree, BCV_EINVAL,
+                    "basis degrees must be 0..8");
+        const bool equal = side_t == 1 && side_s == 1;
+        BCV_REQUIRE(equal || (side_t == 1 && side_s == 2) || (side_t == 2 && side_s == 1), BCV_EINVAL,
+                    "sides must be (1, 1), (1, 2) or (2, 1)");
+        // b: lower corner of the side-2 cube relative to the side-1 cube (pairs of sides 1 and 2)
+        int b[3];
+        for (int ax = 0; ax < 3; ++ax) b[ax] = side_t == 2 ? -offset[ax] : offset[ax];
+        bool ok = true, inside = true;
+        for (int ax = 0; ax < 3; ++ax) {
+            ok = ok && (equal ? (b[ax] >= -1 && b[ax] <= 1) : (b[ax] >= -2 && b[ax] <= 1));
+            inside = inside && (b[ax] == -1 || b[ax] == 0);
+        }
+        BCV_REQUIRE(ok && (equal || !inside), BCV_EINVAL, "the cubes do not touch (or overlap)");
+        const bcv::BasisTouchTable &tab = bcv::basis_touch_table(std::max(p_t, p_s));
+        const int nt = bcv::ncoef(p_t), ns = bcv::ncoef(p_s), nb = tab.nb;
+        const double *blk = equal ? &tab.equal[(size_t)((b[0] + 1) + 3 * (b[1] + 1) + 9 * (b[2] + 1)) * nb * nb]
+                                  : &tab.small_big[(size_t)((b[0] + 2) + 4 * (b[1] + 2) + 16 * (b[2] + 2)) * nb * nb];
+        for (int a = 0; a < nt; ++a)
+            for (int c = 0; c < ns; ++c)
+                out[(size_t)a * ns + c] = side_t == 2 ? blk[(size_t)c * nb + a] : blk[(size_t)a * nb + c];
     });
 }
 

@@ -76,6 +76,49 @@ struct NearSplit {
 // Touching-pair classes in the order of bcv_touching_integrals().
 constexpr int kTouchClasses = 7;
 
+// Degree-p leaf bases (bcv_plan_opts.basis_degree): Legendre tensor polynomials of total degree
+// <= p on each leaf, p <= kMaxBasisDegree, n_basis(p) = ncoef(p) per leaf.
+constexpr int kMaxBasisDegree = 8;
+
+// Exact touching blocks with Legendre weights at degree P (singular_basis.cpp), unit scale (the
+// smaller side 1), without 1/(4 pi); every block is nb x nb, [alpha][beta] in the graded order, and
+// its leading ncoef(p_t) x ncoef(p_s) corner is the block of degrees (p_t, p_s).
+struct BasisTouchTable {
+    int P = 0, nb = 0;
+    // equal sides: source = target + o, o in {-1,0,1}^3, block index (o0+1) + 3 (o1+1) + 9 (o2+1)
+    std::vector<double> equal;
+    // target of side 1 at the origin, source of side 2 with lower corner b in {-2..1}^3 (not both
+    // -1/0 on every axis), block index (b0+2) + 4 (b1+2) + 16 (b2+2); the pair with the larger
+    // target is the transpose (b = minus the small cube's offset)
+    std::vector<double> small_big;
+};
+const BasisTouchTable &basis_touch_table(int P);
+
+// Near-field work of the leaf bases: up to kBasisRows rows (coefficients a0 .. of target t) over
+// the columns [j0, j0 + len) of t's block row; out = -1 writes u, else the unit's kBasisRows partial
+// sums go to partial[out .. out + kBasisRows).
+constexpr int kBasisRows = 8;
+struct BasisUnit {
+    int64_t j0;
+    int32_t t, a0, len, out;
+};
+// A (target, first row) whose columns are cut into `count` units with partial sums at
+// [first, first + count) (in kBasisRows blocks), added in column order.
+struct BasisSplit {
+    int32_t t, a0, first, count;
+};
+
+// Gauss rules and the per-degree moment and evaluation factors of the leaf bases (basis.hip).
+constexpr int kMaxBasisQ = 8;
+struct BasisTables {
+    double x[kMaxBasisDegree + 3][kMaxBasisDegree + 2];  // [n][k]: n-point Gauss-Legendre nodes on [0, 1]
+    double w[kMaxBasisDegree + 3][kMaxBasisDegree + 2];  // and weights (summing to 1)
+    double leg[kMaxBasisDegree + 3][kMaxBasisDegree + 1][kMaxBasisDegree + 2];  // [n][a][k] = P_a(2 x_k - 1)
+    double t[kMaxBasisDegree + 1][kMaxBasisQ + 1][kMaxBasisDegree + 1];   // [p][b][a]: moments
+    double e[kMaxBasisDegree + 1][kMaxBasisDegree + 1][kMaxBasisQ + 1];   // [p][a][b]: evaluation
+};
+BasisTables basis_tables();
+
 // Boundary faces (BtV): a face is (leaf, axis, side), the leaf's face normal to `axis` at its low
 // (side 0) or high (side 1) end. A touching (cell, face) pair of equal size is the cube [0,1]^3 and
 // the face of the cube at integer offset o in {-1, 0, 1}^3 (units of the cell side); its class
@@ -196,6 +239,23 @@ struct bcv_plan_s {
     float *d_fscale = nullptr;          // BCV_MIXED_SPLIT16: partial maxima of |f| (256) and the scale (1)
     bcv::M2LSplit *d_m2l_splits = nullptr;
     double *d_m2l_partial = nullptr;    // 64 x K per piece of a split task
+
+    // Degree-p leaf bases (opts.basis_degree = 1): leaf w has ncoef(L - level) coefficients; entries
+    // 0 .. n_leaves - 1 of f and u are the degree-0 ones, the others follow leaf by leaf.
+    int basis = 0;
+    int basis_P = 0;                  // largest leaf degree
+    int64_t n_dofs = 0;               // length of f and u
+    int64_t n_bvals = 0, n_bcols = 0, n_bwork = 0, n_bsplits = 0;
+    int64_t *d_hi_off = nullptr;      // per leaf: first higher coefficient minus n_leaves
+    int32_t *d_dof_leaf = nullptr;    // per higher coefficient: its leaf
+    int64_t *d_bcb = nullptr;         // n_leaves + 1: near row of target t is columns [bcb[t], bcb[t+1])
+    int64_t *d_bvb = nullptr;         // per target leaf: first block entry (row alpha at + alpha row_len)
+    int32_t *d_bcol = nullptr;        // near-row columns: source coefficient positions
+    double *d_bval = nullptr;         // near-field blocks
+    bcv::BasisUnit *d_bwork = nullptr;    // apply work units, longest first
+    bcv::BasisSplit *d_bsplits = nullptr; // rows cut into several units
+    double *d_bpartial = nullptr;         // kBasisRows partial sums per unit of a cut row
+    bcv::BasisTables *d_btab = nullptr;
 
     // BtV (Algorithm 3), built when the plan options ask for it.
     int boundary = 0;

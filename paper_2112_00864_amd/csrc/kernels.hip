@@ -112,42 +112,6 @@ __constant__ constexpr FaceKappaTable<Q> kFaceKappa{};
 // also write the folded rows the interaction phase reads; for the leaf moments this is the folded
 // kappa table.
 template <int Q>
-struct FoldTable {  // Mr^b = sum_t c[b][t] M^{src[b][t]} (full positions)
-    static constexpr int fold_terms()
-    {
-        int best = 1;
-        for (int bx = 0; bx <= Q; ++bx)
-            for (int by = 0; bx + by <= Q; ++by) best = std::max(best, (bx / 2 + 1) * (by / 2 + 1));
-        return best;
-    }
-    static constexpr int R = nreduced(Q), kTerms = fold_terms();
-    int n[R], src[R][kTerms];
-    double c[R][kTerms];
-    constexpr FoldTable() : n{}, src{}, c{}
-    {
-        constexpr ReducedIndex<Q> ri{};
-        for (int b = 0; b < R; ++b) {
-            const int bx = ri.e[b][0], by = ri.e[b][1], bz = ri.e[b][2];
-            int cnt = 0;
-            double sign = 1.0;
-            for (int k = 0; 2 * k <= bx + by; ++k, sign = -sign) {
-                double binom = 1.0;  // C(k, i)
-                for (int i = 0; i <= k; ++i) {
-                    if (i > 0) binom = binom * (k - i + 1) / i;
-                    const int j = k - i;
-                    if (2 * i > bx || 2 * j > by) continue;
-                    src[b][cnt] = mi_index(bx - 2 * i, by - 2 * j, bz + 2 * k);
-                    c[b][cnt] = sign * binom;
-                    ++cnt;
-                }
-            }
-            n[b] = cnt;
-        }
-    }
-};
-
-
-template <int Q>
 struct FoldedKappaTable {
     double v[nreduced(Q)];
     constexpr FoldedKappaTable() : v{}
@@ -2028,6 +1992,43 @@ void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStre
     marks.finish(st);
 }
 
+// VtV apply with degree-p leaf bases (opts.basis_degree = 1), on the caller's stream: the leaf moments
+// from all basis coefficients with each leaf's rule, the unchanged passes and interaction phase, the
+// near field from the plan's blocks, then the evaluation of every coefficient.
+template <int Q>
+void basis_apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStream_t st)
+{
+    const bool far = (parts & BCV_PART_FAR) && !p.direct;
+    const bool near = (parts & BCV_PART_NEAR) != 0;
+    PhaseMarks marks(p);
+    if (far) {
+        marks.start(BCV_PHASE_P2M, st);
+        launch_basis_p2m(p, f, st);
+        marks.stop(BCV_PHASE_P2M, st);
+        marks.start(BCV_PHASE_M2M, st);
+        upward_pass<Q>(p, st, f);  // level L - 1 from the degree-0 coefficients of its level-L children
+        marks.stop(BCV_PHASE_M2M, st);
+        marks.start(BCV_PHASE_M2L, st);
+        interaction_phase<Q>(p, st);
+        marks.stop(BCV_PHASE_M2L, st);
+        marks.start(BCV_PHASE_L2L, st);
+        downward_pass<Q>(p, st);
+        marks.stop(BCV_PHASE_L2L, st);
+    }
+    marks.start(BCV_PHASE_NEAR, st);
+    if (near)
+        launch_basis_near(p, f, u, st);
+    else
+        launch_basis_zero(p, u, st);
+    marks.stop(BCV_PHASE_NEAR, st);
+    if (far) {
+        marks.start(BCV_PHASE_EVAL, st);
+        launch_basis_eval(p, u, st);
+        marks.stop(BCV_PHASE_EVAL, st);
+    }
+    marks.finish(st);
+}
+
 // BtV apply (Algorithm 3), on the caller's stream: boundary moments, upward pass, interaction
 // phase (all interaction-list sources; cells without boundary faces below them carry zero moments),
 // downward pass, then the near field of the boundary faces fused with the evaluation phase.
@@ -2122,6 +2123,15 @@ void launch_btv(const bcv_plan_s &p, const double *qf, const double *gf, double 
 
 void launch_apply(const bcv_plan_s &p, const double *f, double *u, int parts, hipStream_t st)
 {
+    if (p.basis) {
+        switch (p.q) {
+        case 4: basis_apply_q<4>(p, f, u, parts, st); break;
+        case 6: basis_apply_q<6>(p, f, u, parts, st); break;
+        case 8: basis_apply_q<8>(p, f, u, parts, st); break;
+        default: fail(BCV_ENOTSUP, "degree-p leaf bases: expansion orders 4, 6, 8");
+        }
+        return;
+    }
     if (p.q_schedule) {  // every phase picks its kernels by the level's order (the template order is unused)
         apply_q<4>(p, f, u, parts, st);
         return;

@@ -32,6 +32,17 @@ void launch_near_narrow(const bcv_plan_s &p, hipStream_t stream);
 void launch_near_assemble_ordered(const bcv_plan_s &p, const std::vector<int64_t> &entry,
                                   const std::vector<int32_t> &target, const std::vector<int8_t> &order);
 
+// Degree-p leaf bases (basis.hip). Plan time: every near pair's block (pair k: target pair_t[k],
+// source in p.d_col[k], block at column pair_pos[k] of the target's block row), on the null stream
+// (synchronizes). Apply: the near field (overwrites u), a zero fill of u, the leaf moments (full and
+// folded rows) and the evaluation of every coefficient (adds to u).
+void launch_basis_assemble(const bcv_plan_s &p, const std::vector<int32_t> &pair_t,
+                           const std::vector<int32_t> &pair_pos, const BasisTouchTable &touch);
+void launch_basis_near(const bcv_plan_s &p, const double *f, double *u, hipStream_t stream);
+void launch_basis_zero(const bcv_plan_s &p, double *u, hipStream_t stream);
+void launch_basis_p2m(const bcv_plan_s &p, const double *f, hipStream_t stream);
+void launch_basis_eval(const bcv_plan_s &p, double *u, hipStream_t stream);
+
 // int_{[0,1]^3} int_{delta+[0,1]^3} 1/|x-y| dy dx for n non-touching integer offsets (host arrays:
 // deltas 3 per offset, out n), by an n_gauss-point Gauss-Legendre rule in each of the six variables,
 // on the current device.

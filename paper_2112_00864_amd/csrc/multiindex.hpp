@@ -4,6 +4,7 @@
 // degree d, a0 runs from d down to 0 and, for each a0, a1 from d-a0 down to 0. Hence every
 // alpha with |alpha| <= m occupies exactly the first ncoef(m) positions.
 #pragma once
+#include <algorithm>
 
 namespace bcv {
 
@@ -79,6 +80,44 @@ struct ReducedIndex {
         int n = d * d;  // entries of lower degree
         for (int a = d; a > i; --a) n += (a == d ? 1 : 2);
         return n + k;
+    }
+};
+
+// Harmonic folding of moments onto the multi-indices with b_z <= 1 (see the M2L section of
+// kernels.hip): Mr^b = sum_t c[b][t] M^{src[b][t]} over the (Q + 1)^2 reduced b, with
+//     Mr^b = sum_k (-1)^k sum_{i + j = k} C(k, i) M^{b - 2i e_x - 2j e_y + 2k e_z}.
+template <int Q>
+struct FoldTable {  // Mr^b = sum_t c[b][t] M^{src[b][t]} (full positions)
+    static constexpr int fold_terms()
+    {
+        int best = 1;
+        for (int bx = 0; bx <= Q; ++bx)
+            for (int by = 0; bx + by <= Q; ++by) best = std::max(best, (bx / 2 + 1) * (by / 2 + 1));
+        return best;
+    }
+    static constexpr int R = nreduced(Q), kTerms = fold_terms();
+    int n[R], src[R][kTerms];
+    double c[R][kTerms];
+    constexpr FoldTable() : n{}, src{}, c{}
+    {
+        constexpr ReducedIndex<Q> ri{};
+        for (int b = 0; b < R; ++b) {
+            const int bx = ri.e[b][0], by = ri.e[b][1], bz = ri.e[b][2];
+            int cnt = 0;
+            double sign = 1.0;
+            for (int k = 0; 2 * k <= bx + by; ++k, sign = -sign) {
+                double binom = 1.0;  // C(k, i)
+                for (int i = 0; i <= k; ++i) {
+                    if (i > 0) binom = binom * (k - i + 1) / i;
+                    const int j = k - i;
+                    if (2 * i > bx || 2 * j > by) continue;
+                    src[b][cnt] = mi_index(bx - 2 * i, by - 2 * j, bz + 2 * k);
+                    c[b][cnt] = sign * binom;
+                    ++cnt;
+                }
+            }
+            n[b] = cnt;
+        }
     }
 };
 

@@ -836,6 +836,92 @@ BtvNear build_btv_near(const bcv_tree_s &t, const std::vector<Grid> &g, bool dir
 
 }  // namespace
 
+// Degree-p leaf bases: coefficient layout, the block rows of the near field (columns = source
+// coefficients, shared by the target's rows), the apply's work items, and per near entry its target
+// and the position of its block in the target's row (for the plan-time assembly).
+void build_basis_near(bcv_plan_s &p, const bcv_tree_s &t, const NearCSR &near, std::vector<int32_t> &pair_t,
+                      std::vector<int32_t> &pair_pos)
+{
+    const int64_t nl = p.n_leaves;
+    std::vector<int32_t> nb(nl);
+    std::vector<int64_t> hi_off(nl + 1, 0);
+    for (int64_t w = 0; w < nl; ++w) {
+        nb[w] = ncoef(t.L - t.level[t.leaf_cell[w]]);
+        hi_off[w + 1] = hi_off[w] + (nb[w] - 1);
+    }
+    p.n_dofs = nl + hi_off[nl];
+    BCV_REQUIRE(p.n_dofs < (int64_t(1) << 31), BCV_ENOTSUP, "degree-p leaf bases: more than 2^31 coefficients");
+    std::vector<int32_t> dof_leaf(std::max<int64_t>(hi_off[nl], 1));
+    for (int64_t w = 0; w < nl; ++w)
+        for (int64_t k = hi_off[w]; k < hi_off[w + 1]; ++k) dof_leaf[k] = (int32_t)w;
+    std::vector<int64_t> cb(nl + 1, 0), vb(nl, 0);
+    pair_t.resize(near.col.size());
+    pair_pos.resize(near.col.size());
+    for (int64_t w = 0; w < nl; ++w) {
+        int64_t len = 0;
+        for (int64_t e = near.row[w]; e < near.row[w + 1]; ++e) {
+            pair_t[e] = (int32_t)w;
+            BCV_REQUIRE(len < (int64_t(1) << 31), BCV_ENOTSUP, "degree-p leaf bases: near row too long");
+            pair_pos[e] = (int32_t)len;
+            len += nb[near.col[e] & 0x0FFFFFFFu];
+        }
+        cb[w + 1] = cb[w] + len;
+    }
+    int64_t nv = 0;
+    for (int64_t w = 0; w < nl; ++w) {
+        vb[w] = nv;
+        nv += (int64_t)nb[w] * (cb[w + 1] - cb[w]);
+    }
+    std::vector<int32_t> bcol(std::max<int64_t>(cb[nl], 1));
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t w = 0; w < nl; ++w) {
+        int64_t j = cb[w];
+        for (int64_t e = near.row[w]; e < near.row[w + 1]; ++e) {
+            const int32_t s = (int32_t)(near.col[e] & 0x0FFFFFFFu);
+            bcol[j++] = s;
+            for (int k = 1; k < nb[s]; ++k) bcol[j++] = (int32_t)(nl + hi_off[s] + (k - 1));
+        }
+    }
+    // Work units: kBasisRows rows of one target over at most `unit` columns (each unit streams at most
+    // kBasisRows * unit block entries); longer rows are cut into equal pieces with partial sums.
+    const int64_t unit = 4096;
+    std::vector<BasisUnit> work;
+    std::vector<BasisSplit> splits;
+    int32_t n_partial = 0;
+    for (int64_t w = 0; w < nl; ++w) {
+        const int64_t len = cb[w + 1] - cb[w];
+        const int64_t pieces = std::max<int64_t>(1, (len + unit - 1) / unit);
+        for (int a0 = 0; a0 < nb[w]; a0 += kBasisRows) {
+            if (pieces == 1) {
+                work.push_back({0, (int32_t)w, a0, (int32_t)len, -1});
+                continue;
+            }
+            splits.push_back({(int32_t)w, a0, n_partial, (int32_t)pieces});
+            for (int64_t k = 0; k < pieces; ++k) {
+                const int64_t j0 = len * k / pieces, j1 = len * (k + 1) / pieces;
+                work.push_back({j0, (int32_t)w, a0, (int32_t)(j1 - j0), n_partial});
+                n_partial += kBasisRows;
+            }
+        }
+    }
+    std::stable_sort(work.begin(), work.end(), [](const BasisUnit &a, const BasisUnit &b) { return a.len > b.len; });
+    p.n_bvals = nv;
+    p.n_bcols = cb[nl];
+    p.n_bwork = (int64_t)work.size();
+    p.n_bsplits = (int64_t)splits.size();
+    p.d_bsplits = upload(&p, splits);
+    if (n_partial > 0) p.d_bpartial = alloc_zero<double>(&p, (size_t)n_partial);
+    p.d_hi_off = upload(&p, hi_off);
+    p.d_dof_leaf = upload(&p, dof_leaf);
+    p.d_bcb = upload(&p, cb);
+    p.d_bvb = upload(&p, vb);
+    p.d_bcol = upload(&p, bcol);
+    p.d_bwork = upload(&p, work);
+    p.d_bval = alloc_zero<double>(&p, (size_t)std::max<int64_t>(nv, 1));
+    const BasisTables tb = basis_tables();
+    p.d_btab = upload(&p, &tb, 1);
+}
+
 void destroy_plan(bcv_plan_s *p);
 
 bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int device)
@@ -854,6 +940,22 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         BCV_REQUIRE(opts.q == 6 && !opts.q_schedule, BCV_ENOTSUP,
                     "BCV_MIXED_SPLIT16 supports the fixed order q = 6 only");
     for (int lev = 0; lev <= t.L + 1 && lev <= kMaxLevel + 1; ++lev) p->lvl_start[lev] = t.lvl_start[lev];
+    if (opts.basis_degree != 0) {
+        BCV_REQUIRE(opts.basis_degree == 1, BCV_EINVAL, "basis_degree must be 0 or 1");
+        BCV_REQUIRE(opts.precision == BCV_FP64, BCV_ENOTSUP, "degree-p leaf bases: BCV_FP64 only");
+        BCV_REQUIRE(!opts.q_schedule && (opts.q == 4 || opts.q == 6 || opts.q == 8), BCV_ENOTSUP,
+                    "degree-p leaf bases: fixed orders 4, 6, 8 only");
+        BCV_REQUIRE(t.n_meshes == 1 && t.mesh_side[0] == 1.0, BCV_ENOTSUP,
+                    "degree-p leaf bases: a single mesh of side 1");
+        BCV_REQUIRE(!opts.boundary && !opts.surrogate, BCV_ENOTSUP,
+                    "degree-p leaf bases: no boundary structures, no surrogate");
+        int coarsest = t.L;
+        for (int64_t l = 0; l < t.n_leaves(); ++l) coarsest = std::min<int>(coarsest, t.level[t.leaf_cell[l]]);
+        BCV_REQUIRE(t.L - coarsest <= kMaxBasisDegree, BCV_ENOTSUP, "degree-p leaf bases: leaf degrees above 8");
+        p->basis = 1;
+        p->basis_P = t.L - coarsest;
+        p->near_order = 0;
+    }
     p->streams = opts.streams;
     if (p->streams == 2) {
         BCV_HIP(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
@@ -932,6 +1034,7 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
     }
 
     NearCSR vol_near;  // kept for the VtB rows
+    std::vector<int32_t> basis_pair_t, basis_pair_pos;  // degree-p leaf bases: per near entry
     // Level-dependent near-field rule: per-leaf Gauss orders and the entries that need them.
     std::vector<int8_t> near_order;
     std::vector<int64_t> ordered_entry;
@@ -955,6 +1058,7 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
                     }
                 }
         }
+        if (p->basis) build_basis_near(*p, t, near, basis_pair_t, basis_pair_pos);
         p->n_near = (int64_t)near.col.size();
         p->n_touch = near.n_touch;
         p->d_split = upload(p.get(), near.split);
@@ -1096,7 +1200,9 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         if (vu.n_partial > 0) p->d_vtb_partial = alloc_zero<double>(p.get(), (size_t)vu.n_partial);
     }
 
-    if (opts.nearfield == BCV_NEAR_ASSEMBLED) {
+    if (p->basis) {
+        launch_basis_assemble(*p, basis_pair_t, basis_pair_pos, basis_touch_table(p->basis_P));
+    } else if (opts.nearfield == BCV_NEAR_ASSEMBLED) {
         p->d_val = alloc_zero<double>(p.get(), (size_t)p->n_near);
         launch_near_assemble(*p, nullptr);
         BCV_HIP(hipDeviceSynchronize());
@@ -1130,7 +1236,8 @@ void destroy_plan(bcv_plan_s *p)
                     p->d_slot_mask, p->d_m2l_A, p->d_G48, p->d_M16, p->d_fscale, p->d_uscale,
                     p->d_m2l_splits, p->d_m2l_partial, p->d_faces, p->d_leaf_faces, p->d_btv_col,
                     p->d_btv_units, p->d_btv_splits, p->d_btv_partial, p->d_btv_touch, p->d_vtb_col,
-                    p->d_vtb_units, p->d_vtb_splits, p->d_vtb_partial};
+                    p->d_vtb_units, p->d_vtb_splits, p->d_vtb_partial, p->d_hi_off, p->d_dof_leaf, p->d_bcb,
+                    p->d_bvb, p->d_bcol, p->d_bval, p->d_bwork, p->d_bsplits, p->d_bpartial, p->d_btab};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     p->magic = 0;

@@ -25,6 +25,7 @@ __all__ = [
     "harmonic_params",
     "harmonic",
     "face_data",
+    "legendre_coefficients",
 ]
 
 
@@ -148,3 +149,35 @@ def face_data(faces, seed=0, n=4):
     sign = 2.0 * side - 1.0
     dudn = sign[:, None] * grad[rows[:, None], np.arange(n * n)[None, :], ax[:, None]]
     return dudn @ ww, u @ ww
+
+
+def legendre_coefficients(level_ijk, L, func, extra=4):
+    """Density input for degree-p leaf bases: on each leaf (level l, side a, centre c) the coefficients
+    f_alpha = <phi^alpha, func> / ||phi^alpha||^2 of the L2 projection of func onto
+    phi^alpha(x) = prod_i P_{alpha_i}(2 (x_i - c_i)/a), |alpha| <= p = L - l (Legendre), by an
+    (p + extra)-point Gauss-Legendre rule per axis. Returns (coefficients, offsets): leaf-major, leaf w
+    owning coefficients[offsets[w]:offsets[w+1]], alpha in the graded order (total degree, then
+    alpha_x descending, then alpha_y descending)."""
+    lv = np.asarray(level_ijk, dtype=np.int64)
+    deg = L - lv[:, 0]
+    nb = (deg + 1) * (deg + 2) * (deg + 3) // 6
+    offsets = np.concatenate([[0], np.cumsum(nb)]).astype(np.int64)
+    out = np.empty(offsets[-1])
+    for p in np.unique(deg):
+        sel = np.nonzero(deg == p)[0]
+        t, w = _gauss_legendre_unit(int(p) + extra)
+        nodes = np.stack(np.meshgrid(t, t, t, indexing="ij"), axis=-1).reshape(-1, 3)
+        weights = np.einsum("i,j,k->ijk", w, w, w).ravel()
+        P = np.polynomial.legendre.legvander(2.0 * nodes - 1.0, int(p))  # (n^3, 3, p + 1)
+        idx = [(i, j, d - i - j) for d in range(p + 1) for i in range(d, -1, -1) for j in range(d - i, -1, -1)]
+        phi = np.stack([P[:, 0, i] * P[:, 1, j] * P[:, 2, k] for i, j, k in idx], axis=1)  # (n^3, nb)
+        norm = np.array([(2 * i + 1) * (2 * j + 1) * (2 * k + 1) for i, j, k in idx], dtype=np.float64)
+        a = np.ldexp(1.0, -lv[sel, 0].astype(np.int32))
+        for c0 in range(0, len(sel), 4096):
+            s = sel[c0 : c0 + 4096]
+            pts = lv[s, 1:4][:, None, :] * a[c0 : c0 + 4096, None, None] + a[c0 : c0 + 4096, None, None] * nodes[None]
+            vals = func(pts) * weights[None, :]  # (n, n^3)
+            coef = (vals @ phi) * norm[None, :]
+            for r in range(len(idx)):
+                out[offsets[s] + r] = coef[:, r]
+    return out, offsets

@@ -156,3 +156,38 @@ def test_order_range():
         with pytest.raises(bcv.BCVError) as e:
             bcv.plan_interactions(t, q=q)
         assert e.value.status == bcv.bcv.EINVAL
+
+
+def test_basis_options_checked_before_device_use():
+    t = bcv.build_bc_tree(3)
+    with pytest.raises(bcv.BCVError) as e:
+        bcv.plan_interactions(t, basis_degree=2)
+    assert e.value.status == bcv.bcv.EINVAL
+    for kw in ({"precision": bcv.MIXED_F32}, {"q": 5}, {"q_schedule": 1}, {"boundary": True}):
+        with pytest.raises(bcv.BCVError) as e:
+            bcv.plan_interactions(t, basis_degree=1, **kw)
+        assert e.value.status == bcv.bcv.ENOTSUP
+
+
+@pytest.mark.parametrize("degrees", [(0, 0), (1, 1), (2, 2), (3, 1), (1, 3), (4, 3)])
+def test_touching_basis_blocks_against_oracle(degrees):
+    """The library's touching blocks (self-similarity of the cube with regular pairs by 6-D Gauss,
+    host) against the oracle's (convolution reduction with Duffy pyramids), every kind of contact."""
+    from oracle import basis
+
+    p_t, p_s = degrees
+    cases = [((0, 0, 0), 1, 1), ((1, 0, 0), 1, 1), ((0, -1, 1), 1, 1), ((1, 1, -1), 1, 1), ((0, 0, 1), 1, 2),
+             ((-2, 0, 0), 1, 2), ((1, -2, 0), 1, 2), ((-2, -2, 1), 1, 2), ((0, 0, -1), 2, 1), ((2, 1, 0), 2, 1),
+             ((-1, 2, -1), 2, 1)]
+    for off, st, ss in cases:
+        got = bcv.touching_basis_block(p_t, p_s, st, ss, off)
+        ref = basis.touching_block(np.zeros(3, dtype=np.int64), st, np.array(off), ss, 1.0, p_t, p_s) * 4.0 * np.pi
+        assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref)), (off, st, ss)
+
+
+def test_touching_basis_block_errors():
+    for args in ((9, 0, 1, 1, (1, 0, 0)), (0, -1, 1, 1, (1, 0, 0)), (1, 1, 2, 2, (1, 0, 0)),
+                 (1, 1, 1, 1, (2, 0, 0)), (1, 1, 1, 2, (-1, 0, -1)), (1, 1, 2, 1, (-2, 0, 0))):
+        with pytest.raises(bcv.BCVError) as e:
+            bcv.touching_basis_block(*args)
+        assert e.value.status == bcv.bcv.EINVAL

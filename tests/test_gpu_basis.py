@@ -1,0 +1,162 @@
+"""Degree-p leaf bases (opts.basis_degree = 1, p_l = L - l) on the GPU against the oracle
+(oracle.basis): direct mode against O1, the FMM against O2 (all coefficients, q = 4, 6, 8), sampled
+leaves of every degree at h = 1/64 and at the bench's h = 1/128 (FP64 bar 1e-10), the near and far
+parts, linearity in f, and the captured graph."""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+
+import paper_2112_00864_amd as bcv  # noqa: E402
+
+from oracle import basis  # noqa: E402
+from oracle.mesh import BCMesh  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def announce(*a):
+    print("[gpu]", *a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def layout(lf):
+    """Library positions of the oracle's leaf-major coefficients: alpha = 0 of every leaf first (leaf
+    order), then the higher coefficients leaf by leaf (bcv_plan_opts.basis_degree)."""
+    nl = len(lf.lv)
+    nbs = np.diff(lf.off)
+    hi = np.concatenate([[0], np.cumsum(nbs - 1)])
+    pos = np.empty(lf.off[-1], dtype=np.int64)
+    pos[lf.off[:-1]] = np.arange(nl)
+    for w in range(nl):
+        pos[lf.off[w] + 1 : lf.off[w + 1]] = nl + hi[w] + np.arange(nbs[w] - 1)
+    return pos
+
+
+def gpu_apply(plan, F, pos, parts=None):
+    import torch
+
+    f = np.empty_like(F)
+    f[pos] = F
+    fd = torch.tensor(f, device="cuda:0")
+    ud = torch.full_like(fd, float("nan"))
+    if parts is None:
+        bcv.vtv_apply(plan, fd, ud)
+    else:
+        bcv.vtv_apply_parts(plan, fd, ud, parts)
+    torch.cuda.synchronize()
+    return ud.cpu().numpy()[pos]
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_layout_and_sizes():
+    m = BCMesh(4)
+    lf = basis.Leaves(m)
+    plan = bcv.plan_interactions(bcv.build_bc_tree(4), q=6, basis_degree=1, streams=1)
+    assert plan.n_dofs == lf.off[-1] and plan.n_leaves == len(lf.lv)
+    assert plan.info["n_basis_vals"] > plan.info["n_near"]
+
+
+def test_direct_against_O1():
+    m = BCMesh(3)
+    lf = basis.Leaves(m)
+    F = np.random.default_rng(0).standard_normal(lf.off[-1])
+    plan = bcv.plan_interactions(bcv.build_bc_tree(3), q=6, direct=True, basis_degree=1, streams=1)
+    u = gpu_apply(plan, F, layout(lf))
+    ref = basis.apply_direct(m, F)
+    announce("basis direct L=3 vs O1: rel-L2 %.3e" % rel(u, ref))
+    assert rel(u, ref) <= TOL
+
+
+@pytest.mark.parametrize("q", [4, 6, 8])
+def test_fmm_against_O2(q):
+    m = BCMesh(3)
+    lf = basis.Leaves(m)
+    F = np.random.default_rng(q).standard_normal(lf.off[-1])
+    plan = bcv.plan_interactions(bcv.build_bc_tree(3), q=q, basis_degree=1, streams=1)
+    pos = layout(lf)
+    fm = basis.BasisFMM(m, q)
+    u = gpu_apply(plan, F, pos)
+    ref = fm.apply_basis(F)
+    un = gpu_apply(plan, F, pos, bcv.PART_NEAR)
+    near = np.concatenate(fm.near_field_basis(F, range(len(lf.lv))))
+    announce("basis FMM L=3 q=%d vs O2: total %.3e, near %.3e" % (q, rel(u, ref), rel(un, near)))
+    assert rel(u, ref) <= TOL and rel(un, near) <= TOL
+
+
+@pytest.mark.parametrize("L", [5, 7])
+def test_sampled_leaves_of_every_degree(L):
+    m = BCMesh(L)
+    lf = basis.Leaves(m)
+    F = np.random.default_rng(L).standard_normal(lf.off[-1])
+    plan = bcv.plan_interactions(bcv.build_bc_tree(L), q=6, basis_degree=1, streams=1)
+    u = gpu_apply(plan, F, layout(lf))
+    rng = np.random.default_rng(100 + L)
+    targets = [0, len(lf.lv) - 1]
+    for p in range(0, int(lf.p.max()) + 1):
+        cand = np.nonzero(lf.p == p)[0]
+        targets += list(rng.choice(cand, min(2, len(cand)), replace=False))
+    targets = np.array(sorted(set(int(t) for t in targets)))
+    announce("basis L=%d: O2 at %d leaves (degrees %s)" % (L, len(targets), sorted(set(lf.p[targets].tolist()))))
+    ref = basis.BasisFMM(m, 6).apply_basis_sampled(F, targets)
+    got = np.concatenate([u[lf.off[t] : lf.off[t + 1]] for t in targets])
+    err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    announce("basis L=%d sampled vs O2: max rel %.3e" % (L, err))
+    assert err <= TOL
+
+
+def test_parts_linearity_and_graph():
+    import torch
+
+    m = BCMesh(4)
+    lf = basis.Leaves(m)
+    pos = layout(lf)
+    rng = np.random.default_rng(7)
+    F1, F2 = rng.standard_normal(lf.off[-1]), rng.standard_normal(lf.off[-1])
+    plan = bcv.plan_interactions(bcv.build_bc_tree(4), q=6, basis_degree=1, streams=1)
+    u = gpu_apply(plan, F1, pos)
+    un = gpu_apply(plan, F1, pos, bcv.PART_NEAR)
+    uf = gpu_apply(plan, F1, pos, bcv.PART_FAR)
+    assert np.max(np.abs(un + uf - u)) <= 1e-14 * np.max(np.abs(u))
+    u12 = gpu_apply(plan, 2.0 * F1 - 3.0 * F2, pos)
+    assert rel(u12, 2.0 * u - 3.0 * gpu_apply(plan, F2, pos)) <= 1e-14
+    assert np.all(gpu_apply(plan, np.zeros_like(F1), pos) == 0.0)
+    f = np.empty_like(F1)
+    f[pos] = F1
+    fd = torch.tensor(f, device="cuda:0")
+    ud = torch.full_like(fd, float("nan"))
+    graph = bcv.vtv_graph_create(plan, fd, ud)
+    for rep in range(3):
+        ud.fill_(float("nan"))
+        graph.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(ud.cpu().numpy()[pos], u)
+
+
+def test_option_errors():
+    tree = bcv.build_bc_tree(3)
+    for kw, code in ((dict(basis_degree=2), bcv.EINVAL), (dict(basis_degree=1, precision=bcv.MIXED_F32), bcv.ENOTSUP),
+                     (dict(basis_degree=1, q=5), bcv.ENOTSUP), (dict(basis_degree=1, q_schedule=1), bcv.ENOTSUP),
+                     (dict(basis_degree=1, boundary=True), bcv.ENOTSUP)):
+        with pytest.raises(bcv.BCVError) as e:
+            bcv.plan_interactions(tree, **kw)
+        assert e.value.status == code
+    forest = bcv.build_bc_forest([3, 3])
+    with pytest.raises(bcv.BCVError) as e:
+        bcv.plan_interactions(forest, q=6, basis_degree=1)
+    assert e.value.status == bcv.ENOTSUP
