@@ -1,7 +1,8 @@
 """Degree-p leaf bases (opts.basis_degree = 1, p_l = L - l) on the GPU against the oracle
 (oracle.basis): direct mode against O1, the FMM against O2 (all coefficients, q = 4, 6, 8), sampled
-leaves of every degree at h = 1/64 and at the bench's h = 1/128 (FP64 bar 1e-10), the near and far
-parts, linearity in f, and the captured graph."""
+leaves of every degree at h = 1/32 and at the bench's h = 1/128 (FP64 bar 1e-10), the near and far
+parts, linearity in f, the captured graph, and the O(h) rate of the projected potential of f = 1
+against its closed form up to h = 1/64."""
 
 import os
 import sys
@@ -160,3 +161,58 @@ def test_option_errors():
     with pytest.raises(bcv.BCVError) as e:
         bcv.plan_interactions(forest, q=6, basis_degree=1)
     assert e.value.status == bcv.ENOTSUP
+
+
+def _projection_error(L, degree):
+    """f = 1 on the unit cube: the L2 error of the projection sum_alpha u_alpha phi^alpha / ||phi^alpha||^2
+    of the GPU result against the closed-form potential, relative to its norm (a (p + 3)-point rule
+    per axis on each leaf)."""
+    import torch
+
+    from closed_forms import box_potential
+
+    tree = bcv.build_bc_tree(L)
+    lv = tree.leaves().astype(np.int64)
+    nl = len(lv)
+    p_of = (L - lv[:, 0]) if degree else np.zeros(nl, dtype=np.int64)
+    plan = bcv.plan_interactions(tree, q=6, basis_degree=1 if degree else 0, streams=1)
+    f = torch.zeros(plan.n_dofs, dtype=torch.float64, device="cuda:0")
+    f[:nl] = 1.0  # degree-0 coefficients: f = 1
+    u = torch.empty_like(f)
+    bcv.vtv_apply(plan, f, u)
+    torch.cuda.synchronize()
+    u = u.cpu().numpy()
+    nb = (p_of + 1) * (p_of + 2) * (p_of + 3) // 6
+    hi = np.concatenate([[0], np.cumsum(nb - 1)])
+    e2 = n2 = 0.0
+    for p in np.unique(p_of):
+        sel = np.nonzero(p_of == p)[0]
+        t, w = np.polynomial.legendre.leggauss(int(p) + 3)
+        t, w = 0.5 * (t + 1.0), 0.5 * w
+        X = np.stack(np.meshgrid(t, t, t, indexing="ij"), -1).reshape(-1, 3)
+        W = np.einsum("i,j,k->ijk", w, w, w).ravel()
+        P = np.polynomial.legendre.legvander(2.0 * X - 1.0, int(p))
+        idx = basis.basis_indices(int(p))
+        phi = np.stack([P[:, 0, i] * P[:, 1, j] * P[:, 2, k] * (2 * i + 1) * (2 * j + 1) * (2 * k + 1)
+                        for i, j, k in idx], axis=1)  # phi^alpha / ||phi^alpha||^2 times the volume
+        a = np.ldexp(1.0, -lv[sel, 0].astype(np.int32))
+        coef = np.empty((len(sel), len(idx)))
+        coef[:, 0] = u[sel]
+        for r in range(1, len(idx)):
+            coef[:, r] = u[nl + hi[sel] + r - 1]
+        proj = (coef @ phi.T) / (a ** 3)[:, None]
+        U = box_potential(lv[sel, 1:4][:, None, :] * a[:, None, None] + a[:, None, None] * X[None])
+        e2 += float(np.sum(W[None, :] * (proj - U) ** 2 * (a ** 3)[:, None]))
+        n2 += float(np.sum(W[None, :] * U ** 2 * (a ** 3)[:, None]))
+    return np.sqrt(e2 / n2)
+
+
+def test_order_h_rate_at_larger_meshes():
+    """The paper's O(h) best approximation with p_l = L - l (Sec. 4) carried on to h = 1/64 on the GPU:
+    the error of the projected potential halves with h, while degree 0 on the coarse leaves stalls."""
+    errs = {deg: [_projection_error(L, deg) for L in (4, 5, 6)] for deg in (0, 1)}
+    announce("f = 1, L2 error of the projection, h = 1/16, 1/32, 1/64: p_l = L - l %s; degree 0 %s"
+             % (["%.3e" % e for e in errs[1]], ["%.3e" % e for e in errs[0]]))
+    r1 = [errs[1][k + 1] / errs[1][k] for k in range(2)]
+    r0 = [errs[0][k + 1] / errs[0][k] for k in range(2)]
+    assert max(r1) <= 0.55 and min(r0) >= 0.7 and errs[1][2] < 0.5 * errs[0][2]
