@@ -529,6 +529,8 @@ def main():
     ap.add_argument("--cpu-targets", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="mixed path without the touching-pair surrogate")
+    ap.add_argument("--surrogate-pairs", type=int, default=2000000,
+                    help="training pairs of the touching-pair surrogate (generated and labelled on the GPU)")
     ap.add_argument("--no-split16", action="store_true",
                     help="skip the mixed apply with the interaction phase on the matrix cores")
     ap.add_argument("--no-btv", action="store_true", help="skip the BtV (Algorithm 3) measurement")
@@ -582,9 +584,12 @@ def main():
         # touching-pair surrogate for the mixed path, trained on the GPU (not timed)
         t0 = time.perf_counter()
         surrogate = bcv.mlp_create(width=128, seed=1, device=dev)
-        sur_report = surrogate.train(n_train=100000, n_valid=20000, epochs=20, batch=2048, lr=2e-3, seed=42,
-                                     n_gauss_lo=5, n_gauss_hi=16, tol=SURROGATE_TOL)
+        epochs = max(2, min(20, (20 * 100000) // args.surrogate_pairs))  # about 2e6 pair-visits in all
+        sur_report = surrogate.train(n_train=args.surrogate_pairs, n_valid=20000, epochs=epochs, batch=2048, lr=2e-3,
+                                     seed=42, n_gauss_lo=5, n_gauss_hi=16, tol=SURROGATE_TOL)
         sur_report["train_seconds"] = time.perf_counter() - t0
+        sur_report["n_train"] = args.surrogate_pairs
+        sur_report["epochs"] = epochs
         print("surrogate trained: %s" % json.dumps(sur_report), file=sys.stderr, flush=True)
 
     runs = {}
