@@ -540,6 +540,9 @@ def main():
                     help="skip the neighbour-marking / level-dependent near-field measurement")
     ap.add_argument("--batched", action="store_true",
                     help="the batched workload: 64 meshes in one forest plan and one graph launch")
+    ap.add_argument("--near-only", action="store_true",
+                    help="only run `steps` near-field applies (PART_NEAR) of the mixed plan on the --L mesh, for "
+                         "counter collection, and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -553,6 +556,21 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_per_dispatch": n * 8}))
+        return
+    if args.near_only:
+        import torch
+
+        import paper_2112_00864_amd as bcv
+        import synth
+
+        tree = bcv.build_bc_tree(args.L)
+        f = torch.tensor(synth.leaf_density(tree.leaves(), seed=0), device="cuda:0")
+        u = torch.empty_like(f)
+        plan = bcv.plan_interactions(tree, q=args.q, precision=bcv.MIXED_F32, nearfield=bcv.NEAR_ASSEMBLED, streams=1)
+        for _ in range(args.steps):
+            bcv.vtv_apply_parts(plan, f, u, bcv.PART_NEAR)
+        torch.cuda.synchronize()
+        print(json.dumps({"near_only_applies": args.steps, "L": args.L}))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (a batch of meshes would "
