@@ -21,11 +21,14 @@ __device__ __forceinline__ float sigmoid(float z) { return 1.0f / (1.0f + __expf
 
 // C[M x N] = op(A) op(B) (+ bias, + C if accumulate). op(A)[m][k] = TA ? A[k * lda + m] :
 // A[m * lda + k]; op(B)[k][n] = TB ? B[n * ldb + k] : B[k * ldb + n]. If H is given it also
-// receives silu(C). One 256-thread block per 64 x 64 tile, 4 x 4 outputs per thread, K in steps
-// of 16 through LDS. Every thread sums in the same order: results do not depend on the launch.
+// receives silu(C). One 256-thread block per 64 x 64 tile, K in steps of 16 through LDS, the products
+// on the matrix cores in FP32 (each wave a 32 x 32 quarter as four 16 x 16 MFMA tiles). The sums run
+// in a fixed order: results do not depend on the launch.
 // Split K: block z covers k in [z k_chunk, (z + 1) k_chunk) and writes its partial product to
 // C + z c_stride (no bias, accumulate or H then; the partial products are summed by
 // sum_splits_kernel in z order).
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
 template <bool TA, bool TB>
 __global__ __launch_bounds__(kThreads) void gemm_kernel(int M, int N, int K, const float *__restrict__ A, int lda,
                                                         const float *__restrict__ B, int ldb,
@@ -36,10 +39,18 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(int M, int N, int K, con
     __shared__ float As[kTileK][kTile + 1];
     __shared__ float Bs[kTileK][kTile + 1];
     const int m0 = blockIdx.y * kTile, n0 = blockIdx.x * kTile;
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    const int wm = 32 * (wave >> 1), wn = 32 * (wave & 1);  // the wave's 32 x 32 quarter of the tile
     const int k_begin = (int)blockIdx.z * k_chunk, k_end = min(K, k_begin + k_chunk);
     C += (int64_t)blockIdx.z * c_stride;
-    float acc[4][4] = {};
+    // v_mfma_f32_16x16x4f32 (FP32 operands, FP32 accumulation): A[i][k] in lane i + 16 k,
+    // B[k][n] in lane n + 16 k, D[i][n] in lane n + 16 (i / 4), element i % 4. Four 16 x 16 tiles
+    // per wave.
+    f4_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
     for (int k0 = k_begin; k0 < k_end; k0 += kTileK) {
         for (int e = threadIdx.x; e < kTileK * kTile; e += kThreads) {
             const int kk = e / kTile, mm = e % kTile;
@@ -50,32 +61,35 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(int M, int N, int K, con
         }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < kTileK; ++kk) {
-            float a[4], b[4];
+        for (int kk = 0; kk < kTileK; kk += 4) {
+            const int kr = kk + lane / 16;
+            float a[2], b[2];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+            for (int i = 0; i < 2; ++i) a[i] = As[kr][wm + 16 * i + lane % 16];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
+            for (int j = 0; j < 2; ++j) b[j] = Bs[kr][wn + 16 * j + lane % 16];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int m = m0 + ty + 16 * i, n = n0 + tx + 16 * j;
-            if (m >= M || n >= N) continue;
-            float z = acc[i][j];
-            if (bias) z += bias[n];
-            float *c = C + (int64_t)m * ldc + n;
-            if (accumulate) z += *c;
-            *c = z;
-            if (H) H[(int64_t)m * ldc + n] = z * sigmoid(z);
-        }
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm + 16 * i + 4 * (lane / 16) + r, n = n0 + wn + 16 * j + lane % 16;
+                if (m >= M || n >= N) continue;
+                float z = acc[i][j][r];
+                if (bias) z += bias[n];
+                float *c = C + (int64_t)m * ldc + n;
+                if (accumulate) z += *c;
+                *c = z;
+                if (H) H[(int64_t)m * ldc + n] = z * sigmoid(z);
+            }
 }
 
 // out[i] = sum over z < splits of part[z * n + i], in z order (+ out[i] if accumulate).
