@@ -399,11 +399,21 @@ def measure_basis(bcv, torch, args, dev):
     hi = np.concatenate([[0], np.cumsum(nb - 1)])
     for k in np.nonzero(nb > 1)[0]:
         f[nl + hi[k] : nl + hi[k + 1]] = coef[off[k] + 1 : off[k + 1]]
+    fd = torch.tensor(f, device="cuda:%d" % dev)
+    ud = torch.empty_like(fd)
+    # the paper's experiment setup: p_l = L - l with q_l = 4 + L - l (Sec. 5)
+    sched = None
+    if 4 + L - 2 <= 10:
+        t0 = time.perf_counter()
+        splan = bcv.plan_interactions(tree, q=4, q_schedule=1, device=dev, streams=1, basis_degree=1)
+        splan_s = time.perf_counter() - t0
+        sms, sph = timed_applies(bcv, torch, splan, fd, ud, args.warmup, args.steps, dev)
+        sched = {"orders": "q_l = 4 + L - l", "ms_per_apply": sms, "value": splan.info["n_dofs"] / (sms * 1e-3),
+                 "phase_ms": sph, "plan_seconds": splan_s}
+        del splan
     t0 = time.perf_counter()
     plan = bcv.plan_interactions(tree, q=args.q, device=dev, streams=1, basis_degree=1)
     plan_s = time.perf_counter() - t0
-    fd = torch.tensor(f, device="cuda:%d" % dev)
-    ud = torch.empty_like(fd)
     ms, phases = timed_applies(bcv, torch, plan, fd, ud, args.warmup, args.steps, dev)
     info = plan.info
     near_bytes = 8 * info["n_basis_vals"] + 12 * info["n_basis_cols"] + 8 * info["n_dofs"]
@@ -419,6 +429,8 @@ def measure_basis(bcv, torch, args, dev):
            "near_roofline": {"bound": "hbm", "bytes": near_bytes, "ms": near_ms,
                              "achieved": near_bytes / (near_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                              "frac": near_bytes / (near_ms * 1e-3) / PEAK_HBM}}
+    if sched is not None:
+        res["level_orders"] = sched
     del plan
     return res
 

@@ -155,9 +155,10 @@ typedef struct {
                               by the alpha = 1 .. ncoef(p_w)-1 coefficients of every leaf with
                               p_w > 0, leaf by leaf (alpha in the graded order of
                               bcv_touching_basis_block); n_dofs in bcv_plan_info. The near field is
-                              assembled at plan time (opts.nearfield is ignored). Requires
-                              BCV_FP64, a fixed q of 4, 6 or 8, a single mesh of side 1, no surrogate,
-                              no opts.boundary, and L - (coarsest leaf level) <= 8 */
+                              assembled at plan time (opts.nearfield is ignored). Combines with any
+                              q and with q_schedule (the paper's experiments take p_l = L - l with
+                              q_l = 4 + L - l, Sec. 5). Requires BCV_FP64, a single mesh of side 1, no
+                              surrogate, no opts.boundary, and L - (coarsest leaf level) <= 8 */
 } bcv_plan_opts;
 
 /* Sizes of a plan (all counts, no pointers). */

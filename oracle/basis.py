@@ -180,10 +180,12 @@ def apply_direct(mesh, F, targets=None, degree_zero=False):
 
 class BasisFMM(fmm.FMM):
     """O2 with degree-p leaf bases: Algorithm 1 with the leaf spaces above; the passes and the
-    interaction phase are those of oracle.fmm (fixed order q)."""
+    interaction phase are those of oracle.fmm (fixed order q, or with q_schedule = 1 the
+    level-dependent orders q_l = q + L - l: the paper's experiment takes both p_l = L - l and
+    q_l = 4 + L - l, Sec. 5)."""
 
-    def __init__(self, mesh, q, degree_zero=False):
-        super().__init__(mesh, q)
+    def __init__(self, mesh, q, degree_zero=False, q_schedule=0):
+        super().__init__(mesh, q, q_schedule=q_schedule)
         self.lf = Leaves(mesh, degree_zero)
 
     def near_field_basis(self, F, targets):

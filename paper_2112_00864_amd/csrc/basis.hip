@@ -229,68 +229,69 @@ __global__ void basis_combine_kernel(int64_t n_splits, const BasisSplit *__restr
     u[dof_of(sp.t, sp.a0 + c, n_leaves, hi_off)] = x;
 }
 
-// Moments of every leaf (one thread per (leaf, j < ldr)): the full coefficients j, j + ldr, ... (not
-// for the degree-0 leaves of level L, whose parents take their moments from the densities, see
-// m2m_leaves_kernel) and the folded coefficient j.
-template <int Q>
+// Moments of every leaf (one thread per (leaf, j < ldr)): the full coefficients j, j + ldr, ... < ncoef(q_l)
+// (not for the degree-0 leaves of level L when skip_finest, whose parents take their moments from
+// the densities, see m2m_leaves_kernel) and the folded coefficient j < (q_l + 1)^2. The multi-index
+// and fold tables of order 10 serve every order: both orders are graded, so those of order q are
+// their prefixes.
 __global__ __launch_bounds__(256) void basis_p2m_kernel(int64_t n_leaves, const int32_t *__restrict__ leaf_cell,
                                                         const double4 *__restrict__ geom, int L,
                                                         const int64_t *__restrict__ hi_off,
-                                                        const BasisTables *__restrict__ tab,
-                                                        const double *__restrict__ f, double *__restrict__ M,
-                                                        double *__restrict__ Mr, int32_t ldk, int32_t ldr)
+                                                        const BasisTables *__restrict__ tab, const BasisOrders bo,
+                                                        int skip_finest, const double *__restrict__ f,
+                                                        double *__restrict__ M, double *__restrict__ Mr)
 {
-    constexpr int K = ncoef(Q), R = nreduced(Q);
+    constexpr int QT = kMaxBasisQ;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t w = idx / ldr;
-    const int j = (int)(idx - w * ldr);
+    const int64_t w = idx / bo.ldr;
+    const int j = (int)(idx - w * bo.ldr);
     if (w >= n_leaves) return;
     const double a = geom[w].w;
-    const int p = L - level_of(a);
+    const int lev = level_of(a);
+    const int p = L - lev;
     const int nf = ncoef(p);
     const double a3 = a * a * a;
     auto moment = [&](int b) {
         double s = 0.0;
         for (int r = 0; r < nf; ++r)
-            s = fma(tab->t[p][kMi<Q>.e[b][0]][kMiB.e[r][0]] * tab->t[p][kMi<Q>.e[b][1]][kMiB.e[r][1]] *
-                        tab->t[p][kMi<Q>.e[b][2]][kMiB.e[r][2]],
+            s = fma(tab->t[p][kMi<QT>.e[b][0]][kMiB.e[r][0]] * tab->t[p][kMi<QT>.e[b][1]][kMiB.e[r][1]] *
+                        tab->t[p][kMi<QT>.e[b][2]][kMiB.e[r][2]],
                     f[dof_of(w, r, n_leaves, hi_off)], s);
         return s * a3;
     };
     const int64_t c = leaf_cell[w];
-    if (p > 0)  // leaves of level L (degree 0): only the folded row; their parents' moments come from f
-        for (int b = j; b < K; b += ldr) M[c * ldk + b] = moment(b);
-    if (j < R) {
+    if (p > 0 || !skip_finest)
+        for (int b = j; b < bo.k[lev]; b += bo.ldr) M[c * bo.ldk + b] = moment(b);
+    if (j < bo.r[lev]) {
         double s = 0.0;
-        for (int k = 0; k < kFoldB<Q>.n[j]; ++k) s = fma(kFoldB<Q>.c[j][k], moment(kFoldB<Q>.src[j][k]), s);
-        Mr[c * ldr + j] = s;
+        for (int k = 0; k < kFoldB<QT>.n[j]; ++k) s = fma(kFoldB<QT>.c[j][k], moment(kFoldB<QT>.src[j][k]), s);
+        Mr[c * bo.ldr + j] = s;
     }
 }
 
-// Evaluation of every coefficient (one thread each): u[(w, alpha)] += a^3 sum_b e(alpha, b) Lambda_w^b.
-template <int Q>
+// Evaluation of every coefficient (one thread each): u[(w, alpha)] += a^3 sum_{b < ncoef(q_l)} e(alpha, b) Lambda_w^b.
 __global__ __launch_bounds__(256) void basis_eval_kernel(int64_t n_dofs, int64_t n_leaves,
                                                          const int32_t *__restrict__ leaf_cell,
                                                          const double4 *__restrict__ geom, int L,
                                                          const int64_t *__restrict__ hi_off,
                                                          const int32_t *__restrict__ dof_leaf,
-                                                         const BasisTables *__restrict__ tab,
-                                                         const double *__restrict__ Lam, int32_t ldk,
-                                                         double *__restrict__ u)
+                                                         const BasisTables *__restrict__ tab, const BasisOrders bo,
+                                                         const double *__restrict__ Lam, double *__restrict__ u)
 {
-    constexpr int K = ncoef(Q);
+    constexpr int QT = kMaxBasisQ;
     const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (d >= n_dofs) return;
     const int64_t w = d < n_leaves ? d : dof_leaf[d - n_leaves];
     const int r = d < n_leaves ? 0 : (int)(d - n_leaves - hi_off[w]) + 1;
     const double a = geom[w].w;
-    const int p = L - level_of(a);
-    const double *lam = Lam + (int64_t)leaf_cell[w] * ldk;
+    const int lev = level_of(a);
+    const int p = L - lev;
+    const double *lam = Lam + (int64_t)leaf_cell[w] * bo.ldk;
     const int r0 = kMiB.e[r][0], r1 = kMiB.e[r][1], r2 = kMiB.e[r][2];
     double s = 0.0;
-    for (int b = 0; b < K; ++b)
-        s = fma(tab->e[p][r0][kMi<Q>.e[b][0]] * tab->e[p][r1][kMi<Q>.e[b][1]] * tab->e[p][r2][kMi<Q>.e[b][2]], lam[b],
-                s);
+    for (int b = 0; b < bo.k[lev]; ++b)
+        s = fma(tab->e[p][r0][kMi<QT>.e[b][0]] * tab->e[p][r1][kMi<QT>.e[b][1]] * tab->e[p][r2][kMi<QT>.e[b][2]],
+                lam[b], s);
     u[d] += s * a * a * a;
 }
 
@@ -399,19 +400,27 @@ void launch_basis_zero(const bcv_plan_s &p, double *u, hipStream_t st)
     check();
 }
 
+namespace {
+BasisOrders basis_orders(const bcv_plan_s &p)
+{
+    BasisOrders bo{};
+    for (int l = 0; l <= kMaxLevel; ++l) {
+        bo.k[l] = ncoef(p.q_level[l]);
+        bo.r[l] = nreduced(p.q_level[l]);
+    }
+    bo.ldk = p.K;
+    bo.ldr = p.R;
+    return bo;
+}
+}  // namespace
+
 void launch_basis_p2m(const bcv_plan_s &p, const double *f, hipStream_t st)
 {
     const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
     const unsigned blocks = (unsigned)((p.n_leaves * p.R + 255) / 256);
-    switch (p.q) {
-    case 4: basis_p2m_kernel<4><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, p.L, p.d_hi_off, p.d_btab, f,
-                                                        p.d_M, p.d_Mr, p.K, p.R); break;
-    case 6: basis_p2m_kernel<6><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, p.L, p.d_hi_off, p.d_btab, f,
-                                                        p.d_M, p.d_Mr, p.K, p.R); break;
-    case 8: basis_p2m_kernel<8><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, p.L, p.d_hi_off, p.d_btab, f,
-                                                        p.d_M, p.d_Mr, p.K, p.R); break;
-    default: fail(BCV_ENOTSUP, "degree-p leaf bases: expansion orders 4, 6, 8");
-    }
+    // with level-dependent orders the upward pass reads the level-L leaves' moments too
+    basis_p2m_kernel<<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, geom, p.L, p.d_hi_off, p.d_btab,
+                                             basis_orders(p), p.q_schedule ? 0 : 1, f, p.d_M, p.d_Mr);
     check();
 }
 
@@ -419,15 +428,8 @@ void launch_basis_eval(const bcv_plan_s &p, double *u, hipStream_t st)
 {
     const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
     const unsigned blocks = (unsigned)((p.n_dofs + 255) / 256);
-    switch (p.q) {
-    case 4: basis_eval_kernel<4><<<blocks, 256, 0, st>>>(p.n_dofs, p.n_leaves, p.d_leaf_cell, geom, p.L, p.d_hi_off,
-                                                         p.d_dof_leaf, p.d_btab, p.d_Lam, p.K, u); break;
-    case 6: basis_eval_kernel<6><<<blocks, 256, 0, st>>>(p.n_dofs, p.n_leaves, p.d_leaf_cell, geom, p.L, p.d_hi_off,
-                                                         p.d_dof_leaf, p.d_btab, p.d_Lam, p.K, u); break;
-    case 8: basis_eval_kernel<8><<<blocks, 256, 0, st>>>(p.n_dofs, p.n_leaves, p.d_leaf_cell, geom, p.L, p.d_hi_off,
-                                                         p.d_dof_leaf, p.d_btab, p.d_Lam, p.K, u); break;
-    default: fail(BCV_ENOTSUP, "degree-p leaf bases: expansion orders 4, 6, 8");
-    }
+    basis_eval_kernel<<<blocks, 256, 0, st>>>(p.n_dofs, p.n_leaves, p.d_leaf_cell, geom, p.L, p.d_hi_off, p.d_dof_leaf,
+                                              p.d_btab, basis_orders(p), p.d_Lam, u);
     check();
 }
 

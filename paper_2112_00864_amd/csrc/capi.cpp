@@ -114,10 +114,8 @@ void check_plan_opts(const bcv_plan_opts &o, int device)
     BCV_REQUIRE(o.near_order == 0 || o.nearfield == BCV_NEAR_ASSEMBLED, BCV_EINVAL,
                 "near_order 1 needs the assembled near field (BCV_NEAR_ASSEMBLED)");
     BCV_REQUIRE(o.basis_degree == 0 || o.basis_degree == 1, BCV_EINVAL, "basis_degree must be 0 or 1");
-    BCV_REQUIRE(o.basis_degree == 0 || (o.precision == BCV_FP64 && !o.q_schedule &&
-                                        (o.q == 4 || o.q == 6 || o.q == 8) && !o.boundary && !o.surrogate),
-                BCV_ENOTSUP,
-                "degree-p leaf bases need BCV_FP64, a fixed q of 4, 6 or 8, no boundary structures and no surrogate");
+    BCV_REQUIRE(o.basis_degree == 0 || (o.precision == BCV_FP64 && !o.boundary && !o.surrogate), BCV_ENOTSUP,
+                "degree-p leaf bases need BCV_FP64, no boundary structures and no surrogate");
     if (o.surrogate) {
         check_mlp(o.surrogate);
         BCV_REQUIRE(o.surrogate_tol >= 0.0, BCV_EINVAL, "negative surrogate tolerance");

@@ -109,7 +109,7 @@ struct BasisSplit {
 };
 
 // Gauss rules and the per-degree moment and evaluation factors of the leaf bases (basis.hip).
-constexpr int kMaxBasisQ = 8;
+constexpr int kMaxBasisQ = kMaxSchedQ;  // expansion orders up to 10 (level-dependent orders)
 struct BasisTables {
     double x[kMaxBasisDegree + 3][kMaxBasisDegree + 2];  // [n][k]: n-point Gauss-Legendre nodes on [0, 1]
     double w[kMaxBasisDegree + 3][kMaxBasisDegree + 2];  // and weights (summing to 1)
@@ -118,6 +118,11 @@ struct BasisTables {
     double e[kMaxBasisDegree + 1][kMaxBasisDegree + 1][kMaxBasisQ + 1];   // [p][a][b]: evaluation
 };
 BasisTables basis_tables();
+// Expansion sizes per level for the basis kernels: ncoef(q_l) and (q_l + 1)^2, and the row strides.
+struct BasisOrders {
+    int32_t k[kMaxLevel + 1], r[kMaxLevel + 1];
+    int32_t ldk, ldr;
+};
 
 // Boundary faces (BtV): a face is (leaf, axis, side), the leaf's face normal to `axis` at its low
 // (side 0) or high (side 1) end. A touching (cell, face) pair of equal size is the cube [0,1]^3 and

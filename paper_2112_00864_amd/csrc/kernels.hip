@@ -2006,7 +2006,7 @@ void basis_apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, h
         launch_basis_p2m(p, f, st);
         marks.stop(BCV_PHASE_P2M, st);
         marks.start(BCV_PHASE_M2M, st);
-        upward_pass<Q>(p, st, f);  // level L - 1 from the degree-0 coefficients of its level-L children
+        upward_pass<Q>(p, st, f);  // fixed orders: level L - 1 from the degree-0 coefficients of its children
         marks.stop(BCV_PHASE_M2M, st);
         marks.start(BCV_PHASE_M2L, st);
         interaction_phase<Q>(p, st);
@@ -2124,11 +2124,15 @@ void launch_btv(const bcv_plan_s &p, const double *qf, const double *gf, double 
 void launch_apply(const bcv_plan_s &p, const double *f, double *u, int parts, hipStream_t st)
 {
     if (p.basis) {
+        if (p.q_schedule) {  // the passes pick their kernels level by level
+            basis_apply_q<4>(p, f, u, parts, st);
+            return;
+        }
         switch (p.q) {
         case 4: basis_apply_q<4>(p, f, u, parts, st); break;
         case 6: basis_apply_q<6>(p, f, u, parts, st); break;
         case 8: basis_apply_q<8>(p, f, u, parts, st); break;
-        default: fail(BCV_ENOTSUP, "degree-p leaf bases: expansion orders 4, 6, 8");
+        default: fail(BCV_ENOTSUP, "expansion order not compiled");
         }
         return;
     }

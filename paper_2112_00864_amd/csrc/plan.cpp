@@ -943,8 +943,6 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
     if (opts.basis_degree != 0) {
         BCV_REQUIRE(opts.basis_degree == 1, BCV_EINVAL, "basis_degree must be 0 or 1");
         BCV_REQUIRE(opts.precision == BCV_FP64, BCV_ENOTSUP, "degree-p leaf bases: BCV_FP64 only");
-        BCV_REQUIRE(!opts.q_schedule && (opts.q == 4 || opts.q == 6 || opts.q == 8), BCV_ENOTSUP,
-                    "degree-p leaf bases: fixed orders 4, 6, 8 only");
         BCV_REQUIRE(t.n_meshes == 1 && t.mesh_side[0] == 1.0, BCV_ENOTSUP,
                     "degree-p leaf bases: a single mesh of side 1");
         BCV_REQUIRE(!opts.boundary && !opts.surrogate, BCV_ENOTSUP,

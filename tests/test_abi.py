@@ -163,7 +163,7 @@ def test_basis_options_checked_before_device_use():
     with pytest.raises(bcv.BCVError) as e:
         bcv.plan_interactions(t, basis_degree=2)
     assert e.value.status == bcv.bcv.EINVAL
-    for kw in ({"precision": bcv.MIXED_F32}, {"q": 5}, {"q_schedule": 1}, {"boundary": True}):
+    for kw in ({"precision": bcv.MIXED_F32}, {"boundary": True}):
         with pytest.raises(bcv.BCVError) as e:
             bcv.plan_interactions(t, basis_degree=1, **kw)
         assert e.value.status == bcv.bcv.ENOTSUP

@@ -149,10 +149,36 @@ def test_parts_linearity_and_graph():
         assert np.array_equal(ud.cpu().numpy()[pos], u)
 
 
+@pytest.mark.parametrize("L, q", [(3, 4), (3, 6), (6, 4)])
+def test_level_orders_against_O2(L, q):
+    """The paper's experiment setup: p_l = L - l with q_l = q + L - l (Sec. 5), against O2 with the same
+    orders (all coefficients at h = 1/8; sampled leaves of every degree at h = 1/64)."""
+    m = BCMesh(L)
+    lf = basis.Leaves(m)
+    F = np.random.default_rng(40 + L + q).standard_normal(lf.off[-1])
+    plan = bcv.plan_interactions(bcv.build_bc_tree(L), q=q, q_schedule=1, basis_degree=1, streams=1)
+    u = gpu_apply(plan, F, layout(lf))
+    fm = basis.BasisFMM(m, q, q_schedule=1)
+    if L <= 3:
+        ref = fm.apply_basis(F)
+        err = rel(u, ref)
+    else:
+        rng = np.random.default_rng(7)
+        targets = [0, len(lf.lv) - 1]
+        for p in range(int(lf.p.max()) + 1):
+            cand = np.nonzero(lf.p == p)[0]
+            targets += list(rng.choice(cand, min(2, len(cand)), replace=False))
+        targets = np.array(sorted(set(int(t) for t in targets)))
+        ref = fm.apply_basis_sampled(F, targets)
+        got = np.concatenate([u[lf.off[t] : lf.off[t + 1]] for t in targets])
+        err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    announce("basis + level orders L=%d q=%d vs O2: %.3e" % (L, q, err))
+    assert err <= TOL
+
+
 def test_option_errors():
     tree = bcv.build_bc_tree(3)
     for kw, code in ((dict(basis_degree=2), bcv.EINVAL), (dict(basis_degree=1, precision=bcv.MIXED_F32), bcv.ENOTSUP),
-                     (dict(basis_degree=1, q=5), bcv.ENOTSUP), (dict(basis_degree=1, q_schedule=1), bcv.ENOTSUP),
                      (dict(basis_degree=1, boundary=True), bcv.ENOTSUP)):
         with pytest.raises(bcv.BCVError) as e:
             bcv.plan_interactions(tree, **kw)

@@ -221,3 +221,19 @@ def test_order_h_rate_with_level_degrees():
     _, _, z3 = _closed_form_errors(3, True)
     _, _, z4 = _closed_form_errors(4, True)
     assert a4 / a3 <= 0.5 and z4 / z3 >= 0.6 and a4 < z4
+
+
+def test_level_orders_with_degree_bases():
+    """The paper's experiment setup, p_l = L - l with q_l = q0 + L - l (Sec. 5): O2 with these orders
+    against O1 is more accurate than the fixed q0 and converges as q0 grows (h = 1/8, random
+    coefficients; stated 1.4e-6 and 9.6e-8 for q0 = 4 and 6, against 6.4e-6 and 3.6e-7 at fixed q)."""
+    mesh = BCMesh(3)
+    lf = basis.Leaves(mesh)
+    F = np.random.default_rng(0).standard_normal(lf.off[-1])
+    u = basis.apply_direct(mesh, F)
+    err = {}
+    for q0 in (4, 6):
+        for sched in (0, 1):
+            v = basis.BasisFMM(mesh, q0, q_schedule=sched).apply_basis(F)
+            err[(q0, sched)] = np.linalg.norm(v - u) / np.linalg.norm(u)
+    assert err[(4, 1)] < err[(4, 0)] and err[(6, 1)] < err[(6, 0)] and err[(6, 1)] < err[(4, 1)] / 10
