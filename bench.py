@@ -287,7 +287,8 @@ def measure_btv(bcv, torch, tree, f, args, dev):
         del out[prec]["vtb"]["uf"]
     return {"vtb_mixed_vs_fp64_rel": vtb_rel, "n_vtb_near_pairs": info["n_vtb_near"],"metric": "BtV cell-potentials/s (Algorithm 3, u = <1_w, V[q] - K[g]>), 1 GPU",
             "unit": "cell-potentials/s", "n_faces": info["n_faces"], "n_btv_near_pairs": info["n_btv_near"],
-            "n_btv_touching_pairs": info["n_btv_touch"], "fp64": out["fp64"], "mixed": out["mixed"],
+            "n_btv_touching_pairs": info["n_btv_touch"],
+            "n_btv_m2l_pairs": info["n_btv_m2l"], "n_vtb_m2l_pairs": info["n_vtb_m2l"], "n_vtv_m2l_pairs": info["n_m2l"], "fp64": out["fp64"], "mixed": out["mixed"],
             "mixed_vs_fp64_rel_l2": rel, "representation_formula_rel_err": rep,
             "data": "synthetic: face averages of u = sum_k c_k/|x - p_k| (4 poles outside the cube, seed 0) and "
                     "of du/dn; the representation formula gives u in the cube"}

@@ -188,6 +188,9 @@ typedef struct {
     int64_t n_basis_vals; /* near-field block entries held by a plan with opts.basis_degree = 1 */
     int64_t n_basis_cols; /* their distinct columns: per target leaf, the coefficients of its near
                              sources (shared by the target's rows) */
+    int64_t n_btv_m2l;    /* interaction-list pairs of the BtV apply: boundary sources only (0
+                             without opts.boundary or for a direct plan) */
+    int64_t n_vtb_m2l;    /* interaction-list pairs of the VtB apply: boundary targets only */
 } bcv_plan_info;
 
 /* Build the BC octree of Sec. 2 on the host. desc and out must be non-NULL.

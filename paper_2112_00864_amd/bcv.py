@@ -57,7 +57,8 @@ class PlanInfo(ctypes.Structure):
                                               "n_btv_touch", "n_vtb_near", "n_near_ordered",
                                               "device_bytes")] + [
         ("K", ctypes.c_int32), ("L", ctypes.c_int32), ("surrogate_classes", ctypes.c_int32), ("pad", ctypes.c_int32),
-        ("n_dofs", ctypes.c_int64), ("n_basis_vals", ctypes.c_int64), ("n_basis_cols", ctypes.c_int64)]
+        ("n_dofs", ctypes.c_int64), ("n_basis_vals", ctypes.c_int64), ("n_basis_cols", ctypes.c_int64),
+        ("n_btv_m2l", ctypes.c_int64), ("n_vtb_m2l", ctypes.c_int64)]
 
 
 CONTACT_FACE, CONTACT_EDGE, CONTACT_VERTEX = 1, 2, 3

@@ -293,6 +293,8 @@ bcv_status bcv_plan_get_info(bcv_plan plan, bcv_plan_info *info)
         info->n_dofs = plan->basis ? plan->n_dofs : plan->n_leaves;
         info->n_basis_vals = plan->n_bvals;
         info->n_basis_cols = plan->n_bcols;
+        info->n_btv_m2l = plan->btv_m2l.n_pairs;
+        info->n_vtb_m2l = plan->vtb_m2l.n_pairs;
     });
 }
 

@@ -171,6 +171,21 @@ void mlp_save(const bcv_mlp_s &net, const char *path);
 bcv_mlp_s *mlp_load(const char *path, int device);
 }  // namespace bcv
 
+// An interaction plan other than the VtV one (opts.boundary): the BtV plan, whose lists hold the
+// boundary sources only (I(w) ∩ B_l, Algorithm 3), and the VtB plan, whose targets are the boundary
+// cells only (Algorithm 2 needs their local coefficients alone). Same layout as the plan's own
+// M2L fields; the apply swaps them in.
+struct M2LSet {
+    int64_t n_tasks = 0, n_pairs = 0, n_m2l_splits = 0, m2l_groups = 0;
+    bcv::M2LTask *d_tasks = nullptr;
+    int32_t *d_task_targets = nullptr;
+    int32_t *d_slot_off = nullptr;
+    uint32_t *d_slot_src = nullptr;
+    bcv::M2LSplit *d_m2l_splits = nullptr;
+    double *d_m2l_partial = nullptr;
+    int32_t xcd_begin[bcv::kXcds + 1] = {};
+};
+
 struct bcv_plan_s {
     static constexpr uint32_t kMagic = 0x42435650u;  // "BCVP"
     uint32_t magic = kMagic;
@@ -264,6 +279,7 @@ struct bcv_plan_s {
 
     // BtV (Algorithm 3), built when the plan options ask for it.
     int boundary = 0;
+    M2LSet btv_m2l, vtb_m2l;  // their interaction plans (far-field plans only)
     int64_t n_faces = 0, n_btv_near = 0, n_btv_touch = 0, n_btv_units = 0, n_btv_splits = 0;
     uint32_t *d_faces = nullptr;        // per boundary face: leaf | (2 axis + side) << 28
     int32_t *d_leaf_faces = nullptr;    // n_leaves + 1: the faces of leaf t are [d_leaf_faces[t], d_leaf_faces[t + 1])

@@ -2029,9 +2029,27 @@ void basis_apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, h
     marks.finish(st);
 }
 
+// The plan with one of its other interaction plans (BtV, VtB) in place of the VtV one (a shallow
+// copy: the device buffers stay the plan's).
+bcv_plan_s with_m2l(const bcv_plan_s &p, const M2LSet &ms)
+{
+    bcv_plan_s q = p;
+    q.n_tasks = ms.n_tasks;
+    q.d_tasks = ms.d_tasks;
+    q.d_task_targets = ms.d_task_targets;
+    q.d_slot_off = ms.d_slot_off;
+    q.d_slot_src = ms.d_slot_src;
+    q.n_m2l_splits = ms.n_m2l_splits;
+    q.d_m2l_splits = ms.d_m2l_splits;
+    q.d_m2l_partial = ms.d_m2l_partial;
+    q.m2l_groups = ms.m2l_groups;
+    for (int x = 0; x <= kXcds; ++x) q.xcd_begin[x] = ms.xcd_begin[x];
+    return q;
+}
+
 // BtV apply (Algorithm 3), on the caller's stream: boundary moments, upward pass, interaction
-// phase (all interaction-list sources; cells without boundary faces below them carry zero moments),
-// downward pass, then the near field of the boundary faces fused with the evaluation phase.
+// phase over the boundary sources I(w) ∩ B_l (the plan's BtV interaction plan), downward pass, then
+// the near field of the boundary faces fused with the evaluation phase.
 template <int Q>
 void btv_q(const bcv_plan_s &p, const double *qf, const double *gf, double *u, hipStream_t st)
 {
@@ -2048,7 +2066,7 @@ void btv_q(const bcv_plan_s &p, const double *qf, const double *gf, double *u, h
                                                               p.d_faces, qf, gf, p.d_M, p.d_Mr);
         check_launch();
         upward_pass<Q>(p, st);
-        interaction_phase<Q>(p, st);
+        interaction_phase<Q>(with_m2l(p, p.btv_m2l), st);
         downward_pass<Q>(p, st);
     }
     const double *lam = far ? p.d_Lam : nullptr;
@@ -2069,8 +2087,10 @@ void btv_q(const bcv_plan_s &p, const double *qf, const double *gf, double *u, h
 }
 
 // VtB apply (Algorithm 2), on the caller's stream: moments of every leaf, upward pass, interaction
-// phase and downward pass (for every cell; the boundary cells' coefficients are the ones used),
-// then the near field of the faces fused with the evaluation at the faces.
+// phase for the boundary cells only (the plan's VtB interaction plan), downward pass (the boundary
+// cells' coefficients, whose ancestors are boundary cells, are the ones used; the other cells'
+// coefficients are not written by this apply's interaction phase and are never read), then the near
+// field of the faces fused with the evaluation at the faces.
 template <int Q>
 void vtb_q(const bcv_plan_s &p, const double *f, double *uf, hipStream_t st)
 {
@@ -2080,7 +2100,7 @@ void vtb_q(const bcv_plan_s &p, const double *f, double *uf, hipStream_t st)
     if (far) {
         launch_p2m<Q>(p, f, st, true);
         upward_pass<Q>(p, st, f);
-        interaction_phase<Q>(p, st);
+        interaction_phase<Q>(with_m2l(p, p.vtb_m2l), st);
         downward_pass<Q>(p, st);
     }
     const double *lam = far ? p.d_Lam : nullptr;

@@ -305,8 +305,10 @@ constexpr int kDefaultMaxSlotsSchedule = 256;
 
 int offset_key(int a, int b, int c) { return ((a + 7) * 15 + (b + 7)) * 15 + (c + 7); }
 
-// Sorted interaction-offset keys of cell c at level lev (its I list, eq. after spaceDecomp:Om).
-void interaction_keys(const bcv_tree_s &t, const std::vector<Grid> &g, int lev, int32_t c, std::vector<int32_t> &keys)
+// Sorted interaction-offset keys of cell c at level lev (its I list, eq. after spaceDecomp:Om);
+// with source_ok, only the sources s with source_ok[s] (the BtV interaction sources I(w) ∩ B_l).
+void interaction_keys(const bcv_tree_s &t, const std::vector<Grid> &g, int lev, int32_t c, std::vector<int32_t> &keys,
+                      const uint8_t *source_ok = nullptr)
 {
     keys.clear();
     const int i = t.ijk[3 * c], j = t.ijk[3 * c + 1], k = t.ijk[3 * c + 2];
@@ -315,6 +317,7 @@ void interaction_keys(const bcv_tree_s &t, const std::vector<Grid> &g, int lev, 
         if (pn < 0 || !t.refined[pn]) continue;  // only marked parent-neighbours have children
         for (int d = 0; d < 8; ++d) {
             const int32_t s = t.first_child[pn] + d;
+            if (source_ok && !source_ok[s]) continue;
             const int a = i - t.ijk[3 * s], b = j - t.ijk[3 * s + 1], cc = k - t.ijk[3 * s + 2];
             if (!is_neighbour_offset(a, b, cc)) keys.push_back(offset_key(a, b, cc));
         }
@@ -346,8 +349,11 @@ uint64_t hash_keys(const std::vector<int32_t> &keys)
 // ranges of their own (the levels are launched one by one, at their own expansion orders).
 // small_slots > 0: the limit for phases of fewer than 2^20 slots (about 256 per wave slot of the
 // GPU), where shorter pieces give more waves.
+// source_ok: only these sources enter the lists (the BtV plan: boundary cells); target_ok: only
+// these cells are targets (the VtB plan: boundary cells, whose local coefficients the faces need).
 M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, const std::vector<int32_t> &max_slots,
-                  bool per_level = false, int32_t small_slots = 0)
+                  bool per_level = false, int32_t small_slots = 0, const uint8_t *source_ok = nullptr,
+                  const uint8_t *target_ok = nullptr)
 {
     M2LPlan m;
     const int32_t zero_row = (int32_t)t.n_cells();
@@ -362,28 +368,33 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, const std::ve
     for (int lev = t.L; lev >= 2; --lev) {
         const int32_t b = t.lvl_start[lev], n = t.lvl_start[lev + 1] - b;
         std::vector<uint64_t> sig(n);
+        std::vector<char> is_t(n, 1);
+        if (target_ok)
+            for (int32_t q = 0; q < n; ++q) is_t[q] = target_ok[b + q] != 0;
 #pragma omp parallel
         {
             std::vector<int32_t> keys;
 #pragma omp for schedule(dynamic, 256)
             for (int32_t q = 0; q < n; ++q) {
-                interaction_keys(t, g, lev, b + q, keys);
+                interaction_keys(t, g, lev, b + q, keys, source_ok);
                 sig[q] = hash_keys(keys);
             }
         }
         // classes in order of their first (Morton-smallest) member
-        std::vector<int32_t> order(n);
-        for (int32_t q = 0; q < n; ++q) order[q] = q;
+        std::vector<int32_t> order;
+        for (int32_t q = 0; q < n; ++q)
+            if (is_t[q]) order.push_back(q);
         std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return sig[x] < sig[y]; });
+        const int32_t nt = (int32_t)order.size();
         struct Class {
             int32_t s0, s1;  // range in order
             int axis;
         };
         std::vector<Class> classes;
         std::unordered_map<uint64_t, int32_t> class_of_sig;
-        for (int32_t s0 = 0; s0 < n;) {
+        for (int32_t s0 = 0; s0 < nt;) {
             int32_t s1 = s0;
-            while (s1 < n && sig[order[s1]] == sig[order[s0]]) ++s1;
+            while (s1 < nt && sig[order[s1]] == sig[order[s0]]) ++s1;
             // the class in rows along the axis with the most member pairs two cells apart (x first on
             // ties); a class may span several separate patches of the level
             int axis = 0;
@@ -392,7 +403,7 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, const std::ve
                 const int32_t *c = &t.ijk[3 * (b + order[r])];
                 for (int ax = 0; ax < 3; ++ax) {
                     const int32_t nb = g[lev].at(c[0] + 2 * (ax == 0), c[1] + 2 * (ax == 1), c[2] + 2 * (ax == 2));
-                    pairs[ax] += nb >= 0 && sig[nb - b] == sig[order[s0]];
+                    pairs[ax] += nb >= 0 && is_t[nb - b] && sig[nb - b] == sig[order[s0]];
                 }
             }
             for (int ax = 1; ax < 3; ++ax)
@@ -421,6 +432,10 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, const std::ve
                 const int32_t *c = &t.ijk[3 * (b + order[r])];
                 const int32_t nb = g[lev].at(c[0] + (ax == 0), c[1] + (ax == 1), c[2] + (ax == 2));
                 if (nb < 0) continue;
+                if (!is_t[nb - b]) {
+                    ok = false;
+                    break;
+                }
                 const int32_t pc = class_of(nb);
                 if (cand < 0) cand = pc;
                 ok = pc == cand;
@@ -498,7 +513,7 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, const std::ve
             const int nl = (int)ch.cells.size();
             std::fill(used.begin(), used.end(), 0);
             for (int lane = 0; lane < nl; ++lane) {
-                interaction_keys(t, g, ch.lev, ch.cells[lane], keys);
+                interaction_keys(t, g, ch.lev, ch.cells[lane], keys, source_ok);
                 for (int32_t key : keys) used[key] = 1;
             }
             Out &o = outs[q];
@@ -538,7 +553,8 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, const std::ve
         for (size_t q = 0; q < chunks.size(); ++q) {
             const Chunk &ch = chunks[q];
             const int nl = (int)ch.cells.size();
-            for (int lane = 0; lane < nl; ++lane) interaction_keys(t, g, ch.lev, ch.cells[lane], lane_keys[lane]);
+            for (int lane = 0; lane < nl; ++lane)
+                interaction_keys(t, g, ch.lev, ch.cells[lane], lane_keys[lane], source_ok);
             Out &o = outs[q];
             uint32_t *src = m.slot_src.get() + chunk_base[q] * 64;
             for (size_t k = 0; k < o.keys.size(); ++k) {
@@ -1154,6 +1170,40 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         p->m2l_groups = (int64_t)kXcds * longest;
         for (int lev = 0; lev <= kMaxLevel; ++lev)
             for (int x = 0; x <= kXcds; ++x) p->level_xcd[lev][x] = m2l.level_xcd[lev][x];
+        if (opts.boundary) {
+            // BtV: sources restricted to the boundary cells B_l; VtB: targets restricted to them.
+            std::vector<uint8_t> on_b(t.n_cells(), 0);
+            for (int64_t c = 0; c < t.n_cells(); ++c) {
+                const int lev = t.level[c];
+                const int32_t top = (1 << lev) - 1;
+                const int32_t *x = &t.ijk[3 * c];
+                on_b[c] = std::min({x[0], x[1], x[2], top - x[0], top - x[1], top - x[2]}) == 0;
+            }
+            const int32_t small = opts.m2l_max_slots == 0 ? kDefaultMaxSlotsSchedule : 0;
+            auto make_set = [&](const uint8_t *src_ok, const uint8_t *tgt_ok, M2LSet &ms) {
+                M2LPlan b = build_m2l(t, grids, level_slots, false, small, src_ok, tgt_ok);
+                for (int32_t &k : b.slot_key) {
+                    const int32_t id = id_of_key[k & 0x7FFFFFFF];
+                    BCV_REQUIRE(id >= 0, BCV_ESTATE, "internal: boundary interaction offset without a table");
+                    k = id | (k & (int32_t)0x80000000);
+                }
+                ms.n_tasks = (int64_t)b.tasks.size();
+                ms.n_pairs = b.n_pairs;
+                ms.d_tasks = upload(p.get(), b.tasks);
+                ms.d_task_targets = upload(p.get(), b.targets);
+                ms.d_slot_off = upload(p.get(), b.slot_key);
+                ms.d_slot_src = upload(p.get(), b.slot_src.get(), (size_t)b.slot_key.size() * 64);
+                ms.n_m2l_splits = (int64_t)b.splits.size();
+                ms.d_m2l_splits = upload(p.get(), b.splits);
+                if (b.n_pieces > 0) ms.d_m2l_partial = alloc_zero<double>(p.get(), (size_t)b.n_pieces * 64 * p->K);
+                int32_t lg = 0;
+                for (int x = 0; x <= kXcds; ++x) ms.xcd_begin[x] = b.xcd_begin[x];
+                for (int x = 0; x < kXcds; ++x) lg = std::max(lg, b.xcd_begin[x + 1] - b.xcd_begin[x]);
+                ms.m2l_groups = (int64_t)kXcds * lg;
+            };
+            make_set(on_b.data(), nullptr, p->btv_m2l);
+            make_set(nullptr, on_b.data(), p->vtb_m2l);
+        }
         p->d_M = alloc_zero<double>(p.get(), (size_t)(p->n_cells + 1) * p->K);
         p->d_Lam = alloc_zero<double>(p.get(), (size_t)p->n_cells * p->K);
         const size_t n_folded = (size_t)(p->n_cells + 1) * (size_t)p->R;
@@ -1235,7 +1285,11 @@ void destroy_plan(bcv_plan_s *p)
                     p->d_m2l_splits, p->d_m2l_partial, p->d_faces, p->d_leaf_faces, p->d_btv_col,
                     p->d_btv_units, p->d_btv_splits, p->d_btv_partial, p->d_btv_touch, p->d_vtb_col,
                     p->d_vtb_units, p->d_vtb_splits, p->d_vtb_partial, p->d_hi_off, p->d_dof_leaf, p->d_bcb,
-                    p->d_bvb, p->d_bcol, p->d_bval, p->d_bwork, p->d_bsplits, p->d_bpartial, p->d_btab};
+                    p->d_bvb, p->d_bcol, p->d_bval, p->d_bwork, p->d_bsplits, p->d_bpartial, p->d_btab,
+                    p->btv_m2l.d_tasks, p->btv_m2l.d_task_targets, p->btv_m2l.d_slot_off, p->btv_m2l.d_slot_src,
+                    p->btv_m2l.d_m2l_splits, p->btv_m2l.d_m2l_partial, p->vtb_m2l.d_tasks,
+                    p->vtb_m2l.d_task_targets, p->vtb_m2l.d_slot_off, p->vtb_m2l.d_slot_src,
+                    p->vtb_m2l.d_m2l_splits, p->vtb_m2l.d_m2l_partial};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     p->magic = 0;
