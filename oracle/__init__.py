@@ -19,6 +19,10 @@ Contents (each function cites the passage of the paper it follows):
   basis.py     degree-p leaf bases (p_l = L - l, Legendre tensor polynomials): O1 and O2 with
                polynomial leaf spaces, entry blocks (exact where the cubes touch, via
                touching.box_pair_poly), projection of a density onto the leaf spaces.
+  mapped.py    mapped (curved) meshes, the BC octree pushed through a map (the cube-to-ball map;
+               plain-C loops in mapped.c): entries with a singular rule for touching curved cells,
+               O1 by direct summation and O2 step by step with Taylor translations between the
+               images of the cell centres.
   boundary.py  BtV (Algorithm 3): single- and double-layer entries of (leaf, boundary face) pairs
                (exact by convolution where they touch, point rule elsewhere), O1 by direct
                summation and O2 step by step.

@@ -1,0 +1,174 @@
+"""Pins of the mapped-mesh oracle (oracle/mapped.py, oracle/mapped.c) against facts fixed outside it.
+
+* the cube-to-ball map: boundary onto the sphere, centre fixed, Jacobian against finite
+  differences, the ball's volume;
+* the batched shift matrices against oracle.taylor's M2M matrix;
+* the singular rule: with the identity map it reproduces the exact touching integrals of cubes
+  (oracle.touching, pinned on its own), it is symmetric, and on curved cells it agrees with the
+  same rule at higher orders;
+* the whole mapped operator against the Newton potential of the uniform ball, R^2/2 - r^2/6
+  (a textbook closed form): with a high-order rule on the non-touching pairs the cell integrals
+  agree to 1e-7, with the 2x2x2 point rule to its discretisation error;
+* the mapped FMM: with the identity map its far field equals oracle.fmm's; on the ball it tends to
+  the direct sum as q grows; the sampled form equals the full one.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import direct, fmm, mapped, touching
+from oracle.mesh import BCMesh
+
+HIGH = dict(n_lam=8, n_mu=12, n_z=8, n_s=8, n_r=8)
+
+
+def _ball(x):
+    return mapped.map_points("ball", x)
+
+
+def test_map_takes_the_cube_onto_the_ball():
+    rng = np.random.default_rng(0)
+    x = rng.random((500, 3))
+    ax = rng.integers(0, 3, 500)
+    x[np.arange(500), ax] = rng.integers(0, 2, 500)  # points on the cube's faces
+    p, _ = _ball(x)
+    assert np.abs(np.linalg.norm(p - 0.5, axis=1) - 0.5).max() < 1e-15
+    c, jc = _ball(np.array([[0.5, 0.5, 0.5]]))
+    assert np.abs(c - 0.5).max() == 0.0 and abs(jc[0] - 1.0) < 1e-15
+    # interior points stay inside, radius increasing along a ray
+    t = np.linspace(0.01, 0.99, 50)
+    ray = 0.5 + np.outer(t, [0.5, 0.3, -0.2])
+    r = np.linalg.norm(_ball(ray)[0] - 0.5, axis=1)
+    assert np.all(np.diff(r) > 0) and r.max() < 0.5
+
+
+def test_jacobian_against_finite_differences():
+    rng = np.random.default_rng(1)
+    x = 0.05 + 0.9 * rng.random((40, 3))
+    _, J = _ball(x)
+    h = 1e-6
+    D = np.empty((40, 3, 3))
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = h
+        D[:, :, k] = (_ball(x + e)[0] - _ball(x - e)[0]) / (2 * h)
+    assert np.abs(np.abs(np.linalg.det(D)) / J - 1).max() < 1e-8
+    assert J.min() > 0
+
+
+def test_ball_volume():
+    t, w = np.polynomial.legendre.leggauss(30)
+    t, w = 0.5 * (t + 1), 0.5 * w
+    X = np.stack(np.meshgrid(t, t, t, indexing="ij"), -1).reshape(-1, 3)
+    W = np.einsum("i,j,k->ijk", w, w, w).ravel()
+    vol = np.sum(W * _ball(X)[1])
+    assert abs(vol / (np.pi / 6) - 1) < 1e-10
+    mm = mapped.MappedMesh(BCMesh(3), "ball")  # the leaves' 2x2x2 weights: discretisation level
+    assert abs(mm.weights.sum() / (np.pi / 6) - 1) < 1e-3
+
+
+def test_shift_matrices_equal_taylor_m2m():
+    from oracle.taylor import m2m_matrix
+
+    d = np.random.default_rng(2).normal(size=(4, 3))
+    M = mapped.shift_matrices(d, 6)
+    for k in range(4):
+        R = m2m_matrix(d[k], 6)
+        assert np.abs(M[k] - R).max() < 1e-14 * np.abs(R).max()
+
+
+def _pairs_by_class(L):
+    m = BCMesh(L)
+    lv = m.leaf_array()
+    lo_int, size, _, a = direct.leaf_geometry(lv, L)
+    n = len(lv)
+    ti = np.repeat(np.arange(n), n)
+    si = np.tile(np.arange(n), n)
+    cls = direct.touching_class_index(lo_int[ti], size[ti], lo_int[si], size[si])
+    return m, ti, si, cls, a
+
+
+def test_singular_rule_reproduces_cube_constants():
+    m, ti, si, cls, a = _pairs_by_class(3)
+    mm = mapped.MappedMesh(m, "identity")
+    consts = touching.constants(40)
+    for c in range(7):
+        sel = np.nonzero(cls == c)[0][:3]
+        assert len(sel) > 0
+        ex = consts[c] * np.minimum(a[ti[sel]], a[si[sel]]) ** 5 / (4 * np.pi)
+        assert np.abs(mapped.touch_entries(mm, ti[sel], si[sel]) / ex - 1).max() < 1e-6, c
+        assert np.abs(mapped.touch_entries(mm, ti[sel], si[sel], HIGH) / ex - 1).max() < 1e-9, c
+
+
+def test_singular_rule_on_the_ball_symmetric_and_converged():
+    m, ti, si, cls, _ = _pairs_by_class(3)
+    mm = mapped.MappedMesh(m, "ball")
+    rng = np.random.default_rng(3)
+    for c in range(7):
+        sel = rng.choice(np.nonzero(cls == c)[0], 3, replace=False)
+        v = mapped.touch_entries(mm, ti[sel], si[sel])
+        assert np.abs(v / mapped.touch_entries(mm, si[sel], ti[sel]) - 1).max() < 1e-13, c
+        assert np.abs(v / mapped.touch_entries(mm, ti[sel], si[sel], HIGH) - 1).max() < 1e-7, c
+
+
+def _cell_integrals_of_ball_potential(mm):
+    t, w = np.polynomial.legendre.leggauss(10)
+    t, w = 0.5 * (t + 1), 0.5 * w
+    X = np.stack(np.meshgrid(t, t, t, indexing="ij"), -1).reshape(-1, 3)
+    W = np.einsum("i,j,k->ijk", w, w, w).ravel()
+    out = np.empty(len(mm.leaves))
+    for k in range(len(out)):
+        p, J = _ball(mm.lo[k] + mm.a[k] * X)
+        out[k] = np.sum(W * J * mapped.ball_potential(p)) * mm.a[k] ** 3
+    return out
+
+
+def test_uniform_ball_closed_form():
+    """f = 1 on the ball mesh: u_w = int_w V with V = R^2/2 - r^2/6 the ball's Newton potential."""
+    mm = mapped.MappedMesh(BCMesh(2), "ball")
+    n = len(mm.leaves)
+    ti = np.repeat(np.arange(n), n)
+    si = np.tile(np.arange(n), n)
+    tch = mm.touching(ti, si)
+    A = np.empty(n * n)
+    A[tch] = mapped.touch_entries(mm, ti[tch], si[tch])
+    A[~tch] = mapped.regular_entries(mm, ti[~tch], si[~tch], 6)
+    ex = _cell_integrals_of_ball_potential(mm)
+    assert np.abs(A.reshape(n, n).sum(axis=1) / ex - 1).max() < 1e-7  # measured 2.4e-8
+    u = mapped.apply_direct(mm, np.ones(n))  # the 2x2x2 rule on non-touching pairs
+    assert np.abs(u / ex - 1).max() < 5e-4  # measured 3.0e-4
+    Am = mapped.matrix(mm)
+    assert np.abs(Am - Am.T).max() < 1e-14 * np.abs(Am).max()
+    assert np.abs(Am.sum(axis=1) - u).max() < 1e-14 * np.abs(u).max()
+
+
+def test_identity_map_far_field_equals_cube_fmm():
+    m = BCMesh(3)
+    f = np.random.default_rng(4).normal(size=len(m.leaves))
+    mm = mapped.MappedMesh(m, "identity")
+    F = mapped.MappedFMM(mm, 4)
+    G = fmm.FMM(m, 4)
+    far_m = F.evaluation(F.downward(F.interaction(F.upward(F.moments(f)))), np.zeros(len(f)))
+    far_c = G.evaluation(G.downward(G.interaction(G.upward(G.moments(f)))), np.zeros(len(f)))
+    assert np.abs(far_m - far_c).max() < 1e-13 * np.abs(far_c).max()
+
+
+@pytest.fixture(scope="module")
+def ball3():
+    m = BCMesh(3)
+    mm = mapped.MappedMesh(m, "ball")
+    f = np.random.default_rng(5).normal(size=len(m.leaves))
+    fmms = {q: mapped.MappedFMM(mm, q) for q in (4, 6)}
+    return mm, f, mapped.apply_direct(mm, f), fmms, {q: F.apply(f) for q, F in fmms.items()}
+
+
+def test_ball_fmm_tends_to_direct(ball3):
+    mm, f, ud, _, u = ball3
+    errs = [np.linalg.norm(u[q] - ud) / np.linalg.norm(ud) for q in (4, 6)]
+    assert errs[1] < errs[0] / 5 and errs[1] < 3e-6, errs  # measured 2.1e-5, 1.8e-6 (q = 8: 1.9e-7)
+
+
+def test_sampled_equals_full(ball3):
+    mm, f, _, fmms, u = ball3
+    tg = np.array([0, 17, 200, len(f) - 1])
+    assert np.abs(fmms[6].apply_sampled(f, tg) - u[6][tg]).max() < 1e-14 * np.abs(u[6]).max()
