@@ -55,7 +55,16 @@ typedef enum {
  * l < L a cell is marked (refined) by the marking rule; every level-L cell is a leaf. */
 enum {
     BCV_GEOM_BOX = 0, /* the axis-aligned cube [lo, hi] (all of lo and hi zero: the unit cube [0,1]^3) */
-    BCV_GEOM_BALL = 1 /* a cube-to-ball mapped mesh: not built (BCV_ENOTSUP) */
+    BCV_GEOM_BALL = 1 /* the ball inscribed in the cube [lo, hi]: the cube's BC octree pushed through the
+                         analytic cube-to-sphere map (volume form of the mapping reviewed by Zucker and
+                         Higashi, JCGT 7(2), 2018; with u = 2 xi - 1, y_i = u_i sqrt(1 - u_j^2/2 - u_k^2/2
+                         + u_j^2 u_k^2/3)). Cells are curved; the near and interaction lists are those
+                         of the reference octree, expansion centres the images of the reference centres,
+                         non-touching entries the mapped 2x2x2 rule (weights (a^3/8) det D Phi), touching
+                         entries a singular rule in the relative coordinate (Sec. 1.2 entries on curved
+                         cells). Plans need BCV_NEAR_ASSEMBLED, q = 4, 6 or 8, BCV_FP64 or BCV_MIXED_F32,
+                         and no boundary, basis, surrogate, level-dependent order or near_order options
+                         (BCV_ENOTSUP otherwise); a forest may mix cubes and balls */
 };
 enum {
     BCV_MARK_FACE = 0,     /* marked iff the cell has a face on the boundary (M_l = B_l) */
@@ -66,7 +75,7 @@ enum {
                               BCV_MARK_FACE) */
 };
 typedef struct {
-    int geometry;     /* BCV_GEOM_BOX */
+    int geometry;     /* BCV_GEOM_BOX or BCV_GEOM_BALL */
     double lo[3];     /* lower corner of the domain cube */
     double hi[3];     /* upper corner; hi - lo must be the same positive side s on all three axes */
     int L;            /* finest level, 2 <= L <= 9 (boundary leaves have side h = s 2^-L) */
@@ -195,7 +204,7 @@ typedef struct {
 
 /* Build the BC octree of Sec. 2 on the host. desc and out must be non-NULL.
  * Errors: BCV_EINVAL (L outside 2..9, marking not 0 or 1, a box that is not a cube of positive side),
- * BCV_ENOTSUP (geometry BCV_GEOM_BALL), BCV_ENOMEM. */
+ * BCV_ENOMEM. */
 bcv_status bcv_build_bc_tree(const bcv_mesh_desc *desc, bcv_tree *out);
 
 /* A forest of n_meshes BC meshes for a batched apply: one tree, one plan and one apply (and one
@@ -220,6 +229,8 @@ bcv_status bcv_tree_num_leaves(bcv_tree tree, int64_t *n);
  *              along x, bit 1 along y, bit 2 along z), the points of the point rule, the moments and
  *              the evaluation (Sec. 3 with this reading of the integrals);
  *   gauss_w:   n_leaves x 8 doubles, their weights |w|/8.
+ * On a BCV_GEOM_BALL mesh the points are the images of the reference cube's points under the map and
+ * the weights (s 2^-l)^3 / 8 times det D Phi there (s the side of the mesh's cube).
  * Errors: BCV_EINVAL (tree NULL), BCV_ESTATE. */
 bcv_status bcv_tree_leaves(bcv_tree tree, int32_t *level_ijk, double *gauss_xyz, double *gauss_w);
 

@@ -205,15 +205,17 @@ class Tree:
             self._h = None
 
 
-def build_bc_forest(Ls, marking=0, boxes=None):
+def build_bc_forest(Ls, marking=0, boxes=None, geometry=GEOM_BOX):
     """One tree holding len(Ls) meshes; mesh m occupies [4m, 4m+1) x [0,1)^2 (see bcv.h).
-    marking: one rule for every mesh, or a list with one per mesh. boxes: None (unit cubes) or one
-    (lo, hi) cube per mesh."""
+    marking, geometry: one value for every mesh, or a list with one per mesh. boxes: None (unit
+    cubes) or one (lo, hi) cube per mesh."""
     marks = list(marking) if isinstance(marking, (list, tuple)) else [marking] * len(Ls)
-    if len(marks) != len(Ls):
-        raise ValueError("one marking per mesh")
+    geoms = list(geometry) if isinstance(geometry, (list, tuple)) else [geometry] * len(Ls)
+    if len(marks) != len(Ls) or len(geoms) != len(Ls):
+        raise ValueError("one marking and one geometry per mesh")
     boxes = [(None, None)] * len(Ls) if boxes is None else list(boxes)
-    descs = (MeshDesc * len(Ls))(*[_mesh_desc(L, mk, lo, hi) for L, mk, (lo, hi) in zip(Ls, marks, boxes)])
+    descs = (MeshDesc * len(Ls))(*[_mesh_desc(L, mk, lo, hi, gm)
+                                   for L, mk, (lo, hi), gm in zip(Ls, marks, boxes, geoms)])
     h = ctypes.c_void_p()
     _check(lib().bcv_build_bc_forest(len(Ls), descs, ctypes.byref(h)))
     return Tree(h)

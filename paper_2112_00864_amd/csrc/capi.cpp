@@ -5,6 +5,7 @@
 #include <string>
 #include <vector>
 
+#include "ballmap.hpp"
 #include "internal.hpp"
 #include "multiindex.hpp"
 #include "kernels.hpp"
@@ -12,7 +13,8 @@
 
 namespace bcv {
 bcv_tree_s *build_tree(int L, int marking);
-bcv_tree_s *build_forest(int n, const int *Ls, const int *markings, const double *lo, const double *side);
+bcv_tree_s *build_forest(int n, const int *Ls, const int *markings, const double *lo, const double *side,
+                         const int *geoms);
 bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int device);
 void destroy_plan(bcv_plan_s *p);
 void touching_integrals(int device, double out[kTouchClasses]);
@@ -70,8 +72,8 @@ void check_mesh_desc(const bcv_mesh_desc &d, double lo[3], double *side)
 {
     BCV_REQUIRE(d.L >= 2 && d.L <= 9, BCV_EINVAL, "L must be in 2..9");
     BCV_REQUIRE(d.marking == 0 || d.marking == 1, BCV_EINVAL, "marking must be 0 or 1");
-    BCV_REQUIRE(d.geometry != BCV_GEOM_BALL, BCV_ENOTSUP, "cube-to-ball mapped meshes are not built");
-    BCV_REQUIRE(d.geometry == BCV_GEOM_BOX, BCV_EINVAL, "geometry must be BCV_GEOM_BOX");
+    BCV_REQUIRE(d.geometry == BCV_GEOM_BOX || d.geometry == BCV_GEOM_BALL, BCV_EINVAL,
+                "geometry must be BCV_GEOM_BOX or BCV_GEOM_BALL");
     bool unit = true;
     for (int ax = 0; ax < 3; ++ax) unit = unit && d.lo[ax] == 0.0 && d.hi[ax] == 0.0;
     if (unit) {
@@ -158,14 +160,15 @@ bcv_status bcv_build_bc_forest(int n_meshes, const bcv_mesh_desc *descs, bcv_tre
         BCV_REQUIRE(descs != nullptr && out != nullptr, BCV_EINVAL, "NULL argument");
         *out = nullptr;
         BCV_REQUIRE(n_meshes >= 1 && n_meshes <= 4096, BCV_EINVAL, "n_meshes must be in 1..4096");
-        std::vector<int> Ls(n_meshes), marks(n_meshes);
+        std::vector<int> Ls(n_meshes), marks(n_meshes), geoms(n_meshes);
         std::vector<double> lo(3 * (size_t)n_meshes), side(n_meshes);
         for (int m = 0; m < n_meshes; ++m) {
             check_mesh_desc(descs[m], &lo[3 * (size_t)m], &side[m]);
             Ls[m] = descs[m].L;
             marks[m] = descs[m].marking;
+            geoms[m] = descs[m].geometry;
         }
-        *out = bcv::build_forest(n_meshes, Ls.data(), marks.data(), lo.data(), side.data());
+        *out = bcv::build_forest(n_meshes, Ls.data(), marks.data(), lo.data(), side.data(), geoms.data());
     });
 }
 
@@ -188,8 +191,8 @@ bcv_status bcv_build_bc_tree(const bcv_mesh_desc *desc, bcv_tree *out)
         *out = nullptr;
         double lo[3], side = 1.0;
         check_mesh_desc(*desc, lo, &side);
-        const int L = desc->L, marking = desc->marking;
-        *out = bcv::build_forest(1, &L, &marking, lo, &side);
+        const int L = desc->L, marking = desc->marking, geom = desc->geometry;
+        *out = bcv::build_forest(1, &L, &marking, lo, &side, &geom);
     });
 }
 
@@ -219,12 +222,17 @@ bcv_status bcv_tree_leaves(bcv_tree tree, int32_t *level_ijk, double *gauss_xyz,
             const double s = tree->mesh_side[m], a = std::ldexp(s, -lev);
             const int64_t local[3] = {tree->ijk[3 * c] - ((int64_t)4 * m << lev), tree->ijk[3 * c + 1],
                                       tree->ijk[3 * c + 2]};
+            const double ar = std::ldexp(1.0, -lev);  // side in the mesh's reference cube
             for (int g = 0; g < 8; ++g) {
+                double x[3], p[3], jac = 1.0;
+                for (int ax = 0; ax < 3; ++ax) x[ax] = ar * ((double)local[ax] + node[(g >> ax) & 1]);
+                if (tree->mesh_geom[m] == BCV_GEOM_BALL)
+                    bcv::ball_map(x, p, &jac);
+                else
+                    p[0] = x[0], p[1] = x[1], p[2] = x[2];
                 if (gauss_xyz)
-                    for (int ax = 0; ax < 3; ++ax)
-                        gauss_xyz[(8 * l + g) * 3 + ax] =
-                            tree->mesh_lo[3 * m + ax] + a * ((double)local[ax] + node[(g >> ax) & 1]);
-                if (gauss_w) gauss_w[8 * l + g] = a * a * a * 0.125;
+                    for (int ax = 0; ax < 3; ++ax) gauss_xyz[(8 * l + g) * 3 + ax] = tree->mesh_lo[3 * m + ax] + s * p[ax];
+                if (gauss_w) gauss_w[8 * l + g] = a * a * a * 0.125 * jac;
             }
         }
     });

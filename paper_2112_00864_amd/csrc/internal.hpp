@@ -27,6 +27,9 @@ struct bcv_tree_s {
     // Physical domain of each mesh: the cube with lower corner mesh_lo[3m..3m+2] and side mesh_side[m]
     // (the unit cube unless the description says otherwise).
     std::vector<double> mesh_lo, mesh_side;
+    // Geometry of each mesh: BCV_GEOM_BOX (the cube itself) or BCV_GEOM_BALL (the cube's octree pushed
+    // through the cube-to-ball map onto the inscribed ball).
+    std::vector<int8_t> mesh_geom;
 
     int64_t n_cells() const { return (int64_t)level.size(); }
     int64_t n_leaves() const { return (int64_t)leaf_cell.size(); }
@@ -276,6 +279,20 @@ struct bcv_plan_s {
     bcv::BasisSplit *d_bsplits = nullptr; // rows cut into several units
     double *d_bpartial = nullptr;         // kBasisRows partial sums per unit of a cut row
     bcv::BasisTables *d_btab = nullptr;
+
+    // Mapped meshes (some mesh of the tree is BCV_GEOM_BALL): every cell's expansion centre is the
+    // image of its reference centre, every leaf has its own moment row, the interaction phase works
+    // pair by pair, and the near field is assembled (mapped.hip).
+    int mapped = 0;
+    double *d_leaf_pts = nullptr;   // 8 per leaf: mapped Gauss point x, y, z and weight
+    double *d_centre = nullptr;     // 4 per cell: expansion centre x, y, z and side a (reference frame)
+    double *d_kap = nullptr;        // per leaf: kappa^b = sum_g w_g ((x_g - x_w)/a)^b / b!, K entries
+    double *d_kapr = nullptr;       // per leaf: the folded rows of (-1)^|b| kappa^b, R entries
+    uint8_t *d_leaf_mapped = nullptr;  // per leaf: 1 if its mesh is a ball
+    int64_t n_ilist = 0;            // interaction-list pairs (cells of levels >= 2, CSR by target)
+    int64_t *d_ilist_off = nullptr;
+    int32_t *d_ilist_src = nullptr;
+    int64_t n_mapped_touch = 0;     // touching near entries of ball leaves (singular rule)
 
     // BtV (Algorithm 3), built when the plan options ask for it.
     int boundary = 0;

@@ -596,28 +596,6 @@ __global__ __launch_bounds__(kWave *tree_waves<Q>()) void l2l_kernel(int n_par, 
 // pair (532 at Q = 6, against C(Q + 6, 6) = 924 over all multi-indices), and a source row holds
 // (Q + 1)^2 folded moments instead of K.
 template <int Q>
-struct ExpandTable {  // Lambda^a = sum_t c[a][t] Lambda~^{src[a][t]} (reduced positions), a full
-    static constexpr int K = ncoef(Q), kTerms = Q / 2 + 1;
-    int n[K], src[K][kTerms];
-    double c[K][kTerms];
-    constexpr ExpandTable() : n{}, src{}, c{}
-    {
-        constexpr MultiIndex<Q> mi{};
-        for (int a = 0; a < K; ++a) {
-            const int ax = mi.e[a][0], ay = mi.e[a][1], az = mi.e[a][2], k = az / 2;
-            const double sign = (k & 1) ? -1.0 : 1.0;
-            double binom = 1.0;
-            for (int i = 0; i <= k; ++i) {
-                if (i > 0) binom = binom * (k - i + 1) / i;
-                src[a][i] = ReducedIndex<Q>::index(ax + 2 * i, az - 2 * k, mi.deg[a]);
-                c[a][i] = sign * binom;
-            }
-            n[a] = k + 1;
-        }
-    }
-};
-
-template <int Q>
 struct RTables {
     static constexpr ReducedIndex<Q> ri{};
     static constexpr ExpandTable<Q> ex{};
@@ -1104,12 +1082,13 @@ __global__ __launch_bounds__(256) void near_eval_kernel(XcdRanges xr, const Near
         const int64_t e0 = un.begin, e1 = un.end;
         if (kAssembled && !kMixed) {
             acc = assembled_dot(col, val, f, e0, e1, lane, acc);
-        } else if (kAssembled) {  // FP32 entries; the touching pairs exact, in FP64
+        } else if (kAssembled) {  // FP32 entries; the touching pairs exact, in FP64 (from the class
+                                  // value, or per pair where the plan keeps FP64 entries: mapped meshes)
             const int64_t es = min(max(split[t], e0), e1);
             const double a_t = gt.w;
             for (int64_t e = e0 + lane; e < es; e += kWave) {
                 const uint32_t code = col[e];
-                acc = fma(touch_entry(code, a_t, tv), f[code & 0x0FFFFFFFu], acc);
+                acc = fma(val != nullptr ? val[e] : touch_entry(code, a_t, tv), f[code & 0x0FFFFFFFu], acc);
             }
             acc = assembled_dot(col, val32, f, es, e1, lane, acc);
         } else {
@@ -1602,7 +1581,7 @@ void launch_near_q(const bcv_plan_s &p, const double *f, const double *lam, int 
     const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
     const bool mixed = p.precision != BCV_FP64;
     if (p.nearfield == BCV_NEAR_ASSEMBLED && mixed)
-        near_eval_kernel<Q, true, true><<<blocks, 256, 0, st>>>(xr, p.d_units, p.d_split, p.d_col, nullptr,
+        near_eval_kernel<Q, true, true><<<blocks, 256, 0, st>>>(xr, p.d_units, p.d_split, p.d_col, p.d_val,
                                                                 p.d_val32, geom, f, lam, p.d_leaf_cell,
                                                                 touch_values(p), parts, p.d_partial, u, lo);
     else if (p.nearfield == BCV_NEAR_ASSEMBLED)
@@ -2141,8 +2120,50 @@ void launch_btv(const bcv_plan_s &p, const double *qf, const double *gf, double 
     }
 }
 
+// VtV apply on a mapped mesh (mapped.hip), on the caller's stream: the near field from the assembled
+// entries (it writes u), then P2M, the upward pass, the interaction phase pair by pair, the downward
+// pass and the evaluation, which adds to u.
+template <int Q>
+void mapped_apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStream_t st)
+{
+    const bool far = (parts & BCV_PART_FAR) && !p.direct;
+    const bool near = (parts & BCV_PART_NEAR) != 0;
+    PhaseMarks marks(p);
+    marks.start(BCV_PHASE_NEAR, st);
+    if (near)
+        launch_near<Q>(p, f, nullptr, BCV_PART_NEAR, u, st);
+    else
+        launch_mapped_zero(p, u, st);
+    marks.stop(BCV_PHASE_NEAR, st);
+    if (far) {
+        const int phase_id[4] = {BCV_PHASE_P2M, BCV_PHASE_M2M, BCV_PHASE_M2L, BCV_PHASE_L2L};
+        for (int ph = 0; ph < 4; ++ph) {
+            marks.start(phase_id[ph], st);
+            launch_mapped_phase(p, f, ph, st);
+            marks.stop(phase_id[ph], st);
+        }
+        marks.start(BCV_PHASE_EVAL, st);
+        launch_mapped_eval(p, u, st);
+        marks.stop(BCV_PHASE_EVAL, st);
+    }
+    if (p.d_uscale != nullptr) {  // domains of side s != 1: u = s^5 u(unit side)
+        scale_kernel<<<(unsigned)((p.n_leaves + 255) / 256), 256, 0, st>>>(p.n_leaves, p.d_uscale, u);
+        check_launch();
+    }
+    marks.finish(st);
+}
+
 void launch_apply(const bcv_plan_s &p, const double *f, double *u, int parts, hipStream_t st)
 {
+    if (p.mapped) {
+        switch (p.q) {
+        case 4: mapped_apply_q<4>(p, f, u, parts, st); break;
+        case 6: mapped_apply_q<6>(p, f, u, parts, st); break;
+        case 8: mapped_apply_q<8>(p, f, u, parts, st); break;
+        default: fail(BCV_ENOTSUP, "expansion order not compiled");
+        }
+        return;
+    }
     if (p.basis) {
         if (p.q_schedule) {  // the passes pick their kernels level by level
             basis_apply_q<4>(p, f, u, parts, st);

@@ -9,6 +9,12 @@ namespace bcv {
 // Algorithm 1 on `stream`: moments, upward pass, interaction phase, downward pass, and the
 // near field fused with the evaluation phase. parts: BCV_PART_NEAR | BCV_PART_FAR.
 void launch_apply(const bcv_plan_s &p, const double *f, double *u, int parts, hipStream_t stream);
+// mapped meshes (mapped.hip): phase 0 P2M, 1 M2M, 2 interaction, 3 L2L; evaluation adds to u
+void launch_mapped_phase(const bcv_plan_s &p, const double *f, int phase, hipStream_t stream);
+void launch_mapped_eval(const bcv_plan_s &p, double *u, hipStream_t stream);
+void launch_mapped_zero(const bcv_plan_s &p, double *u, hipStream_t stream);
+void launch_mapped_assemble(const bcv_plan_s &p, const std::vector<int64_t> &touch_entry,
+                            const std::vector<int32_t> &touch_target, const int rule_orders[5]);
 // BtV apply (Algorithm 3): u = <1_w, V[q] - K[g]> from face data qf, gf (device, n_faces each).
 void launch_btv(const bcv_plan_s &p, const double *qf, const double *gf, double *u, hipStream_t stream);
 // VtB apply (Algorithm 2): uf = <1_f, N f> on every boundary face from leaf densities f.

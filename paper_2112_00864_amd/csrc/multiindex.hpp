@@ -121,4 +121,29 @@ struct FoldTable {  // Mr^b = sum_t c[b][t] M^{src[b][t]} (full positions)
     }
 };
 
+// Local coefficients of the harmonic reduction expanded to every multi-index (see the M2L section of
+// kernels.hip): Lambda^a for a_z >= 2 from the reduced ones (a_z <= 1), with k = floor(a_z / 2),
+//     Lambda^a = (-1)^k sum_{i + j = k} C(k, i) Lambda^{a - 2k e_z + 2i e_x + 2j e_y}.
+template <int Q>
+struct ExpandTable {  // Lambda^a = sum_t c[a][t] Lambda~^{src[a][t]} (reduced positions), a full
+    static constexpr int K = ncoef(Q), kTerms = Q / 2 + 1;
+    int n[K], src[K][kTerms];
+    double c[K][kTerms];
+    constexpr ExpandTable() : n{}, src{}, c{}
+    {
+        constexpr MultiIndex<Q> mi{};
+        for (int a = 0; a < K; ++a) {
+            const int ax = mi.e[a][0], az = mi.e[a][2], k = az / 2;
+            const double sign = (k & 1) ? -1.0 : 1.0;
+            double binom = 1.0;
+            for (int i = 0; i <= k; ++i) {
+                if (i > 0) binom = binom * (k - i + 1) / i;
+                src[a][i] = ReducedIndex<Q>::index(ax + 2 * i, az - 2 * k, mi.deg[a]);
+                c[a][i] = sign * binom;
+            }
+            n[a] = k + 1;
+        }
+    }
+};
+
 }  // namespace bcv

@@ -23,6 +23,7 @@
 #include <new>
 #include <vector>
 
+#include "ballmap.hpp"
 #include "internal.hpp"
 #include "kernels.hpp"
 #include "multiindex.hpp"
@@ -300,6 +301,10 @@ struct M2LPlan {
 // than 256 at h = 1/128 and 1/256; shorter pieces add partial sums and gathering first slots). With
 // level-dependent orders each level is its own launch, and 256 measured faster (4% in FP64); so
 // did small meshes, whose few tasks need the shorter pieces to fill the GPU.
+// Orders of the singular rule for touching mapped cells (lambda, mu, z, s, r; see mapped.hip): about
+// 1e-8 relative on ball cells against the same rule at orders (8, 12, 8, 8, 8).
+constexpr int kMappedRule[5] = {5, 8, 6, 4, 4};
+
 constexpr int kDefaultMaxSlots = 320;
 constexpr int kDefaultMaxSlotsSchedule = 256;
 
@@ -940,6 +945,137 @@ void build_basis_near(bcv_plan_s &p, const bcv_tree_s &t, const NearCSR &near, s
 
 void destroy_plan(bcv_plan_s *p);
 
+// Mapped meshes: the per-leaf and per-cell geometry of the apply (see mapped.hip) and the touching
+// near entries of ball leaves for the singular rule. Reference frame of the forest: mesh m occupies
+// [4m, 4m + 1) x [0,1)^2, and a ball mesh's cells are the images of its reference cubes under the
+// cube-to-ball map of its unit cube, shifted back by 4m along x.
+template <int Q>
+void mapped_rows(const std::vector<double> &pts, const std::vector<double> &cen, const bcv_tree_s &t,
+                 std::vector<double> &kap, std::vector<double> &kapr)
+{
+    constexpr int K = ncoef(Q), R = nreduced(Q);
+    constexpr MultiIndex<Q> mi{};
+    constexpr FoldTable<Q> fold{};
+    const int64_t nl = t.n_leaves();
+    kap.assign((size_t)nl * K, 0.0);
+    kapr.assign((size_t)nl * R, 0.0);
+#pragma omp parallel for schedule(static)
+    for (int64_t l = 0; l < nl; ++l) {
+        const int32_t c = t.leaf_cell[l];
+        const double a = std::ldexp(1.0, -t.level[c]);
+        double row[K] = {};
+        for (int g = 0; g < 8; ++g) {
+            const double *x = &pts[(8 * l + g) * 4];
+            double pw[3][Q + 1];
+            for (int ax = 0; ax < 3; ++ax) {
+                const double d = (x[ax] - cen[4 * c + ax]) / a;
+                pw[ax][0] = 1.0;
+                for (int k = 1; k <= Q; ++k) pw[ax][k] = pw[ax][k - 1] * d / k;
+            }
+            for (int b = 0; b < K; ++b) row[b] += x[3] * pw[0][mi.e[b][0]] * pw[1][mi.e[b][1]] * pw[2][mi.e[b][2]];
+        }
+        for (int b = 0; b < K; ++b) kap[(size_t)l * K + b] = row[b];
+        for (int r = 0; r < R; ++r) {
+            double v = 0.0;
+            for (int k = 0; k < fold.n[r]; ++k) {
+                const int src = fold.src[r][k];
+                v += fold.c[r][k] * ((mi.deg[src] & 1) ? -row[src] : row[src]);
+            }
+            kapr[(size_t)l * R + r] = v;
+        }
+    }
+}
+
+void setup_mapped(bcv_plan_s *p, const bcv_tree_s &t, const std::vector<Grid> &g, const NearCSR &near, bool direct,
+                  std::vector<int64_t> &touch_entry, std::vector<int32_t> &touch_target)
+{
+    const int64_t nl = t.n_leaves(), nc = t.n_cells();
+    const double node[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
+    auto mesh_of = [&](int32_t c) { return (t.ijk[3 * c] >> t.level[c]) / 4; };
+    // the image of a reference point (forest frame) and the Jacobian determinant there
+    auto place = [&](int m, const double x[3], double out[3]) {
+        double jac = 1.0;
+        const double sh = 4.0 * m;
+        if (t.mesh_geom[m] == BCV_GEOM_BALL) {
+            const double xl[3] = {x[0] - sh, x[1], x[2]};
+            ball_map(xl, out, &jac);
+            out[0] += sh;
+        } else {
+            out[0] = x[0], out[1] = x[1], out[2] = x[2];
+        }
+        return jac;
+    };
+    std::vector<double> pts((size_t)nl * 32), cen((size_t)nc * 4);
+    std::vector<uint8_t> lm(nl);
+#pragma omp parallel for schedule(static)
+    for (int64_t l = 0; l < nl; ++l) {
+        const int32_t c = t.leaf_cell[l];
+        const double a = std::ldexp(1.0, -t.level[c]);
+        const int m = mesh_of(c);
+        lm[l] = t.mesh_geom[m] == BCV_GEOM_BALL;
+        for (int gi = 0; gi < 8; ++gi) {
+            const double x[3] = {a * (t.ijk[3 * c] + node[gi & 1]), a * (t.ijk[3 * c + 1] + node[(gi >> 1) & 1]),
+                                 a * (t.ijk[3 * c + 2] + node[(gi >> 2) & 1])};
+            double *o = &pts[(size_t)(8 * l + gi) * 4];
+            const double jac = place(m, x, o);
+            o[3] = a * a * a * 0.125 * jac;
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; ++c) {
+        const double a = std::ldexp(1.0, -t.level[c]);
+        const double x[3] = {a * (t.ijk[3 * c] + 0.5), a * (t.ijk[3 * c + 1] + 0.5), a * (t.ijk[3 * c + 2] + 0.5)};
+        place(mesh_of((int32_t)c), x, &cen[4 * c]);
+        cen[4 * c + 3] = a;
+    }
+    std::vector<double> kap, kapr;
+    switch (p->q) {
+    case 4: mapped_rows<4>(pts, cen, t, kap, kapr); break;
+    case 6: mapped_rows<6>(pts, cen, t, kap, kapr); break;
+    case 8: mapped_rows<8>(pts, cen, t, kap, kapr); break;
+    default: fail(BCV_ENOTSUP, "mapped meshes: q must be 4, 6 or 8");
+    }
+    p->d_leaf_pts = upload(p, pts);
+    p->d_centre = upload(p, cen);
+    p->d_kap = upload(p, kap);
+    p->d_kapr = upload(p, kapr);
+    p->d_leaf_mapped = upload(p, lm);
+    // touching entries of ball leaves (they come first in each row)
+    for (int64_t l = 0; l < nl; ++l)
+        if (lm[l])
+            for (int64_t e = near.row[l]; e < near.split[l]; ++e) {
+                touch_entry.push_back(e);
+                touch_target.push_back((int32_t)l);
+            }
+    p->n_mapped_touch = (int64_t)touch_entry.size();
+    if (direct) return;
+    // interaction lists, CSR over the cells of levels >= 2 (cell order)
+    const int32_t c0 = t.L >= 2 ? t.lvl_start[2] : (int32_t)nc;
+    std::vector<int64_t> off((size_t)(nc - c0) + 1, 0);
+    std::vector<std::vector<int32_t>> lists((size_t)(nc - c0));
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t c = c0; c < nc; ++c) {
+        const int lev = t.level[c];
+        const int i = t.ijk[3 * c], j = t.ijk[3 * c + 1], k = t.ijk[3 * c + 2];
+        auto &out = lists[(size_t)(c - c0)];
+        for (const auto &o : stencil()) {
+            const int32_t pn = g[lev - 1].at((i >> 1) + o[0], (j >> 1) + o[1], (k >> 1) + o[2]);
+            if (pn < 0 || !t.refined[pn]) continue;
+            for (int d = 0; d < 8; ++d) {
+                const int32_t s = t.first_child[pn] + d;
+                if (!is_neighbour_offset(i - t.ijk[3 * s], j - t.ijk[3 * s + 1], k - t.ijk[3 * s + 2])) out.push_back(s);
+            }
+        }
+    }
+    for (size_t q = 0; q < lists.size(); ++q) off[q + 1] = off[q] + (int64_t)lists[q].size();
+    std::vector<int32_t> src((size_t)off.back());
+    for (size_t q = 0; q < lists.size(); ++q) std::copy(lists[q].begin(), lists[q].end(), src.begin() + off[q]);
+    p->n_ilist = off.back();
+    p->n_m2l = p->n_ilist;
+    p->d_ilist_off = upload(p, off);
+    p->d_ilist_src = upload(p, src);
+}
+
 bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int device)
 {
     BCV_HIP(hipSetDevice(device));
@@ -956,6 +1092,17 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         BCV_REQUIRE(opts.q == 6 && !opts.q_schedule, BCV_ENOTSUP,
                     "BCV_MIXED_SPLIT16 supports the fixed order q = 6 only");
     for (int lev = 0; lev <= t.L + 1 && lev <= kMaxLevel + 1; ++lev) p->lvl_start[lev] = t.lvl_start[lev];
+    for (int m = 0; m < t.n_meshes; ++m) p->mapped = p->mapped || t.mesh_geom[m] == BCV_GEOM_BALL;
+    if (p->mapped) {
+        BCV_REQUIRE(opts.nearfield == BCV_NEAR_ASSEMBLED, BCV_ENOTSUP,
+                    "mapped (ball) meshes need the assembled near field (BCV_NEAR_ASSEMBLED)");
+        BCV_REQUIRE(opts.q == 4 || opts.q == 6 || opts.q == 8, BCV_ENOTSUP, "mapped (ball) meshes: q = 4, 6 or 8");
+        BCV_REQUIRE(!opts.q_schedule && opts.near_order == 0 && opts.basis_degree == 0 && !opts.boundary &&
+                        !opts.surrogate && opts.precision != BCV_MIXED_SPLIT16,
+                    BCV_ENOTSUP,
+                    "mapped (ball) meshes: fixed order, the 2x2x2 near rule, BCV_FP64 or BCV_MIXED_F32, no "
+                    "basis, boundary or surrogate");
+    }
     if (opts.basis_degree != 0) {
         BCV_REQUIRE(opts.basis_degree == 1, BCV_EINVAL, "basis_degree must be 0 or 1");
         BCV_REQUIRE(opts.precision == BCV_FP64, BCV_ENOTSUP, "degree-p leaf bases: BCV_FP64 only");
@@ -1048,6 +1195,8 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
     }
 
     NearCSR vol_near;  // kept for the VtB rows
+    std::vector<int64_t> mapped_touch_entry;  // mapped meshes: touching entries of ball leaves
+    std::vector<int32_t> mapped_touch_target;
     std::vector<int32_t> basis_pair_t, basis_pair_pos;  // degree-p leaf bases: per near entry
     // Level-dependent near-field rule: per-leaf Gauss orders and the entries that need them.
     std::vector<int8_t> near_order;
@@ -1085,6 +1234,7 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         p->d_units = upload(p.get(), nu.units);
         p->d_splits = upload(p.get(), nu.splits);
         if (nu.n_partial > 0) p->d_partial = alloc_zero<double>(p.get(), (size_t)nu.n_partial);
+        if (p->mapped) setup_mapped(p.get(), t, grids, near, opts.direct != 0, mapped_touch_entry, mapped_touch_target);
         if (opts.boundary) vol_near = std::move(near);
     }
 
@@ -1113,6 +1263,7 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         if (per_level)
             for (int lev = 0; lev <= t.L; ++lev)
                 level_slots[lev] = std::max<int32_t>(8, slots >> std::min(16, p->q_level[lev] - opts.q));
+        if (!p->mapped) {  // the lattice interaction plan (mapped meshes: CSR lists, setup_mapped)
         M2LPlan m2l = build_m2l(t, grids, level_slots, per_level,
                                 opts.m2l_max_slots == 0 && !per_level ? kDefaultMaxSlotsSchedule : 0);
         std::vector<int32_t> id_of_key(15 * 15 * 15, -1);
@@ -1204,6 +1355,7 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
             make_set(on_b.data(), nullptr, p->btv_m2l);
             make_set(nullptr, on_b.data(), p->vtb_m2l);
         }
+        }
         p->d_M = alloc_zero<double>(p.get(), (size_t)(p->n_cells + 1) * p->K);
         p->d_Lam = alloc_zero<double>(p.get(), (size_t)p->n_cells * p->K);
         const size_t n_folded = (size_t)(p->n_cells + 1) * (size_t)p->R;
@@ -1255,13 +1407,16 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         launch_near_assemble(*p, nullptr);
         BCV_HIP(hipDeviceSynchronize());
         if (opts.near_order == 1) launch_near_assemble_ordered(*p, ordered_entry, ordered_target, near_order);
+        if (p->mapped) launch_mapped_assemble(*p, mapped_touch_entry, mapped_touch_target, kMappedRule);
         if (p->precision != BCV_FP64) {  // the apply reads FP32 entries (touching pairs stay exact)
             p->d_val32 = alloc_zero<float>(p.get(), (size_t)p->n_near);
             launch_near_narrow(*p, nullptr);
             BCV_HIP(hipDeviceSynchronize());
-            BCV_HIP(hipFree(p->d_val));
-            p->d_val = nullptr;
-            p->device_bytes -= (int64_t)(sizeof(double) * p->n_near);
+            if (!p->mapped) {  // mapped meshes keep the FP64 entries: their touching values are per pair
+                BCV_HIP(hipFree(p->d_val));
+                p->d_val = nullptr;
+                p->device_bytes -= (int64_t)(sizeof(double) * p->n_near);
+            }
         }
     }
     p->n_near_ordered = (int64_t)ordered_entry.size();
@@ -1289,7 +1444,8 @@ void destroy_plan(bcv_plan_s *p)
                     p->btv_m2l.d_tasks, p->btv_m2l.d_task_targets, p->btv_m2l.d_slot_off, p->btv_m2l.d_slot_src,
                     p->btv_m2l.d_m2l_splits, p->btv_m2l.d_m2l_partial, p->vtb_m2l.d_tasks,
                     p->vtb_m2l.d_task_targets, p->vtb_m2l.d_slot_off, p->vtb_m2l.d_slot_src,
-                    p->vtb_m2l.d_m2l_splits, p->vtb_m2l.d_m2l_partial};
+                    p->vtb_m2l.d_m2l_splits, p->vtb_m2l.d_m2l_partial, p->d_leaf_pts, p->d_centre, p->d_kap,
+                    p->d_kapr, p->d_leaf_mapped, p->d_ilist_off, p->d_ilist_src};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     p->magic = 0;

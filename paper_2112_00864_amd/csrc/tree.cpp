@@ -40,7 +40,8 @@ static bool near_boundary(int lev, int32_t i, int32_t j, int32_t k)
 // (their integer offsets are at least 4 * 2^l - 2^l > sqrt(12) apart at level l) and the planner
 // treats the forest as one mesh. With n = 1 this is the single mesh of the unit cube.
 // lo (3 per mesh) and side (1 per mesh) place each mesh's cube in physical space; NULL: unit cubes.
-bcv_tree_s *build_forest(int n, const int *Ls, const int *markings, const double *lo, const double *side)
+bcv_tree_s *build_forest(int n, const int *Ls, const int *markings, const double *lo, const double *side,
+                         const int *geoms)
 {
     auto *t = new bcv_tree_s;
     t->L = 0;
@@ -51,6 +52,9 @@ bcv_tree_s *build_forest(int n, const int *Ls, const int *markings, const double
     t->mesh_side.assign(n, 1.0);
     if (lo) std::copy(lo, lo + 3 * n, t->mesh_lo.begin());
     if (side) std::copy(side, side + n, t->mesh_side.begin());
+    t->mesh_geom.assign(n, 0);
+    if (geoms)
+        for (int m = 0; m < n; ++m) t->mesh_geom[m] = (int8_t)geoms[m];
     auto push = [&](int32_t i, int32_t j, int32_t k, int lev, int32_t par) {
         t->ijk.push_back(i);
         t->ijk.push_back(j);
@@ -97,7 +101,7 @@ bcv_tree_s *build_forest(int n, const int *Ls, const int *markings, const double
     return t;
 }
 
-bcv_tree_s *build_tree(int L, int marking) { return build_forest(1, &L, &marking, nullptr, nullptr); }
+bcv_tree_s *build_tree(int L, int marking) { return build_forest(1, &L, &marking, nullptr, nullptr, nullptr); }
 
 // Boundary faces of the unit cube: the faces of level-L leaves in the planes x, y, z = 0 or 1
 // (a cell meeting the boundary has a face on it and is refined down to level L).

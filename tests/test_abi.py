@@ -129,8 +129,8 @@ def test_mesh_geometry_arguments():
             bcv.build_bc_tree(3, lo=lo, hi=hi)
         assert e.value.status == bcv.bcv.EINVAL
     with pytest.raises(bcv.BCVError) as e:
-        bcv.build_bc_tree(3, geometry=bcv.GEOM_BALL)
-    assert e.value.status == bcv.bcv.ENOTSUP
+        bcv.build_bc_tree(3, geometry=7)
+    assert e.value.status == bcv.bcv.EINVAL
 
 
 @pytest.mark.parametrize("lo,side", [((0.0, 0.0, 0.0), 1.0), ((1.0, -2.0, 0.5), 2.0)])
@@ -148,6 +148,22 @@ def test_gauss_points_match_oracle(lo, side):
     pts, wo = direct.gauss_points(lv[:, 1:4] * a[:, None], a)
     assert np.allclose(xyz, np.asarray(lo) + side * pts, rtol=0, atol=1e-15 * side)
     assert np.allclose(w, side ** 3 * np.broadcast_to(wo[:, None], w.shape), rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("lo,side", [((0.0, 0.0, 0.0), 1.0), ((1.0, -2.0, 0.5), 2.0)])
+def test_ball_gauss_points_match_oracle(lo, side):
+    """Ball meshes: the library's mapped Gauss points and weights (cube-to-ball map of its own)
+    against the mapped-mesh oracle's, placed in the ball inscribed in lo + side [0,1]^3."""
+    from oracle import mapped
+
+    L = 4
+    hi = tuple(x + side for x in lo)
+    t = bcv.build_bc_tree(L, lo=lo, hi=hi, geometry=bcv.GEOM_BALL)
+    xyz, w = t.gauss_points()
+    mm = mapped.MappedMesh(BCMesh(L), "ball")
+    assert np.abs(xyz - (np.asarray(lo) + side * mm.points)).max() <= 4e-16 * side * (1 + np.abs(lo).max())
+    assert np.abs(w / (side ** 3 * mm.weights) - 1).max() <= 1e-13
+    assert abs(w.sum() / (np.pi / 6 * side ** 3) - 1) < 1e-3  # the ball's volume, to the rule's error
 
 
 def test_order_range():
