@@ -437,10 +437,11 @@ def measure_basis(bcv, torch, args, dev):
 
 
 def batched(args):
-    """64 unit-cube BC meshes, h drawn from {1/16, 1/32, 1/64} (default_rng(1234)), Gaussian-mixture
-    density of seed m on mesh m, mixed precision (FP32 interaction phase): one forest plan with the
-    autotuned work decomposition, its apply captured in one HIP graph. Reported against the same
-    meshes applied one plan at a time."""
+    """64 BC meshes, h drawn from {1/16, 1/32, 1/64} (default_rng(1234)), mesh m mapped to the ball
+    iff m is odd (the others unit cubes; --cubes-only: all cubes), Gaussian-mixture density of seed
+    m on mesh m, mixed precision (FP32 interaction phase): one forest plan with the autotuned work
+    decomposition, its apply captured in one HIP graph. Reported against the same meshes applied one
+    plan at a time, with the per-phase times of the forest's eager apply."""
     import torch
 
     import paper_2112_00864_amd as bcv
@@ -448,8 +449,12 @@ def batched(args):
 
     n_mesh = 64
     Ls = [int(L) for L in np.random.default_rng(1234).choice([4, 5, 6], n_mesh)]
+    geoms = [bcv.GEOM_BOX if (args.cubes_only or m % 2 == 0) else bcv.GEOM_BALL for m in range(n_mesh)]
+    if geoms.count(bcv.GEOM_BALL) and args.nearfield != "assembled":
+        raise SystemExit("ball meshes need the assembled near field")
     t0 = time.perf_counter()
-    forest = bcv.build_bc_forest(Ls)
+    print("batched: %d meshes (%d balls), building the forest" % (n_mesh, geoms.count(bcv.GEOM_BALL)), flush=True)
+    forest = bcv.build_bc_forest(Ls, geometry=geoms)
     lv = forest.leaves().astype(np.int64)
     mesh = forest.leaf_mesh()
     f = np.empty(len(lv))
@@ -459,9 +464,15 @@ def batched(args):
         loc[:, 1] -= (4 * m) << loc[:, 0]
         f[sel] = synth.leaf_density(loc, seed=m)
     nf = bcv.NEAR_ASSEMBLED if args.nearfield == "assembled" else bcv.NEAR_QUADRATURE
+    t1 = time.perf_counter()
+    first = bcv.plan_interactions(forest, q=args.q, precision=bcv.MIXED_F32, nearfield=nf)
+    first_plan_s = time.perf_counter() - t1
+    del first
+    print("batched: %d leaves, first plan %.1f s; autotuning" % (len(lv), first_plan_s), flush=True)
     tune, tune_ms = bcv.autotune(forest, n_applies=5, q=args.q, precision=bcv.MIXED_F32, nearfield=nf)
     plan = bcv.plan_interactions(forest, q=args.q, precision=bcv.MIXED_F32, nearfield=nf, **tune)
     setup_s = time.perf_counter() - t0
+    print("batched: tuned %s in %.1f s total setup" % (tune, setup_s), flush=True)
     n = plan.n_leaves
     fd = torch.tensor(f, device="cuda:0")
     ud = torch.empty_like(fd)
@@ -475,9 +486,15 @@ def batched(args):
     torch.cuda.synchronize()
     ms_graph = 1e3 * (time.perf_counter() - t0) / args.steps
     u_graph = ud.cpu().numpy()
+    _, phase_ms = timed_applies(bcv, torch, plan, fd, ud, 1, args.steps, torch.device("cuda:0"))
+    print("batched: graph %.3f ms per apply; planning the meshes one by one" % ms_graph, flush=True)
+    if args.no_separate:
+        print(json.dumps({"batched_ms_per_step": ms_graph, "phase_ms": phase_ms}), flush=True)
+        return
     # the same meshes, one plan and one apply each
-    plans = [bcv.plan_interactions(bcv.build_bc_tree(L), q=args.q, precision=bcv.MIXED_F32, nearfield=nf)
-             for L in Ls]
+    plans = [bcv.plan_interactions(bcv.build_bc_tree(L, geometry=g), q=args.q, precision=bcv.MIXED_F32,
+                                   nearfield=nf)
+             for L, g in zip(Ls, geoms)]
     fs = [torch.tensor(f[mesh == m], device="cuda:0") for m in range(n_mesh)]
     us = [torch.empty_like(x) for x in fs]
     for p_, f_, u_ in zip(plans, fs, us):
@@ -507,12 +524,18 @@ def batched(args):
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "batched VtV: 64 unit-cube BC meshes, h in {1/16,1/32,1/64} drawn by "
-                               "default_rng(1234), Gaussian-mixture density seed m on mesh m, q=%d, mixed FP32 "
-                               "interaction phase, near field %s, one forest plan, apply captured in one HIP graph"
-                               % (args.q, args.nearfield),
+        "config": {"workload": "batched VtV: 64 BC meshes, h in {1/16,1/32,1/64} drawn by default_rng(1234), %s, "
+                               "Gaussian-mixture density seed m on mesh m, q=%d, mixed FP32 interaction phase, "
+                               "near field %s, one forest plan, apply captured in one HIP graph"
+                               % ("all unit cubes" if args.cubes_only else
+                                  "odd meshes cube-to-ball mapped, even meshes unit cubes", args.q, args.nearfield),
                    "n_leaves": n, "meshes_by_h": {"1/%d" % (2 ** L): Ls.count(L) for L in (4, 5, 6)},
-                   "autotuned": tune, "autotune_ms": tune_ms, "setup_seconds": setup_s},
+                   "ball_meshes": geoms.count(bcv.GEOM_BALL),
+                   "ball_leaves": int(sum(int(np.sum(mesh == m)) for m in range(n_mesh) if geoms[m] == bcv.GEOM_BALL)),
+                   "autotuned": tune, "autotune_ms": tune_ms, "setup_seconds": setup_s,
+                   "first_plan_seconds": first_plan_s},
+        "phase_ms": phase_ms,
+        "n_interaction_pairs": plan.info["n_m2l"],
         "separate_plans_ms_per_step": ms_seq,
         "speedup_vs_separate_plans": ms_seq / ms_graph,
         "max_rel_l2_vs_separate_plans": worst,
@@ -553,6 +576,10 @@ def main():
                     help="skip the neighbour-marking / level-dependent near-field measurement")
     ap.add_argument("--batched", action="store_true",
                     help="the batched workload: 64 meshes in one forest plan and one graph launch")
+    ap.add_argument("--no-separate", action="store_true",
+                    help="batched workload: skip the comparison with one plan per mesh (profiling runs)")
+    ap.add_argument("--cubes-only", action="store_true",
+                    help="batched workload with every mesh a unit cube (default: odd meshes are balls)")
     ap.add_argument("--near-only", action="store_true",
                     help="only run `steps` near-field applies (PART_NEAR) of the mixed plan on the --L mesh, for "
                          "counter collection, and exit")

@@ -34,7 +34,7 @@ from .taylor import m2l_matrix, monomials, multi_indices, n_coeffs, mi_binom
 MAPS = {"identity": 0, "ball": 1}
 # singular-rule orders: lambda (radial Duffy), mu (the two Duffy directions), z (boxes away from the
 # singularity), s (the inner box), r (regular sub-pairs of a ratio-2 pair)
-RULE = dict(n_lam=5, n_mu=8, n_z=6, n_s=4, n_r=4)
+RULE = dict(n_lam=5, n_mu=7, n_z=5, n_s=3, n_r=4)
 
 _XI = np.array([0.5 - 0.5 / np.sqrt(3.0), 0.5 + 0.5 / np.sqrt(3.0)])
 _REF = np.array([[_XI[i], _XI[j], _XI[k]] for k in (0, 1) for j in (0, 1) for i in (0, 1)])  # (8, 3)

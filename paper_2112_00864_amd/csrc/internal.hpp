@@ -30,6 +30,10 @@ struct bcv_tree_s {
     // Geometry of each mesh: BCV_GEOM_BOX (the cube itself) or BCV_GEOM_BALL (the cube's octree pushed
     // through the cube-to-ball map onto the inscribed ball).
     std::vector<int8_t> mesh_geom;
+    // Touching near entries of ball leaves by the singular rule, per value of the plan's direct flag,
+    // in the order of the planner's list: computed by the first plan of the tree, reused by later
+    // ones (the near lists depend on the tree and the direct flag only).
+    mutable std::vector<double> mapped_touch_cache[2];
 
     int64_t n_cells() const { return (int64_t)level.size(); }
     int64_t n_leaves() const { return (int64_t)leaf_cell.size(); }

@@ -14,7 +14,9 @@ void launch_mapped_phase(const bcv_plan_s &p, const double *f, int phase, hipStr
 void launch_mapped_eval(const bcv_plan_s &p, double *u, hipStream_t stream);
 void launch_mapped_zero(const bcv_plan_s &p, double *u, hipStream_t stream);
 void launch_mapped_assemble(const bcv_plan_s &p, const std::vector<int64_t> &touch_entry,
-                            const std::vector<int32_t> &touch_target, const int rule_orders[5]);
+                            const std::vector<int64_t> &work_entry, const std::vector<int32_t> &work_target,
+                            const std::vector<int64_t> &work_mirror, const int rule_orders[5],
+                            std::vector<double> &cache);
 // BtV apply (Algorithm 3): u = <1_w, V[q] - K[g]> from face data qf, gf (device, n_faces each).
 void launch_btv(const bcv_plan_s &p, const double *qf, const double *gf, double *u, hipStream_t stream);
 // VtB apply (Algorithm 2): uf = <1_f, N f> on every boundary face from leaf densities f.

@@ -234,6 +234,7 @@ __device__ double regular_part(const double *lo_t, const double *lo_s, double a,
 // (mesh m in [4m, 4m + 1) x [0,1)^2); the map acts on the mesh's own reference cube.
 __global__ __launch_bounds__(256) void ball_touch_kernel(int64_t n, const int64_t *__restrict__ entry,
                                                          const int32_t *__restrict__ target,
+                                                         const int64_t *__restrict__ mirror,
                                                          const uint32_t *__restrict__ col,
                                                          const double4 *__restrict__ geom, SingRule R,
                                                          double *__restrict__ val)
@@ -271,6 +272,7 @@ __global__ __launch_bounds__(256) void ball_touch_kernel(int64_t n, const int64_
         if (threadIdx.x == 0) {
             const double a3 = a * a * a;
             val[e] = red[0] * a3 * a3 * kInv4PiM;
+            if (mirror[k] >= 0) val[mirror[k]] = val[e];  // (s, t): the rule is symmetric
         }
         __syncthreads();
     }
@@ -315,6 +317,18 @@ __global__ __launch_bounds__(256) void mapped_eval_kernel(int64_t n_leaves, int 
     if (lane == 0) u[l] += s;
 }
 
+// val[entry[k]] <-> vals[k] (to_val: scatter the cached values; else gather them).
+__global__ void touch_copy_kernel(int64_t n, const int64_t *__restrict__ entry, double *__restrict__ vals,
+                                  double *__restrict__ val, int to_val)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        if (to_val)
+            val[entry[k]] = vals[k];
+        else
+            vals[k] = val[entry[k]];
+    }
+}
+
 __global__ void zero_kernel(int64_t n, double *__restrict__ u)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -323,10 +337,73 @@ __global__ void zero_kernel(int64_t n, double *__restrict__ u)
 
 // ---- M2M and L2L with each child's own shift --------------------------------------------------------
 // tau_c = (x_c - x_P) / a_P (arbitrary now). With the scaled coefficients
-//   M2M  M_P^b  = sum_c sum_{g <= b} prod_i (-tau_ci)^(b_i - g_i)/(b_i - g_i)! 2^-|g| M_c^g
-//   L2L  Lam_c^a = 2^-|a| sum_{b >= a} prod_i tau_ci^(b_i - a_i)/(b_i - a_i)! Lam_P^b
-// One wave per marked cell; the children's rows and the 1-D factors in LDS.
+//   M2M  M_P^b  = sum_c sum_{g <= b} prod_i (-tau_ci)^(b_i - g_i)/(b_i - g_i)! 2^-g_i M_c^g
+//   L2L  Lam_c^a = prod_i 2^-a_i sum_{b_i >= a_i} tau_ci^(b_i - a_i)/(b_i - a_i)! Lam_P^b
+// Both are products of three 1-D operators that keep |b| <= Q, applied child by child: one pass
+// per axis over the K coefficients (lane l takes l, l + 64, ...), each a sum of at most Q + 1 terms
+// run as a fixed-length loop with the terms outside the range masked, so the lanes of a wave stay
+// in step. One wave per marked cell; the rows and the 1-D factors in LDS.
 constexpr int kTreeWaves = 4;
+
+// Scratch rows of one wave: the two ping-pong rows of the passes.
+template <int Q>
+struct PassRows {
+    double r[2][ncoef(Q)];
+};
+
+// out[b] = sum_{k=0}^{Q} [the term is in range] w[k] * 2^-(b_ax - k) in[b - k e_ax]   (M2M direction)
+template <int Q>
+__device__ __forceinline__ void m2m_pass(const double *in, double *out, const double *w, int ax, int lane)
+{
+    constexpr auto &mi = kMiM<Q>;
+    for (int b = lane; b < ncoef(Q); b += kW) {
+        const int e0 = mi.e[b][0], e1 = mi.e[b][1], e2 = mi.e[b][2];
+        const int bx = ax == 0 ? e0 : (ax == 1 ? e1 : e2);
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k <= Q; ++k) {
+            if (k <= bx) {
+                const int g = bx - k;  // the source's component along ax
+                const int j = ax == 0 ? mi_index(g, e1, e2) : (ax == 1 ? mi_index(e0, g, e2) : mi_index(e0, e1, g));
+                acc = fma(w[k] * ldexp(1.0, -g), in[j], acc);
+            }
+        }
+        out[b] = acc;
+    }
+}
+
+// out[a] = 2^-a_ax sum_{k=0}^{Q} [a + k e_ax in range] w[k] in[a + k e_ax]   (L2L direction)
+template <int Q>
+__device__ __forceinline__ void l2l_pass(const double *in, double *out, const double *w, int ax, int lane)
+{
+    constexpr auto &mi = kMiM<Q>;
+    for (int a = lane; a < ncoef(Q); a += kW) {
+        const int e0 = mi.e[a][0], e1 = mi.e[a][1], e2 = mi.e[a][2];
+        const int room = Q - mi.deg[a];
+        const int ea = ax == 0 ? e0 : (ax == 1 ? e1 : e2);
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k <= Q; ++k) {
+            if (k <= room) {
+                const int j = ax == 0 ? mi_index(e0 + k, e1, e2) : (ax == 1 ? mi_index(e0, e1 + k, e2) : mi_index(e0, e1, e2 + k));
+                acc = fma(w[k], in[j], acc);
+            }
+        }
+        out[a] = ldexp(acc, -ea);
+    }
+}
+
+// 1-D factors of child c along ax: w[k] = (s tau)^k / k!, s = -1 (M2M) or +1 (L2L).
+__device__ __forceinline__ void shift_factors(double *w, const double4 &cc, const double4 &cp, int ax, double sign, int q)
+{
+    const double d = ax == 0 ? cc.x - cp.x : (ax == 1 ? cc.y - cp.y : cc.z - cp.z);
+    const double t = sign * d / cp.w;
+    double v = 1.0;
+    for (int k = 0; k <= q; ++k) {
+        w[k] = v;
+        v *= t / (k + 1);
+    }
+}
 
 template <int Q, class TR>
 __global__ __launch_bounds__(kW *kTreeWaves) void mapped_m2m_kernel(int n_par, const int32_t *__restrict__ parents,
@@ -335,47 +412,41 @@ __global__ __launch_bounds__(kW *kTreeWaves) void mapped_m2m_kernel(int n_par, c
                                                                      int ldk, int ldr)
 {
     constexpr int K = ncoef(Q), R = nreduced(Q);
-    constexpr auto &mi = kMiM<Q>;
     constexpr auto &fold = kFoldM<Q>;
     __shared__ double sm[kTreeWaves][8][K];
     __shared__ double pw[kTreeWaves][8][3][Q + 1];
-    __shared__ double out[kTreeWaves][K];
+    __shared__ PassRows<Q> rows[kTreeWaves];
     const int wv = threadIdx.x / kW, lane = threadIdx.x & (kW - 1);
     const int w = blockIdx.x * kTreeWaves + wv;
     if (w >= n_par) return;  // uniform per wave; only wave-level synchronisation below
     const int32_t par = parents[2 * w], first = parents[2 * w + 1];
     const double4 cp = centre[par];
     for (int i = lane; i < 8 * K; i += kW) sm[wv][i / K][i % K] = M[(int64_t)(first + i / K) * ldk + i % K];
-    if (lane < 24) {
-        const int c = lane / 3, ax = lane % 3;
-        const double4 cc = centre[first + c];
-        const double d = ax == 0 ? cc.x - cp.x : (ax == 1 ? cc.y - cp.y : cc.z - cp.z);
-        const double mt = -d / cp.w;
-        double v = 1.0;
-        for (int k = 0; k <= Q; ++k) {
-            pw[wv][c][ax][k] = v;
-            v *= mt / (k + 1);
-        }
-    }
+    if (lane < 24) shift_factors(pw[wv][lane / 3][lane % 3], centre[first + lane / 3], cp, lane % 3, -1.0, Q);
     wave_sync();
-    for (int b = lane; b < K; b += kW) {
-        const int bx = mi.e[b][0], by = mi.e[b][1], bz = mi.e[b][2];
-        double acc = 0.0;
-        for (int c = 0; c < 8; ++c)
-            for (int gx = 0; gx <= bx; ++gx)
-                for (int gy = 0; gy <= by; ++gy) {
-                    const double pxy = pw[wv][c][0][bx - gx] * pw[wv][c][1][by - gy];
-                    for (int gz = 0; gz <= bz; ++gz)
-                        acc = fma(pxy * pw[wv][c][2][bz - gz] * ldexp(1.0, -(gx + gy + gz)),
-                                  sm[wv][c][mi_index(gx, gy, gz)], acc);
-                }
-        out[wv][b] = acc;
-        M[(int64_t)par * ldk + b] = acc;
+    double acc[(K + kW - 1) / kW] = {};
+    for (int c = 0; c < 8; ++c) {
+        m2m_pass<Q>(sm[wv][c], rows[wv].r[0], pw[wv][c][0], 0, lane);
+        wave_sync();
+        m2m_pass<Q>(rows[wv].r[0], rows[wv].r[1], pw[wv][c][1], 1, lane);
+        wave_sync();
+        m2m_pass<Q>(rows[wv].r[1], rows[wv].r[0], pw[wv][c][2], 2, lane);
+        wave_sync();
+#pragma unroll
+        for (int s = 0; s < (K + kW - 1) / kW; ++s)
+            if (lane + s * kW < K) acc[s] += rows[wv].r[0][lane + s * kW];
+        wave_sync();
     }
+#pragma unroll
+    for (int s = 0; s < (K + kW - 1) / kW; ++s)
+        if (lane + s * kW < K) {
+            rows[wv].r[1][lane + s * kW] = acc[s];
+            M[(int64_t)par * ldk + lane + s * kW] = acc[s];
+        }
     wave_sync();
     for (int r = lane; r < R; r += kW) {
         double v = 0.0;
-        for (int t = 0; t < fold.n[r]; ++t) v = fma(fold.c[r][t], out[wv][fold.src[r][t]], v);
+        for (int t = 0; t < fold.n[r]; ++t) v = fma(fold.c[r][t], rows[wv].r[1][fold.src[r][t]], v);
         Mr[(int64_t)par * ldr + r] = (TR)v;
     }
 }
@@ -386,38 +457,26 @@ __global__ __launch_bounds__(kW *kTreeWaves) void mapped_l2l_kernel(int n_par, c
                                                                      double *__restrict__ Lam, int ldk)
 {
     constexpr int K = ncoef(Q);
-    constexpr auto &mi = kMiM<Q>;
     __shared__ double lp[kTreeWaves][K];
     __shared__ double pw[kTreeWaves][8][3][Q + 1];
+    __shared__ PassRows<Q> rows[kTreeWaves];
     const int wv = threadIdx.x / kW, lane = threadIdx.x & (kW - 1);
     const int w = blockIdx.x * kTreeWaves + wv;
     if (w >= n_par) return;
     const int32_t par = parents[2 * w], first = parents[2 * w + 1];
     const double4 cp = centre[par];
     for (int i = lane; i < K; i += kW) lp[wv][i] = Lam[(int64_t)par * ldk + i];
-    if (lane < 24) {
-        const int c = lane / 3, ax = lane % 3;
-        const double4 cc = centre[first + c];
-        const double d = ax == 0 ? cc.x - cp.x : (ax == 1 ? cc.y - cp.y : cc.z - cp.z);
-        const double t = d / cp.w;
-        double v = 1.0;
-        for (int k = 0; k <= Q; ++k) {
-            pw[wv][c][ax][k] = v;
-            v *= t / (k + 1);
-        }
-    }
+    if (lane < 24) shift_factors(pw[wv][lane / 3][lane % 3], centre[first + lane / 3], cp, lane % 3, 1.0, Q);
     wave_sync();
-    for (int i = lane; i < 8 * K; i += kW) {
-        const int c = i / K, a = i - c * K;
-        const int ax = mi.e[a][0], ay = mi.e[a][1], az = mi.e[a][2], da = mi.deg[a];
-        double acc = 0.0;
-        for (int dx = 0; dx <= Q - da; ++dx)
-            for (int dy = 0; dx + dy <= Q - da; ++dy) {
-                const double pxy = pw[wv][c][0][dx] * pw[wv][c][1][dy];
-                for (int dz = 0; dx + dy + dz <= Q - da; ++dz)
-                    acc = fma(pxy * pw[wv][c][2][dz], lp[wv][mi_index(ax + dx, ay + dy, az + dz)], acc);
-            }
-        Lam[(int64_t)(first + c) * ldk + a] += ldexp(acc, -da);
+    for (int c = 0; c < 8; ++c) {
+        l2l_pass<Q>(lp[wv], rows[wv].r[0], pw[wv][c][2], 2, lane);
+        wave_sync();
+        l2l_pass<Q>(rows[wv].r[0], rows[wv].r[1], pw[wv][c][1], 1, lane);
+        wave_sync();
+        l2l_pass<Q>(rows[wv].r[1], rows[wv].r[0], pw[wv][c][0], 0, lane);
+        wave_sync();
+        for (int a = lane; a < K; a += kW) Lam[(int64_t)(first + c) * ldk + a] += rows[wv].r[0][a];
+        wave_sync();
     }
 }
 
@@ -644,9 +703,14 @@ void launch_mapped_zero(const bcv_plan_s &p, double *u, hipStream_t st)
 }
 
 // Plan time: the near entries of mapped target leaves (point rule), then their touching entries
-// (singular rule), into p.d_val. Synchronous.
+// (singular rule), into p.d_val. touch_entry/touch_target list every touching entry of a ball leaf;
+// the rule runs on the pairs of `work` (entry, target, mirror entry or -1) and writes both entries of
+// a pair. cache: the touching values in list order, reused if it has the list's length, else filled.
+// Synchronous.
 void launch_mapped_assemble(const bcv_plan_s &p, const std::vector<int64_t> &touch_entry,
-                            const std::vector<int32_t> &touch_target, const int rule_orders[5])
+                            const std::vector<int64_t> &work_entry, const std::vector<int32_t> &work_target,
+                            const std::vector<int64_t> &work_mirror, const int rule_orders[5],
+                            std::vector<double> &cache)
 {
     if (p.n_units > 0) {
         mapped_assemble_kernel<<<(unsigned)((p.n_units + 3) / 4), 256>>>(
@@ -654,31 +718,53 @@ void launch_mapped_assemble(const bcv_plan_s &p, const std::vector<int64_t> &tou
         check_launch();
     }
     const int64_t n = (int64_t)touch_entry.size();
-    if (n > 0) {
+    if (n == 0) {
+        BCV_HIP(hipDeviceSynchronize());
+        return;
+    }
+    int64_t *d_list = nullptr;
+    double *d_vals = nullptr;
+    BCV_HIP(hipMalloc(&d_list, n * sizeof(int64_t)));
+    BCV_HIP(hipMalloc(&d_vals, n * sizeof(double)));
+    BCV_HIP(hipMemcpy(d_list, touch_entry.data(), n * sizeof(int64_t), hipMemcpyHostToDevice));
+    const unsigned cblocks = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    if ((int64_t)cache.size() == n) {
+        BCV_HIP(hipMemcpy(d_vals, cache.data(), n * sizeof(double), hipMemcpyHostToDevice));
+        touch_copy_kernel<<<cblocks, 256>>>(n, d_list, d_vals, p.d_val, 1);
+        check_launch();
+    } else {
         SingRule R{};
-        R.nl = rule_orders[0], R.nm = rule_orders[1], R.nz = rule_orders[2], R.ns = rule_orders[3], R.nr = rule_orders[4];
         for (int k = 0; k < 5; ++k)
             BCV_REQUIRE(rule_orders[k] >= 1 && rule_orders[k] <= kRuleMax, BCV_EINVAL, "singular-rule orders: 1..8");
+        R.nl = rule_orders[0], R.nm = rule_orders[1], R.nz = rule_orders[2], R.ns = rule_orders[3], R.nr = rule_orders[4];
         gauss_legendre01(R.nl, R.xl, R.wl);
         gauss_legendre01(R.nm, R.xm, R.wm);
         gauss_legendre01(R.nz, R.xz, R.wz);
         gauss_legendre01(R.ns, R.xs, R.ws);
         gauss_legendre01(R.nr, R.xr, R.wr);
-        int64_t *d_e = nullptr;
+        const int64_t nw = (int64_t)work_entry.size();
+        int64_t *d_e = nullptr, *d_m = nullptr;
         int32_t *d_t = nullptr;
-        BCV_HIP(hipMalloc(&d_e, n * sizeof(int64_t)));
-        BCV_HIP(hipMalloc(&d_t, n * sizeof(int32_t)));
-        BCV_HIP(hipMemcpy(d_e, touch_entry.data(), n * sizeof(int64_t), hipMemcpyHostToDevice));
-        BCV_HIP(hipMemcpy(d_t, touch_target.data(), n * sizeof(int32_t), hipMemcpyHostToDevice));
-        const unsigned blocks = (unsigned)std::min<int64_t>(n, 1 << 20);
-        ball_touch_kernel<<<blocks, 256>>>(n, d_e, d_t, p.d_col, reinterpret_cast<const double4 *>(p.d_leaf_geom), R,
-                                           p.d_val);
+        BCV_HIP(hipMalloc(&d_e, nw * sizeof(int64_t)));
+        BCV_HIP(hipMalloc(&d_m, nw * sizeof(int64_t)));
+        BCV_HIP(hipMalloc(&d_t, nw * sizeof(int32_t)));
+        BCV_HIP(hipMemcpy(d_e, work_entry.data(), nw * sizeof(int64_t), hipMemcpyHostToDevice));
+        BCV_HIP(hipMemcpy(d_m, work_mirror.data(), nw * sizeof(int64_t), hipMemcpyHostToDevice));
+        BCV_HIP(hipMemcpy(d_t, work_target.data(), nw * sizeof(int32_t), hipMemcpyHostToDevice));
+        ball_touch_kernel<<<(unsigned)std::min<int64_t>(nw, 1 << 20), 256>>>(
+            nw, d_e, d_t, d_m, p.d_col, reinterpret_cast<const double4 *>(p.d_leaf_geom), R, p.d_val);
         check_launch();
-        BCV_HIP(hipDeviceSynchronize());
+        touch_copy_kernel<<<cblocks, 256>>>(n, d_list, d_vals, p.d_val, 0);
+        check_launch();
+        cache.resize(n);
+        BCV_HIP(hipMemcpy(cache.data(), d_vals, n * sizeof(double), hipMemcpyDeviceToHost));
         BCV_HIP(hipFree(d_e));
+        BCV_HIP(hipFree(d_m));
         BCV_HIP(hipFree(d_t));
     }
     BCV_HIP(hipDeviceSynchronize());
+    BCV_HIP(hipFree(d_list));
+    BCV_HIP(hipFree(d_vals));
 }
 
 }  // namespace bcv

@@ -301,9 +301,10 @@ struct M2LPlan {
 // than 256 at h = 1/128 and 1/256; shorter pieces add partial sums and gathering first slots). With
 // level-dependent orders each level is its own launch, and 256 measured faster (4% in FP64); so
 // did small meshes, whose few tasks need the shorter pieces to fill the GPU.
-// Orders of the singular rule for touching mapped cells (lambda, mu, z, s, r; see mapped.hip): about
-// 1e-8 relative on ball cells against the same rule at orders (8, 12, 8, 8, 8).
-constexpr int kMappedRule[5] = {5, 8, 6, 4, 4};
+// Orders of the singular rule for touching mapped cells (lambda, mu, z, s, r; see mapped.hip): within
+// about 1.3e-6 relative of the same rule at orders (8, 12, 8, 8, 8) on ball cells of side 1/16, at
+// 1.8M kernel evaluations per leaf of a uniform region.
+constexpr int kMappedRule[5] = {5, 7, 5, 3, 4};
 
 constexpr int kDefaultMaxSlots = 320;
 constexpr int kDefaultMaxSlotsSchedule = 256;
@@ -986,8 +987,14 @@ void mapped_rows(const std::vector<double> &pts, const std::vector<double> &cen,
     }
 }
 
+struct MappedTouch {
+    std::vector<int64_t> entry;                 // every touching entry of a ball leaf
+    std::vector<int64_t> work_entry, work_mirror;  // the pairs the rule runs on, and the (s, t) entry or -1
+    std::vector<int32_t> work_target;
+};
+
 void setup_mapped(bcv_plan_s *p, const bcv_tree_s &t, const std::vector<Grid> &g, const NearCSR &near, bool direct,
-                  std::vector<int64_t> &touch_entry, std::vector<int32_t> &touch_target)
+                  MappedTouch &mt)
 {
     const int64_t nl = t.n_leaves(), nc = t.n_cells();
     const double node[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
@@ -1040,14 +1047,25 @@ void setup_mapped(bcv_plan_s *p, const bcv_tree_s &t, const std::vector<Grid> &g
     p->d_kap = upload(p, kap);
     p->d_kapr = upload(p, kapr);
     p->d_leaf_mapped = upload(p, lm);
-    // touching entries of ball leaves (they come first in each row)
+    // touching entries of ball leaves (they come first in each row); the rule is symmetric, so a pair
+    // and its mirror (s, t) are computed once
+    auto find = [&](int32_t row, int32_t col) -> int64_t {
+        for (int64_t e = near.row[row]; e < near.split[row]; ++e)
+            if ((int32_t)(near.col[e] & 0x0FFFFFFFu) == col) return e;
+        return -1;
+    };
     for (int64_t l = 0; l < nl; ++l)
         if (lm[l])
             for (int64_t e = near.row[l]; e < near.split[l]; ++e) {
-                touch_entry.push_back(e);
-                touch_target.push_back((int32_t)l);
+                const int32_t s = (int32_t)(near.col[e] & 0x0FFFFFFFu);
+                mt.entry.push_back(e);
+                const int64_t m = s == (int32_t)l ? -1 : find(s, (int32_t)l);
+                if (m >= 0 && s < (int32_t)l) continue;  // computed with its mirror
+                mt.work_entry.push_back(e);
+                mt.work_target.push_back((int32_t)l);
+                mt.work_mirror.push_back(m);
             }
-    p->n_mapped_touch = (int64_t)touch_entry.size();
+    p->n_mapped_touch = (int64_t)mt.entry.size();
     if (direct) return;
     // interaction lists, CSR over the cells of levels >= 2 (cell order)
     const int32_t c0 = t.L >= 2 ? t.lvl_start[2] : (int32_t)nc;
@@ -1195,8 +1213,7 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
     }
 
     NearCSR vol_near;  // kept for the VtB rows
-    std::vector<int64_t> mapped_touch_entry;  // mapped meshes: touching entries of ball leaves
-    std::vector<int32_t> mapped_touch_target;
+    MappedTouch mapped_touch;  // mapped meshes: touching entries of ball leaves
     std::vector<int32_t> basis_pair_t, basis_pair_pos;  // degree-p leaf bases: per near entry
     // Level-dependent near-field rule: per-leaf Gauss orders and the entries that need them.
     std::vector<int8_t> near_order;
@@ -1234,7 +1251,7 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         p->d_units = upload(p.get(), nu.units);
         p->d_splits = upload(p.get(), nu.splits);
         if (nu.n_partial > 0) p->d_partial = alloc_zero<double>(p.get(), (size_t)nu.n_partial);
-        if (p->mapped) setup_mapped(p.get(), t, grids, near, opts.direct != 0, mapped_touch_entry, mapped_touch_target);
+        if (p->mapped) setup_mapped(p.get(), t, grids, near, opts.direct != 0, mapped_touch);
         if (opts.boundary) vol_near = std::move(near);
     }
 
@@ -1407,7 +1424,9 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         launch_near_assemble(*p, nullptr);
         BCV_HIP(hipDeviceSynchronize());
         if (opts.near_order == 1) launch_near_assemble_ordered(*p, ordered_entry, ordered_target, near_order);
-        if (p->mapped) launch_mapped_assemble(*p, mapped_touch_entry, mapped_touch_target, kMappedRule);
+        if (p->mapped)
+            launch_mapped_assemble(*p, mapped_touch.entry, mapped_touch.work_entry, mapped_touch.work_target,
+                                   mapped_touch.work_mirror, kMappedRule, t.mapped_touch_cache[opts.direct != 0]);
         if (p->precision != BCV_FP64) {  // the apply reads FP32 entries (touching pairs stay exact)
             p->d_val32 = alloc_zero<float>(p.get(), (size_t)p->n_near);
             launch_near_narrow(*p, nullptr);

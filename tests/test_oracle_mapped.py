@@ -8,7 +8,8 @@
   same rule at higher orders;
 * the whole mapped operator against the Newton potential of the uniform ball, R^2/2 - r^2/6
   (a textbook closed form): with a high-order rule on the non-touching pairs the cell integrals
-  agree to 1e-7, with the 2x2x2 point rule to its discretisation error;
+  agree to 1e-6 (the singular rule's own accuracy), with the 2x2x2 point rule to its
+  discretisation error;
 * the mapped FMM: with the identity map its far field equals oracle.fmm's; on the ball it tends to
   the direct sum as q grows; the sampled form equals the full one.
 """
@@ -108,7 +109,8 @@ def test_singular_rule_on_the_ball_symmetric_and_converged():
         sel = rng.choice(np.nonzero(cls == c)[0], 3, replace=False)
         v = mapped.touch_entries(mm, ti[sel], si[sel])
         assert np.abs(v / mapped.touch_entries(mm, si[sel], ti[sel]) - 1).max() < 1e-13, c
-        assert np.abs(v / mapped.touch_entries(mm, ti[sel], si[sel], HIGH) - 1).max() < 1e-7, c
+        # measured 2.2e-6 at most (the rule's orders trade this for plan time on the GPU)
+        assert np.abs(v / mapped.touch_entries(mm, ti[sel], si[sel], HIGH) - 1).max() < 5e-6, c
 
 
 def _cell_integrals_of_ball_potential(mm):
@@ -134,7 +136,7 @@ def test_uniform_ball_closed_form():
     A[tch] = mapped.touch_entries(mm, ti[tch], si[tch])
     A[~tch] = mapped.regular_entries(mm, ti[~tch], si[~tch], 6)
     ex = _cell_integrals_of_ball_potential(mm)
-    assert np.abs(A.reshape(n, n).sum(axis=1) / ex - 1).max() < 1e-7  # measured 2.4e-8
+    assert np.abs(A.reshape(n, n).sum(axis=1) / ex - 1).max() < 3e-6  # measured 9.4e-7 (2.4e-8 at HIGH orders)
     u = mapped.apply_direct(mm, np.ones(n))  # the 2x2x2 rule on non-touching pairs
     assert np.abs(u / ex - 1).max() < 5e-4  # measured 3.0e-4
     Am = mapped.matrix(mm)
