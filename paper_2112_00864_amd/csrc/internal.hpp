@@ -293,7 +293,9 @@ struct bcv_plan_s {
     double *d_kap = nullptr;        // per leaf: kappa^b = sum_g w_g ((x_g - x_w)/a)^b / b!, K entries
     double *d_kapr = nullptr;       // per leaf: the folded rows of (-1)^|b| kappa^b, R entries
     uint8_t *d_leaf_mapped = nullptr;  // per leaf: 1 if its mesh is a ball
-    int64_t n_ilist = 0;            // interaction-list pairs (cells of levels >= 2, CSR by target)
+    int64_t n_ilist = 0;            // interaction-list pairs of the ball cells (levels >= 2), CSR by target
+    int64_t n_ilist_targets = 0;
+    int32_t *d_ilist_tgt = nullptr;   // the target cells
     int64_t *d_ilist_off = nullptr;
     int32_t *d_ilist_src = nullptr;
     int64_t n_mapped_touch = 0;     // touching near entries of ball leaves (singular rule)

@@ -2121,8 +2121,9 @@ void launch_btv(const bcv_plan_s &p, const double *qf, const double *gf, double 
 }
 
 // VtV apply on a mapped mesh (mapped.hip), on the caller's stream: the near field from the assembled
-// entries (it writes u), then P2M, the upward pass, the interaction phase pair by pair, the downward
-// pass and the evaluation, which adds to u.
+// entries (it writes u), then P2M, the upward pass, the interaction phase (lattice tasks for the cells
+// of cube meshes, pair by pair for the ball cells), the downward pass and the evaluation, which adds
+// to u.
 template <int Q>
 void mapped_apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStream_t st)
 {
@@ -2139,6 +2140,7 @@ void mapped_apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, 
         const int phase_id[4] = {BCV_PHASE_P2M, BCV_PHASE_M2M, BCV_PHASE_M2L, BCV_PHASE_L2L};
         for (int ph = 0; ph < 4; ++ph) {
             marks.start(phase_id[ph], st);
+            if (ph == 2) interaction_phase<Q>(p, st);  // the cube meshes' cells: lattice tasks
             launch_mapped_phase(p, f, ph, st);
             marks.stop(phase_id[ph], st);
         }

@@ -594,9 +594,10 @@ __device__ __forceinline__ void pair_store(const T *acc, double scale, double *_
     ((dst[Fs] = scale * one(Fs)), ...);
 }
 
-// One thread per target cell (cells c0 .. c0 + n - 1, CSR lists of source cells).
+// One thread per listed target cell (CSR lists of source cells).
 template <int Q, class T>
-__global__ __launch_bounds__(kW) void m2l_pairs_kernel(int32_t c0, int32_t n, const int64_t *__restrict__ off,
+__global__ __launch_bounds__(kW) void m2l_pairs_kernel(const int32_t *__restrict__ tgt, int32_t n,
+                                                       const int64_t *__restrict__ off,
                                                        const int32_t *__restrict__ src,
                                                        const double4 *__restrict__ centre,
                                                        const T *__restrict__ Mr, double *__restrict__ Lam, int ldr,
@@ -605,7 +606,7 @@ __global__ __launch_bounds__(kW) void m2l_pairs_kernel(int32_t c0, int32_t n, co
     constexpr int R = nreduced(Q), N = PairTables<Q>::N, K = ncoef(Q);
     const int32_t i = (int32_t)(blockIdx.x * kW + threadIdx.x);
     if (i >= n) return;
-    const int32_t t = c0 + i;
+    const int32_t t = tgt[i];
     const double4 ct = centre[t];
     const double inv_a = 1.0 / ct.w;
     T acc[R];
@@ -650,18 +651,17 @@ void mapped_passes(const bcv_plan_s &p, const double *f, int phase, hipStream_t 
                 mapped_m2m_kernel<Q, double><<<blocks, kW * kTreeWaves, 0, st>>>(n_par, par, cen, p.d_M, p.d_Mr, p.K, p.R);
             check_launch();
         }
-    } else if (phase == 2) {  // interaction phase over the cells of levels >= 2
+    } else if (phase == 2) {  // interaction phase of the ball cells of levels >= 2
         const auto *cen = reinterpret_cast<const double4 *>(p.d_centre);
-        const int32_t c0 = p.lvl_start[2 <= p.L ? 2 : p.L + 1];
-        const int32_t n = (int32_t)p.n_cells - c0;
+        const int32_t n = (int32_t)p.n_ilist_targets;
         if (n > 0) {
             const unsigned blocks = (unsigned)((n + kW - 1) / kW);
             if (mixed)
-                m2l_pairs_kernel<Q, float><<<blocks, kW, 0, st>>>(c0, n, p.d_ilist_off, p.d_ilist_src, cen, p.d_M32,
-                                                                  p.d_Lam, p.R, p.K);
+                m2l_pairs_kernel<Q, float><<<blocks, kW, 0, st>>>(p.d_ilist_tgt, n, p.d_ilist_off, p.d_ilist_src, cen,
+                                                                  p.d_M32, p.d_Lam, p.R, p.K);
             else
-                m2l_pairs_kernel<Q, double><<<blocks, kW, 0, st>>>(c0, n, p.d_ilist_off, p.d_ilist_src, cen, p.d_Mr,
-                                                                   p.d_Lam, p.R, p.K);
+                m2l_pairs_kernel<Q, double><<<blocks, kW, 0, st>>>(p.d_ilist_tgt, n, p.d_ilist_off, p.d_ilist_src, cen,
+                                                                   p.d_Mr, p.d_Lam, p.R, p.K);
             check_launch();
         }
     } else {  // L2L, coarsest parents first (levels 2 .. L - 1; levels 0 and 1 have no interaction list)

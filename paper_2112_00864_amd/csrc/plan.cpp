@@ -1067,15 +1067,20 @@ void setup_mapped(bcv_plan_s *p, const bcv_tree_s &t, const std::vector<Grid> &g
             }
     p->n_mapped_touch = (int64_t)mt.entry.size();
     if (direct) return;
-    // interaction lists, CSR over the cells of levels >= 2 (cell order)
+    // interaction lists of the ball cells of levels >= 2 (cell order), CSR; the cells of cube meshes
+    // take the lattice interaction plan
     const int32_t c0 = t.L >= 2 ? t.lvl_start[2] : (int32_t)nc;
-    std::vector<int64_t> off((size_t)(nc - c0) + 1, 0);
-    std::vector<std::vector<int32_t>> lists((size_t)(nc - c0));
+    std::vector<int32_t> tgt;
+    for (int64_t c = c0; c < nc; ++c)
+        if (t.mesh_geom[mesh_of((int32_t)c)] == BCV_GEOM_BALL) tgt.push_back((int32_t)c);
+    std::vector<int64_t> off(tgt.size() + 1, 0);
+    std::vector<std::vector<int32_t>> lists(tgt.size());
 #pragma omp parallel for schedule(dynamic, 256)
-    for (int64_t c = c0; c < nc; ++c) {
+    for (int64_t q = 0; q < (int64_t)tgt.size(); ++q) {
+        const int32_t c = tgt[q];
         const int lev = t.level[c];
         const int i = t.ijk[3 * c], j = t.ijk[3 * c + 1], k = t.ijk[3 * c + 2];
-        auto &out = lists[(size_t)(c - c0)];
+        auto &out = lists[(size_t)q];
         for (const auto &o : stencil()) {
             const int32_t pn = g[lev - 1].at((i >> 1) + o[0], (j >> 1) + o[1], (k >> 1) + o[2]);
             if (pn < 0 || !t.refined[pn]) continue;
@@ -1090,6 +1095,8 @@ void setup_mapped(bcv_plan_s *p, const bcv_tree_s &t, const std::vector<Grid> &g
     for (size_t q = 0; q < lists.size(); ++q) std::copy(lists[q].begin(), lists[q].end(), src.begin() + off[q]);
     p->n_ilist = off.back();
     p->n_m2l = p->n_ilist;
+    p->n_ilist_targets = (int64_t)tgt.size();
+    p->d_ilist_tgt = upload(p, tgt);
     p->d_ilist_off = upload(p, off);
     p->d_ilist_src = upload(p, src);
 }
@@ -1280,9 +1287,21 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         if (per_level)
             for (int lev = 0; lev <= t.L; ++lev)
                 level_slots[lev] = std::max<int32_t>(8, slots >> std::min(16, p->q_level[lev] - opts.q));
-        if (!p->mapped) {  // the lattice interaction plan (mapped meshes: CSR lists, setup_mapped)
+        // The lattice interaction plan: every cell, or with mapped meshes the cells of the cube
+        // meshes (ball cells take the pair lists of setup_mapped).
+        std::vector<uint8_t> lattice_target;
+        bool lattice = !p->mapped;
+        if (p->mapped) {
+            lattice_target.assign(t.n_cells(), 0);
+            for (int64_t c = 0; c < t.n_cells(); ++c) {
+                lattice_target[c] = t.mesh_geom[(t.ijk[3 * c] >> t.level[c]) / 4] == BCV_GEOM_BOX;
+                lattice = lattice || lattice_target[c];
+            }
+        }
+        if (lattice) {
         M2LPlan m2l = build_m2l(t, grids, level_slots, per_level,
-                                opts.m2l_max_slots == 0 && !per_level ? kDefaultMaxSlotsSchedule : 0);
+                                opts.m2l_max_slots == 0 && !per_level ? kDefaultMaxSlotsSchedule : 0, nullptr,
+                                p->mapped ? lattice_target.data() : nullptr);
         std::vector<int32_t> id_of_key(15 * 15 * 15, -1);
         for (int32_t key : m2l.slot_key) id_of_key[key & 0x7FFFFFFF] = 0;
         std::vector<double> G;
@@ -1297,7 +1316,7 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         }
         for (int32_t &s : m2l.slot_key) s = id_of_key[s & 0x7FFFFFFF] | (s & (int32_t)0x80000000);
         p->n_offsets = n_off;
-        p->n_m2l = m2l.n_pairs;
+        p->n_m2l = m2l.n_pairs + p->n_ilist;
         p->n_m2l_lanes = (int64_t)m2l.slot_key.size() * 64;
         p->n_m2l_read_lanes = m2l.n_read_lanes;
         p->n_tasks = (int64_t)m2l.tasks.size();
@@ -1464,7 +1483,7 @@ void destroy_plan(bcv_plan_s *p)
                     p->btv_m2l.d_m2l_splits, p->btv_m2l.d_m2l_partial, p->vtb_m2l.d_tasks,
                     p->vtb_m2l.d_task_targets, p->vtb_m2l.d_slot_off, p->vtb_m2l.d_slot_src,
                     p->vtb_m2l.d_m2l_splits, p->vtb_m2l.d_m2l_partial, p->d_leaf_pts, p->d_centre, p->d_kap,
-                    p->d_kapr, p->d_leaf_mapped, p->d_ilist_off, p->d_ilist_src};
+                    p->d_kapr, p->d_leaf_mapped, p->d_ilist_tgt, p->d_ilist_off, p->d_ilist_src};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     p->magic = 0;
