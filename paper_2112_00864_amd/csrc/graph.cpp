@@ -90,8 +90,8 @@ double time_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int device, int
 
 }  // namespace
 
-// Coordinate search: near_unit first (with the base piece length), then m2l_max_slots (not for trees
-// with mapped meshes, whose interaction phase works pair by pair).
+// Coordinate search: near_unit first (with the base piece length), then m2l_max_slots (not for forests
+// of ball meshes only, whose interaction phase works pair by pair).
 double autotune(const bcv_tree_s &t, const bcv_plan_opts &base, int device, int n_applies, bcv_plan_opts &best)
 {
     BCV_REQUIRE(n_applies >= 1 && n_applies <= 1000, BCV_EINVAL, "n_applies must be 1..1000");
@@ -115,10 +115,10 @@ double autotune(const bcv_tree_s &t, const bcv_plan_opts &base, int device, int 
             const double ms = time_plan(t, o, device, n_applies, f, u, st);
             if (ms < best_ms) best_ms = ms, best = o;
         }
-        bool mapped = false;  // forests with ball meshes have no lattice interaction tasks
-        for (int m = 0; m < t.n_meshes; ++m) mapped = mapped || t.mesh_geom[m] == BCV_GEOM_BALL;
+        bool lattice = false;  // forests of ball meshes only have no lattice interaction tasks
+        for (int m = 0; m < t.n_meshes; ++m) lattice = lattice || t.mesh_geom[m] == BCV_GEOM_BOX;
         for (int slots : {128, 256, 320, 512, 1024}) {
-            if (mapped) break;
+            if (!lattice) break;
             bcv_plan_opts o = best;
             o.m2l_max_slots = slots;
             const double ms = time_plan(t, o, device, n_applies, f, u, st);
