@@ -200,6 +200,7 @@ typedef struct {
     int64_t n_btv_m2l;    /* interaction-list pairs of the BtV apply: boundary sources only (0
                              without opts.boundary or for a direct plan) */
     int64_t n_vtb_m2l;    /* interaction-list pairs of the VtB apply: boundary targets only */
+    int64_t n_mapped_touch_pairs; /* touching pairs of ball leaves (a pair and its mirror counted once) */
 } bcv_plan_info;
 
 /* Build the BC octree of Sec. 2 on the host. desc and out must be non-NULL.
@@ -480,6 +481,14 @@ bcv_status bcv_surrogate_eval(bcv_mlp mlp, int64_t n, const bcv_touch_pair *pair
                               double *est_err, int32_t *fallback, int64_t *n_fallback);
 /* Flat file: header (magic, version, inputs, width, both Gauss orders, residual scale, kappa) then the
  * FP32 parameters. */
+/* Entries of n touching pairs of cube-to-ball mapped cells by the planner's singular rule (the
+ * touching entries of BCV_GEOM_BALL plans, Sec. 1.2 entries on curved cells): cube t of pair i is
+ * geom_t[4i..4i+3] (lower corner in the reference cube [0,1]^3, side 2^-l, l <= 12, a cube of the
+ * octree), its partner geom_s[4i..4i+3] (equal cubes, or of equal side or ratio 2 with closed cubes
+ * touching from outside); value[i] = int int G J J over the two curved cells of the unit-diameter ball.
+ * Host arrays; synchronous. Errors: BCV_EINVAL (NULL arrays, cubes not of the octree or not
+ * touching), BCV_EDEVICE. */
+bcv_status bcv_mapped_pair_entries(int device, int64_t n, const double *geom_t, const double *geom_s, double *value);
 bcv_status bcv_mlp_save(bcv_mlp mlp, const char *path);
 bcv_status bcv_mlp_load(const char *path, int device, bcv_mlp *out);
 

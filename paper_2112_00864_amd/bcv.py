@@ -58,7 +58,7 @@ class PlanInfo(ctypes.Structure):
                                               "device_bytes")] + [
         ("K", ctypes.c_int32), ("L", ctypes.c_int32), ("surrogate_classes", ctypes.c_int32), ("pad", ctypes.c_int32),
         ("n_dofs", ctypes.c_int64), ("n_basis_vals", ctypes.c_int64), ("n_basis_cols", ctypes.c_int64),
-        ("n_btv_m2l", ctypes.c_int64), ("n_vtb_m2l", ctypes.c_int64)]
+        ("n_btv_m2l", ctypes.c_int64), ("n_vtb_m2l", ctypes.c_int64), ("n_mapped_touch_pairs", ctypes.c_int64)]
 
 
 CONTACT_FACE, CONTACT_EDGE, CONTACT_VERTEX = 1, 2, 3
@@ -129,6 +129,7 @@ def lib():
         L.bcv_mlp_train.argtypes = [vp, ctypes.POINTER(TrainOpts), ctypes.POINTER(TrainReport)]
         L.bcv_surrogate_eval.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(TouchPair), ctypes.c_double, dp, dp,
                                          i32p, i64p]
+        L.bcv_mapped_pair_entries.argtypes = [ctypes.c_int, ctypes.c_int64, dp, dp, dp]
         L.bcv_mlp_save.argtypes = [vp, ctypes.c_char_p]
         L.bcv_mlp_load.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(vp)]
         L.bcv_build_bc_forest.argtypes = [ctypes.c_int, ctypes.POINTER(MeshDesc), ctypes.POINTER(vp)]
@@ -147,7 +148,8 @@ def lib():
                      "bcv_mlp_get_params", "bcv_mlp_set_params", "bcv_mlp_forward", "bcv_mlp_forward_noalloc",
                      "bcv_mlp_loss_grad",
                      "bcv_mlp_train", "bcv_surrogate_eval", "bcv_mlp_save", "bcv_mlp_load", "bcv_build_bc_forest",
-                     "bcv_tree_leaf_mesh", "bcv_vtv_graph_create", "bcv_graph_launch", "bcv_autotune"):
+                     "bcv_tree_leaf_mesh", "bcv_vtv_graph_create", "bcv_graph_launch", "bcv_autotune",
+                     "bcv_mapped_pair_entries"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -501,6 +503,18 @@ def mlp_create(width=128, seed=0, device=0):
     h = ctypes.c_void_p()
     _check(lib().bcv_mlp_create(width, seed, device, ctypes.byref(h)))
     return MLP(h, device)
+
+
+def mapped_pair_entries(geom_t, geom_s, device=0):
+    """Entries of touching pairs of cube-to-ball mapped cells by the planner's singular rule (rows: lower
+    corner in the reference cube [0,1]^3 and side of each cube)."""
+    gt = np.ascontiguousarray(geom_t, dtype=np.float64).reshape(-1, 4)
+    gs = np.ascontiguousarray(geom_s, dtype=np.float64).reshape(-1, 4)
+    if len(gt) != len(gs):
+        raise ValueError("one partner per cube")
+    value = np.empty(len(gt))
+    _check(lib().bcv_mapped_pair_entries(device, len(gt), _dp(gt), _dp(gs), _dp(value)))
+    return value
 
 
 def mlp_load(path, device=0):

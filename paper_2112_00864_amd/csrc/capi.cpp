@@ -303,6 +303,7 @@ bcv_status bcv_plan_get_info(bcv_plan plan, bcv_plan_info *info)
         info->n_basis_cols = plan->n_bcols;
         info->n_btv_m2l = plan->btv_m2l.n_pairs;
         info->n_vtb_m2l = plan->vtb_m2l.n_pairs;
+        info->n_mapped_touch_pairs = plan->n_mapped_pairs;
     });
 }
 
@@ -458,6 +459,38 @@ bcv_status bcv_mlp_create(int width, uint64_t seed, int device, bcv_mlp *out)
         *out = nullptr;
         check_device(device);
         on_device(device, [&] { *out = bcv::mlp_create(width, seed, device); });
+    });
+}
+
+bcv_status bcv_mapped_pair_entries(int device, int64_t n, const double *geom_t, const double *geom_s, double *value)
+{
+    return guard([&] {
+        check_device(device);
+        BCV_REQUIRE(n >= 0 && (n == 0 || (geom_t && geom_s && value)), BCV_EINVAL, "bad arguments");
+        for (int64_t i = 0; i < n; ++i) {
+            const double *g[2] = {geom_t + 4 * i, geom_s + 4 * i};
+            for (const double *c : g) {
+                BCV_REQUIRE(c[3] > 0.0, BCV_EINVAL, "sides must be 2^-l, l in 0..12");
+                const int lev = -std::ilogb(c[3]);
+                BCV_REQUIRE(std::ldexp(1.0, -lev) == c[3] && lev >= 0 && lev <= 12, BCV_EINVAL,
+                            "sides must be 2^-l, l in 0..12");
+                for (int ax = 0; ax < 3; ++ax)
+                    BCV_REQUIRE(c[ax] >= 0.0 && c[ax] + c[3] <= 1.0 &&
+                                    std::ldexp(c[ax], lev) == std::floor(std::ldexp(c[ax], lev)),
+                                BCV_EINVAL, "a cube of the reference octree inside [0,1]^3");
+            }
+            const double big = std::max(g[0][3], g[1][3]), small = std::min(g[0][3], g[1][3]);
+            BCV_REQUIRE(big == small || big == 2.0 * small, BCV_EINVAL, "sides equal or in ratio 2");
+            bool touch = true, overlap = true;
+            for (int ax = 0; ax < 3; ++ax) {
+                const double lo = std::max(g[0][ax], g[1][ax]), hi = std::min(g[0][ax] + g[0][3], g[1][ax] + g[1][3]);
+                touch = touch && lo <= hi;
+                overlap = overlap && lo < hi;
+            }
+            BCV_REQUIRE(touch && (!overlap || big == small), BCV_EINVAL,
+                        "the closed cubes must touch (equal cubes, or a smaller cube outside the larger)");
+        }
+        on_device(device, [&] { bcv::mapped_rule_values(n, geom_t, geom_s, bcv::kMappedRule, value); });
     });
 }
 

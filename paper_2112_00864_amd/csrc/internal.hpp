@@ -158,6 +158,14 @@ struct bcv_mlp_s {
 
 namespace bcv {
 constexpr int kMlpIn = 6, kMlpOut = 2;
+// Orders of the singular rule for touching mapped cells (lambda, mu, z, s, r; see mapped.hip): within
+// about 1.3e-6 relative of the same rule at orders (8, 12, 8, 8, 8) on ball cells of side 1/16 away
+// from the cube's edges (1e-4 on cells along an edge, 1e-3 at a corner, where det D Phi tends to 0),
+// at 1.8M kernel evaluations per leaf of a uniform region.
+constexpr int kMappedRule[5] = {5, 7, 5, 3, 4};
+// The singular rule on explicit pairs (4 doubles per cube: lower corner in the reference cube [0,1]^3
+// and side; host arrays), results into out (host).
+void mapped_rule_values(int64_t n, const double *geom_t, const double *geom_s, const int orders[5], double *out);
 int64_t mlp_n_params(const bcv_mlp_s &net);
 bcv_mlp_s *mlp_create(int width, uint64_t seed, int device);
 void mlp_destroy(bcv_mlp_s *net);
@@ -299,6 +307,7 @@ struct bcv_plan_s {
     int64_t *d_ilist_off = nullptr;
     int32_t *d_ilist_src = nullptr;
     int64_t n_mapped_touch = 0;     // touching near entries of ball leaves (singular rule)
+    int64_t n_mapped_pairs = 0;     // of which computed (a pair and its mirror once)
 
     // BtV (Algorithm 3), built when the plan options ask for it.
     int boundary = 0;

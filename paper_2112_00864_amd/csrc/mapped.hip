@@ -227,11 +227,51 @@ __device__ double regular_part(const double *lo_t, const double *lo_s, double a,
     return sum;
 }
 
-// Touching entries of mapped leaves: one block per listed entry (its index and target leaf); the
-// source comes from the entry's column. Equal sides: the singular rule; sides in ratio 2: the larger
-// cube's 8 children against the smaller one, by the singular rule where they touch and the tensor
-// rule elsewhere. Geometry: lower corners and sides of the leaves in the forest's reference frame
-// (mesh m in [4m, 4m + 1) x [0,1)^2); the map acts on the mesh's own reference cube.
+// This thread's share of the singular rule for the touching cubes (lower corner, side) t and s of one
+// mesh's reference cube, without the factor a^6 / (4 pi) (a the smaller side, returned): equal sides,
+// the rule above; sides in ratio 2, the larger cube's 8 children against the smaller one, by the rule
+// where they touch and the tensor rule elsewhere.
+__device__ double pair_part(const double *lt, double at, const double *ls, double as, const SingRule &R, int tid,
+                            int nthreads, double *a_small)
+{
+    double sum = 0.0;
+    if (at == as) {
+        *a_small = at;
+        return touch_same_part(lt, ls, at, R, tid, nthreads);
+    }
+    const bool big_t = at > as;
+    const double a = big_t ? as : at;
+    *a_small = a;
+    const double *lb = big_t ? lt : ls, *lm = big_t ? ls : lt;
+    for (int c = 0; c < 8; ++c) {
+        const double lc[3] = {lb[0] + a * (c & 1), lb[1] + a * ((c >> 1) & 1), lb[2] + a * ((c >> 2) & 1)};
+        bool touch = true;
+        for (int i = 0; i < 3; ++i) touch = touch && fmax(lc[i], lm[i]) <= fmin(lc[i] + a, lm[i] + a);
+        const double *pt = big_t ? lc : lm, *ps = big_t ? lm : lc;
+        sum += touch ? touch_same_part(pt, ps, a, R, tid, nthreads) : regular_part(pt, ps, a, R, tid, nthreads);
+    }
+    return sum;
+}
+
+// Sum of the block's shares (256 threads), times a^6 / (4 pi), in thread 0.
+__device__ double block_entry(double part, double a, double *red)
+{
+    red[threadIdx.x] = part;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    const double a3 = a * a * a;
+    const double v = red[0] * a3 * a3 * kInv4PiM;
+    __syncthreads();
+    return v;
+}
+
+// Touching entries of mapped leaves: one block per listed entry (its index, target leaf and the
+// index of its mirror (s, t) or -1, written with the same value: the rule is symmetric); the source
+// comes from the entry's column. Geometry: lower corners and sides of the leaves in the forest's
+// reference frame (mesh m in [4m, 4m + 1) x [0,1)^2); the map acts on the mesh's own reference cube.
 __global__ __launch_bounds__(256) void ball_touch_kernel(int64_t n, const int64_t *__restrict__ entry,
                                                          const int32_t *__restrict__ target,
                                                          const int64_t *__restrict__ mirror,
@@ -246,36 +286,45 @@ __global__ __launch_bounds__(256) void ball_touch_kernel(int64_t n, const int64_
         const double4 gt = geom[t], gs = geom[s];
         const double shift = 4.0 * floor(gt.x * 0.25);  // the mesh's offset along x
         const double lt[3] = {gt.x - shift, gt.y, gt.z}, ls[3] = {gs.x - shift, gs.y, gs.z};
-        double sum = 0.0, a;
-        if (gt.w == gs.w) {
-            a = gt.w;
-            sum = touch_same_part(lt, ls, a, R, threadIdx.x, blockDim.x);
-        } else {
-            const bool big_t = gt.w > gs.w;
-            a = big_t ? gs.w : gt.w;
-            const double *lb = big_t ? lt : ls, *lm = big_t ? ls : lt;
-            for (int c = 0; c < 8; ++c) {
-                const double lc[3] = {lb[0] + a * (c & 1), lb[1] + a * ((c >> 1) & 1), lb[2] + a * ((c >> 2) & 1)};
-                bool touch = true;
-                for (int i = 0; i < 3; ++i) touch = touch && fmax(lc[i], lm[i]) <= fmin(lc[i] + a, lm[i] + a);
-                const double *pt = big_t ? lc : lm, *ps = big_t ? lm : lc;
-                sum += touch ? touch_same_part(pt, ps, a, R, threadIdx.x, blockDim.x)
-                             : regular_part(pt, ps, a, R, threadIdx.x, blockDim.x);
-            }
-        }
-        red[threadIdx.x] = sum;
-        __syncthreads();
-        for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-            if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-            __syncthreads();
-        }
+        double a;
+        const double part = pair_part(lt, gt.w, ls, gs.w, R, threadIdx.x, blockDim.x, &a);
+        const double v = block_entry(part, a, red);
         if (threadIdx.x == 0) {
-            const double a3 = a * a * a;
-            val[e] = red[0] * a3 * a3 * kInv4PiM;
-            if (mirror[k] >= 0) val[mirror[k]] = val[e];  // (s, t): the rule is symmetric
+            val[e] = v;
+            if (mirror[k] >= 0) val[mirror[k]] = v;
         }
-        __syncthreads();
     }
+}
+
+// The same rule on explicit pairs: pair k is the cube (gt[k].xyz, gt[k].w) against (gs[k].xyz,
+// gs[k].w) of the reference cube [0,1]^3.
+__global__ __launch_bounds__(256) void ball_pair_kernel(int64_t n, const double4 *__restrict__ gt,
+                                                        const double4 *__restrict__ gs, SingRule R,
+                                                        double *__restrict__ out)
+{
+    __shared__ double red[256];
+    for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
+        const double4 t = gt[k], s = gs[k];
+        const double lt[3] = {t.x, t.y, t.z}, ls[3] = {s.x, s.y, s.z};
+        double a;
+        const double part = pair_part(lt, t.w, ls, s.w, R, threadIdx.x, blockDim.x, &a);
+        const double v = block_entry(part, a, red);
+        if (threadIdx.x == 0) out[k] = v;
+    }
+}
+
+SingRule make_rule(const int orders[5])
+{
+    SingRule R{};
+    for (int k = 0; k < 5; ++k)
+        BCV_REQUIRE(orders[k] >= 1 && orders[k] <= kRuleMax, BCV_EINVAL, "singular-rule orders: 1..8");
+    R.nl = orders[0], R.nm = orders[1], R.nz = orders[2], R.ns = orders[3], R.nr = orders[4];
+    gauss_legendre01(R.nl, R.xl, R.wl);
+    gauss_legendre01(R.nm, R.xm, R.wm);
+    gauss_legendre01(R.nz, R.xz, R.wz);
+    gauss_legendre01(R.ns, R.xs, R.ws);
+    gauss_legendre01(R.nr, R.xr, R.wr);
+    return R;
 }
 
 // ---- P2M and evaluation from the leaves' moment rows -------------------------------------------
@@ -733,15 +782,7 @@ void launch_mapped_assemble(const bcv_plan_s &p, const std::vector<int64_t> &tou
         touch_copy_kernel<<<cblocks, 256>>>(n, d_list, d_vals, p.d_val, 1);
         check_launch();
     } else {
-        SingRule R{};
-        for (int k = 0; k < 5; ++k)
-            BCV_REQUIRE(rule_orders[k] >= 1 && rule_orders[k] <= kRuleMax, BCV_EINVAL, "singular-rule orders: 1..8");
-        R.nl = rule_orders[0], R.nm = rule_orders[1], R.nz = rule_orders[2], R.ns = rule_orders[3], R.nr = rule_orders[4];
-        gauss_legendre01(R.nl, R.xl, R.wl);
-        gauss_legendre01(R.nm, R.xm, R.wm);
-        gauss_legendre01(R.nz, R.xz, R.wz);
-        gauss_legendre01(R.ns, R.xs, R.ws);
-        gauss_legendre01(R.nr, R.xr, R.wr);
+        const SingRule R = make_rule(rule_orders);
         const int64_t nw = (int64_t)work_entry.size();
         int64_t *d_e = nullptr, *d_m = nullptr;
         int32_t *d_t = nullptr;
@@ -765,6 +806,24 @@ void launch_mapped_assemble(const bcv_plan_s &p, const std::vector<int64_t> &tou
     BCV_HIP(hipDeviceSynchronize());
     BCV_HIP(hipFree(d_list));
     BCV_HIP(hipFree(d_vals));
+}
+
+// The singular rule of `orders` on explicit pairs (host arrays of 4 doubles per cube: lower corner in
+// the reference cube [0,1]^3 and side); results into out (host). Synchronous.
+void mapped_rule_values(int64_t n, const double *geom_t, const double *geom_s, const int orders[5], double *out)
+{
+    if (n <= 0) return;
+    const SingRule R = make_rule(orders);
+    double *d = nullptr;
+    BCV_HIP(hipMalloc(&d, (size_t)n * 9 * sizeof(double)));
+    double *dt = d, *ds = d + 4 * n, *dv = d + 8 * n;
+    BCV_HIP(hipMemcpy(dt, geom_t, (size_t)n * 4 * sizeof(double), hipMemcpyHostToDevice));
+    BCV_HIP(hipMemcpy(ds, geom_s, (size_t)n * 4 * sizeof(double), hipMemcpyHostToDevice));
+    ball_pair_kernel<<<(unsigned)std::min<int64_t>(n, 1 << 20), 256>>>(n, reinterpret_cast<const double4 *>(dt),
+                                                                      reinterpret_cast<const double4 *>(ds), R, dv);
+    check_launch();
+    BCV_HIP(hipMemcpy(out, dv, (size_t)n * sizeof(double), hipMemcpyDeviceToHost));
+    BCV_HIP(hipFree(d));
 }
 
 }  // namespace bcv

@@ -301,11 +301,6 @@ struct M2LPlan {
 // than 256 at h = 1/128 and 1/256; shorter pieces add partial sums and gathering first slots). With
 // level-dependent orders each level is its own launch, and 256 measured faster (4% in FP64); so
 // did small meshes, whose few tasks need the shorter pieces to fill the GPU.
-// Orders of the singular rule for touching mapped cells (lambda, mu, z, s, r; see mapped.hip): within
-// about 1.3e-6 relative of the same rule at orders (8, 12, 8, 8, 8) on ball cells of side 1/16, at
-// 1.8M kernel evaluations per leaf of a uniform region.
-constexpr int kMappedRule[5] = {5, 7, 5, 3, 4};
-
 constexpr int kDefaultMaxSlots = 320;
 constexpr int kDefaultMaxSlotsSchedule = 256;
 
@@ -1066,6 +1061,7 @@ void setup_mapped(bcv_plan_s *p, const bcv_tree_s &t, const std::vector<Grid> &g
                 mt.work_mirror.push_back(m);
             }
     p->n_mapped_touch = (int64_t)mt.entry.size();
+    p->n_mapped_pairs = (int64_t)mt.work_entry.size();
     if (direct) return;
     // interaction lists of the ball cells of levels >= 2 (cell order), CSR; the cells of cube meshes
     // take the lattice interaction plan
@@ -1443,9 +1439,10 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         launch_near_assemble(*p, nullptr);
         BCV_HIP(hipDeviceSynchronize());
         if (opts.near_order == 1) launch_near_assemble_ordered(*p, ordered_entry, ordered_target, near_order);
-        if (p->mapped)
+        if (p->mapped) {
             launch_mapped_assemble(*p, mapped_touch.entry, mapped_touch.work_entry, mapped_touch.work_target,
                                    mapped_touch.work_mirror, kMappedRule, t.mapped_touch_cache[opts.direct != 0]);
+        }
         if (p->precision != BCV_FP64) {  // the apply reads FP32 entries (touching pairs stay exact)
             p->d_val32 = alloc_zero<float>(p.get(), (size_t)p->n_near);
             launch_near_narrow(*p, nullptr);

@@ -1,5 +1,6 @@
 """Mapped (cube-to-ball) meshes on the GPU against the mapped-mesh oracle (oracle/mapped.py).
 
+* the singular rule for touching curved cells on explicit pairs against the oracle's;
 * direct mode (every pair near) against O1 on the ball, FP64: the mapped point rule and the singular
   rule for touching curved cells, entry by entry through the sums;
 * the FMM against O2 on the ball (q = 4, 6, 8), FP64, and the mixed path;
@@ -51,6 +52,34 @@ def ball3():
 
     mm = mapped.MappedMesh(BCMesh(3), "ball")
     return mm
+
+
+def test_rule_on_explicit_pairs_matches_oracle():
+    """The planner's singular rule on explicit pairs (bcv_mapped_pair_entries) against the oracle's
+    rule (the same published method at the same orders, written separately), 6 pairs of each of the
+    7 touching classes of the h = 1/16 ball mesh; and its argument checks."""
+    from oracle import mapped
+    from oracle.direct import leaf_geometry, touching_class_index
+    from oracle.mesh import BCMesh
+
+    mm = mapped.MappedMesh(BCMesh(4), "ball")
+    lo_int, size, _, _ = leaf_geometry(mm.leaves, 4)
+    n = len(mm.leaves)
+    rng = np.random.default_rng(3)
+    ti, si = rng.integers(0, n, 400000), rng.integers(0, n, 400000)
+    cls = touching_class_index(lo_int[ti], size[ti], lo_int[si], size[si])
+    sel = np.concatenate([rng.choice(np.nonzero(cls == c)[0], 6, replace=False) for c in range(7)])
+    gt = np.concatenate([mm.lo[ti[sel]], mm.a[ti[sel], None]], axis=1)
+    gs = np.concatenate([mm.lo[si[sel]], mm.a[si[sel], None]], axis=1)
+    ours = bcv.mapped_pair_entries(gt, gs)
+    ref = mapped.touch_entries(mm, ti[sel], si[sel])
+    err = float(np.max(np.abs(ours / ref - 1)))
+    announce("explicit pairs: library rule vs oracle rule, 42 pairs of 7 classes: max rel %.2e" % err)
+    assert err <= 1e-12
+    for bad_s in ([0.5, 0.5, 0.5, 0.0625], [0.0, 0.0, 0.0, 0.3], [0.03, 0.0, 0.0, 0.0625]):  # apart, side, corner
+        with pytest.raises(bcv.BCVError) as e:
+            bcv.mapped_pair_entries([[0.0, 0.0, 0.0, 0.0625]], [bad_s])
+        assert e.value.status == bcv.bcv.EINVAL
 
 
 @pytest.mark.parametrize("L", [2, 3])
