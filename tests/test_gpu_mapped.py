@@ -210,3 +210,45 @@ def test_forest_of_cubes_and_balls_against_O2():
         worst32 = max(worst32, float(np.max(np.abs(u32[sel][sample] - ref) / np.abs(ref))))
     announce("forest vs O2: FP64 max rel %.3e, mixed max rel %.3e" % (worst64, worst32))
     assert worst64 <= 1e-10 and worst32 <= 1e-5
+
+
+def test_graph_and_batched_calls_on_a_forest_with_balls():
+    """A cube/ball forest: every replay of the captured apply equals the eager apply bit for bit (with
+    other eager work between replays), and bcv_vtv_apply_batched over separate ball and cube plans
+    equals their applies one by one."""
+    import torch
+
+    Ls = [3, 4, 3, 4]
+    geoms = [bcv.GEOM_BALL, bcv.GEOM_BOX, bcv.GEOM_BOX, bcv.GEOM_BALL]
+    forest = bcv.build_bc_forest(Ls, geometry=geoms)
+    f = synth.leaf_density(forest.leaves().astype(np.int64), seed=6)
+    plan = bcv.plan_interactions(forest, q=6, nearfield=bcv.NEAR_ASSEMBLED, precision=bcv.MIXED_F32)
+    fd = torch.tensor(f, device="cuda:0")
+    ud = torch.full_like(fd, float("nan"))
+    ref = torch.empty_like(fd)
+    bcv.vtv_apply(plan, fd, ref)
+    torch.cuda.synchronize()
+    graph = bcv.vtv_graph_create(plan, fd, ud)
+    other = bcv.plan_interactions(ball_tree(2), q=4, nearfield=bcv.NEAR_ASSEMBLED)
+    fo = torch.ones(other.n_leaves, dtype=torch.float64, device="cuda:0")
+    uo = torch.empty_like(fo)
+    for rep in range(3):
+        ud.fill_(float("nan"))
+        graph.launch()
+        torch.cuda.synchronize()
+        diff = float(torch.max(torch.abs(ud - ref)).item())
+        announce("cube/ball forest, replay %d: max |graph - eager| %.3e" % (rep, diff))
+        assert diff == 0.0
+        bcv.vtv_apply(other, fo, uo)
+        torch.cuda.synchronize()
+    trees = [ball_tree(3), bcv.build_bc_tree(3), ball_tree(4)]
+    plans = [bcv.plan_interactions(t, q=6, nearfield=bcv.NEAR_ASSEMBLED) for t in trees]
+    fs = [torch.tensor(density(t, seed=k), device="cuda:0") for k, t in enumerate(trees)]
+    us = [torch.full_like(x, float("nan")) for x in fs]
+    bcv.vtv_apply_batched(plans, fs, us)
+    torch.cuda.synchronize()
+    for p_, f_, u_ in zip(plans, fs, us):
+        one = torch.empty_like(f_)
+        bcv.vtv_apply(p_, f_, one)
+        torch.cuda.synchronize()
+        assert float(torch.max(torch.abs(u_ - one)).item()) == 0.0
