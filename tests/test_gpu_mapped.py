@@ -252,3 +252,29 @@ def test_graph_and_batched_calls_on_a_forest_with_balls():
         bcv.vtv_apply(p_, f_, one)
         torch.cuda.synchronize()
         assert float(torch.max(torch.abs(u_ - one)).item()) == 0.0
+
+
+def test_scaled_ball_and_neighbour_marking():
+    """The ball inscribed in the cube lo + s [0,1]^3 gives s^5 times the unit ball's potentials; a ball
+    mesh refined by the neighbour marking rule against O2 of the same mesh."""
+    from oracle import mapped
+    from oracle.mesh import BCMesh
+
+    t1 = ball_tree(3)
+    f = density(t1, seed=8)
+    u1 = gpu_apply(bcv.plan_interactions(t1, q=6, nearfield=bcv.NEAR_ASSEMBLED), f)
+    s, lo = 0.37, (-1.3, 0.25, 2.0)
+    ts = bcv.build_bc_tree(3, lo=lo, hi=tuple(x + s for x in lo), geometry=bcv.GEOM_BALL)
+    us = gpu_apply(bcv.plan_interactions(ts, q=6, nearfield=bcv.NEAR_ASSEMBLED), f)
+    err = float(np.max(np.abs(us - s ** 5 * u1) / np.abs(s ** 5 * u1)))
+    announce("ball of side %.2f against s^5 x unit ball: max rel %.2e" % (s, err))
+    assert err <= 1e-13
+    tm = bcv.build_bc_tree(4, marking=bcv.MARK_NEIGHBOR, geometry=bcv.GEOM_BALL)
+    fm = density(tm, seed=9)
+    um = gpu_apply(bcv.plan_interactions(tm, q=6, nearfield=bcv.NEAR_ASSEMBLED), fm)
+    n = len(fm)
+    sample = np.unique(np.concatenate([[0, n - 1], np.random.default_rng(12).choice(n, 6, replace=False)]))
+    ref = mapped.MappedFMM(mapped.MappedMesh(BCMesh(4, marking=1), "ball"), 6).apply_sampled(fm, sample)
+    em = float(np.max(np.abs(um[sample] - ref) / np.abs(ref)))
+    announce("ball h=1/16, neighbour marking (%d leaves) against O2 at %d leaves: max rel %.2e" % (n, len(sample), em))
+    assert em <= 1e-10
