@@ -588,19 +588,29 @@ struct PairT {
     static constexpr PairTables<Q> t{};
 };
 
+// D_g for g_z = 2 follows from harmonicity, D_{(i, j, 2)} = -D_{(i + 2, j, 0)} - D_{(i, j + 2, 0)} (both
+// of the same degree and earlier in the order); the others from the recurrence, with 1/|g| a
+// compile-time factor (a multiplication, not a division per entry).
 template <int Q, int k>
 __device__ __forceinline__ void deriv_step(double *D, const double *o, double inv_r2)
 {
     constexpr auto &pt = PairT<Q>::t;
     constexpr int n = pt.deg[k];
-    double s1 = 0.0, s2 = 0.0;
+    if constexpr (pt.e[k][2] == 2) {
+        constexpr int kx = pt.pos(pt.e[k][0] + 2, pt.e[k][1], 0), ky = pt.pos(pt.e[k][0], pt.e[k][1] + 2, 0);
+        static_assert(kx >= 0 && kx < k && ky >= 0 && ky < k, "harmonic partners come first");
+        D[k] = -D[kx] - D[ky];
+    } else {
+        double s1 = 0.0, s2 = 0.0;
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        if (pt.m1[k][ax] >= 0) s1 = fma((double)pt.e[k][ax] * o[ax], D[pt.m1[k][ax] >= 0 ? pt.m1[k][ax] : 0], s1);
-        if (pt.m2[k][ax] >= 0)
-            s2 = fma((double)(pt.e[k][ax] * (pt.e[k][ax] - 1)), D[pt.m2[k][ax] >= 0 ? pt.m2[k][ax] : 0], s2);
+        for (int ax = 0; ax < 3; ++ax) {
+            if (pt.m1[k][ax] >= 0) s1 = fma((double)pt.e[k][ax] * o[ax], D[pt.m1[k][ax] >= 0 ? pt.m1[k][ax] : 0], s1);
+            if (pt.m2[k][ax] >= 0)
+                s2 = fma((double)(pt.e[k][ax] * (pt.e[k][ax] - 1)), D[pt.m2[k][ax] >= 0 ? pt.m2[k][ax] : 0], s2);
+        }
+        constexpr double inv_n = 1.0 / n;
+        D[k] = (-(double)(2 * n - 1) * s1 - (double)(n - 1) * s2) * (inv_r2 * inv_n);
     }
-    D[k] = (-(double)(2 * n - 1) * s1 - (double)(n - 1) * s2) * (inv_r2 / (double)n);
 }
 
 template <int Q, int... Ks>
@@ -613,15 +623,16 @@ __device__ __forceinline__ void derivatives(double *D, const double *o, std::int
 }
 
 template <int Q, class T, int B, int... As>
-__device__ __forceinline__ void pair_column(T *acc, const double *D, T mb, std::integer_sequence<int, As...>)
+__device__ __forceinline__ void pair_column(T *acc, const T *D, T mb, std::integer_sequence<int, As...>)
 {
     constexpr auto &pt = PairT<Q>::t;
-    ((acc[As] = fma((T)D[pt.sum[As][B] >= 0 ? pt.sum[As][B] : 0], mb, acc[As])), ...);
+    ((acc[As] = fma(D[pt.sum[As][B] >= 0 ? pt.sum[As][B] : 0], mb, acc[As])), ...);
 }
 
-// The source's folded moments are read column by column (not held all at once).
+// The source's folded moments are read column by column (not held all at once); D: the derivatives
+// in the contraction's type (converted once per pair).
 template <int Q, class T, int... Bs>
-__device__ __forceinline__ void pair_contract(T *acc, const double *D, const T *__restrict__ m,
+__device__ __forceinline__ void pair_contract(T *acc, const T *D, const T *__restrict__ m,
                                               std::integer_sequence<int, Bs...>)
 {
     constexpr ReducedIndex<Q> ri{};
@@ -668,7 +679,10 @@ __global__ __launch_bounds__(kW) void m2l_pairs_kernel(const int32_t *__restrict
         const double o[3] = {(ct.x - cs.x) * inv_a, (ct.y - cs.y) * inv_a, (ct.z - cs.z) * inv_a};
         double D[N];
         derivatives<Q>(D, o, std::make_integer_sequence<int, N - 1>{});
-        pair_contract<Q, T>(acc, D, Mr + (int64_t)s * ldr, std::make_integer_sequence<int, R>{});
+        T Dt[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) Dt[k] = (T)D[k];
+        pair_contract<Q, T>(acc, Dt, Mr + (int64_t)s * ldr, std::make_integer_sequence<int, R>{});
     }
     pair_store<Q, T>(acc, inv_a, Lam + (int64_t)t * ldk, std::make_integer_sequence<int, K>{});
 }
