@@ -1615,13 +1615,13 @@ void launch_near(const bcv_plan_s &p, const double *f, const double *lam, int pa
         launch_near_q<Q>(p, f, lam, parts, u, st);
 }
 template <int Q, int A0, int A1, int B0, int B1, class T>
-void launch_m2l_block(const bcv_plan_s &p, const XcdRanges &ranges, const T *G, const T *Mr, hipStream_t st)
+void launch_m2l_block(const bcv_plan_s &p, const XcdRanges &ranges, const T *G, const T *Mr, hipStream_t st, size_t lds = 0)
 {
     // four waves per SIMD (128 registers) where the block fits, else two; eight (64 registers) for the
     // smallest blocks up to order 8 (the FP32 order-4 block: 17% faster than at four waves; above
     // order 8 their expansion epilogue spills at 64)
     constexpr int regs = (A1 - A0 + B1 - B0) * (int)(sizeof(T) / 4);
-    m2l_shift_kernel<Q, T, A0, A1, B0, B1, (regs > 110 ? 2 : (regs <= 50 && Q <= 8 ? 8 : 4))><<<(unsigned)p.m2l_groups, kWave, 0, st>>>(
+    m2l_shift_kernel<Q, T, A0, A1, B0, B1, (regs > 110 ? 2 : (regs <= 50 && Q <= 8 ? 8 : 4))><<<(unsigned)p.m2l_groups, kWave, lds, st>>>(
         ranges, p.d_tasks, p.d_task_targets, p.d_slot_off, p.d_slot_src, G, Mr, p.d_m2l_partial, p.d_Lam, p.R, p.K);
     check_launch();
 }
@@ -1630,34 +1630,34 @@ void launch_m2l_block(const bcv_plan_s &p, const XcdRanges &ranges, const T *G, 
 // triangle, by degree bands (n(d) = (d + 1)^2 reduced multi-indices of degree <= d); the block that
 // writes comes first.
 template <int Q>
-void launch_m2l(const bcv_plan_s &p, const double *G, const double *Mr, hipStream_t st)
+void launch_m2l(const bcv_plan_s &p, const double *G, const double *Mr, hipStream_t st, size_t lds = 0)
 {
     constexpr int R = nreduced(Q);
     XcdRanges ranges;
     for (int x = 0; x <= kXcds; ++x) ranges.begin[x] = p.xcd_begin[x];
     if constexpr (Q == 4) {
-        launch_m2l_block<Q, 0, R, 0, R>(p, ranges, G, Mr, st);     // everything: 50 doubles
+        launch_m2l_block<Q, 0, R, 0, R>(p, ranges, G, Mr, st, lds);  // everything: 50 doubles
     } else if constexpr (Q == 6) {
-        launch_m2l_block<Q, 0, R, 0, R>(p, ranges, G, Mr, st);     // everything: 98 doubles (two waves)
+        launch_m2l_block<Q, 0, R, 0, R>(p, ranges, G, Mr, st, lds);  // everything: 98 doubles (two waves)
     } else {
         static_assert(Q == 8, "orders 4, 6, 8");
-        launch_m2l_block<Q, 0, R, 0, 36>(p, ranges, G, Mr, st);    // all a, |b| <= 5 (two waves)
-        launch_m2l_block<Q, 0, 9, 36, R>(p, ranges, G, Mr, st);    // |a| <= 2, |b| >= 6
+        launch_m2l_block<Q, 0, R, 0, 36>(p, ranges, G, Mr, st, lds);  // all a, |b| <= 5 (two waves)
+        launch_m2l_block<Q, 0, 9, 36, R>(p, ranges, G, Mr, st, lds);  // |a| <= 2, |b| >= 6
     }
 }
 
 template <int Q>
-void launch_m2l(const bcv_plan_s &p, const float *G, const float *Mr, hipStream_t st)
+void launch_m2l(const bcv_plan_s &p, const float *G, const float *Mr, hipStream_t st, size_t lds = 0)
 {
     constexpr int R = nreduced(Q);
     XcdRanges ranges;
     for (int x = 0; x <= kXcds; ++x) ranges.begin[x] = p.xcd_begin[x];
     if constexpr (Q <= 6) {
-        launch_m2l_block<Q, 0, R, 0, R>(p, ranges, G, Mr, st);     // everything: 2 (Q + 1)^2 floats
+        launch_m2l_block<Q, 0, R, 0, R>(p, ranges, G, Mr, st, lds);  // everything: 2 (Q + 1)^2 floats
     } else {
         static_assert(Q == 8, "orders 4, 6, 8");
-        launch_m2l_block<Q, 0, R, 0, 16>(p, ranges, G, Mr, st);    // all a, |b| <= 3
-        launch_m2l_block<Q, 0, 25, 16, R>(p, ranges, G, Mr, st);   // |a| <= 4, |b| >= 4
+        launch_m2l_block<Q, 0, R, 0, 16>(p, ranges, G, Mr, st, lds);  // all a, |b| <= 3
+        launch_m2l_block<Q, 0, 25, 16, R>(p, ranges, G, Mr, st, lds);  // |a| <= 4, |b| >= 4
     }
 }
 
@@ -1842,8 +1842,9 @@ void upward_pass(const bcv_plan_s &p, hipStream_t st, const double *f_fused = nu
 
 // matrix_cores: the VtV apply of a BCV_MIXED_SPLIT16 plan (which ran fmax_partial_kernel over f);
 // the BtV and VtB applies of such a plan take the FP32 lane-shift kernels.
+// lds: bytes of (unused) LDS each lane-shifting interaction block reserves, to cap how many share a CU.
 template <int Q>
-void interaction_phase(const bcv_plan_s &p, hipStream_t st, bool matrix_cores = false)
+void interaction_phase(const bcv_plan_s &p, hipStream_t st, bool matrix_cores = false, size_t lds = 0)
 {
     if (p.n_tasks == 0) return;
     // the folded moment rows were written with the moments (P2M, boundary P2M, M2M)
@@ -1863,9 +1864,9 @@ void interaction_phase(const bcv_plan_s &p, hipStream_t st, bool matrix_cores = 
                     launch_m2l_level<QL, double>(p, lev, p.d_G, p.d_Mr, st);
             });
     } else if (mixed) {
-        launch_m2l<Q>(p, p.d_G32, p.d_M32, st);
+        launch_m2l<Q>(p, p.d_G32, p.d_M32, st, lds);
     } else {
-        launch_m2l<Q>(p, p.d_G, p.d_Mr, st);
+        launch_m2l<Q>(p, p.d_G, p.d_Mr, st, lds);
     }
     if (p.n_m2l_splits > 0) {
         m2l_combine_kernel<<<dim3((unsigned)p.n_m2l_splits, (unsigned)((p.K + 3) / 4)), 256, 0, st>>>(
@@ -1894,6 +1895,12 @@ void downward_pass(const bcv_plan_s &p, hipStream_t st, bool skip_last = false)
             run(std::integral_constant<int, Q>{});
     }
 }
+
+// With the near field on the side stream, every interaction block reserves this much LDS (unused),
+// so that at most 12 of them (3 waves per SIMD) share a CU and the near field's blocks find wave slots
+// beside them instead of waiting for the interaction phase to drain (measured 1.6% to 2.5% faster
+// per apply at h = 1/256 than without; 8, 10 and 14 per CU were slower).
+constexpr size_t kM2lShareLds = 13 * 1024;
 
 template <int Q>
 void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStream_t st)
@@ -1930,7 +1937,7 @@ void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStre
             BCV_HIP(hipEventRecord(p.ev_join, p.side));
         }
         marks.start(BCV_PHASE_M2L, st);
-        interaction_phase<Q>(p, st, split16);
+        interaction_phase<Q>(p, st, split16, fork ? kM2lShareLds : 0);
         marks.stop(BCV_PHASE_M2L, st);
         marks.start(BCV_PHASE_L2L, st);
         downward_pass<Q>(p, st, fork && fuse_last);
