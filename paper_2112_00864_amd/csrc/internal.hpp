@@ -248,6 +248,8 @@ struct bcv_plan_s {
     double *d_leaf_geom = nullptr;  // 4 per leaf: lower corner x, y, z and side
     int32_t *d_leaf_cell = nullptr;
     int32_t *d_cell_leaf = nullptr;  // per cell: its leaf number, -1 for a marked cell (far-field plans)
+    int32_t *d_rest_leaves = nullptr;  // the leaves above the finest level, in leaf order
+    int64_t n_rest_leaves = 0;
     int64_t *d_split = nullptr;     // per near row: first point-rule entry (touching entries come first)
     uint32_t *d_col = nullptr;      // source leaf | code << 28: code = touch class + 1 (0: not touching),
                                     // + 8 where the source is the smaller cube of a touching pair

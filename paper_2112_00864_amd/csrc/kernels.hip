@@ -178,6 +178,36 @@ struct LeafParentTable {
 template <int Q>
 __constant__ constexpr LeafParentTable<Q> kLeafParent{};
 
+// The evaluation of a parent's local expansion at its 8 leaf children, through their L2L: child c
+// (c = x + 2y + 4z, bit 0 on an axis = the lower half, tau = -1/4 there and +1/4 above) gets
+//   sum_a kappa_a Lambda_c^a = sum_a kappa_a 2^-|a| sum_{b >= a} prod_i tau_i^(b_i-a_i)/(b_i-a_i)! Lambda_P^b
+//                            = sum_b E[c][b] Lambda_P^b,
+// E[c][b] = prod_i e1[side_i][b_i], e1[side][e] = sum_{g <= e} kappa_axis(g) 2^-g tau^(e-g)/(e-g)!
+// (kappa and the shift are products over the axes; a <= b keeps |a| <= |b| <= Q, so nothing the L2L
+// truncates is lost).
+template <int Q>
+struct LeafEvalTable {
+    double E[8][ncoef(Q)];
+    constexpr LeafEvalTable() : E{}
+    {
+        constexpr MultiIndex<Q> mi{};
+        double e1[2][Q + 1] = {};
+        for (int side = 0; side < 2; ++side)
+            for (int e = 0; e <= Q; ++e)
+                for (int g = 0; g <= e; ++g) {
+                    double t = kappa_axis_ce(g);
+                    for (int k = 1; k <= e - g; ++k) t *= (side ? 0.25 : -0.25) / k;
+                    for (int k = 0; k < g; ++k) t *= 0.5;
+                    e1[side][e] += t;
+                }
+        for (int c = 0; c < 8; ++c)
+            for (int b = 0; b < ncoef(Q); ++b)
+                E[c][b] = e1[c & 1][mi.e[b][0]] * e1[(c >> 1) & 1][mi.e[b][1]] * e1[(c >> 2) & 1][mi.e[b][2]];
+    }
+};
+template <int Q>
+__constant__ constexpr LeafEvalTable<Q> kLeafEval{};
+
 // (1/4)^k / k! for k = 0..kMaxOrder (translation coefficients; the sign (-1)^k is applied by the caller).
 constexpr int kMaxOrder = 12;
 struct QuarterTable {
@@ -463,15 +493,10 @@ __global__ __launch_bounds__(kWave *tree_waves<Q>()) void m2m_kernel(int n_par, 
 }
 
 // Q: the parent's order; the children keep their first k_child coefficients (their own order).
-// kEval (parents whose children are leaves): instead of storing the children's locals, evaluate them
-// at once, u_c += a^3 sum_a kappa_a (Lambda_c^a + the parent's contribution).
-template <int Q, bool kEval = false>
+template <int Q>
 __global__ __launch_bounds__(kWave *tree_waves<Q>()) void l2l_kernel(int n_par, const int32_t *__restrict__ parents,
                                                                       double *__restrict__ Lam, int32_t ldk,
-                                                                      int32_t k_child,
-                                                                      const int32_t *__restrict__ cell_leaf = nullptr,
-                                                                      const double4 *__restrict__ geom = nullptr,
-                                                                      double *__restrict__ u = nullptr)
+                                                                      int32_t k_child)
 {
     constexpr int K = MultiIndex<Q>::K, NB = (K + kWave - 1) / kWave;
     constexpr auto &mi = Tables<Q>::mi;
@@ -538,7 +563,6 @@ __global__ __launch_bounds__(kWave *tree_waves<Q>()) void l2l_kernel(int n_par, 
     __syncthreads();
     if (active) {  // x: slots 3 + y + 2z -> child x + 2y + 4z, added to the children's locals with 2^-|a|
         double *__restrict__ dst = Lam + (int64_t)child0 * ldk;  // 8 consecutive children
-        double ev[8] = {};  // kEval: each child's partial evaluation sum over this lane's coefficients
 #pragma unroll
         for (int n = 0; n < NB; ++n) {
             const int a = lane + kWave * n;
@@ -554,32 +578,42 @@ __global__ __launch_bounds__(kWave *tree_waves<Q>()) void l2l_kernel(int n_par, 
                 }
             }
             const double sc = ldexp(1.0, -dg[n]);
-            if constexpr (kEval) {
-                const double kap = kKappa<Q>.v[a];
 #pragma unroll
-                for (int yz = 0; yz < 4; ++yz) {
-                    ev[2 * yz] = fma(kap, dst[(int64_t)(2 * yz) * ldk + a] + lo[yz] * sc, ev[2 * yz]);
-                    ev[2 * yz + 1] = fma(kap, dst[(int64_t)(2 * yz + 1) * ldk + a] + hi[yz] * sc, ev[2 * yz + 1]);
-                }
-            } else {
-#pragma unroll
-                for (int yz = 0; yz < 4; ++yz) {
-                    dst[(int64_t)(2 * yz) * ldk + a] += lo[yz] * sc;
-                    dst[(int64_t)(2 * yz + 1) * ldk + a] += hi[yz] * sc;
-                }
+            for (int yz = 0; yz < 4; ++yz) {
+                dst[(int64_t)(2 * yz) * ldk + a] += lo[yz] * sc;
+                dst[(int64_t)(2 * yz + 1) * ldk + a] += hi[yz] * sc;
             }
         }
-        if constexpr (kEval) {
+    }
+}
+
+// The last level's L2L fused with the evaluation of its children, all of them leaves of one level
+// (fixed orders): u_c += a^3 sum_a kappa_a (Lambda_c^a + the parent's L2L contribution), with the
+// parent's part through kLeafEval, so the children's locals are read but not written. One wave per
+// parent; lane l takes child l / 8 and its coefficients l % 8, l % 8 + 8, ...
+template <int Q>
+__global__ __launch_bounds__(256) void leaf_eval_kernel(int n_par, const int32_t *__restrict__ parents,
+                                                        const double *__restrict__ Lam, int32_t ldk,
+                                                        const int32_t *__restrict__ cell_leaf,
+                                                        const double4 *__restrict__ geom, double *__restrict__ u)
+{
+    constexpr int K = MultiIndex<Q>::K;
+    const int pi = (int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
+    const int lane = threadIdx.x % kWave, c = lane >> 3, j = lane & 7;
+    if (pi >= n_par) return;  // uniform per wave
+    const int32_t child = parents[2 * pi + 1] + c;  // 8 consecutive children
+    const double *__restrict__ lp = Lam + (int64_t)parents[2 * pi] * ldk;
+    const double *__restrict__ lc = Lam + (int64_t)child * ldk;
+    double s = 0.0;
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                const double v = wave_sum(ev[c]);
-                if (lane == 0) {
-                    const int32_t leaf = cell_leaf[child0 + c];
-                    const double a = geom[leaf].w;
-                    u[leaf] = fma(v, a * a * a, u[leaf]);
-                }
-            }
-        }
+    for (int b = j; b < K; b += 8) s = fma(kKappa<Q>.v[b], lc[b], fma(kLeafEval<Q>.E[c][b], lp[b], s));
+    s += __shfl_xor(s, 1, kWave);
+    s += __shfl_xor(s, 2, kWave);
+    s += __shfl_xor(s, 4, kWave);
+    if (j == 0) {
+        const int32_t leaf = cell_leaf[child];
+        const double a = geom[leaf].w;
+        u[leaf] = fma(s, a * a * a, u[leaf]);
     }
 }
 
@@ -1175,24 +1209,29 @@ __global__ __launch_bounds__(256) void eval_add_kernel(int64_t n_leaves, const d
     if (lane == 0) u[t] += s;
 }
 
-// The same for the leaves off skip_level, whose leaves the fused last L2L evaluates: one thread per
-// leaf, so that those (most of them) leave at once and the few others read their own rows.
+// The same for a list of leaves (those off the finest level, whose leaves leaf_eval_kernel
+// evaluates): 8 lanes per leaf, lane j of a group takes coefficients j, j + 8, ...
 template <int Q>
-__global__ __launch_bounds__(256) void eval_add_rest_kernel(int64_t n_leaves, const double4 *__restrict__ geom,
-                                                            const double *__restrict__ Lam,
-                                                            const int32_t *__restrict__ leaf_cell,
-                                                            double *__restrict__ u, const LevelOrders lo,
-                                                            int skip_level)
+__global__ __launch_bounds__(256) void eval_list_kernel(int64_t n, const int32_t *__restrict__ list,
+                                                        const double4 *__restrict__ geom,
+                                                        const double *__restrict__ Lam,
+                                                        const int32_t *__restrict__ leaf_cell,
+                                                        double *__restrict__ u, const LevelOrders lo)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_leaves) return;
-    const double a = geom[t].w;
-    const int lev = level_of_side(a);
-    if (lev == skip_level) return;
-    const double *__restrict__ lam = Lam + (int64_t)leaf_cell[t] * lo.ldk;
-    double s = 0.0;
-    for (int k = 0; k < lo.k[lev]; ++k) s = fma(kKappa<Q>.v[k], lam[k], s);
-    u[t] = fma(s, a * a * a, u[t]);
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+    const int j = threadIdx.x & 7;
+    const int32_t t = i < n ? list[i] : 0;
+    double s = 0.0, a = 0.0;
+    if (i < n) {
+        a = geom[t].w;
+        const int nk = lo.k[level_of_side(a)];
+        const double *__restrict__ lam = Lam + (int64_t)leaf_cell[t] * lo.ldk;
+        for (int k = j; k < nk; k += 8) s = fma(kKappa<Q>.v[k], lam[k], s);
+    }
+    s += __shfl_xor(s, 1, kWave);
+    s += __shfl_xor(s, 2, kWave);
+    s += __shfl_xor(s, 4, kWave);
+    if (i < n && j == 0) u[t] = fma(s, a * a * a, u[t]);
 }
 
 // ---- BtV (Algorithm 3): boundary moments and the near field of boundary faces --------------------
@@ -1949,18 +1988,18 @@ void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStre
         if (fuse_last) {  // the last level's L2L fused with the evaluation of its leaf children
             const int lev = p.L - 1;
             const int n_par = p.parent_begin[lev + 1] - p.parent_begin[lev];
-            l2l_kernel<Q, true><<<(unsigned)((n_par + tree_waves<Q>() - 1) / tree_waves<Q>()), kWave * tree_waves<Q>(), 0,
-                                  st>>>(n_par, p.d_parents + 2 * p.parent_begin[lev], p.d_Lam, p.K, p.K, p.d_cell_leaf,
-                                        geom, u);
+            leaf_eval_kernel<Q><<<(unsigned)((n_par + 3) / 4), 256, 0, st>>>(
+                n_par, p.d_parents + 2 * p.parent_begin[lev], p.d_Lam, p.K, p.d_cell_leaf, geom, u);
             check_launch();
         }
         if (p.q_schedule)
             eval_add_kernel<kMaxSchedQ><<<(unsigned)((p.n_leaves + 3) / 4), 256, 0, st>>>(
                 p.n_leaves, geom, p.d_Lam, p.d_leaf_cell, u, level_orders(p));
-        else if (fuse_last)
-            eval_add_rest_kernel<Q><<<(unsigned)((p.n_leaves + 255) / 256), 256, 0, st>>>(
-                p.n_leaves, geom, p.d_Lam, p.d_leaf_cell, u, level_orders(p), p.L);
-        else
+        else if (fuse_last) {
+            if (p.n_rest_leaves > 0)
+                eval_list_kernel<Q><<<(unsigned)((p.n_rest_leaves + 31) / 32), 256, 0, st>>>(
+                    p.n_rest_leaves, p.d_rest_leaves, geom, p.d_Lam, p.d_leaf_cell, u, level_orders(p));
+        } else
             eval_add_kernel<Q><<<(unsigned)((p.n_leaves + 3) / 4), 256, 0, st>>>(p.n_leaves, geom, p.d_Lam,
                                                                               p.d_leaf_cell, u, level_orders(p));
         check_launch();

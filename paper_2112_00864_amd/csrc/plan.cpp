@@ -1205,6 +1205,13 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
     }
     p->d_leaf_geom = upload(p.get(), lg);
     p->d_leaf_cell = upload(p.get(), t.leaf_cell);
+    {
+        std::vector<int32_t> rest;
+        for (int64_t l = 0; l < p->n_leaves; ++l)
+            if (t.level[t.leaf_cell[l]] != p->L) rest.push_back((int32_t)l);
+        p->n_rest_leaves = (int64_t)rest.size();
+        if (!rest.empty()) p->d_rest_leaves = upload(p.get(), rest);
+    }
     if (scaled) {
         std::vector<double> us(p->n_leaves);
         for (int64_t l = 0; l < p->n_leaves; ++l) {
@@ -1467,7 +1474,7 @@ void destroy_plan(bcv_plan_s *p)
     if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
     if (p->ev_join) (void)hipEventDestroy(p->ev_join);
     if (p->side) (void)hipStreamDestroy(p->side);
-    void *bufs[] = {p->d_leaf_geom, p->d_leaf_cell, p->d_cell_leaf, p->d_split, p->d_col, p->d_val, p->d_val32, p->d_units,
+    void *bufs[] = {p->d_leaf_geom, p->d_leaf_cell, p->d_cell_leaf, p->d_rest_leaves, p->d_split, p->d_col, p->d_val, p->d_val32, p->d_units,
                     p->d_splits, p->d_partial, p->d_M, p->d_Lam, p->d_G,
                     p->d_M32, p->d_Mr, p->d_G32,
                     p->d_parents, p->d_tasks, p->d_task_targets, p->d_slot_off, p->d_slot_src,
