@@ -308,33 +308,53 @@ __device__ __forceinline__ double near_entry(uint32_t code, const double4 gt, co
     return point_rule(gt, gs);
 }
 
+// Lane k's value, in every lane (k wave-uniform).
+__device__ __forceinline__ int lane_value(int v, int k) { return __builtin_amdgcn_readlane(v, k); }
+__device__ __forceinline__ double lane_value(double v, int k)
+{
+    const int64_t b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)b, k), hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+    return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
 // ---- P2M: M^b = f a^3 kappa_b on every leaf, and the folded row Mr = f a^3 fold(kappa) ------------
 // Q: the largest order of any level; a level-l leaf writes its ncoef(q_l) and (q_l + 1)^2 leading
 // coefficients (the tables are graded, so those are the order-q_l tables).
 // Leaves of level skip_level write only their folded rows (their parents' moments come from
-// m2m_leaves_kernel); -1 = none. One thread per (leaf, j), j < ldr: it writes folded coefficient j
-// and full coefficients j, j + ldr, ... of its leaf, so a row's stores are contiguous.
+// m2m_leaves_kernel); -1 = none. One wave per 64 consecutive leaves: lane l reads leaf l's density,
+// side and cell, then the wave writes the leaves' rows one after the other, lanes over coefficients.
 template <int Q, class TR>
 __global__ __launch_bounds__(256) void p2m_kernel(int64_t n_leaves, const int32_t *__restrict__ leaf_cell,
                                                   const double4 *__restrict__ geom, const double *__restrict__ f,
                                                   double *__restrict__ M, TR *__restrict__ Mr, const LevelOrders lo,
                                                   int skip_level)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t leaf = idx / lo.ldr;
-    const int j = (int)(idx - leaf * lo.ldr);
-    if (leaf >= n_leaves) return;
-    const double a = geom[leaf].w;
-    const int lev = level_of_side(a);
-    const double s = f[leaf] * (a * a * a);
-    const int64_t c = leaf_cell[leaf];
-    if (j < lo.r[lev]) Mr[c * lo.ldr + j] = (TR)(s * kFoldedKappa<Q>.v[j]);
-    if (lev != skip_level)
-        for (int b = j; b < lo.k[lev]; b += lo.ldr) M[c * lo.ldk + b] = s * kKappa<Q>.v[b];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t base = ((int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * kWave;
+    if (base >= n_leaves) return;  // uniform per wave
+    const int cnt = (int)min((int64_t)kWave, n_leaves - base);
+    double sl = 0.0;
+    int cl = 0, levl = 0;
+    if (lane < cnt) {
+        const double a = geom[base + lane].w;
+        levl = level_of_side(a);
+        sl = f[base + lane] * (a * a * a);
+        cl = leaf_cell[base + lane];
+    }
+    for (int k = 0; k < cnt; ++k) {
+        const double sk = lane_value(sl, k);
+        const int64_t c = lane_value(cl, k);
+        const int lev = lane_value(levl, k);
+        for (int j = lane; j < lo.r[lev]; j += kWave) Mr[c * lo.ldr + j] = (TR)(sk * kFoldedKappa<Q>.v[j]);
+        if (lev != skip_level)
+            for (int b = lane; b < lo.k[lev]; b += kWave) M[c * lo.ldk + b] = sk * kKappa<Q>.v[b];
+    }
 }
 
-// M2M for parents whose 8 children are leaves, straight from the children's densities (one wave
-// per parent; see LeafParentTable).
+// M2M for parents whose 8 children are leaves, straight from the children's densities (see
+// LeafParentTable). One wave per 64 parents: lane l gathers parent l's 8 densities, then the wave
+// writes the parents' rows one after the other, lanes over coefficients (each lane keeps the table
+// entries of its coefficients in registers).
 template <int Q, class TR>
 __global__ __launch_bounds__(256) void m2m_leaves_kernel(int n_par, const int32_t *__restrict__ parents,
                                                          const int32_t *__restrict__ cell_leaf,
@@ -342,31 +362,54 @@ __global__ __launch_bounds__(256) void m2m_leaves_kernel(int n_par, const int32_
                                                          const double *__restrict__ f, double *__restrict__ M,
                                                          TR *__restrict__ Mr, int32_t ldk, int32_t ldr)
 {
-    constexpr int K = MultiIndex<Q>::K, R = nreduced(Q);
-    const int pi = (int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
+    constexpr int K = MultiIndex<Q>::K, R = nreduced(Q), NK = (K + kWave - 1) / kWave, NR = (R + kWave - 1) / kWave;
     const int lane = threadIdx.x % kWave;
-    if (pi >= n_par) return;
-    const int32_t cell = parents[2 * pi], child0 = parents[2 * pi + 1];
-    double fc[8];
-    double a = 0.0;
+    const int base = (int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * kWave;
+    if (base >= n_par) return;  // uniform per wave
+    const int cnt = min(kWave, n_par - base);
+    double fl[8] = {}, a3l = 0.0;
+    int celll = 0;
+    if (lane < cnt) {
+        celll = parents[2 * (base + lane)];
+        const int32_t child0 = parents[2 * (base + lane) + 1];
+        double a = 0.0;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const int32_t leaf = cell_leaf[child0 + c];
-        fc[c] = f[leaf];
-        a = geom[leaf].w;
+        for (int c = 0; c < 8; ++c) {
+            const int32_t leaf = cell_leaf[child0 + c];
+            fl[c] = f[leaf];
+            a = geom[leaf].w;
+        }
+        a3l = a * a * a;
     }
-    const double a3 = a * a * a;
-    for (int b = lane; b < K; b += kWave) {
-        double v = 0.0;
+    double w[NK][8], wr[NR][8];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) v = fma(fc[c], kLeafParent<Q>.W[c][b], v);
-        M[(int64_t)cell * ldk + b] = v * a3;
-    }
-    for (int r = lane; r < R; r += kWave) {
-        double v = 0.0;
+    for (int n = 0; n < NK; ++n)
 #pragma unroll
-        for (int c = 0; c < 8; ++c) v = fma(fc[c], kLeafParent<Q>.Wr[c][r], v);
-        Mr[(int64_t)cell * ldr + r] = (TR)(v * a3);
+        for (int c = 0; c < 8; ++c) w[n][c] = lane + kWave * n < K ? kLeafParent<Q>.W[c][lane + kWave * n] : 0.0;
+#pragma unroll
+    for (int n = 0; n < NR; ++n)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) wr[n][c] = lane + kWave * n < R ? kLeafParent<Q>.Wr[c][lane + kWave * n] : 0.0;
+    for (int k = 0; k < cnt; ++k) {
+        double fc[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) fc[c] = lane_value(fl[c], k);
+        const double a3 = lane_value(a3l, k);
+        const int64_t cell = lane_value(celll, k);
+#pragma unroll
+        for (int n = 0; n < NK; ++n) {
+            double v = 0.0;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) v = fma(fc[c], w[n][c], v);
+            if (lane + kWave * n < K) M[cell * ldk + lane + kWave * n] = v * a3;
+        }
+#pragma unroll
+        for (int n = 0; n < NR; ++n) {
+            double v = 0.0;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) v = fma(fc[c], wr[n][c], v);
+            if (lane + kWave * n < R) Mr[cell * ldr + lane + kWave * n] = (TR)(v * a3);
+        }
     }
 }
 
@@ -1820,7 +1863,7 @@ void launch_p2m(const bcv_plan_s &p, const double *f, hipStream_t st, bool fused
 {
     const int skip = fused && !p.q_schedule ? p.L : -1;
     const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
-    const unsigned blocks = (unsigned)((p.n_leaves * (int64_t)p.R + 255) / 256);
+    const unsigned blocks = (unsigned)((p.n_leaves + 255) / 256);  // 64 leaves per wave
     const LevelOrders lo = level_orders(p);
     constexpr int QT = Q > kMaxSchedQ ? Q : kMaxSchedQ;  // tables large enough for every level's order
     if (p.precision != BCV_FP64) {
@@ -1850,7 +1893,7 @@ void upward_pass(const bcv_plan_s &p, hipStream_t st, const double *f_fused = nu
         if (n_par == 0) continue;
         if (f_fused != nullptr && !p.q_schedule && lev == p.L - 1) {  // every child is a level-L leaf
             const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
-            const unsigned blocks = (unsigned)((n_par + 3) / 4);
+            const unsigned blocks = (unsigned)((n_par + 255) / 256);  // 64 parents per wave
             const int32_t *par = p.d_parents + 2 * p.parent_begin[lev];
             if (p.precision != BCV_FP64)
                 m2m_leaves_kernel<Q, float><<<blocks, 256, 0, st>>>(n_par, par, p.d_cell_leaf, geom, f_fused, p.d_M,
