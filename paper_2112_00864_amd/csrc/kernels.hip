@@ -466,7 +466,16 @@ __global__ __launch_bounds__(kWave *tree_waves<Q>()) void m2m_kernel(int n_par, 
     if (active) {
         cell = parents[2 * pi];
         const double *__restrict__ src = M + (int64_t)parents[2 * pi + 1] * ldk;  // 8 consecutive children
-        for (int n = lane; n < 8 * K; n += kWave) B[n / K][n % K] = src[(int64_t)(n / K) * ldk + n % K];
+        constexpr int NL = (8 * K + kWave - 1) / kWave;
+        double v[NL];  // every load issued before the first LDS store
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int n = lane + kWave * i;
+            v[i] = n < 8 * K ? src[(int64_t)(n / K) * ldk + n % K] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < NL; ++i)
+            if (lane + kWave * i < 8 * K) B[(lane + kWave * i) / K][(lane + kWave * i) % K] = v[i];
     }
     __syncthreads();
     // x: children (0,y,z) + (1,y,z) -> 4 vectors indexed by y + 2z (lower child: -tau = +1/4)
@@ -560,9 +569,16 @@ __global__ __launch_bounds__(kWave *tree_waves<Q>()) void l2l_kernel(int n_par, 
         dg[n] = ex[n] + ey[n] + ez[n];
     }
     int32_t child0 = 0;
+    double old[NB][8];  // the children's own locals, read while the passes run
     if (active) {
         child0 = parents[2 * pi + 1];
         const double *__restrict__ src = Lam + (int64_t)parents[2 * pi] * ldk;
+        const double *__restrict__ dst = Lam + (int64_t)child0 * ldk;  // 8 consecutive children
+#pragma unroll
+        for (int n = 0; n < NB; ++n)
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                old[n][c] = lane + kWave * n < k_child ? dst[(int64_t)c * ldk + lane + kWave * n] : 0.0;
         for (int n = lane; n < K; n += kWave) B[0][n] = src[n];
     }
     __syncthreads();
@@ -623,8 +639,8 @@ __global__ __launch_bounds__(kWave *tree_waves<Q>()) void l2l_kernel(int n_par, 
             const double sc = ldexp(1.0, -dg[n]);
 #pragma unroll
             for (int yz = 0; yz < 4; ++yz) {
-                dst[(int64_t)(2 * yz) * ldk + a] += lo[yz] * sc;
-                dst[(int64_t)(2 * yz + 1) * ldk + a] += hi[yz] * sc;
+                dst[(int64_t)(2 * yz) * ldk + a] = fma(lo[yz], sc, old[n][2 * yz]);
+                dst[(int64_t)(2 * yz + 1) * ldk + a] = fma(hi[yz], sc, old[n][2 * yz + 1]);
             }
         }
     }
