@@ -649,30 +649,45 @@ __global__ __launch_bounds__(kWave *tree_waves<Q>()) void l2l_kernel(int n_par, 
 // The last level's L2L fused with the evaluation of its children, all of them leaves of one level
 // (fixed orders): u_c += a^3 sum_a kappa_a (Lambda_c^a + the parent's L2L contribution), with the
 // parent's part through kLeafEval, so the children's locals are read but not written. One wave per
-// parent; lane l takes child l / 8 and its coefficients l % 8, l % 8 + 8, ...
+// kLeafEvalPar consecutive parents, one after the other; lane l takes child l / 8 and its coefficients
+// l % 8 + 8 i, whose table entries it keeps in registers.
+constexpr int kLeafEvalPar = 4;
 template <int Q>
 __global__ __launch_bounds__(256) void leaf_eval_kernel(int n_par, const int32_t *__restrict__ parents,
                                                         const double *__restrict__ Lam, int32_t ldk,
                                                         const int32_t *__restrict__ cell_leaf,
                                                         const double4 *__restrict__ geom, double *__restrict__ u)
 {
-    constexpr int K = MultiIndex<Q>::K;
-    const int pi = (int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
+    constexpr int K = MultiIndex<Q>::K, NI = (K + 7) / 8;
     const int lane = threadIdx.x % kWave, c = lane >> 3, j = lane & 7;
-    if (pi >= n_par) return;  // uniform per wave
-    const int32_t child = parents[2 * pi + 1] + c;  // 8 consecutive children
-    const double *__restrict__ lp = Lam + (int64_t)parents[2 * pi] * ldk;
-    const double *__restrict__ lc = Lam + (int64_t)child * ldk;
-    double s = 0.0;
+    const int p0 = (int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * kLeafEvalPar;
+    if (p0 >= n_par) return;  // uniform per wave
+    double ke[NI], kk[NI];
 #pragma unroll
-    for (int b = j; b < K; b += 8) s = fma(kKappa<Q>.v[b], lc[b], fma(kLeafEval<Q>.E[c][b], lp[b], s));
-    s += __shfl_xor(s, 1, kWave);
-    s += __shfl_xor(s, 2, kWave);
-    s += __shfl_xor(s, 4, kWave);
-    if (j == 0) {
-        const int32_t leaf = cell_leaf[child];
-        const double a = geom[leaf].w;
-        u[leaf] = fma(s, a * a * a, u[leaf]);
+    for (int i = 0; i < NI; ++i) {
+        const int b = j + 8 * i;
+        ke[i] = b < K ? kLeafEval<Q>.E[c][b] : 0.0;
+        kk[i] = b < K ? kKappa<Q>.v[b] : 0.0;
+    }
+    const int p1 = min(p0 + kLeafEvalPar, n_par);
+    for (int pi = p0; pi < p1; ++pi) {
+        const int32_t child = parents[2 * pi + 1] + c;  // 8 consecutive children
+        const double *__restrict__ lp = Lam + (int64_t)parents[2 * pi] * ldk;
+        const double *__restrict__ lc = Lam + (int64_t)child * ldk;
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            const int b = j + 8 * i;
+            if (b < K) s = fma(kk[i], lc[b], fma(ke[i], lp[b], s));
+        }
+        s += __shfl_xor(s, 1, kWave);
+        s += __shfl_xor(s, 2, kWave);
+        s += __shfl_xor(s, 4, kWave);
+        if (j == 0) {
+            const int32_t leaf = cell_leaf[child];
+            const double a = geom[leaf].w;
+            u[leaf] = fma(s, a * a * a, u[leaf]);
+        }
     }
 }
 
@@ -2047,7 +2062,7 @@ void apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, hipStre
         if (fuse_last) {  // the last level's L2L fused with the evaluation of its leaf children
             const int lev = p.L - 1;
             const int n_par = p.parent_begin[lev + 1] - p.parent_begin[lev];
-            leaf_eval_kernel<Q><<<(unsigned)((n_par + 3) / 4), 256, 0, st>>>(
+            leaf_eval_kernel<Q><<<(unsigned)((n_par + 4 * kLeafEvalPar - 1) / (4 * kLeafEvalPar)), 256, 0, st>>>(
                 n_par, p.d_parents + 2 * p.parent_begin[lev], p.d_Lam, p.K, p.d_cell_leaf, geom, u);
             check_launch();
         }
