@@ -329,19 +329,20 @@ SingRule make_rule(const int orders[5])
 
 // ---- P2M and evaluation from the leaves' moment rows -------------------------------------------
 // M^b = f (-1)^|b| kappa^b (full rows, FP64) and the folded row Mr = f kappar (kappar: the folded,
-// signed kappa). One thread per (leaf, j).
-template <class TR>
-__global__ __launch_bounds__(256) void mapped_p2m_kernel(int64_t n_leaves, int K, int R,
-                                                         const int32_t *__restrict__ leaf_cell,
+// signed kappa). One thread per (leaf, j); K = ncoef(Q) is a compile-time constant, so splitting the
+// thread index is a multiplication, not a 64-bit division.
+template <int Q, class TR>
+__global__ __launch_bounds__(256) void mapped_p2m_kernel(int64_t n_leaves, const int32_t *__restrict__ leaf_cell,
                                                          const double *__restrict__ kap,
                                                          const double *__restrict__ kapr,
                                                          const double *__restrict__ f, double *__restrict__ M,
                                                          TR *__restrict__ Mr, int ldk, int ldr)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_leaves * K) return;
-    const int64_t l = i / K;
-    const int j = (int)(i - l * K);
+    constexpr int K = ncoef(Q), R = (Q + 1) * (Q + 1);
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (uint64_t)n_leaves * K) return;
+    const int64_t l = (int64_t)(i / K);
+    const int j = (int)(i - (uint64_t)l * K);
     const int32_t c = leaf_cell[l];
     const double fl = f[l];
     const double v = fl * kap[i];
@@ -349,21 +350,27 @@ __global__ __launch_bounds__(256) void mapped_p2m_kernel(int64_t n_leaves, int K
     if (j < R) Mr[(int64_t)c * ldr + j] = (TR)(fl * kapr[l * R + j]);
 }
 
-// u_w += sum_a kappa_w^a Lambda_w^a. One wave per leaf.
-__global__ __launch_bounds__(256) void mapped_eval_kernel(int64_t n_leaves, int K, const int32_t *__restrict__ leaf_cell,
+// u_w += sum_a kappa_w^a Lambda_w^a. 8 lanes per leaf: lane j of a group takes a = j, j + 8, ...
+template <int Q>
+__global__ __launch_bounds__(256) void mapped_eval_kernel(int64_t n_leaves, const int32_t *__restrict__ leaf_cell,
                                                           const double *__restrict__ kap,
                                                           const double *__restrict__ Lam, int ldk,
                                                           double *__restrict__ u)
 {
-    const int lane = threadIdx.x & (kW - 1);
-    const int64_t l = (int64_t)blockIdx.x * (blockDim.x / kW) + (threadIdx.x / kW);
-    if (l >= n_leaves) return;
-    const double *lam = Lam + (int64_t)leaf_cell[l] * ldk;
-    const double *kr = kap + l * K;
+    constexpr int K = ncoef(Q);
+    const int64_t l = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+    const int j = threadIdx.x & 7;
     double s = 0.0;
-    for (int a = lane; a < K; a += kW) s = fma(kr[a], lam[a], s);
-    s = wave_sum_m(s);
-    if (lane == 0) u[l] += s;
+    if (l < n_leaves) {
+        const double *__restrict__ lam = Lam + (int64_t)leaf_cell[l] * ldk;
+        const double *__restrict__ kr = kap + l * K;
+#pragma unroll
+        for (int a = j; a < K; a += 8) s = fma(kr[a], lam[a], s);
+    }
+    s += __shfl_xor(s, 1, kW);
+    s += __shfl_xor(s, 2, kW);
+    s += __shfl_xor(s, 4, kW);
+    if (l < n_leaves && j == 0) u[l] += s;
 }
 
 // val[entry[k]] <-> vals[k] (to_val: scatter the cached values; else gather them).
@@ -470,8 +477,19 @@ __global__ __launch_bounds__(kW *kTreeWaves) void mapped_m2m_kernel(int n_par, c
     if (w >= n_par) return;  // uniform per wave; only wave-level synchronisation below
     const int32_t par = parents[2 * w], first = parents[2 * w + 1];
     const double4 cp = centre[par];
-    for (int i = lane; i < 8 * K; i += kW) sm[wv][i / K][i % K] = M[(int64_t)(first + i / K) * ldk + i % K];
-    if (lane < 24) shift_factors(pw[wv][lane / 3][lane % 3], centre[first + lane / 3], cp, lane % 3, -1.0, Q);
+    {
+        constexpr int NL = (8 * K + kW - 1) / kW;
+        double v[NL];  // every load issued before the first LDS store
+#pragma unroll
+        for (int n = 0; n < NL; ++n) {
+            const int i = lane + kW * n;
+            v[n] = i < 8 * K ? M[(int64_t)(first + i / K) * ldk + i % K] : 0.0;
+        }
+        if (lane < 24) shift_factors(pw[wv][lane / 3][lane % 3], centre[first + lane / 3], cp, lane % 3, -1.0, Q);
+#pragma unroll
+        for (int n = 0; n < NL; ++n)
+            if (lane + kW * n < 8 * K) sm[wv][(lane + kW * n) / K][(lane + kW * n) % K] = v[n];
+    }
     wave_sync();
     double acc[(K + kW - 1) / kW] = {};
     for (int c = 0; c < 8; ++c) {
@@ -514,9 +532,17 @@ __global__ __launch_bounds__(kW *kTreeWaves) void mapped_l2l_kernel(int n_par, c
     if (w >= n_par) return;
     const int32_t par = parents[2 * w], first = parents[2 * w + 1];
     const double4 cp = centre[par];
+    constexpr int NA = (K + kW - 1) / kW;
+    double old[8][NA];  // the children's own locals, read while the passes run
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int n = 0; n < NA; ++n)
+            old[c][n] = lane + kW * n < K ? Lam[(int64_t)(first + c) * ldk + lane + kW * n] : 0.0;
     for (int i = lane; i < K; i += kW) lp[wv][i] = Lam[(int64_t)par * ldk + i];
     if (lane < 24) shift_factors(pw[wv][lane / 3][lane % 3], centre[first + lane / 3], cp, lane % 3, 1.0, Q);
     wave_sync();
+#pragma unroll
     for (int c = 0; c < 8; ++c) {
         l2l_pass<Q>(lp[wv], rows[wv].r[0], pw[wv][c][2], 2, lane);
         wave_sync();
@@ -524,7 +550,10 @@ __global__ __launch_bounds__(kW *kTreeWaves) void mapped_l2l_kernel(int n_par, c
         wave_sync();
         l2l_pass<Q>(rows[wv].r[1], rows[wv].r[0], pw[wv][c][0], 0, lane);
         wave_sync();
-        for (int a = lane; a < K; a += kW) Lam[(int64_t)(first + c) * ldk + a] += rows[wv].r[0][a];
+#pragma unroll
+        for (int n = 0; n < NA; ++n)
+            if (lane + kW * n < K)
+                Lam[(int64_t)(first + c) * ldk + lane + kW * n] = old[c][n] + rows[wv].r[0][lane + kW * n];
         wave_sync();
     }
 }
@@ -692,14 +721,15 @@ void mapped_passes(const bcv_plan_s &p, const double *f, int phase, hipStream_t 
 {
     const bool mixed = p.precision != BCV_FP64;
     if (phase == 0) {  // P2M
+        if (p.K != ncoef(Q) || p.R != (Q + 1) * (Q + 1)) fail(BCV_ESTATE, "mapped P2M: row lengths");
         const int64_t n = p.n_leaves * p.K;
         const unsigned blocks = (unsigned)((n + 255) / 256);
         if (mixed)
-            mapped_p2m_kernel<float><<<blocks, 256, 0, st>>>(p.n_leaves, p.K, p.R, p.d_leaf_cell, p.d_kap, p.d_kapr, f,
-                                                             p.d_M, p.d_M32, p.K, p.R);
+            mapped_p2m_kernel<Q, float><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, p.d_kap, p.d_kapr, f,
+                                                                p.d_M, p.d_M32, p.K, p.R);
         else
-            mapped_p2m_kernel<double><<<blocks, 256, 0, st>>>(p.n_leaves, p.K, p.R, p.d_leaf_cell, p.d_kap, p.d_kapr,
-                                                              f, p.d_M, p.d_Mr, p.K, p.R);
+            mapped_p2m_kernel<Q, double><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, p.d_kap, p.d_kapr, f,
+                                                                 p.d_M, p.d_Mr, p.K, p.R);
         check_launch();
     } else if (phase == 1) {  // M2M, finest parents first
         const auto *cen = reinterpret_cast<const double4 *>(p.d_centre);
@@ -754,8 +784,13 @@ void launch_mapped_phase(const bcv_plan_s &p, const double *f, int phase, hipStr
 
 void launch_mapped_eval(const bcv_plan_s &p, double *u, hipStream_t st)
 {
-    mapped_eval_kernel<<<(unsigned)((p.n_leaves + 3) / 4), 256, 0, st>>>(p.n_leaves, p.K, p.d_leaf_cell, p.d_kap,
-                                                                        p.d_Lam, p.K, u);
+    const unsigned blocks = (unsigned)((p.n_leaves + 31) / 32);  // 8 lanes per leaf
+    switch (p.q) {
+    case 4: mapped_eval_kernel<4><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, p.d_kap, p.d_Lam, p.K, u); break;
+    case 6: mapped_eval_kernel<6><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, p.d_kap, p.d_Lam, p.K, u); break;
+    case 8: mapped_eval_kernel<8><<<blocks, 256, 0, st>>>(p.n_leaves, p.d_leaf_cell, p.d_kap, p.d_Lam, p.K, u); break;
+    default: fail(BCV_ENOTSUP, "mapped meshes: q must be 4, 6 or 8");
+    }
     check_launch();
 }
 
