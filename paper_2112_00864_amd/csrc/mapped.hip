@@ -407,45 +407,98 @@ struct PassRows {
     double r[2][ncoef(Q)];
 };
 
-// out[b] = sum_{k=0}^{Q} [the term is in range] w[k] * 2^-(b_ax - k) in[b - k e_ax]   (M2M direction)
+// The terms of a lane's passes do not depend on the child, so their positions are worked out once
+// per wave: code[ax][n][k] for the lane's n-th coefficient b = lane + 64 n, term k along axis ax, is
+// (position of the term's row entry) << 4 | (the exponent the term scales by), or -1 out of range.
 template <int Q>
-__device__ __forceinline__ void m2m_pass(const double *in, double *out, const double *w, int ax, int lane)
+struct PassCodes {
+    static constexpr int NB = (ncoef(Q) + kW - 1) / kW;
+    int code[3][NB][Q + 1];
+};
+
+// M2M: term k of b is in[b - k e_ax] times w[k] 2^-(b_ax - k), for k <= b_ax.
+template <int Q>
+__device__ __forceinline__ void m2m_codes(PassCodes<Q> &pc, int lane)
 {
     constexpr auto &mi = kMiM<Q>;
-    for (int b = lane; b < ncoef(Q); b += kW) {
-        const int e0 = mi.e[b][0], e1 = mi.e[b][1], e2 = mi.e[b][2];
-        const int bx = ax == 0 ? e0 : (ax == 1 ? e1 : e2);
-        double acc = 0.0;
 #pragma unroll
-        for (int k = 0; k <= Q; ++k) {
-            if (k <= bx) {
+    for (int n = 0; n < PassCodes<Q>::NB; ++n) {
+        const int b = lane + kW * n;
+        const int e0 = b < ncoef(Q) ? mi.e[b][0] : 0, e1 = b < ncoef(Q) ? mi.e[b][1] : 0,
+                  e2 = b < ncoef(Q) ? mi.e[b][2] : 0;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const int bx = ax == 0 ? e0 : (ax == 1 ? e1 : e2);
+#pragma unroll
+            for (int k = 0; k <= Q; ++k) {
                 const int g = bx - k;  // the source's component along ax
                 const int j = ax == 0 ? mi_index(g, e1, e2) : (ax == 1 ? mi_index(e0, g, e2) : mi_index(e0, e1, g));
-                acc = fma(w[k] * ldexp(1.0, -g), in[j], acc);
+                pc.code[ax][n][k] = b < ncoef(Q) && k <= bx ? (j << 4) | g : -1;
             }
         }
-        out[b] = acc;
     }
 }
 
-// out[a] = 2^-a_ax sum_{k=0}^{Q} [a + k e_ax in range] w[k] in[a + k e_ax]   (L2L direction)
+// L2L: term k of a is in[a + k e_ax] times w[k] (the pass then scales by 2^-a_ax), for k <= Q - |a|.
 template <int Q>
-__device__ __forceinline__ void l2l_pass(const double *in, double *out, const double *w, int ax, int lane)
+__device__ __forceinline__ void l2l_codes(PassCodes<Q> &pc, int lane)
 {
     constexpr auto &mi = kMiM<Q>;
-    for (int a = lane; a < ncoef(Q); a += kW) {
-        const int e0 = mi.e[a][0], e1 = mi.e[a][1], e2 = mi.e[a][2];
-        const int room = Q - mi.deg[a];
-        const int ea = ax == 0 ? e0 : (ax == 1 ? e1 : e2);
+#pragma unroll
+    for (int n = 0; n < PassCodes<Q>::NB; ++n) {
+        const int a = lane + kW * n;
+        const int e0 = a < ncoef(Q) ? mi.e[a][0] : 0, e1 = a < ncoef(Q) ? mi.e[a][1] : 0,
+                  e2 = a < ncoef(Q) ? mi.e[a][2] : 0;
+        const int room = Q - (e0 + e1 + e2);
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const int ea = ax == 0 ? e0 : (ax == 1 ? e1 : e2);
+#pragma unroll
+            for (int k = 0; k <= Q; ++k) {
+                const int j = ax == 0 ? mi_index(e0 + k, e1, e2) : (ax == 1 ? mi_index(e0, e1 + k, e2) : mi_index(e0, e1, e2 + k));
+                pc.code[ax][n][k] = a < ncoef(Q) && k <= room ? (j << 4) | ea : -1;
+            }
+        }
+    }
+}
+
+// out[b] = sum_k w[k] 2^-(b_ax - k) in[b - k e_ax]   (M2M direction)
+template <int Q, int AX>
+__device__ __forceinline__ void m2m_pass(const double *in, double *out, const double *w, const PassCodes<Q> &pc,
+                                         int lane)
+{
+#pragma unroll
+    for (int n = 0; n < PassCodes<Q>::NB; ++n) {
+        if (lane + kW * n >= ncoef(Q)) continue;
         double acc = 0.0;
 #pragma unroll
         for (int k = 0; k <= Q; ++k) {
-            if (k <= room) {
-                const int j = ax == 0 ? mi_index(e0 + k, e1, e2) : (ax == 1 ? mi_index(e0, e1 + k, e2) : mi_index(e0, e1, e2 + k));
-                acc = fma(w[k], in[j], acc);
+            const int code = pc.code[AX][n][k];
+            if (code >= 0) acc = fma(ldexp(w[k], -(code & 15)), in[code >> 4], acc);
+        }
+        out[lane + kW * n] = acc;
+    }
+}
+
+// out[a] = 2^-a_ax sum_k w[k] in[a + k e_ax]   (L2L direction)
+template <int Q, int AX>
+__device__ __forceinline__ void l2l_pass(const double *in, double *out, const double *w, const PassCodes<Q> &pc,
+                                         int lane)
+{
+#pragma unroll
+    for (int n = 0; n < PassCodes<Q>::NB; ++n) {
+        if (lane + kW * n >= ncoef(Q)) continue;
+        double acc = 0.0;
+        int ea = 0;
+#pragma unroll
+        for (int k = 0; k <= Q; ++k) {
+            const int code = pc.code[AX][n][k];
+            if (code >= 0) {
+                acc = fma(w[k], in[code >> 4], acc);
+                ea = code & 15;
             }
         }
-        out[a] = ldexp(acc, -ea);
+        out[lane + kW * n] = ldexp(acc, -ea);
     }
 }
 
@@ -491,13 +544,15 @@ __global__ __launch_bounds__(kW *kTreeWaves) void mapped_m2m_kernel(int n_par, c
             if (lane + kW * n < 8 * K) sm[wv][(lane + kW * n) / K][(lane + kW * n) % K] = v[n];
     }
     wave_sync();
+    PassCodes<Q> pc;
+    m2m_codes<Q>(pc, lane);
     double acc[(K + kW - 1) / kW] = {};
     for (int c = 0; c < 8; ++c) {
-        m2m_pass<Q>(sm[wv][c], rows[wv].r[0], pw[wv][c][0], 0, lane);
+        m2m_pass<Q, 0>(sm[wv][c], rows[wv].r[0], pw[wv][c][0], pc, lane);
         wave_sync();
-        m2m_pass<Q>(rows[wv].r[0], rows[wv].r[1], pw[wv][c][1], 1, lane);
+        m2m_pass<Q, 1>(rows[wv].r[0], rows[wv].r[1], pw[wv][c][1], pc, lane);
         wave_sync();
-        m2m_pass<Q>(rows[wv].r[1], rows[wv].r[0], pw[wv][c][2], 2, lane);
+        m2m_pass<Q, 2>(rows[wv].r[1], rows[wv].r[0], pw[wv][c][2], pc, lane);
         wave_sync();
 #pragma unroll
         for (int s = 0; s < (K + kW - 1) / kW; ++s)
@@ -542,13 +597,15 @@ __global__ __launch_bounds__(kW *kTreeWaves) void mapped_l2l_kernel(int n_par, c
     for (int i = lane; i < K; i += kW) lp[wv][i] = Lam[(int64_t)par * ldk + i];
     if (lane < 24) shift_factors(pw[wv][lane / 3][lane % 3], centre[first + lane / 3], cp, lane % 3, 1.0, Q);
     wave_sync();
+    PassCodes<Q> pc;
+    l2l_codes<Q>(pc, lane);
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-        l2l_pass<Q>(lp[wv], rows[wv].r[0], pw[wv][c][2], 2, lane);
+        l2l_pass<Q, 2>(lp[wv], rows[wv].r[0], pw[wv][c][2], pc, lane);
         wave_sync();
-        l2l_pass<Q>(rows[wv].r[0], rows[wv].r[1], pw[wv][c][1], 1, lane);
+        l2l_pass<Q, 1>(rows[wv].r[0], rows[wv].r[1], pw[wv][c][1], pc, lane);
         wave_sync();
-        l2l_pass<Q>(rows[wv].r[1], rows[wv].r[0], pw[wv][c][0], 0, lane);
+        l2l_pass<Q, 0>(rows[wv].r[1], rows[wv].r[0], pw[wv][c][0], pc, lane);
         wave_sync();
 #pragma unroll
         for (int n = 0; n < NA; ++n)
