@@ -128,7 +128,7 @@ typedef struct {
                               network may be destroyed afterwards. */
     double surrogate_tol;  /* e.g. 1e-7; 0 forces the fallback for every class */
     int near_unit;         /* work-unit size of the near field: rows longer than this many entries are
-                              cut into pieces of about equal length (0 = 512; else 64..65536) */
+                              cut into pieces of about equal length (0 = 2048; else 64..65536) */
     int m2l_max_slots;     /* longest slot list of one interaction task; longer lists are cut into
                               pieces whose partial sums are added in a fixed order (0 = 320, or 256
                               with q_schedule = 1 or under 2^20 slots in all; else 16..65536) */
