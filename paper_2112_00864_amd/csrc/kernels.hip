@@ -2258,10 +2258,22 @@ void mapped_apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, 
     marks.stop(BCV_PHASE_NEAR, st);
     if (far) {
         const int phase_id[4] = {BCV_PHASE_P2M, BCV_PHASE_M2M, BCV_PHASE_M2L, BCV_PHASE_L2L};
+        // with a second stream, the ball cells' pair kernel runs beside the cube cells' lattice
+        // tasks (disjoint targets), so that each fills the other's tail
+        const bool fork = p.streams == 2 && p.side != nullptr && p.n_tasks > 0 && p.n_ilist_targets > 0;
         for (int ph = 0; ph < 4; ++ph) {
             marks.start(phase_id[ph], st);
-            if (ph == 2) interaction_phase<Q>(p, st);  // the cube meshes' cells: lattice tasks
-            launch_mapped_phase(p, f, ph, st);
+            if (ph == 2 && fork) {
+                BCV_HIP(hipEventRecord(p.ev_fork, st));
+                BCV_HIP(hipStreamWaitEvent(p.side, p.ev_fork, 0));
+                launch_mapped_phase(p, f, ph, p.side);
+                BCV_HIP(hipEventRecord(p.ev_join, p.side));
+                interaction_phase<Q>(p, st);
+                BCV_HIP(hipStreamWaitEvent(st, p.ev_join, 0));
+            } else {
+                if (ph == 2) interaction_phase<Q>(p, st);  // the cube meshes' cells: lattice tasks
+                launch_mapped_phase(p, f, ph, st);
+            }
             marks.stop(phase_id[ph], st);
         }
         marks.start(BCV_PHASE_EVAL, st);
