@@ -226,6 +226,7 @@ struct bcv_plan_s {
     int streams = 1;
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork2 = nullptr;  // the second fork of a mapped apply (its interaction phase)
 
     // Phase timing: a start and a stop event per phase per recorded apply, see bcv_plan_enable_timing.
     std::vector<hipEvent_t> events;

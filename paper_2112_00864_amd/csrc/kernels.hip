@@ -2250,22 +2250,32 @@ void mapped_apply_q(const bcv_plan_s &p, const double *f, double *u, int parts, 
     const bool far = (parts & BCV_PART_FAR) && !p.direct;
     const bool near = (parts & BCV_PART_NEAR) != 0;
     PhaseMarks marks(p);
-    marks.start(BCV_PHASE_NEAR, st);
-    if (near)
-        launch_near<Q>(p, f, nullptr, BCV_PART_NEAR, u, st);
-    else
-        launch_mapped_zero(p, u, st);
-    marks.stop(BCV_PHASE_NEAR, st);
+    // With a second stream: after P2M (bandwidth-bound) the near field runs there beside M2M
+    // (latency-bound, level by level), and then the ball cells' pair kernel beside the cube cells'
+    // lattice tasks (disjoint targets), so that each fills the other's tail; the main stream waits
+    // for both before L2L.
+    const bool two = far && p.streams == 2 && p.side != nullptr;
+    auto near_part = [&](hipStream_t ns) {
+        marks.start(BCV_PHASE_NEAR, ns);
+        if (near)
+            launch_near<Q>(p, f, nullptr, BCV_PART_NEAR, u, ns);
+        else
+            launch_mapped_zero(p, u, ns);
+        marks.stop(BCV_PHASE_NEAR, ns);
+    };
+    if (!two) near_part(st);
     if (far) {
         const int phase_id[4] = {BCV_PHASE_P2M, BCV_PHASE_M2M, BCV_PHASE_M2L, BCV_PHASE_L2L};
-        // with a second stream, the ball cells' pair kernel runs beside the cube cells' lattice
-        // tasks (disjoint targets), so that each fills the other's tail
-        const bool fork = p.streams == 2 && p.side != nullptr && p.n_tasks > 0 && p.n_ilist_targets > 0;
         for (int ph = 0; ph < 4; ++ph) {
-            marks.start(phase_id[ph], st);
-            if (ph == 2 && fork) {
+            if (ph == 1 && two) {
                 BCV_HIP(hipEventRecord(p.ev_fork, st));
                 BCV_HIP(hipStreamWaitEvent(p.side, p.ev_fork, 0));
+                near_part(p.side);
+            }
+            marks.start(phase_id[ph], st);
+            if (ph == 2 && two) {
+                BCV_HIP(hipEventRecord(p.ev_fork2, st));
+                BCV_HIP(hipStreamWaitEvent(p.side, p.ev_fork2, 0));
                 launch_mapped_phase(p, f, ph, p.side);
                 BCV_HIP(hipEventRecord(p.ev_join, p.side));
                 interaction_phase<Q>(p, st);

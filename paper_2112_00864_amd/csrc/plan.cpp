@@ -1144,6 +1144,7 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         BCV_HIP(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
         BCV_HIP(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
         BCV_HIP(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
+        BCV_HIP(hipEventCreateWithFlags(&p->ev_fork2, hipEventDisableTiming));
     }
     // expansion orders per level and the row strides of the coefficient arrays. Orders without
     // kernels of their own (fixed q other than 4, 6, 8) run the level-by-level kernels of the
@@ -1474,6 +1475,7 @@ void destroy_plan(bcv_plan_s *p)
     for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
     if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
     if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+    if (p->ev_fork2) (void)hipEventDestroy(p->ev_fork2);
     if (p->side) (void)hipStreamDestroy(p->side);
     void *bufs[] = {p->d_leaf_geom, p->d_leaf_cell, p->d_cell_leaf, p->d_rest_leaves, p->d_split, p->d_col, p->d_val, p->d_val32, p->d_units,
                     p->d_splits, p->d_partial, p->d_M, p->d_Lam, p->d_G,
