@@ -120,6 +120,26 @@ def test_fmm_matches_O2(q, ball3):
     assert np.max(np.abs(parts["near"] + parts["far"] - u)) <= 1e-13 * np.max(np.abs(u))
 
 
+@pytest.mark.parametrize("precision", [bcv.FP64, bcv.MIXED_F32])
+def test_one_and_two_streams_agree(precision):
+    """With two streams the mapped apply runs its near field beside M2M and the ball cells' pair kernel
+    beside the lattice tasks; every kernel computes the same values in the same order either way."""
+    Ls = [4, 3]
+    tree = bcv.build_bc_forest(Ls, geometry=[bcv.GEOM_BALL, bcv.GEOM_BOX])
+    lv = tree.leaves().astype(np.int64)
+    mesh = tree.leaf_mesh()
+    f = np.empty(len(lv))
+    for m in range(len(Ls)):
+        loc = lv[mesh == m].copy()
+        loc[:, 1] -= (4 * m) << loc[:, 0]
+        f[mesh == m] = synth.leaf_density(loc, seed=4 + m)
+    announce("ball + cube forest, streams 1 vs 2, precision %d" % precision)
+    a = gpu_apply(bcv.plan_interactions(tree, q=6, nearfield=bcv.NEAR_ASSEMBLED, precision=precision, streams=1), f)
+    b = gpu_apply(bcv.plan_interactions(tree, q=6, nearfield=bcv.NEAR_ASSEMBLED, precision=precision, streams=2), f)
+    announce("max abs diff %.3e" % float(np.max(np.abs(a - b))))
+    assert np.array_equal(a, b)
+
+
 def test_mixed_precision_against_O2(ball3):
     from oracle import mapped
 
