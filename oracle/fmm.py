@@ -23,7 +23,10 @@ local coefficients of degree <= q_l; leaf moments are computed to q_l; M2M maps 
 (degree <= q_{l+1}) to the parent's degree <= q_l moments, so the parent's top-degree moments receive
 only the child's terms of lower degree; the interaction phase at level l truncates to
 |alpha| + |beta| <= q_l; L2L keeps the child's degrees <= q_{l+1}. q_levels gives the orders per
-level explicitly (a constant list is the fixed-q method).
+level explicitly (a constant list is the fixed-q method). exact_moments=True takes the other reading
+of the upward pass: every cell carries moments of degree <= max_l q_l (leaf moments to that degree,
+M2M without truncation), so a cell's moments are exactly those of the point rule over all of its
+leaves; the interaction at level l still uses the degrees <= q_l of its sources' moments.
 near_order=1 gives the near field the level-dependent Gauss rule of oracle.direct (n_l = 2 + L - l
 points per axis on a level-l leaf); the moments and the evaluation keep the 2x2x2 rule, so the
 result then tends to oracle.direct.apply_near_order as q grows.
@@ -41,7 +44,7 @@ _CHILD_POS = [(dx, dy, dz) for dz in (0, 1) for dy in (0, 1) for dx in (0, 1)]
 
 
 class FMM:
-    def __init__(self, mesh, q, near_order=0, q_schedule=0, q_levels=None):
+    def __init__(self, mesh, q, near_order=0, q_schedule=0, q_levels=None, exact_moments=False):
         self.mesh = mesh
         self.q = q
         self.near_order = near_order
@@ -49,6 +52,9 @@ class FMM:
             q_levels = [q + (mesh.L - lev) if q_schedule else q for lev in range(mesh.L + 1)]
         self.q_of = [int(v) for v in q_levels]
         self.K_of = [n_coeffs(v) for v in self.q_of]
+        # degrees carried by the moments of each level
+        self.qm_of = [max(self.q_of)] * len(self.q_of) if exact_moments else list(self.q_of)
+        self.Km_of = [n_coeffs(v) for v in self.qm_of]
         self.K = n_coeffs(q)
         self.leaves = mesh.leaf_array()
         self.orders = None if near_order == 0 else direct.near_gauss_orders(self.leaves, mesh.L, near_order)
@@ -70,16 +76,18 @@ class FMM:
             rows.append((np.array(pos, dtype=np.int64), np.array(idx, dtype=np.int64)))
         return rows
 
-    def _point_moments(self, lev, cells, chunk=8192):
-        """sum_g w_g (x_g - x_w)^b over the 2x2x2 points of level-lev cells, |b| <= q_lev: (n, K_lev)."""
+    def _point_moments(self, lev, cells, chunk=8192, order=None):
+        """sum_g w_g (x_g - x_w)^b over the 2x2x2 points of level-lev cells, |b| <= order (default
+        q_lev): (n, n_coeffs(order))."""
+        order = self.q_of[lev] if order is None else order
         a = self.mesh.side(lev)
         lo_all = np.asarray(cells, dtype=np.float64).reshape(-1, 3) * a
-        out = np.empty((len(lo_all), self.K_of[lev]))
+        out = np.empty((len(lo_all), n_coeffs(order)))
         for s in range(0, len(lo_all), chunk):
             lo = lo_all[s : s + chunk]
             pts, w = direct.gauss_points(lo, np.full(len(lo), a))
             centre = lo + 0.5 * a
-            mono = monomials(pts - centre[:, None, :], self.q_of[lev])  # (n, 8, K_lev)
+            mono = monomials(pts - centre[:, None, :], order)  # (n, 8, n_coeffs(order))
             out[s : s + chunk] = mono.sum(axis=1) * w[:, None]
         return out
 
@@ -89,12 +97,12 @@ class FMM:
         return np.array([(p - 0.5) * a / 2.0 for p in pos])
 
     def _m2m(self, lev, pos):
-        """Parent (level lev, degree <= q_lev) from child (degree <= q_{lev+1}) moments."""
+        """Parent (level lev, the degrees its moments carry) from child (level lev + 1) moments."""
         key = ("m2m", lev, pos)
         if key not in self._cache:
-            qp, qc = self.q_of[lev], self.q_of[lev + 1]
+            qp, qc = self.qm_of[lev], self.qm_of[lev + 1]
             M = m2m_matrix(self._child_offset(lev, pos), max(qp, qc))
-            self._cache[key] = M[: self.K_of[lev], : self.K_of[lev + 1]]
+            self._cache[key] = M[: self.Km_of[lev], : self.Km_of[lev + 1]]
         return self._cache[key]
 
     def _l2l(self, lev, pos):
@@ -134,11 +142,11 @@ class FMM:
     def moments(self, f):
         """Leaf moments by level: f times the point-rule integral of each monomial about the centre."""
         mesh = self.mesh
-        m = [np.zeros((len(mesh.levels[lev]), self.K_of[lev])) for lev in range(mesh.L + 1)]
+        m = [np.zeros((len(mesh.levels[lev]), self.Km_of[lev])) for lev in range(mesh.L + 1)]
         for lev, (pos, idx) in enumerate(self._rows):
             if len(pos):
                 cells = [mesh.levels[lev][p] for p in pos]
-                m[lev][pos] = self._point_moments(lev, cells) * f[idx][:, None]
+                m[lev][pos] = self._point_moments(lev, cells, order=self.qm_of[lev]) * f[idx][:, None]
         return m
 
     def _children_rows(self, lev):
@@ -159,7 +167,7 @@ class FMM:
             par, kids = self._children_rows(lev)
             if len(par) == 0:
                 continue
-            acc = np.zeros((len(par), self.K_of[lev]))
+            acc = np.zeros((len(par), self.Km_of[lev]))
             for pos in _CHILD_POS:
                 acc += m[lev + 1][kids[pos]] @ self._m2m(lev, pos).T
             m[lev][par] = acc
@@ -182,7 +190,7 @@ class FMM:
             for o, T in zip(offsets, self._m2l(lev, offsets)):
                 tp = np.array(groups[o][0], dtype=np.int64)
                 sp = np.array(groups[o][1], dtype=np.int64)
-                lam[lev][tp] += m[lev][sp] @ T.T  # a target has at most one source per offset
+                lam[lev][tp] += m[lev][sp, : self.K_of[lev]] @ T.T  # at most one source per offset
         return lam
 
     def downward(self, lam):
@@ -225,7 +233,7 @@ class FMM:
             offs = [(c[0] - s[0], c[1] - s[1], c[2] - s[2]) for s in srcs]
             idx = mesh.index[lev]
             for T, s in zip(self._m2l(lev, offs), srcs):
-                lam += T @ m[lev][idx[s]]
+                lam += T @ m[lev][idx[s], : self.K_of[lev]]
         if lev > 0:
             par = (c[0] >> 1, c[1] >> 1, c[2] >> 1)
             pos = (c[0] & 1, c[1] & 1, c[2] & 1)
@@ -247,6 +255,6 @@ class FMM:
         return u
 
 
-def apply(mesh, f, q, targets=None, near_order=0, q_schedule=0):
-    fm = FMM(mesh, q, near_order, q_schedule)
+def apply(mesh, f, q, targets=None, near_order=0, q_schedule=0, exact_moments=False):
+    fm = FMM(mesh, q, near_order, q_schedule, exact_moments=exact_moments)
     return fm.apply(f) if targets is None else fm.apply_sampled(f, targets)

@@ -102,3 +102,64 @@ def test_level_schedule_converges_in_q0():
     u1 = direct.apply(lv, 4, f, tg)
     errs = [_rel(lv[tg], fmm.FMM(m, q0, q_schedule=1).apply_sampled(f, tg), u1) for q0 in (2, 3, 4)]
     assert errs[0] > errs[1] > errs[2] and errs[2] < 3e-7
+
+
+def _subtree_moments(m, lv, f, lev, c, order):
+    """Brute force: sum over the leaves inside cell (lev, c) of f times the 2x2x2 point rule of
+    (x - x_c)^b, |b| <= order, about the cell's own centre."""
+    from oracle.taylor import monomials
+
+    a = m.side(lev)
+    centre = (np.asarray(c, dtype=np.float64) + 0.5) * a
+    inside = (lv[:, 1:] >> (lv[:, :1] - lev)) == np.asarray(c)
+    sel = np.nonzero((lv[:, 0] >= lev) & inside.all(axis=1))[0]
+    side = np.ldexp(1.0, -lv[sel, 0].astype(np.int32))
+    pts, w = direct.gauss_points(lv[sel, 1:] * side[:, None], side)
+    mono = monomials(pts - centre, order)  # (n, 8, K)
+    return np.einsum("n,ngk->k", f[sel] * w, mono)
+
+
+def test_exact_moments_are_the_subtree_moments():
+    """The exact-moment reading (every cell's moments to the largest level order, M2M untruncated):
+    each marked cell's moments equal the point-rule moments of all of its leaves about its centre,
+    computed directly (the shift of a polynomial is exact). The reading as printed loses the
+    parents' top-degree terms: there the same comparison fails at degree q_l."""
+    from oracle.taylor import n_coeffs
+
+    L = 4
+    m = BCMesh(L)
+    lv = m.leaf_array()
+    f = synth.leaf_density(lv, seed=2)
+    ex = fmm.FMM(m, 3, q_schedule=1, exact_moments=True)
+    pr = fmm.FMM(m, 3, q_schedule=1)
+    assert ex.qm_of == [3 + L - 0] * (L + 1) and pr.qm_of == pr.q_of
+    mom_ex = ex.upward(ex.moments(f))
+    mom_pr = pr.upward(pr.moments(f))
+    worst_pr = 0.0
+    checked = 0
+    for lev in (1, 2, 3):
+        for p, c in enumerate(m.levels[lev]):
+            if not m.is_refined(lev, c) or p % 3:
+                continue
+            ref = _subtree_moments(m, lv, f, lev, c, ex.qm_of[lev])
+            scale = np.max(np.abs(ref))
+            assert np.max(np.abs(mom_ex[lev][p] - ref)) <= 1e-13 * scale
+            k0, k = n_coeffs(pr.q_of[lev] - 1), n_coeffs(pr.q_of[lev])  # the degree-q_l block
+            top = np.max(np.abs(ref[k0:k]))
+            worst_pr = max(worst_pr, np.max(np.abs(mom_pr[lev][p][k0:k] - ref[k0:k])) / top)
+            checked += 1
+    assert checked >= 10 and worst_pr > 1e-3
+
+
+def test_exact_moments_converge_to_direct():
+    """With the schedule, the exact-moment reading also tends to O1 as q0 grows, and at every q0 it
+    is at least as close to O1 as the reading as printed (it only adds moment terms)."""
+    m = BCMesh(4)
+    lv = m.leaf_array()
+    f = synth.leaf_density(lv, seed=1)
+    tg = np.arange(0, len(lv), 5)
+    u1 = direct.apply(lv, 4, f, tg)
+    ex = [_rel(lv[tg], fmm.FMM(m, q0, q_schedule=1, exact_moments=True).apply_sampled(f, tg), u1) for q0 in (2, 3, 4)]
+    pr = [_rel(lv[tg], fmm.FMM(m, q0, q_schedule=1).apply_sampled(f, tg), u1) for q0 in (2, 3, 4)]
+    assert ex[0] > ex[1] > ex[2] and ex[2] < 3e-7
+    assert all(e <= 1.05 * p for e, p in zip(ex, pr))
