@@ -168,6 +168,14 @@ typedef struct {
                               q and with q_schedule (the paper's experiments take p_l = L - l with
                               q_l = 4 + L - l, Sec. 5). Requires BCV_FP64, a single mesh of side 1, no
                               surrogate, no opts.boundary, and L - (coarsest leaf level) <= 8 */
+    int exact_moments;     /* with q_schedule = 1 only (Algorithm 1's upward pass, the other reading of
+                              its M2M with level-dependent orders). 0: as q_schedule describes (a
+                              parent's top-degree moments receive only its children's lower-degree
+                              terms). 1: every cell carries moments of degree <= the largest order
+                              q + L - 2 (leaf moments to that degree, M2M untruncated), so a cell's
+                              moments are those of all of its leaves; the interaction phase at level
+                              l still uses the degrees <= q_l. Requires q_schedule = 1 and
+                              basis_degree = 0 */
 } bcv_plan_opts;
 
 /* Sizes of a plan (all counts, no pointers). */

@@ -48,7 +48,7 @@ class PlanOpts(ctypes.Structure):
                 ("direct", ctypes.c_int), ("nearfield", ctypes.c_int), ("streams", ctypes.c_int),
                 ("surrogate", ctypes.c_void_p), ("surrogate_tol", ctypes.c_double), ("near_unit", ctypes.c_int),
                 ("m2l_max_slots", ctypes.c_int), ("q_schedule", ctypes.c_int), ("near_order", ctypes.c_int),
-                ("boundary", ctypes.c_int), ("basis_degree", ctypes.c_int)]
+                ("boundary", ctypes.c_int), ("basis_degree", ctypes.c_int), ("exact_moments", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -262,17 +262,18 @@ class Plan:
 
 
 def _opts(q=6, eta0=0.5, direct=False, nearfield=NEAR_QUADRATURE, streams=2, precision=FP64, surrogate=None,
-          surrogate_tol=1e-7, near_unit=0, m2l_max_slots=0, boundary=False, near_order=0, q_schedule=0, basis_degree=0):
+          surrogate_tol=1e-7, near_unit=0, m2l_max_slots=0, boundary=False, near_order=0, q_schedule=0, basis_degree=0,
+          exact_moments=False):
     return PlanOpts(eta0, q, precision, 1 if direct else 0, nearfield, streams,
                     surrogate.handle if surrogate is not None else None, surrogate_tol, near_unit, m2l_max_slots,
-                    q_schedule, near_order, 1 if boundary else 0, basis_degree)
+                    q_schedule, near_order, 1 if boundary else 0, basis_degree, 1 if exact_moments else 0)
 
 
 def plan_interactions(tree, q=6, eta0=0.5, direct=False, nearfield=NEAR_QUADRATURE, device=0, streams=2,
                       precision=FP64, surrogate=None, surrogate_tol=1e-7, near_unit=0, m2l_max_slots=0,
-                      boundary=False, near_order=0, q_schedule=0, basis_degree=0):
+                      boundary=False, near_order=0, q_schedule=0, basis_degree=0, exact_moments=False):
     opts = _opts(q, eta0, direct, nearfield, streams, precision, surrogate, surrogate_tol, near_unit, m2l_max_slots,
-                 boundary, near_order, q_schedule, basis_degree)
+                 boundary, near_order, q_schedule, basis_degree, exact_moments)
     h = ctypes.c_void_p()
     _check(lib().bcv_plan_interactions(tree.handle, ctypes.byref(opts), device, ctypes.byref(h)))
     return Plan(h, device)

@@ -109,6 +109,9 @@ void check_plan_opts(const bcv_plan_opts &o, int device)
     BCV_REQUIRE(o.boundary == 0 || o.boundary == 1, BCV_EINVAL, "boundary must be 0 or 1");
     BCV_REQUIRE(o.near_order == 0 || o.near_order == 1, BCV_EINVAL, "near_order must be 0 or 1");
     BCV_REQUIRE(o.q_schedule == 0 || o.q_schedule == 1, BCV_EINVAL, "q_schedule must be 0 or 1");
+    BCV_REQUIRE(o.exact_moments == 0 || o.exact_moments == 1, BCV_EINVAL, "exact_moments must be 0 or 1");
+    BCV_REQUIRE(o.exact_moments == 0 || (o.q_schedule == 1 && o.basis_degree == 0), BCV_ENOTSUP,
+                "exact_moments requires q_schedule = 1 and basis_degree = 0");
     BCV_REQUIRE(o.q_schedule == 0 || o.boundary == 0, BCV_ENOTSUP,
                 "level-dependent orders are not combined with the boundary (BtV/VtB) structures");
     BCV_REQUIRE(o.q == 4 || o.q == 6 || o.q == 8 || o.boundary == 0, BCV_ENOTSUP,

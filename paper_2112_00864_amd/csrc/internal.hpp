@@ -212,6 +212,7 @@ struct bcv_plan_s {
     // stride of the moment and local arrays, ncoef(max order); R = (max order + 1)^2 that of the
     // folded rows.
     int q_schedule = 0;
+    int exact_moments = 0;  // q_schedule: every cell's moments to the largest order (M2M untruncated)
     int q_level[bcv::kMaxLevel + 1] = {};
     int R = 0;
     int64_t n_near_ordered = 0;    // near entries that took it

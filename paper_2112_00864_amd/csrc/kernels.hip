@@ -1670,6 +1670,14 @@ struct PhaseMarks {
     }
 };
 
+// The largest expansion order of any level of the plan.
+int max_order(const bcv_plan_s &p)
+{
+    int q = 0;
+    for (int l = 0; l <= p.L; ++l) q = std::max(q, p.q_level[l]);
+    return q;
+}
+
 LevelOrders level_orders(const bcv_plan_s &p)
 {
     LevelOrders lo{};
@@ -1895,7 +1903,9 @@ void launch_p2m(const bcv_plan_s &p, const double *f, hipStream_t st, bool fused
     const int skip = fused && !p.q_schedule ? p.L : -1;
     const auto *geom = reinterpret_cast<const double4 *>(p.d_leaf_geom);
     const unsigned blocks = (unsigned)((p.n_leaves + 255) / 256);  // 64 leaves per wave
-    const LevelOrders lo = level_orders(p);
+    LevelOrders lo = level_orders(p);
+    if (p.exact_moments)  // every leaf's moments to the largest order (its folded row keeps its own)
+        for (int l = 0; l <= kMaxLevel; ++l) lo.k[l] = p.K;
     constexpr int QT = Q > kMaxSchedQ ? Q : kMaxSchedQ;  // tables large enough for every level's order
     if (p.precision != BCV_FP64) {
         if (p.q_schedule)
@@ -1946,7 +1956,9 @@ void upward_pass(const bcv_plan_s &p, hipStream_t st, const double *f_fused = nu
                     n_par, p.d_parents + 2 * p.parent_begin[lev], p.d_M, p.d_Mr, p.K, p.R);
             check_launch();
         };
-        if (p.q_schedule)
+        if (p.exact_moments)  // parents keep every degree of the largest order
+            with_order(max_order(p), run);
+        else if (p.q_schedule)
             with_order(p.q_level[lev], run);
         else
             run(std::integral_constant<int, Q>{});

@@ -1151,6 +1151,7 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
     // level-dependent orders with the same order on every level.
     const bool per_level = opts.q_schedule || !(opts.q == 4 || opts.q == 6 || opts.q == 8);
     p->q_schedule = per_level;
+    p->exact_moments = opts.exact_moments;
     int q_max = opts.q;
     for (int lev = 0; lev <= kMaxLevel; ++lev) {
         p->q_level[lev] = opts.q_schedule ? opts.q + t.L - std::max(lev, 2) : opts.q;

@@ -68,6 +68,14 @@ def test_plan_argument_errors_before_device_use():
         assert e.value.status == bcv.bcv.EINVAL
 
 
+def test_exact_moments_need_the_level_schedule():
+    t = bcv.build_bc_tree(3)
+    for kw in ({"exact_moments": True}, {"exact_moments": True, "q_schedule": 1, "basis_degree": 1}):
+        with pytest.raises(bcv.BCVError) as e:
+            bcv.plan_interactions(t, q=4, **kw)
+        assert e.value.status == bcv.bcv.ENOTSUP
+
+
 def test_schedule_is_not_combined_with_the_boundary_structures():
     with pytest.raises(bcv.BCVError) as e:
         bcv.plan_interactions(bcv.build_bc_tree(3), q=4, q_schedule=1, boundary=True)

@@ -114,3 +114,29 @@ def test_schedule_option_errors():
     with pytest.raises(bcv.BCVError) as e:
         bcv.plan_interactions(bcv.build_bc_forest([3, 4]), q=4, q_schedule=1)
     assert e.value.status == bcv.bcv.ENOTSUP
+
+
+@pytest.mark.parametrize("L,q,precision", [(3, 4, bcv.FP64), (4, 4, bcv.FP64), (4, 6, bcv.FP64),
+                                           (4, 4, bcv.MIXED_F32)])
+def test_exact_moments_match_O2(L, q, precision):
+    """The exact-moment reading of the upward pass (every cell's moments to the largest order) against
+    O2 with the same reading. The two readings give different operators (the printed one drops the
+    parents' top-degree terms, which are small: 5e-10 at L = 4, q = 4), and the FP64 GPU result is
+    far closer to its own reading's O2 than to the other's."""
+    m, lv = mesh(L)
+    f = synth.leaf_density(lv, seed=2)
+    announce("schedule, exact moments, L=%d q=%d precision %d" % (L, q, precision))
+    tree = bcv.build_bc_tree(L)
+    u = gpu_apply(bcv.plan_interactions(tree, q=q, q_schedule=1, exact_moments=True, precision=precision,
+                                        nearfield=bcv.NEAR_ASSEMBLED), f)
+    ref = fmm.FMM(m, q, q_schedule=1, exact_moments=True).apply(f)
+    e = rel_l2(lv, u, ref)
+    printed = fmm.FMM(m, q, q_schedule=1).apply(f)
+    d = rel_l2(lv, printed, ref)
+    announce("exact moments L=%d q=%d: vs O2 %.3e (the printed reading differs by %.3e)" % (L, q, e, d))
+    assert e <= (TOL if precision == bcv.FP64 else 1e-6)
+    # The GPU follows its own reading, not the other one. At L = 3 the readings coincide: the only
+    # dropped terms are the leaves' moments of odd degree q_3 + 1 about their centres, which the
+    # symmetric 2x2x2 rule makes zero.
+    if precision == bcv.FP64 and L >= 4:
+        assert d > 100 * e
