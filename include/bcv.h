@@ -119,7 +119,9 @@ typedef struct {
                       2: after the upward pass, the near field is forked to a plan-owned second
                       stream (default priority), runs concurrently with the interaction phase
                       and the downward pass, and is joined back to the caller's stream before
-                      the evaluation phase */
+                      the evaluation phase. Plans with cube-to-ball meshes fork twice instead:
+                      the near field after P2M (beside M2M), then the ball cells' interaction
+                      pairs beside the cube cells' interaction tasks, both joined before L2L */
     bcv_mlp surrogate;     /* NULL: the touching-pair integrals come from bcv_touching_integrals.
                               Else each of the six face/edge/vertex classes takes the trained
                               surrogate's value where its error estimate is <= surrogate_tol
