@@ -1809,6 +1809,8 @@ template <class F>
 void with_order(int q, F &&f)
 {
     switch (q) {
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
     case 4: f(std::integral_constant<int, 4>{}); break;
     case 5: f(std::integral_constant<int, 5>{}); break;
     case 6: f(std::integral_constant<int, 6>{}); break;
