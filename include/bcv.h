@@ -105,8 +105,8 @@ enum { BCV_FP64 = 0, BCV_MIXED_F32 = 1, BCV_MIXED_SPLIT16 = 2 };
 /* Plan options. */
 typedef struct {
     double eta0;   /* separation parameter of the neighbour test (eq. def:neighbors); must be 0.5 */
-    int q;         /* expansion order, |alpha| + |beta| <= q (Sec. 3): 2..10. Orders 4, 6 and 8 have
-                      their own interaction kernels; 2, 3, 5, 7, 9 and 10 run the level-by-level
+    int q;         /* expansion order, |alpha| + |beta| <= q (Sec. 3): 0..10. Orders 4, 6 and 8 have
+                      their own interaction kernels; 0-3, 5, 7, 9 and 10 run the level-by-level
                       kernels of q_schedule with the same order on every level (single-mesh trees,
                       no opts.boundary) */
     int precision; /* BCV_FP64, BCV_MIXED_F32 or BCV_MIXED_SPLIT16 */

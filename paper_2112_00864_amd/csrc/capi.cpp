@@ -95,7 +95,7 @@ void check_mesh_desc(const bcv_mesh_desc &d, double lo[3], double *side)
 void check_plan_opts(const bcv_plan_opts &o, int device)
 {
     BCV_REQUIRE(o.eta0 == 0.5, BCV_EINVAL, "eta0 must be 0.5");
-    BCV_REQUIRE(o.q >= 2 && o.q <= 10, BCV_EINVAL, "q must be in 2..10");
+    BCV_REQUIRE(o.q >= 0 && o.q <= 10, BCV_EINVAL, "q must be in 0..10");
     BCV_REQUIRE(o.precision == BCV_FP64 || o.precision == BCV_MIXED_F32 || o.precision == BCV_MIXED_SPLIT16,
                 BCV_EINVAL, "precision must be BCV_FP64, BCV_MIXED_F32 or BCV_MIXED_SPLIT16");
     BCV_REQUIRE(o.direct == 0 || o.direct == 1, BCV_EINVAL, "direct must be 0 or 1");

@@ -61,7 +61,7 @@ def test_tree_argument_errors():
 
 def test_plan_argument_errors_before_device_use():
     t = bcv.build_bc_tree(3)
-    for kw in ({"q": 1}, {"q": 11}, {"eta0": 0.4}, {"near_order": 2}, {"near_order": 1},  # 1 needs the assembled mode
+    for kw in ({"q": -1}, {"q": 11}, {"eta0": 0.4}, {"near_order": 2}, {"near_order": 1},  # 1 needs the assembled mode
                {"near_order": 1, "nearfield": bcv.NEAR_QUADRATURE}, {"q_schedule": 2}):
         with pytest.raises(bcv.BCVError) as e:
             bcv.plan_interactions(t, **kw)
@@ -176,7 +176,7 @@ def test_ball_gauss_points_match_oracle(lo, side):
 
 def test_order_range():
     t = bcv.build_bc_tree(3)
-    for q in (1, 11):
+    for q in (-1, 11):
         with pytest.raises(bcv.BCVError) as e:
             bcv.plan_interactions(t, q=q)
         assert e.value.status == bcv.bcv.EINVAL

@@ -3,7 +3,7 @@
 * A cube of side s at any position: the VtV potential is s^5 times that of the unit cube (the
   operator scales exactly; the library applies the factor at the end, a power of two here, so the
   comparison is exact), checked against O2 times s^5.
-* Fixed expansion orders without kernels of their own (2, 3, 5, 7) run the level-by-level kernels:
+* Fixed expansion orders without kernels of their own (0 to 3, 5, 7) run the level-by-level kernels:
   against O2 with the same constant order, bar 1e-10.
 * bcv_vtv_apply_batched: three plans of different meshes, one call, equal to three single applies.
 """
@@ -58,7 +58,7 @@ def test_scaled_domain():
     assert ex.value.status == bcv.ENOTSUP
 
 
-@pytest.mark.parametrize("q", [2, 3, 5, 7])
+@pytest.mark.parametrize("q", [0, 1, 2, 3, 5, 7])
 def test_other_fixed_orders(q):
     L = 4
     m = BCMesh(L)
