@@ -355,7 +355,7 @@ uint64_t hash_keys(const std::vector<int32_t> &keys)
 // these cells are targets (the VtB plan: boundary cells, whose local coefficients the faces need).
 M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, const std::vector<int32_t> &max_slots,
                   bool per_level = false, int32_t small_slots = 0, const uint8_t *source_ok = nullptr,
-                  const uint8_t *target_ok = nullptr)
+                  const uint8_t *target_ok = nullptr, bool merge = true)
 {
     M2LPlan m;
     const int32_t zero_row = (int32_t)t.n_cells();
@@ -414,10 +414,14 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, const std::ve
             classes.push_back(Class{s0, s1, axis});
             s0 = s1;
         }
-        // A class of at least 64 cells whose members' neighbours one cell further along its axis
-        // form one other class of the same size and axis (the cells of the other child position,
-        // e.g. in the interior of a face) is merged with it: rows then step by one cell, so runs of
-        // offsets are twice as long and rows twice as dense, for a slightly larger union of lists.
+        // merge: a class of at least 64 cells whose members' neighbours one cell further along its
+        // axis form one other class of the same size and axis (the cells of the other child
+        // position, e.g. in the interior of a face) is merged with it: rows then step by one cell,
+        // so runs of offsets are twice as long and rows twice as dense (fewer row reads), for a
+        // larger union of lists (more masked lanes). FP64 plans merge (their rows cost twice the
+        // bytes), and so do the matrix-core plans (6.15 against 6.28 ms per apply); FP32 lane-shift
+        // plans do not (h = 1/256: FP32 interaction phase 4.01 ms unmerged against 4.41 merged, apply
+        // 5.21 against 5.44 ms; FP64 7.15 against 7.56 ms per apply the other way).
         std::vector<int32_t> partner(classes.size(), -1);
         auto class_of = [&](int32_t cell) -> int32_t {
             const int32_t *c = &t.ijk[3 * cell];
@@ -426,7 +430,7 @@ M2LPlan build_m2l(const bcv_tree_s &t, const std::vector<Grid> &g, const std::ve
         };
         for (size_t k = 0; k < classes.size(); ++k) {
             const Class &C = classes[k];
-            if (C.s1 - C.s0 < 64 || partner[k] >= 0) continue;
+            if (!merge || C.s1 - C.s0 < 64 || partner[k] >= 0) continue;
             const int ax = C.axis;
             int32_t cand = -1;
             bool ok = true;
@@ -1307,7 +1311,7 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
         if (lattice) {
         M2LPlan m2l = build_m2l(t, grids, level_slots, per_level,
                                 opts.m2l_max_slots == 0 && !per_level ? kDefaultMaxSlotsSchedule : 0, nullptr,
-                                p->mapped ? lattice_target.data() : nullptr);
+                                p->mapped ? lattice_target.data() : nullptr, opts.precision != BCV_MIXED_F32);
         std::vector<int32_t> id_of_key(15 * 15 * 15, -1);
         for (int32_t key : m2l.slot_key) id_of_key[key & 0x7FFFFFFF] = 0;
         std::vector<double> G;
@@ -1374,7 +1378,7 @@ bcv_plan_s *build_plan(const bcv_tree_s &t, const bcv_plan_opts &opts, int devic
             }
             const int32_t small = opts.m2l_max_slots == 0 ? kDefaultMaxSlotsSchedule : 0;
             auto make_set = [&](const uint8_t *src_ok, const uint8_t *tgt_ok, M2LSet &ms) {
-                M2LPlan b = build_m2l(t, grids, level_slots, false, small, src_ok, tgt_ok);
+                M2LPlan b = build_m2l(t, grids, level_slots, false, small, src_ok, tgt_ok, opts.precision != BCV_MIXED_F32);
                 for (int32_t &k : b.slot_key) {
                     const int32_t id = id_of_key[k & 0x7FFFFFFF];
                     BCV_REQUIRE(id >= 0, BCV_ESTATE, "internal: boundary interaction offset without a table");
