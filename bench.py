@@ -658,7 +658,6 @@ def main():
               % (prec, r["plan_s"], r["ms"], json.dumps({k: round(v, 4) for k, v in r["phases"].items()})),
               file=sys.stderr, flush=True)
 
-    info = runs[precisions[0]]["info"]
     rel_l2 = None
     if "fp64" in runs and "mixed" in runs:
         a, b = runs["mixed"]["u"], runs["fp64"]["u"]
@@ -671,6 +670,7 @@ def main():
     if args.precision == "both" and head != "mixed":
         print("mixed path missed the rel-L2 gate (%s): reporting FP64" % rel_l2, file=sys.stderr, flush=True)
     h = runs[head]
+    info = h["info"]  # the headline plan's (the packing, and so its lane counts, depends on the precision)
 
     cpu = None
     if not args.no_cpu:
